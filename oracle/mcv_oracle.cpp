@@ -1,0 +1,1057 @@
+// mcv_oracle.cpp -- serial FP64 CPU oracle for weighted neutron-packet transport.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+// GPU path is checked against.  Only the test-suite, the smoke check and the
+// CPU-baseline leg of the benchmark may load it.  It shares no code, header,
+// constant or table generator with the GPU library: every constant and every
+// formula below is written out here on its own.
+//
+// What it computes (arXiv:1504.02776, "MCViNE"):
+//   * ray tracing through a composite of homogeneous scatterers: intersect the
+//     forward ray with every shape, walk the material intervals in order
+//     (Sec. 2.4.3 "Ray Tracing");
+//   * packet splitting: at every material interval the packet is split into a
+//     transmitted part (weight times the attenuation e^{-mu L}) and a scattered
+//     part born at a random point of the interval, with a randomly chosen
+//     kernel (Sec. 2.4.3 "Multiple Scattering"; Supplement S3, interactM1);
+//   * multiple scattering as repeated splitting of scattered packets up to a
+//     maximum order, leftovers leaving with attenuation only (Supplement S3,
+//     scatterM / interactM_path1);
+//   * the scattering kernels of Supplement S4: incoherent elastic, powder
+//     Bragg (Debye-Scherrer cones), incoherent one-phonon from a DOS, and a
+//     dispersion surface E(Q) with S(Q); plus a tabulated isotropic S(Q,E)
+//     (Sec. 2.4.2, kernel "S(Q,omega) histogram");
+//   * detection on a sphere or on 3He tubes: chord through the tube, MC
+//     absorption point, weight times absorption probability, pixel from the
+//     axial position, time of flight (Sec. 2.4.3 "Ray tracing in a detector
+//     system");
+//   * intensity per (pixel, tof) bin = sum of packet probabilities (Sec. 3,
+//     four-step workflow, "Reduction").
+//
+// Where the paper is silent the readings are the ones listed in the design
+// notes (forced-collision point on a segment, implicit capture, 1/v
+// absorption, per-packet order count, nearest interceptor, and so on); each is
+// restated at the place it is used.
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3", SC'11), keyed by the 64-bit seed, with the
+// counter (id_lo, id_hi | stream<<30, lineage, block).  Every random decision
+// of a packet is a fixed word of a fixed block, so the traversal order of the
+// packet tree does not change any result.
+//
+// Decision margins: for every discrete decision the oracle records how far
+// the continuous quantity was from the decision boundary, divided by a stated
+// uncertainty scale.  Packets with a margin below 1 are "near-decision" in the
+// parity tests (a single-precision implementation may legitimately take the
+// other branch there).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------- constants
+// CODATA 2018 values, restated independently of any other source file.
+const double kEperV2 = 5.22703759e-6;     // E[meV] = kEperV2 * v[m/s]^2
+const double kHbar2over2mn = 2.0721249;   // E[meV] = kHbar2over2mn * k[1/A]^2
+const double kBoltzmann = 0.08617333;     // meV / K
+const double kNeutronMassAmu = 1.00866491595;
+const double kV2200 = 2200.0;             // reference speed for sigma_abs
+const double kHe3SigmaAbs = 5333.0;       // barn at 2200 m/s
+const double kSurfaceEps = 1e-7;          // m; intervals ending closer are behind
+const double kHuge = 1e30;                // stands for an unbounded interval end
+const double kPi = 3.14159265358979323846;
+
+// uncertainty scales used to normalise decision margins
+const double kTauRel = 2e-5;     // relative, for sums of cross sections etc.
+const double kTauGeom = 2e-6;    // m, for geometric distances near a surface
+const double kTauCos = 2e-6;     // in cos(2theta), sphere rings
+const double kTauTof = 4e-6;     // relative time of flight
+const double kTauImpact = 4e-4;  // relative impact parameter in a tube
+const double kTauU = 2e-6;       // absolute, for u < p tests on computed p
+
+inline double k_from_speed(double v) { return v * std::sqrt(kEperV2 / kHbar2over2mn); }
+inline double speed_from_k(double k) { return k * std::sqrt(kHbar2over2mn / kEperV2); }
+
+// ----------------------------------------------------------------- ABI types
+// (mirrored by ctypes in oracle.py)
+enum { SHAPE_BOX = 1, SHAPE_CYLINDER = 2, SHAPE_ANNULUS = 3 };
+enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5 };
+enum { BEAM_MONO = 1, BEAM_GAUSS = 2 };
+enum { DET_SPHERE = 1, DET_TUBES = 2 };
+enum { STREAM_SOURCE = 0, STREAM_SCATTER = 1, STREAM_DETECT = 2 };
+
+}  // namespace
+
+extern "C" {
+
+struct OShape {
+  int32_t type;
+  int32_t pad;
+  double dims[3];  // BOX: full x,y,z; CYLINDER: r,h,-; ANNULUS: r_in,r_out,h
+  double pos[3];   // lab position of the shape centre, m
+  double rot[9];   // local->lab rotation, row major
+};
+
+struct OKernel {
+  int32_t type;
+  int32_t dw;      // 1: multiply by the Debye-Waller factor of the scatterer
+  double sigma;    // nominal cross section, barn (ignored by POWDER)
+  // POWDER
+  double v0;       // cell volume, A^3
+  int32_t nrefl;
+  int32_t pad0;
+  const double* d;   // d-spacings, A
+  const double* F2;  // multiplicity * |F|^2 per cell, barn
+  // PHONON
+  double M;        // amu
+  double T;        // K
+  int32_t nbins;
+  int32_t pad1;
+  double emax;     // meV, DOS defined on [0, emax]
+  const double* dos;  // raw (unnormalised) DOS values, one per bin
+  // SPINWAVE
+  double J, S, a, gamma;  // meV, -, A, meV (HWHM)
+  double crot[9];         // lab->crystal rotation
+  // SQE
+  int32_t nQ, nE;
+  double Qmax, Emin, Emax;
+  const double* sqe;      // nQ x nE, row major (Q slow)
+};
+
+struct OScatterer {
+  OShape shape;
+  double n;          // atoms / A^3
+  double sigma_abs;  // barn at 2200 m/s
+  int32_t nk;
+  int32_t pad;
+  OKernel k[3];
+};
+
+struct OBeam {
+  int32_t type;
+  int32_t pad;
+  double E, sigma_rel, W, H, z0;
+};
+
+struct ODetector {
+  int32_t type;
+  int32_t n2t;      // sphere rings
+  int32_t ntof;
+  int32_t nrows, ncols, npix;
+  double R;
+  double tof_lo, tof_hi;
+  double phi_lo, phi_hi;  // rad, tube columns
+  double row_y[8];
+  double length, radius, n_he;
+};
+
+struct OSetup {
+  OBeam beam;
+  int32_t nscat;
+  int32_t K;         // maximum scattering order
+  OScatterer s[4];
+  ODetector det;
+  double min_prob;
+};
+
+struct ORecord {
+  uint64_t id;
+  uint32_t lineage;
+  int32_t order;
+  double pos[3], vel[3], t, w;  // state when leaving the sample assembly
+  int64_t bin;                  // -1: not recorded
+  double value;                 // contribution to the histogram
+  double tof;
+  int32_t tube;                 // -1 for the sphere or a miss
+  int32_t pixel;
+  double margin_anc;            // smallest normalised margin of the ancestors
+  double margin_own;            // smallest normalised margin of this packet
+  double value_sens;            // |d value / d lateral ray offset| (tubes)
+};
+
+struct OTally {
+  double w_escaped[8];      // sum of escaping weight per order
+  double w_detected[8];     // sum of recorded value per order
+  uint64_t n_packets[8];    // packets per order
+  uint64_t n_detected, n_missed, n_out_of_window, n_zero_weight;
+  uint64_t n_rng_blocks, n_transcend, n_sqrt, n_shape_tests, n_tube_tests,
+      n_table_steps, n_hist_updates;
+  double w_start[8];        // sum of weight at the start of each flight, per order
+  double w_scat[8];         // weight split off to scattering (before the kernel factor)
+  double w_abs[8];          // weight removed by absorption in split segments
+  double w_lost[8];         // weight removed in segments that were not split
+};
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 as defined by Salmon et al. (SC'11): ten rounds of
+// (hi,lo) = M * x on words 0 and 2, permuted with xor of the key; the key is
+// advanced by the Weyl constants between rounds.
+struct Block {
+  uint32_t w[4];
+};
+
+Block philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                    uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t p0 = (uint64_t)M0 * c0;
+    uint64_t p1 = (uint64_t)M1 * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  Block b = {{c0, c1, c2, c3}};
+  return b;
+}
+
+// 23 random bits -> an odd multiple of 2^-24 in (0,1); exact in binary32 too.
+inline double to_uniform(uint32_t x) {
+  return ((double)(x >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+struct Rng {
+  uint64_t seed;
+  OTally* tally;
+  // Four uniforms of block `block` in stream `stream` for packet (id, lineage).
+  void draw(uint64_t id, int stream, uint32_t lineage, uint32_t block, double u[4]) {
+    Block b = philox4x32_10((uint32_t)id, (uint32_t)(id >> 32) | ((uint32_t)stream << 30),
+                            lineage, block, (uint32_t)seed, (uint32_t)(seed >> 32));
+    for (int i = 0; i < 4; ++i) u[i] = to_uniform(b.w[i]);
+    tally->n_rng_blocks++;
+  }
+};
+
+// ------------------------------------------------------------- 3-vectors
+struct V3 {
+  double x, y, z;
+};
+inline V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 scale(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 cross(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+// y = M x with M row major
+inline V3 matvec(const double* m, V3 v) {
+  return {m[0] * v.x + m[1] * v.y + m[2] * v.z, m[3] * v.x + m[4] * v.y + m[5] * v.z,
+          m[6] * v.x + m[7] * v.y + m[8] * v.z};
+}
+// y = M^T x
+inline V3 matTvec(const double* m, V3 v) {
+  return {m[0] * v.x + m[3] * v.y + m[6] * v.z, m[1] * v.x + m[4] * v.y + m[7] * v.z,
+          m[2] * v.x + m[5] * v.y + m[8] * v.z};
+}
+
+// ------------------------------------------------------------- packets
+struct Packet {
+  V3 pos;
+  V3 dir;        // unit vector
+  double speed;  // m/s
+  double t;      // s
+  double w;      // probability weight
+  uint32_t lineage;
+  int order;
+  double margin_anc;  // min normalised margin of the decisions that made it
+};
+
+struct Interval {
+  double s_in, s_out;
+  int scat;  // scatterer index
+  int sub;   // interval index within the scatterer
+};
+
+// ------------------------------------------------------------- geometry
+// Ray p + s d (d unit).  Each routine returns the parameter interval(s) where
+// the ray is inside the shape, with no clipping to s >= 0.  `margin` is
+// lowered to the distance from a grazing or tangent decision.
+
+// Slab |p_a + s d_a| <= h along one axis.  Returns false if the ray misses.
+bool slab(double p, double d, double h, double* lo, double* hi, double* margin) {
+  if (d == 0.0) {
+    *margin = std::min(*margin, std::fabs(std::fabs(p) - h) / kTauGeom);
+    if (p < -h || p > h) return false;
+    *lo = -kHuge;
+    *hi = kHuge;
+    return true;
+  }
+  double s1 = (-h - p) / d, s2 = (h - p) / d;
+  *lo = std::min(s1, s2);
+  *hi = std::max(s1, s2);
+  return true;
+}
+
+// Infinite circular cylinder of radius r about the local y axis.
+bool radial(V3 p, V3 d, double r, double* lo, double* hi, double* margin) {
+  double a = d.x * d.x + d.z * d.z;
+  double c = p.x * p.x + p.z * p.z - r * r;
+  if (a == 0.0) {
+    double rho = std::sqrt(p.x * p.x + p.z * p.z);
+    *margin = std::min(*margin, std::fabs(rho - r) / kTauGeom);
+    if (c > 0.0) return false;
+    *lo = -kHuge;
+    *hi = kHuge;
+    return true;
+  }
+  // distance of closest approach to the axis in the x-z plane
+  double s_c = -(p.x * d.x + p.z * d.z) / a;
+  double qx = p.x + s_c * d.x, qz = p.z + s_c * d.z;
+  double b2 = qx * qx + qz * qz;
+  *margin = std::min(*margin, std::fabs(std::sqrt(b2) - r) / kTauGeom);
+  if (b2 >= r * r) return false;
+  double half = std::sqrt((r * r - b2) / a);
+  *lo = s_c - half;
+  *hi = s_c + half;
+  return true;
+}
+
+bool cylinder_interval(V3 p, V3 d, double r, double h, double* lo, double* hi,
+                       double* margin) {
+  double a0, a1, b0, b1;
+  if (!radial(p, d, r, &a0, &a1, margin)) return false;
+  if (!slab(p.y, d.y, 0.5 * h, &b0, &b1, margin)) return false;
+  *lo = std::max(a0, b0);
+  *hi = std::min(a1, b1);
+  if (a0 > -kHuge && b0 > -kHuge)
+    *margin = std::min(*margin, std::fabs(a0 - b0) / kTauGeom);
+  if (*lo < kHuge && *hi > -kHuge)
+    *margin = std::min(*margin, std::fabs(*hi - *lo) / kTauGeom);
+  return *hi > *lo;
+}
+
+int shape_intervals(const OShape& sh, V3 pl, V3 dl, double lo[2], double hi[2],
+                    double* margin) {
+  // pl, dl already in the shape frame
+  if (sh.type == SHAPE_BOX) {
+    double l[3], h[3];
+    if (!slab(pl.x, dl.x, 0.5 * sh.dims[0], &l[0], &h[0], margin)) return 0;
+    if (!slab(pl.y, dl.y, 0.5 * sh.dims[1], &l[1], &h[1], margin)) return 0;
+    if (!slab(pl.z, dl.z, 0.5 * sh.dims[2], &l[2], &h[2], margin)) return 0;
+    double L = std::max(l[0], std::max(l[1], l[2]));
+    double H = std::min(h[0], std::min(h[1], h[2]));
+    if (L < kHuge && H > -kHuge) *margin = std::min(*margin, std::fabs(H - L) / kTauGeom);
+    if (H <= L) return 0;
+    lo[0] = L;
+    hi[0] = H;
+    return 1;
+  }
+  if (sh.type == SHAPE_CYLINDER) {
+    if (!cylinder_interval(pl, dl, sh.dims[0], sh.dims[1], &lo[0], &hi[0], margin)) return 0;
+    return 1;
+  }
+  // ANNULUS: outer cylinder minus the inner cylinder of the same height
+  double a0, a1, b0, b1;
+  if (!cylinder_interval(pl, dl, sh.dims[1], sh.dims[2], &a0, &a1, margin)) return 0;
+  double mdummy = kHuge;
+  bool inner = cylinder_interval(pl, dl, sh.dims[0], sh.dims[2], &b0, &b1, &mdummy);
+  *margin = std::min(*margin, mdummy);
+  if (!inner || b1 <= a0 || b0 >= a1) {
+    lo[0] = a0;
+    hi[0] = a1;
+    return 1;
+  }
+  int n = 0;
+  if (b0 > a0) {
+    lo[n] = a0;
+    hi[n] = b0;
+    ++n;
+  }
+  if (a1 > b1) {
+    lo[n] = b1;
+    hi[n] = a1;
+    ++n;
+  }
+  return n;
+}
+
+// ------------------------------------------------------------- materials
+struct KernelInfo {
+  // host-side derived data for one kernel (FP64)
+  std::vector<double> d_sorted, f2_sorted;  // powder, by descending d
+  std::vector<double> cdf;                  // phonon, cumulative DOS (normalised)
+  double de = 0.0;                          // phonon bin width
+};
+
+struct ScatInfo {
+  KernelInfo k[3];
+  double dw_coef = 0.0;  // 2W / Q^2 in A^2, from the scatterer's phonon DOS
+};
+
+// gamma_0 = integral of coth(E/2kT) Z(E)/E dE over [0, Emax], midpoint rule on
+// the DOS bins; Z normalised to unit area (Supplement S4, multi-phonon).
+double gamma0(const OKernel& k) {
+  double de = k.emax / k.nbins;
+  double area = 0.0;
+  for (int b = 0; b < k.nbins; ++b) area += k.dos[b] * de;
+  double g = 0.0;
+  for (int b = 0; b < k.nbins; ++b) {
+    double e = (b + 0.5) * de;
+    double z = k.dos[b] / area;
+    g += (1.0 / std::tanh(e / (2.0 * kBoltzmann * k.T))) * z / e * de;
+  }
+  return g;
+}
+
+double hbar2_over_2M(double M_amu) { return kHbar2over2mn * kNeutronMassAmu / M_amu; }
+
+void prepare(const OSetup& S, std::vector<ScatInfo>& info) {
+  info.assign(S.nscat, ScatInfo());
+  for (int s = 0; s < S.nscat; ++s) {
+    const OScatterer& sc = S.s[s];
+    for (int j = 0; j < sc.nk; ++j) {
+      const OKernel& k = sc.k[j];
+      KernelInfo& ki = info[s].k[j];
+      if (k.type == K_POWDER) {
+        std::vector<int> idx(k.nrefl);
+        for (int i = 0; i < k.nrefl; ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](int a, int b) { return k.d[a] > k.d[b]; });
+        for (int i : idx) {
+          ki.d_sorted.push_back(k.d[i]);
+          ki.f2_sorted.push_back(k.F2[i]);
+        }
+      } else if (k.type == K_PHONON) {
+        ki.de = k.emax / k.nbins;
+        double area = 0.0;
+        for (int b = 0; b < k.nbins; ++b) area += k.dos[b];
+        double c = 0.0;
+        for (int b = 0; b < k.nbins; ++b) {
+          c += k.dos[b] / area;
+          ki.cdf.push_back(c);
+        }
+        info[s].dw_coef = hbar2_over_2M(k.M) * gamma0(k);
+      }
+    }
+  }
+}
+
+// linear attenuation coefficients, 1/m, of kernel j and of absorption
+// mu = 100 * n[1/A^3] * sigma[b]; absorption follows the 1/v law.
+struct Mu {
+  double k[3];
+  double scat, abs, total;
+};
+
+Mu attenuation(const OScatterer& sc, const ScatInfo& si, double speed, double* margin) {
+  Mu m;
+  double kk = k_from_speed(speed);
+  double lambda = 2.0 * kPi / kk;
+  m.scat = 0.0;
+  for (int j = 0; j < sc.nk; ++j) {
+    const OKernel& k = sc.k[j];
+    if (k.type == K_POWDER) {
+      // sum of Debye-Scherrer cone cross sections per unit volume:
+      // lambda^2 / (2 v0^2) * sum_{d > lambda/2} d |F|^2 (Supplement S4)
+      const KernelInfo& ki = si.k[j];
+      double sum = 0.0;
+      for (size_t i = 0; i < ki.d_sorted.size(); ++i) {
+        *margin = std::min(*margin, std::fabs(ki.d_sorted[i] - 0.5 * lambda) /
+                                        (kTauRel * ki.d_sorted[i]));
+        if (ki.d_sorted[i] > 0.5 * lambda) sum += ki.d_sorted[i] * ki.f2_sorted[i];
+      }
+      m.k[j] = 100.0 * lambda * lambda / (2.0 * k.v0 * k.v0) * sum;
+    } else {
+      m.k[j] = 100.0 * sc.n * k.sigma;
+    }
+    m.scat += m.k[j];
+  }
+  m.abs = 100.0 * sc.n * sc.sigma_abs * (kV2200 / speed);
+  m.total = m.scat + m.abs;
+  return m;
+}
+
+// ------------------------------------------------------------- kernels
+struct Scatter {
+  V3 dir;
+  double speed;
+  double factor;  // weight multiplier
+};
+
+V3 isotropic_direction(double u_cos, double u_phi) {
+  double c = 2.0 * u_cos - 1.0;
+  double s = std::sqrt(std::max(0.0, 1.0 - c * c));
+  double phi = 2.0 * kPi * u_phi;
+  return {s * std::cos(phi), s * std::sin(phi), c};
+}
+
+// Orthonormal basis perpendicular to a unit vector n (Duff et al., "Building
+// an Orthonormal Basis, Revisited", JCGT 6(1), 2017).
+void perp_basis(V3 n, V3* e1, V3* e2, double* margin) {
+  *margin = std::min(*margin, std::fabs(n.z) / 1e-6);
+  double sgn = n.z >= 0.0 ? 1.0 : -1.0;
+  double a = -1.0 / (sgn + n.z);
+  double b = n.x * n.y * a;
+  *e1 = {1.0 + sgn * n.x * n.x * a, sgn * b, -sgn * n.x};
+  *e2 = {b, sgn + n.y * n.y * a, -n.y};
+}
+
+// incoherent elastic: dsigma/dOmega = sigma_inc/4pi N e^{-2W} (Supplement S4)
+Scatter k_iso(const OKernel& k, const ScatInfo& si, const Packet& P, const double* u) {
+  Scatter r;
+  r.dir = isotropic_direction(u[2], u[3]);
+  r.speed = P.speed;
+  r.factor = 1.0;
+  if (k.dw) {
+    double kk = k_from_speed(P.speed);
+    V3 Q = sub(scale(P.dir, kk), scale(r.dir, kk));
+    r.factor = std::exp(-si.dw_coef * dot(Q, Q));
+  }
+  return r;
+}
+
+// powder Bragg: one Debye-Scherrer cone chosen with probability proportional
+// to its cross section; 2theta = 2 asin(lambda / 2d); uniform azimuth
+Scatter k_powder(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
+                 const Packet& P, const double* u, double* margin) {
+  Scatter r;
+  double kk = k_from_speed(P.speed);
+  double lambda = 2.0 * kPi / kk;
+  double total = 0.0;
+  size_t nact = 0;
+  for (size_t i = 0; i < ki.d_sorted.size(); ++i)
+    if (ki.d_sorted[i] > 0.5 * lambda) {
+      total += ki.d_sorted[i] * ki.f2_sorted[i];
+      nact = i + 1;
+    }
+  double target = u[2] * total;
+  double cum = 0.0;
+  size_t pick = nact - 1;
+  for (size_t i = 0; i < nact; ++i) {
+    cum += ki.d_sorted[i] * ki.f2_sorted[i];
+    *margin = std::min(*margin, std::fabs(target - cum) / (kTauRel * total));
+    if (target < cum) {
+      pick = i;
+      break;
+    }
+  }
+  double d = ki.d_sorted[pick];
+  double sin_b = lambda / (2.0 * d);
+  double two_theta = 2.0 * std::asin(sin_b);
+  double phi = 2.0 * kPi * u[3];
+  V3 e1, e2;
+  perp_basis(P.dir, &e1, &e2, margin);
+  V3 lateral = add(scale(e1, std::cos(phi)), scale(e2, std::sin(phi)));
+  r.dir = add(scale(P.dir, std::cos(two_theta)), scale(lateral, std::sin(two_theta)));
+  r.speed = P.speed;
+  r.factor = 1.0;
+  if (k.dw) {
+    double Q = 2.0 * kPi / d;
+    r.factor = std::exp(-si.dw_coef * Q * Q);
+  }
+  return r;
+}
+
+// incoherent one-phonon (Supplement S4):
+//   d2sigma/dOmega dEf = sigma/4pi (kf/ki) N (hbar^2 Q^2/2M) e^{-2W} Z(E)/E
+//                        * {coth(E/2kT) +- 1}/2
+// Proposal: E from Z, creation (+) with probability (coth+1)/(2 coth),
+// isotropic direction.  The ratio of the cross section per unit of sigma to
+// this proposal density is (kf/ki)(hbar^2 Q^2/2M) e^{-2W} coth(E/2kT)/E.
+Scatter k_phonon(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
+                 const Packet& P, const double* u, double* margin) {
+  Scatter r;
+  int b = 0;
+  for (; b < k.nbins; ++b)
+    if (u[2] < ki.cdf[b]) break;
+  if (b == k.nbins) b = k.nbins - 1;
+  double e = (b + u[3]) * ki.de;
+  double kT = kBoltzmann * k.T;
+  double nb = 1.0 / std::expm1(e / kT);  // Bose occupation
+  double p_create = (nb + 1.0) / (2.0 * nb + 1.0);
+  *margin = std::min(*margin, std::fabs(u[4] - p_create) / kTauU);
+  bool create = u[4] < p_create;
+  double Ei = kEperV2 * P.speed * P.speed;
+  double Ef = create ? Ei - e : Ei + e;
+  *margin = std::min(*margin, std::fabs(Ef) / (kTauRel * Ei));
+  r.dir = isotropic_direction(u[5], u[6]);
+  if (Ef <= 0.0) {
+    r.speed = P.speed;
+    r.factor = 0.0;
+    return r;
+  }
+  double k_i = k_from_speed(P.speed);
+  double k_f = std::sqrt(Ef / kHbar2over2mn);
+  r.speed = speed_from_k(k_f);
+  V3 Q = sub(scale(P.dir, k_i), scale(r.dir, k_f));
+  double Q2 = dot(Q, Q);
+  double h2m = hbar2_over_2M(k.M);
+  double dw = k.dw ? std::exp(-si.dw_coef * Q2) : 1.0;
+  double coth = 1.0 / std::tanh(e / (2.0 * kT));
+  r.factor = (k_f / k_i) * h2m * Q2 * dw * coth / e;
+  return r;
+}
+
+// dispersion surface S(Q) delta(E - E(Q)) with the delta broadened to a
+// Lorentzian of HWHM gamma; E(Q) = 4JS(3 - sum_a cos(Q_a a)); S(Q) = 1.
+// Proposal: isotropic direction, energy transfer uniform on [E_lo, E_hi].
+Scatter k_spinwave(const OKernel& k, const Packet& P, const double* u) {
+  Scatter r;
+  double Ei = kEperV2 * P.speed * P.speed;
+  double wmax = 24.0 * k.J * k.S;
+  double lo = -10.0 * k.gamma;
+  double hi = std::min(wmax + 10.0 * k.gamma, 0.99 * Ei);
+  r.dir = isotropic_direction(u[3], u[4]);
+  r.speed = P.speed;
+  if (hi <= lo) {
+    r.factor = 0.0;
+    return r;
+  }
+  double E = lo + u[2] * (hi - lo);
+  double Ef = Ei - E;
+  double k_i = k_from_speed(P.speed);
+  double k_f = std::sqrt(Ef / kHbar2over2mn);
+  r.speed = speed_from_k(k_f);
+  V3 Q = sub(scale(P.dir, k_i), scale(r.dir, k_f));
+  V3 Qc = matvec(k.crot, Q);
+  double w = 4.0 * k.J * k.S *
+             (3.0 - std::cos(Qc.x * k.a) - std::cos(Qc.y * k.a) - std::cos(Qc.z * k.a));
+  double x = E - w;
+  double lor = (k.gamma / kPi) / (x * x + k.gamma * k.gamma);
+  r.factor = (k_f / k_i) * lor * (hi - lo);
+  return r;
+}
+
+// tabulated isotropic S(Q,E): value of the grid cell containing (|Q|, E)
+Scatter k_sqe(const OKernel& k, const Packet& P, const double* u, double* margin) {
+  Scatter r;
+  double Ei = kEperV2 * P.speed * P.speed;
+  double E = k.Emin + u[2] * (k.Emax - k.Emin);
+  double Ef = Ei - E;
+  r.dir = isotropic_direction(u[3], u[4]);
+  r.speed = P.speed;
+  *margin = std::min(*margin, std::fabs(Ef) / (kTauRel * Ei));
+  if (Ef <= 0.0) {
+    r.factor = 0.0;
+    return r;
+  }
+  double k_i = k_from_speed(P.speed);
+  double k_f = std::sqrt(Ef / kHbar2over2mn);
+  r.speed = speed_from_k(k_f);
+  double Q = norm(sub(scale(P.dir, k_i), scale(r.dir, k_f)));
+  double fq = Q / k.Qmax * k.nQ;
+  double fe = (E - k.Emin) / (k.Emax - k.Emin) * k.nE;
+  *margin = std::min(*margin, std::fabs(fq - std::nearbyint(fq)) / (kTauRel * std::max(fq, 1.0)));
+  *margin = std::min(*margin, std::fabs(fe - std::nearbyint(fe)) / (kTauRel * std::max(fe, 1.0)));
+  int iq = (int)std::floor(fq);
+  int ie = (int)std::floor(fe);
+  if (ie < 0) ie = 0;
+  if (ie > k.nE - 1) ie = k.nE - 1;
+  if (iq >= k.nQ) {
+    r.factor = 0.0;
+    return r;
+  }
+  r.factor = (k_f / k_i) * k.sqe[iq * k.nE + ie] * (k.Emax - k.Emin);
+  return r;
+}
+
+// ------------------------------------------------------------- simulation
+struct Sim {
+  const OSetup& S;
+  std::vector<ScatInfo> info;
+  Rng rng;
+  double* hist;
+  double* hist_w2;
+  ORecord* recs;
+  uint64_t rec_cap;
+  uint64_t n_rec;
+  OTally* tally;
+
+  Sim(const OSetup& s) : S(s) {}
+
+  // ----- detector: sphere of radius R about the origin, rings in 2theta
+  void detect_sphere(const Packet& P, ORecord& rec, double* margin) {
+    const ODetector& D = S.det;
+    double b = dot(P.pos, P.dir);
+    double c = dot(P.pos, P.pos) - D.R * D.R;
+    if (c >= 0.0) return;  // already outside the sphere
+    double s = -b + std::sqrt(b * b - c);
+    V3 hit = add(P.pos, scale(P.dir, s));
+    double cz = std::max(-1.0, std::min(1.0, hit.z / D.R));
+    double tt = std::acos(cz);
+    double width = kPi / D.n2t;
+    int ring = (int)std::floor(tt / width);
+    if (ring > D.n2t - 1) ring = D.n2t - 1;
+    if (ring < 0) ring = 0;
+    // distance in cos(2theta) to the ring edges that bound this ring
+    double m_lo = ring > 0 ? std::fabs(cz - std::cos(ring * width)) : kHuge;
+    double m_hi = ring < D.n2t - 1 ? std::fabs(cz - std::cos((ring + 1) * width)) : kHuge;
+    *margin = std::min(*margin, std::min(m_lo, m_hi) / kTauCos);
+    double tof = P.t + s / P.speed;
+    rec.tof = tof;
+    double dt = (D.tof_hi - D.tof_lo) / D.ntof;
+    double ft = (tof - D.tof_lo) / dt;
+    int it = (int)std::floor(ft);
+    *margin = std::min(*margin, std::fabs(ft - std::nearbyint(ft)) * dt / (kTauTof * std::fabs(tof)));
+    if (ft < 0.0 || it >= D.ntof) {
+      tally->n_out_of_window++;
+      return;
+    }
+    rec.bin = (int64_t)ring * D.ntof + it;
+    rec.value = P.w;
+  }
+
+  // ----- detector: vertical 3He tubes on a cylinder of radius R
+  // brute force over every tube; the first tube on the ray records
+  void detect_tubes(const Packet& P, ORecord& rec, double* margin) {
+    const ODetector& D = S.det;
+    double best = kHuge, second = kHuge;
+    int best_tube = -1;
+    double best_out = 0.0, best_b = 0.0, best_dperp = 0.0;
+    double dphi = (D.phi_hi - D.phi_lo) / D.ncols;
+    for (int row = 0; row < D.nrows; ++row) {
+      for (int col = 0; col < D.ncols; ++col) {
+        tally->n_tube_tests++;
+        double phi = D.phi_lo + (col + 0.5) * dphi;
+        V3 c = {D.R * std::sin(phi), D.row_y[row], D.R * std::cos(phi)};
+        V3 p = sub(P.pos, c);
+        double lo, hi, m = kHuge;
+        // radial part with the impact parameter kept for the margin
+        double a = P.dir.x * P.dir.x + P.dir.z * P.dir.z;
+        if (a == 0.0) continue;
+        double s_c = -(p.x * P.dir.x + p.z * P.dir.z) / a;
+        double qx = p.x + s_c * P.dir.x, qz = p.z + s_c * P.dir.z;
+        double bimp = std::sqrt(qx * qx + qz * qz);
+        if (std::fabs(bimp - D.radius) < kTauImpact * D.radius) *margin = std::min(*margin, std::fabs(bimp - D.radius) / (kTauImpact * D.radius));
+        if (!cylinder_interval(p, P.dir, D.radius, D.length, &lo, &hi, &m)) {
+          if (bimp < D.radius) *margin = std::min(*margin, m);
+          continue;
+        }
+        if (bimp < D.radius) *margin = std::min(*margin, m);
+        if (hi <= 0.0) continue;
+        double s_in = std::max(lo, 0.0);
+        if (s_in < best) {
+          second = best;
+          best = s_in;
+          best_tube = row * D.ncols + col;
+          best_out = hi;
+          best_b = bimp;
+          best_dperp = std::sqrt(a);
+        } else if (s_in < second) {
+          second = s_in;
+        }
+      }
+    }
+    if (best_tube < 0) {
+      tally->n_missed++;
+      return;
+    }
+    if (second < kHuge) *margin = std::min(*margin, (second - best) / kTauGeom);
+    double chord = best_out - best;
+    double mu = 100.0 * D.n_he * kHe3SigmaAbs * (kV2200 / P.speed);
+    double pabs = -std::expm1(-mu * chord);
+    double u[4];
+    rng.draw(rec.id, STREAM_DETECT, P.lineage, 0, u);
+    double s_a = best - std::log1p(-u[0] * pabs) / mu;
+    double y_a = P.pos.y + s_a * P.dir.y;
+    int row = best_tube / D.ncols;
+    double y_bot = D.row_y[row] - 0.5 * D.length;
+    double fp = (y_a - y_bot) / D.length * D.npix;
+    int pix = (int)std::floor(fp);
+    if (pix < 0) pix = 0;
+    if (pix > D.npix - 1) pix = D.npix - 1;
+    double ym = std::fabs(fp - std::nearbyint(fp)) * D.length / D.npix;
+    if (std::nearbyint(fp) > 0 && std::nearbyint(fp) < D.npix) *margin = std::min(*margin, ym / kTauGeom);
+    double tof = P.t + s_a / P.speed;
+    rec.tof = tof;
+    rec.tube = best_tube;
+    rec.pixel = pix;
+    double dt = (D.tof_hi - D.tof_lo) / D.ntof;
+    double ft = (tof - D.tof_lo) / dt;
+    int it = (int)std::floor(ft);
+    *margin = std::min(*margin, std::fabs(ft - std::nearbyint(ft)) * dt / (kTauTof * std::fabs(tof)));
+    // sensitivity of the recorded value to a sideways shift of the ray
+    double rr = D.radius * D.radius - best_b * best_b;
+    if (rr > 0.0)
+      rec.value_sens = P.w * mu * std::exp(-mu * chord) * 2.0 * best_b / (std::sqrt(rr) * best_dperp);
+    if (ft < 0.0 || it >= D.ntof) {
+      tally->n_out_of_window++;
+      return;
+    }
+    rec.bin = ((int64_t)best_tube * D.npix + pix) * D.ntof + it;
+    rec.value = P.w * pabs;
+  }
+
+  void detect(const Packet& P, uint64_t id, double flight_margin) {
+    ORecord rec;
+    std::memset(&rec, 0, sizeof(rec));
+    rec.id = id;
+    rec.lineage = P.lineage;
+    rec.order = P.order;
+    rec.pos[0] = P.pos.x; rec.pos[1] = P.pos.y; rec.pos[2] = P.pos.z;
+    rec.vel[0] = P.dir.x * P.speed; rec.vel[1] = P.dir.y * P.speed; rec.vel[2] = P.dir.z * P.speed;
+    rec.t = P.t;
+    rec.w = P.w;
+    rec.bin = -1;
+    rec.tube = -1;
+    rec.pixel = -1;
+    rec.margin_anc = P.margin_anc;
+    double margin = kHuge;
+    if (S.det.type == DET_SPHERE) detect_sphere(P, rec, &margin);
+    else detect_tubes(P, rec, &margin);
+    rec.margin_own = std::min(flight_margin, margin);
+    tally->w_escaped[P.order] += P.w;
+    if (rec.bin >= 0) {
+      hist[rec.bin] += rec.value;
+      if (hist_w2) hist_w2[rec.bin] += rec.value * rec.value;
+      tally->n_detected++;
+      tally->n_hist_updates++;
+      tally->w_detected[P.order] += rec.value;
+    }
+    if (recs && n_rec < rec_cap) recs[n_rec] = rec;
+    n_rec++;
+  }
+
+  // ----- one flight of a packet through the assembly; returns its children
+  // Sec. 2.4.3 / Supplement S3: each material interval on the ray splits the
+  // packet; the transmitted part keeps flying, the scattered part starts at a
+  // point of the interval drawn from the truncated exponential.
+  void fly(Packet& P, uint64_t id, std::vector<Packet>& children, double* own_margin) {
+    std::vector<Interval> segs;
+    for (int s = 0; s < S.nscat; ++s) {
+      const OShape& sh = S.s[s].shape;
+      V3 pl = matTvec(sh.rot, sub(P.pos, {sh.pos[0], sh.pos[1], sh.pos[2]}));
+      V3 dl = matTvec(sh.rot, P.dir);
+      double lo[2], hi[2];
+      tally->n_shape_tests++;
+      int n = shape_intervals(sh, pl, dl, lo, hi, own_margin);
+      for (int i = 0; i < n; ++i) {
+        *own_margin = std::min(*own_margin, std::fabs(hi[i] - kSurfaceEps) / kTauGeom);
+        if (hi[i] <= kSurfaceEps) continue;  // behind or leaving through this surface
+        *own_margin = std::min(*own_margin, std::fabs(lo[i]) / kTauGeom);
+        Interval iv = {std::max(lo[i], 0.0), hi[i], s, i};
+        segs.push_back(iv);
+      }
+    }
+    std::stable_sort(segs.begin(), segs.end(),
+                     [](const Interval& a, const Interval& b) { return a.s_in < b.s_in; });
+    V3 start = P.pos;
+    double t0 = P.t;
+    for (size_t g = 0; g < segs.size(); ++g) {
+      const Interval& iv = segs[g];
+      const OScatterer& sc = S.s[iv.scat];
+      const ScatInfo& si = info[iv.scat];
+      double L = iv.s_out - iv.s_in;
+      double m_mu = kHuge;
+      Mu mu = attenuation(sc, si, P.speed, &m_mu);
+      *own_margin = std::min(*own_margin, m_mu);
+      double att = std::exp(-mu.total * L);
+      double a = -std::expm1(-mu.total * L);  // probability to interact
+      tally->n_transcend += 2;
+      if (P.order < S.K && P.w >= S.min_prob && mu.scat > 0.0) {
+        uint32_t lin = P.lineage * 8u + (uint32_t)g + 1u;
+        double u[8];
+        rng.draw(id, STREAM_SCATTER, lin, 0, u);
+        rng.draw(id, STREAM_SCATTER, lin, 1, u + 4);
+        // forced collision: x ~ mu e^{-mu x} / (1 - e^{-mu L}) on [0, L]
+        double x = -std::log1p(-u[0] * a) / mu.total;
+        tally->n_transcend++;
+        double child_margin = *own_margin;
+        Packet C;
+        C.pos = add(start, scale(P.dir, iv.s_in + x));
+        C.t = t0 + (iv.s_in + x) / P.speed;
+        C.dir = P.dir;
+        C.speed = P.speed;
+        C.w = P.w * (mu.scat / mu.total) * a;
+        tally->w_abs[P.order] += P.w * (mu.abs / mu.total) * a;
+        tally->w_scat[P.order] += C.w;
+        // kernel choice with probability mu_k / mu_s
+        double target = u[1] * mu.scat;
+        double cum = 0.0;
+        int kk = sc.nk - 1;
+        for (int j = 0; j < sc.nk; ++j) {
+          cum += mu.k[j];
+          if (j < sc.nk - 1)
+            child_margin = std::min(child_margin, std::fabs(target - cum) / (kTauRel * mu.scat));
+          if (target < cum) {
+            kk = j;
+            break;
+          }
+        }
+        const OKernel& k = sc.k[kk];
+        Scatter r;
+        Packet Pin = P;  // state of the incident packet at the scattering point
+        switch (k.type) {
+          case K_ISO_EL: r = k_iso(k, si, Pin, u); break;
+          case K_POWDER: r = k_powder(k, si.k[kk], si, Pin, u, &child_margin); break;
+          case K_PHONON: r = k_phonon(k, si.k[kk], si, Pin, u, &child_margin); break;
+          case K_SPINWAVE: r = k_spinwave(k, Pin, u); break;
+          default: r = k_sqe(k, Pin, u, &child_margin); break;
+        }
+        tally->n_transcend += 4;
+        C.dir = r.dir;
+        C.speed = r.speed;
+        C.w *= r.factor;
+        C.lineage = lin;
+        C.order = P.order + 1;
+        C.margin_anc = std::min(P.margin_anc, child_margin);
+        if (C.w > 0.0) children.push_back(C);
+        else tally->n_zero_weight++;
+      } else {
+        tally->w_lost[P.order] += P.w * a;
+      }
+      P.w *= att;
+    }
+    if (!segs.empty()) {
+      double s_end = segs.back().s_out;
+      P.pos = add(start, scale(P.dir, s_end));
+      P.t = t0 + s_end / P.speed;
+    }
+  }
+
+  void process(Packet& P, uint64_t id) {
+    tally->n_packets[P.order]++;
+    tally->w_start[P.order] += P.w;
+    std::vector<Packet> children;
+    double own = kHuge;
+    fly(P, id, children, &own);
+    detect(P, id, own);
+    // depth first; the order is immaterial because every random number is
+    // addressed by (id, stream, lineage, block)
+    for (Packet& C : children) process(C, id);
+  }
+
+  void source(uint64_t id, Packet& P) {
+    const OBeam& B = S.beam;
+    double u[4];
+    double E = B.E;
+    uint32_t block = 0;
+    rng.draw(id, STREAM_SOURCE, 1u, block, u);
+    double x = (u[0] - 0.5) * B.W;
+    double y = (u[1] - 0.5) * B.H;
+    if (B.type == BEAM_GAUSS) {
+      for (;;) {
+        // Box-Muller on the last two words of the block
+        E = B.E * (1.0 + B.sigma_rel * std::sqrt(-2.0 * std::log(u[2])) * std::cos(2.0 * kPi * u[3]));
+        if (E > 0.0) break;
+        rng.draw(id, STREAM_SOURCE, 1u, ++block, u);
+      }
+    }
+    P.pos = {x, y, B.z0};
+    P.dir = {0.0, 0.0, 1.0};
+    P.speed = std::sqrt(E / kEperV2);
+    P.t = B.z0 / P.speed;
+    P.w = 1.0;
+    P.lineage = 1u;
+    P.order = 0;
+    P.margin_anc = kHuge;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int oracle_abi_version(void) { return 3; }
+int oracle_sizeof_setup(void) { return (int)sizeof(OSetup); }
+int oracle_sizeof_record(void) { return (int)sizeof(ORecord); }
+int oracle_sizeof_tally(void) { return (int)sizeof(OTally); }
+
+void oracle_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                   uint32_t out[4]) {
+  Block b = philox4x32_10(c0, c1, c2, c3, k0, k1);
+  for (int i = 0; i < 4; ++i) out[i] = b.w[i];
+}
+
+double oracle_uniform(uint32_t x) { return to_uniform(x); }
+
+// Intervals of one shape along a ray (lab frame), for geometry pins.
+int oracle_shape_intervals(const OShape* sh, const double p[3], const double d[3], double lo[2],
+                           double hi[2]) {
+  V3 P = {p[0], p[1], p[2]}, D = {d[0], d[1], d[2]};
+  V3 pl = matTvec(sh->rot, sub(P, {sh->pos[0], sh->pos[1], sh->pos[2]}));
+  V3 dl = matTvec(sh->rot, D);
+  double m = kHuge;
+  return shape_intervals(*sh, pl, dl, lo, hi, &m);
+}
+
+// Attenuation coefficients (1/m) of scatterer s at speed v: out = {mu_k[0..2], mu_s, mu_abs}.
+void oracle_attenuation(const OSetup* S, int s, double speed, double out[5]) {
+  std::vector<ScatInfo> info;
+  prepare(*S, info);
+  double m = kHuge;
+  Mu mu = attenuation(S->s[s], info[s], speed, &m);
+  for (int j = 0; j < 3; ++j) out[j] = j < S->s[s].nk ? mu.k[j] : 0.0;
+  out[3] = mu.scat;
+  out[4] = mu.abs;
+}
+
+// Debye-Waller coefficient 2W/Q^2 (A^2) of scatterer s, and gamma_0 of kernel j.
+double oracle_dw_coef(const OSetup* S, int s) {
+  std::vector<ScatInfo> info;
+  prepare(*S, info);
+  return info[s].dw_coef;
+}
+double oracle_gamma0(const OKernel* k) { return gamma0(*k); }
+
+// One kernel draw for an incident packet with speed v along dir, with the
+// eight uniforms u[0..7] (u[2..7] are the kernel's).  out = {vx,vy,vz,factor}.
+void oracle_kernel_sample(const OSetup* S, int s, int j, const double dir[3], double speed,
+                          const double u[8], double out[4]) {
+  std::vector<ScatInfo> info;
+  prepare(*S, info);
+  Packet P;
+  std::memset(&P, 0, sizeof(P));
+  P.dir = {dir[0], dir[1], dir[2]};
+  P.speed = speed;
+  double m = kHuge;
+  const OKernel& k = S->s[s].k[j];
+  Scatter r;
+  switch (k.type) {
+    case K_ISO_EL: r = k_iso(k, info[s], P, u); break;
+    case K_POWDER: r = k_powder(k, info[s].k[j], info[s], P, u, &m); break;
+    case K_PHONON: r = k_phonon(k, info[s].k[j], info[s], P, u, &m); break;
+    case K_SPINWAVE: r = k_spinwave(k, P, u); break;
+    default: r = k_sqe(k, P, u, &m); break;
+  }
+  out[0] = r.dir.x * r.speed;
+  out[1] = r.dir.y * r.speed;
+  out[2] = r.dir.z * r.speed;
+  out[3] = r.factor;
+}
+
+// Full transport of histories [first, first+n).  hist (and hist_w2 if not
+// null) are accumulated into.  Records of every escaping packet go to recs
+// (up to rec_cap); *n_rec gets the total count.
+int oracle_run(const OSetup* S, uint64_t seed, uint64_t first, uint64_t n, double* hist,
+               double* hist_w2, ORecord* recs, uint64_t rec_cap, uint64_t* n_rec, OTally* tally) {
+  if (S->K < 0 || S->K > 7) return 1;
+  std::memset(tally, 0, sizeof(OTally));
+  Sim sim(*S);
+  prepare(*S, sim.info);
+  sim.rng.seed = seed;
+  sim.rng.tally = tally;
+  sim.hist = hist;
+  sim.hist_w2 = hist_w2;
+  sim.recs = recs;
+  sim.rec_cap = rec_cap;
+  sim.n_rec = 0;
+  sim.tally = tally;
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t id = first + i;
+    Packet P;
+    sim.source(id, P);
+    sim.process(P, id);
+  }
+  if (n_rec) *n_rec = sim.n_rec;
+  return 0;
+}
+
+}  // extern "C"

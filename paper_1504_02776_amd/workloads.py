@@ -1,0 +1,247 @@
+"""Seeded synthetic workloads: beam, sample assembly, detector and tables.
+
+This module only *describes inputs*.  It holds none of the transport method's
+arithmetic (no attenuation, no kernel sampling, no table normalisation, no
+Debye-Waller integral): the GPU library and the CPU oracle each derive what
+they need from these raw inputs on their own.  It is the one module both
+sides read.
+
+Every floating-point table is rounded to binary32 and handed out as float64,
+so both sides start from bit-identical values.
+
+The workloads stand in for the paper's measured experiments (Sec. 3: a
+vanadium plate, an aluminium plate, a K2V3O8 crystal on ARCS, SEQUOIA and
+HYSPEC), whose data, beam models and phonon tables are not available: the
+sample shapes and kernel types follow the paper, the numbers are synthetic.
+"""
+
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+IDENTITY = [1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0]
+
+# Only used to place time-of-flight windows around the elastic arrival time of
+# each workload; E[meV] = 5.22703759e-6 v[m/s]^2 (CODATA 2018).
+_E_PER_V2 = 5.22703759e-6
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def _elastic_time(E_meV: float, R: float) -> float:
+    return R / math.sqrt(E_meV / _E_PER_V2)
+
+
+def _tof_window(E_meV, R, lo, hi):
+    te = _elastic_time(E_meV, R)
+    return float(np.float32(lo * te)), float(np.float32(hi * te))
+
+
+def beam(E, sigma_rel=0.0, W=0.02, H=0.02, z0=-0.1):
+    """Uniform W x H beam, collimated along +z, starting at z = z0."""
+    return {"type": "gauss" if sigma_rel > 0 else "mono", "E": float(E),
+            "sigma_rel": float(sigma_rel), "W": W, "H": H, "z0": z0}
+
+
+def box(x, y, z, pos=(0.0, 0.0, 0.0), rot=IDENTITY):
+    return {"type": "box", "dims": [x, y, z], "pos": list(pos), "rot": list(rot)}
+
+
+def cylinder(r, h, pos=(0.0, 0.0, 0.0), rot=IDENTITY):
+    return {"type": "cylinder", "dims": [r, h, 0.0], "pos": list(pos), "rot": list(rot)}
+
+
+def annulus(r_in, r_out, h, pos=(0.0, 0.0, 0.0), rot=IDENTITY):
+    return {"type": "annulus", "dims": [r_in, r_out, h], "pos": list(pos), "rot": list(rot)}
+
+
+def iso_el(sigma, dw=0):
+    return {"type": "iso_el", "sigma": float(sigma), "dw": int(dw)}
+
+
+def powder(v0, d, F2, dw=0):
+    return {"type": "powder", "sigma": 0.0, "v0": float(v0), "d": _f32(d), "F2": _f32(F2),
+            "dw": int(dw)}
+
+
+def phonon(sigma, M, T, emax, dos, dw=1):
+    return {"type": "phonon", "sigma": float(sigma), "M": float(M), "T": float(T),
+            "emax": float(emax), "dos": _f32(dos), "dw": int(dw)}
+
+
+def spinwave(sigma, J, S, a, gamma, crot=IDENTITY):
+    return {"type": "spinwave", "sigma": float(sigma), "J": float(J), "S": float(S),
+            "a": float(a), "gamma": float(gamma), "crot": list(crot), "dw": 0}
+
+
+def sqe_grid(sigma, Qmax, Emin, Emax, S):
+    S = _f32(S)
+    return {"type": "sqe", "sigma": float(sigma), "Qmax": float(Qmax), "Emin": float(Emin),
+            "Emax": float(Emax), "S": S, "nQ": int(S.shape[0]), "nE": int(S.shape[1]), "dw": 0}
+
+
+def scatterer(shape, n, sigma_abs, kernels):
+    return {"shape": shape, "n": float(n), "sigma_abs": float(sigma_abs), "kernels": kernels}
+
+
+def sphere_detector(R, n2t, ntof, tof_lo, tof_hi):
+    return {"type": "sphere", "R": R, "n2t": n2t, "ntof": ntof, "tof_lo": tof_lo,
+            "tof_hi": tof_hi}
+
+
+def tube_detector(nrows, ncols, npix, ntof, tof_lo, tof_hi, R=3.0, radius=0.0127,
+                  length=1.0, phi_lo_deg=10.0, phi_hi_deg=134.0,
+                  row_y=(-1.53, -0.51, 0.51, 1.53), n_he=2.44634e-4):
+    """Vertical 3He tubes on a cylinder of radius R about the vertical axis.
+
+    n_he: 3He number density in atoms/A^3 (10 atm at 300 K is 2.44634e-4).
+    """
+    return {"type": "tubes", "R": R, "nrows": nrows, "ncols": ncols, "npix": npix,
+            "ntof": ntof, "tof_lo": tof_lo, "tof_hi": tof_hi, "radius": radius,
+            "length": length, "phi_lo": math.radians(phi_lo_deg),
+            "phi_hi": math.radians(phi_hi_deg), "row_y": list(row_y), "n_he": n_he}
+
+
+# --------------------------------------------------------------- tables
+def synthetic_dos(rng, nbins=500, emax=50.0):
+    """Raw smooth DOS: e^2 times three Gaussians, rolled off towards emax.
+
+    Values at bin centres; not normalised (normalisation is the method's).
+    """
+    e = (np.arange(nbins) + 0.5) * (emax / nbins)
+    a = rng.uniform(0.5, 1.5, 3)
+    c = rng.uniform(10.0, 45.0, 3)
+    s = rng.uniform(2.0, 6.0, 3)
+    g = sum(a[i] * np.exp(-0.5 * ((e - c[i]) / s[i]) ** 2) for i in range(3))
+    return _f32(e * e * g * (1.0 - (e / emax) ** 8)), (a, c, s)
+
+
+def shifted_dos(params, shift, nbins=500, emax=50.0):
+    a, c, s = params
+    e = (np.arange(nbins) + 0.5) * (emax / nbins)
+    g = sum(a[i] * np.exp(-0.5 * ((e - c[i] * shift) / s[i]) ** 2) for i in range(3))
+    return _f32(e * e * g * (1.0 - (e / emax) ** 8))
+
+
+def random_reflections(rng, n=50, dmin=1.0, dmax=5.0, fmin=1.0, fmax=100.0):
+    d = rng.uniform(dmin, dmax, n)
+    F2 = np.exp(rng.uniform(math.log(fmin), math.log(fmax), n))
+    return _f32(d), _f32(F2)
+
+
+def fcc_shells(a=4.05, dmin=0.5, bc_fm=3.449):
+    """Reflections of an fcc lattice (h,k,l all even or all odd) grouped by
+    |hkl|^2, d >= dmin.  F2 = multiplicity * 16 b_c^2 in barn."""
+    nmax = int(math.ceil(a / dmin)) + 1
+    counts = {}
+    for h in range(-nmax, nmax + 1):
+        for k in range(-nmax, nmax + 1):
+            for l in range(-nmax, nmax + 1):
+                if (h, k, l) == (0, 0, 0):
+                    continue
+                if not (h % 2 == k % 2 == l % 2):
+                    continue
+                n2 = h * h + k * k + l * l
+                if a / math.sqrt(n2) < dmin:
+                    continue
+                counts[n2] = counts.get(n2, 0) + 1
+    keys = sorted(counts)
+    bc2 = (bc_fm * 1e-15) ** 2 / 1e-28  # barn
+    d = [a / math.sqrt(n2) for n2 in keys]
+    F2 = [counts[n2] * 16.0 * bc2 for n2 in keys]
+    return _f32(d), _f32(F2)
+
+
+# --------------------------------------------------------------- workloads
+def plate_config(N=100_000, seed=0):
+    """Plain method, small: isotropic incoherent plate, single scattering,
+    spherical detector 180 x 100."""
+    E = 60.0
+    lo, hi = _tof_window(E, 3.0, 0.5, 2.0)
+    return {
+        "name": "plate-iso-sphere",
+        "beam": beam(E),
+        "scatterers": [scatterer(box(0.05, 0.05, 0.002), 0.08, 2.0, [iso_el(5.0)])],
+        "detector": sphere_detector(3.0, 180, 100, lo, hi),
+        "K": 1, "min_prob": 0.0, "N": N, "seed": seed,
+    }
+
+
+def powder_config(N=10_000_000, seed=0, dos_shift=1.0):
+    """Powder cylinder: Bragg (50 random reflections) + incoherent one-phonon
+    from a smooth 500-bin DOS at 300 K, Debye-Waller on, 3 orders, 1000
+    tubes x 128 pixels x 1000 tof bins."""
+    rng = np.random.default_rng(0)
+    d, F2 = random_reflections(rng)
+    dos, params = synthetic_dos(rng)
+    if dos_shift != 1.0:
+        dos = shifted_dos(params, dos_shift)
+    E = 100.0
+    lo, hi = _tof_window(E, 3.0, 0.7, 2.0)
+    return {
+        "name": "powder-cylinder-tubes",
+        "beam": beam(E, sigma_rel=0.02),
+        "scatterers": [scatterer(cylinder(0.01, 0.05), 0.08, 2.0, [
+            powder(100.0, d, F2, dw=1),
+            phonon(5.0, 50.9415, 300.0, 50.0, dos, dw=1),
+        ])],
+        "detector": tube_detector(4, 250, 128, 1000, lo, hi),
+        "K": 3, "min_prob": 0.0, "N": N, "seed": seed,
+    }
+
+
+def crystal_config(N=100_000_000, seed=0):
+    """Single-crystal slab with a nearest-neighbour cubic spin wave inside an
+    aluminium-like annular can; 3 orders; 2000 tubes x 128 x 500."""
+    d, F2 = fcc_shells()
+    E = 50.0
+    lo, hi = _tof_window(E, 3.0, 0.8, 2.0)
+    return {
+        "name": "crystal-can-tubes",
+        "beam": beam(E),
+        "scatterers": [
+            scatterer(box(0.015, 0.03, 0.003), 0.08, 2.0, [
+                spinwave(4.0, 2.0, 0.5, 4.0, 0.5), iso_el(1.0)]),
+            scatterer(annulus(0.010, 0.011, 0.05), 0.0602, 0.23, [
+                powder(4.05 ** 3, d, F2, dw=0), iso_el(0.008)]),
+        ],
+        "detector": tube_detector(4, 500, 128, 500, lo, hi, radius=0.00635),
+        "K": 3, "min_prob": 0.0, "N": N, "seed": seed,
+    }
+
+
+def sqe_config(N=20_000, seed=0):
+    """Tabulated isotropic S(Q,E) in a plate (no measured workload uses it)."""
+    rng = np.random.default_rng(7)
+    nQ, nE = 100, 100
+    Q = (np.arange(nQ) + 0.5) * (12.0 / nQ)
+    Ev = -10.0 + (np.arange(nE) + 0.5) * (60.0 / nE)
+    S = np.exp(-((Ev[None, :] - 20.0 * np.sin(Q[:, None] / 4.0)) / 4.0) ** 2) + \
+        0.05 * rng.uniform(size=(nQ, nE))
+    E = 60.0
+    lo, hi = _tof_window(E, 3.0, 0.5, 2.5)
+    return {
+        "name": "plate-sqe-sphere",
+        "beam": beam(E),
+        "scatterers": [scatterer(box(0.05, 0.05, 0.004), 0.08, 1.0,
+                                 [sqe_grid(3.0, 12.0, -10.0, 50.0, S), iso_el(1.0)])],
+        "detector": sphere_detector(3.0, 180, 100, lo, hi),
+        "K": 2, "min_prob": 0.0, "N": N, "seed": seed,
+    }
+
+
+def with_n(cfg, N):
+    c = copy.deepcopy(cfg)
+    c["N"] = int(N)
+    return c
+
+
+def detector_nbins(det):
+    if det["type"] == "sphere":
+        return det["n2t"] * det["ntof"]
+    return det["nrows"] * det["ncols"] * det["npix"] * det["ntof"]
