@@ -1,0 +1,256 @@
+/* mcv.h -- C ABI of the MI355X weighted neutron-transport library.
+ *
+ * The calls follow the paper's statement of the problem (arXiv:1504.02776,
+ * Sec. 3 four-step workflow): a beam of neutron packets is sent through a
+ * sample assembly (Sec. 2.4.1-2.4.3, composite scatterer, multiple
+ * scattering; Supplement S3), the scattered packets are intercepted by a
+ * detector system (Sec. 2.4.3, "Ray tracing in a detector system"), and the
+ * intensity of a (pixel, time-of-flight) bin is the sum of the probabilities
+ * of the packets recorded in it (Sec. 3, "Reduction").
+ *
+ * Conventions
+ *   - Every call returns an mcv_status; mcv_last_error() gives a message for
+ *     the last failing call of the calling thread.  No exception crosses the
+ *     ABI.  A device fault of an earlier asynchronous launch is reported by a
+ *     later call or by mcv_sync().
+ *   - Units: energies meV; cross sections barn (absorption at 2200 m/s, 1/v
+ *     law); number densities atoms per cubic angstrom; d-spacings, lattice
+ *     constants angstrom; cell volumes cubic angstrom; geometry metre; time
+ *     second; temperature kelvin; masses atomic mass units.
+ *   - Lab frame: beam along +z, y vertical.  t = 0 when an incident packet
+ *     crosses z = 0.
+ *   - Handles (mcv_assembly, mcv_detector, mcv_plan) belong to the library
+ *     and are released with their *_destroy call.  Host arrays passed to the
+ *     builders are copied during the call.  Device buffers (histograms, packet
+ *     records, counters, gradients, workspaces) belong to the caller; the
+ *     library never frees them.
+ *   - Streams are passed as `void*` holding a hipStream_t (NULL: the null
+ *     stream).  Launches are asynchronous on that stream.
+ *   - Precision: packet state and kernel sampling in binary32; histogram
+ *     accumulation in binary64; host-side table preparation in binary64,
+ *     stored as binary32 on the device.
+ */
+#ifndef MCV_H
+#define MCV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MCV_OK = 0,
+  MCV_EINVAL = 1,        /* bad argument; nothing was launched or changed */
+  MCV_EUNSUPPORTED = 2,  /* outside the supported configuration space     */
+  MCV_EOVERLAP = 3,      /* scatterer volumes may overlap                 */
+  MCV_ENOMEM = 4,        /* device or host allocation failed              */
+  MCV_ECAPACITY = 5,     /* an output buffer is too small                 */
+  MCV_EHIP = 6           /* a HIP runtime call failed                     */
+} mcv_status;
+
+typedef struct mcv_assembly_s* mcv_assembly;
+typedef struct mcv_detector_s* mcv_detector;
+typedef struct mcv_plan_s* mcv_plan;
+
+/* ---------------------------------------------------------------- shapes */
+enum { MCV_SHAPE_BOX = 1, MCV_SHAPE_CYLINDER = 2, MCV_SHAPE_ANNULUS = 3 };
+
+/* Sec. 2.4.2 (shapes of homogeneous scatterers).
+ * BOX: dims = full lengths along local x, y, z.
+ * CYLINDER: dims = {radius, height, unused}; axis = local y.
+ * ANNULUS: dims = {inner radius, outer radius, height}; the outer cylinder
+ *   minus the inner cylinder of the same height (a can wall, open ends).
+ * pos: lab position of the shape centre; rot: local->lab rotation (row
+ * major, orthonormal). */
+typedef struct {
+  int32_t type;
+  int32_t reserved;
+  double dims[3];
+  double pos[3];
+  double rot[9];
+} mcv_shape;
+
+/* Homogeneous material: n atoms/A^3 (or formula units, consistent with the
+ * kernels' sigma), absorption cross section sigma_abs at 2200 m/s. */
+typedef struct {
+  double n_per_A3;
+  double sigma_abs_b;
+} mcv_material;
+
+/* --------------------------------------------------------------- kernels */
+enum {
+  MCV_K_ISO_EL = 1,    /* incoherent elastic (Supplement S4)                  */
+  MCV_K_POWDER = 2,    /* coherent elastic powder, Debye-Scherrer cones (S4)  */
+  MCV_K_PHONON = 3,    /* incoherent one-phonon from a DOS (S4)               */
+  MCV_K_SPINWAVE = 4,  /* dispersion surface E(Q), S(Q) = 1, Lorentzian (S4)  */
+  MCV_K_SQE = 5        /* tabulated isotropic S(Q,E) (Sec. 2.4.2)             */
+};
+
+/* One scattering kernel.  Only the fields of `type` are read.
+ *   sigma_b: nominal cross section per atom; the kernel's attenuation
+ *     coefficient is 100 n sigma_b per metre (not used by POWDER, whose cross
+ *     section is the sum of its cones at the packet's wavelength).
+ *   dw: 1 = multiply by the Debye-Waller factor exp(-2W), 2W = (hbar^2 Q^2 /
+ *     2M) gamma_0, with M, T and gamma_0 from the PHONON kernel of the same
+ *     scatterer (which must exist).
+ *   POWDER: v0 cell volume; nrefl reflections with d-spacing d[i] and
+ *     F2[i] = multiplicity * |F|^2 per cell (barn).
+ *   PHONON: mass M_amu, temperature T_K (> 0), nbins DOS values dos[] (raw,
+ *     >= 0, normalised by the library) on bins of width emax/nbins over
+ *     [0, emax].
+ *   SPINWAVE: E(Q) = 4 J S (3 - sum_a cos(Q_a a)), Q in the crystal frame
+ *     crot * Q_lab; gamma = Lorentzian HWHM.
+ *   SQE: S(Q,E) on nQ x nE cells over [0, Qmax] x [Emin, Emax], row major
+ *     with Q slow; E is the energy transfer to the sample. */
+typedef struct {
+  int32_t type;
+  int32_t dw;
+  double sigma_b;
+  double v0;
+  int32_t nrefl;
+  int32_t reserved0;
+  const double* d;
+  const double* F2;
+  double M_amu;
+  double T_K;
+  int32_t nbins;
+  int32_t reserved1;
+  double emax;
+  const double* dos;
+  double J, S, a, gamma;
+  double crot[9];
+  int32_t nQ, nE;
+  double Qmax, Emin, Emax;
+  const double* sqe;
+} mcv_kernel;
+
+/* ------------------------------------------------------------- assembly */
+/* Sample assembly: up to 4 homogeneous scatterers, each with up to 3
+ * kernels (Sec. 2.4.1 composite scatterer, flattened). */
+mcv_status mcv_assembly_create(mcv_assembly* out);
+
+/* Adds a scatterer; *idx receives its index.  Errors: MCV_EINVAL for a bad
+ * shape, material or kernel; MCV_EUNSUPPORTED beyond 4 scatterers, 3
+ * kernels, or 7 material intervals per ray over the assembly (box and
+ * cylinder count 1, annulus 2); MCV_EOVERLAP when the new volume cannot be
+ * shown disjoint from an existing one (disjoint bounding boxes, or the new
+ * shape inside the hole of an annulus, or vice versa).  Arrays are copied. */
+mcv_status mcv_assembly_add(mcv_assembly a, const mcv_shape* shape, const mcv_material* mat,
+                            const mcv_kernel* kernels, int32_t nk, int32_t* idx);
+mcv_status mcv_assembly_destroy(mcv_assembly a);
+
+/* ------------------------------------------------------------- detectors */
+/* Sphere of radius R about the origin (Sec. 2.4.3): bin = ring * n_tof +
+ * tof_bin, ring = floor(2theta / (pi / n_2theta)) with 2theta the angle of
+ * the hit point from +z; tof bins of equal width on [tof_lo, tof_hi);
+ * packets outside the window are not recorded.  Recorded value = weight. */
+mcv_status mcv_detector_sphere(mcv_detector* out, double R, int32_t n_2theta, int32_t n_tof,
+                               double tof_lo, double tof_hi);
+
+/* Vertical 3He tubes (Sec. 2.4.3, "Ray tracing in a detector system"): tube
+ * (row r, column c) has its axis at (R sin phi_c, ., R cos phi_c), phi_c =
+ * phi_lo + (c + 1/2)(phi_hi - phi_lo)/ncols, spanning y in row_y[r] -+
+ * length/2; radius `radius`; 3He density n_he (atoms/A^3, absorption
+ * 5333 b at 2200 m/s, 1/v).  Only the first tube on a packet's ray records:
+ * value = weight * (1 - exp(-mu_He chord)); the absorption point is drawn
+ * on the chord; pixel = floor(n_pix (y_abs - y_bottom) / length); bin =
+ * ((tube * n_pix + pixel) * n_tof + tof_bin), tube = r * ncols + c.
+ * Requirements: row_y ascending, nrows <= 8, neighbouring tubes do not
+ * overlap, R >= 10 radius. */
+typedef struct {
+  int32_t nrows, ncols;
+  double R, phi_lo, phi_hi;
+  double row_y[8];
+  double length, radius, n_he;
+} mcv_tube_layout;
+
+mcv_status mcv_detector_tubes(mcv_detector* out, const mcv_tube_layout* layout, int32_t n_pix,
+                              int32_t n_tof, double tof_lo, double tof_hi);
+/* number of histogram bins (int64 so that 1.28e8-bin layouts are exact) */
+int64_t mcv_detector_nbins(mcv_detector d);
+mcv_status mcv_detector_destroy(mcv_detector d);
+
+/* ----------------------------------------------------------------- plans */
+/* max_orders: maximum number of scattering events of a packet (Supplement
+ * S3 max_ms); packets that reach it cross the remaining material with
+ * attenuation only.  min_prob: packets below it are not split (0 = off).
+ * block_size: threads per workgroup (0 = default 256; multiple of 64, <=
+ * 1024).  waves_per_simd: target resident waves per SIMD used to size the
+ * grid (0 = default). */
+typedef struct {
+  int32_t max_orders;
+  int32_t block_size;
+  double min_prob;
+  int32_t waves_per_simd;
+  int32_t reserved;
+} mcv_opts;
+
+/* Validates the assembly with the detector and uploads the device tables to
+ * `device`.  The plan keeps its own copies; assembly and detector may be
+ * destroyed afterwards.  Errors: MCV_EINVAL, MCV_EUNSUPPORTED (sample not
+ * well inside the detector radius, max_orders > 7), MCV_ENOMEM, MCV_EHIP. */
+mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const mcv_opts* opts,
+                           int32_t device);
+mcv_status mcv_plan_destroy(mcv_plan p);
+int64_t mcv_plan_nbins(mcv_plan p);
+
+/* ------------------------------------------------------------------ beam */
+enum { MCV_BEAM_MONO = 1, MCV_BEAM_GAUSS = 2 };
+
+/* Uniform W x H rectangle at z = z0 < 0, collimated along +z.  MONO: energy
+ * E.  GAUSS: E (1 + sigma_rel g), g standard normal by Box-Muller, redrawn
+ * while E <= 0 (sigma_rel <= 0.2). */
+typedef struct {
+  int32_t type;
+  int32_t reserved;
+  double E, sigma_rel, W, H, z0;
+} mcv_beam;
+
+/* ------------------------------------------------------------ transport */
+/* Traces histories first .. first+n-1 (ids) through the assembly and adds
+ * their recorded values to hist[nbins] (device, binary64) and, if hist_w2 is
+ * not NULL, their squares to hist_w2[nbins].  Random numbers: Philox4x32-10
+ * keyed by `seed`, counter (id_lo, id_hi | stream << 30, lineage, block), so
+ * disjoint id ranges are independent and their sums equal one larger run
+ * (up to binary64 summation order).  Errors: MCV_EINVAL (null hist, n >
+ * 2^62, bad beam), MCV_EHIP. */
+mcv_status mcv_run(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t first, uint64_t n,
+                   double* hist, double* hist_w2, void* stream);
+
+/* One record per packet leaving the sample assembly (the paper's saved
+ * scattered neutrons, Sec. 3 step 2, joined with the detector result). */
+typedef struct {
+  uint64_t id;       /* history id */
+  uint32_t lineage;  /* 1 for the source packet; child of segment g of a
+                        packet with lineage L: 8 L + g + 1 */
+  int32_t order;     /* number of scattering events */
+  float pos[3];      /* where it leaves the assembly */
+  float vel[3];
+  float t;
+  float w;
+  int64_t bin;       /* -1: missed or outside the window */
+  float value;       /* recorded value */
+  float tof;
+  int32_t tube;      /* -1 for the sphere or a miss */
+  int32_t pixel;
+} mcv_packet_record;
+
+/* Same transport as mcv_run, also writing records (device array of
+ * `capacity`) in arbitrary order; *n_out_dev (device uint64, zeroed by the
+ * caller) receives the number of packets, which may exceed capacity (then
+ * only `capacity` records are written and the caller sees the overflow).
+ * hist may be NULL here. */
+mcv_status mcv_trace(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t first, uint64_t n,
+                     double* hist, mcv_packet_record* records, uint64_t capacity,
+                     uint64_t* n_out_dev, void* stream);
+
+/* Waits for the stream and reports a pending device error. */
+mcv_status mcv_sync(void* stream);
+const char* mcv_last_error(void);
+int32_t mcv_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCV_H */

@@ -171,6 +171,8 @@ struct ORecord {
   double margin_anc;            // smallest normalised margin of the ancestors
   double margin_own;            // smallest normalised margin of this packet
   double value_sens;            // |d value / d lateral ray offset| (tubes)
+  uint32_t kinds;               // bit t set: a kernel of type t scattered an ancestor
+  int32_t pad;
 };
 
 struct OTally {
@@ -180,6 +182,10 @@ struct OTally {
   uint64_t n_detected, n_missed, n_out_of_window, n_zero_weight;
   uint64_t n_rng_blocks, n_transcend, n_sqrt, n_shape_tests, n_tube_tests,
       n_table_steps, n_hist_updates;
+  uint64_t n_segments;      // material intervals crossed
+  uint64_t n_splits;        // scattered children drawn
+  uint64_t n_kernel[6];     // kernel draws by type
+  uint64_t n_detect;        // detector calls (escaping packets)
   double w_start[8];        // sum of weight at the start of each flight, per order
   double w_scat[8];         // weight split off to scattering (before the kernel factor)
   double w_abs[8];          // weight removed by absorption in split segments
@@ -271,6 +277,7 @@ struct Packet {
   uint32_t lineage;
   int order;
   double margin_anc;  // min normalised margin of the decisions that made it
+  uint32_t kinds;     // kernel types met in its ancestry (bit = type)
 };
 
 struct Interval {
@@ -572,6 +579,8 @@ Scatter k_phonon(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
   for (; b < k.nbins; ++b)
     if (u[2] < ki.cdf[b]) break;
   if (b == k.nbins) b = k.nbins - 1;
+  *margin = std::min(*margin, std::fabs(u[2] - ki.cdf[b]) / kTauU);
+  if (b > 0) *margin = std::min(*margin, std::fabs(u[2] - ki.cdf[b - 1]) / kTauU);
   double e = (b + u[3]) * ki.de;
   double kT = kBoltzmann * k.T;
   double nb = 1.0 / std::expm1(e / kT);  // Bose occupation
@@ -803,7 +812,9 @@ struct Sim {
     rec.tube = -1;
     rec.pixel = -1;
     rec.margin_anc = P.margin_anc;
+    rec.kinds = P.kinds;
     double margin = kHuge;
+    tally->n_detect++;
     if (S.det.type == DET_SPHERE) detect_sphere(P, rec, &margin);
     else detect_tubes(P, rec, &margin);
     rec.margin_own = std::min(flight_margin, margin);
@@ -852,6 +863,7 @@ struct Sim {
       double m_mu = kHuge;
       Mu mu = attenuation(sc, si, P.speed, &m_mu);
       *own_margin = std::min(*own_margin, m_mu);
+      tally->n_segments++;
       double att = std::exp(-mu.total * L);
       double a = -std::expm1(-mu.total * L);  // probability to interact
       tally->n_transcend += 2;
@@ -886,6 +898,8 @@ struct Sim {
           }
         }
         const OKernel& k = sc.k[kk];
+        tally->n_splits++;
+        tally->n_kernel[k.type]++;
         Scatter r;
         Packet Pin = P;  // state of the incident packet at the scattering point
         switch (k.type) {
@@ -902,6 +916,7 @@ struct Sim {
         C.lineage = lin;
         C.order = P.order + 1;
         C.margin_anc = std::min(P.margin_anc, child_margin);
+        C.kinds = P.kinds | (1u << k.type);
         if (C.w > 0.0) children.push_back(C);
         else tally->n_zero_weight++;
       } else {
@@ -952,6 +967,7 @@ struct Sim {
     P.lineage = 1u;
     P.order = 0;
     P.margin_anc = kHuge;
+    P.kinds = 0u;
   }
 };
 

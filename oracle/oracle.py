@@ -79,6 +79,8 @@ class OTally(C.Structure):
                 ("n_transcend", C.c_uint64), ("n_sqrt", C.c_uint64),
                 ("n_shape_tests", C.c_uint64), ("n_tube_tests", C.c_uint64),
                 ("n_table_steps", C.c_uint64), ("n_hist_updates", C.c_uint64),
+                ("n_segments", C.c_uint64), ("n_splits", C.c_uint64),
+                ("n_kernel", C.c_uint64 * 6), ("n_detect", C.c_uint64),
                 ("w_start", C.c_double * 8), ("w_scat", C.c_double * 8),
                 ("w_abs", C.c_double * 8), ("w_lost", C.c_double * 8)]
 
@@ -88,7 +90,7 @@ RECORD_DTYPE = np.dtype([
     ("pos", np.float64, 3), ("vel", np.float64, 3), ("t", np.float64), ("w", np.float64),
     ("bin", np.int64), ("value", np.float64), ("tof", np.float64), ("tube", np.int32),
     ("pixel", np.int32), ("margin_anc", np.float64), ("margin_own", np.float64),
-    ("value_sens", np.float64)])
+    ("value_sens", np.float64), ("kinds", np.uint32), ("pad", np.int32)])
 
 SHAPES = {"box": 1, "cylinder": 2, "annulus": 3}
 KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5}

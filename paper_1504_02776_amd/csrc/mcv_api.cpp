@@ -1,0 +1,658 @@
+// mcv_api.cpp -- host side of the C ABI declared in include/mcv.h.
+//
+// Builds sample assemblies and detectors, validates them, prepares the
+// binary32 device tables in binary64 (sorted d-spacings and prefix sums of
+// the Debye-Scherrer cross sections, the normalised cumulative phonon DOS,
+// the Debye-Waller coefficient from the DOS, tube column positions), uploads
+// a plan, and launches the transport kernels.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/mcv.h"
+#include "mcv_internal.h"
+
+namespace mcv {
+hipError_t launch_transport(const DevPlan* plan, const float* tables, int n_tables, int stack_cap,
+                            const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
+                            int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
+                            DevRecord* rec, uint64_t cap, unsigned long long* n_out,
+                            hipStream_t stream);
+size_t transport_static_lds();
+hipError_t set_transport_lds_limit(size_t bytes);
+}  // namespace mcv
+
+using namespace mcv;
+
+namespace {
+
+thread_local std::string g_err;
+
+mcv_status fail(mcv_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+mcv_status hipfail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return MCV_EHIP;
+}
+
+// CODATA 2018 values used by the host-side table preparation
+const double kHbar2over2mn = 2.0721249;  // meV A^2
+const double kBoltzmann = 0.08617333;    // meV / K
+const double kNeutronMassAmu = 1.00866491595;
+const double kPi = 3.14159265358979323846;
+const double kHe3SigmaAbs = 5333.0;      // barn at 2200 m/s
+
+struct KernelCopy {
+  mcv_kernel k;
+  std::vector<double> d, F2, dos, sqe;
+};
+
+struct Scatterer {
+  mcv_shape shape;
+  mcv_material mat;
+  std::vector<KernelCopy> kernels;
+};
+
+bool finite_all(const double* x, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+int intervals_of(const mcv_shape& s) { return s.type == MCV_SHAPE_ANNULUS ? 2 : 1; }
+
+// lab-frame corners of the bounding box of a shape
+std::vector<std::array<double, 3>> corners(const mcv_shape& s) {
+  double hx, hy, hz;
+  if (s.type == MCV_SHAPE_BOX) {
+    hx = 0.5 * s.dims[0];
+    hy = 0.5 * s.dims[1];
+    hz = 0.5 * s.dims[2];
+  } else if (s.type == MCV_SHAPE_CYLINDER) {
+    hx = hz = s.dims[0];
+    hy = 0.5 * s.dims[1];
+  } else {
+    hx = hz = s.dims[1];
+    hy = 0.5 * s.dims[2];
+  }
+  std::vector<std::array<double, 3>> out;
+  for (int i = 0; i < 8; ++i) {
+    double l[3] = {(i & 1) ? hx : -hx, (i & 2) ? hy : -hy, (i & 4) ? hz : -hz};
+    std::array<double, 3> p;
+    for (int r = 0; r < 3; ++r)
+      p[r] = s.pos[r] + s.rot[3 * r] * l[0] + s.rot[3 * r + 1] * l[1] + s.rot[3 * r + 2] * l[2];
+    out.push_back(p);
+  }
+  return out;
+}
+
+void aabb(const mcv_shape& s, double lo[3], double hi[3]) {
+  auto c = corners(s);
+  for (int r = 0; r < 3; ++r) {
+    lo[r] = 1e300;
+    hi[r] = -1e300;
+    for (auto& p : c) {
+      lo[r] = std::min(lo[r], p[r]);
+      hi[r] = std::max(hi[r], p[r]);
+    }
+  }
+}
+
+// every bounding-box corner of `inner` lies inside the hole of annulus `ann`
+bool inside_hole(const mcv_shape& inner, const mcv_shape& ann) {
+  if (ann.type != MCV_SHAPE_ANNULUS) return false;
+  for (auto& p : corners(inner)) {
+    double r[3] = {p[0] - ann.pos[0], p[1] - ann.pos[1], p[2] - ann.pos[2]};
+    double x = ann.rot[0] * r[0] + ann.rot[3] * r[1] + ann.rot[6] * r[2];
+    double z = ann.rot[2] * r[0] + ann.rot[5] * r[1] + ann.rot[8] * r[2];
+    if (x * x + z * z >= ann.dims[0] * ann.dims[0]) return false;
+  }
+  return true;
+}
+
+bool disjoint(const mcv_shape& a, const mcv_shape& b) {
+  double la[3], ha[3], lb[3], hb[3];
+  aabb(a, la, ha);
+  aabb(b, lb, hb);
+  for (int r = 0; r < 3; ++r)
+    if (ha[r] <= lb[r] || hb[r] <= la[r]) return true;
+  return inside_hole(a, b) || inside_hole(b, a);
+}
+
+double bounding_radius(const mcv_shape& s) {
+  double m = 0.0;
+  for (auto& p : corners(s)) m = std::max(m, std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]));
+  return m;
+}
+
+mcv_status check_shape(const mcv_shape& s) {
+  if (s.type < MCV_SHAPE_BOX || s.type > MCV_SHAPE_ANNULUS) return fail(MCV_EINVAL, "unknown shape type");
+  if (!finite_all(s.dims, 3) || !finite_all(s.pos, 3) || !finite_all(s.rot, 9))
+    return fail(MCV_EINVAL, "non-finite shape parameter");
+  int nd = s.type == MCV_SHAPE_ANNULUS ? 3 : (s.type == MCV_SHAPE_BOX ? 3 : 2);
+  for (int i = 0; i < nd; ++i)
+    if (!(s.dims[i] > 0.0)) return fail(MCV_EINVAL, "shape dimensions must be > 0");
+  if (s.type == MCV_SHAPE_ANNULUS && !(s.dims[0] < s.dims[1]))
+    return fail(MCV_EINVAL, "annulus needs inner radius < outer radius");
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double d = 0.0;
+      for (int k = 0; k < 3; ++k) d += s.rot[3 * i + k] * s.rot[3 * j + k];
+      if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-6)
+        return fail(MCV_EINVAL, "rotation is not orthonormal");
+    }
+  return MCV_OK;
+}
+
+mcv_status check_kernel(const mcv_kernel& k) {
+  if (k.dw != 0 && k.dw != 1) return fail(MCV_EINVAL, "dw must be 0 or 1");
+  switch (k.type) {
+    case MCV_K_ISO_EL:
+      if (!(k.sigma_b >= 0.0)) return fail(MCV_EINVAL, "sigma must be >= 0");
+      return MCV_OK;
+    case MCV_K_POWDER:
+      if (!(k.v0 > 0.0) || k.nrefl < 1 || k.nrefl > 4096 || !k.d || !k.F2)
+        return fail(MCV_EINVAL, "powder kernel needs v0 > 0 and 1..4096 reflections");
+      for (int i = 0; i < k.nrefl; ++i)
+        if (!(k.d[i] > 0.0) || !(k.F2[i] >= 0.0) || !std::isfinite(k.d[i]) || !std::isfinite(k.F2[i]))
+          return fail(MCV_EINVAL, "powder reflections need d > 0 and F2 >= 0");
+      return MCV_OK;
+    case MCV_K_PHONON: {
+      if (!(k.sigma_b >= 0.0) || !(k.M_amu > 0.0) || !(k.T_K > 0.0) || !(k.emax > 0.0) ||
+          k.nbins < 1 || k.nbins > 8192 || !k.dos)
+        return fail(MCV_EINVAL, "phonon kernel needs M > 0, T > 0, emax > 0, 1..8192 bins");
+      double s = 0.0;
+      for (int i = 0; i < k.nbins; ++i) {
+        if (!(k.dos[i] >= 0.0) || !std::isfinite(k.dos[i])) return fail(MCV_EINVAL, "DOS values must be >= 0");
+        s += k.dos[i];
+      }
+      if (!(s > 0.0)) return fail(MCV_EINVAL, "DOS must have positive area");
+      return MCV_OK;
+    }
+    case MCV_K_SPINWAVE:
+      if (!(k.sigma_b >= 0.0) || !(k.gamma > 0.0) || !(k.a > 0.0) || !finite_all(k.crot, 9))
+        return fail(MCV_EINVAL, "spin-wave kernel needs gamma > 0 and a > 0");
+      if (k.dw) return fail(MCV_EUNSUPPORTED, "Debye-Waller factor not supported for the spin-wave kernel");
+      return MCV_OK;
+    case MCV_K_SQE:
+      if (!(k.sigma_b >= 0.0) || k.nQ < 1 || k.nE < 1 || (int64_t)k.nQ * k.nE > 65536 ||
+          !(k.Qmax > 0.0) || !(k.Emax > k.Emin) || !k.sqe)
+        return fail(MCV_EINVAL, "S(Q,E) kernel needs a grid of 1..65536 cells, Qmax > 0, Emax > Emin");
+      for (int i = 0; i < k.nQ * k.nE; ++i)
+        if (!(k.sqe[i] >= 0.0) || !std::isfinite(k.sqe[i])) return fail(MCV_EINVAL, "S(Q,E) values must be >= 0");
+      if (k.dw) return fail(MCV_EUNSUPPORTED, "Debye-Waller factor not supported for the S(Q,E) kernel");
+      return MCV_OK;
+    default:
+      return fail(MCV_EINVAL, "unknown kernel type");
+  }
+}
+
+}  // namespace
+
+struct mcv_assembly_s {
+  std::vector<Scatterer> scat;
+};
+
+struct mcv_detector_s {
+  int type = 0;
+  double R = 0, tof_lo = 0, tof_hi = 0;
+  int n2t = 0, ntof = 0, npix = 0;
+  mcv_tube_layout tubes;
+};
+
+struct mcv_plan_s {
+  int device = 0;
+  DevPlan host;
+  std::vector<float> tables;
+  DevPlan* d_plan = nullptr;
+  float* d_tables = nullptr;
+  int block = 256;
+  int cus = 256;
+  int waves_per_simd = 4;
+  int64_t nbins = 0;
+  double R = 0;
+};
+
+extern "C" {
+
+int32_t mcv_abi_version(void) { return 1; }
+
+const char* mcv_last_error(void) { return g_err.c_str(); }
+
+mcv_status mcv_assembly_create(mcv_assembly* out) {
+  if (!out) return fail(MCV_EINVAL, "null output handle");
+  *out = new (std::nothrow) mcv_assembly_s();
+  return *out ? MCV_OK : fail(MCV_ENOMEM, "host allocation failed");
+}
+
+mcv_status mcv_assembly_destroy(mcv_assembly a) {
+  delete a;
+  return MCV_OK;
+}
+
+mcv_status mcv_assembly_add(mcv_assembly a, const mcv_shape* shape, const mcv_material* mat,
+                            const mcv_kernel* kernels, int32_t nk, int32_t* idx) {
+  if (!a || !shape || !mat || (nk > 0 && !kernels)) return fail(MCV_EINVAL, "null argument");
+  if (nk < 0) return fail(MCV_EINVAL, "negative kernel count");
+  if (a->scat.size() >= (size_t)kMaxScat) return fail(MCV_EUNSUPPORTED, "at most 4 scatterers");
+  if (nk > kMaxKern) return fail(MCV_EUNSUPPORTED, "at most 3 kernels per scatterer");
+  mcv_status st = check_shape(*shape);
+  if (st != MCV_OK) return st;
+  if (!(mat->n_per_A3 >= 0.0) || !(mat->sigma_abs_b >= 0.0) || !std::isfinite(mat->n_per_A3) ||
+      !std::isfinite(mat->sigma_abs_b))
+    return fail(MCV_EINVAL, "material needs n >= 0 and sigma_abs >= 0");
+  bool has_phonon = false, wants_dw = false;
+  for (int j = 0; j < nk; ++j) {
+    if ((st = check_kernel(kernels[j])) != MCV_OK) return st;
+    has_phonon |= kernels[j].type == MCV_K_PHONON;
+    wants_dw |= kernels[j].dw == 1;
+  }
+  if (wants_dw && !has_phonon)
+    return fail(MCV_EINVAL, "a Debye-Waller factor needs a phonon kernel in the same scatterer");
+  int nphon = 0;
+  for (int j = 0; j < nk; ++j) nphon += kernels[j].type == MCV_K_PHONON;
+  if (nphon > 1) return fail(MCV_EUNSUPPORTED, "at most one phonon kernel per scatterer");
+  int slots = intervals_of(*shape);
+  for (auto& s : a->scat) slots += intervals_of(s.shape);
+  if (slots > 7) return fail(MCV_EUNSUPPORTED, "more than 7 material intervals per ray");
+  for (auto& s : a->scat)
+    if (!disjoint(s.shape, *shape))
+      return fail(MCV_EOVERLAP, "scatterer volume may overlap an existing scatterer");
+  Scatterer sc;
+  sc.shape = *shape;
+  sc.mat = *mat;
+  for (int j = 0; j < nk; ++j) {
+    KernelCopy kc;
+    kc.k = kernels[j];
+    const mcv_kernel& k = kernels[j];
+    if (k.type == MCV_K_POWDER) {
+      kc.d.assign(k.d, k.d + k.nrefl);
+      kc.F2.assign(k.F2, k.F2 + k.nrefl);
+    } else if (k.type == MCV_K_PHONON) {
+      kc.dos.assign(k.dos, k.dos + k.nbins);
+    } else if (k.type == MCV_K_SQE) {
+      kc.sqe.assign(k.sqe, k.sqe + (size_t)k.nQ * k.nE);
+    }
+    kc.k.d = kc.k.F2 = kc.k.dos = kc.k.sqe = nullptr;
+    sc.kernels.push_back(std::move(kc));
+  }
+  a->scat.push_back(std::move(sc));
+  if (idx) *idx = (int32_t)a->scat.size() - 1;
+  return MCV_OK;
+}
+
+mcv_status mcv_detector_sphere(mcv_detector* out, double R, int32_t n_2theta, int32_t n_tof,
+                               double tof_lo, double tof_hi) {
+  if (!out) return fail(MCV_EINVAL, "null output handle");
+  if (!(R > 0.0) || n_2theta < 1 || n_tof < 1 || !(tof_hi > tof_lo) || !std::isfinite(tof_lo) ||
+      !std::isfinite(tof_hi))
+    return fail(MCV_EINVAL, "sphere detector needs R > 0, bins >= 1, tof_hi > tof_lo");
+  auto* d = new (std::nothrow) mcv_detector_s();
+  if (!d) return fail(MCV_ENOMEM, "host allocation failed");
+  d->type = DET_SPHERE;
+  d->R = R;
+  d->n2t = n_2theta;
+  d->ntof = n_tof;
+  d->tof_lo = tof_lo;
+  d->tof_hi = tof_hi;
+  *out = d;
+  return MCV_OK;
+}
+
+mcv_status mcv_detector_tubes(mcv_detector* out, const mcv_tube_layout* L, int32_t n_pix,
+                              int32_t n_tof, double tof_lo, double tof_hi) {
+  if (!out || !L) return fail(MCV_EINVAL, "null argument");
+  if (L->nrows < 1 || L->nrows > kMaxRows || L->ncols < 1 || n_pix < 1 || n_tof < 1)
+    return fail(MCV_EINVAL, "tube layout needs 1..8 rows, >= 1 column, pixel and tof bins");
+  if (!(L->R > 0.0) || !(L->radius > 0.0) || !(L->length > 0.0) || !(L->n_he >= 0.0) ||
+      !(L->phi_hi > L->phi_lo) || !(tof_hi > tof_lo))
+    return fail(MCV_EINVAL, "tube layout needs R, radius, length > 0, phi_hi > phi_lo");
+  if (L->R < 10.0 * L->radius) return fail(MCV_EUNSUPPORTED, "tube circle radius must be >= 10 tube radii");
+  const double dphi = (L->phi_hi - L->phi_lo) / L->ncols;
+  if (L->ncols > 1 && 2.0 * L->R * std::sin(0.5 * dphi) < 2.0 * L->radius)
+    return fail(MCV_EINVAL, "neighbouring tubes overlap");
+  if (L->phi_hi - L->phi_lo > 2.0 * kPi) return fail(MCV_EINVAL, "tube columns span more than 2 pi");
+  for (int r = 1; r < L->nrows; ++r)
+    if (!(L->row_y[r] - L->row_y[r - 1] >= L->length))
+      return fail(MCV_EINVAL, "rows must be ascending and must not overlap");
+  if ((int64_t)L->nrows * L->ncols * n_pix * n_tof > (int64_t)1 << 40)
+    return fail(MCV_EUNSUPPORTED, "histogram too large");
+  auto* d = new (std::nothrow) mcv_detector_s();
+  if (!d) return fail(MCV_ENOMEM, "host allocation failed");
+  d->type = DET_TUBES;
+  d->R = L->R;
+  d->npix = n_pix;
+  d->ntof = n_tof;
+  d->tof_lo = tof_lo;
+  d->tof_hi = tof_hi;
+  d->tubes = *L;
+  *out = d;
+  return MCV_OK;
+}
+
+int64_t mcv_detector_nbins(mcv_detector d) {
+  if (!d) return -1;
+  if (d->type == DET_SPHERE) return (int64_t)d->n2t * d->ntof;
+  return (int64_t)d->tubes.nrows * d->tubes.ncols * d->npix * d->ntof;
+}
+
+mcv_status mcv_detector_destroy(mcv_detector d) {
+  delete d;
+  return MCV_OK;
+}
+
+mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const mcv_opts* opts,
+                           int32_t device) {
+  if (!out || !a || !d) return fail(MCV_EINVAL, "null argument");
+  *out = nullptr;
+  mcv_opts o = {};
+  o.max_orders = 1;
+  if (opts) o = *opts;
+  if (o.max_orders < 0 || o.max_orders > kMaxOrders) return fail(MCV_EUNSUPPORTED, "max_orders must be 0..7");
+  if (!(o.min_prob >= 0.0)) return fail(MCV_EINVAL, "min_prob must be >= 0");
+  int block = o.block_size ? o.block_size : 256;
+  if (block < 64 || block > 256 || block % 64) return fail(MCV_EINVAL, "block_size must be 64, 128, 192 or 256");
+
+  auto p = new (std::nothrow) mcv_plan_s();
+  if (!p) return fail(MCV_ENOMEM, "host allocation failed");
+  std::memset(&p->host, 0, sizeof(DevPlan));
+  DevPlan& P = p->host;
+  std::vector<float>& T = p->tables;
+  P.nscat = (int)a->scat.size();
+  P.K = o.max_orders;
+  P.min_prob = (float)o.min_prob;
+  int smax = 0;
+  double brad = 0.0;
+  for (int s = 0; s < P.nscat; ++s) {
+    const Scatterer& sc = a->scat[s];
+    DevScat& S = P.s[s];
+    smax += intervals_of(sc.shape);
+    brad = std::max(brad, bounding_radius(sc.shape));
+    S.shape = sc.shape.type;
+    S.nk = (int)sc.kernels.size();
+    if (sc.shape.type == MCV_SHAPE_BOX) {
+      for (int i = 0; i < 3; ++i) S.h[i] = (float)(0.5 * sc.shape.dims[i]);
+    } else if (sc.shape.type == MCV_SHAPE_CYLINDER) {
+      S.h[0] = (float)sc.shape.dims[0];
+      S.h[1] = (float)(0.5 * sc.shape.dims[1]);
+    } else {
+      S.h[0] = (float)sc.shape.dims[0];
+      S.h[1] = (float)sc.shape.dims[1];
+      S.h[2] = (float)(0.5 * sc.shape.dims[2]);
+    }
+    for (int i = 0; i < 3; ++i) S.pos[i] = (float)sc.shape.pos[i];
+    for (int i = 0; i < 9; ++i) S.rot[i] = (float)sc.shape.rot[i];
+    S.mu_abs2200 = (float)(100.0 * sc.mat.n_per_A3 * sc.mat.sigma_abs_b * 2200.0);
+    // Debye-Waller coefficient from the scatterer's phonon DOS:
+    // 2W/Q^2 = hbar^2/2M * gamma_0, gamma_0 = int coth(E/2kT) Z(E)/E dE
+    double dw = 0.0;
+    for (const KernelCopy& kc : sc.kernels) {
+      if (kc.k.type != MCV_K_PHONON) continue;
+      const int nb = kc.k.nbins;
+      const double de = kc.k.emax / nb;
+      double area = 0.0;
+      for (double v : kc.dos) area += v * de;
+      double g0 = 0.0;
+      for (int b = 0; b < nb; ++b) {
+        const double e = (b + 0.5) * de;
+        g0 += kc.dos[b] / area / e * de / std::tanh(e / (2.0 * kBoltzmann * kc.k.T_K));
+      }
+      dw = kHbar2over2mn * kNeutronMassAmu / kc.k.M_amu * g0;
+    }
+    S.dw_coef = (float)dw;
+    for (int j = 0; j < S.nk; ++j) {
+      const KernelCopy& kc = sc.kernels[j];
+      const mcv_kernel& k = kc.k;
+      DevKernel& K = S.k[j];
+      K.type = k.type;
+      K.dw = k.dw;
+      K.mu = (float)(100.0 * sc.mat.n_per_A3 * k.sigma_b);
+      if (k.type == MCV_K_POWDER) {
+        std::vector<int> idx(k.nrefl);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return kc.d[x] > kc.d[y]; });
+        K.nrefl = k.nrefl;
+        K.t_d = (int)T.size();
+        for (int i : idx) T.push_back((float)kc.d[i]);
+        K.t_pref = (int)T.size();
+        double acc = 0.0;
+        for (int i : idx) {
+          acc += kc.d[i] * kc.F2[i];
+          T.push_back((float)acc);
+        }
+        K.bragg_coef = (float)(100.0 / (2.0 * k.v0 * k.v0));
+      } else if (k.type == MCV_K_PHONON) {
+        K.nbins = k.nbins;
+        K.t_cdf = (int)T.size();
+        double tot = 0.0;
+        for (double v : kc.dos) tot += v;
+        double acc = 0.0;
+        for (int b = 0; b < k.nbins; ++b) {
+          acc += kc.dos[b];
+          T.push_back(b == k.nbins - 1 ? 1.0f : (float)(acc / tot));
+        }
+        K.de = (float)(k.emax / k.nbins);
+        K.kT = (float)(kBoltzmann * k.T_K);
+        K.h2m = (float)(kHbar2over2mn * kNeutronMassAmu / k.M_amu);
+      } else if (k.type == MCV_K_SPINWAVE) {
+        K.j4s = (float)(4.0 * k.J * k.S);
+        K.wmax = (float)(24.0 * k.J * k.S);
+        K.a = (float)k.a;
+        K.gamma = (float)k.gamma;
+        for (int i = 0; i < 9; ++i) K.crot[i] = (float)k.crot[i];
+      } else if (k.type == MCV_K_SQE) {
+        K.t_s = (int)T.size();
+        for (double v : kc.sqe) T.push_back((float)v);
+        K.nQ = k.nQ;
+        K.nE = k.nE;
+        K.Qmax = (float)k.Qmax;
+        K.Emin = (float)k.Emin;
+        K.Emax = (float)k.Emax;
+        K.q_scale = (float)(k.nQ / k.Qmax);
+        K.e_scale = (float)(k.nE / (k.Emax - k.Emin));
+      }
+    }
+  }
+  P.smax = smax;
+  P.stack_cap = smax > 1 ? (smax - 1) * P.K : 0;
+
+  DevDet& D = P.det;
+  D.type = d->type;
+  D.ntof = d->ntof;
+  D.tof_lo = (float)d->tof_lo;
+  D.inv_dt = (float)(d->ntof / (d->tof_hi - d->tof_lo));
+  D.R = (float)d->R;
+  if (d->type == DET_SPHERE) {
+    if (brad > 0.5 * d->R) {
+      delete p;
+      return fail(MCV_EUNSUPPORTED, "sample must lie within half the sphere radius");
+    }
+    D.n2t = d->n2t;
+    D.ring_scale = (float)(d->n2t / kPi);
+  } else {
+    const mcv_tube_layout& L = d->tubes;
+    if (brad > 0.05 * L.R) {
+      delete p;
+      return fail(MCV_EUNSUPPORTED, "sample must lie within 5% of the tube circle radius");
+    }
+    D.nrows = L.nrows;
+    D.ncols = L.ncols;
+    D.npix = d->npix;
+    D.phi_lo = (float)L.phi_lo;
+    D.inv_dphi = (float)(L.ncols / (L.phi_hi - L.phi_lo));
+    for (int r = 0; r < L.nrows; ++r) D.row_y[r] = (float)L.row_y[r];
+    D.half_len = (float)(0.5 * L.length);
+    D.radius = (float)L.radius;
+    D.mu_he2200 = (float)(100.0 * L.n_he * kHe3SigmaAbs * 2200.0);
+    D.pix_scale = (float)(d->npix / L.length);
+    D.t_cols = (int)T.size();
+    const double dphi = (L.phi_hi - L.phi_lo) / L.ncols;
+    for (int c = 0; c < L.ncols; ++c) {
+      const double phi = L.phi_lo + (c + 0.5) * dphi;
+      T.push_back((float)(L.R * std::sin(phi)));
+      T.push_back((float)(L.R * std::cos(phi)));
+    }
+  }
+  P.n_tables = (int)T.size();
+  if (T.empty()) T.push_back(0.0f);
+  p->nbins = mcv_detector_nbins(d);
+  p->R = d->R;
+
+  // LDS: plan + tables + per-lane stack
+  const size_t tab_bytes = 4 * (size_t)((P.n_tables + 3) & ~3);
+  size_t lds_dyn = tab_bytes + (size_t)P.stack_cap * kFields * 4 * block;
+  while (lds_dyn + transport_static_lds() > 160 * 1024 && block > 64) {
+    block -= 64;
+    lds_dyn = tab_bytes + (size_t)P.stack_cap * kFields * 4 * block;
+  }
+  if (lds_dyn + transport_static_lds() > 160 * 1024) {
+    delete p;
+    return fail(MCV_EUNSUPPORTED, "tables and packet stack exceed the 160 KiB of LDS");
+  }
+  p->block = block;
+  p->device = device;
+  p->waves_per_simd = o.waves_per_simd > 0 ? o.waves_per_simd : 4;
+
+  hipError_t e;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if ((e = hipSetDevice(device)) != hipSuccess) {
+    delete p;
+    return hipfail(e, "hipSetDevice");
+  }
+  int cus = 0;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  p->cus = cus > 0 ? cus : 256;
+  if ((e = set_transport_lds_limit(160 * 1024 - transport_static_lds())) != hipSuccess) {
+    (void)hipSetDevice(cur);
+    delete p;
+    return hipfail(e, "hipFuncSetAttribute");
+  }
+  if ((e = hipMalloc(&p->d_plan, sizeof(DevPlan))) != hipSuccess ||
+      (e = hipMalloc(&p->d_tables, T.size() * sizeof(float))) != hipSuccess) {
+    if (p->d_plan) (void)hipFree(p->d_plan);
+    (void)hipSetDevice(cur);
+    delete p;
+    return fail(MCV_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(p->d_plan, &P, sizeof(DevPlan), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(p->d_tables, T.data(), T.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+          hipSuccess) {
+    (void)hipFree(p->d_plan);
+    (void)hipFree(p->d_tables);
+    (void)hipSetDevice(cur);
+    delete p;
+    return hipfail(e, "hipMemcpy");
+  }
+  (void)hipSetDevice(cur);
+  *out = p;
+  return MCV_OK;
+}
+
+mcv_status mcv_plan_destroy(mcv_plan p) {
+  if (!p) return MCV_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  (void)hipFree(p->d_plan);
+  (void)hipFree(p->d_tables);
+  (void)hipSetDevice(cur);
+  delete p;
+  return MCV_OK;
+}
+
+int64_t mcv_plan_nbins(mcv_plan p) { return p ? p->nbins : -1; }
+
+}  // extern "C"
+
+namespace {
+
+mcv_status make_beam(const mcv_plan_s* p, const mcv_beam* b, DevBeam* out) {
+  if (!b) return fail(MCV_EINVAL, "null beam");
+  if (b->type != MCV_BEAM_MONO && b->type != MCV_BEAM_GAUSS) return fail(MCV_EINVAL, "unknown beam type");
+  if (!(b->E > 0.0) || !std::isfinite(b->E)) return fail(MCV_EINVAL, "beam energy must be > 0");
+  if (!(b->W >= 0.0) || !(b->H >= 0.0) || !std::isfinite(b->W) || !std::isfinite(b->H))
+    return fail(MCV_EINVAL, "beam size must be >= 0");
+  if (!(b->z0 < 0.0) || std::fabs(b->z0) > 0.05 * p->R)
+    return fail(MCV_EINVAL, "beam start z0 must be negative and within 5% of the detector radius");
+  if (std::hypot(0.5 * b->W, 0.5 * b->H) > 0.05 * p->R) return fail(MCV_EINVAL, "beam too wide for the detector");
+  if (b->type == MCV_BEAM_GAUSS && !(b->sigma_rel >= 0.0 && b->sigma_rel <= 0.2))
+    return fail(MCV_EINVAL, "sigma_rel must be in [0, 0.2]");
+  out->type = b->type;
+  out->E = (float)b->E;
+  out->sigma_rel = (float)b->sigma_rel;
+  out->W = (float)b->W;
+  out->H = (float)b->H;
+  out->z0 = (float)b->z0;
+  return MCV_OK;
+}
+
+mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t first, uint64_t n,
+                  double* hist, double* hist_w2, DevRecord* rec, uint64_t cap,
+                  unsigned long long* n_out, void* stream) {
+  DevBeam B;
+  mcv_status st = make_beam(p, beam, &B);
+  if (st != MCV_OK) return st;
+  if (n > ((uint64_t)1 << 62) || first > ((uint64_t)1 << 62) - n)
+    return fail(MCV_EINVAL, "history ids must stay below 2^62");
+  if (n == 0) return MCV_OK;
+  const uint64_t waves_per_block = (uint64_t)p->block / 64;
+  const uint64_t target = (uint64_t)p->cus * 4 * p->waves_per_simd * 2;
+  uint64_t waves = (n + 63) / 64;
+  if (waves > target) waves = target;
+  const uint64_t per_wave = (n + waves - 1) / waves;
+  waves = (n + per_wave - 1) / per_wave;
+  const uint64_t grid = (waves + waves_per_block - 1) / waves_per_block;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  hipError_t e = launch_transport(p->d_plan, p->d_tables, p->host.n_tables, p->host.stack_cap, B,
+                                  seed, first, n, (int)grid, p->block, per_wave, hist, hist_w2,
+                                  rec, cap, n_out, (hipStream_t)stream);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return hipfail(e, "transport launch");
+  return MCV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcv_status mcv_run(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t first, uint64_t n,
+                   double* hist, double* hist_w2, void* stream) {
+  if (!p) return fail(MCV_EINVAL, "null plan");
+  if (!hist) return fail(MCV_EINVAL, "null histogram");
+  return launch(p, beam, seed, first, n, hist, hist_w2, nullptr, 0, nullptr, stream);
+}
+
+mcv_status mcv_trace(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t first, uint64_t n,
+                     double* hist, mcv_packet_record* records, uint64_t capacity,
+                     uint64_t* n_out_dev, void* stream) {
+  static_assert(sizeof(mcv_packet_record) == sizeof(DevRecord), "record layout");
+  if (!p) return fail(MCV_EINVAL, "null plan");
+  if (!records || !n_out_dev) return fail(MCV_EINVAL, "null record buffer or counter");
+  return launch(p, beam, seed, first, n, hist, nullptr, reinterpret_cast<DevRecord*>(records),
+                capacity, reinterpret_cast<unsigned long long*>(n_out_dev), stream);
+}
+
+mcv_status mcv_sync(void* stream) {
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(e, "hipStreamSynchronize");
+  e = hipGetLastError();
+  if (e != hipSuccess) return hipfail(e, "pending device error");
+  return MCV_OK;
+}
+
+}  // extern "C"

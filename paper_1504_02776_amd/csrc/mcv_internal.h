@@ -1,0 +1,120 @@
+// mcv_internal.h -- device-side plan layout shared by the host library and
+// the HIP kernels of the transport library (not part of the public ABI).
+//
+// A plan is a flat POD copied once to device memory and, at the start of
+// every workgroup, into LDS together with its binary32 tables, so that
+// per-lane (divergent) lookups of scatterer and kernel parameters are LDS
+// reads instead of scratch or kernarg traffic.
+#ifndef MCV_INTERNAL_H
+#define MCV_INTERNAL_H
+
+#include <stdint.h>
+
+namespace mcv {
+
+constexpr int kMaxScat = 4;
+constexpr int kMaxKern = 3;
+constexpr int kMaxRows = 8;
+constexpr int kMaxSlots = 2 * kMaxScat;  // material intervals per flight
+constexpr int kMaxOrders = 7;
+constexpr int kFields = 10;              // words per stacked packet
+
+enum { SHAPE_BOX = 1, SHAPE_CYLINDER = 2, SHAPE_ANNULUS = 3 };
+enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5 };
+enum { DET_SPHERE = 1, DET_TUBES = 2 };
+enum { STREAM_SOURCE = 0u, STREAM_SCATTER = 1u, STREAM_DETECT = 2u };
+
+struct DevKernel {
+  int32_t type;
+  int32_t dw;
+  float mu;          // 100 n sigma (1/m); POWDER: unused
+  // POWDER: mu_B(lambda) = bragg_coef * lambda^2 * prefix[n_active - 1]
+  float bragg_coef;  // 100 / (2 v0^2)
+  int32_t t_d;       // offset of d-spacings sorted by descending d
+  int32_t t_pref;    // offset of prefix sums of d |F|^2 in that order
+  int32_t nrefl;
+  // PHONON
+  int32_t t_cdf;     // offset of the normalised cumulative DOS
+  int32_t nbins;
+  float de;          // bin width, meV
+  float kT;          // meV
+  float h2m;         // hbar^2 / 2M, meV A^2
+  // SPINWAVE
+  float j4s;         // 4 J S
+  float a;           // lattice constant
+  float gamma;       // HWHM
+  float wmax;        // 24 J S
+  float crot[9];     // lab -> crystal
+  // SQE
+  int32_t t_s;
+  int32_t nQ, nE;
+  float Qmax, Emin, Emax;
+  float q_scale;     // nQ / Qmax
+  float e_scale;     // nE / (Emax - Emin)
+};
+
+struct DevScat {
+  int32_t shape;
+  int32_t nk;
+  float h[3];        // BOX: half lengths; CYLINDER: r, h/2, -; ANNULUS: r_in, r_out, h/2
+  float pos[3];
+  float rot[9];      // local -> lab, row major
+  float mu_abs2200;  // 100 n sigma_abs * 2200 (1/m * m/s)
+  float dw_coef;     // 2W / Q^2 (A^2)
+  DevKernel k[kMaxKern];
+};
+
+struct DevDet {
+  int32_t type;
+  int32_t ntof;
+  float tof_lo;
+  float inv_dt;      // ntof / (tof_hi - tof_lo)
+  float R;
+  // sphere
+  int32_t n2t;
+  float ring_scale;  // n2t / pi
+  // tubes
+  int32_t nrows, ncols, npix;
+  float phi_lo, inv_dphi;
+  float row_y[kMaxRows];
+  float half_len;
+  float radius;
+  float mu_he2200;   // 100 n_He 5333 * 2200
+  float pix_scale;   // npix / length
+  int32_t t_cols;    // offset of (x_c, z_c) per column
+};
+
+struct DevPlan {
+  int32_t nscat;
+  int32_t K;
+  int32_t smax;       // largest number of material intervals on one ray
+  int32_t stack_cap;  // stacked packets per lane = (smax - 1) * K
+  float min_prob;
+  int32_t n_tables;   // binary32 words in the table blob
+  DevScat s[kMaxScat];
+  DevDet det;
+};
+
+struct DevBeam {
+  int32_t type;  // 1 mono, 2 gauss
+  float E, sigma_rel, W, H, z0;
+};
+
+struct DevRecord {  // mirrors mcv_packet_record
+  uint64_t id;
+  uint32_t lineage;
+  int32_t order;
+  float pos[3];
+  float vel[3];
+  float t;
+  float w;
+  int64_t bin;
+  float value;
+  float tof;
+  int32_t tube;
+  int32_t pixel;
+};
+
+}  // namespace mcv
+
+#endif

@@ -1,0 +1,896 @@
+// mcv_transport.hip -- gfx950 kernels of the weighted neutron-transport path.
+//
+// Method (arXiv:1504.02776): a source packet is traced through the sample
+// assembly; at every material interval on its ray it is split into a
+// transmitted part (weight times e^{-mu L}) and a scattered part born at a
+// random point of the interval with a randomly chosen kernel (Sec. 2.4.3
+// "Multiple Scattering"; Supplement S3, interactM1).  Scattered packets are
+// split again up to the maximum order (Supplement S3, scatterM), then every
+// packet leaving the assembly is handed to the detector (Sec. 2.4.3,
+// "Ray tracing in a detector system") and its value is added to I(pixel, tof)
+// (Sec. 3, intensity = sum of packet probabilities).
+//
+// GPU organisation (MI355X, wave64):
+//   * one lane owns one history at a time and walks its packet tree depth
+//     first; the first child of a flight stays in registers and the others
+//     go to a per-lane stack in LDS whose depth is bounded by
+//     (segments per flight - 1) * max order;
+//   * each wave owns a contiguous range of history ids; when lanes run out
+//     of work they take new histories together (ballot + prefix count), so
+//     lanes stay busy until the range is exhausted;
+//   * the plan (scatterers, kernels, detector) and its binary32 tables are
+//     copied to LDS once per workgroup, so divergent per-lane lookups are
+//     LDS reads;
+//   * every random number is a word of a Philox4x32-10 block addressed by
+//     (seed, id, stream, lineage, block): the traversal order is free;
+//   * recorded values go to the binary64 histogram with hardware FP64
+//     atomics.
+// Nothing here is a dense contraction; the kernel is bound by VALU issue and
+// by the histogram atomics.
+
+#include <hip/hip_runtime.h>
+
+#include "mcv_internal.h"
+
+namespace mcv {
+namespace dev {
+
+constexpr float kKperV = 1.588253594514238e-3f;  // k [1/A] per m/s
+constexpr float kVperK = 629.6223748234908f;      // m/s per 1/A
+constexpr float kEperV2 = 5.22703759e-6f;         // meV per (m/s)^2
+constexpr float kHb2m = 2.0721249f;               // hbar^2/2m_n, meV A^2
+constexpr float kTwoPi = 6.283185307179586f;
+constexpr float kInvPi = 0.3183098861837907f;
+constexpr float kSurf = 1e-7f;                    // m
+constexpr float kBig = 1e30f;
+
+// ------------------------------------------------------------------ RNG
+// Philox4x32-10 (Salmon et al., SC'11).
+__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    // one 32x32->64 multiply gives both halves (v_mad_u64_u32)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    c1 = (uint32_t)p1;
+    c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c3 = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// 23 bits -> odd multiple of 2^-24 in (0,1), exact in binary32
+__device__ __forceinline__ float unif(uint32_t x) {
+  return (float)(x >> 9) * 0x1p-23f + 0x1p-24f;
+}
+
+__device__ __forceinline__ void draw4(uint64_t id, uint32_t stream, uint32_t lin, uint32_t block,
+                                      uint64_t seed, float* u) {
+  uint32_t c0 = (uint32_t)id, c1 = (uint32_t)(id >> 32) | (stream << 30), c2 = lin, c3 = block;
+  philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+  u[0] = unif(c0);
+  u[1] = unif(c1);
+  u[2] = unif(c2);
+  u[3] = unif(c3);
+}
+
+// ------------------------------------------------------------------ packets
+struct Pk {
+  float px, py, pz;
+  float dx, dy, dz;  // unit direction
+  float sp;          // speed, m/s
+  float t, w;
+  uint32_t lin;
+};
+
+__device__ __forceinline__ int order_of(uint32_t lin) { return (31 - __clz(lin)) / 3; }
+
+// ------------------------------------------------------------------ geometry
+// Intervals in "centre +- half" form keep the length of an interval exact
+// when both of its ends come from the same surface pair.
+struct Iv {
+  float lo, hi, len;
+  int entry;  // surface the interval is entered through (see snap_entry)
+};
+
+// entry-surface codes: 1..3 box face normal to local x, y, z; 4 outer
+// cylinder wall; 5 inner (annulus) wall; 6 end cap
+enum { ENTRY_NONE = 0, ENTRY_BOX_X = 1, ENTRY_OUTER = 4, ENTRY_INNER = 5, ENTRY_CAP = 6 };
+
+// slab |q + s d| <= h; returns false on a miss.  (c - hw, c + hw)
+__device__ __forceinline__ bool slab(float q, float d, float h, float& c, float& hw) {
+  if (d == 0.0f) {
+    if (fabsf(q) > h) return false;
+    c = 0.0f;
+    hw = kBig;
+    return true;
+  }
+  c = -q / d;
+  hw = h / fabsf(d);
+  return true;
+}
+
+// infinite cylinder x^2 + z^2 <= r^2; sq = sqrt(r^2 a - cross^2) for annuli
+__device__ __forceinline__ bool radial(float qx, float qz, float dx, float dz, float r, float& c,
+                                       float& hw, float& sq, float& a_out) {
+  const float a = dx * dx + dz * dz;
+  a_out = a;
+  if (a == 0.0f) {
+    if (qx * qx + qz * qz > r * r) return false;
+    c = 0.0f;
+    hw = kBig;
+    sq = 0.0f;
+    return true;
+  }
+  const float cr = qx * dz - qz * dx;
+  const float disc = r * r * a - cr * cr;
+  if (disc <= 0.0f) return false;
+  sq = sqrtf(disc);
+  c = -(qx * dx + qz * dz) / a;
+  hw = sq / a;
+  return true;
+}
+
+// finite cylinder (radial x slab in y); which: 0 both ends radial, 1 both
+// slab, 2 mixed
+__device__ __forceinline__ bool cyl(float qx, float qy, float qz, float dx, float dy, float dz,
+                                    float r, float hh, Iv& iv, float& sq, float& a, int& lo_rad,
+                                    int& hi_rad) {
+  float cr, hr, cs, hs;
+  if (!radial(qx, qz, dx, dz, r, cr, hr, sq, a)) return false;
+  if (!slab(qy, dy, hh, cs, hs)) return false;
+  const float l1 = cr - hr, l2 = cs - hs, h1 = cr + hr, h2 = cs + hs;
+  lo_rad = l1 >= l2;
+  hi_rad = h1 <= h2;
+  iv.lo = lo_rad ? l1 : l2;
+  iv.hi = hi_rad ? h1 : h2;
+  if (!(iv.hi > iv.lo)) return false;
+  if (lo_rad && hi_rad) iv.len = 2.0f * hr;
+  else if (!lo_rad && !hi_rad) iv.len = 2.0f * hs;
+  else iv.len = iv.hi - iv.lo;
+  return true;
+}
+
+// intervals of scatterer S along p + s d (lab); returns count (0..2)
+__device__ __forceinline__ int shape_iv(const DevScat& S, const Pk& P, Iv& i0, Iv& i1) {
+  const float rx = P.px - S.pos[0], ry = P.py - S.pos[1], rz = P.pz - S.pos[2];
+  const float* R = S.rot;
+  // local = R^T (p - pos)
+  const float qx = R[0] * rx + R[3] * ry + R[6] * rz;
+  const float qy = R[1] * rx + R[4] * ry + R[7] * rz;
+  const float qz = R[2] * rx + R[5] * ry + R[8] * rz;
+  const float dx = R[0] * P.dx + R[3] * P.dy + R[6] * P.dz;
+  const float dy = R[1] * P.dx + R[4] * P.dy + R[7] * P.dz;
+  const float dz = R[2] * P.dx + R[5] * P.dy + R[8] * P.dz;
+  if (S.shape == SHAPE_BOX) {
+    float c0, h0, c1, h1, c2, h2;
+    if (!slab(qx, dx, S.h[0], c0, h0) || !slab(qy, dy, S.h[1], c1, h1) ||
+        !slab(qz, dz, S.h[2], c2, h2))
+      return 0;
+    float lo = c0 - h0, hi = c0 + h0, hl = h0;
+    int alo = 0, ahi = 0;
+    if (c1 - h1 > lo) { lo = c1 - h1; alo = 1; }
+    if (c2 - h2 > lo) { lo = c2 - h2; alo = 2; }
+    if (c1 + h1 < hi) { hi = c1 + h1; ahi = 1; hl = h1; }
+    if (c2 + h2 < hi) { hi = c2 + h2; ahi = 2; hl = h2; }
+    if (!(hi > lo)) return 0;
+    i0.lo = lo;
+    i0.hi = hi;
+    i0.len = (alo == ahi) ? 2.0f * hl : hi - lo;
+    i0.entry = ENTRY_BOX_X + alo;
+    return 1;
+  }
+  float sq_o, a, sq_i;
+  int lr_o, hr_o, lr_i, hr_i;
+  const float r_out = S.shape == SHAPE_CYLINDER ? S.h[0] : S.h[1];
+  const float hh = S.shape == SHAPE_CYLINDER ? S.h[1] : S.h[2];
+  Iv o;
+  if (!cyl(qx, qy, qz, dx, dy, dz, r_out, hh, o, sq_o, a, lr_o, hr_o)) return 0;
+  o.entry = lr_o ? ENTRY_OUTER : ENTRY_CAP;
+  if (S.shape == SHAPE_CYLINDER) {
+    i0 = o;
+    return 1;
+  }
+  Iv in;
+  const bool hit_in = cyl(qx, qy, qz, dx, dy, dz, S.h[0], hh, in, sq_i, a, lr_i, hr_i);
+  if (!hit_in || in.hi <= o.lo || in.lo >= o.hi) {
+    i0 = o;
+    return 1;
+  }
+  // wall thickness along the ray when both ends are on the two radial surfaces
+  const float wall = (a > 0.0f) ? (r_out * r_out - S.h[0] * S.h[0]) / (sq_o + sq_i) : 0.0f;
+  int n = 0;
+  if (in.lo > o.lo) {
+    i0.lo = o.lo;
+    i0.hi = in.lo;
+    i0.len = (lr_o && lr_i) ? wall : in.lo - o.lo;
+    i0.entry = o.entry;
+    n = 1;
+  }
+  if (o.hi > in.hi) {
+    Iv& t = n == 0 ? i0 : i1;
+    t.lo = in.hi;
+    t.hi = o.hi;
+    t.len = (hr_o && hr_i) ? wall : o.hi - in.hi;
+    t.entry = hr_i ? ENTRY_INNER : ENTRY_CAP;
+    ++n;
+  }
+  return n;
+}
+
+// Puts an entry point computed as start + s d exactly onto the surface it
+// enters (in the shape frame): a packet that comes from afar would otherwise
+// carry the rounding of its long approach (ulp of 0.1 m ~ 7e-9 m) into the
+// birth point of its children, which grazing exits amplify.
+__device__ __forceinline__ void snap_entry(const DevScat& S, int code, float dx, float dy,
+                                           float dz, float& x, float& y, float& z) {
+  const float* R = S.rot;
+  const float rx = x - S.pos[0], ry = y - S.pos[1], rz = z - S.pos[2];
+  float q[3] = {R[0] * rx + R[3] * ry + R[6] * rz, R[1] * rx + R[4] * ry + R[7] * rz,
+                R[2] * rx + R[5] * ry + R[8] * rz};
+  const float dl[3] = {R[0] * dx + R[3] * dy + R[6] * dz, R[1] * dx + R[4] * dy + R[7] * dz,
+                       R[2] * dx + R[5] * dy + R[8] * dz};
+  if (code >= ENTRY_BOX_X && code <= ENTRY_BOX_X + 2) {
+    const int a = code - ENTRY_BOX_X;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (i == a) q[i] = dl[i] > 0.0f ? -S.h[i] : S.h[i];
+  } else if (code == ENTRY_OUTER || code == ENTRY_INNER) {
+    const float r = (code == ENTRY_INNER || S.shape == SHAPE_CYLINDER) ? S.h[0] : S.h[1];
+    const float f = r * rsqrtf(q[0] * q[0] + q[2] * q[2]);
+    q[0] *= f;
+    q[2] *= f;
+  } else if (code == ENTRY_CAP) {
+    const float hh = S.shape == SHAPE_CYLINDER ? S.h[1] : S.h[2];
+    q[1] = dl[1] > 0.0f ? -hh : hh;
+  } else {
+    return;
+  }
+  x = S.pos[0] + R[0] * q[0] + R[1] * q[1] + R[2] * q[2];
+  y = S.pos[1] + R[3] * q[0] + R[4] * q[1] + R[5] * q[2];
+  z = S.pos[2] + R[6] * q[0] + R[7] * q[1] + R[8] * q[2];
+}
+
+// Orthonormal basis perpendicular to unit n (Duff et al., JCGT 6(1), 2017)
+__device__ __forceinline__ void perp_basis(float nx, float ny, float nz, float& e1x, float& e1y,
+                                           float& e1z, float& e2x, float& e2y, float& e2z) {
+  const float sg = nz >= 0.0f ? 1.0f : -1.0f;
+  const float a = -1.0f / (sg + nz);
+  const float b = nx * ny * a;
+  e1x = 1.0f + sg * nx * nx * a;
+  e1y = sg * b;
+  e1z = -sg * nx;
+  e2x = b;
+  e2y = sg + ny * ny * a;
+  e2z = -ny;
+}
+
+// isotropic direction from two uniforms: cos = 2u - 1, phi = 2 pi u'
+__device__ __forceinline__ void iso_dir(float uc, float up, float& x, float& y, float& z) {
+  const float c = 2.0f * uc - 1.0f;
+  const float s = 2.0f * sqrtf(uc * (1.0f - uc));
+  float sn, cs;
+  sincospif(2.0f * up, &sn, &cs);
+  x = s * cs;
+  y = s * sn;
+  z = c;
+}
+
+// number of reflections with d > lambda/2 in a table sorted by descending d
+__device__ __forceinline__ int n_active(const float* d, int n, float half_lambda) {
+  int lo = 0, hi = n;  // first index with d <= half_lambda
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (d[mid] > half_lambda) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// first index i with x < a[i] in an ascending table (n if none)
+__device__ __forceinline__ int first_above(const float* a, int n, float x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (x < a[mid]) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+struct Mu {
+  float k[kMaxKern];
+  float scat, total;
+};
+
+__device__ __forceinline__ Mu attenuation(const DevScat& S, const float* tab, float sp) {
+  Mu m;
+  m.scat = 0.0f;
+#pragma unroll
+  for (int j = 0; j < kMaxKern; ++j) {
+    float mu = 0.0f;
+    if (j < S.nk) {
+      const DevKernel& K = S.k[j];
+      if (K.type == K_POWDER) {
+        const float lambda = kTwoPi / (sp * kKperV);
+        const int na = n_active(tab + K.t_d, K.nrefl, 0.5f * lambda);
+        mu = na > 0 ? K.bragg_coef * lambda * lambda * tab[K.t_pref + na - 1] : 0.0f;
+      } else {
+        mu = K.mu;
+      }
+    }
+    m.k[j] = mu;
+    m.scat += mu;
+  }
+  m.total = m.scat + S.mu_abs2200 / sp;
+  return m;
+}
+
+// ------------------------------------------------------------------ kernels
+// Each returns the outgoing direction and speed and the weight factor
+// (true cross section per unit nominal cross section / proposal density).
+struct Out {
+  float dx, dy, dz, sp, f;
+};
+
+// |k_i - k_f|^2 without cancellation: (ki - kf)^2 + ki kf |d_i - d_f|^2
+__device__ __forceinline__ float q2_of(float ki, float kf, float dk, const Pk& P, float ox,
+                                       float oy, float oz) {
+  const float ex = P.dx - ox, ey = P.dy - oy, ez = P.dz - oz;
+  return dk * dk + ki * kf * (ex * ex + ey * ey + ez * ez);
+}
+
+__device__ __forceinline__ Out k_iso(const DevKernel& K, const DevScat& S, const Pk& P,
+                                     const float* u) {
+  Out o;
+  iso_dir(u[2], u[3], o.dx, o.dy, o.dz);
+  o.sp = P.sp;
+  o.f = 1.0f;
+  if (K.dw) {
+    const float k = P.sp * kKperV;
+    o.f = expf(-S.dw_coef * q2_of(k, k, 0.0f, P, o.dx, o.dy, o.dz));
+  }
+  return o;
+}
+
+__device__ __forceinline__ Out k_powder(const DevKernel& K, const DevScat& S, const float* tab,
+                                        const Pk& P, const float* u) {
+  Out o;
+  const float lambda = kTwoPi / (P.sp * kKperV);
+  const int na = n_active(tab + K.t_d, K.nrefl, 0.5f * lambda);
+  const float* pref = tab + K.t_pref;
+  const float target = u[2] * pref[na - 1];
+  int i = first_above(pref, na, target);
+  if (i > na - 1) i = na - 1;
+  const float d = tab[K.t_d + i];
+  const float sb = lambda / (2.0f * d);              // sin(theta_B)
+  const float cb = sqrtf((1.0f - sb) * (1.0f + sb));  // cos(theta_B)
+  const float c2 = (cb - sb) * (cb + sb);             // cos(2 theta_B)
+  const float s2 = 2.0f * sb * cb;                    // sin(2 theta_B)
+  float e1x, e1y, e1z, e2x, e2y, e2z;
+  perp_basis(P.dx, P.dy, P.dz, e1x, e1y, e1z, e2x, e2y, e2z);
+  float sn, cs;
+  sincospif(2.0f * u[3], &sn, &cs);
+  o.dx = c2 * P.dx + s2 * (cs * e1x + sn * e2x);
+  o.dy = c2 * P.dy + s2 * (cs * e1y + sn * e2y);
+  o.dz = c2 * P.dz + s2 * (cs * e1z + sn * e2z);
+  o.sp = P.sp;
+  o.f = 1.0f;
+  if (K.dw) {
+    const float q = kTwoPi / d;
+    o.f = expf(-S.dw_coef * q * q);
+  }
+  return o;
+}
+
+__device__ __forceinline__ Out k_phonon(const DevKernel& K, const DevScat& S, const float* tab,
+                                        const Pk& P, const float* u) {
+  Out o;
+  int b = first_above(tab + K.t_cdf, K.nbins, u[2]);
+  if (b > K.nbins - 1) b = K.nbins - 1;
+  const float e = ((float)b + u[3]) * K.de;
+  const float x = e / K.kT;
+  const float p_create = 1.0f / (1.0f + expf(-x));  // (n+1)/(2n+1)
+  const bool create = u[4] < p_create;
+  const float Ei = kEperV2 * P.sp * P.sp;
+  const float Ef = create ? Ei - e : Ei + e;
+  iso_dir(u[5], u[6], o.dx, o.dy, o.dz);
+  if (!(Ef > 0.0f)) {
+    o.sp = P.sp;
+    o.f = 0.0f;
+    return o;
+  }
+  const float ki = P.sp * kKperV;
+  const float kf = sqrtf(Ef / kHb2m);
+  const float dk = (create ? e : -e) / (kHb2m * (ki + kf));
+  const float q2 = q2_of(ki, kf, dk, P, o.dx, o.dy, o.dz);
+  const float dw = K.dw ? expf(-S.dw_coef * q2) : 1.0f;
+  const float coth = 1.0f / tanhf(0.5f * x);
+  o.sp = kf * kVperK;
+  o.f = (kf / ki) * K.h2m * q2 * dw * coth / e;
+  return o;
+}
+
+__device__ __forceinline__ Out k_spinwave(const DevKernel& K, const Pk& P, const float* u) {
+  Out o;
+  const float Ei = kEperV2 * P.sp * P.sp;
+  const float lo = -10.0f * K.gamma;
+  const float hi = fminf(K.wmax + 10.0f * K.gamma, 0.99f * Ei);
+  iso_dir(u[3], u[4], o.dx, o.dy, o.dz);
+  o.sp = P.sp;
+  if (!(hi > lo)) {
+    o.f = 0.0f;
+    return o;
+  }
+  const float E = lo + u[2] * (hi - lo);
+  const float ki = P.sp * kKperV;
+  const float kf = sqrtf((Ei - E) / kHb2m);
+  const float qx = ki * P.dx - kf * o.dx, qy = ki * P.dy - kf * o.dy, qz = ki * P.dz - kf * o.dz;
+  const float* C = K.crot;
+  const float cx = C[0] * qx + C[1] * qy + C[2] * qz;
+  const float cy = C[3] * qx + C[4] * qy + C[5] * qz;
+  const float cz = C[6] * qx + C[7] * qy + C[8] * qz;
+  const float w = K.j4s * (3.0f - cosf(cx * K.a) - cosf(cy * K.a) - cosf(cz * K.a));
+  const float xx = E - w;
+  const float lor = K.gamma * kInvPi / (xx * xx + K.gamma * K.gamma);
+  o.sp = kf * kVperK;
+  o.f = (kf / ki) * lor * (hi - lo);
+  return o;
+}
+
+__device__ __forceinline__ Out k_sqe(const DevKernel& K, const float* tab, const Pk& P,
+                                     const float* u) {
+  Out o;
+  const float Ei = kEperV2 * P.sp * P.sp;
+  const float E = K.Emin + u[2] * (K.Emax - K.Emin);
+  const float Ef = Ei - E;
+  iso_dir(u[3], u[4], o.dx, o.dy, o.dz);
+  o.sp = P.sp;
+  if (!(Ef > 0.0f)) {
+    o.f = 0.0f;
+    return o;
+  }
+  const float ki = P.sp * kKperV;
+  const float kf = sqrtf(Ef / kHb2m);
+  const float dk = E / (kHb2m * (ki + kf));
+  const float q = sqrtf(q2_of(ki, kf, dk, P, o.dx, o.dy, o.dz));
+  const int iq = (int)floorf(q * K.q_scale);
+  int ie = (int)floorf((E - K.Emin) * K.e_scale);
+  ie = ie < 0 ? 0 : (ie > K.nE - 1 ? K.nE - 1 : ie);
+  o.sp = kf * kVperK;
+  o.f = iq < K.nQ ? (kf / ki) * tab[K.t_s + iq * K.nE + ie] * (K.Emax - K.Emin) : 0.0f;
+  return o;
+}
+
+// ------------------------------------------------------------------ detectors
+struct Hit {
+  int64_t bin;
+  float value, tof;
+  int tube, pixel;
+};
+
+__device__ __forceinline__ int tof_bin(const DevDet& D, float tof) {
+  const float ft = (tof - D.tof_lo) * D.inv_dt;
+  if (!(ft >= 0.0f)) return -1;
+  const int it = (int)floorf(ft);
+  return it < D.ntof ? it : -1;
+}
+
+__device__ __forceinline__ Hit detect_sphere(const DevDet& D, const Pk& P) {
+  Hit h;
+  h.bin = -1;
+  h.value = 0.0f;
+  h.tof = 0.0f;
+  h.tube = -1;
+  h.pixel = -1;
+  const float b = P.px * P.dx + P.py * P.dy + P.pz * P.dz;
+  const float r2 = P.px * P.px + P.py * P.py + P.pz * P.pz;
+  const float c = r2 - D.R * D.R;
+  if (c >= 0.0f) return h;
+  const float s = -b + sqrtf(b * b - c);
+  const float cz = fminf(1.0f, fmaxf(-1.0f, (P.pz + s * P.dz) / D.R));
+  int ring = (int)floorf(acosf(cz) * D.ring_scale);
+  ring = ring > D.n2t - 1 ? D.n2t - 1 : (ring < 0 ? 0 : ring);
+  h.tof = P.t + s / P.sp;
+  const int it = tof_bin(D, h.tof);
+  if (it < 0) return h;
+  h.bin = (int64_t)ring * D.ntof + it;
+  h.value = P.w;
+  return h;
+}
+
+// First tube on the ray among the few whose axis can come within a radius
+// of it: the columns around the azimuth where the ray crosses radius R, in
+// the rows its height range overlaps.  Exact cylinder tests decide.
+__device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, const Pk& P,
+                                            uint64_t id, uint64_t seed) {
+  Hit h;
+  h.bin = -1;
+  h.value = 0.0f;
+  h.tof = 0.0f;
+  h.tube = -1;
+  h.pixel = -1;
+  const float a = P.dx * P.dx + P.dz * P.dz;
+  if (a == 0.0f) return h;
+  const float bq = P.px * P.dx + P.pz * P.dz;
+  const float cq = P.px * P.px + P.pz * P.pz - D.R * D.R;
+  const float sR = (-bq + sqrtf(bq * bq - a * cq)) / a;
+  const float xR = P.px + sR * P.dx, zR = P.pz + sR * P.dz, yR = P.py + sR * P.dy;
+  const float fc = (atan2f(xR, zR) - D.phi_lo) * D.inv_dphi;
+  if (!(fc > -2.0f && fc < (float)D.ncols + 1.0f)) return h;
+  const int col = (int)floorf(fc);
+  const float ra = sqrtf(a);
+  const float dyr = 1.25f * D.radius * fabsf(P.dy) / ra + 1e-4f;
+  float best = kBig, best_hi = 0.0f, best_len = 0.0f;
+  int best_tube = -1, best_row = 0;
+  for (int r = 0; r < D.nrows; ++r) {
+    const float yc = D.row_y[r];
+    if (yR + dyr < yc - D.half_len || yR - dyr > yc + D.half_len) continue;
+#pragma unroll
+    for (int dc = -1; dc <= 1; ++dc) {
+      const int cc = col + dc;
+      if (cc < 0 || cc >= D.ncols) continue;
+      const float qx = P.px - tab[D.t_cols + 2 * cc];
+      const float qz = P.pz - tab[D.t_cols + 2 * cc + 1];
+      const float qy = P.py - yc;
+      Iv iv;
+      float sq, aa;
+      int lr, hr;
+      if (!cyl(qx, qy, qz, P.dx, P.dy, P.dz, D.radius, D.half_len, iv, sq, aa, lr, hr)) continue;
+      if (!(iv.hi > 0.0f)) continue;
+      float lo = iv.lo, len = iv.len;
+      if (lo < 0.0f) {
+        lo = 0.0f;
+        len = iv.hi;
+      }
+      if (lo < best) {
+        best = lo;
+        best_hi = iv.hi;
+        best_len = len;
+        best_tube = r * D.ncols + cc;
+        best_row = r;
+      }
+    }
+  }
+  if (best_tube < 0) return h;
+  (void)best_hi;
+  const float mu = D.mu_he2200 / P.sp;
+  const float pabs = -expm1f(-mu * best_len);
+  float u[4];
+  draw4(id, STREAM_DETECT, P.lin, 0u, seed, u);
+  const float s_a = best - log1pf(-u[0] * pabs) / mu;
+  const float y_a = P.py + s_a * P.dy;
+  int pix = (int)floorf((y_a - (D.row_y[best_row] - D.half_len)) * D.pix_scale);
+  pix = pix < 0 ? 0 : (pix > D.npix - 1 ? D.npix - 1 : pix);
+  h.tof = P.t + s_a / P.sp;
+  h.tube = best_tube;
+  h.pixel = pix;
+  const int it = tof_bin(D, h.tof);
+  if (it < 0) return h;
+  h.bin = ((int64_t)best_tube * D.npix + pix) * D.ntof + it;
+  h.value = P.w * pabs;
+  return h;
+}
+
+// ------------------------------------------------------------------ source
+__device__ __forceinline__ Pk source(const DevBeam& B, uint64_t id, uint64_t seed) {
+  float u[4];
+  draw4(id, STREAM_SOURCE, 1u, 0u, seed, u);
+  Pk P;
+  P.px = (u[0] - 0.5f) * B.W;
+  P.py = (u[1] - 0.5f) * B.H;
+  P.pz = B.z0;
+  float E = B.E;
+  if (B.type == 2) {
+    uint32_t blk = 0;
+    for (;;) {
+      E = B.E * (1.0f + B.sigma_rel * sqrtf(-2.0f * logf(u[2])) * cospif(2.0f * u[3]));
+      if (E > 0.0f || blk >= 63u) break;
+      draw4(id, STREAM_SOURCE, 1u, ++blk, seed, u);
+    }
+  }
+  P.dx = 0.0f;
+  P.dy = 0.0f;
+  P.dz = 1.0f;
+  P.sp = E > 0.0f ? sqrtf(E / kEperV2) : 1.0f;
+  P.t = B.z0 / P.sp;
+  P.w = E > 0.0f ? 1.0f : 0.0f;
+  P.lin = 1u;
+  return P;
+}
+
+// ------------------------------------------------------------------ stack
+__device__ __forceinline__ void push(float* st, int slot, int nthreads, int tid, const Pk& C) {
+  float* b = st + (size_t)slot * kFields * nthreads + tid;
+  b[0 * nthreads] = C.px;
+  b[1 * nthreads] = C.py;
+  b[2 * nthreads] = C.pz;
+  b[3 * nthreads] = C.dx;
+  b[4 * nthreads] = C.dy;
+  b[5 * nthreads] = C.dz;
+  b[6 * nthreads] = C.sp;
+  b[7 * nthreads] = C.t;
+  b[8 * nthreads] = C.w;
+  b[9 * nthreads] = __uint_as_float(C.lin);
+}
+
+__device__ __forceinline__ Pk pop(const float* st, int slot, int nthreads, int tid) {
+  const float* b = st + (size_t)slot * kFields * nthreads + tid;
+  Pk C;
+  C.px = b[0 * nthreads];
+  C.py = b[1 * nthreads];
+  C.pz = b[2 * nthreads];
+  C.dx = b[3 * nthreads];
+  C.dy = b[4 * nthreads];
+  C.dz = b[5 * nthreads];
+  C.sp = b[6 * nthreads];
+  C.t = b[7 * nthreads];
+  C.w = b[8 * nthreads];
+  C.lin = __float_as_uint(b[9 * nthreads]);
+  return C;
+}
+
+// ------------------------------------------------------------------ flight
+// Splits P at every material interval on its ray (children: first in *nxt,
+// the others pushed on the lane stack) and moves it to where it leaves.
+__device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, Pk& P, uint64_t id,
+                                    uint64_t seed, Pk& nxt, bool& has_nxt, float* st, int& nst,
+                                    int nthreads, int tid) {
+  float lo[kMaxSlots], hi[kMaxSlots], len[kMaxSlots];
+  uint32_t valid = 0u, codes = 0u;
+#pragma unroll
+  for (int s = 0; s < kMaxScat; ++s) {
+    Iv a, b;
+    a.lo = a.hi = a.len = b.lo = b.hi = b.len = 0.0f;
+    a.entry = b.entry = ENTRY_NONE;
+    const int n = s < PL.nscat ? shape_iv(PL.s[s], P, a, b) : 0;
+    lo[2 * s] = a.lo;
+    hi[2 * s] = a.hi;
+    len[2 * s] = a.len;
+    lo[2 * s + 1] = b.lo;
+    hi[2 * s + 1] = b.hi;
+    len[2 * s + 1] = b.len;
+    codes |= ((uint32_t)a.entry << (8 * s)) | ((uint32_t)b.entry << (8 * s + 4));
+    if (n > 0 && a.hi > kSurf) valid |= 1u << (2 * s);
+    if (n > 1 && b.hi > kSurf) valid |= 1u << (2 * s + 1);
+  }
+  // a packet inside a scatterer starts its interval at 0
+#pragma unroll
+  for (int j = 0; j < kMaxSlots; ++j) {
+    if (lo[j] <= 0.0f) {
+      lo[j] = 0.0f;
+      len[j] = hi[j];
+      codes &= ~(0xFu << (4 * j));
+    }
+  }
+  const int order = order_of(P.lin);
+  const float sx = P.px, sy = P.py, sz = P.pz, t0 = P.t;
+  float s_end = 0.0f;
+  uint32_t g = 0;
+  while (valid) {
+    // nearest remaining interval; ties to the lower scatterer index
+    int j = 0;
+    float best = kBig;
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; ++q) {
+      if ((valid >> q) & 1u) {
+        if (lo[q] < best) {
+          best = lo[q];
+          j = q;
+        }
+      }
+    }
+    valid &= ~(1u << j);
+    float slo = 0.0f, shi = 0.0f, sl = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; ++q) {
+      if (q == j) {
+        slo = lo[q];
+        shi = hi[q];
+        sl = len[q];
+      }
+    }
+    const DevScat& S = PL.s[j >> 1];
+    const Mu mu = attenuation(S, tab, P.sp);
+    const float ml = mu.total * sl;
+    const float att = expf(-ml);
+    const float pint = -expm1f(-ml);  // probability to interact in the interval
+    if (order < PL.K && P.w >= PL.min_prob && mu.scat > 0.0f) {
+      const uint32_t lin = P.lin * 8u + g + 1u;
+      float u[8];
+      draw4(id, STREAM_SCATTER, lin, 0u, seed, u);
+      draw4(id, STREAM_SCATTER, lin, 1u, seed, u + 4);
+      const float x = -log1pf(-u[0] * pint) / mu.total;
+      // birth point = entry point (on its surface) + x along the ray
+      float ex = sx + slo * P.dx, ey = sy + slo * P.dy, ez = sz + slo * P.dz;
+      snap_entry(S, (int)((codes >> (4 * j)) & 0xFu), P.dx, P.dy, P.dz, ex, ey, ez);
+      Pk C;
+      C.px = ex + x * P.dx;
+      C.py = ey + x * P.dy;
+      C.pz = ez + x * P.dz;
+      C.t = t0 + (slo + x) / P.sp;
+      C.w = P.w * (mu.scat / mu.total) * pint;
+      C.lin = lin;
+      // kernel k with probability mu_k / mu_s: first k with u mu_s < sum_{i<=k} mu_i
+      const float target = u[1] * mu.scat;
+      float cum = 0.0f;
+      int kk = S.nk - 1;
+      bool found = false;
+#pragma unroll
+      for (int q = 0; q < kMaxKern; ++q) {
+        if (q < S.nk && !found) {
+          cum += mu.k[q];
+          if (target < cum) {
+            kk = q;
+            found = true;
+          }
+        }
+      }
+      const DevKernel& K = S.k[kk];
+      Out o;
+      switch (K.type) {
+        case K_ISO_EL: o = k_iso(K, S, P, u); break;
+        case K_POWDER: o = k_powder(K, S, tab, P, u); break;
+        case K_PHONON: o = k_phonon(K, S, tab, P, u); break;
+        case K_SPINWAVE: o = k_spinwave(K, P, u); break;
+        default: o = k_sqe(K, tab, P, u); break;
+      }
+      C.dx = o.dx;
+      C.dy = o.dy;
+      C.dz = o.dz;
+      C.sp = o.sp;
+      C.w *= o.f;
+      if (C.w > 0.0f) {
+        if (!has_nxt) {
+          nxt = C;
+          has_nxt = true;
+        } else if (nst < PL.stack_cap) {
+          push(st, nst, nthreads, tid, C);
+          ++nst;
+        }
+      }
+    }
+    P.w *= att;
+    s_end = shi;
+    ++g;
+  }
+  if (g > 0) {
+    P.px = sx + s_end * P.dx;
+    P.py = sy + s_end * P.dy;
+    P.pz = sz + s_end * P.dz;
+    P.t = t0 + s_end / P.sp;
+  }
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+template <bool TRACE>
+__global__ void __launch_bounds__(256) transport(const DevPlan* __restrict__ gplan,
+                                                 const float* __restrict__ gtab, DevBeam beam,
+                                                 uint64_t seed, uint64_t first, uint64_t n,
+                                                 uint64_t per_wave, double* __restrict__ hist,
+                                                 double* __restrict__ hist_w2,
+                                                 DevRecord* __restrict__ rec, uint64_t cap,
+                                                 unsigned long long* __restrict__ n_out) {
+  __shared__ DevPlan PL;
+  extern __shared__ float dyn[];
+  const int tid = threadIdx.x;
+  const int nthreads = blockDim.x;
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(gplan);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&PL);
+    for (int i = tid; i < (int)(sizeof(DevPlan) / 4); i += nthreads) dst[i] = src[i];
+    const int nt = gplan->n_tables;
+    for (int i = tid; i < nt; i += nthreads) dyn[i] = gtab[i];
+  }
+  __syncthreads();
+  const float* tab = dyn;
+  float* st = dyn + ((PL.n_tables + 3) & ~3);
+
+  const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
+  const uint64_t begin = wave * per_wave;
+  if (begin >= n) return;  // whole wave leaves together
+  const uint64_t end = begin + per_wave < n ? begin + per_wave : n;
+  const uint64_t lt = lanemask_lt();
+
+  Pk cur;
+  cur.lin = 0u;
+  bool has = false;
+  uint64_t hid = 0;
+  int nst = 0;
+  uint64_t next = begin;
+  while (true) {
+    if (!has && nst > 0) {
+      --nst;
+      cur = pop(st, nst, nthreads, tid);
+      has = true;
+    }
+    const bool need = !has;
+    const uint64_t m = __ballot(need);
+    if (need) {
+      const uint64_t h = next + (uint64_t)__popcll(m & lt);
+      if (h < end) {
+        hid = first + h;
+        cur = source(beam, hid, seed);
+        has = cur.w > 0.0f;
+      }
+    }
+    next += (uint64_t)__popcll(m);
+    if (__ballot(has) == 0ull) break;
+    if (has) {
+      Pk nxt;
+      nxt.lin = 0u;
+      bool has_nxt = false;
+      fly(PL, tab, cur, hid, seed, nxt, has_nxt, st, nst, nthreads, tid);
+      const Hit hh = PL.det.type == DET_SPHERE ? detect_sphere(PL.det, cur)
+                                               : detect_tubes(PL.det, tab, cur, hid, seed);
+      if (hh.bin >= 0) {
+        if (hist) unsafeAtomicAdd(hist + hh.bin, (double)hh.value);
+        if (hist_w2) unsafeAtomicAdd(hist_w2 + hh.bin, (double)hh.value * (double)hh.value);
+      }
+      if (TRACE) {
+        const unsigned long long slot = atomicAdd(n_out, 1ull);
+        if (slot < cap) {
+          DevRecord r;
+          r.id = hid;
+          r.lineage = cur.lin;
+          r.order = order_of(cur.lin);
+          r.pos[0] = cur.px;
+          r.pos[1] = cur.py;
+          r.pos[2] = cur.pz;
+          r.vel[0] = cur.dx * cur.sp;
+          r.vel[1] = cur.dy * cur.sp;
+          r.vel[2] = cur.dz * cur.sp;
+          r.t = cur.t;
+          r.w = cur.w;
+          r.bin = hh.bin;
+          r.value = hh.value;
+          r.tof = hh.tof;
+          r.tube = hh.tube;
+          r.pixel = hh.pixel;
+          rec[slot] = r;
+        }
+      }
+      if (has_nxt) cur = nxt;
+      else has = false;
+    }
+  }
+}
+
+}  // namespace dev
+
+// ------------------------------------------------------------------ launch
+hipError_t launch_transport(const DevPlan* plan, const float* tables, int n_tables, int stack_cap,
+                            const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
+                            int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
+                            DevRecord* rec, uint64_t cap, unsigned long long* n_out,
+                            hipStream_t stream) {
+  const size_t lds = sizeof(float) * ((size_t)((n_tables + 3) & ~3) +
+                                      (size_t)stack_cap * kFields * block);
+  if (rec) {
+    hipLaunchKernelGGL(dev::transport<true>, dim3(grid), dim3(block), lds, stream, plan, tables,
+                       beam, seed, first, n, per_wave, hist, hist_w2, rec, cap, n_out);
+  } else {
+    hipLaunchKernelGGL(dev::transport<false>, dim3(grid), dim3(block), lds, stream, plan, tables,
+                       beam, seed, first, n, per_wave, hist, hist_w2, rec, cap, n_out);
+  }
+  return hipGetLastError();
+}
+
+size_t transport_static_lds() { return sizeof(DevPlan); }
+
+hipError_t set_transport_lds_limit(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::transport<false>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::transport<true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace mcv

@@ -1,0 +1,307 @@
+"""Python binding of the C ABI in include/mcv.h (argument marshalling only).
+
+Every step of the transport runs in the HIP library ``libmcv.so``; this module
+converts workload descriptions to the ABI structs and passes device pointers
+of torch tensors (torch supplies device memory and streams, nothing else).
+If the library is missing the import of :func:`lib` raises: there is no
+fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcv.so")
+
+MCV_OK, MCV_EINVAL, MCV_EUNSUPPORTED, MCV_EOVERLAP, MCV_ENOMEM, MCV_ECAPACITY, MCV_EHIP = range(7)
+STATUS_NAMES = ["MCV_OK", "MCV_EINVAL", "MCV_EUNSUPPORTED", "MCV_EOVERLAP", "MCV_ENOMEM",
+                "MCV_ECAPACITY", "MCV_EHIP"]
+
+SHAPES = {"box": 1, "cylinder": 2, "annulus": 3}
+KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5}
+
+
+class MCVError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
+        self.status = status
+
+
+class mcv_shape(C.Structure):
+    _fields_ = [("type", C.c_int32), ("reserved", C.c_int32), ("dims", C.c_double * 3),
+                ("pos", C.c_double * 3), ("rot", C.c_double * 9)]
+
+
+class mcv_material(C.Structure):
+    _fields_ = [("n_per_A3", C.c_double), ("sigma_abs_b", C.c_double)]
+
+
+class mcv_kernel(C.Structure):
+    _fields_ = [("type", C.c_int32), ("dw", C.c_int32), ("sigma_b", C.c_double),
+                ("v0", C.c_double), ("nrefl", C.c_int32), ("reserved0", C.c_int32),
+                ("d", C.POINTER(C.c_double)), ("F2", C.POINTER(C.c_double)),
+                ("M_amu", C.c_double), ("T_K", C.c_double), ("nbins", C.c_int32),
+                ("reserved1", C.c_int32), ("emax", C.c_double), ("dos", C.POINTER(C.c_double)),
+                ("J", C.c_double), ("S", C.c_double), ("a", C.c_double), ("gamma", C.c_double),
+                ("crot", C.c_double * 9), ("nQ", C.c_int32), ("nE", C.c_int32),
+                ("Qmax", C.c_double), ("Emin", C.c_double), ("Emax", C.c_double),
+                ("sqe", C.POINTER(C.c_double))]
+
+
+class mcv_tube_layout(C.Structure):
+    _fields_ = [("nrows", C.c_int32), ("ncols", C.c_int32), ("R", C.c_double),
+                ("phi_lo", C.c_double), ("phi_hi", C.c_double), ("row_y", C.c_double * 8),
+                ("length", C.c_double), ("radius", C.c_double), ("n_he", C.c_double)]
+
+
+class mcv_opts(C.Structure):
+    _fields_ = [("max_orders", C.c_int32), ("block_size", C.c_int32), ("min_prob", C.c_double),
+                ("waves_per_simd", C.c_int32), ("reserved", C.c_int32)]
+
+
+class mcv_beam(C.Structure):
+    _fields_ = [("type", C.c_int32), ("reserved", C.c_int32), ("E", C.c_double),
+                ("sigma_rel", C.c_double), ("W", C.c_double), ("H", C.c_double),
+                ("z0", C.c_double)]
+
+
+RECORD_DTYPE = np.dtype([
+    ("id", np.uint64), ("lineage", np.uint32), ("order", np.int32), ("pos", np.float32, 3),
+    ("vel", np.float32, 3), ("t", np.float32), ("w", np.float32), ("bin", np.int64),
+    ("value", np.float32), ("tof", np.float32), ("tube", np.int32), ("pixel", np.int32)])
+assert RECORD_DTYPE.itemsize == 72
+
+# every symbol include/mcv.h declares (checked by the CPU test-suite)
+EXPORTS = ["mcv_assembly_create", "mcv_assembly_add", "mcv_assembly_destroy",
+           "mcv_detector_sphere", "mcv_detector_tubes", "mcv_detector_nbins",
+           "mcv_detector_destroy", "mcv_plan_create", "mcv_plan_destroy", "mcv_plan_nbins",
+           "mcv_run", "mcv_trace", "mcv_sync", "mcv_last_error", "mcv_abi_version"]
+
+_lib = None
+
+P = C.c_void_p
+PP = C.POINTER(C.c_void_p)
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "mcv_assembly_create": [PP],
+            "mcv_assembly_add": [P, C.POINTER(mcv_shape), C.POINTER(mcv_material),
+                                 C.POINTER(mcv_kernel), C.c_int32, C.POINTER(C.c_int32)],
+            "mcv_assembly_destroy": [P],
+            "mcv_detector_sphere": [PP, C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_double],
+            "mcv_detector_tubes": [PP, C.POINTER(mcv_tube_layout), C.c_int32, C.c_int32,
+                                   C.c_double, C.c_double],
+            "mcv_detector_destroy": [P],
+            "mcv_plan_create": [PP, P, P, C.POINTER(mcv_opts), C.c_int32],
+            "mcv_plan_destroy": [P],
+            "mcv_run": [P, C.POINTER(mcv_beam), C.c_uint64, C.c_uint64, C.c_uint64, P, P, P],
+            "mcv_trace": [P, C.POINTER(mcv_beam), C.c_uint64, C.c_uint64, C.c_uint64, P, P,
+                          C.c_uint64, P, P],
+            "mcv_sync": [P],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.mcv_detector_nbins.argtypes = [P]
+        L.mcv_detector_nbins.restype = C.c_int64
+        L.mcv_plan_nbins.argtypes = [P]
+        L.mcv_plan_nbins.restype = C.c_int64
+        L.mcv_last_error.restype = C.c_char_p
+        L.mcv_abi_version.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != MCV_OK:
+        raise MCVError(status, lib().mcv_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _kernel_struct(k, keep):
+    s = mcv_kernel()
+    s.type = KERNELS[k["type"]]
+    s.dw = int(k.get("dw", 0))
+    s.sigma_b = float(k.get("sigma", 0.0))
+    t = k["type"]
+    if t == "powder":
+        d = np.ascontiguousarray(k["d"], dtype=np.float64)
+        F2 = np.ascontiguousarray(k["F2"], dtype=np.float64)
+        keep += [d, F2]
+        s.v0, s.nrefl, s.d, s.F2 = k["v0"], len(d), _dptr(d), _dptr(F2)
+    elif t == "phonon":
+        dos = np.ascontiguousarray(k["dos"], dtype=np.float64)
+        keep.append(dos)
+        s.M_amu, s.T_K, s.emax = k["M"], k["T"], k["emax"]
+        s.nbins, s.dos = len(dos), _dptr(dos)
+    elif t == "spinwave":
+        s.J, s.S, s.a, s.gamma = k["J"], k["S"], k["a"], k["gamma"]
+        s.crot[:] = k["crot"]
+    elif t == "sqe":
+        g = np.ascontiguousarray(np.asarray(k["S"], dtype=np.float64).reshape(-1))
+        keep.append(g)
+        s.nQ, s.nE = k["nQ"], k["nE"]
+        s.Qmax, s.Emin, s.Emax = k["Qmax"], k["Emin"], k["Emax"]
+        s.sqe = _dptr(g)
+    return s
+
+
+class Assembly:
+    def __init__(self):
+        self.h = C.c_void_p()
+        check(lib().mcv_assembly_create(C.byref(self.h)))
+
+    def add(self, sc):
+        sh = mcv_shape()
+        sh.type = SHAPES[sc["shape"]["type"]]
+        sh.dims[:] = sc["shape"]["dims"]
+        sh.pos[:] = sc["shape"]["pos"]
+        sh.rot[:] = sc["shape"]["rot"]
+        mat = mcv_material(sc["n"], sc["sigma_abs"])
+        keep = []
+        ks = (mcv_kernel * max(1, len(sc["kernels"])))()
+        for j, k in enumerate(sc["kernels"]):
+            ks[j] = _kernel_struct(k, keep)
+        idx = C.c_int32(-1)
+        check(lib().mcv_assembly_add(self.h, C.byref(sh), C.byref(mat), ks, len(sc["kernels"]),
+                                     C.byref(idx)))
+        return idx.value
+
+    def close(self):
+        if self.h:
+            lib().mcv_assembly_destroy(self.h)
+            self.h = C.c_void_p()
+
+    __del__ = close
+
+
+class Detector:
+    def __init__(self, det):
+        self.h = C.c_void_p()
+        if det["type"] == "sphere":
+            check(lib().mcv_detector_sphere(C.byref(self.h), det["R"], det["n2t"], det["ntof"],
+                                            det["tof_lo"], det["tof_hi"]))
+        else:
+            L = mcv_tube_layout()
+            L.nrows, L.ncols = det["nrows"], det["ncols"]
+            L.R, L.phi_lo, L.phi_hi = det["R"], det["phi_lo"], det["phi_hi"]
+            L.row_y[:len(det["row_y"])] = det["row_y"]
+            L.length, L.radius, L.n_he = det["length"], det["radius"], det["n_he"]
+            check(lib().mcv_detector_tubes(C.byref(self.h), C.byref(L), det["npix"],
+                                           det["ntof"], det["tof_lo"], det["tof_hi"]))
+
+    @property
+    def nbins(self):
+        return lib().mcv_detector_nbins(self.h)
+
+    def close(self):
+        if self.h:
+            lib().mcv_detector_destroy(self.h)
+            self.h = C.c_void_p()
+
+    __del__ = close
+
+
+def make_beam(b):
+    return mcv_beam(2 if b["type"] == "gauss" else 1, 0, b["E"], b["sigma_rel"], b["W"],
+                    b["H"], b["z0"])
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A device plan for one workload description (sample + detector + orders)."""
+
+    def __init__(self, cfg, device=0, block_size=0, waves_per_simd=0):
+        self.cfg = cfg
+        self.device = device
+        asm = Assembly()
+        for sc in cfg["scatterers"]:
+            asm.add(sc)
+        det = Detector(cfg["detector"])
+        opts = mcv_opts(int(cfg["K"]), int(block_size), float(cfg.get("min_prob", 0.0)),
+                        int(waves_per_simd), 0)
+        self.h = C.c_void_p()
+        check(lib().mcv_plan_create(C.byref(self.h), asm.h, det.h, C.byref(opts), device))
+        asm.close()
+        det.close()
+        self.nbins = lib().mcv_plan_nbins(self.h)
+        self.beam = make_beam(cfg["beam"])
+
+    def zeros(self):
+        import torch
+        return torch.zeros(self.nbins, dtype=torch.float64, device=f"cuda:{self.device}")
+
+    def run(self, hist, n=None, first=0, seed=None, hist_w2=None, stream=None, beam=None):
+        """Adds histories [first, first+n) into `hist` (float64 device tensor)."""
+        n = self.cfg["N"] if n is None else n
+        seed = self.cfg["seed"] if seed is None else seed
+        b = self.beam if beam is None else make_beam(beam)
+        self._check_hist(hist)
+        if hist_w2 is not None:
+            self._check_hist(hist_w2)
+        check(lib().mcv_run(self.h, C.byref(b), seed, first, n, C.c_void_p(hist.data_ptr()),
+                            C.c_void_p(hist_w2.data_ptr()) if hist_w2 is not None else None,
+                            _stream_ptr(stream)))
+
+    def trace(self, n=None, first=0, seed=None, capacity=None, hist=None, stream=None):
+        """Runs the transport and returns the packet records (numpy) and count."""
+        import torch
+        n = self.cfg["N"] if n is None else n
+        seed = self.cfg["seed"] if seed is None else seed
+        cap = capacity if capacity is not None else max(64, 48 * n)
+        dev = f"cuda:{self.device}"
+        rec = torch.empty(cap * RECORD_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+        if hist is not None:
+            self._check_hist(hist)
+        check(lib().mcv_trace(self.h, C.byref(self.beam), seed, first, n,
+                              C.c_void_p(hist.data_ptr()) if hist is not None else None,
+                              C.c_void_p(rec.data_ptr()), cap, C.c_void_p(cnt.data_ptr()),
+                              _stream_ptr(stream)))
+        torch.cuda.synchronize(dev)
+        count = int(cnt.item())
+        m = min(count, cap)
+        out = np.frombuffer(rec[:m * RECORD_DTYPE.itemsize].cpu().numpy().tobytes(),
+                            dtype=RECORD_DTYPE)
+        return out, count
+
+    def _check_hist(self, h):
+        import torch
+        if h.dtype != torch.float64 or not h.is_cuda or h.numel() < self.nbins or \
+                not h.is_contiguous():
+            raise ValueError("histogram must be a contiguous float64 CUDA tensor of nbins")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mcv_plan_destroy(self.h)
+            self.h = C.c_void_p()
+
+    __del__ = close
+
+
+def sync(stream=None):
+    check(lib().mcv_sync(_stream_ptr(stream)))

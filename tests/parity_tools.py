@@ -1,0 +1,154 @@
+"""Packet-by-packet and histogram comparison of the HIP path with the oracle.
+
+Tolerances (binary32 packet state on the GPU against the binary64 oracle):
+  position   |dx| <= 1e-5 |x| + 1e-7 m       (1e-7 m = 1e-5 of a 1 cm sample)
+  velocity   |dv| <= 1e-5 |v|
+  time       |dt| <= 1e-5 |t| + 3e-11 s       (3e-11 s = 1e-5 of 1 cm / 3 km/s)
+  weight     |dw| <= 1e-5 |w|, 1e-4 |w| below a spin-wave scattering (its
+             weight depends on cos(Q_a a) with Q_a a up to ~40 rad, where one
+             binary32 rounding of Q moves E(Q) by ~1e-5 meV against a 0.5 meV
+             Lorentzian)
+  value      |dv| <= 1e-5 |v| + |d value/d offset| * 1e-6 m (+ the spin-wave
+             allowance): at 3 m a binary32 direction fixes the ray's lateral
+             position only to a few 1e-7 m, and a tube's chord is steep in it
+  tof        |dt| <= 1e-5 |tof|
+Discrete results (packet existence, bin) must be equal unless the oracle's
+margin to the decision is below its stated uncertainty (margin < 1): such
+"near-decision" packets may go either way and are only counted.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+SPINWAVE_BIT = 1 << 4
+DELTA_B = 1e-6
+
+
+def _key(r):
+    return (r["id"].astype(np.uint64) << np.uint64(32)) | r["lineage"].astype(np.uint64)
+
+
+def compare_packets(gpu, orc, max_flag_frac=0.05):
+    """Returns a dict of statistics; raises AssertionError on a mismatch."""
+    kg, ko = _key(gpu), _key(orc)
+    assert len(np.unique(kg)) == len(kg), "duplicate (id, lineage) in GPU records"
+    assert len(np.unique(ko)) == len(ko), "duplicate (id, lineage) in oracle records"
+    og = np.argsort(kg)
+    oo = np.argsort(ko)
+    kg, gpu = kg[og], gpu[og]
+    ko, orc = ko[oo], orc[oo]
+    margin = np.minimum(orc["margin_anc"], orc["margin_own"])
+    common_o = np.isin(ko, kg)
+    common_g = np.isin(kg, ko)
+    # packets that exist on one side only must descend from a near decision
+    okeys = dict(zip(ko.tolist(), range(len(ko))))
+
+    def flagged_ancestor(key):
+        idv, lin = int(key) >> 32, int(key) & 0xFFFFFFFF
+        while lin >= 1:
+            k = (idv << 32) | lin
+            if k in okeys:
+                i = okeys[k]
+                if margin[i] < 1.0:
+                    return True
+            lin >>= 3
+        return False
+
+    only_o = ko[~common_o]
+    for k in only_o:
+        i = okeys[int(k)]
+        assert orc["margin_anc"][i] < 1.0 or flagged_ancestor(k), \
+            f"oracle packet missing on GPU: id={int(k) >> 32} lin={int(k) & 0xFFFFFFFF}"
+    only_g = kg[~common_g]
+    for k in only_g:
+        assert flagged_ancestor(k), \
+            f"extra GPU packet: id={int(k) >> 32} lin={int(k) & 0xFFFFFFFF}"
+
+    g = gpu[common_g]
+    o = orc[common_o]
+    assert np.array_equal(_key(g), _key(o))
+    ok_state = (o["margin_anc"] >= 1.0) & (o["margin_own"] >= 1.0)
+    spin = (o["kinds"] & SPINWAVE_BIT) != 0
+    wtol = np.where(spin, 1e-4, 1e-5)
+
+    failures = []
+    stats = {}
+
+    def check(name, a, b, tol, mask):
+        err = np.abs(a - b)
+        tolv = np.broadcast_to(tol, err.shape)
+        ratio = np.where(mask, err / np.maximum(tolv, 1e-300), 0.0)
+        if mask.any():
+            stats[name] = (float(ratio.max()), float(np.quantile(ratio[mask], 0.999)),
+                           int((ratio > 1).sum()))
+        bad = mask & ~(err <= tolv)
+        if bad.any():
+            i = np.flatnonzero(bad)[np.argmax(ratio[bad])]
+            failures.append(f"{name}: {int(bad.sum())} over tolerance, worst id={o['id'][i]} "
+                            f"lin={o['lineage'][i]} order={o['order'][i]} gpu={a[i]!r} "
+                            f"oracle={b[i]!r} tol={tolv[i]!r} kinds={o['kinds'][i]}")
+
+    for ax in range(3):
+        check(f"pos[{ax}]", g["pos"][:, ax].astype(np.float64), o["pos"][:, ax],
+              1e-5 * np.abs(o["pos"][:, ax]) + 1e-7, ok_state)
+    vnorm = np.linalg.norm(o["vel"], axis=1)
+    for ax in range(3):
+        check(f"vel[{ax}]", g["vel"][:, ax].astype(np.float64), o["vel"][:, ax], 1e-5 * vnorm,
+              ok_state)
+    check("t", g["t"].astype(np.float64), o["t"], 1e-5 * np.abs(o["t"]) + 3e-11, ok_state)
+    check("w", g["w"].astype(np.float64), o["w"], wtol * np.abs(o["w"]) + 1e-30, ok_state)
+    # detector
+    both = ok_state & (o["bin"] >= 0) | ok_state & (g["bin"] >= 0)
+    bad = ok_state & (g["bin"] != o["bin"])
+    if bad.any():
+        i = np.flatnonzero(bad)[0]
+        failures.append(f"bin: {int(bad.sum())} differ, first id={o['id'][i]} "
+                        f"lin={o['lineage'][i]} gpu={g['bin'][i]} oracle={o['bin'][i]} "
+                        f"margins={o['margin_anc'][i]},{o['margin_own'][i]}")
+    vt = wtol * np.abs(o["value"]) + o["value_sens"] * DELTA_B + 1e-30
+    same_bin = both & (g["bin"] == o["bin"])
+    check("value", g["value"].astype(np.float64), o["value"], vt, same_bin)
+    rec = same_bin & (o["bin"] >= 0)
+    check("tof", g["tof"].astype(np.float64), o["tof"], 1e-5 * np.abs(o["tof"]) + 1e-12, rec)
+    nflag = int((~ok_state).sum()) + len(only_o) + len(only_g)
+    frac = nflag / max(1, len(orc))
+    print(f"[parity-stats] n={len(orc)} flagged={nflag} ({frac:.2e}) "
+          + " ".join(f"{k}:max={v[0]:.3g},q999={v[1]:.3g},over={v[2]}" for k, v in stats.items()),
+          flush=True)
+    if failures:
+        raise AssertionError("; ".join(failures))
+    assert frac <= max_flag_frac, f"too many near-decision packets: {frac}"
+    return {"n_gpu": len(gpu), "n_oracle": len(orc), "n_common": len(g),
+            "n_flagged": nflag, "flag_frac": frac,
+            "max_rel_w": float(np.max(np.abs(g["w"][ok_state] - o["w"][ok_state]) /
+                                      np.maximum(np.abs(o["w"][ok_state]), 1e-300)))
+            if ok_state.any() else 0.0}
+
+
+def compare_hist(hg, ho, gpu, orc):
+    """Per-bin: |G - O| <= sum over the bin's packets of their value
+    tolerance, plus the values of near-decision packets on either side."""
+    hg = np.asarray(hg, dtype=np.float64)
+    ho = np.asarray(ho, dtype=np.float64)
+    n = len(ho)
+    margin = np.minimum(orc["margin_anc"], orc["margin_own"])
+    spin = (orc["kinds"] & SPINWAVE_BIT) != 0
+    tol_o = np.where(spin, 1e-4, 1e-5) * np.abs(orc["value"]) + orc["value_sens"] * DELTA_B
+    allow = np.zeros(n)
+    m = orc["bin"] >= 0
+    np.add.at(allow, orc["bin"][m], tol_o[m])
+    f = m & (margin < 1.0)
+    np.add.at(allow, orc["bin"][f], np.abs(orc["value"][f]))
+    # any GPU packet not matched to an unflagged oracle packet
+    kg = _key(gpu)
+    ko_ok = _key(orc)[margin >= 1.0]
+    unmatched = ~np.isin(kg, ko_ok) & (gpu["bin"] >= 0)
+    np.add.at(allow, gpu["bin"][unmatched], np.abs(gpu["value"][unmatched]).astype(np.float64))
+    diff = np.abs(hg - ho)
+    bad = diff > allow * 1.0000001 + 1e-12 * np.abs(ho) + 1e-300
+    if bad.any():
+        i = np.flatnonzero(bad)[0]
+        raise AssertionError(f"histogram bin {i}: gpu={hg[i]} oracle={ho[i]} allow={allow[i]}")
+    return {"bins_nonzero": int((ho != 0).sum()), "sum_gpu": float(hg.sum()),
+            "sum_oracle": float(ho.sum())}
