@@ -175,6 +175,15 @@ struct ORecord {
   int32_t pad;
 };
 
+// Parameters of a gradient: the raw DOS values of kernel dos_k of scatterer
+// dos_s (one parameter per bin), sigma_abs of scatterer abs_s, and the
+// nominal sigma of kernel sig_k of scatterer sig_s.  Gradient layout:
+// [DOS bins..., sigma_abs, sigma].
+struct OParamMap {
+  int32_t dos_s, dos_k, abs_s, sig_s, sig_k;
+  int32_t pad;
+};
+
 struct OTally {
   double w_escaped[8];      // sum of escaping weight per order
   double w_detected[8];     // sum of recorded value per order
@@ -278,6 +287,7 @@ struct Packet {
   int order;
   double margin_anc;  // min normalised margin of the decisions that made it
   uint32_t kinds;     // kernel types met in its ancestry (bit = type)
+  std::vector<double> dlogw;  // d log(w) / d(parameters), when gradients are on
 };
 
 struct Interval {
@@ -490,6 +500,8 @@ struct Scatter {
   V3 dir;
   double speed;
   double factor;  // weight multiplier
+  double dw_q2;   // Q^2 entering the Debye-Waller factor (0 if none)
+  int dos_bin;    // DOS bin of a one-phonon draw (-1 otherwise)
 };
 
 V3 isotropic_direction(double u_cos, double u_phi) {
@@ -516,10 +528,13 @@ Scatter k_iso(const OKernel& k, const ScatInfo& si, const Packet& P, const doubl
   r.dir = isotropic_direction(u[2], u[3]);
   r.speed = P.speed;
   r.factor = 1.0;
+  r.dw_q2 = 0.0;
+  r.dos_bin = -1;
   if (k.dw) {
     double kk = k_from_speed(P.speed);
     V3 Q = sub(scale(P.dir, kk), scale(r.dir, kk));
-    r.factor = std::exp(-si.dw_coef * dot(Q, Q));
+    r.dw_q2 = dot(Q, Q);
+    r.factor = std::exp(-si.dw_coef * r.dw_q2);
   }
   return r;
 }
@@ -559,9 +574,12 @@ Scatter k_powder(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
   r.dir = add(scale(P.dir, std::cos(two_theta)), scale(lateral, std::sin(two_theta)));
   r.speed = P.speed;
   r.factor = 1.0;
+  r.dw_q2 = 0.0;
+  r.dos_bin = -1;
   if (k.dw) {
     double Q = 2.0 * kPi / d;
-    r.factor = std::exp(-si.dw_coef * Q * Q);
+    r.dw_q2 = Q * Q;
+    r.factor = std::exp(-si.dw_coef * r.dw_q2);
   }
   return r;
 }
@@ -575,10 +593,12 @@ Scatter k_powder(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
 Scatter k_phonon(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
                  const Packet& P, const double* u, double* margin) {
   Scatter r;
+  r.dw_q2 = 0.0;
   int b = 0;
   for (; b < k.nbins; ++b)
     if (u[2] < ki.cdf[b]) break;
   if (b == k.nbins) b = k.nbins - 1;
+  r.dos_bin = b;
   *margin = std::min(*margin, std::fabs(u[2] - ki.cdf[b]) / kTauU);
   if (b > 0) *margin = std::min(*margin, std::fabs(u[2] - ki.cdf[b - 1]) / kTauU);
   double e = (b + u[3]) * ki.de;
@@ -603,6 +623,7 @@ Scatter k_phonon(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
   double Q2 = dot(Q, Q);
   double h2m = hbar2_over_2M(k.M);
   double dw = k.dw ? std::exp(-si.dw_coef * Q2) : 1.0;
+  r.dw_q2 = k.dw ? Q2 : 0.0;
   double coth = 1.0 / std::tanh(e / (2.0 * kT));
   r.factor = (k_f / k_i) * h2m * Q2 * dw * coth / e;
   return r;
@@ -613,6 +634,8 @@ Scatter k_phonon(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
 // Proposal: isotropic direction, energy transfer uniform on [E_lo, E_hi].
 Scatter k_spinwave(const OKernel& k, const Packet& P, const double* u) {
   Scatter r;
+  r.dw_q2 = 0.0;
+  r.dos_bin = -1;
   double Ei = kEperV2 * P.speed * P.speed;
   double wmax = 24.0 * k.J * k.S;
   double lo = -10.0 * k.gamma;
@@ -641,6 +664,8 @@ Scatter k_spinwave(const OKernel& k, const Packet& P, const double* u) {
 // tabulated isotropic S(Q,E): value of the grid cell containing (|Q|, E)
 Scatter k_sqe(const OKernel& k, const Packet& P, const double* u, double* margin) {
   Scatter r;
+  r.dw_q2 = 0.0;
+  r.dos_bin = -1;
   double Ei = kEperV2 * P.speed * P.speed;
   double E = k.Emin + u[2] * (k.Emax - k.Emin);
   double Ef = Ei - E;
@@ -673,8 +698,18 @@ Scatter k_sqe(const OKernel& k, const Packet& P, const double* u, double* margin
 
 // ------------------------------------------------------------- simulation
 struct Sim {
+  // S: the parameters the weights are evaluated at; Sp: the parameters the
+  // random choices are drawn from (the same setup except for a gradient or a
+  // re-weighting check, where Sp is frozen at the reference point)
   const OSetup& S;
-  std::vector<ScatInfo> info;
+  const OSetup& Sp;
+  std::vector<ScatInfo> info, pinfo;
+  // gradient (forward mode): dense tangent of log(w) for every packet
+  bool tangent = false;
+  OParamMap pm;
+  int np = 0;
+  const double* dLdI = nullptr;
+  double* grad = nullptr;
   Rng rng;
   double* hist;
   double* hist_w2;
@@ -683,7 +718,42 @@ struct Sim {
   uint64_t n_rec;
   OTally* tally;
 
-  Sim(const OSetup& s) : S(s) {}
+  Sim(const OSetup& s, const OSetup& sp) : S(s), Sp(sp) {}
+
+  // d mu_total / d theta of scatterer s at speed v (only sigma_abs and the
+  // nominal sigma are parameters of the attenuation)
+  void add_dmu(std::vector<double>& g, int s, double speed, double scale) const {
+    const OScatterer& sc = S.s[s];
+    if (s == pm.abs_s) g[np - 2] += scale * 100.0 * sc.n * (kV2200 / speed);
+    if (s == pm.sig_s) g[np - 1] += scale * 100.0 * sc.n;
+  }
+
+  // d log(DW factor) / d theta for a Debye-Waller factor exp(-h2m gamma0 Q^2)
+  // of the scatterer that owns the parameter DOS:
+  // gamma0 = sum_b c_b theta_b / S, c_b = coth(e_b/2kT) de / e_b, S = sum theta de
+  void add_ddw(std::vector<double>& g, double q2) const {
+    const OKernel& k = S.s[pm.dos_s].k[pm.dos_k];
+    double de = k.emax / k.nbins;
+    double Ssum = 0.0;
+    for (int b = 0; b < k.nbins; ++b) Ssum += k.dos[b] * de;
+    double g0 = gamma0(k);
+    double h2m = hbar2_over_2M(k.M);
+    for (int b = 0; b < k.nbins; ++b) {
+      double e = (b + 0.5) * de;
+      double c = de / (e * std::tanh(e / (2.0 * kBoltzmann * k.T)));
+      g[b] += -h2m * q2 * (c - g0 * de) / Ssum;
+    }
+  }
+
+  // d log Z(e) / d theta for a draw from DOS bin b: Z_b = theta_b / S
+  void add_dlogz(std::vector<double>& g, int b) const {
+    const OKernel& k = S.s[pm.dos_s].k[pm.dos_k];
+    double de = k.emax / k.nbins;
+    double Ssum = 0.0;
+    for (int j = 0; j < k.nbins; ++j) Ssum += k.dos[j] * de;
+    for (int j = 0; j < k.nbins; ++j) g[j] -= de / Ssum;
+    g[b] += 1.0 / k.dos[b];
+  }
 
   // ----- detector: sphere of radius R about the origin, rings in 2theta
   void detect_sphere(const Packet& P, ORecord& rec, double* margin) {
@@ -819,7 +889,11 @@ struct Sim {
     else detect_tubes(P, rec, &margin);
     rec.margin_own = std::min(flight_margin, margin);
     tally->w_escaped[P.order] += P.w;
-    if (rec.bin >= 0) {
+    if (rec.bin >= 0 && tangent) {
+      double g = dLdI[rec.bin] * rec.value;
+      for (int j = 0; j < np; ++j) grad[j] += g * P.dlogw[j];
+    }
+    if (rec.bin >= 0 && hist) {
       hist[rec.bin] += rec.value;
       if (hist_w2) hist_w2[rec.bin] += rec.value * rec.value;
       tally->n_detected++;
@@ -859,21 +933,26 @@ struct Sim {
       const Interval& iv = segs[g];
       const OScatterer& sc = S.s[iv.scat];
       const ScatInfo& si = info[iv.scat];
+      // random choices follow the proposal parameters (identical to S except
+      // when re-weighting or differentiating with frozen proposals)
+      const OScatterer& scp = Sp.s[iv.scat];
+      const ScatInfo& sip = pinfo[iv.scat];
       double L = iv.s_out - iv.s_in;
       double m_mu = kHuge;
       Mu mu = attenuation(sc, si, P.speed, &m_mu);
+      Mu mup = attenuation(scp, sip, P.speed, &m_mu);
       *own_margin = std::min(*own_margin, m_mu);
       tally->n_segments++;
       double att = std::exp(-mu.total * L);
-      double a = -std::expm1(-mu.total * L);  // probability to interact
+      double a = -std::expm1(-mup.total * L);  // probability to interact
       tally->n_transcend += 2;
-      if (P.order < S.K && P.w >= S.min_prob && mu.scat > 0.0) {
+      if (P.order < S.K && P.w >= S.min_prob && mup.scat > 0.0) {
         uint32_t lin = P.lineage * 8u + (uint32_t)g + 1u;
         double u[8];
         rng.draw(id, STREAM_SCATTER, lin, 0, u);
         rng.draw(id, STREAM_SCATTER, lin, 1, u + 4);
         // forced collision: x ~ mu e^{-mu x} / (1 - e^{-mu L}) on [0, L]
-        double x = -std::log1p(-u[0] * a) / mu.total;
+        double x = -std::log1p(-u[0] * a) / mup.total;
         tally->n_transcend++;
         double child_margin = *own_margin;
         Packet C;
@@ -881,38 +960,59 @@ struct Sim {
         C.t = t0 + (iv.s_in + x) / P.speed;
         C.dir = P.dir;
         C.speed = P.speed;
-        C.w = P.w * (mu.scat / mu.total) * a;
-        tally->w_abs[P.order] += P.w * (mu.abs / mu.total) * a;
+        C.w = P.w * (mup.scat / mup.total) * a;
+        tally->w_abs[P.order] += P.w * (mup.abs / mup.total) * a;
         tally->w_scat[P.order] += C.w;
         // kernel choice with probability mu_k / mu_s
-        double target = u[1] * mu.scat;
+        double target = u[1] * mup.scat;
         double cum = 0.0;
         int kk = sc.nk - 1;
         for (int j = 0; j < sc.nk; ++j) {
-          cum += mu.k[j];
+          cum += mup.k[j];
           if (j < sc.nk - 1)
-            child_margin = std::min(child_margin, std::fabs(target - cum) / (kTauRel * mu.scat));
+            child_margin = std::min(child_margin, std::fabs(target - cum) / (kTauRel * mup.scat));
           if (target < cum) {
             kk = j;
             break;
           }
         }
+        // true rate over proposal density of the point and the kernel; 1 when
+        // the two parameter sets coincide
+        C.w *= (mu.k[kk] * std::exp(-mu.total * x)) / (mup.k[kk] * std::exp(-mup.total * x));
         const OKernel& k = sc.k[kk];
         tally->n_splits++;
         tally->n_kernel[k.type]++;
         Scatter r;
         Packet Pin = P;  // state of the incident packet at the scattering point
+        const OKernel& kp = scp.k[kk];
         switch (k.type) {
-          case K_ISO_EL: r = k_iso(k, si, Pin, u); break;
-          case K_POWDER: r = k_powder(k, si.k[kk], si, Pin, u, &child_margin); break;
-          case K_PHONON: r = k_phonon(k, si.k[kk], si, Pin, u, &child_margin); break;
-          case K_SPINWAVE: r = k_spinwave(k, Pin, u); break;
-          default: r = k_sqe(k, Pin, u, &child_margin); break;
+          case K_ISO_EL: r = k_iso(kp, sip, Pin, u); break;
+          case K_POWDER: r = k_powder(kp, sip.k[kk], sip, Pin, u, &child_margin); break;
+          case K_PHONON: r = k_phonon(kp, sip.k[kk], sip, Pin, u, &child_margin); break;
+          case K_SPINWAVE: r = k_spinwave(kp, Pin, u); break;
+          default: r = k_sqe(kp, Pin, u, &child_margin); break;
+        }
+        // evaluation-point Debye-Waller factor and DOS over the proposal's
+        if (r.dw_q2 > 0.0) r.factor *= std::exp(-(si.dw_coef - sip.dw_coef) * r.dw_q2);
+        if (r.dos_bin >= 0) {
+          double ssum = 0.0, psum = 0.0;
+          for (int b = 0; b < k.nbins; ++b) {
+            ssum += k.dos[b];
+            psum += kp.dos[b];
+          }
+          r.factor *= (k.dos[r.dos_bin] / ssum) / (kp.dos[r.dos_bin] / psum);
         }
         tally->n_transcend += 4;
         C.dir = r.dir;
         C.speed = r.speed;
         C.w *= r.factor;
+        if (tangent) {
+          C.dlogw = P.dlogw;
+          if (iv.scat == pm.sig_s && kk == pm.sig_k) C.dlogw[np - 1] += 1.0 / k.sigma;
+          add_dmu(C.dlogw, iv.scat, P.speed, -x);
+          if (r.dw_q2 > 0.0 && iv.scat == pm.dos_s) add_ddw(C.dlogw, r.dw_q2);
+          if (r.dos_bin >= 0 && iv.scat == pm.dos_s && kk == pm.dos_k) add_dlogz(C.dlogw, r.dos_bin);
+        }
         C.lineage = lin;
         C.order = P.order + 1;
         C.margin_anc = std::min(P.margin_anc, child_margin);
@@ -923,6 +1023,7 @@ struct Sim {
         tally->w_lost[P.order] += P.w * a;
       }
       P.w *= att;
+      if (tangent) add_dmu(P.dlogw, iv.scat, P.speed, -L);
     }
     if (!segs.empty()) {
       double s_end = segs.back().s_out;
@@ -968,6 +1069,7 @@ struct Sim {
     P.order = 0;
     P.margin_anc = kHuge;
     P.kinds = 0u;
+    if (tangent) P.dlogw.assign(np, 0.0);
   }
 };
 
@@ -1023,8 +1125,7 @@ void oracle_kernel_sample(const OSetup* S, int s, int j, const double dir[3], do
                           const double u[8], double out[4]) {
   std::vector<ScatInfo> info;
   prepare(*S, info);
-  Packet P;
-  std::memset(&P, 0, sizeof(P));
+  Packet P{};
   P.dir = {dir[0], dir[1], dir[2]};
   P.speed = speed;
   double m = kHuge;
@@ -1046,12 +1147,17 @@ void oracle_kernel_sample(const OSetup* S, int s, int j, const double dir[3], do
 // Full transport of histories [first, first+n).  hist (and hist_w2 if not
 // null) are accumulated into.  Records of every escaping packet go to recs
 // (up to rec_cap); *n_rec gets the total count.
-int oracle_run(const OSetup* S, uint64_t seed, uint64_t first, uint64_t n, double* hist,
-               double* hist_w2, ORecord* recs, uint64_t rec_cap, uint64_t* n_rec, OTally* tally) {
+// Transport with weights evaluated at S and every random choice drawn from
+// the proposal Sp (Sp = S for a plain run).  Sp may differ from S only in
+// table values and cross sections, not in structure.
+int oracle_run2(const OSetup* S, const OSetup* Sp, uint64_t seed, uint64_t first, uint64_t n,
+                double* hist, double* hist_w2, ORecord* recs, uint64_t rec_cap, uint64_t* n_rec,
+                OTally* tally) {
   if (S->K < 0 || S->K > 7) return 1;
   std::memset(tally, 0, sizeof(OTally));
-  Sim sim(*S);
+  Sim sim(*S, *Sp);
   prepare(*S, sim.info);
+  prepare(*Sp, sim.pinfo);
   sim.rng.seed = seed;
   sim.rng.tally = tally;
   sim.hist = hist;
@@ -1067,6 +1173,46 @@ int oracle_run(const OSetup* S, uint64_t seed, uint64_t first, uint64_t n, doubl
     sim.process(P, id);
   }
   if (n_rec) *n_rec = sim.n_rec;
+  return 0;
+}
+
+int oracle_run(const OSetup* S, uint64_t seed, uint64_t first, uint64_t n, double* hist,
+               double* hist_w2, ORecord* recs, uint64_t rec_cap, uint64_t* n_rec, OTally* tally) {
+  return oracle_run2(S, S, seed, first, n, hist, hist_w2, recs, rec_cap, n_rec, tally);
+}
+
+// Forward-mode gradient of sum_b dLdI[b] I_b with respect to the parameters
+// of `pm`, with every random choice frozen at S (the weights of a path are
+// its true density over the proposal density at S).  grad[] is accumulated
+// into; its length is nbins(DOS) + 2.
+int oracle_gradient(const OSetup* S, const OParamMap* pm, uint64_t seed, uint64_t first,
+                    uint64_t n, const double* dLdI, double* grad, OTally* tally) {
+  if (S->K < 0 || S->K > 7) return 1;
+  const OKernel& kd = S->s[pm->dos_s].k[pm->dos_k];
+  if (kd.type != K_PHONON) return 2;
+  std::memset(tally, 0, sizeof(OTally));
+  Sim sim(*S, *S);
+  prepare(*S, sim.info);
+  prepare(*S, sim.pinfo);
+  sim.tangent = true;
+  sim.pm = *pm;
+  sim.np = kd.nbins + 2;
+  sim.dLdI = dLdI;
+  sim.grad = grad;
+  sim.rng.seed = seed;
+  sim.rng.tally = tally;
+  sim.hist = nullptr;
+  sim.hist_w2 = nullptr;
+  sim.recs = nullptr;
+  sim.rec_cap = 0;
+  sim.n_rec = 0;
+  sim.tally = tally;
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t id = first + i;
+    Packet P;
+    sim.source(id, P);
+    sim.process(P, id);
+  }
   return 0;
 }
 

@@ -71,6 +71,11 @@ class OSetup(C.Structure):
                 ("s", OScatterer * 4), ("det", ODetector), ("min_prob", C.c_double)]
 
 
+class OParamMap(C.Structure):
+    _fields_ = [("dos_s", C.c_int32), ("dos_k", C.c_int32), ("abs_s", C.c_int32),
+                ("sig_s", C.c_int32), ("sig_k", C.c_int32), ("pad", C.c_int32)]
+
+
 class OTally(C.Structure):
     _fields_ = [("w_escaped", C.c_double * 8), ("w_detected", C.c_double * 8),
                 ("n_packets", C.c_uint64 * 8), ("n_detected", C.c_uint64),
@@ -108,6 +113,14 @@ def lib():
         L.oracle_run.argtypes = [C.POINTER(OSetup), C.c_uint64, C.c_uint64, C.c_uint64,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
                                  C.POINTER(C.c_uint64), C.POINTER(OTally)]
+        L.oracle_run2.restype = C.c_int
+        L.oracle_run2.argtypes = [C.POINTER(OSetup), C.POINTER(OSetup), C.c_uint64, C.c_uint64,
+                                  C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64,
+                                  C.POINTER(C.c_uint64), C.POINTER(OTally)]
+        L.oracle_gradient.restype = C.c_int
+        L.oracle_gradient.argtypes = [C.POINTER(OSetup), C.POINTER(OParamMap), C.c_uint64,
+                                      C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p,
+                                      C.POINTER(OTally)]
         L.oracle_philox.argtypes = [C.c_uint32] * 6 + [C.POINTER(C.c_uint32)]
         L.oracle_uniform.restype = C.c_double
         L.oracle_uniform.argtypes = [C.c_uint32]
@@ -230,6 +243,45 @@ def run(cfg, n=None, first=0, seed=None, records=True, rec_cap=None, w2=False):
             raise RuntimeError("record capacity exceeded")
         recs = recs[:nrec.value]
     return hist, hw2, recs, tally
+
+
+def run_reweighted(cfg_eval, cfg_prop, n=None, first=0, seed=None):
+    """Histogram with weights at cfg_eval and every random choice drawn from
+    cfg_prop (frozen proposals; same structure, other table values/sigmas)."""
+    L = lib()
+    se, sp = Setup(cfg_eval), Setup(cfg_prop)
+    n = cfg_eval["N"] if n is None else n
+    seed = cfg_eval["seed"] if seed is None else seed
+    hist = np.zeros(se.nbins(), dtype=np.float64)
+    tally = OTally()
+    nrec = C.c_uint64(0)
+    rc = L.oracle_run2(C.byref(se.S), C.byref(sp.S), seed, first, n, hist.ctypes.data, None,
+                       None, 0, C.byref(nrec), C.byref(tally))
+    if rc != 0:
+        raise RuntimeError(f"oracle_run2 failed: {rc}")
+    return hist
+
+
+def gradient(cfg, param_map, dLdI, n=None, first=0, seed=None):
+    """Forward-mode gradient of sum_b dLdI[b] I_b w.r.t. (DOS bins..., sigma_abs,
+    sigma) of the parameter map {dos: (s, k), abs: s, sig: (s, k)}, with the
+    random choices frozen at cfg."""
+    L = lib()
+    st = Setup(cfg)
+    n = cfg["N"] if n is None else n
+    seed = cfg["seed"] if seed is None else seed
+    pm = OParamMap(param_map["dos"][0], param_map["dos"][1], param_map["abs"],
+                   param_map["sig"][0], param_map["sig"][1], 0)
+    nb = len(cfg["scatterers"][pm.dos_s]["kernels"][pm.dos_k]["dos"])
+    g = np.zeros(nb + 2)
+    d = np.ascontiguousarray(dLdI, dtype=np.float64)
+    assert d.shape[0] == st.nbins()
+    tally = OTally()
+    rc = L.oracle_gradient(C.byref(st.S), C.byref(pm), seed, first, n, d.ctypes.data,
+                           g.ctypes.data, C.byref(tally))
+    if rc != 0:
+        raise RuntimeError(f"oracle_gradient failed: {rc}")
+    return g
 
 
 def philox(ctr, key):
