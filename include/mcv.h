@@ -245,6 +245,43 @@ mcv_status mcv_trace(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t f
                      double* hist, mcv_packet_record* records, uint64_t capacity,
                      uint64_t* n_out_dev, void* stream);
 
+/* ------------------------------------------------------------- adjoint */
+/* Parameters of a gradient (an extension of the paper's method: the
+ * derivatives of the Monte Carlo estimate of I with every random choice held
+ * fixed): the raw values theta_b of the DOS of one one-phonon kernel (the
+ * kernel samples Z = theta / sum(theta de)), sigma_abs of one scatterer, and
+ * the nominal sigma of one non-powder kernel.  -1 in abs_scatterer /
+ * sigma_scatterer leaves that parameter out (its gradient entry stays 0).
+ * Gradient layout: [theta_0 .. theta_{nb-1}, sigma_abs, sigma]. */
+typedef struct {
+  int32_t dos_scatterer, dos_kernel;
+  int32_t abs_scatterer;
+  int32_t sigma_scatterer, sigma_kernel;
+  int32_t reserved;
+} mcv_param_map;
+
+/* number of gradient entries (nb + 2), or -1 for an invalid map */
+int64_t mcv_adjoint_nparams(mcv_plan p, const mcv_param_map* pm);
+
+/* Re-traces histories first .. first+n-1 with the same random numbers as
+ * mcv_run and adds to grad[nparams] (device, binary64, zeroed by the caller)
+ * the sum over recorded packets of dL_dI[bin] * value * d log(value)/d theta,
+ * where a packet's weight is its path density at theta over the density the
+ * path was drawn from at the plan's parameters (at theta = the plan's values
+ * this is the derivative of the estimate of sum_b dL_dI[b] I_b).  dL_dI:
+ * device binary64 [nbins].  The plan keeps a small FP64 workspace:
+ * concurrent adjoint calls on one plan race.  Supports max_orders <= 4.
+ * Errors: MCV_EINVAL, MCV_EUNSUPPORTED, MCV_ENOMEM, MCV_EHIP. */
+mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam, uint64_t seed,
+                       uint64_t first, uint64_t n, const double* dL_dI, double* grad,
+                       void* stream);
+
+/* Weighted L2 loss of a histogram against a target (streaming): *loss +=
+ * sum_b w_b (I_b - T_b)^2 and dL_dI_b = 2 w_b (I_b - T_b).  Device binary64
+ * arrays of n entries, 16-byte aligned; *loss is accumulated into. */
+mcv_status mcv_loss_grad(const double* I, const double* T, const double* w, int64_t n,
+                         double* dL_dI, double* loss, void* stream);
+
 /* Waits for the stream and reports a pending device error. */
 mcv_status mcv_sync(void* stream);
 const char* mcv_last_error(void);

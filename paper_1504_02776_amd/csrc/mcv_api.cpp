@@ -26,7 +26,12 @@ hipError_t launch_transport(const DevPlan* plan, const float* tables, int n_tabl
                             const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
                             int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
-                            hipStream_t stream);
+                            const AdjArgs* adj, hipStream_t stream);
+hipError_t launch_adjoint_finalize(double* grad, const double* sums, const double* dense_a,
+                                   double dnorm, int nb, hipStream_t stream);
+hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
+                            double* dLdI, double* loss, int grid, hipStream_t stream);
+size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb);
 size_t transport_static_lds();
 hipError_t set_transport_lds_limit(size_t bytes);
 }  // namespace mcv
@@ -212,9 +217,21 @@ struct mcv_detector_s {
   mcv_tube_layout tubes;
 };
 
+struct AdjointTables {
+  int key[5] = {-9, -9, -9, -9, -9};
+  int nb = 0;
+  double* inv_theta = nullptr;  // device [nb]
+  double* dense_a = nullptr;    // device [nb]
+  double* sums = nullptr;       // device [2]
+  double dnorm = 0.0;
+  int block = 0;
+};
+
 struct mcv_plan_s {
   int device = 0;
   DevPlan host;
+  std::vector<Scatterer> scat;  // host copy (adjoint tables)
+  AdjointTables adj;
   std::vector<float> tables;
   DevPlan* d_plan = nullptr;
   float* d_tables = nullptr;
@@ -395,6 +412,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     for (int i = 0; i < 3; ++i) S.pos[i] = (float)sc.shape.pos[i];
     for (int i = 0; i < 9; ++i) S.rot[i] = (float)sc.shape.rot[i];
     S.mu_abs2200 = (float)(100.0 * sc.mat.n_per_A3 * sc.mat.sigma_abs_b * 2200.0);
+    S.n100 = (float)(100.0 * sc.mat.n_per_A3);
     // Debye-Waller coefficient from the scatterer's phonon DOS:
     // 2W/Q^2 = hbar^2/2M * gamma_0, gamma_0 = int coth(E/2kT) Z(E)/E dE
     double dw = 0.0;
@@ -511,11 +529,10 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   p->R = d->R;
 
   // LDS: plan + tables + per-lane stack
-  const size_t tab_bytes = 4 * (size_t)((P.n_tables + 3) & ~3);
-  size_t lds_dyn = tab_bytes + (size_t)P.stack_cap * kFields * 4 * block;
+  size_t lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0);
   while (lds_dyn + transport_static_lds() > 160 * 1024 && block > 64) {
     block -= 64;
-    lds_dyn = tab_bytes + (size_t)P.stack_cap * kFields * 4 * block;
+    lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0);
   }
   if (lds_dyn + transport_static_lds() > 160 * 1024) {
     delete p;
@@ -523,6 +540,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   }
   p->block = block;
   p->device = device;
+  p->scat = a->scat;
   p->waves_per_simd = o.waves_per_simd > 0 ? o.waves_per_simd : 4;
 
   hipError_t e;
@@ -568,6 +586,9 @@ mcv_status mcv_plan_destroy(mcv_plan p) {
   (void)hipSetDevice(p->device);
   (void)hipFree(p->d_plan);
   (void)hipFree(p->d_tables);
+  if (p->adj.inv_theta) (void)hipFree(p->adj.inv_theta);
+  if (p->adj.dense_a) (void)hipFree(p->adj.dense_a);
+  if (p->adj.sums) (void)hipFree(p->adj.sums);
   (void)hipSetDevice(cur);
   delete p;
   return MCV_OK;
@@ -599,6 +620,16 @@ mcv_status make_beam(const mcv_plan_s* p, const mcv_beam* b, DevBeam* out) {
   return MCV_OK;
 }
 
+void grid_shape(const mcv_plan_s* p, uint64_t n, int block, uint64_t* grid, uint64_t* per_wave) {
+  const uint64_t waves_per_block = (uint64_t)block / 64;
+  const uint64_t target = (uint64_t)p->cus * 4 * p->waves_per_simd * 2;
+  uint64_t waves = (n + 63) / 64;
+  if (waves > target) waves = target;
+  *per_wave = (n + waves - 1) / waves;
+  waves = (n + *per_wave - 1) / *per_wave;
+  *grid = (waves + waves_per_block - 1) / waves_per_block;
+}
+
 mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t first, uint64_t n,
                   double* hist, double* hist_w2, DevRecord* rec, uint64_t cap,
                   unsigned long long* n_out, void* stream) {
@@ -608,19 +639,14 @@ mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t firs
   if (n > ((uint64_t)1 << 62) || first > ((uint64_t)1 << 62) - n)
     return fail(MCV_EINVAL, "history ids must stay below 2^62");
   if (n == 0) return MCV_OK;
-  const uint64_t waves_per_block = (uint64_t)p->block / 64;
-  const uint64_t target = (uint64_t)p->cus * 4 * p->waves_per_simd * 2;
-  uint64_t waves = (n + 63) / 64;
-  if (waves > target) waves = target;
-  const uint64_t per_wave = (n + waves - 1) / waves;
-  waves = (n + per_wave - 1) / per_wave;
-  const uint64_t grid = (waves + waves_per_block - 1) / waves_per_block;
+  uint64_t grid, per_wave;
+  grid_shape(p, n, p->block, &grid, &per_wave);
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
   hipError_t e = launch_transport(p->d_plan, p->d_tables, p->host.n_tables, p->host.stack_cap, B,
                                   seed, first, n, (int)grid, p->block, per_wave, hist, hist_w2,
-                                  rec, cap, n_out, (hipStream_t)stream);
+                                  rec, cap, n_out, nullptr, (hipStream_t)stream);
   if (cur != p->device) (void)hipSetDevice(cur);
   if (e != hipSuccess) return hipfail(e, "transport launch");
   return MCV_OK;
@@ -652,6 +678,158 @@ mcv_status mcv_sync(void* stream) {
   if (e != hipSuccess) return hipfail(e, "hipStreamSynchronize");
   e = hipGetLastError();
   if (e != hipSuccess) return hipfail(e, "pending device error");
+  return MCV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+const double kBoltzmannA = 0.08617333;
+
+// FP64 tables of the adjoint for one parameter map (cached in the plan):
+// 1/theta_b for the sparse DOS terms; for the dense terms, with S = sum
+// theta de, c_b = de / (e_b tanh(e_b / 2kT)), gamma0 = sum c_b theta_b / S:
+// dense_a[b] = -(hbar^2/2M)(c_b - gamma0 de)/S (per unit of sum Q^2 over
+// Debye-Waller events) and dnorm = -de/S (per one-phonon draw).
+mcv_status adjoint_tables(mcv_plan p, const mcv_param_map* pm) {
+  AdjointTables& A = p->adj;
+  int key[5] = {pm->dos_scatterer, pm->dos_kernel, pm->abs_scatterer, pm->sigma_scatterer,
+                pm->sigma_kernel};
+  if (A.inv_theta && std::equal(key, key + 5, A.key)) return MCV_OK;
+  const KernelCopy& kc = p->scat[pm->dos_scatterer].kernels[pm->dos_kernel];
+  const int nb = kc.k.nbins;
+  const double de = kc.k.emax / nb;
+  double S = 0.0;
+  for (double v : kc.dos) S += v * de;
+  const double kT = kBoltzmannA * kc.k.T_K;
+  std::vector<double> c(nb), inv(nb), dense(nb);
+  double g0 = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const double e = (b + 0.5) * de;
+    c[b] = de / (e * std::tanh(e / (2.0 * kT)));
+    g0 += c[b] * kc.dos[b] / S;
+  }
+  const double h2m = kHbar2over2mn * kNeutronMassAmu / kc.k.M_amu;
+  for (int b = 0; b < nb; ++b) {
+    inv[b] = kc.dos[b] > 0.0 ? 1.0 / kc.dos[b] : 0.0;
+    dense[b] = -h2m * (c[b] - g0 * de) / S;
+  }
+  if (A.inv_theta) (void)hipFree(A.inv_theta);
+  if (A.dense_a) (void)hipFree(A.dense_a);
+  A.inv_theta = A.dense_a = nullptr;
+  hipError_t e;
+  if (!A.sums && (e = hipMalloc(&A.sums, 2 * sizeof(double))) != hipSuccess)
+    return fail(MCV_ENOMEM, "hipMalloc adjoint sums");
+  if ((e = hipMalloc(&A.inv_theta, nb * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&A.dense_a, nb * sizeof(double))) != hipSuccess)
+    return fail(MCV_ENOMEM, "hipMalloc adjoint tables");
+  if ((e = hipMemcpy(A.inv_theta, inv.data(), nb * sizeof(double), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(A.dense_a, dense.data(), nb * sizeof(double), hipMemcpyHostToDevice)) !=
+          hipSuccess)
+    return hipfail(e, "hipMemcpy adjoint tables");
+  A.nb = nb;
+  A.dnorm = -de / S;
+  std::copy(key, key + 5, A.key);
+  int block = p->block;
+  while (transport_lds_bytes(p->host.n_tables, p->host.stack_cap, block, nb) +
+                 transport_static_lds() > 160 * 1024 && block > 64)
+    block -= 64;
+  if (transport_lds_bytes(p->host.n_tables, p->host.stack_cap, block, nb) +
+          transport_static_lds() > 160 * 1024)
+    return fail(MCV_EUNSUPPORTED, "adjoint partials do not fit in LDS");
+  A.block = block;
+  return MCV_OK;
+}
+
+mcv_status check_param_map(mcv_plan p, const mcv_param_map* pm) {
+  if (!pm) return fail(MCV_EINVAL, "null parameter map");
+  const int ns = (int)p->scat.size();
+  if (pm->dos_scatterer < 0 || pm->dos_scatterer >= ns || pm->dos_kernel < 0 ||
+      pm->dos_kernel >= (int)p->scat[pm->dos_scatterer].kernels.size() ||
+      p->scat[pm->dos_scatterer].kernels[pm->dos_kernel].k.type != MCV_K_PHONON)
+    return fail(MCV_EINVAL, "dos_scatterer/dos_kernel must name a one-phonon kernel");
+  if (p->scat[pm->dos_scatterer].kernels[pm->dos_kernel].k.nbins > 65535)
+    return fail(MCV_EUNSUPPORTED, "adjoint supports up to 65535 DOS bins");
+  if (pm->abs_scatterer < -1 || pm->abs_scatterer >= ns)
+    return fail(MCV_EINVAL, "abs_scatterer out of range");
+  if (pm->sigma_scatterer < -1 || pm->sigma_scatterer >= ns)
+    return fail(MCV_EINVAL, "sigma_scatterer out of range");
+  if (pm->sigma_scatterer >= 0) {
+    const auto& ks = p->scat[pm->sigma_scatterer].kernels;
+    if (pm->sigma_kernel < 0 || pm->sigma_kernel >= (int)ks.size() ||
+        ks[pm->sigma_kernel].k.type == MCV_K_POWDER || !(ks[pm->sigma_kernel].k.sigma_b > 0.0))
+      return fail(MCV_EINVAL, "sigma_kernel must name a non-powder kernel with sigma > 0");
+  }
+  if (p->host.K > kAdjMaxOrders) return fail(MCV_EUNSUPPORTED, "adjoint supports max_orders <= 4");
+  return MCV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t mcv_adjoint_nparams(mcv_plan p, const mcv_param_map* pm) {
+  if (!p || check_param_map(p, pm) != MCV_OK) return -1;
+  return (int64_t)p->scat[pm->dos_scatterer].kernels[pm->dos_kernel].k.nbins + 2;
+}
+
+mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam, uint64_t seed,
+                       uint64_t first, uint64_t n, const double* dL_dI, double* grad,
+                       void* stream) {
+  if (!p) return fail(MCV_EINVAL, "null plan");
+  mcv_status st = check_param_map(p, pm);
+  if (st != MCV_OK) return st;
+  if (!dL_dI || !grad) return fail(MCV_EINVAL, "null dL_dI or grad");
+  DevBeam B;
+  if ((st = make_beam(p, beam, &B)) != MCV_OK) return st;
+  if (n > ((uint64_t)1 << 62) || first > ((uint64_t)1 << 62) - n)
+    return fail(MCV_EINVAL, "history ids must stay below 2^62");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  st = adjoint_tables(p, pm);
+  if (st == MCV_OK && n > 0) {
+    AdjArgs AA;
+    AA.dos_s = pm->dos_scatterer;
+    AA.dos_k = pm->dos_kernel;
+    AA.abs_s = pm->abs_scatterer;
+    AA.sig_s = pm->sigma_scatterer;
+    AA.sig_k = pm->sigma_kernel;
+    AA.nb = p->adj.nb;
+    AA.dLdI = dL_dI;
+    AA.grad = grad;
+    AA.sums = p->adj.sums;
+    AA.inv_theta = p->adj.inv_theta;
+    uint64_t grid, per_wave;
+    grid_shape(p, n, p->adj.block, &grid, &per_wave);
+    hipError_t e = launch_transport(p->d_plan, p->d_tables, p->host.n_tables, p->host.stack_cap,
+                                    B, seed, first, n, (int)grid, p->adj.block, per_wave, nullptr,
+                                    nullptr, nullptr, 0, nullptr, &AA, (hipStream_t)stream);
+    if (e == hipSuccess)
+      e = launch_adjoint_finalize(grad, p->adj.sums, p->adj.dense_a, p->adj.dnorm, p->adj.nb,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) st = hipfail(e, "adjoint launch");
+  }
+  if (cur != p->device) (void)hipSetDevice(cur);
+  return st;
+}
+
+mcv_status mcv_loss_grad(const double* I, const double* T, const double* w, int64_t n,
+                         double* dL_dI, double* loss, void* stream) {
+  if (!I || !T || !w || !dL_dI || !loss || n < 0) return fail(MCV_EINVAL, "bad loss arguments");
+  if (((uintptr_t)I | (uintptr_t)T | (uintptr_t)w | (uintptr_t)dL_dI) & 15u)
+    return fail(MCV_EINVAL, "loss arrays must be 16-byte aligned");
+  if (n == 0) return MCV_OK;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int64_t grid = (n / 2 + 255) / 256;
+  if (grid > (int64_t)cus * 16) grid = (int64_t)cus * 16;
+  if (grid < 1) grid = 1;
+  hipError_t e = launch_loss_grad(I, T, w, n, dL_dI, loss, (int)grid, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(e, "loss launch");
   return MCV_OK;
 }
 

@@ -60,6 +60,7 @@ struct DevScat {
   float pos[3];
   float rot[9];      // local -> lab, row major
   float mu_abs2200;  // 100 n sigma_abs * 2200 (1/m * m/s)
+  float n100;        // 100 n: d mu / d sigma (1/m per barn)
   float dw_coef;     // 2W / Q^2 (A^2)
   DevKernel k[kMaxKern];
 };
@@ -94,6 +95,20 @@ struct DevPlan {
   DevScat s[kMaxScat];
   DevDet det;
 };
+
+// Parameters of an adjoint run (raw DOS bins of one phonon kernel, sigma_abs
+// of one scatterer, nominal sigma of one kernel) and where it accumulates.
+struct AdjArgs {
+  int32_t dos_s, dos_k, abs_s, sig_s, sig_k;
+  int32_t nb;               // DOS bins
+  const double* dLdI;       // per histogram bin
+  double* grad;             // [nb + 2]: DOS bins, sigma_abs, sigma
+  double* sums;             // [2]: sum g A, sum g n_phonon (dense DOS terms)
+  const double* inv_theta;  // [nb]: 1 / raw DOS value
+};
+
+constexpr int kAdjFields = 6;  // extra words per stacked packet in adjoint mode
+constexpr int kAdjMaxOrders = 4;
 
 struct DevBeam {
   int32_t type;  // 1 mono, 2 gauss

@@ -334,6 +334,8 @@ __device__ __forceinline__ Mu attenuation(const DevScat& S, const float* tab, fl
 // (true cross section per unit nominal cross section / proposal density).
 struct Out {
   float dx, dy, dz, sp, f;
+  float dwq2;  // Q^2 of the Debye-Waller factor applied (0 if none)
+  int bin;     // DOS bin of a one-phonon draw (-1 otherwise)
 };
 
 // |k_i - k_f|^2 without cancellation: (ki - kf)^2 + ki kf |d_i - d_f|^2
@@ -349,9 +351,12 @@ __device__ __forceinline__ Out k_iso(const DevKernel& K, const DevScat& S, const
   iso_dir(u[2], u[3], o.dx, o.dy, o.dz);
   o.sp = P.sp;
   o.f = 1.0f;
+  o.dwq2 = 0.0f;
+  o.bin = -1;
   if (K.dw) {
     const float k = P.sp * kKperV;
-    o.f = expf(-S.dw_coef * q2_of(k, k, 0.0f, P, o.dx, o.dy, o.dz));
+    o.dwq2 = q2_of(k, k, 0.0f, P, o.dx, o.dy, o.dz);
+    o.f = expf(-S.dw_coef * o.dwq2);
   }
   return o;
 }
@@ -379,9 +384,12 @@ __device__ __forceinline__ Out k_powder(const DevKernel& K, const DevScat& S, co
   o.dz = c2 * P.dz + s2 * (cs * e1z + sn * e2z);
   o.sp = P.sp;
   o.f = 1.0f;
+  o.dwq2 = 0.0f;
+  o.bin = -1;
   if (K.dw) {
     const float q = kTwoPi / d;
-    o.f = expf(-S.dw_coef * q * q);
+    o.dwq2 = q * q;
+    o.f = expf(-S.dw_coef * o.dwq2);
   }
   return o;
 }
@@ -398,6 +406,8 @@ __device__ __forceinline__ Out k_phonon(const DevKernel& K, const DevScat& S, co
   const float Ei = kEperV2 * P.sp * P.sp;
   const float Ef = create ? Ei - e : Ei + e;
   iso_dir(u[5], u[6], o.dx, o.dy, o.dz);
+  o.bin = b;
+  o.dwq2 = 0.0f;
   if (!(Ef > 0.0f)) {
     o.sp = P.sp;
     o.f = 0.0f;
@@ -408,6 +418,7 @@ __device__ __forceinline__ Out k_phonon(const DevKernel& K, const DevScat& S, co
   const float dk = (create ? e : -e) / (kHb2m * (ki + kf));
   const float q2 = q2_of(ki, kf, dk, P, o.dx, o.dy, o.dz);
   const float dw = K.dw ? expf(-S.dw_coef * q2) : 1.0f;
+  o.dwq2 = K.dw ? q2 : 0.0f;
   const float coth = 1.0f / tanhf(0.5f * x);
   o.sp = kf * kVperK;
   o.f = (kf / ki) * K.h2m * q2 * dw * coth / e;
@@ -421,6 +432,8 @@ __device__ __forceinline__ Out k_spinwave(const DevKernel& K, const Pk& P, const
   const float hi = fminf(K.wmax + 10.0f * K.gamma, 0.99f * Ei);
   iso_dir(u[3], u[4], o.dx, o.dy, o.dz);
   o.sp = P.sp;
+  o.dwq2 = 0.0f;
+  o.bin = -1;
   if (!(hi > lo)) {
     o.f = 0.0f;
     return o;
@@ -449,6 +462,8 @@ __device__ __forceinline__ Out k_sqe(const DevKernel& K, const float* tab, const
   const float Ef = Ei - E;
   iso_dir(u[3], u[4], o.dx, o.dy, o.dz);
   o.sp = P.sp;
+  o.dwq2 = 0.0f;
+  o.bin = -1;
   if (!(Ef > 0.0f)) {
     o.f = 0.0f;
     return o;
@@ -603,8 +618,20 @@ __device__ __forceinline__ Pk source(const DevBeam& B, uint64_t id, uint64_t see
 }
 
 // ------------------------------------------------------------------ stack
-__device__ __forceinline__ void push(float* st, int slot, int nthreads, int tid, const Pk& C) {
-  float* b = st + (size_t)slot * kFields * nthreads + tid;
+// Adjoint carry of a packet: d log(w)/d sigma_abs, d log(w)/d sigma, the sum
+// A of hbar^2 Q^2 / 2M ... over its Debye-Waller events (Q^2 only; the
+// constant is applied at the end), the number of one-phonon draws and their
+// DOS bins (16 bits each, up to kAdjMaxOrders).
+struct Adj {
+  float dabs, dsig, A;
+  uint32_t nph, b01, b23;
+};
+
+template <bool ADJ>
+__device__ __forceinline__ void push(float* st, int slot, int nthreads, int tid, const Pk& C,
+                                     const Adj& a) {
+  constexpr int NF = kFields + (ADJ ? kAdjFields : 0);
+  float* b = st + (size_t)slot * NF * nthreads + tid;
   b[0 * nthreads] = C.px;
   b[1 * nthreads] = C.py;
   b[2 * nthreads] = C.pz;
@@ -615,11 +642,21 @@ __device__ __forceinline__ void push(float* st, int slot, int nthreads, int tid,
   b[7 * nthreads] = C.t;
   b[8 * nthreads] = C.w;
   b[9 * nthreads] = __uint_as_float(C.lin);
+  if (ADJ) {
+    b[10 * nthreads] = a.dabs;
+    b[11 * nthreads] = a.dsig;
+    b[12 * nthreads] = a.A;
+    b[13 * nthreads] = __uint_as_float(a.nph);
+    b[14 * nthreads] = __uint_as_float(a.b01);
+    b[15 * nthreads] = __uint_as_float(a.b23);
+  }
 }
 
-__device__ __forceinline__ Pk pop(const float* st, int slot, int nthreads, int tid) {
-  const float* b = st + (size_t)slot * kFields * nthreads + tid;
-  Pk C;
+template <bool ADJ>
+__device__ __forceinline__ void pop(const float* st, int slot, int nthreads, int tid, Pk& C,
+                                    Adj& a) {
+  constexpr int NF = kFields + (ADJ ? kAdjFields : 0);
+  const float* b = st + (size_t)slot * NF * nthreads + tid;
   C.px = b[0 * nthreads];
   C.py = b[1 * nthreads];
   C.pz = b[2 * nthreads];
@@ -630,15 +667,26 @@ __device__ __forceinline__ Pk pop(const float* st, int slot, int nthreads, int t
   C.t = b[7 * nthreads];
   C.w = b[8 * nthreads];
   C.lin = __float_as_uint(b[9 * nthreads]);
-  return C;
+  if (ADJ) {
+    a.dabs = b[10 * nthreads];
+    a.dsig = b[11 * nthreads];
+    a.A = b[12 * nthreads];
+    a.nph = __float_as_uint(b[13 * nthreads]);
+    a.b01 = __float_as_uint(b[14 * nthreads]);
+    a.b23 = __float_as_uint(b[15 * nthreads]);
+  }
 }
 
 // ------------------------------------------------------------------ flight
 // Splits P at every material interval on its ray (children: first in *nxt,
-// the others pushed on the lane stack) and moves it to where it leaves.
-__device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, Pk& P, uint64_t id,
-                                    uint64_t seed, Pk& nxt, bool& has_nxt, float* st, int& nst,
-                                    int nthreads, int tid) {
+// the others pushed on the lane stack) and moves it to where it leaves.  In
+// adjoint mode the carries follow: each crossed length L adds -L dmu/dtheta,
+// each birth adds d log(mu_k) - x dmu/dtheta and the kernel's terms.
+template <bool ADJ>
+__device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, const AdjArgs& AA,
+                                    Pk& P, Adj& pa, uint64_t id, uint64_t seed, Pk& nxt,
+                                    Adj& na, bool& has_nxt, float* st, int& nst, int nthreads,
+                                    int tid) {
   float lo[kMaxSlots], hi[kMaxSlots], len[kMaxSlots];
   uint32_t valid = 0u, codes = 0u;
 #pragma unroll
@@ -693,11 +741,17 @@ __device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, Pk& P, 
         sl = len[q];
       }
     }
-    const DevScat& S = PL.s[j >> 1];
+    const int si = j >> 1;
+    const DevScat& S = PL.s[si];
     const Mu mu = attenuation(S, tab, P.sp);
     const float ml = mu.total * sl;
     const float att = expf(-ml);
     const float pint = -expm1f(-ml);  // probability to interact in the interval
+    float dmu_abs = 0.0f, dmu_sig = 0.0f;
+    if (ADJ) {
+      if (si == AA.abs_s) dmu_abs = S.n100 * 2200.0f / P.sp;
+      if (si == AA.sig_s) dmu_sig = S.n100;
+    }
     if (order < PL.K && P.w >= PL.min_prob && mu.scat > 0.0f) {
       const uint32_t lin = P.lin * 8u + g + 1u;
       float u[8];
@@ -743,17 +797,38 @@ __device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, Pk& P, 
       C.dz = o.dz;
       C.sp = o.sp;
       C.w *= o.f;
+      Adj ca;
+      if (ADJ) {
+        ca = pa;
+        ca.dabs -= x * dmu_abs;
+        ca.dsig -= x * dmu_sig;
+        if (si == AA.sig_s && kk == AA.sig_k) ca.dsig += S.n100 / K.mu;
+        if (si == AA.dos_s) {
+          ca.A += o.dwq2;
+          if (kk == AA.dos_k && o.bin >= 0) {
+            const uint32_t sh = 16u * (ca.nph & 1u);
+            if (ca.nph < 2u) ca.b01 |= (uint32_t)o.bin << sh;
+            else ca.b23 |= (uint32_t)o.bin << sh;
+            ++ca.nph;
+          }
+        }
+      }
       if (C.w > 0.0f) {
         if (!has_nxt) {
           nxt = C;
+          if (ADJ) na = ca;
           has_nxt = true;
         } else if (nst < PL.stack_cap) {
-          push(st, nst, nthreads, tid, C);
+          push<ADJ>(st, nst, nthreads, tid, C, ca);
           ++nst;
         }
       }
     }
     P.w *= att;
+    if (ADJ) {
+      pa.dabs -= sl * dmu_abs;
+      pa.dsig -= sl * dmu_sig;
+    }
     s_end = shi;
     ++g;
   }
@@ -770,14 +845,23 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-template <bool TRACE>
-__global__ void __launch_bounds__(256) transport(const DevPlan* __restrict__ gplan,
+enum { MODE_RUN = 0, MODE_TRACE = 1, MODE_ADJOINT = 2 };
+
+// MODE_RUN: histogram only.  MODE_TRACE: also one record per packet leaving
+// the sample.  MODE_ADJOINT: re-traces the same histories (same random
+// numbers) and accumulates dL/dtheta = sum over recorded packets of
+// dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
+// per workgroup.
+template <int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) transport(const DevPlan* __restrict__ gplan,
                                                  const float* __restrict__ gtab, DevBeam beam,
                                                  uint64_t seed, uint64_t first, uint64_t n,
                                                  uint64_t per_wave, double* __restrict__ hist,
                                                  double* __restrict__ hist_w2,
                                                  DevRecord* __restrict__ rec, uint64_t cap,
-                                                 unsigned long long* __restrict__ n_out) {
+                                                 unsigned long long* __restrict__ n_out,
+                                                 AdjArgs AA) {
+  constexpr bool ADJ = MODE == MODE_ADJOINT;
   __shared__ DevPlan PL;
   extern __shared__ float dyn[];
   const int tid = threadIdx.x;
@@ -789,108 +873,227 @@ __global__ void __launch_bounds__(256) transport(const DevPlan* __restrict__ gpl
     const int nt = gplan->n_tables;
     for (int i = tid; i < nt; i += nthreads) dyn[i] = gtab[i];
   }
+  const int tab_words = (gplan->n_tables + 3) & ~3;
+  // adjoint partials: [nb] per DOS bin (sum of g), then sigma_abs, sigma, A, n_phonon
+  double* acc = reinterpret_cast<double*>(dyn + tab_words);
+  const int acc_words = ADJ ? 2 * (((AA.nb + 4) + 1) & ~1) : 0;
+  if (ADJ)
+    for (int i = tid; i < AA.nb + 4; i += nthreads) acc[i] = 0.0;
   __syncthreads();
   const float* tab = dyn;
-  float* st = dyn + ((PL.n_tables + 3) & ~3);
+  float* st = dyn + tab_words + acc_words;
 
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
-  if (begin >= n) return;  // whole wave leaves together
-  const uint64_t end = begin + per_wave < n ? begin + per_wave : n;
-  const uint64_t lt = lanemask_lt();
-
-  Pk cur;
-  cur.lin = 0u;
-  bool has = false;
-  uint64_t hid = 0;
-  int nst = 0;
-  uint64_t next = begin;
-  while (true) {
-    if (!has && nst > 0) {
-      --nst;
-      cur = pop(st, nst, nthreads, tid);
-      has = true;
-    }
-    const bool need = !has;
-    const uint64_t m = __ballot(need);
-    if (need) {
-      const uint64_t h = next + (uint64_t)__popcll(m & lt);
-      if (h < end) {
-        hid = first + h;
-        cur = source(beam, hid, seed);
-        has = cur.w > 0.0f;
+  if (begin < n) {  // uniform per wave
+    const uint64_t end = begin + per_wave < n ? begin + per_wave : n;
+    const uint64_t lt = lanemask_lt();
+    Pk cur;
+    cur.lin = 0u;
+    Adj ca = {0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+    bool has = false;
+    uint64_t hid = 0;
+    int nst = 0;
+    uint64_t next = begin;
+    while (true) {
+      if (!has && nst > 0) {
+        --nst;
+        pop<ADJ>(st, nst, nthreads, tid, cur, ca);
+        has = true;
       }
-    }
-    next += (uint64_t)__popcll(m);
-    if (__ballot(has) == 0ull) break;
-    if (has) {
-      Pk nxt;
-      nxt.lin = 0u;
-      bool has_nxt = false;
-      fly(PL, tab, cur, hid, seed, nxt, has_nxt, st, nst, nthreads, tid);
-      const Hit hh = PL.det.type == DET_SPHERE ? detect_sphere(PL.det, cur)
-                                               : detect_tubes(PL.det, tab, cur, hid, seed);
-      if (hh.bin >= 0) {
-        if (hist) unsafeAtomicAdd(hist + hh.bin, (double)hh.value);
-        if (hist_w2) unsafeAtomicAdd(hist_w2 + hh.bin, (double)hh.value * (double)hh.value);
-      }
-      if (TRACE) {
-        const unsigned long long slot = atomicAdd(n_out, 1ull);
-        if (slot < cap) {
-          DevRecord r;
-          r.id = hid;
-          r.lineage = cur.lin;
-          r.order = order_of(cur.lin);
-          r.pos[0] = cur.px;
-          r.pos[1] = cur.py;
-          r.pos[2] = cur.pz;
-          r.vel[0] = cur.dx * cur.sp;
-          r.vel[1] = cur.dy * cur.sp;
-          r.vel[2] = cur.dz * cur.sp;
-          r.t = cur.t;
-          r.w = cur.w;
-          r.bin = hh.bin;
-          r.value = hh.value;
-          r.tof = hh.tof;
-          r.tube = hh.tube;
-          r.pixel = hh.pixel;
-          rec[slot] = r;
+      const bool need = !has;
+      const uint64_t m = __ballot(need);
+      if (need) {
+        const uint64_t h = next + (uint64_t)__popcll(m & lt);
+        if (h < end) {
+          hid = first + h;
+          cur = source(beam, hid, seed);
+          ca = Adj{0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+          has = cur.w > 0.0f;
         }
       }
-      if (has_nxt) cur = nxt;
-      else has = false;
+      next += (uint64_t)__popcll(m);
+      if (__ballot(has) == 0ull) break;
+      if (has) {
+        Pk nxt;
+        nxt.lin = 0u;
+        Adj na = ca;
+        bool has_nxt = false;
+        fly<ADJ>(PL, tab, AA, cur, ca, hid, seed, nxt, na, has_nxt, st, nst, nthreads, tid);
+        const Hit hh = PL.det.type == DET_SPHERE ? detect_sphere(PL.det, cur)
+                                                 : detect_tubes(PL.det, tab, cur, hid, seed);
+        if (hh.bin >= 0) {
+          if (ADJ) {
+            const double gv = AA.dLdI[hh.bin] * (double)hh.value;
+            if (gv != 0.0) {
+              atomicAdd(&acc[AA.nb + 0], gv * (double)ca.dabs);
+              atomicAdd(&acc[AA.nb + 1], gv * (double)ca.dsig);
+              atomicAdd(&acc[AA.nb + 2], gv * (double)ca.A);
+              atomicAdd(&acc[AA.nb + 3], gv * (double)ca.nph);
+              for (uint32_t e = 0; e < ca.nph && e < (uint32_t)kAdjMaxOrders; ++e) {
+                const uint32_t w = e < 2u ? ca.b01 : ca.b23;
+                atomicAdd(&acc[(w >> (16u * (e & 1u))) & 0xFFFFu], gv);
+              }
+            }
+          } else {
+            if (hist) unsafeAtomicAdd(hist + hh.bin, (double)hh.value);
+            if (hist_w2) unsafeAtomicAdd(hist_w2 + hh.bin, (double)hh.value * (double)hh.value);
+          }
+        }
+        if (MODE == MODE_TRACE) {
+          const unsigned long long slot = atomicAdd(n_out, 1ull);
+          if (slot < cap) {
+            DevRecord r;
+            r.id = hid;
+            r.lineage = cur.lin;
+            r.order = order_of(cur.lin);
+            r.pos[0] = cur.px;
+            r.pos[1] = cur.py;
+            r.pos[2] = cur.pz;
+            r.vel[0] = cur.dx * cur.sp;
+            r.vel[1] = cur.dy * cur.sp;
+            r.vel[2] = cur.dz * cur.sp;
+            r.t = cur.t;
+            r.w = cur.w;
+            r.bin = hh.bin;
+            r.value = hh.value;
+            r.tof = hh.tof;
+            r.tube = hh.tube;
+            r.pixel = hh.pixel;
+            rec[slot] = r;
+          }
+        }
+        if (has_nxt) {
+          cur = nxt;
+          if (ADJ) ca = na;
+        } else {
+          has = false;
+        }
+      }
     }
+  }
+  if (ADJ) {
+    __syncthreads();
+    for (int i = tid; i < AA.nb; i += nthreads)
+      if (acc[i] != 0.0) unsafeAtomicAdd(&AA.grad[i], acc[i] * AA.inv_theta[i]);
+    if (tid == 0) {
+      unsafeAtomicAdd(&AA.grad[AA.nb], acc[AA.nb]);
+      unsafeAtomicAdd(&AA.grad[AA.nb + 1], acc[AA.nb + 1]);
+      unsafeAtomicAdd(&AA.sums[0], acc[AA.nb + 2]);
+      unsafeAtomicAdd(&AA.sums[1], acc[AA.nb + 3]);
+    }
+  }
+}
+
+// grad[j] += dense_a[j] * sum(g A) + dnorm * sum(g n_phonon): the terms of
+// the Debye-Waller factor (through gamma_0) and of the DOS normalisation,
+// which touch every bin
+__global__ void adjoint_finalize(double* __restrict__ grad, const double* __restrict__ sums,
+                                 const double* __restrict__ dense_a, double dnorm, int nb) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < nb) grad[j] += dense_a[j] * sums[0] + dnorm * sums[1];
+}
+
+__global__ void zero2(double* p) {
+  if (threadIdx.x < 2) p[threadIdx.x] = 0.0;
+}
+
+// L = sum_b w_b (I_b - T_b)^2 and dL/dI_b = 2 w_b (I_b - T_b), streaming;
+// one atomic per workgroup for L
+__global__ void __launch_bounds__(256) loss_grad(const double* __restrict__ I,
+                                                 const double* __restrict__ T,
+                                                 const double* __restrict__ w, int64_t n,
+                                                 double* __restrict__ dLdI,
+                                                 double* __restrict__ loss) {
+  __shared__ double part[4];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 2;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; i < n; i += stride) {
+    if (i + 1 < n) {
+      const double2 a = *reinterpret_cast<const double2*>(I + i);
+      const double2 b = *reinterpret_cast<const double2*>(T + i);
+      const double2 c = *reinterpret_cast<const double2*>(w + i);
+      const double d0 = a.x - b.x, d1 = a.y - b.y;
+      double2 o;
+      o.x = 2.0 * c.x * d0;
+      o.y = 2.0 * c.y * d1;
+      *reinterpret_cast<double2*>(dLdI + i) = o;
+      acc += c.x * d0 * d0 + c.y * d1 * d1;
+    } else {
+      const double d0 = I[i] - T[i];
+      dLdI[i] = 2.0 * w[i] * d0;
+      acc += w[i] * d0 * d0;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += part[i];
+    unsafeAtomicAdd(loss, t);
   }
 }
 
 }  // namespace dev
 
 // ------------------------------------------------------------------ launch
+size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb) {
+  const size_t tab = (size_t)((n_tables + 3) & ~3);
+  const size_t acc = adj_nb > 0 ? 2 * (size_t)(((adj_nb + 4) + 1) & ~1) : 0;
+  const size_t nf = kFields + (adj_nb > 0 ? kAdjFields : 0);
+  return sizeof(float) * (tab + acc + (size_t)stack_cap * nf * block);
+}
+
 hipError_t launch_transport(const DevPlan* plan, const float* tables, int n_tables, int stack_cap,
                             const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
                             int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
-                            hipStream_t stream) {
-  const size_t lds = sizeof(float) * ((size_t)((n_tables + 3) & ~3) +
-                                      (size_t)stack_cap * kFields * block);
-  if (rec) {
-    hipLaunchKernelGGL(dev::transport<true>, dim3(grid), dim3(block), lds, stream, plan, tables,
-                       beam, seed, first, n, per_wave, hist, hist_w2, rec, cap, n_out);
+                            const AdjArgs* adj, hipStream_t stream) {
+  AdjArgs AA = {};
+  AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = -1;
+  if (adj) AA = *adj;
+  const size_t lds = transport_lds_bytes(n_tables, stack_cap, block, adj ? adj->nb : 0);
+  if (adj) {
+    hipLaunchKernelGGL(dev::zero2, dim3(1), dim3(64), 0, stream, AA.sums);
+    hipLaunchKernelGGL(dev::transport<dev::MODE_ADJOINT>, dim3(grid), dim3(block), lds, stream,
+                       plan, tables, beam, seed, first, n, per_wave, hist, hist_w2, rec, cap,
+                       n_out, AA);
+  } else if (rec) {
+    hipLaunchKernelGGL(dev::transport<dev::MODE_TRACE>, dim3(grid), dim3(block), lds, stream,
+                       plan, tables, beam, seed, first, n, per_wave, hist, hist_w2, rec, cap,
+                       n_out, AA);
   } else {
-    hipLaunchKernelGGL(dev::transport<false>, dim3(grid), dim3(block), lds, stream, plan, tables,
-                       beam, seed, first, n, per_wave, hist, hist_w2, rec, cap, n_out);
+    hipLaunchKernelGGL(dev::transport<dev::MODE_RUN>, dim3(grid), dim3(block), lds, stream, plan,
+                       tables, beam, seed, first, n, per_wave, hist, hist_w2, rec, cap, n_out, AA);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_finalize(double* grad, const double* sums, const double* dense_a,
+                                   double dnorm, int nb, hipStream_t stream) {
+  hipLaunchKernelGGL(dev::adjoint_finalize, dim3((nb + 255) / 256), dim3(256), 0, stream, grad,
+                     sums, dense_a, dnorm, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
+                            double* dLdI, double* loss, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(dev::loss_grad, dim3(grid), dim3(256), 0, stream, I, T, w, n, dLdI, loss);
   return hipGetLastError();
 }
 
 size_t transport_static_lds() { return sizeof(DevPlan); }
 
 hipError_t set_transport_lds_limit(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::transport<false>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::transport<true>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* fns[3] = {reinterpret_cast<const void*>(&dev::transport<dev::MODE_RUN>),
+                        reinterpret_cast<const void*>(&dev::transport<dev::MODE_TRACE>),
+                        reinterpret_cast<const void*>(&dev::transport<dev::MODE_ADJOINT>)};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace mcv

@@ -69,6 +69,19 @@ class mcv_beam(C.Structure):
                 ("z0", C.c_double)]
 
 
+class mcv_param_map(C.Structure):
+    _fields_ = [("dos_scatterer", C.c_int32), ("dos_kernel", C.c_int32),
+                ("abs_scatterer", C.c_int32), ("sigma_scatterer", C.c_int32),
+                ("sigma_kernel", C.c_int32), ("reserved", C.c_int32)]
+
+
+def param_map(dos=(0, 1), abs_scatterer=0, sigma=(0, 1)):
+    """Gradient parameters: DOS of kernel dos=(scatterer, kernel), sigma_abs
+    of abs_scatterer, nominal sigma of kernel sigma=(scatterer, kernel)."""
+    return mcv_param_map(dos[0], dos[1], abs_scatterer,
+                         -1 if sigma is None else sigma[0], -1 if sigma is None else sigma[1], 0)
+
+
 RECORD_DTYPE = np.dtype([
     ("id", np.uint64), ("lineage", np.uint32), ("order", np.int32), ("pos", np.float32, 3),
     ("vel", np.float32, 3), ("t", np.float32), ("w", np.float32), ("bin", np.int64),
@@ -79,7 +92,8 @@ assert RECORD_DTYPE.itemsize == 72
 EXPORTS = ["mcv_assembly_create", "mcv_assembly_add", "mcv_assembly_destroy",
            "mcv_detector_sphere", "mcv_detector_tubes", "mcv_detector_nbins",
            "mcv_detector_destroy", "mcv_plan_create", "mcv_plan_destroy", "mcv_plan_nbins",
-           "mcv_run", "mcv_trace", "mcv_sync", "mcv_last_error", "mcv_abi_version"]
+           "mcv_run", "mcv_trace", "mcv_sync", "mcv_last_error", "mcv_abi_version",
+           "mcv_adjoint_nparams", "mcv_adjoint", "mcv_loss_grad"]
 
 _lib = None
 
@@ -110,6 +124,9 @@ def lib():
             "mcv_trace": [P, C.POINTER(mcv_beam), C.c_uint64, C.c_uint64, C.c_uint64, P, P,
                           C.c_uint64, P, P],
             "mcv_sync": [P],
+            "mcv_adjoint": [P, C.POINTER(mcv_param_map), C.POINTER(mcv_beam), C.c_uint64,
+                            C.c_uint64, C.c_uint64, P, P, P],
+            "mcv_loss_grad": [P, P, P, C.c_int64, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -119,6 +136,8 @@ def lib():
         L.mcv_detector_nbins.restype = C.c_int64
         L.mcv_plan_nbins.argtypes = [P]
         L.mcv_plan_nbins.restype = C.c_int64
+        L.mcv_adjoint_nparams.argtypes = [P, C.POINTER(mcv_param_map)]
+        L.mcv_adjoint_nparams.restype = C.c_int64
         L.mcv_last_error.restype = C.c_char_p
         L.mcv_abi_version.restype = C.c_int32
         _lib = L
@@ -289,6 +308,26 @@ class Plan:
                             dtype=RECORD_DTYPE)
         return out, count
 
+    def nparams(self, pm):
+        n = lib().mcv_adjoint_nparams(self.h, C.byref(pm))
+        if n < 0:
+            raise MCVError(MCV_EINVAL, lib().mcv_last_error().decode())
+        return n
+
+    def adjoint(self, pm, dLdI, grad, n=None, first=0, seed=None, stream=None, beam=None):
+        """Adds to grad (float64 device tensor of nparams) the gradient of
+        sum_b dLdI[b] I_b with respect to the parameters of `pm`."""
+        n = self.cfg["N"] if n is None else n
+        seed = self.cfg["seed"] if seed is None else seed
+        b = self.beam if beam is None else make_beam(beam)
+        self._check_hist(dLdI)
+        import torch
+        if grad.dtype != torch.float64 or not grad.is_cuda or grad.numel() < self.nparams(pm):
+            raise ValueError("grad must be a float64 CUDA tensor of nparams entries")
+        check(lib().mcv_adjoint(self.h, C.byref(pm), C.byref(b), seed, first, n,
+                                C.c_void_p(dLdI.data_ptr()), C.c_void_p(grad.data_ptr()),
+                                _stream_ptr(stream)))
+
     def _check_hist(self, h):
         import torch
         if h.dtype != torch.float64 or not h.is_cuda or h.numel() < self.nbins or \
@@ -305,3 +344,14 @@ class Plan:
 
 def sync(stream=None):
     check(lib().mcv_sync(_stream_ptr(stream)))
+
+
+def loss_grad(I, T, w, dLdI, loss, stream=None):
+    """loss += sum w (I - T)^2; dLdI = 2 w (I - T) (float64 device tensors)."""
+    n = I.numel()
+    for t in (T, w, dLdI):
+        if t.numel() != n:
+            raise ValueError("size mismatch")
+    check(lib().mcv_loss_grad(C.c_void_p(I.data_ptr()), C.c_void_p(T.data_ptr()),
+                              C.c_void_p(w.data_ptr()), n, C.c_void_p(dLdI.data_ptr()),
+                              C.c_void_p(loss.data_ptr()), _stream_ptr(stream)))
