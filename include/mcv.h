@@ -282,6 +282,51 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
 mcv_status mcv_loss_grad(const double* I, const double* T, const double* w, int64_t n,
                          double* dL_dI, double* loss, void* stream);
 
+/* ------------------------------------------------------------- batches */
+/* Many independent simulations in one persistent launch (an extension of
+ * the paper's method, whose runs are independent MC streams, Sec. 3).  Each
+ * item is a plan, a beam, a seed, an id range and its own histogram. */
+typedef struct mcv_batch_s* mcv_batch;
+
+typedef struct {
+  mcv_plan plan;
+  mcv_beam beam;
+  uint64_t seed;
+  uint64_t first;
+  uint64_t n;
+  double* hist;  /* device binary64 [mcv_plan_nbins(plan)] */
+} mcv_batch_item;
+
+/* block_size: 64..256, multiple of 64 (0: 256); chunk: histories per work
+ * item of the queue (0: 4096); wgs_per_cu: cap on resident workgroups per CU
+ * (0: as many as fit); zero_hists: 1 = every run zeroes the histograms first
+ * (otherwise runs accumulate). */
+typedef struct {
+  int32_t block_size;
+  int32_t chunk;
+  int32_t wgs_per_cu;
+  int32_t zero_hists;
+} mcv_tuning;
+
+/* Builds the work queue (chunks of (item, id range), longest estimated
+ * first), uploads it, and captures [histogram zeroing + queue reset +
+ * persistent kernel] into a HIP graph.  The histograms and plans must stay
+ * alive until mcv_batch_destroy.  Errors: MCV_EINVAL, MCV_EUNSUPPORTED,
+ * MCV_EHIP. */
+mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t n,
+                            const mcv_tuning* tuning, int32_t device);
+/* Replays the graph on `stream`.  Each item's histogram receives the same
+ * values as mcv_run of that item (up to binary64 summation order).  Runs of
+ * one batch must not overlap. */
+mcv_status mcv_batch_run(mcv_batch b, void* stream);
+mcv_status mcv_batch_destroy(mcv_batch b);
+
+/* Times mcv_batch_run for block sizes {128, 256} x chunks {1024, 4096,
+ * 16384, 65536} (reps runs each after one warm-up) and returns the fastest
+ * tuning and its time per run (ms).  The histograms are overwritten. */
+mcv_status mcv_autotune(const mcv_batch_item* items, int32_t n, int32_t device, int32_t reps,
+                        mcv_tuning* best, double* best_ms);
+
 /* Waits for the stream and reports a pending device error. */
 mcv_status mcv_sync(void* stream);
 const char* mcv_last_error(void);

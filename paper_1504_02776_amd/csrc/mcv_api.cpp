@@ -834,3 +834,243 @@ mcv_status mcv_loss_grad(const double* I, const double* T, const double* w, int6
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batches
+namespace mcv {
+hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32_t n_chunks,
+                        uint32_t* cursor, double* const* zero_ptrs, const uint64_t* zero_sizes,
+                        int n_zero, int grid, int block, size_t lds, int reset_grid,
+                        hipStream_t stream);
+int batch_occupancy(int block, size_t lds);
+}  // namespace mcv
+
+struct mcv_batch_s {
+  int device = 0;
+  BatchItem* d_items = nullptr;
+  BatchChunk* d_chunks = nullptr;
+  uint32_t* d_cursor = nullptr;
+  double** d_zero_ptrs = nullptr;
+  uint64_t* d_zero_sizes = nullptr;
+  uint32_t n_chunks = 0;
+  int n_zero = 0;
+  int grid = 0, block = 0;
+  size_t lds = 0;
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void batch_free(mcv_batch_s* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_chunks) (void)hipFree(b->d_chunks);
+  if (b->d_cursor) (void)hipFree(b->d_cursor);
+  if (b->d_zero_ptrs) (void)hipFree(b->d_zero_ptrs);
+  if (b->d_zero_sizes) (void)hipFree(b->d_zero_sizes);
+  delete b;
+}
+
+// relative cost of one history of a plan: packets per history grow with the
+// order bound and the intervals per ray; the tube detector is dearer
+double history_cost(const mcv_plan_s* p) {
+  const double packets = 1.0 + p->host.K * std::max(1, p->host.smax);
+  return packets * (p->host.det.type == DET_TUBES ? 1.6 : 1.0);
+}
+
+}  // namespace
+
+extern "C" {
+
+mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t n,
+                            const mcv_tuning* tuning, int32_t device) {
+  if (!out || !items || n < 1) return fail(MCV_EINVAL, "batch needs at least one item");
+  *out = nullptr;
+  mcv_tuning t = {0, 0, 0, 1};
+  if (tuning) t = *tuning;
+  int block = t.block_size ? t.block_size : 256;
+  if (block < 64 || block > 256 || block % 64) return fail(MCV_EINVAL, "block_size must be 64..256, multiple of 64");
+  const uint64_t chunk = t.chunk > 0 ? (uint64_t)t.chunk : 4096;
+  if (chunk > 0xFFFFFFFFull) return fail(MCV_EINVAL, "chunk too large");
+  std::vector<BatchItem> hitems(n);
+  std::vector<std::pair<double, BatchChunk>> hchunks;
+  std::vector<double*> zp;
+  std::vector<uint64_t> zs;
+  int n_tables_max = 0, stack_max = 0;
+  for (int i = 0; i < n; ++i) {
+    const mcv_batch_item& it = items[i];
+    if (!it.plan || !it.hist) return fail(MCV_EINVAL, "batch item needs a plan and a histogram");
+    if (it.plan->device != device) return fail(MCV_EINVAL, "batch item plan is on another device");
+    DevBeam B;
+    mcv_status st = make_beam(it.plan, &it.beam, &B);
+    if (st != MCV_OK) return st;
+    if (it.n > ((uint64_t)1 << 62) || it.first > ((uint64_t)1 << 62) - it.n)
+      return fail(MCV_EINVAL, "history ids must stay below 2^62");
+    hitems[i].plan = it.plan->d_plan;
+    hitems[i].tables = it.plan->d_tables;
+    hitems[i].beam = B;
+    hitems[i].seed = it.seed;
+    hitems[i].id0 = it.first;
+    hitems[i].hist = it.hist;
+    n_tables_max = std::max(n_tables_max, it.plan->host.n_tables);
+    stack_max = std::max(stack_max, it.plan->host.stack_cap);
+    const double c = history_cost(it.plan);
+    for (uint64_t f = 0; f < it.n; f += chunk) {
+      BatchChunk ch;
+      ch.item = (uint32_t)i;
+      ch.first = f;
+      ch.count = (uint32_t)std::min<uint64_t>(chunk, it.n - f);
+      hchunks.push_back({c * ch.count, ch});
+    }
+    if (t.zero_hists) {
+      zp.push_back(it.hist);
+      zs.push_back((uint64_t)it.plan->nbins);
+    }
+  }
+  if (hchunks.empty()) return fail(MCV_EINVAL, "batch has no histories");
+  std::stable_sort(hchunks.begin(), hchunks.end(),
+                   [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<BatchChunk> cl;
+  for (auto& c : hchunks) cl.push_back(c.second);
+  size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, 0);
+  while (lds + transport_static_lds() > 160 * 1024 && block > 64) {
+    block -= 64;
+    lds = transport_lds_bytes(n_tables_max, stack_max, block, 0);
+  }
+  if (lds + transport_static_lds() > 160 * 1024)
+    return fail(MCV_EUNSUPPORTED, "batch tables and stacks exceed LDS");
+
+  auto* b = new (std::nothrow) mcv_batch_s();
+  if (!b) return fail(MCV_ENOMEM, "host allocation failed");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(device);
+  b->device = device;
+  b->block = block;
+  b->lds = lds;
+  b->n_chunks = (uint32_t)cl.size();
+  b->n_zero = (int)zp.size();
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  int occ = batch_occupancy(block, lds);
+  if (occ < 1) occ = 1;
+  if (t.wgs_per_cu > 0) occ = std::min(occ, (int)t.wgs_per_cu);
+  b->grid = std::max(1, std::min<int>(cus * occ, (int)cl.size()));
+  hipError_t e = hipSuccess;
+  auto up = [&](void** dst, const void* src, size_t bytes) {
+    if (e != hipSuccess) return;
+    if ((e = hipMalloc(dst, std::max<size_t>(bytes, 8))) != hipSuccess) return;
+    if (bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  up((void**)&b->d_items, hitems.data(), hitems.size() * sizeof(BatchItem));
+  up((void**)&b->d_chunks, cl.data(), cl.size() * sizeof(BatchChunk));
+  uint32_t zero = 0;
+  up((void**)&b->d_cursor, &zero, sizeof(uint32_t));
+  up((void**)&b->d_zero_ptrs, zp.data(), zp.size() * sizeof(double*));
+  up((void**)&b->d_zero_sizes, zs.data(), zs.size() * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    batch_free(b);
+    (void)hipSetDevice(cur);
+    return hipfail(e, "batch upload");
+  }
+  // capture reset + persistent kernel once; runs replay the graph
+  if ((e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) == hipSuccess &&
+      (e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
+    hipError_t el = launch_batch(b->d_items, b->d_chunks, b->n_chunks, b->d_cursor,
+                                 b->d_zero_ptrs, b->d_zero_sizes, b->n_zero, b->grid, b->block,
+                                 b->lds, cus * 4, b->capture);
+    e = hipStreamEndCapture(b->capture, &b->graph);
+    if (e == hipSuccess) e = el;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  }
+  (void)hipSetDevice(cur);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return hipfail(e, "batch graph capture");
+  }
+  *out = b;
+  return MCV_OK;
+}
+
+mcv_status mcv_batch_run(mcv_batch b, void* stream) {
+  if (!b) return fail(MCV_EINVAL, "null batch");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != b->device) (void)hipSetDevice(b->device);
+  hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  if (cur != b->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return hipfail(e, "hipGraphLaunch");
+  return MCV_OK;
+}
+
+mcv_status mcv_batch_destroy(mcv_batch b) {
+  if (!b) return MCV_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(b->device);
+  batch_free(b);
+  (void)hipSetDevice(cur);
+  return MCV_OK;
+}
+
+mcv_status mcv_autotune(const mcv_batch_item* items, int32_t n, int32_t device, int32_t reps,
+                        mcv_tuning* best, double* best_ms) {
+  if (!items || n < 1 || !best) return fail(MCV_EINVAL, "autotune needs items and an output");
+  if (reps < 1) reps = 3;
+  const int blocks[] = {128, 256};
+  const int chunks[] = {1024, 4096, 16384, 65536};
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(device);
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipSetDevice(cur);
+    return hipfail(e, "autotune setup");
+  }
+  double best_t = 1e300;
+  mcv_tuning bt = {256, 4096, 0, 1};
+  mcv_status st = MCV_OK;
+  for (int bl : blocks) {
+    for (int ck : chunks) {
+      mcv_tuning t = {bl, ck, 0, 1};
+      mcv_batch b = nullptr;
+      st = mcv_batch_create(&b, items, n, &t, device);
+      if (st != MCV_OK) break;
+      (void)mcv_batch_run(b, s);  // warm
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r) (void)mcv_batch_run(b, s);
+      (void)hipEventRecord(e1, s);
+      e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      mcv_batch_destroy(b);
+      if (e != hipSuccess) {
+        st = hipfail(e, "autotune run");
+        break;
+      }
+      const double per = ms / reps;
+      if (per < best_t) {
+        best_t = per;
+        bt = t;
+      }
+    }
+    if (st != MCV_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  (void)hipSetDevice(cur);
+  if (st != MCV_OK) return st;
+  *best = bt;
+  if (best_ms) *best_ms = best_t;
+  return MCV_OK;
+}
+
+}  // extern "C"

@@ -115,6 +115,23 @@ struct DevBeam {
   float E, sigma_rel, W, H, z0;
 };
 
+// one simulation of a batch
+struct BatchItem {
+  const DevPlan* plan;
+  const float* tables;
+  DevBeam beam;
+  uint64_t seed;
+  uint64_t id0;  // first history id
+  double* hist;
+};
+
+// a range of histories [id0 + first, id0 + first + count) of one item
+struct BatchChunk {
+  uint32_t item;
+  uint32_t count;
+  uint64_t first;
+};
+
 struct DevRecord {  // mirrors mcv_packet_record
   uint64_t id;
   uint32_t lineage;

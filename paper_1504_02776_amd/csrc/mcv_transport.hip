@@ -847,32 +847,138 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 enum { MODE_RUN = 0, MODE_TRACE = 1, MODE_ADJOINT = 2 };
 
+struct Sinks {
+  double* hist;
+  double* hist_w2;
+  DevRecord* rec;
+  uint64_t cap;
+  unsigned long long* n_out;
+  double* acc;  // adjoint LDS partials
+};
+
+// One wave traces histories first+begin .. first+end-1: every lane walks
+// the packet tree of one history depth first and takes the next history of
+// the range as soon as it is done (ballot + prefix count), so lanes stay busy
+// until the range is exhausted.  Called with the whole wave active.
+template <int MODE>
+__device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab, float* st,
+                                            const DevBeam& beam, uint64_t seed, uint64_t first,
+                                            uint64_t begin, uint64_t end, const Sinks& out,
+                                            const AdjArgs& AA, int nthreads, int tid) {
+  constexpr bool ADJ = MODE == MODE_ADJOINT;
+  const uint64_t lt = lanemask_lt();
+  Pk cur;
+  cur.lin = 0u;
+  Adj ca = {0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+  bool has = false;
+  uint64_t hid = 0;
+  int nst = 0;
+  uint64_t next = begin;
+  while (true) {
+    if (!has && nst > 0) {
+      --nst;
+      pop<ADJ>(st, nst, nthreads, tid, cur, ca);
+      has = true;
+    }
+    const bool need = !has;
+    const uint64_t m = __ballot(need);
+    if (need) {
+      const uint64_t h = next + (uint64_t)__popcll(m & lt);
+      if (h < end) {
+        hid = first + h;
+        cur = source(beam, hid, seed);
+        ca = Adj{0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+        has = cur.w > 0.0f;
+      }
+    }
+    next += (uint64_t)__popcll(m);
+    if (__ballot(has) == 0ull) break;
+    if (has) {
+      Pk nxt;
+      nxt.lin = 0u;
+      Adj na = ca;
+      bool has_nxt = false;
+      fly<ADJ>(PL, tab, AA, cur, ca, hid, seed, nxt, na, has_nxt, st, nst, nthreads, tid);
+      const Hit hh = PL.det.type == DET_SPHERE ? detect_sphere(PL.det, cur)
+                                               : detect_tubes(PL.det, tab, cur, hid, seed);
+      if (hh.bin >= 0) {
+        if (ADJ) {
+          const double gv = AA.dLdI[hh.bin] * (double)hh.value;
+          if (gv != 0.0) {
+            double* acc = out.acc;
+            atomicAdd(&acc[AA.nb + 0], gv * (double)ca.dabs);
+            atomicAdd(&acc[AA.nb + 1], gv * (double)ca.dsig);
+            atomicAdd(&acc[AA.nb + 2], gv * (double)ca.A);
+            atomicAdd(&acc[AA.nb + 3], gv * (double)ca.nph);
+            for (uint32_t e = 0; e < ca.nph && e < (uint32_t)kAdjMaxOrders; ++e) {
+              const uint32_t w = e < 2u ? ca.b01 : ca.b23;
+              atomicAdd(&acc[(w >> (16u * (e & 1u))) & 0xFFFFu], gv);
+            }
+          }
+        } else {
+          if (out.hist) unsafeAtomicAdd(out.hist + hh.bin, (double)hh.value);
+          if (out.hist_w2)
+            unsafeAtomicAdd(out.hist_w2 + hh.bin, (double)hh.value * (double)hh.value);
+        }
+      }
+      if (MODE == MODE_TRACE) {
+        const unsigned long long slot = atomicAdd(out.n_out, 1ull);
+        if (slot < out.cap) {
+          DevRecord r;
+          r.id = hid;
+          r.lineage = cur.lin;
+          r.order = order_of(cur.lin);
+          r.pos[0] = cur.px;
+          r.pos[1] = cur.py;
+          r.pos[2] = cur.pz;
+          r.vel[0] = cur.dx * cur.sp;
+          r.vel[1] = cur.dy * cur.sp;
+          r.vel[2] = cur.dz * cur.sp;
+          r.t = cur.t;
+          r.w = cur.w;
+          r.bin = hh.bin;
+          r.value = hh.value;
+          r.tof = hh.tof;
+          r.tube = hh.tube;
+          r.pixel = hh.pixel;
+          out.rec[slot] = r;
+        }
+      }
+      if (has_nxt) {
+        cur = nxt;
+        if (ADJ) ca = na;
+      } else {
+        has = false;
+      }
+    }
+  }
+}
+
+// copies a plan and its tables into LDS (whole workgroup)
+__device__ __forceinline__ void stage_plan(DevPlan& PL, float* dyn, const DevPlan* gplan,
+                                           const float* gtab, int nthreads, int tid) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(gplan);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&PL);
+  for (int i = tid; i < (int)(sizeof(DevPlan) / 4); i += nthreads) dst[i] = src[i];
+  const int nt = gplan->n_tables;
+  for (int i = tid; i < nt; i += nthreads) dyn[i] = gtab[i];
+}
+
 // MODE_RUN: histogram only.  MODE_TRACE: also one record per packet leaving
 // the sample.  MODE_ADJOINT: re-traces the same histories (same random
 // numbers) and accumulates dL/dtheta = sum over recorded packets of
 // dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
 // per workgroup.
 template <int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) transport(const DevPlan* __restrict__ gplan,
-                                                 const float* __restrict__ gtab, DevBeam beam,
-                                                 uint64_t seed, uint64_t first, uint64_t n,
-                                                 uint64_t per_wave, double* __restrict__ hist,
-                                                 double* __restrict__ hist_w2,
-                                                 DevRecord* __restrict__ rec, uint64_t cap,
-                                                 unsigned long long* __restrict__ n_out,
-                                                 AdjArgs AA) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
+          uint64_t seed, uint64_t first, uint64_t n, uint64_t per_wave, Sinks out, AdjArgs AA) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
   __shared__ DevPlan PL;
   extern __shared__ float dyn[];
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
-  {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(gplan);
-    uint32_t* dst = reinterpret_cast<uint32_t*>(&PL);
-    for (int i = tid; i < (int)(sizeof(DevPlan) / 4); i += nthreads) dst[i] = src[i];
-    const int nt = gplan->n_tables;
-    for (int i = tid; i < nt; i += nthreads) dyn[i] = gtab[i];
-  }
+  stage_plan(PL, dyn, gplan, gtab, nthreads, tid);
   const int tab_words = (gplan->n_tables + 3) & ~3;
   // adjoint partials: [nb] per DOS bin (sum of g), then sigma_abs, sigma, A, n_phonon
   double* acc = reinterpret_cast<double*>(dyn + tab_words);
@@ -880,98 +986,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
   if (ADJ)
     for (int i = tid; i < AA.nb + 4; i += nthreads) acc[i] = 0.0;
   __syncthreads();
-  const float* tab = dyn;
+  out.acc = acc;
   float* st = dyn + tab_words + acc_words;
-
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
-  if (begin < n) {  // uniform per wave
-    const uint64_t end = begin + per_wave < n ? begin + per_wave : n;
-    const uint64_t lt = lanemask_lt();
-    Pk cur;
-    cur.lin = 0u;
-    Adj ca = {0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
-    bool has = false;
-    uint64_t hid = 0;
-    int nst = 0;
-    uint64_t next = begin;
-    while (true) {
-      if (!has && nst > 0) {
-        --nst;
-        pop<ADJ>(st, nst, nthreads, tid, cur, ca);
-        has = true;
-      }
-      const bool need = !has;
-      const uint64_t m = __ballot(need);
-      if (need) {
-        const uint64_t h = next + (uint64_t)__popcll(m & lt);
-        if (h < end) {
-          hid = first + h;
-          cur = source(beam, hid, seed);
-          ca = Adj{0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
-          has = cur.w > 0.0f;
-        }
-      }
-      next += (uint64_t)__popcll(m);
-      if (__ballot(has) == 0ull) break;
-      if (has) {
-        Pk nxt;
-        nxt.lin = 0u;
-        Adj na = ca;
-        bool has_nxt = false;
-        fly<ADJ>(PL, tab, AA, cur, ca, hid, seed, nxt, na, has_nxt, st, nst, nthreads, tid);
-        const Hit hh = PL.det.type == DET_SPHERE ? detect_sphere(PL.det, cur)
-                                                 : detect_tubes(PL.det, tab, cur, hid, seed);
-        if (hh.bin >= 0) {
-          if (ADJ) {
-            const double gv = AA.dLdI[hh.bin] * (double)hh.value;
-            if (gv != 0.0) {
-              atomicAdd(&acc[AA.nb + 0], gv * (double)ca.dabs);
-              atomicAdd(&acc[AA.nb + 1], gv * (double)ca.dsig);
-              atomicAdd(&acc[AA.nb + 2], gv * (double)ca.A);
-              atomicAdd(&acc[AA.nb + 3], gv * (double)ca.nph);
-              for (uint32_t e = 0; e < ca.nph && e < (uint32_t)kAdjMaxOrders; ++e) {
-                const uint32_t w = e < 2u ? ca.b01 : ca.b23;
-                atomicAdd(&acc[(w >> (16u * (e & 1u))) & 0xFFFFu], gv);
-              }
-            }
-          } else {
-            if (hist) unsafeAtomicAdd(hist + hh.bin, (double)hh.value);
-            if (hist_w2) unsafeAtomicAdd(hist_w2 + hh.bin, (double)hh.value * (double)hh.value);
-          }
-        }
-        if (MODE == MODE_TRACE) {
-          const unsigned long long slot = atomicAdd(n_out, 1ull);
-          if (slot < cap) {
-            DevRecord r;
-            r.id = hid;
-            r.lineage = cur.lin;
-            r.order = order_of(cur.lin);
-            r.pos[0] = cur.px;
-            r.pos[1] = cur.py;
-            r.pos[2] = cur.pz;
-            r.vel[0] = cur.dx * cur.sp;
-            r.vel[1] = cur.dy * cur.sp;
-            r.vel[2] = cur.dz * cur.sp;
-            r.t = cur.t;
-            r.w = cur.w;
-            r.bin = hh.bin;
-            r.value = hh.value;
-            r.tof = hh.tof;
-            r.tube = hh.tube;
-            r.pixel = hh.pixel;
-            rec[slot] = r;
-          }
-        }
-        if (has_nxt) {
-          cur = nxt;
-          if (ADJ) ca = na;
-        } else {
-          has = false;
-        }
-      }
-    }
-  }
+  if (begin < n)  // uniform per wave
+    trace_range<MODE>(PL, dyn, st, beam, seed, first, begin,
+                      begin + per_wave < n ? begin + per_wave : n, out, AA, nthreads, tid);
   if (ADJ) {
     __syncthreads();
     for (int i = tid; i < AA.nb; i += nthreads)
@@ -981,6 +1002,64 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) t
       unsafeAtomicAdd(&AA.grad[AA.nb + 1], acc[AA.nb + 1]);
       unsafeAtomicAdd(&AA.sums[0], acc[AA.nb + 2]);
       unsafeAtomicAdd(&AA.sums[1], acc[AA.nb + 3]);
+    }
+  }
+}
+
+// Persistent batched transport: workgroups pop chunks (simulation, id
+// range) from a global cursor until the list is exhausted (every workgroup
+// reads the same popped index after a barrier, so all leave together).  A
+// workgroup re-stages plan and tables in LDS only when the simulation
+// changes; its waves split the chunk's ids.  The list is sorted by
+// estimated cost, longest first.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restrict__ chunks,
+                 uint32_t n_chunks, uint32_t* __restrict__ cursor) {
+  __shared__ DevPlan PL;
+  __shared__ uint32_t s_chunk;
+  extern __shared__ float dyn[];
+  const int tid = threadIdx.x;
+  const int nthreads = blockDim.x;
+  const int nwaves = nthreads >> 6;
+  const int wid = tid >> 6;
+  int staged = -1;
+  AdjArgs AA = {};
+  for (;;) {
+    if (tid == 0) s_chunk = atomicAdd(cursor, 1u);
+    __syncthreads();
+    const uint32_t c = s_chunk;
+    if (c >= n_chunks) break;
+    const BatchChunk ch = chunks[c];
+    const BatchItem& it = items[ch.item];
+    if ((int)ch.item != staged) {
+      stage_plan(PL, dyn, it.plan, it.tables, nthreads, tid);
+      staged = (int)ch.item;
+    }
+    __syncthreads();
+    const int tab_words = (PL.n_tables + 3) & ~3;
+    float* st = dyn + tab_words;
+    const uint64_t per = (ch.count + nwaves - 1) / nwaves;
+    const uint64_t b = ch.first + per * wid;
+    const uint64_t e = ch.first + ch.count;
+    Sinks out = {it.hist, nullptr, nullptr, 0, nullptr, nullptr};
+    if (b < e) trace_range<MODE_RUN>(PL, dyn, st, it.beam, it.seed, it.id0, b,
+                                     b + per < e ? b + per : e, out, AA, nthreads, tid);
+    __syncthreads();
+  }
+}
+
+// zeroes a list of FP64 arrays and the chunk cursor (graph-capturable; no
+// memset nodes)
+__global__ void batch_reset(double* const* __restrict__ ptrs, const uint64_t* __restrict__ sizes,
+                            int n, uint32_t* __restrict__ cursor) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cursor = 0u;
+  for (int k = 0; k < n; ++k) {
+    double* p = ptrs[k];
+    const uint64_t m = sizes[k];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 2;
+    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; i < m; i += stride) {
+      if (i + 1 < m) *reinterpret_cast<double2*>(p + i) = make_double2(0.0, 0.0);
+      else p[i] = 0.0;
     }
   }
 }
@@ -1053,21 +1132,39 @@ hipError_t launch_transport(const DevPlan* plan, const float* tables, int n_tabl
   AdjArgs AA = {};
   AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = -1;
   if (adj) AA = *adj;
+  dev::Sinks out = {hist, hist_w2, rec, cap, n_out, nullptr};
   const size_t lds = transport_lds_bytes(n_tables, stack_cap, block, adj ? adj->nb : 0);
   if (adj) {
     hipLaunchKernelGGL(dev::zero2, dim3(1), dim3(64), 0, stream, AA.sums);
     hipLaunchKernelGGL(dev::transport<dev::MODE_ADJOINT>, dim3(grid), dim3(block), lds, stream,
-                       plan, tables, beam, seed, first, n, per_wave, hist, hist_w2, rec, cap,
-                       n_out, AA);
+                       plan, tables, beam, seed, first, n, per_wave, out, AA);
   } else if (rec) {
     hipLaunchKernelGGL(dev::transport<dev::MODE_TRACE>, dim3(grid), dim3(block), lds, stream,
-                       plan, tables, beam, seed, first, n, per_wave, hist, hist_w2, rec, cap,
-                       n_out, AA);
+                       plan, tables, beam, seed, first, n, per_wave, out, AA);
   } else {
     hipLaunchKernelGGL(dev::transport<dev::MODE_RUN>, dim3(grid), dim3(block), lds, stream, plan,
-                       tables, beam, seed, first, n, per_wave, hist, hist_w2, rec, cap, n_out, AA);
+                       tables, beam, seed, first, n, per_wave, out, AA);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32_t n_chunks,
+                        uint32_t* cursor, double* const* zero_ptrs, const uint64_t* zero_sizes,
+                        int n_zero, int grid, int block, size_t lds, int reset_grid,
+                        hipStream_t stream) {
+  hipLaunchKernelGGL(dev::batch_reset, dim3(reset_grid), dim3(256), 0, stream, zero_ptrs,
+                     zero_sizes, n_zero, cursor);
+  hipLaunchKernelGGL(dev::batch_persistent, dim3(grid), dim3(block), lds, stream, items, chunks,
+                     n_chunks, cursor);
+  return hipGetLastError();
+}
+
+int batch_occupancy(int block, size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dev::batch_persistent, block, lds) !=
+      hipSuccess)
+    return 0;
+  return nb;
 }
 
 hipError_t launch_adjoint_finalize(double* grad, const double* sums, const double* dense_a,
@@ -1086,9 +1183,10 @@ hipError_t launch_loss_grad(const double* I, const double* T, const double* w, i
 size_t transport_static_lds() { return sizeof(DevPlan); }
 
 hipError_t set_transport_lds_limit(size_t bytes) {
-  const void* fns[3] = {reinterpret_cast<const void*>(&dev::transport<dev::MODE_RUN>),
+  const void* fns[4] = {reinterpret_cast<const void*>(&dev::transport<dev::MODE_RUN>),
                         reinterpret_cast<const void*>(&dev::transport<dev::MODE_TRACE>),
-                        reinterpret_cast<const void*>(&dev::transport<dev::MODE_ADJOINT>)};
+                        reinterpret_cast<const void*>(&dev::transport<dev::MODE_ADJOINT>),
+                        reinterpret_cast<const void*>(&dev::batch_persistent)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;

@@ -93,7 +93,8 @@ EXPORTS = ["mcv_assembly_create", "mcv_assembly_add", "mcv_assembly_destroy",
            "mcv_detector_sphere", "mcv_detector_tubes", "mcv_detector_nbins",
            "mcv_detector_destroy", "mcv_plan_create", "mcv_plan_destroy", "mcv_plan_nbins",
            "mcv_run", "mcv_trace", "mcv_sync", "mcv_last_error", "mcv_abi_version",
-           "mcv_adjoint_nparams", "mcv_adjoint", "mcv_loss_grad"]
+           "mcv_adjoint_nparams", "mcv_adjoint", "mcv_loss_grad", "mcv_batch_create",
+           "mcv_batch_run", "mcv_batch_destroy", "mcv_autotune"]
 
 _lib = None
 
@@ -355,3 +356,99 @@ def loss_grad(I, T, w, dLdI, loss, stream=None):
     check(lib().mcv_loss_grad(C.c_void_p(I.data_ptr()), C.c_void_p(T.data_ptr()),
                               C.c_void_p(w.data_ptr()), n, C.c_void_p(dLdI.data_ptr()),
                               C.c_void_p(loss.data_ptr()), _stream_ptr(stream)))
+
+
+class mcv_batch_item(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("beam", mcv_beam), ("seed", C.c_uint64),
+                ("first", C.c_uint64), ("n", C.c_uint64), ("hist", C.c_void_p)]
+
+
+class mcv_tuning(C.Structure):
+    _fields_ = [("block_size", C.c_int32), ("chunk", C.c_int32), ("wgs_per_cu", C.c_int32),
+                ("zero_hists", C.c_int32)]
+
+
+def _batch_sigs():
+    L = lib()
+    if getattr(L, "_batch_ready", False):
+        return L
+    L.mcv_batch_create.argtypes = [PP, C.POINTER(mcv_batch_item), C.c_int32,
+                                   C.POINTER(mcv_tuning), C.c_int32]
+    L.mcv_batch_run.argtypes = [P, P]
+    L.mcv_batch_destroy.argtypes = [P]
+    L.mcv_autotune.argtypes = [C.POINTER(mcv_batch_item), C.c_int32, C.c_int32, C.c_int32,
+                               C.POINTER(mcv_tuning), C.POINTER(C.c_double)]
+    for f in (L.mcv_batch_create, L.mcv_batch_run, L.mcv_batch_destroy, L.mcv_autotune):
+        f.restype = C.c_int
+    L._batch_ready = True
+    return L
+
+
+class Batch:
+    """Many simulations in one persistent, graph-captured launch.
+
+    plans: list of Plan; hists: list of float64 device tensors (one per plan).
+    """
+
+    def __init__(self, plans, hists, tuning=None, device=0):
+        L = _batch_sigs()
+        self.plans, self.hists = plans, hists
+        self.items = (mcv_batch_item * len(plans))()
+        for i, (p, h) in enumerate(zip(plans, hists)):
+            p._check_hist(h)
+            self.items[i] = mcv_batch_item(p.h, p.beam, p.cfg["seed"], 0, p.cfg["N"],
+                                           h.data_ptr())
+        t = tuning or mcv_tuning(0, 0, 0, 1)
+        self.tuning = t
+        self.h = C.c_void_p()
+        check(L.mcv_batch_create(C.byref(self.h), self.items, len(plans), C.byref(t), device))
+
+    def run(self, stream=None):
+        check(_batch_sigs().mcv_batch_run(self.h, _stream_ptr(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _batch_sigs().mcv_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    __del__ = close
+
+
+def autotune(plans, hists, device=0, reps=3, cache=None):
+    """Fastest (block size, chunk) for this batch, from a JSON cache keyed by
+    (gfx arch, CU count, workload hash) or by timing every candidate."""
+    import hashlib
+    import json
+    import torch
+    props = torch.cuda.get_device_properties(device)
+    arch = getattr(props, "gcnArchName", "unknown")
+    desc = json.dumps([[p.cfg.get("name"), p.cfg["N"], p.cfg["K"], p.cfg["beam"]["E"],
+                        p.cfg["scatterers"][0]["shape"]["type"], p.cfg["detector"]["type"]]
+                       for p in plans], sort_keys=True)
+    key = f"{arch}|{props.multi_processor_count}|{hashlib.sha1(desc.encode()).hexdigest()[:16]}"
+    path = cache or os.path.join(os.path.expanduser("~"), ".cache", "mcv", "autotune.json")
+    table = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                table = json.load(f)
+        except (OSError, ValueError):
+            table = {}
+    if key in table:
+        t = table[key]
+        return mcv_tuning(t["block_size"], t["chunk"], 0, 1), t["ms"], True
+    L = _batch_sigs()
+    items = (mcv_batch_item * len(plans))()
+    for i, (p, h) in enumerate(zip(plans, hists)):
+        items[i] = mcv_batch_item(p.h, p.beam, p.cfg["seed"], 0, p.cfg["N"], h.data_ptr())
+    best = mcv_tuning()
+    ms = C.c_double(0.0)
+    check(L.mcv_autotune(items, len(plans), device, reps, C.byref(best), C.byref(ms)))
+    table[key] = {"block_size": best.block_size, "chunk": best.chunk, "ms": ms.value}
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(table, f, indent=1)
+    except OSError:
+        pass
+    return best, ms.value, False

@@ -245,3 +245,37 @@ def detector_nbins(det):
     if det["type"] == "sphere":
         return det["n2t"] * det["ntof"]
     return det["nrows"] * det["ncols"] * det["npix"] * det["ntof"]
+
+
+def batch_configs(n_sims=64, seed=4, n_scale=1.0):
+    """Many uneven simulations: Ei log-uniform in [10, 500] meV, histories
+    log-uniform in [1e5, 1e7] (times n_scale), sample shape from {plate,
+    cylinder, annulus}, kernel set from {plate-iso, powder, spin-wave slab};
+    the detector follows the kernel set (sphere 180x100, 1000 tubes x 128 x
+    1000, 2000 tubes x 128 x 500).  Simulation s uses transport seed s."""
+    rng = np.random.default_rng(seed)
+    base_powder = powder_config(N=1)["scatterers"][0]["kernels"]
+    base_spin = crystal_config(N=1)["scatterers"][0]["kernels"]
+    out = []
+    for s in range(n_sims):
+        E = float(np.exp(rng.uniform(math.log(10.0), math.log(500.0))))
+        N = int(np.exp(rng.uniform(math.log(1e5), math.log(1e7))) * n_scale)
+        shape_kind = int(rng.integers(0, 3))
+        kset = int(rng.integers(0, 3))
+        shape = [box(0.05, 0.05, 0.002), cylinder(0.01, 0.05), annulus(0.010, 0.011, 0.05)][shape_kind]
+        if kset == 0:
+            kernels, K = [iso_el(5.0)], 1
+            lo, hi = _tof_window(E, 3.0, 0.5, 2.0)
+            det = sphere_detector(3.0, 180, 100, lo, hi)
+        elif kset == 1:
+            kernels, K = copy.deepcopy(base_powder), 3
+            lo, hi = _tof_window(E, 3.0, 0.7, 2.0)
+            det = tube_detector(4, 250, 128, 1000, lo, hi)
+        else:
+            kernels, K = copy.deepcopy(base_spin), 3
+            lo, hi = _tof_window(E, 3.0, 0.8, 2.0)
+            det = tube_detector(4, 500, 128, 500, lo, hi, radius=0.00635)
+        out.append({"name": f"batch-{s}", "beam": beam(E),
+                    "scatterers": [scatterer(shape, 0.08, 2.0, kernels)],
+                    "detector": det, "K": K, "min_prob": 0.0, "N": max(1, N), "seed": s})
+    return out

@@ -1,0 +1,73 @@
+"""Persistent batched kernel and its graph: each simulation's histogram equals
+its plain launch; replays are idempotent; the autotuner picks a tuning."""
+
+import numpy as np
+import pytest
+
+from paper_1504_02776_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _small_batch(n_sims=10):
+    return W.batch_configs(n_sims=n_sims, n_scale=0.01)
+
+
+def test_batch_equals_plain_launches(torch_cuda):
+    from paper_1504_02776_amd import mcv
+    torch = torch_cuda
+    cfgs = _small_batch()
+    plans = [mcv.Plan(c) for c in cfgs]
+    hb = [p.zeros() for p in plans]
+    print(f"[batch] {len(cfgs)} sims, {sum(c['N'] for c in cfgs)} histories", flush=True)
+    for tuning in [mcv.mcv_tuning(256, 1024, 0, 1), mcv.mcv_tuning(128, 333, 0, 1)]:
+        b = mcv.Batch(plans, hb, tuning)
+        b.run()
+        b.run()  # replay: histograms are zeroed inside the graph
+        torch.cuda.synchronize()
+        for p, h, c in zip(plans, hb, cfgs):
+            ref = p.zeros()
+            p.run(ref)
+            torch.cuda.synchronize()
+            a, r = h.cpu().numpy(), ref.cpu().numpy()
+            assert r.sum() > 0, c["name"]
+            assert np.allclose(a, r, rtol=1e-9, atol=1e-14), c["name"]
+        b.close()
+
+
+def test_batch_accumulates_without_zeroing(torch_cuda):
+    from paper_1504_02776_amd import mcv
+    torch = torch_cuda
+    cfgs = _small_batch(3)
+    plans = [mcv.Plan(c) for c in cfgs]
+    hb = [p.zeros() for p in plans]
+    b = mcv.Batch(plans, hb, mcv.mcv_tuning(256, 4096, 0, 0))
+    b.run()
+    b.run()
+    torch.cuda.synchronize()
+    for p, h in zip(plans, hb):
+        ref = p.zeros()
+        p.run(ref)
+        torch.cuda.synchronize()
+        assert np.allclose(h.cpu().numpy(), 2 * ref.cpu().numpy(), rtol=1e-9, atol=1e-14)
+
+
+def test_autotune_returns_and_caches(torch_cuda, tmp_path):
+    from paper_1504_02776_amd import mcv
+    cfgs = _small_batch(4)
+    plans = [mcv.Plan(c) for c in cfgs]
+    hb = [p.zeros() for p in plans]
+    cache = str(tmp_path / "tune.json")
+    t, ms, cached = mcv.autotune(plans, hb, reps=1, cache=cache)
+    assert t.block_size in (128, 256) and t.chunk in (1024, 4096, 16384, 65536)
+    assert ms > 0 and not cached
+    t2, ms2, cached2 = mcv.autotune(plans, hb, reps=1, cache=cache)
+    assert cached2 and (t2.block_size, t2.chunk) == (t.block_size, t.chunk)
