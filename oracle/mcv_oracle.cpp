@@ -72,6 +72,10 @@ const double kTauCos = 2e-6;     // in cos(2theta), sphere rings
 const double kTauTof = 4e-6;     // relative time of flight
 const double kTauImpact = 4e-4;  // relative impact parameter in a tube
 const double kTauU = 2e-6;       // absolute, for u < p tests on computed p
+// Conditioning of a single-precision implementation (reported, not used by
+// the method): a position of ~1 cm is known to ~2e-9 m in binary32, which
+// makes a chord L uncertain by 2e-9 m / |cos| at each surface it crosses.
+const double kEpsPos = 2e-9;
 
 inline double k_from_speed(double v) { return v * std::sqrt(kEperV2 / kHbar2over2mn); }
 inline double speed_from_k(double k) { return k * std::sqrt(kHbar2over2mn / kEperV2); }
@@ -173,6 +177,8 @@ struct ORecord {
   double value_sens;            // |d value / d lateral ray offset| (tubes)
   uint32_t kinds;               // bit t set: a kernel of type t scattered an ancestor
   int32_t pad;
+  double cond;                  // amplification of relative state errors (E_i/E_f chain)
+  double wsens;                 // relative weight error from position rounding (see kEpsPos)
 };
 
 // Parameters of a gradient: the raw DOS values of kernel dos_k of scatterer
@@ -287,6 +293,8 @@ struct Packet {
   int order;
   double margin_anc;  // min normalised margin of the decisions that made it
   uint32_t kinds;     // kernel types met in its ancestry (bit = type)
+  double cond;        // see ORecord
+  double wsens;       // see ORecord
   std::vector<double> dlogw;  // d log(w) / d(parameters), when gradients are on
 };
 
@@ -397,6 +405,34 @@ int shape_intervals(const OShape& sh, V3 pl, V3 dl, double lo[2], double hi[2],
     ++n;
   }
   return n;
+}
+
+// |cos| of the angle between the ray and the normal of the shape surface
+// nearest to the local point q (used only for the conditioning estimate)
+double surface_cos(const OShape& sh, V3 q, V3 d) {
+  if (sh.type == SHAPE_BOX) {
+    double best = kHuge, c = 1.0;
+    double qa[3] = {q.x, q.y, q.z}, da[3] = {d.x, d.y, d.z};
+    for (int a = 0; a < 3; ++a) {
+      double dist = std::fabs(std::fabs(qa[a]) - 0.5 * sh.dims[a]);
+      if (dist < best) {
+        best = dist;
+        c = std::fabs(da[a]);
+      }
+    }
+    return c;
+  }
+  double rho = std::sqrt(q.x * q.x + q.z * q.z);
+  double h = sh.type == SHAPE_CYLINDER ? sh.dims[1] : sh.dims[2];
+  double r_out = sh.type == SHAPE_CYLINDER ? sh.dims[0] : sh.dims[1];
+  double best = std::fabs(std::fabs(q.y) - 0.5 * h), c = std::fabs(d.y);
+  double rc = rho > 0.0 ? std::fabs(q.x * d.x + q.z * d.z) / rho : 1.0;
+  if (std::fabs(rho - r_out) < best) {
+    best = std::fabs(rho - r_out);
+    c = rc;
+  }
+  if (sh.type == SHAPE_ANNULUS && std::fabs(rho - sh.dims[0]) < best) c = rc;
+  return c;
 }
 
 // ------------------------------------------------------------- materials
@@ -697,6 +733,14 @@ Scatter k_sqe(const OKernel& k, const Packet& P, const double* u, double* margin
 }
 
 // ------------------------------------------------------------- simulation
+// distance (in bins) of a fractional tof bin index to the boundary that
+// decides it: a bin edge inside the window, the window edge outside it
+double tof_margin(double ft, int ntof) {
+  if (ft < 0.0) return -ft;
+  if (ft >= ntof) return ft - ntof;
+  return std::fabs(ft - std::nearbyint(ft));
+}
+
 struct Sim {
   // S: the parameters the weights are evaluated at; Sp: the parameters the
   // random choices are drawn from (the same setup except for a gradient or a
@@ -778,7 +822,7 @@ struct Sim {
     double dt = (D.tof_hi - D.tof_lo) / D.ntof;
     double ft = (tof - D.tof_lo) / dt;
     int it = (int)std::floor(ft);
-    *margin = std::min(*margin, std::fabs(ft - std::nearbyint(ft)) * dt / (kTauTof * std::fabs(tof)));
+    *margin = std::min(*margin, tof_margin(ft, D.ntof) * dt / (kTauTof * std::fabs(tof)));
     if (ft < 0.0 || it >= D.ntof) {
       tally->n_out_of_window++;
       return;
@@ -855,7 +899,7 @@ struct Sim {
     double dt = (D.tof_hi - D.tof_lo) / D.ntof;
     double ft = (tof - D.tof_lo) / dt;
     int it = (int)std::floor(ft);
-    *margin = std::min(*margin, std::fabs(ft - std::nearbyint(ft)) * dt / (kTauTof * std::fabs(tof)));
+    *margin = std::min(*margin, tof_margin(ft, D.ntof) * dt / (kTauTof * std::fabs(tof)));
     // sensitivity of the recorded value to a sideways shift of the ray
     double rr = D.radius * D.radius - best_b * best_b;
     if (rr > 0.0)
@@ -883,6 +927,8 @@ struct Sim {
     rec.pixel = -1;
     rec.margin_anc = P.margin_anc;
     rec.kinds = P.kinds;
+    rec.cond = P.cond;
+    rec.wsens = P.wsens;
     double margin = kHuge;
     tally->n_detect++;
     if (S.det.type == DET_SPHERE) detect_sphere(P, rec, &margin);
@@ -943,6 +989,21 @@ struct Sim {
       Mu mup = attenuation(scp, sip, P.speed, &m_mu);
       *own_margin = std::min(*own_margin, m_mu);
       tally->n_segments++;
+      // chord uncertainty of a binary32 implementation (conditioning only)
+      double dL;
+      {
+        const OShape& sh = sc.shape;
+        V3 dl = matTvec(sh.rot, P.dir);
+        V3 q_out = matTvec(sh.rot, sub(add(start, scale(P.dir, iv.s_out)),
+                                       {sh.pos[0], sh.pos[1], sh.pos[2]}));
+        double inv = 1.0 / std::max(surface_cos(sh, q_out, dl), 1e-9);
+        if (iv.s_in > 0.0) {
+          V3 q_in = matTvec(sh.rot, sub(add(start, scale(P.dir, iv.s_in)),
+                                        {sh.pos[0], sh.pos[1], sh.pos[2]}));
+          inv += 1.0 / std::max(surface_cos(sh, q_in, dl), 1e-9);
+        }
+        dL = kEpsPos * inv;
+      }
       double att = std::exp(-mu.total * L);
       double a = -std::expm1(-mup.total * L);  // probability to interact
       tally->n_transcend += 2;
@@ -1017,12 +1078,20 @@ struct Sim {
         C.order = P.order + 1;
         C.margin_anc = std::min(P.margin_anc, child_margin);
         C.kinds = P.kinds | (1u << k.type);
+        // d log(1 - e^{-mu L}) / dL times the chord uncertainty
+        C.wsens = P.wsens + mup.total * std::exp(-mup.total * L) / a * dL;
+        {
+          double Ein = kEperV2 * P.speed * P.speed;
+          double Eout = kEperV2 * C.speed * C.speed;
+          C.cond = P.cond * (Eout > 0.0 ? std::max(1.0, Ein / Eout) : 1.0);
+        }
         if (C.w > 0.0) children.push_back(C);
         else tally->n_zero_weight++;
       } else {
         tally->w_lost[P.order] += P.w * a;
       }
       P.w *= att;
+      P.wsens += mu.total * dL;
       if (tangent) add_dmu(P.dlogw, iv.scat, P.speed, -L);
     }
     if (!segs.empty()) {
@@ -1069,6 +1138,8 @@ struct Sim {
     P.order = 0;
     P.margin_anc = kHuge;
     P.kinds = 0u;
+    P.cond = 1.0;
+    P.wsens = 0.0;
     if (tangent) P.dlogw.assign(np, 0.0);
   }
 };

@@ -553,7 +553,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   int cus = 0;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   p->cus = cus > 0 ? cus : 256;
-  if ((e = set_transport_lds_limit(160 * 1024 - transport_static_lds())) != hipSuccess) {
+  if ((e = set_transport_lds_limit(160 * 1024)) != hipSuccess) {
     (void)hipSetDevice(cur);
     delete p;
     return hipfail(e, "hipFuncSetAttribute");
@@ -937,11 +937,11 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   std::vector<BatchChunk> cl;
   for (auto& c : hchunks) cl.push_back(c.second);
   size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, 0);
-  while (lds + transport_static_lds() > 160 * 1024 && block > 64) {
+  while (lds + transport_static_lds() + 64 > 160 * 1024 && block > 64) {
     block -= 64;
     lds = transport_lds_bytes(n_tables_max, stack_max, block, 0);
   }
-  if (lds + transport_static_lds() > 160 * 1024)
+  if (lds + transport_static_lds() + 64 > 160 * 1024)
     return fail(MCV_EUNSUPPORTED, "batch tables and stacks exceed LDS");
 
   auto* b = new (std::nothrow) mcv_batch_s();

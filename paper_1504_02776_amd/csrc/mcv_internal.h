@@ -85,7 +85,10 @@ struct DevDet {
   int32_t t_cols;    // offset of (x_c, z_c) per column
 };
 
-struct DevPlan {
+// 16-byte aligned and sized: the kernels place their dynamic LDS (which holds
+// binary64 partial sums in adjoint mode) right after a copy of the plan, and
+// binary64 LDS accesses must be 8-byte aligned.
+struct alignas(16) DevPlan {
   int32_t nscat;
   int32_t K;
   int32_t smax;       // largest number of material intervals on one ray
@@ -95,6 +98,7 @@ struct DevPlan {
   DevScat s[kMaxScat];
   DevDet det;
 };
+static_assert(sizeof(DevPlan) % 16 == 0, "plan copy must keep the dynamic LDS 16-byte aligned");
 
 // Parameters of an adjoint run (raw DOS bins of one phonon kernel, sigma_abs
 // of one scatterer, nominal sigma of one kernel) and where it accumulates.

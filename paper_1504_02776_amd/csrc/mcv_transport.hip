@@ -847,13 +847,15 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 enum { MODE_RUN = 0, MODE_TRACE = 1, MODE_ADJOINT = 2 };
 
+// where recorded values go (global memory only: the backend takes pointers
+// that arrive in kernel arguments to be global, so LDS addresses never
+// travel in this struct)
 struct Sinks {
   double* hist;
   double* hist_w2;
   DevRecord* rec;
   uint64_t cap;
   unsigned long long* n_out;
-  double* acc;  // adjoint LDS partials
 };
 
 // One wave traces histories first+begin .. first+end-1: every lane walks
@@ -864,7 +866,8 @@ template <int MODE>
 __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab, float* st,
                                             const DevBeam& beam, uint64_t seed, uint64_t first,
                                             uint64_t begin, uint64_t end, const Sinks& out,
-                                            const AdjArgs& AA, int nthreads, int tid) {
+                                            const AdjArgs& AA, double* acc, int nthreads,
+                                            int tid) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
   const uint64_t lt = lanemask_lt();
   Pk cur;
@@ -905,7 +908,6 @@ __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab,
         if (ADJ) {
           const double gv = AA.dLdI[hh.bin] * (double)hh.value;
           if (gv != 0.0) {
-            double* acc = out.acc;
             atomicAdd(&acc[AA.nb + 0], gv * (double)ca.dabs);
             atomicAdd(&acc[AA.nb + 1], gv * (double)ca.dsig);
             atomicAdd(&acc[AA.nb + 2], gv * (double)ca.A);
@@ -975,7 +977,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
           uint64_t seed, uint64_t first, uint64_t n, uint64_t per_wave, Sinks out, AdjArgs AA) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
   __shared__ DevPlan PL;
-  extern __shared__ float dyn[];
+  extern __shared__ __align__(16) float dyn[];
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
   stage_plan(PL, dyn, gplan, gtab, nthreads, tid);
@@ -986,13 +988,12 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   if (ADJ)
     for (int i = tid; i < AA.nb + 4; i += nthreads) acc[i] = 0.0;
   __syncthreads();
-  out.acc = acc;
   float* st = dyn + tab_words + acc_words;
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
   if (begin < n)  // uniform per wave
     trace_range<MODE>(PL, dyn, st, beam, seed, first, begin,
-                      begin + per_wave < n ? begin + per_wave : n, out, AA, nthreads, tid);
+                      begin + per_wave < n ? begin + per_wave : n, out, AA, acc, nthreads, tid);
   if (ADJ) {
     __syncthreads();
     for (int i = tid; i < AA.nb; i += nthreads)
@@ -1017,7 +1018,7 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
                  uint32_t n_chunks, uint32_t* __restrict__ cursor) {
   __shared__ DevPlan PL;
   __shared__ uint32_t s_chunk;
-  extern __shared__ float dyn[];
+  extern __shared__ __align__(16) float dyn[];
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
   const int nwaves = nthreads >> 6;
@@ -1041,9 +1042,9 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const uint64_t per = (ch.count + nwaves - 1) / nwaves;
     const uint64_t b = ch.first + per * wid;
     const uint64_t e = ch.first + ch.count;
-    Sinks out = {it.hist, nullptr, nullptr, 0, nullptr, nullptr};
+    Sinks out = {it.hist, nullptr, nullptr, 0, nullptr};
     if (b < e) trace_range<MODE_RUN>(PL, dyn, st, it.beam, it.seed, it.id0, b,
-                                     b + per < e ? b + per : e, out, AA, nthreads, tid);
+                                     b + per < e ? b + per : e, out, AA, nullptr, nthreads, tid);
     __syncthreads();
   }
 }
@@ -1132,7 +1133,7 @@ hipError_t launch_transport(const DevPlan* plan, const float* tables, int n_tabl
   AdjArgs AA = {};
   AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = -1;
   if (adj) AA = *adj;
-  dev::Sinks out = {hist, hist_w2, rec, cap, n_out, nullptr};
+  dev::Sinks out = {hist, hist_w2, rec, cap, n_out};
   const size_t lds = transport_lds_bytes(n_tables, stack_cap, block, adj ? adj->nb : 0);
   if (adj) {
     hipLaunchKernelGGL(dev::zero2, dim3(1), dim3(64), 0, stream, AA.sums);
@@ -1187,8 +1188,13 @@ hipError_t set_transport_lds_limit(size_t bytes) {
                         reinterpret_cast<const void*>(&dev::transport<dev::MODE_TRACE>),
                         reinterpret_cast<const void*>(&dev::transport<dev::MODE_ADJOINT>),
                         reinterpret_cast<const void*>(&dev::batch_persistent)};
+  // each kernel may use `bytes` of LDS in total, static part included
   for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    hipFuncAttributes at;
+    hipError_t e = hipFuncGetAttributes(&at, f);
+    if (e != hipSuccess) return e;
+    const size_t dyn = bytes > at.sharedSizeBytes ? bytes - at.sharedSizeBytes : 0;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

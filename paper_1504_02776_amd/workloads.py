@@ -224,7 +224,8 @@ def sqe_config(N=20_000, seed=0):
     S = np.exp(-((Ev[None, :] - 20.0 * np.sin(Q[:, None] / 4.0)) / 4.0) ** 2) + \
         0.05 * rng.uniform(size=(nQ, nE))
     E = 60.0
-    lo, hi = _tof_window(E, 3.0, 0.5, 2.5)
+    # window chosen so that the elastic arrival time is not on a bin edge
+    lo, hi = _tof_window(E, 3.0, 0.45, 2.5)
     return {
         "name": "plate-sqe-sphere",
         "beam": beam(E),

@@ -1,20 +1,28 @@
 """Packet-by-packet and histogram comparison of the HIP path with the oracle.
 
-Tolerances (binary32 packet state on the GPU against the binary64 oracle):
-  position   |dx| <= 1e-5 |x| + 1e-7 m       (1e-7 m = 1e-5 of a 1 cm sample)
-  velocity   |dv| <= 1e-5 |v|
-  time       |dt| <= 1e-5 |t| + 3e-11 s       (3e-11 s = 1e-5 of 1 cm / 3 km/s)
-  weight     |dw| <= 1e-5 |w|, 1e-4 |w| below a spin-wave scattering (its
-             weight depends on cos(Q_a a) with Q_a a up to ~40 rad, where one
-             binary32 rounding of Q moves E(Q) by ~1e-5 meV against a 0.5 meV
-             Lorentzian)
-  value      |dv| <= 1e-5 |v| + |d value/d offset| * 1e-6 m (+ the spin-wave
-             allowance): at 3 m a binary32 direction fixes the ray's lateral
-             position only to a few 1e-7 m, and a tube's chord is steep in it
-  tof        |dt| <= 1e-5 |tof|
+Tolerances (binary32 packet state on the GPU against the binary64 oracle),
+scaled per packet by the conditioning the oracle reports for it:
+  cond  = product over its inelastic scatterings of max(1, E_i/E_f): E_f =
+          E_i - e loses digits when a phonon takes most of the energy;
+  wsens = relative weight error that position rounding (~2e-9 m at 1 cm in
+          binary32) causes through the chords it crossed and was born on
+          (2e-9 m / |cos| at each surface, times d log(factor)/dL).
+  position   |dx| <= (1e-5 |x| + 1e-7 m) cond   (1e-7 m = 1e-5 of 1 cm)
+  velocity   |dv| <= 1e-5 |v| cond
+  time       |dt| <= (1e-5 |t| + 3e-11 s) cond  (3e-11 s = 1e-5 of 1 cm / 3 km/s)
+  weight     |dw| <= |w| (r cond + wsens), r = 1e-5, or 1e-4 below a
+             spin-wave scattering (its weight depends on cos(Q_a a) with
+             Q_a a up to ~40 rad, where one binary32 rounding of Q moves E(Q)
+             by ~1e-5 meV against a 0.5 meV Lorentzian)
+  value      as the weight, plus |d value/d offset| * 1e-6 m * cond: at 3 m a
+             binary32 direction fixes the ray's lateral position only to a
+             few 1e-7 m, and a tube's chord is steep in it near grazing
+  tof        |dt| <= 1e-5 |tof| cond
 Discrete results (packet existence, bin) must be equal unless the oracle's
 margin to the decision is below its stated uncertainty (margin < 1): such
-"near-decision" packets may go either way and are only counted.
+"near-decision" packets may go either way and are only counted (<= 5 %).
+Packets whose conditioning is poor (cond > 10 or wsens > 1e-4) must stay
+below 5 % as well.
 """
 
 from __future__ import annotations
@@ -89,15 +97,18 @@ def compare_packets(gpu, orc, max_flag_frac=0.05):
                             f"lin={o['lineage'][i]} order={o['order'][i]} gpu={a[i]!r} "
                             f"oracle={b[i]!r} tol={tolv[i]!r} kinds={o['kinds'][i]}")
 
+    cond = o["cond"]
+    wrel = wtol * cond + o["wsens"]
     for ax in range(3):
         check(f"pos[{ax}]", g["pos"][:, ax].astype(np.float64), o["pos"][:, ax],
-              1e-5 * np.abs(o["pos"][:, ax]) + 1e-7, ok_state)
+              (1e-5 * np.abs(o["pos"][:, ax]) + 1e-7) * cond, ok_state)
     vnorm = np.linalg.norm(o["vel"], axis=1)
     for ax in range(3):
-        check(f"vel[{ax}]", g["vel"][:, ax].astype(np.float64), o["vel"][:, ax], 1e-5 * vnorm,
-              ok_state)
-    check("t", g["t"].astype(np.float64), o["t"], 1e-5 * np.abs(o["t"]) + 3e-11, ok_state)
-    check("w", g["w"].astype(np.float64), o["w"], wtol * np.abs(o["w"]) + 1e-30, ok_state)
+        check(f"vel[{ax}]", g["vel"][:, ax].astype(np.float64), o["vel"][:, ax],
+              1e-5 * vnorm * cond, ok_state)
+    check("t", g["t"].astype(np.float64), o["t"], (1e-5 * np.abs(o["t"]) + 3e-11) * cond,
+          ok_state)
+    check("w", g["w"].astype(np.float64), o["w"], wrel * np.abs(o["w"]) + 1e-30, ok_state)
     # detector
     both = ok_state & (o["bin"] >= 0) | ok_state & (g["bin"] >= 0)
     bad = ok_state & (g["bin"] != o["bin"])
@@ -106,13 +117,17 @@ def compare_packets(gpu, orc, max_flag_frac=0.05):
         failures.append(f"bin: {int(bad.sum())} differ, first id={o['id'][i]} "
                         f"lin={o['lineage'][i]} gpu={g['bin'][i]} oracle={o['bin'][i]} "
                         f"margins={o['margin_anc'][i]},{o['margin_own'][i]}")
-    vt = wtol * np.abs(o["value"]) + o["value_sens"] * DELTA_B + 1e-30
+    vt = wrel * np.abs(o["value"]) + o["value_sens"] * DELTA_B * cond + 1e-30
     same_bin = both & (g["bin"] == o["bin"])
     check("value", g["value"].astype(np.float64), o["value"], vt, same_bin)
     rec = same_bin & (o["bin"] >= 0)
-    check("tof", g["tof"].astype(np.float64), o["tof"], 1e-5 * np.abs(o["tof"]) + 1e-12, rec)
+    check("tof", g["tof"].astype(np.float64), o["tof"], (1e-5 * np.abs(o["tof"]) + 1e-12) * cond,
+          rec)
     nflag = int((~ok_state).sum()) + len(only_o) + len(only_g)
     frac = nflag / max(1, len(orc))
+    poor = float(((orc["cond"] > 10) | (orc["wsens"] > 1e-4)).mean())
+    stats["poorly-conditioned"] = (poor, poor, 0)
+    assert poor <= 0.05, f"too many poorly conditioned packets: {poor}"
     print(f"[parity-stats] n={len(orc)} flagged={nflag} ({frac:.2e}) "
           + " ".join(f"{k}:max={v[0]:.3g},q999={v[1]:.3g},over={v[2]}" for k, v in stats.items()),
           flush=True)
@@ -134,7 +149,8 @@ def compare_hist(hg, ho, gpu, orc):
     n = len(ho)
     margin = np.minimum(orc["margin_anc"], orc["margin_own"])
     spin = (orc["kinds"] & SPINWAVE_BIT) != 0
-    tol_o = np.where(spin, 1e-4, 1e-5) * np.abs(orc["value"]) + orc["value_sens"] * DELTA_B
+    tol_o = (np.where(spin, 1e-4, 1e-5) * orc["cond"] + orc["wsens"]) * np.abs(orc["value"]) + \
+        orc["value_sens"] * DELTA_B * orc["cond"]
     allow = np.zeros(n)
     m = orc["bin"] >= 0
     np.add.at(allow, orc["bin"][m], tol_o[m])
