@@ -174,11 +174,16 @@ struct ORecord {
   int32_t pixel;
   double margin_anc;            // smallest normalised margin of the ancestors
   double margin_own;            // smallest normalised margin of this packet
-  double value_sens;            // |d value / d lateral ray offset| (tubes)
+  double value_sens;            // allowance on value: its change when the ray is shifted
+                                // sideways by its binary32 uncertainty (tubes)
   uint32_t kinds;               // bit t set: a kernel of type t scattered an ancestor
   int32_t pad;
   double cond;                  // amplification of relative state errors (E_i/E_f chain)
   double wsens;                 // relative weight error from position rounding (see kEpsPos)
+  double tof_tol;               // allowance on tof from the same sideways shift
+  double ddir;                  // binary32 uncertainty of the direction (rad)
+  double dpos;                  // binary32 uncertainty of the position (m)
+  double dtime;                 // binary32 uncertainty of the time (s)
 };
 
 // Parameters of a gradient: the raw DOS values of kernel dos_k of scatterer
@@ -295,6 +300,9 @@ struct Packet {
   uint32_t kinds;     // kernel types met in its ancestry (bit = type)
   double cond;        // see ORecord
   double wsens;       // see ORecord
+  double ddir;        // see ORecord
+  double dpos;        // see ORecord
+  double dtime;       // see ORecord
   std::vector<double> dlogw;  // d log(w) / d(parameters), when gradients are on
 };
 
@@ -533,11 +541,12 @@ Mu attenuation(const OScatterer& sc, const ScatInfo& si, double speed, double* m
 
 // ------------------------------------------------------------- kernels
 struct Scatter {
-  V3 dir;
-  double speed;
-  double factor;  // weight multiplier
-  double dw_q2;   // Q^2 entering the Debye-Waller factor (0 if none)
-  int dos_bin;    // DOS bin of a one-phonon draw (-1 otherwise)
+  V3 dir{0.0, 0.0, 0.0};
+  double speed = 0.0;
+  double factor = 0.0;   // weight multiplier
+  double dw_q2 = 0.0;    // Q^2 entering the Debye-Waller factor (0 if none)
+  int dos_bin = -1;      // DOS bin of a one-phonon draw (-1 otherwise)
+  double dq_sens = 0.0;  // |d log(factor) / dQ| (per 1/A of error in Q), for conditioning
 };
 
 V3 isotropic_direction(double u_cos, double u_phi) {
@@ -561,6 +570,7 @@ void perp_basis(V3 n, V3* e1, V3* e2, double* margin) {
 // incoherent elastic: dsigma/dOmega = sigma_inc/4pi N e^{-2W} (Supplement S4)
 Scatter k_iso(const OKernel& k, const ScatInfo& si, const Packet& P, const double* u) {
   Scatter r;
+  r.dq_sens = 0.0;
   r.dir = isotropic_direction(u[2], u[3]);
   r.speed = P.speed;
   r.factor = 1.0;
@@ -629,6 +639,7 @@ Scatter k_powder(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
 Scatter k_phonon(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
                  const Packet& P, const double* u, double* margin) {
   Scatter r;
+  r.dq_sens = 0.0;
   r.dw_q2 = 0.0;
   int b = 0;
   for (; b < k.nbins; ++b)
@@ -670,6 +681,7 @@ Scatter k_phonon(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
 // Proposal: isotropic direction, energy transfer uniform on [E_lo, E_hi].
 Scatter k_spinwave(const OKernel& k, const Packet& P, const double* u) {
   Scatter r;
+  r.dq_sens = 0.0;
   r.dw_q2 = 0.0;
   r.dos_bin = -1;
   double Ei = kEperV2 * P.speed * P.speed;
@@ -694,12 +706,18 @@ Scatter k_spinwave(const OKernel& k, const Packet& P, const double* u) {
   double x = E - w;
   double lor = (k.gamma / kPi) / (x * x + k.gamma * k.gamma);
   r.factor = (k_f / k_i) * lor * (hi - lo);
+  // conditioning: |d log L / d omega| * |grad_Q omega| (crystal axes)
+  double gw = 4.0 * k.J * k.S * k.a *
+              (std::fabs(std::sin(Qc.x * k.a)) + std::fabs(std::sin(Qc.y * k.a)) +
+               std::fabs(std::sin(Qc.z * k.a)));
+  r.dq_sens = 2.0 * std::fabs(x) / (x * x + k.gamma * k.gamma) * gw;
   return r;
 }
 
 // tabulated isotropic S(Q,E): value of the grid cell containing (|Q|, E)
 Scatter k_sqe(const OKernel& k, const Packet& P, const double* u, double* margin) {
   Scatter r;
+  r.dq_sens = 0.0;
   r.dw_q2 = 0.0;
   r.dos_bin = -1;
   double Ei = kEperV2 * P.speed * P.speed;
@@ -816,7 +834,7 @@ struct Sim {
     // distance in cos(2theta) to the ring edges that bound this ring
     double m_lo = ring > 0 ? std::fabs(cz - std::cos(ring * width)) : kHuge;
     double m_hi = ring < D.n2t - 1 ? std::fabs(cz - std::cos((ring + 1) * width)) : kHuge;
-    *margin = std::min(*margin, std::min(m_lo, m_hi) / kTauCos);
+    *margin = std::min(*margin, std::min(m_lo, m_hi) / (kTauCos + 3.0 * (P.ddir + 1e-7)));
     double tof = P.t + s / P.speed;
     rec.tof = tof;
     double dt = (D.tof_hi - D.tof_lo) / D.ntof;
@@ -835,6 +853,10 @@ struct Sim {
   // brute force over every tube; the first tube on the ray records
   void detect_tubes(const Packet& P, ORecord& rec, double* margin) {
     const ODetector& D = S.det;
+    // lateral uncertainty of the ray at the detector for a binary32
+    // implementation, and the geometric decision scale it implies
+    const double db = (P.ddir + 1e-7) * D.R + 1e-8;
+    const double tauG = kTauGeom + 3.0 * db;
     double best = kHuge, second = kHuge;
     int best_tube = -1;
     double best_out = 0.0, best_b = 0.0, best_dperp = 0.0;
@@ -852,7 +874,8 @@ struct Sim {
         double s_c = -(p.x * P.dir.x + p.z * P.dir.z) / a;
         double qx = p.x + s_c * P.dir.x, qz = p.z + s_c * P.dir.z;
         double bimp = std::sqrt(qx * qx + qz * qz);
-        if (std::fabs(bimp - D.radius) < kTauImpact * D.radius) *margin = std::min(*margin, std::fabs(bimp - D.radius) / (kTauImpact * D.radius));
+        const double tauI = kTauImpact * D.radius + 3.0 * db;
+        if (std::fabs(bimp - D.radius) < tauI) *margin = std::min(*margin, std::fabs(bimp - D.radius) / tauI);
         if (!cylinder_interval(p, P.dir, D.radius, D.length, &lo, &hi, &m)) {
           if (bimp < D.radius) *margin = std::min(*margin, m);
           continue;
@@ -876,7 +899,7 @@ struct Sim {
       tally->n_missed++;
       return;
     }
-    if (second < kHuge) *margin = std::min(*margin, (second - best) / kTauGeom);
+    if (second < kHuge) *margin = std::min(*margin, (second - best) / tauG);
     double chord = best_out - best;
     double mu = 100.0 * D.n_he * kHe3SigmaAbs * (kV2200 / P.speed);
     double pabs = -std::expm1(-mu * chord);
@@ -891,7 +914,7 @@ struct Sim {
     if (pix < 0) pix = 0;
     if (pix > D.npix - 1) pix = D.npix - 1;
     double ym = std::fabs(fp - std::nearbyint(fp)) * D.length / D.npix;
-    if (std::nearbyint(fp) > 0 && std::nearbyint(fp) < D.npix) *margin = std::min(*margin, ym / kTauGeom);
+    if (std::nearbyint(fp) > 0 && std::nearbyint(fp) < D.npix) *margin = std::min(*margin, ym / tauG);
     double tof = P.t + s_a / P.speed;
     rec.tof = tof;
     rec.tube = best_tube;
@@ -900,10 +923,35 @@ struct Sim {
     double ft = (tof - D.tof_lo) / dt;
     int it = (int)std::floor(ft);
     *margin = std::min(*margin, tof_margin(ft, D.ntof) * dt / (kTauTof * std::fabs(tof)));
-    // sensitivity of the recorded value to a sideways shift of the ray
-    double rr = D.radius * D.radius - best_b * best_b;
-    if (rr > 0.0)
-      rec.value_sens = P.w * mu * std::exp(-mu * chord) * 2.0 * best_b / (std::sqrt(rr) * best_dperp);
+    // allowance: value and tof of the same tube for the ray shifted sideways
+    // by db in two perpendicular directions (chords cut by the caps included)
+    {
+      (void)best_b;
+      (void)best_dperp;
+      int brow = best_tube / D.ncols, bcol = best_tube % D.ncols;
+      double phi = D.phi_lo + (bcol + 0.5) * dphi;
+      V3 c = {D.R * std::sin(phi), D.row_y[brow], D.R * std::cos(phi)};
+      V3 e1, e2;
+      double mdummy = kHuge;
+      perp_basis(P.dir, &e1, &e2, &mdummy);
+      double vmax = 0.0, tmax = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        V3 sh = scale(k < 2 ? e1 : e2, (k & 1) ? -db : db);
+        V3 p = sub(add(P.pos, sh), c);
+        double lo2, hi2, m2 = kHuge;
+        if (!cylinder_interval(p, P.dir, D.radius, D.length, &lo2, &hi2, &m2) || hi2 <= 0.0) {
+          vmax = std::max(vmax, P.w * pabs);
+          continue;
+        }
+        double s_in2 = std::max(lo2, 0.0);
+        double pabs2 = -std::expm1(-mu * (hi2 - s_in2));
+        double s_a2 = s_in2 - std::log1p(-u[0] * pabs2) / mu;
+        vmax = std::max(vmax, std::fabs(P.w * pabs2 - P.w * pabs));
+        tmax = std::max(tmax, std::fabs(s_a2 - s_a) / P.speed);
+      }
+      rec.value_sens = vmax;
+      rec.tof_tol = tmax;
+    }
     if (ft < 0.0 || it >= D.ntof) {
       tally->n_out_of_window++;
       return;
@@ -929,6 +977,9 @@ struct Sim {
     rec.kinds = P.kinds;
     rec.cond = P.cond;
     rec.wsens = P.wsens;
+    rec.ddir = P.ddir;
+    rec.dpos = P.dpos;
+    rec.dtime = P.dtime;
     double margin = kHuge;
     tally->n_detect++;
     if (S.det.type == DET_SPHERE) detect_sphere(P, rec, &margin);
@@ -975,6 +1026,7 @@ struct Sim {
                      [](const Interval& a, const Interval& b) { return a.s_in < b.s_in; });
     V3 start = P.pos;
     double t0 = P.t;
+    double last_dL_exit = 0.0;
     for (size_t g = 0; g < segs.size(); ++g) {
       const Interval& iv = segs[g];
       const OScatterer& sc = S.s[iv.scat];
@@ -990,19 +1042,23 @@ struct Sim {
       *own_margin = std::min(*own_margin, m_mu);
       tally->n_segments++;
       // chord uncertainty of a binary32 implementation (conditioning only)
-      double dL;
+      double dL, dL_exit;
       {
         const OShape& sh = sc.shape;
         V3 dl = matTvec(sh.rot, P.dir);
         V3 q_out = matTvec(sh.rot, sub(add(start, scale(P.dir, iv.s_out)),
                                        {sh.pos[0], sh.pos[1], sh.pos[2]}));
-        double inv = 1.0 / std::max(surface_cos(sh, q_out, dl), 1e-9);
+        // lateral uncertainty at a surface: position rounding plus the
+        // direction's uncertainty over the distance flown
+        // (weights: lateral uncertainty only -- sliding the start along the
+        // ray does not move the surfaces it meets)
+        dL_exit = (kEpsPos + P.ddir * iv.s_out) / std::max(surface_cos(sh, q_out, dl), 1e-9);
+        dL = dL_exit;
         if (iv.s_in > 0.0) {
           V3 q_in = matTvec(sh.rot, sub(add(start, scale(P.dir, iv.s_in)),
                                         {sh.pos[0], sh.pos[1], sh.pos[2]}));
-          inv += 1.0 / std::max(surface_cos(sh, q_in, dl), 1e-9);
+          dL += (kEpsPos + P.ddir * iv.s_in) / std::max(surface_cos(sh, q_in, dl), 1e-9);
         }
-        dL = kEpsPos * inv;
       }
       double att = std::exp(-mu.total * L);
       double a = -std::expm1(-mup.total * L);  // probability to interact
@@ -1084,6 +1140,23 @@ struct Sim {
           double Ein = kEperV2 * P.speed * P.speed;
           double Eout = kEperV2 * C.speed * C.speed;
           C.cond = P.cond * (Eout > 0.0 ? std::max(1.0, Ein / Eout) : 1.0);
+          C.dpos = P.dpos + P.ddir * (iv.s_in + x) + kEpsPos + dL;
+          C.dtime = P.dtime + (dL + kEpsPos) / P.speed;
+          if (r.dq_sens > 0.0) {
+            double kin = k_from_speed(P.speed), kout = k_from_speed(C.speed);
+            double dq = kin * (P.ddir + 2e-7) + kout * 2e-7 + (kin + kout) * 2e-7 * P.cond;
+            C.wsens += r.dq_sens * dq;
+          }
+          if (k.type == K_POWDER) {
+            // the cone angle 2 asin(lambda/2d) from a binary32 wavelength:
+            // d(2 theta) = 2 tan(theta) d lambda / lambda
+            double c = dot(P.dir, C.dir);
+            double th = 0.5 * std::acos(std::max(-1.0, std::min(1.0, c)));
+            double tn = std::tan(std::min(th, 0.5 * kPi - 1e-6));
+            C.ddir = P.ddir + 2e-7 + 2.0 * tn * 2e-7 * P.cond;
+          } else {
+            C.ddir = 2e-7;  // a fresh isotropic direction
+          }
         }
         if (C.w > 0.0) children.push_back(C);
         else tally->n_zero_weight++;
@@ -1092,12 +1165,15 @@ struct Sim {
       }
       P.w *= att;
       P.wsens += mu.total * dL;
+      last_dL_exit = dL_exit;
       if (tangent) add_dmu(P.dlogw, iv.scat, P.speed, -L);
     }
     if (!segs.empty()) {
       double s_end = segs.back().s_out;
       P.pos = add(start, scale(P.dir, s_end));
       P.t = t0 + s_end / P.speed;
+      P.dpos += P.ddir * s_end + last_dL_exit;
+      P.dtime += last_dL_exit / P.speed;
     }
   }
 
@@ -1140,6 +1216,9 @@ struct Sim {
     P.kinds = 0u;
     P.cond = 1.0;
     P.wsens = 0.0;
+    P.ddir = 0.0;
+    P.dpos = 0.0;
+    P.dtime = 0.0;
     if (tangent) P.dlogw.assign(np, 0.0);
   }
 };

@@ -96,7 +96,8 @@ RECORD_DTYPE = np.dtype([
     ("bin", np.int64), ("value", np.float64), ("tof", np.float64), ("tube", np.int32),
     ("pixel", np.int32), ("margin_anc", np.float64), ("margin_own", np.float64),
     ("value_sens", np.float64), ("kinds", np.uint32), ("pad", np.int32),
-    ("cond", np.float64), ("wsens", np.float64)])
+    ("cond", np.float64), ("wsens", np.float64), ("tof_tol", np.float64),
+    ("ddir", np.float64), ("dpos", np.float64), ("dtime", np.float64)])
 
 SHAPES = {"box": 1, "cylinder": 2, "annulus": 3}
 KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5}
