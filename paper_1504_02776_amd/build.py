@@ -20,15 +20,16 @@ def hipcc() -> str:
     return exe
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source for gfx950 and link libmcv.so next to this file."""
+def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
+    """Compile every source for gfx950 and link libmcv.so next to this file
+    (or to `out`, with extra compiler flags, for variants)."""
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build") if out == LIB else out + ".build"
     os.makedirs(bdir, exist_ok=True)
     common = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
               # packed FP32 instructions are kept out of generated code
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-              "-I", os.path.join(HERE, "..", "include"), "-Wall"]
+              "-I", os.path.join(HERE, "..", "include"), "-Wall"] + list(extra)
     for src in SOURCES:
         obj = os.path.join(bdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
@@ -39,13 +40,13 @@ def build(verbose: bool = False) -> str:
         if verbose and r.stderr.strip():
             print(r.stderr)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -22,7 +22,7 @@
 #include "mcv_internal.h"
 
 namespace mcv {
-hipError_t launch_transport(const DevPlan* plan, const float* tables, int n_tables, int stack_cap,
+hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const float* tables,
                             const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
                             int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
@@ -644,7 +644,7 @@ mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t firs
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
-  hipError_t e = launch_transport(p->d_plan, p->d_tables, p->host.n_tables, p->host.stack_cap, B,
+  hipError_t e = launch_transport(p->d_plan, p->host, p->d_tables, B,
                                   seed, first, n, (int)grid, p->block, per_wave, hist, hist_w2,
                                   rec, cap, n_out, nullptr, (hipStream_t)stream);
   if (cur != p->device) (void)hipSetDevice(cur);
@@ -804,7 +804,7 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
     AA.inv_theta = p->adj.inv_theta;
     uint64_t grid, per_wave;
     grid_shape(p, n, p->adj.block, &grid, &per_wave);
-    hipError_t e = launch_transport(p->d_plan, p->d_tables, p->host.n_tables, p->host.stack_cap,
+    hipError_t e = launch_transport(p->d_plan, p->host, p->d_tables,
                                     B, seed, first, n, (int)grid, p->adj.block, per_wave, nullptr,
                                     nullptr, nullptr, 0, nullptr, &AA, (hipStream_t)stream);
     if (e == hipSuccess)

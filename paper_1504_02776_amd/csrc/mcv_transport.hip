@@ -30,7 +30,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "mcv_internal.h"
+
+// resident waves per SIMD the transport kernels are compiled for (register
+// budget 512 / N per lane)
+#ifndef MCV_WAVES_PER_EU
+#define MCV_WAVES_PER_EU 2
+#endif
 
 namespace mcv {
 namespace dev {
@@ -682,32 +690,51 @@ __device__ __forceinline__ void pop(const float* st, int slot, int nthreads, int
 // the others pushed on the lane stack) and moves it to where it leaves.  In
 // adjoint mode the carries follow: each crossed length L adds -L dmu/dtheta,
 // each birth adds d log(mu_k) - x dmu/dtheta and the kernel's terms.
-template <bool ADJ>
+// Interval slots of a flight: scatterer s owns slot s, or slots 2s and 2s+1
+// when the assembly has an annulus (TWO).  NSC = scatterers the code is
+// compiled for; the slot arrays then live in registers with static indices.
+template <int NSC, bool TWO>
+struct Slots {
+  static constexpr int N = TWO ? 2 * NSC : NSC;
+  static __device__ __forceinline__ constexpr int of(int s, int i) { return TWO ? 2 * s + i : s; }
+  static __device__ __forceinline__ constexpr int scat(int j) { return TWO ? j >> 1 : j; }
+};
+
+template <bool ADJ, int NSC, bool TWO>
 __device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, const AdjArgs& AA,
                                     Pk& P, Adj& pa, uint64_t id, uint64_t seed, Pk& nxt,
                                     Adj& na, bool& has_nxt, float* st, int& nst, int nthreads,
                                     int tid) {
-  float lo[kMaxSlots], hi[kMaxSlots], len[kMaxSlots];
+  using SL = Slots<NSC, TWO>;
+  constexpr int NS = SL::N;
+  float lo[NS], hi[NS], len[NS];
   uint32_t valid = 0u, codes = 0u;
 #pragma unroll
-  for (int s = 0; s < kMaxScat; ++s) {
+  for (int s = 0; s < NSC; ++s) {
     Iv a, b;
     a.lo = a.hi = a.len = b.lo = b.hi = b.len = 0.0f;
     a.entry = b.entry = ENTRY_NONE;
     const int n = s < PL.nscat ? shape_iv(PL.s[s], P, a, b) : 0;
-    lo[2 * s] = a.lo;
-    hi[2 * s] = a.hi;
-    len[2 * s] = a.len;
-    lo[2 * s + 1] = b.lo;
-    hi[2 * s + 1] = b.hi;
-    len[2 * s + 1] = b.len;
-    codes |= ((uint32_t)a.entry << (8 * s)) | ((uint32_t)b.entry << (8 * s + 4));
-    if (n > 0 && a.hi > kSurf) valid |= 1u << (2 * s);
-    if (n > 1 && b.hi > kSurf) valid |= 1u << (2 * s + 1);
+    constexpr int dummy = 0;
+    (void)dummy;
+    const int j0 = SL::of(s, 0);
+    lo[j0] = a.lo;
+    hi[j0] = a.hi;
+    len[j0] = a.len;
+    codes |= (uint32_t)a.entry << (4 * j0);
+    if (n > 0 && a.hi > kSurf) valid |= 1u << j0;
+    if (TWO) {
+      const int j1 = SL::of(s, 1);
+      lo[j1] = b.lo;
+      hi[j1] = b.hi;
+      len[j1] = b.len;
+      codes |= (uint32_t)b.entry << (4 * j1);
+      if (n > 1 && b.hi > kSurf) valid |= 1u << j1;
+    }
   }
   // a packet inside a scatterer starts its interval at 0
 #pragma unroll
-  for (int j = 0; j < kMaxSlots; ++j) {
+  for (int j = 0; j < NS; ++j) {
     if (lo[j] <= 0.0f) {
       lo[j] = 0.0f;
       len[j] = hi[j];
@@ -723,7 +750,7 @@ __device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, const A
     int j = 0;
     float best = kBig;
 #pragma unroll
-    for (int q = 0; q < kMaxSlots; ++q) {
+    for (int q = 0; q < NS; ++q) {
       if ((valid >> q) & 1u) {
         if (lo[q] < best) {
           best = lo[q];
@@ -734,14 +761,14 @@ __device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, const A
     valid &= ~(1u << j);
     float slo = 0.0f, shi = 0.0f, sl = 0.0f;
 #pragma unroll
-    for (int q = 0; q < kMaxSlots; ++q) {
+    for (int q = 0; q < NS; ++q) {
       if (q == j) {
         slo = lo[q];
         shi = hi[q];
         sl = len[q];
       }
     }
-    const int si = j >> 1;
+    const int si = SL::scat(j);
     const DevScat& S = PL.s[si];
     const Mu mu = attenuation(S, tab, P.sp);
     const float ml = mu.total * sl;
@@ -862,7 +889,7 @@ struct Sinks {
 // the packet tree of one history depth first and takes the next history of
 // the range as soon as it is done (ballot + prefix count), so lanes stay busy
 // until the range is exhausted.  Called with the whole wave active.
-template <int MODE>
+template <int MODE, int NSC, bool TWO>
 __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab, float* st,
                                             const DevBeam& beam, uint64_t seed, uint64_t first,
                                             uint64_t begin, uint64_t end, const Sinks& out,
@@ -901,7 +928,8 @@ __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab,
       nxt.lin = 0u;
       Adj na = ca;
       bool has_nxt = false;
-      fly<ADJ>(PL, tab, AA, cur, ca, hid, seed, nxt, na, has_nxt, st, nst, nthreads, tid);
+      fly<ADJ, NSC, TWO>(PL, tab, AA, cur, ca, hid, seed, nxt, na, has_nxt, st, nst, nthreads,
+                         tid);
       const Hit hh = PL.det.type == DET_SPHERE ? detect_sphere(PL.det, cur)
                                                : detect_tubes(PL.det, tab, cur, hid, seed);
       if (hh.bin >= 0) {
@@ -971,8 +999,8 @@ __device__ __forceinline__ void stage_plan(DevPlan& PL, float* dyn, const DevPla
 // numbers) and accumulates dL/dtheta = sum over recorded packets of
 // dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
 // per workgroup.
-template <int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+template <int MODE, int NSC, bool TWO>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MCV_WAVES_PER_EU)))
 transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
           uint64_t seed, uint64_t first, uint64_t n, uint64_t per_wave, Sinks out, AdjArgs AA) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
@@ -992,7 +1020,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
   if (begin < n)  // uniform per wave
-    trace_range<MODE>(PL, dyn, st, beam, seed, first, begin,
+    trace_range<MODE, NSC, TWO>(PL, dyn, st, beam, seed, first, begin,
                       begin + per_wave < n ? begin + per_wave : n, out, AA, acc, nthreads, tid);
   if (ADJ) {
     __syncthreads();
@@ -1013,7 +1041,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
 // workgroup re-stages plan and tables in LDS only when the simulation
 // changes; its waves split the chunk's ids.  The list is sorted by
 // estimated cost, longest first.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MCV_WAVES_PER_EU)))
 batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restrict__ chunks,
                  uint32_t n_chunks, uint32_t* __restrict__ cursor) {
   __shared__ DevPlan PL;
@@ -1043,7 +1071,7 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const uint64_t b = ch.first + per * wid;
     const uint64_t e = ch.first + ch.count;
     Sinks out = {it.hist, nullptr, nullptr, 0, nullptr};
-    if (b < e) trace_range<MODE_RUN>(PL, dyn, st, it.beam, it.seed, it.id0, b,
+    if (b < e) trace_range<MODE_RUN, kMaxScat, true>(PL, dyn, st, it.beam, it.seed, it.id0, b,
                                      b + per < e ? b + per : e, out, AA, nullptr, nthreads, tid);
     __syncthreads();
   }
@@ -1125,7 +1153,40 @@ size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb) {
   return sizeof(float) * (tab + acc + (size_t)stack_cap * nf * block);
 }
 
-hipError_t launch_transport(const DevPlan* plan, const float* tables, int n_tables, int stack_cap,
+namespace {
+
+template <int MODE, int NSC, bool TWO>
+void launch_one(int grid, int block, size_t lds, hipStream_t stream, const DevPlan* plan,
+                const float* tables, const DevBeam& beam, uint64_t seed, uint64_t first,
+                uint64_t n, uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
+  hipLaunchKernelGGL((dev::transport<MODE, NSC, TWO>), dim3(grid), dim3(block), lds, stream, plan,
+                     tables, beam, seed, first, n, per_wave, out, AA);
+}
+
+template <int MODE>
+void launch_mode(int nsc, bool two, int grid, int block, size_t lds, hipStream_t stream,
+                 const DevPlan* plan, const float* tables, const DevBeam& beam, uint64_t seed,
+                 uint64_t first, uint64_t n, uint64_t per_wave, const dev::Sinks& out,
+                 const AdjArgs& AA) {
+#define MCV_LAUNCH(NSC_, TWO_)                                                                 \
+  launch_one<MODE, NSC_, TWO_>(grid, block, lds, stream, plan, tables, beam, seed, first, n,  \
+                               per_wave, out, AA)
+  if (nsc <= 1) {
+    if (two) MCV_LAUNCH(1, true);
+    else MCV_LAUNCH(1, false);
+  } else if (nsc == 2) {
+    if (two) MCV_LAUNCH(2, true);
+    else MCV_LAUNCH(2, false);
+  } else {
+    if (two) MCV_LAUNCH(4, true);
+    else MCV_LAUNCH(4, false);
+  }
+#undef MCV_LAUNCH
+}
+
+}  // namespace
+
+hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const float* tables,
                             const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
                             int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
@@ -1134,17 +1195,20 @@ hipError_t launch_transport(const DevPlan* plan, const float* tables, int n_tabl
   AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = -1;
   if (adj) AA = *adj;
   dev::Sinks out = {hist, hist_w2, rec, cap, n_out};
-  const size_t lds = transport_lds_bytes(n_tables, stack_cap, block, adj ? adj->nb : 0);
+  const size_t lds =
+      transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, adj ? adj->nb : 0);
+  const int nsc = host_plan.nscat;
+  const bool two = host_plan.smax > host_plan.nscat;
   if (adj) {
     hipLaunchKernelGGL(dev::zero2, dim3(1), dim3(64), 0, stream, AA.sums);
-    hipLaunchKernelGGL(dev::transport<dev::MODE_ADJOINT>, dim3(grid), dim3(block), lds, stream,
-                       plan, tables, beam, seed, first, n, per_wave, out, AA);
+    launch_mode<dev::MODE_ADJOINT>(nsc, two, grid, block, lds, stream, plan, tables, beam, seed,
+                                   first, n, per_wave, out, AA);
   } else if (rec) {
-    hipLaunchKernelGGL(dev::transport<dev::MODE_TRACE>, dim3(grid), dim3(block), lds, stream,
-                       plan, tables, beam, seed, first, n, per_wave, out, AA);
+    launch_mode<dev::MODE_TRACE>(nsc, two, grid, block, lds, stream, plan, tables, beam, seed,
+                                 first, n, per_wave, out, AA);
   } else {
-    hipLaunchKernelGGL(dev::transport<dev::MODE_RUN>, dim3(grid), dim3(block), lds, stream, plan,
-                       tables, beam, seed, first, n, per_wave, out, AA);
+    launch_mode<dev::MODE_RUN>(nsc, two, grid, block, lds, stream, plan, tables, beam, seed,
+                               first, n, per_wave, out, AA);
   }
   return hipGetLastError();
 }
@@ -1183,11 +1247,24 @@ hipError_t launch_loss_grad(const double* I, const double* T, const double* w, i
 
 size_t transport_static_lds() { return sizeof(DevPlan); }
 
+namespace {
+template <int MODE>
+void push_mode(std::vector<const void*>& v) {
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, true>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, false>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, true>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, false>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, true>));
+}
+}  // namespace
+
 hipError_t set_transport_lds_limit(size_t bytes) {
-  const void* fns[4] = {reinterpret_cast<const void*>(&dev::transport<dev::MODE_RUN>),
-                        reinterpret_cast<const void*>(&dev::transport<dev::MODE_TRACE>),
-                        reinterpret_cast<const void*>(&dev::transport<dev::MODE_ADJOINT>),
-                        reinterpret_cast<const void*>(&dev::batch_persistent)};
+  std::vector<const void*> fns;
+  push_mode<dev::MODE_RUN>(fns);
+  push_mode<dev::MODE_TRACE>(fns);
+  push_mode<dev::MODE_ADJOINT>(fns);
+  fns.push_back(reinterpret_cast<const void*>(&dev::batch_persistent));
   // each kernel may use `bytes` of LDS in total, static part included
   for (const void* f : fns) {
     hipFuncAttributes at;
