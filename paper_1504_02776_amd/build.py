@@ -1,4 +1,5 @@
-"""Builds the HIP transport library (libmcv.so) for gfx950, in-tree."""
+"""Builds the HIP transport library (libmcv.so) for gfx950, in-tree, and the
+primitive cost probe (libmcv_probe.so, measurement only)."""
 
 from __future__ import annotations
 
@@ -10,6 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcv.so")
 SOURCES = ["mcv_transport.hip", "mcv_api.cpp"]
+PROBE_LIB = os.path.join(HERE, "libmcv_probe.so")
+PROBE_SOURCES = ["mcv_probe.hip"]
 ARCH = os.environ.get("MCV_OFFLOAD_ARCH", "gfx950")
 
 
@@ -20,17 +23,18 @@ def hipcc() -> str:
     return exe
 
 
-def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
+def build(verbose: bool = False, out: str = LIB, extra=(), sources=None) -> str:
     """Compile every source for gfx950 and link libmcv.so next to this file
     (or to `out`, with extra compiler flags, for variants)."""
     objs = []
+    sources = SOURCES if sources is None else sources
     bdir = os.path.join(HERE, "_build") if out == LIB else out + ".build"
     os.makedirs(bdir, exist_ok=True)
     common = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
               # packed FP32 instructions are kept out of generated code
               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
               "-I", os.path.join(HERE, "..", "include"), "-Wall"] + list(extra)
-    for src in SOURCES:
+    for src in sources:
         obj = os.path.join(bdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
         cmd = [hipcc()] + common + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
@@ -49,5 +53,11 @@ def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
     return out
 
 
+def build_probe(verbose: bool = False) -> str:
+    """The cost probe: the library's sources plus the probe kernels."""
+    return build(verbose, out=PROBE_LIB, sources=PROBE_SOURCES)
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_probe(verbose=True))

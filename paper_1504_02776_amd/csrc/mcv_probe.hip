@@ -1,0 +1,233 @@
+// Cost probe for the transport library's device primitives on gfx950.
+//
+// Each probe kernel runs one primitive of the hot path (a Philox block, a
+// shape's interval test, the attenuation terms of one interval, the split of
+// a child, one kernel draw, one detector test, the source) many times per
+// lane at full occupancy with every lane converged, on packets made from a
+// cheap integer hash.  The time of a probe minus the time of the null probe
+// (the same packet construction, no primitive), times the VALU issue rate,
+// per call, is the primitive's cost in lane-operation slots.  With the
+// primitive counts per history of the algorithm these give the arithmetic
+// work per history that the transport roofline is priced against.
+//
+// Built as its own shared library together with the library's sources (the
+// probes call the very device functions the transport kernels inline, and
+// take plans made by the same plan builder).  Measurement infrastructure,
+// not part of the transport path.
+
+#include "mcv_transport.hip"
+#include "mcv_api.cpp"
+
+namespace mcv {
+namespace probe {
+
+using namespace dev;
+
+enum {
+  PR_NULL = 0,
+  PR_RNG = 1,
+  PR_SOURCE = 2,
+  PR_SHAPE = 3,
+  PR_SEGMENT = 4,
+  PR_SPLIT = 5,
+  PR_KERNEL = 6,
+  PR_DETECT = 7
+};
+
+// 32-bit integer mix (the "lowbias32" constants of C. Wellons' hash search)
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+constexpr int kNU = 8;
+
+// a packet near the sample (within +-3 cm of the origin), isotropic
+// direction, speed sp0 (1 +- 10 %), and kNU uniforms for the primitive
+__device__ __forceinline__ void make_input(uint32_t& h, float sp0, Pk& P, float* u) {
+  float v[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    h = mix32(h + 0x9e3779b9u);
+    v[i] = unif(h);
+  }
+#pragma unroll
+  for (int i = 0; i < kNU; ++i) {
+    h = mix32(h + 0x9e3779b9u);
+    u[i] = unif(h);
+  }
+  P.px = 0.06f * (v[0] - 0.5f);
+  P.py = 0.06f * (v[1] - 0.5f);
+  P.pz = 0.06f * (v[2] - 0.5f);
+  iso_dir(v[3], v[4], P.dx, P.dy, P.dz);
+  P.sp = sp0 * (0.9f + 0.2f * v[5]);
+  P.t = 1e-4f * v[0];
+  P.w = 1.0f;
+  P.lin = 9u;
+}
+
+__device__ __forceinline__ int entry_code_of(const DevScat& S) {
+  return S.shape == SHAPE_BOX ? ENTRY_BOX_X + 2 : ENTRY_OUTER;
+}
+
+template <int PR>
+__global__ void __launch_bounds__(256)
+probe_kernel(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
+             uint64_t seed, int arg, uint32_t iters, float sp0, float* __restrict__ sink,
+             uint32_t* __restrict__ hits) {
+  __shared__ DevPlan PL;
+  extern __shared__ __align__(16) float dyn[];
+  const int tid = threadIdx.x;
+  stage_plan(PL, dyn, gplan, gtab, blockDim.x, tid);
+  __syncthreads();
+  const uint32_t gid = blockIdx.x * blockDim.x + tid;
+  uint32_t h = mix32(gid * 0x2545f491u + 0x1234567u);
+  float acc = 0.0f;
+  uint32_t nh = 0;
+  for (uint32_t it = 0; it < iters; ++it) {
+    Pk P;
+    float u[kNU];
+    make_input(h, sp0, P, u);
+    acc += P.px + P.py + P.pz + P.dx + P.dy + P.dz + P.sp + u[0] + u[1] + u[2] + u[3] + u[4] +
+           u[5] + u[6] + u[7];
+    if (PR == PR_RNG) {
+      float r[4];
+      draw4((uint64_t)gid * iters + it, STREAM_SCATTER, h, 0u, seed, r);
+      acc += r[0] + r[1] + r[2] + r[3];
+    } else if (PR == PR_SOURCE) {
+      const Pk S = source(beam, (uint64_t)gid * iters + it + h, seed);
+      acc += S.px + S.py + S.pz + S.sp + S.t + S.w;
+    } else if (PR == PR_SHAPE) {
+      Iv a, b;
+      a.lo = a.hi = a.len = b.lo = b.hi = b.len = 0.0f;
+      const int n = shape_iv(PL.s[arg], P, a, b);
+      acc += a.lo + a.hi + a.len + b.lo + b.len + (float)(n + a.entry + b.entry);
+    } else if (PR == PR_SEGMENT) {
+      Mu mu;
+      float att, pint;
+      segment_terms(PL.s[arg], dyn, P.sp, 0.02f * u[0], mu, att, pint);
+      acc += att + pint + mu.scat;
+    } else if (PR == PR_SPLIT) {
+      const DevScat& S = PL.s[arg];
+      Mu mu;
+      mu.scat = 0.0f;
+#pragma unroll
+      for (int q = 0; q < kMaxKern; ++q) {
+        mu.k[q] = q < S.nk ? 0.1f + u[2 + q] : 0.0f;
+        mu.scat += mu.k[q];
+      }
+      mu.total = mu.scat + 0.5f;
+      Pk C;
+      float x;
+      const int k = split_child(S, mu, 0.5f * u[5], P, P.px, P.py, P.pz, P.t, 0.01f * u[6],
+                                (gid & 1u) ? entry_code_of(S) : ENTRY_NONE, u, 73u, C, x);
+      acc += C.px + C.py + C.pz + C.t + C.w + x + (float)k;
+    } else if (PR == PR_KERNEL) {
+      const DevScat& S = PL.s[arg >> 2];
+      const Out o = kernel_eval(S.k[arg & 3], S, dyn, P, u);
+      acc += o.dx + o.dy + o.dz + o.sp + o.f + o.dwq2 + (float)o.bin;
+    } else if (PR == PR_DETECT) {
+      const Hit hh = PL.det.type == DET_SPHERE
+                         ? detect_sphere(PL.det, P)
+                         : detect_tubes(PL.det, dyn, P, (uint64_t)gid * iters + it, seed);
+      acc += hh.value + hh.tof + (float)hh.bin;
+      if (PL.det.type != DET_SPHERE && hh.tube >= 0) ++nh;
+    }
+  }
+  sink[gid] = acc;
+  hits[gid] = nh;
+}
+
+template <int PR>
+hipError_t launch_probe(mcv_plan p, const DevBeam& B, uint64_t seed, int arg, uint32_t iters,
+                        float sp0, int grid, float* sink, uint32_t* hits, hipStream_t s) {
+  const size_t lds = sizeof(float) * (size_t)((p->host.n_tables + 3) & ~3);
+  hipLaunchKernelGGL((probe_kernel<PR>), dim3(grid), dim3(256), lds, s, p->d_plan, p->d_tables, B,
+                     seed, arg, iters, sp0, sink, hits);
+  return hipGetLastError();
+}
+
+}  // namespace probe
+}  // namespace mcv
+
+extern "C" {
+
+// Runs probe `kind` (PR_*) with argument `arg` (scatterer index; for
+// kernels scatterer * 4 + kernel) on `grid` workgroups of 256 lanes,
+// `iters` calls per lane, `reps` timed repetitions after one warm-up.
+// Writes the best time in ms and the number of detector draws per call.
+// Returns MCV_OK or an error status (bad kind, argument or launch).
+mcv_status mcv_probe_time(mcv_plan p, const mcv_beam* beam, uint64_t seed, int32_t kind,
+                          int32_t arg, uint32_t iters, int32_t grid, int32_t reps,
+                          double* ms_out, double* draws_per_call) {
+  using namespace mcv::probe;
+  if (!p || !ms_out || !draws_per_call) return fail(MCV_EINVAL, "null argument");
+  if (grid <= 0 || grid > 65536 || iters == 0 || reps <= 0) return fail(MCV_EINVAL, "bad size");
+  if ((kind == PR_SHAPE || kind == PR_SEGMENT || kind == PR_SPLIT) &&
+      (arg < 0 || arg >= p->host.nscat))
+    return fail(MCV_EINVAL, "scatterer index out of range");
+  if (kind == PR_KERNEL &&
+      (arg < 0 || (arg >> 2) >= p->host.nscat || (arg & 3) >= p->host.s[arg >> 2].nk))
+    return fail(MCV_EINVAL, "kernel index out of range");
+  if (kind < PR_NULL || kind > PR_DETECT) return fail(MCV_EINVAL, "unknown probe");
+  DevBeam B;
+  mcv_status st = make_beam(p, beam, &B);
+  if (st != MCV_OK) return st;
+  (void)hipSetDevice(p->device);
+  if (set_transport_lds_limit(160 * 1024) != hipSuccess) return fail(MCV_EHIP, "lds limit");
+  const size_t lanes = (size_t)grid * 256;
+  float* sink = nullptr;
+  uint32_t* hits = nullptr;
+  hipError_t e = hipMalloc(&sink, lanes * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&hits, lanes * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    (void)hipFree(sink);
+    return hipfail(e, "probe buffers");
+  }
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  const float sp0 = std::sqrt((float)beam->E / 5.22703759e-6f);
+  double best = 1e30;
+  for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+    (void)hipEventRecord(a, nullptr);
+    switch (kind) {
+#define MCV_PROBE_CASE(K)                                                              \
+  case K:                                                                              \
+    e = launch_probe<K>(p, B, seed, arg, iters, sp0, grid, sink, hits, nullptr); \
+    break;
+      MCV_PROBE_CASE(PR_NULL)
+      MCV_PROBE_CASE(PR_RNG)
+      MCV_PROBE_CASE(PR_SOURCE)
+      MCV_PROBE_CASE(PR_SHAPE)
+      MCV_PROBE_CASE(PR_SEGMENT)
+      MCV_PROBE_CASE(PR_SPLIT)
+      MCV_PROBE_CASE(PR_KERNEL)
+      MCV_PROBE_CASE(PR_DETECT)
+#undef MCV_PROBE_CASE
+    }
+    (void)hipEventRecord(b, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (r > 0 && ms < best) best = ms;
+  }
+  std::vector<uint32_t> hh(lanes);
+  if (e == hipSuccess) e = hipMemcpy(hh.data(), hits, lanes * sizeof(uint32_t), hipMemcpyDeviceToHost);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipFree(sink);
+  (void)hipFree(hits);
+  if (e != hipSuccess) return hipfail(e, "probe run");
+  double tot = 0.0;
+  for (uint32_t v : hh) tot += v;
+  *ms_out = best;
+  *draws_per_call = tot / ((double)lanes * iters);
+  return MCV_OK;
+}
+
+}  // extern "C"

@@ -35,9 +35,14 @@
 #include "mcv_internal.h"
 
 // resident waves per SIMD the transport kernels are compiled for (register
-// budget 512 / N per lane)
+// budget 512 / N per lane): the single-scatterer, single-interval kernels
+// (short live ranges) run best with more waves in flight, the others with
+// fewer waves and no spills
 #ifndef MCV_WAVES_PER_EU
 #define MCV_WAVES_PER_EU 2
+#endif
+#ifndef MCV_WAVES_PER_EU_SIMPLE
+#define MCV_WAVES_PER_EU_SIMPLE 4
 #endif
 
 namespace mcv {
@@ -700,6 +705,62 @@ struct Slots {
   static __device__ __forceinline__ constexpr int scat(int j) { return TWO ? j >> 1 : j; }
 };
 
+// attenuation coefficients at speed sp, transmission exp(-mu L) and the
+// probability 1 - exp(-mu L) to interact within the interval length L
+__device__ __forceinline__ void segment_terms(const DevScat& S, const float* tab, float sp,
+                                              float L, Mu& mu, float& att, float& pint) {
+  mu = attenuation(S, tab, sp);
+  const float ml = mu.total * L;
+  att = expf(-ml);
+  pint = -expm1f(-ml);
+}
+
+__device__ __forceinline__ Out kernel_eval(const DevKernel& K, const DevScat& S,
+                                           const float* tab, const Pk& P, const float* u) {
+  switch (K.type) {
+    case K_ISO_EL: return k_iso(K, S, P, u);
+    case K_POWDER: return k_powder(K, S, tab, P, u);
+    case K_PHONON: return k_phonon(K, S, tab, P, u);
+    case K_SPINWAVE: return k_spinwave(K, P, u);
+    default: return k_sqe(K, tab, P, u);
+  }
+}
+
+// The child of a forced collision in one interval: free path x from the
+// truncated exponential, birth point on the ray (from the entry point put on
+// its surface), time, weight w mu_s/mu (1 - exp(-mu L)), and the kernel k
+// chosen with probability mu_k / mu_s (first k with u mu_s below the running
+// sum).  Returns k.
+__device__ __forceinline__ int split_child(const DevScat& S, const Mu& mu, float pint,
+                                           const Pk& P, float sx, float sy, float sz, float t0,
+                                           float slo, int code, const float* u, uint32_t lin,
+                                           Pk& C, float& x) {
+  x = -log1pf(-u[0] * pint) / mu.total;
+  float ex = sx + slo * P.dx, ey = sy + slo * P.dy, ez = sz + slo * P.dz;
+  snap_entry(S, code, P.dx, P.dy, P.dz, ex, ey, ez);
+  C.px = ex + x * P.dx;
+  C.py = ey + x * P.dy;
+  C.pz = ez + x * P.dz;
+  C.t = t0 + (slo + x) / P.sp;
+  C.w = P.w * (mu.scat / mu.total) * pint;
+  C.lin = lin;
+  const float target = u[1] * mu.scat;
+  float cum = 0.0f;
+  int kk = S.nk - 1;
+  bool found = false;
+#pragma unroll
+  for (int q = 0; q < kMaxKern; ++q) {
+    if (q < S.nk && !found) {
+      cum += mu.k[q];
+      if (target < cum) {
+        kk = q;
+        found = true;
+      }
+    }
+  }
+  return kk;
+}
+
 template <bool ADJ, int NSC, bool TWO>
 __device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, const AdjArgs& AA,
                                     Pk& P, Adj& pa, uint64_t id, uint64_t seed, Pk& nxt,
@@ -770,10 +831,9 @@ __device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, const A
     }
     const int si = SL::scat(j);
     const DevScat& S = PL.s[si];
-    const Mu mu = attenuation(S, tab, P.sp);
-    const float ml = mu.total * sl;
-    const float att = expf(-ml);
-    const float pint = -expm1f(-ml);  // probability to interact in the interval
+    Mu mu;
+    float att, pint;
+    segment_terms(S, tab, P.sp, sl, mu, att, pint);
     float dmu_abs = 0.0f, dmu_sig = 0.0f;
     if (ADJ) {
       if (si == AA.abs_s) dmu_abs = S.n100 * 2200.0f / P.sp;
@@ -784,41 +844,12 @@ __device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, const A
       float u[8];
       draw4(id, STREAM_SCATTER, lin, 0u, seed, u);
       draw4(id, STREAM_SCATTER, lin, 1u, seed, u + 4);
-      const float x = -log1pf(-u[0] * pint) / mu.total;
-      // birth point = entry point (on its surface) + x along the ray
-      float ex = sx + slo * P.dx, ey = sy + slo * P.dy, ez = sz + slo * P.dz;
-      snap_entry(S, (int)((codes >> (4 * j)) & 0xFu), P.dx, P.dy, P.dz, ex, ey, ez);
       Pk C;
-      C.px = ex + x * P.dx;
-      C.py = ey + x * P.dy;
-      C.pz = ez + x * P.dz;
-      C.t = t0 + (slo + x) / P.sp;
-      C.w = P.w * (mu.scat / mu.total) * pint;
-      C.lin = lin;
-      // kernel k with probability mu_k / mu_s: first k with u mu_s < sum_{i<=k} mu_i
-      const float target = u[1] * mu.scat;
-      float cum = 0.0f;
-      int kk = S.nk - 1;
-      bool found = false;
-#pragma unroll
-      for (int q = 0; q < kMaxKern; ++q) {
-        if (q < S.nk && !found) {
-          cum += mu.k[q];
-          if (target < cum) {
-            kk = q;
-            found = true;
-          }
-        }
-      }
+      float x;
+      const int kk = split_child(S, mu, pint, P, sx, sy, sz, t0, slo,
+                                 (int)((codes >> (4 * j)) & 0xFu), u, lin, C, x);
       const DevKernel& K = S.k[kk];
-      Out o;
-      switch (K.type) {
-        case K_ISO_EL: o = k_iso(K, S, P, u); break;
-        case K_POWDER: o = k_powder(K, S, tab, P, u); break;
-        case K_PHONON: o = k_phonon(K, S, tab, P, u); break;
-        case K_SPINWAVE: o = k_spinwave(K, P, u); break;
-        default: o = k_sqe(K, tab, P, u); break;
-      }
+      const Out o = kernel_eval(K, S, tab, P, u);
       C.dx = o.dx;
       C.dy = o.dy;
       C.dz = o.dz;
@@ -885,10 +916,94 @@ struct Sinks {
   unsigned long long* n_out;
 };
 
+// Histogram bins that many lanes of a wave hit at the same step (the
+// unscattered beam lands in one pixel and one time bin for every history)
+// would serialise on one global address.  Such lanes combine their values
+// with a wave sum, and the group's first lane adds the sum into a small
+// per-workgroup LDS cache (direct mapped on the bin index, a slot claimed by
+// compare-and-swap of its tag), which is flushed with one global atomic per
+// slot when the workgroup ends.  Lanes alone in their bin add directly.
+// Cache layout in LDS: double v[kHotSlots], double v2[kHotSlots],
+// int tag[kHotSlots] (-1 = free).
+constexpr int kHotSlots = 64;
+constexpr int kHotRounds = 2;
+constexpr int kHotWords = 5 * kHotSlots;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ void hot_init(double* hot, int nthreads, int tid) {
+  int* tag = reinterpret_cast<int*>(hot + 2 * kHotSlots);
+  for (int i = tid; i < kHotSlots; i += nthreads) {
+    hot[i] = 0.0;
+    hot[kHotSlots + i] = 0.0;
+    tag[i] = -1;
+  }
+}
+
+// adds the cache into the histogram and clears it (after a barrier)
+__device__ __forceinline__ void hot_flush(double* hot, double* hist, double* hist_w2,
+                                          int nthreads, int tid) {
+  int* tag = reinterpret_cast<int*>(hot + 2 * kHotSlots);
+  for (int i = tid; i < kHotSlots; i += nthreads) {
+    const int b = tag[i];
+    if (b >= 0) {
+      if (hist) unsafeAtomicAdd(hist + b, hot[i]);
+      if (hist_w2) unsafeAtomicAdd(hist_w2 + b, hot[kHotSlots + i]);
+    }
+    hot[i] = 0.0;
+    hot[kHotSlots + i] = 0.0;
+    tag[i] = -1;
+  }
+}
+
+// one histogram contribution per lane (bin < 0: none); whole wave active
+__device__ __forceinline__ void hist_add(double* hist, double* hist_w2, double* hot, int bin,
+                                         float value) {
+  int* tag = reinterpret_cast<int*>(hot + 2 * kHotSlots);
+  uint64_t pend = __ballot(bin >= 0);
+  bool done = bin < 0;
+  for (int r = 0; r < kHotRounds && pend != 0ull; ++r) {
+    const int lead = __ffsll((unsigned long long)pend) - 1;
+    const int lb = __builtin_amdgcn_readlane(bin, lead);
+    const bool mine = bin == lb;
+    const uint64_t grp = __ballot(mine);
+    pend &= ~grp;
+    if (__popcll(grp) < 2) continue;
+    const double d = mine ? (double)value : 0.0;
+    const double s = wave_sum(d);
+    const double s2 = hist_w2 ? wave_sum(d * d) : 0.0;
+    done = done || mine;
+    if ((int)__lane_id() == lead) {
+      const int slot = lb & (kHotSlots - 1);
+      int t = tag[slot];
+      if (t < 0) {
+        const int old = atomicCAS(&tag[slot], -1, lb);
+        t = old < 0 ? lb : old;
+      }
+      if (t == lb) {
+        atomicAdd(&hot[slot], s);
+        atomicAdd(&hot[kHotSlots + slot], s2);
+      } else {
+        if (hist) unsafeAtomicAdd(hist + lb, s);
+        if (hist_w2) unsafeAtomicAdd(hist_w2 + lb, s2);
+      }
+    }
+  }
+  if (!done) {
+    if (hist) unsafeAtomicAdd(hist + bin, (double)value);
+    if (hist_w2) unsafeAtomicAdd(hist_w2 + bin, (double)value * (double)value);
+  }
+}
+
 // One wave traces histories first+begin .. first+end-1: every lane walks
 // the packet tree of one history depth first and takes the next history of
 // the range as soon as it is done (ballot + prefix count), so lanes stay busy
-// until the range is exhausted.  Called with the whole wave active.
+// until the range is exhausted.  Called with the whole wave active.  `acc`
+// is the workgroup's LDS block: adjoint partials (MODE_ADJOINT) or the
+// histogram bin cache (otherwise).
 template <int MODE, int NSC, bool TWO>
 __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab, float* st,
                                             const DevBeam& beam, uint64_t seed, uint64_t first,
@@ -923,6 +1038,8 @@ __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab,
     }
     next += (uint64_t)__popcll(m);
     if (__ballot(has) == 0ull) break;
+    int hbin = -1;
+    float hval = 0.0f;
     if (has) {
       Pk nxt;
       nxt.lin = 0u;
@@ -946,9 +1063,8 @@ __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab,
             }
           }
         } else {
-          if (out.hist) unsafeAtomicAdd(out.hist + hh.bin, (double)hh.value);
-          if (out.hist_w2)
-            unsafeAtomicAdd(out.hist_w2 + hh.bin, (double)hh.value * (double)hh.value);
+          hbin = hh.bin;
+          hval = hh.value;
         }
       }
       if (MODE == MODE_TRACE) {
@@ -981,6 +1097,7 @@ __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab,
         has = false;
       }
     }
+    if (!ADJ) hist_add(out.hist, out.hist_w2, acc, hbin, hval);
   }
 }
 
@@ -1000,7 +1117,8 @@ __device__ __forceinline__ void stage_plan(DevPlan& PL, float* dyn, const DevPla
 // dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
 // per workgroup.
 template <int MODE, int NSC, bool TWO>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MCV_WAVES_PER_EU)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
+    NSC == 1 && !TWO ? MCV_WAVES_PER_EU_SIMPLE : MCV_WAVES_PER_EU)))
 transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
           uint64_t seed, uint64_t first, uint64_t n, uint64_t per_wave, Sinks out, AdjArgs AA) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
@@ -1010,11 +1128,14 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   const int nthreads = blockDim.x;
   stage_plan(PL, dyn, gplan, gtab, nthreads, tid);
   const int tab_words = (gplan->n_tables + 3) & ~3;
-  // adjoint partials: [nb] per DOS bin (sum of g), then sigma_abs, sigma, A, n_phonon
+  // adjoint partials: [nb] per DOS bin (sum of g), then sigma_abs, sigma, A,
+  // n_phonon; otherwise the histogram bin cache
   double* acc = reinterpret_cast<double*>(dyn + tab_words);
-  const int acc_words = ADJ ? 2 * (((AA.nb + 4) + 1) & ~1) : 0;
+  const int acc_words = ADJ ? 2 * (((AA.nb + 4) + 1) & ~1) : kHotWords;
   if (ADJ)
     for (int i = tid; i < AA.nb + 4; i += nthreads) acc[i] = 0.0;
+  else
+    hot_init(acc, nthreads, tid);
   __syncthreads();
   float* st = dyn + tab_words + acc_words;
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
@@ -1022,6 +1143,10 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   if (begin < n)  // uniform per wave
     trace_range<MODE, NSC, TWO>(PL, dyn, st, beam, seed, first, begin,
                       begin + per_wave < n ? begin + per_wave : n, out, AA, acc, nthreads, tid);
+  if (!ADJ) {
+    __syncthreads();
+    hot_flush(acc, out.hist, out.hist_w2, nthreads, tid);
+  }
   if (ADJ) {
     __syncthreads();
     for (int i = tid; i < AA.nb; i += nthreads)
@@ -1053,6 +1178,8 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
   const int wid = tid >> 6;
   int staged = -1;
   AdjArgs AA = {};
+  double* hot = reinterpret_cast<double*>(dyn);
+  hot_init(hot, nthreads, tid);
   for (;;) {
     if (tid == 0) s_chunk = atomicAdd(cursor, 1u);
     __syncthreads();
@@ -1061,19 +1188,39 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const BatchChunk ch = chunks[c];
     const BatchItem& it = items[ch.item];
     if ((int)ch.item != staged) {
-      stage_plan(PL, dyn, it.plan, it.tables, nthreads, tid);
+      stage_plan(PL, dyn + kHotWords, it.plan, it.tables, nthreads, tid);
       staged = (int)ch.item;
     }
     __syncthreads();
     const int tab_words = (PL.n_tables + 3) & ~3;
-    float* st = dyn + tab_words;
+    float* tab = dyn + kHotWords;
+    float* st = tab + tab_words;
     const uint64_t per = (ch.count + nwaves - 1) / nwaves;
     const uint64_t b = ch.first + per * wid;
     const uint64_t e = ch.first + ch.count;
     Sinks out = {it.hist, nullptr, nullptr, 0, nullptr};
-    if (b < e) trace_range<MODE_RUN, kMaxScat, true>(PL, dyn, st, it.beam, it.seed, it.id0, b,
-                                     b + per < e ? b + per : e, out, AA, nullptr, nthreads, tid);
+    const uint64_t ee = b + per < e ? b + per : e;
+    // the same specialisation as a plain launch of this plan, so that both
+    // evaluate identical arithmetic
+    const bool two = PL.smax > PL.nscat;
+#define MCV_BATCH_TRACE(NSC_, TWO_)                                                        \
+  trace_range<MODE_RUN, NSC_, TWO_>(PL, tab, st, it.beam, it.seed, it.id0, b, ee, out, AA, \
+                                    hot, nthreads, tid)
+    if (b < e) {
+      if (PL.nscat <= 1) {
+        if (two) MCV_BATCH_TRACE(1, true);
+        else MCV_BATCH_TRACE(1, false);
+      } else if (PL.nscat == 2) {
+        if (two) MCV_BATCH_TRACE(2, true);
+        else MCV_BATCH_TRACE(2, false);
+      } else {
+        if (two) MCV_BATCH_TRACE(4, true);
+        else MCV_BATCH_TRACE(4, false);
+      }
+    }
+#undef MCV_BATCH_TRACE
     __syncthreads();
+    hot_flush(hot, it.hist, nullptr, nthreads, tid);
   }
 }
 
@@ -1148,7 +1295,7 @@ __global__ void __launch_bounds__(256) loss_grad(const double* __restrict__ I,
 // ------------------------------------------------------------------ launch
 size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb) {
   const size_t tab = (size_t)((n_tables + 3) & ~3);
-  const size_t acc = adj_nb > 0 ? 2 * (size_t)(((adj_nb + 4) + 1) & ~1) : 0;
+  const size_t acc = adj_nb > 0 ? 2 * (size_t)(((adj_nb + 4) + 1) & ~1) : (size_t)dev::kHotWords;
   const size_t nf = kFields + (adj_nb > 0 ? kAdjFields : 0);
   return sizeof(float) * (tab + acc + (size_t)stack_cap * nf * block);
 }

@@ -1,0 +1,106 @@
+"""Measures the cost of each transport primitive on the GPU, in VALU
+lane-operation slots per call, for the benchmark workloads.
+
+cost = (t_probe - t_null) * VALU issue rate / calls, where the VALU issue
+rate is 256 CUs x 64 lanes x 2.4 GHz (one binary32 lane operation per lane
+per clock) and t_null is the same probe loop without the primitive.  A
+detector probe's own Philox draws are reported beside it so that they are
+not counted twice.  Writes a JSON file (default: primitive_costs.json next
+to this module).
+
+    python -m paper_1504_02776_amd.probe_costs [--out FILE]
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+VALU_PEAK = 256 * 64 * 2.4e9
+GRID = 2048          # workgroups of 256 lanes: 8 per CU
+ITERS = 2048         # calls per lane
+REPS = 3
+
+PR_NULL, PR_RNG, PR_SOURCE, PR_SHAPE, PR_SEGMENT, PR_SPLIT, PR_KERNEL, PR_DETECT = range(8)
+KERNEL_TYPES = {"iso_elastic": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5}
+
+
+def _bind():
+    from paper_1504_02776_amd import mcv
+    from paper_1504_02776_amd.build import PROBE_LIB
+    if not os.path.exists(PROBE_LIB):
+        raise RuntimeError(f"{PROBE_LIB} is missing: run paper_1504_02776_amd/build.py first")
+    mcv.LIB_PATH = PROBE_LIB
+    L = mcv.lib()
+    L.mcv_probe_time.argtypes = [C.c_void_p, C.POINTER(mcv.mcv_beam), C.c_uint64, C.c_int32,
+                                 C.c_int32, C.c_uint32, C.c_int32, C.c_int32,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.mcv_probe_time.restype = C.c_int
+    return mcv, L
+
+
+def probe_workload(cfg):
+    mcv, L = _bind()
+    plan = mcv.Plan(cfg)
+
+    def timed(kind, arg=0):
+        ms, draws = C.c_double(), C.c_double()
+        mcv.check(L.mcv_probe_time(plan.h, C.byref(plan.beam), cfg["seed"], kind, arg, ITERS,
+                                   GRID, REPS, C.byref(ms), C.byref(draws)))
+        return ms.value, draws.value
+
+    calls = GRID * 256 * ITERS
+    t_null, _ = timed(PR_NULL)
+
+    def cost(kind, arg=0):
+        t, d = timed(kind, arg)
+        return (t - t_null) * 1e-3 * VALU_PEAK / calls, d
+
+    out = {"null_ms": t_null, "calls": calls}
+    out["rng_block"] = cost(PR_RNG)[0]
+    out["source"] = cost(PR_SOURCE)[0]
+    nscat = len(cfg["scatterers"])
+    out["shape"] = [cost(PR_SHAPE, s)[0] for s in range(nscat)]
+    out["segment"] = [cost(PR_SEGMENT, s)[0] for s in range(nscat)]
+    out["split"] = [cost(PR_SPLIT, s)[0] for s in range(nscat)]
+    kern = {}
+    for s, sc in enumerate(cfg["scatterers"]):
+        for k, kd in enumerate(sc["kernels"]):
+            kern[f"{s}.{k}"] = {"type": KERNEL_TYPES[kd["type"]], "cost": cost(PR_KERNEL, 4 * s + k)[0]}
+    out["kernel"] = kern
+    c, d = cost(PR_DETECT)
+    out["detect"] = c
+    out["detect_draws_per_call"] = d
+    plan.close() if hasattr(plan, "close") else None
+    return out
+
+
+def main():
+    from paper_1504_02776_amd import workloads as W
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(HERE, "primitive_costs.json"))
+    args = ap.parse_args()
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    res = {"device": props.name, "arch": getattr(props, "gcnArchName", ""),
+           "cus": props.multi_processor_count, "valu_peak_lane_ops": VALU_PEAK,
+           "grid": GRID, "iters": ITERS, "unit": "VALU lane-op slots per call", "workloads": {}}
+    for name, cfg in [("powder", W.powder_config()), ("plate", W.plate_config()),
+                      ("crystal", W.crystal_config()), ("sqe", W.sqe_config())]:
+        res["workloads"][name] = probe_workload(cfg)
+        print(f"[probe] {name}: {json.dumps(res['workloads'][name])}", flush=True)
+    with open(args.out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(f"[probe] wrote {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()
