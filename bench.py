@@ -2,42 +2,47 @@
 
 One step = zero the binary64 I(pixel, tof) histogram + trace one batch of
 synthetic histories through source -> sample assembly -> detector -> histogram
-(every step of the hot path), inputs resident in HBM.  Default workload: the
-powder cylinder (1e7 histories, Bragg + one-phonon kernels, 3 orders, 1000
-tubes x 128 pixels x 1000 tof bins).
+(every step of the hot path), inputs resident in HBM.  The headline workload
+is the powder cylinder (1e7 histories, Bragg + one-phonon kernels, 3 orders,
+1000 tubes x 128 pixels x 1000 tof bins).  Beside it, unless --quick:
 
-Prints ONE JSON line (rank 0).  Only one GPU is supported by this build.
+- batched: 64 uneven simulations in one graph-captured persistent launch
+  (autotuned) against 64 sequential plain launches;
+- adjoint: seconds per gradient step (forward + loss/dL/dI + adjoint) on the
+  powder sample against 500 DOS bins, sigma_abs and sigma_inc, and its ratio
+  to the forward step;
+- plate at 1e9 histories and the crystal-with-can workload at 1e8.
+
+Roofline: the transport kernel is bound by VALU issue.  Its work per history
+is the sum over primitives of (count per history in the algorithm, from the
+oracle's instrumentation on the CPU sample) x (measured cost of the
+primitive in lane-operation slots on gfx950, from probe_costs.py).
+
+Prints ONE JSON line.  Only one GPU is supported by this build.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
+import platform
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# gfx950 VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one
-# binary32 lane operation per lane per clock (an FMA counts once)
+# gfx950 VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one binary32
+# lane operation per lane per clock (FMA counted once, no packed math)
 VALU_PEAK = 256 * 64 * 2.4e9
-
-# Lane-op slots per primitive, counted from the gfx950 code of the library's
-# own device functions (see the design notes for the derivation); the count
-# of each primitive per history comes from the oracle's instrumentation.
-COST = {
-    "rng_block": 96,      # Philox4x32-10: 10 rounds x (2 mul_lo + 2 mul_hi at 4 slots + 2 xor3) + 4 u->f
-    "segment": 60,        # attenuation + split bookkeeping per material interval
-    "split": 120,         # forced-collision point, kernel choice, child state
-    "kernel": {1: 40, 2: 110, 3: 140, 4: 130, 5: 90},
-    "shape_test": 45,     # one shape interval test incl. frame transform
-    "detect_sphere": 60,
-    "detect_tubes": 260,  # candidate lookup (atan2) + ~3 exact tube tests + absorption point
-    "hist_update": 8,
-}
+HBM_PEAK = 8e12
+COSTS = os.path.join(ROOT, "paper_1504_02776_amd", "primitive_costs.json")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "transport_powder_1e7_pmc.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1504_02776_amd", "csrc", f)
+                  for f in ("mcv_transport.hip", "mcv_internal.h")]
 
 
 def workload(name, n=None):
@@ -57,21 +62,49 @@ def workload(name, n=None):
     return cfg
 
 
-def work_per_history(tally, n, det_type):
-    per = tally.n_rng_blocks * COST["rng_block"] + tally.n_segments * COST["segment"]
-    per += tally.n_splits * COST["split"] + tally.n_shape_tests * COST["shape_test"]
-    per += sum(tally.n_kernel[t] * COST["kernel"].get(t, 0) for t in range(6))
-    per += tally.n_detect * (COST["detect_sphere"] if det_type == "sphere" else COST["detect_tubes"])
-    per += tally.n_hist_updates * COST["hist_update"]
-    return per / n
+def kernel_source_sha1():
+    h = hashlib.sha1()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def work_per_history(costs, tally, n, cfg):
+    """VALU lane-op slots per history: algorithm counts x primitive costs."""
+    c = costs
+    nscat = len(cfg["scatterers"])
+    mean = lambda v: sum(v) / len(v)
+    by_type = {}
+    for e in c["kernel"].values():
+        by_type.setdefault(e["type"], []).append(e["cost"])
+    w = n * (c["source"] - c["rng_block"])          # the source's own draw is in the RNG count
+    w += tally.n_rng_blocks * c["rng_block"]
+    w += tally.n_shape_tests / nscat * sum(c["shape"])
+    w += tally.n_segments * mean(c["segment"])
+    w += tally.n_splits * mean(c["split"])
+    w += sum(tally.n_kernel[t] * mean(by_type[t]) for t in by_type)
+    w += tally.n_detect * (c["detect"] - c["detect_draws_per_call"] * c["rng_block"])
+    return w / n
+
+
+def traffic_per_launch():
+    """HBM bytes per launch of the headline kernel from the committed PMC
+    summary, if it was taken on the current kernel sources."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    txt = open(PMC_SUMMARY).read()
+    m = re.search(r"kernel_sources_sha1:\s*([0-9a-f]{40})", txt)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_source_sha1():
+        return None
+    return float(t.group(1))
 
 
 def cpu_baseline(cfg, budget_s=12.0):
     """The oracle as it stands, one host core, on a bounded sample."""
     from oracle import oracle as O
     n = 200
-    elapsed = 0.0
-    tally = None
     while True:
         t0 = time.perf_counter()
         _, _, _, tally = O.run(cfg, n=n, records=False)
@@ -82,21 +115,133 @@ def cpu_baseline(cfg, budget_s=12.0):
     return n, elapsed, tally
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def timed(torch, stream, fn, reps):
+    """Median of `reps` event-timed calls of fn (ms), after one warm-up."""
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def bench_batched(torch, mcv, W, stream, reps):
+    cfgs = W.batch_configs(n_sims=64, seed=4)
+    plans = [mcv.Plan(c) for c in cfgs]
+    hists = [p.zeros() for p in plans]
+    total = sum(c["N"] for c in cfgs)
+    tuning, tune_ms, cached = mcv.autotune(plans, hists)
+    b = mcv.Batch(plans, hists, tuning)
+    t_graph = timed(torch, stream, lambda: b.run(stream), reps)
+
+    def sequential():
+        for p, h in zip(plans, hists):
+            h.zero_()
+            p.run(h, stream=stream)
+    t_seq = timed(torch, stream, sequential, reps)
+    b.close()
+    out = {"sims": len(cfgs), "histories": total,
+           "hist_bytes": int(sum(h.numel() for h in hists) * 8),
+           "graph_ms": t_graph, "sequential_ms": t_seq,
+           "histories_per_s_batched": total / (t_graph / 1e3),
+           "histories_per_s_sequential": total / (t_seq / 1e3),
+           "speedup": t_seq / t_graph,
+           "tuning": {"block_size": tuning.block_size, "chunk": tuning.chunk,
+                      "from_cache": bool(cached)}}
+    del plans, hists
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_adjoint(torch, mcv, W, stream, reps, forward_ms):
+    cfg = W.powder_config()
+    plan = mcv.Plan(cfg)
+    target = mcv.Plan(W.powder_config(dos_shift=1.05))
+    T = target.zeros()
+    target.run(T, seed=1, stream=stream)
+    torch.cuda.synchronize()
+    wgt = 1.0 / (T + 1e-3 * T.mean())
+    del target
+    I = plan.zeros()
+    dLdI = torch.empty_like(I)
+    loss = torch.zeros(1, dtype=torch.float64, device=I.device)
+    pm = mcv.param_map((0, 1), 0, (0, 1))
+    grad = torch.zeros(plan.nparams(pm), dtype=torch.float64, device=I.device)
+
+    def step():
+        I.zero_()
+        loss.zero_()
+        grad.zero_()
+        plan.run(I, stream=stream)
+        mcv.loss_grad(I, T, wgt, dLdI, loss, stream=stream)
+        plan.adjoint(pm, dLdI, grad, stream=stream)
+    t_step = timed(torch, stream, step, reps)
+    t_loss = timed(torch, stream, lambda: mcv.loss_grad(I, T, wgt, dLdI, loss, stream=stream),
+                   reps)
+    t_adj = timed(torch, stream, lambda: plan.adjoint(pm, dLdI, grad, stream=stream), reps)
+    nb = I.numel()
+    out = {"workload": f"powder cylinder 1e7, gradient w.r.t. {grad.numel()} parameters "
+                       "(500 DOS bins, sigma_abs, sigma_inc)",
+           "s_per_step": t_step / 1e3, "forward_s": forward_ms / 1e3,
+           "ratio_to_forward": t_step / forward_ms, "adjoint_kernel_ms": t_adj,
+           "loss_grad_ms": t_loss,
+           "loss_grad_GBps": 4 * 8 * nb / (t_loss / 1e3) / 1e9,
+           "loss_grad_hbm_frac": 4 * 8 * nb / (t_loss / 1e3) / HBM_PEAK}
+    del plan, I, dLdI, T, wgt
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_single(torch, mcv, cfg, stream, reps):
+    plan = mcv.Plan(cfg)
+    h = plan.zeros()
+
+    def step():
+        h.zero_()
+        plan.run(h, stream=stream)
+    t = timed(torch, stream, step, reps)
+    out = {"workload": cfg["name"], "histories": cfg["N"], "ms": t,
+           "histories_per_s": cfg["N"] / (t / 1e3)}
+    del plan, h
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="powder")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (PMC byte calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_1504_02776_amd import mcv
+    from paper_1504_02776_amd import mcv, workloads as W
 
     cfg = workload(args.workload, args.n)
     N = cfg["N"]
@@ -104,13 +249,11 @@ def main():
     hist = plan.zeros()
     stream = torch.cuda.current_stream()
 
-    def step():
+    for _ in range(args.warmup):
         hist.zero_()
         plan.run(hist, n=N, stream=stream)
-
-    for _ in range(args.warmup):
-        step()
     torch.cuda.synchronize()
+    # per-launch events on the stream the kernel runs on
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     t_begin = torch.cuda.Event(enable_timing=True)
@@ -132,6 +275,15 @@ def main():
     ms_per_step = total_ms / args.steps
     value = N * args.steps / (total_ms / 1e3)
     mcv.sync(stream)
+    del hist
+    plan.close()
+
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     out = {
         "metric": "neutron histories/sec at 1 GPU (plain vs batched) + adjoint s/step, vs oracle",
@@ -153,15 +305,35 @@ def main():
     }
     if not args.no_cpu_baseline:
         n_s, el, tally = cpu_baseline(cfg)
-        w_hist = work_per_history(tally, n_s, cfg["detector"]["type"])
-        achieved = N * w_hist / kern_avg_s
-        out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                           "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK, "traffic": None,
-                           "work_per_history": w_hist}
         out["cpu_baseline"] = {"value": n_s / el, "unit": "histories/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"{n_s} histories of the same workload, serial FP64 oracle"}
-    print(json.dumps(out))
+                               "kind": "oracle", "cpu": cpu_model(),
+                               "sample": f"first {n_s} histories of the same workload (seed "
+                                         f"{cfg['seed']}), serial binary64 oracle, {el:.1f} s"}
+        costs = None
+        if os.path.exists(COSTS):
+            with open(COSTS) as f:
+                costs = json.load(f)["workloads"].get(args.workload)
+        if costs is not None:
+            w_hist = work_per_history(costs, tally, n_s, cfg)
+            achieved = N * w_hist / kern_avg_s
+            tb = traffic_per_launch()
+            out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
+                               "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
+                               "frac": achieved / VALU_PEAK, "traffic": tb,
+                               "kernel": "transport (run mode)",
+                               "work_per_history": w_hist,
+                               "histories_per_launch": N}
+    if not args.quick:
+        reps = 3
+        fwd_ms = ms_per_step
+        out["batched"] = bench_batched(torch, mcv, W, stream, reps)
+        print(f"[bench] batched done", file=sys.stderr, flush=True)
+        out["adjoint"] = bench_adjoint(torch, mcv, W, stream, reps, fwd_ms)
+        print(f"[bench] adjoint done", file=sys.stderr, flush=True)
+        out["plate_scaled"] = bench_single(torch, mcv, W.plate_config(N=1_000_000_000), stream,
+                                           reps)
+        out["crystal"] = bench_single(torch, mcv, W.crystal_config(), stream, reps)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -30,7 +30,7 @@ ITERS = 2048         # calls per lane
 REPS = 3
 
 PR_NULL, PR_RNG, PR_SOURCE, PR_SHAPE, PR_SEGMENT, PR_SPLIT, PR_KERNEL, PR_DETECT = range(8)
-KERNEL_TYPES = {"iso_elastic": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5}
+KERNEL_TYPES = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5}
 
 
 def _bind():
