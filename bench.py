@@ -209,19 +209,42 @@ def bench_adjoint(torch, mcv, W, stream, reps, forward_ms):
     return out
 
 
-def bench_single(torch, mcv, cfg, stream, reps):
+def bench_single(torch, mcv, cfg, stream, reps, costs_name=None, cpu_budget_s=4.0):
+    """Plain launches of another workload; with its probe costs, also its
+    roofline fraction (work per history from a short oracle sample)."""
     plan = mcv.Plan(cfg)
     h = plan.zeros()
+    ev = []
 
     def step():
         h.zero_()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
         plan.run(h, stream=stream)
+        b.record(stream)
+        ev.append((a, b))
     t = timed(torch, stream, step, reps)
-    out = {"workload": cfg["name"], "histories": cfg["N"], "ms": t,
+    torch.cuda.synchronize()
+    kern = sorted(a.elapsed_time(b) for a, b in ev[1:])[len(ev[1:]) // 2]
+    out = {"workload": cfg["name"], "histories": cfg["N"], "ms": t, "kernel_ms": kern,
            "histories_per_s": cfg["N"] / (t / 1e3)}
     del plan, h
     torch.cuda.empty_cache()
+    costs = load_costs(costs_name) if costs_name else None
+    if costs is not None:
+        n_s, _, tally = cpu_baseline(cfg, budget_s=cpu_budget_s)
+        w = work_per_history(costs, tally, n_s, cfg)
+        out["roofline"] = {"bound": "alu", "work_per_history": w,
+                           "frac": cfg["N"] * w / (kern / 1e3) / VALU_PEAK}
     return out
+
+
+def load_costs(name):
+    if not os.path.exists(COSTS):
+        return None
+    with open(COSTS) as f:
+        return json.load(f)["workloads"].get(name)
 
 
 def main():
@@ -309,10 +332,7 @@ def main():
                                "kind": "oracle", "cpu": cpu_model(),
                                "sample": f"first {n_s} histories of the same workload (seed "
                                          f"{cfg['seed']}), serial binary64 oracle, {el:.1f} s"}
-        costs = None
-        if os.path.exists(COSTS):
-            with open(COSTS) as f:
-                costs = json.load(f)["workloads"].get(args.workload)
+        costs = load_costs(args.workload.split("-")[0])
         if costs is not None:
             w_hist = work_per_history(costs, tally, n_s, cfg)
             achieved = N * w_hist / kern_avg_s
@@ -331,8 +351,8 @@ def main():
         out["adjoint"] = bench_adjoint(torch, mcv, W, stream, reps, fwd_ms)
         print(f"[bench] adjoint done", file=sys.stderr, flush=True)
         out["plate_scaled"] = bench_single(torch, mcv, W.plate_config(N=1_000_000_000), stream,
-                                           reps)
-        out["crystal"] = bench_single(torch, mcv, W.crystal_config(), stream, reps)
+                                           reps, "plate")
+        out["crystal"] = bench_single(torch, mcv, W.crystal_config(), stream, reps, "crystal")
     print(json.dumps(out), flush=True)
 
 

@@ -31,8 +31,10 @@ hipError_t launch_adjoint_finalize(double* grad, const double* sums, const doubl
                                    double dnorm, int nb, hipStream_t stream);
 hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
                             double* dLdI, double* loss, int grid, hipStream_t stream);
-size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb);
+size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, int hot_n);
 size_t transport_static_lds();
+int transport_waves_per_eu(int nscat, int smax);
+int batch_waves_per_eu();
 hipError_t set_transport_lds_limit(size_t bytes);
 }  // namespace mcv
 
@@ -74,6 +76,17 @@ bool finite_all(const double* x, int n) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(x[i])) return false;
   return true;
+}
+
+// Slots of the LDS histogram bin cache: the most (kHotMin..kHotMax, a power
+// of two) that fit beside `base` bytes of LDS per workgroup when the
+// workgroups of `waves_per_simd` resident waves share a CU's 160 KiB.
+int hot_slots(size_t base, int block, int waves_per_simd) {
+  const int wgs = std::max(1, waves_per_simd * 4 * 64 / block);
+  const size_t budget = (size_t)160 * 1024 / (size_t)wgs;
+  int n = kHotMax;
+  while (n > kHotMin && base + 4 * (size_t)hot_words(n) > budget) n /= 2;
+  return n;
 }
 
 int intervals_of(const mcv_shape& s) { return s.type == MCV_SHAPE_ANNULUS ? 2 : 1; }
@@ -528,16 +541,20 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   p->nbins = mcv_detector_nbins(d);
   p->R = d->R;
 
-  // LDS: plan + tables + per-lane stack
-  size_t lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0);
+  // LDS: plan + tables + bin cache + per-lane stack
+  size_t lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, kHotMin);
   while (lds_dyn + transport_static_lds() > 160 * 1024 && block > 64) {
     block -= 64;
-    lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0);
+    lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, kHotMin);
   }
   if (lds_dyn + transport_static_lds() > 160 * 1024) {
     delete p;
     return fail(MCV_EUNSUPPORTED, "tables and packet stack exceed the 160 KiB of LDS");
   }
+  P.hot_n = hot_slots(transport_static_lds() + transport_lds_bytes(P.n_tables, P.stack_cap,
+                                                                    block, 0, 0),
+                      block, transport_waves_per_eu(P.nscat, P.smax));
+  P.hot_all = mcv_detector_nbins(d) <= kHotAllBins ? 1 : 0;
   p->block = block;
   p->device = device;
   p->scat = a->scat;
@@ -733,10 +750,10 @@ mcv_status adjoint_tables(mcv_plan p, const mcv_param_map* pm) {
   A.dnorm = -de / S;
   std::copy(key, key + 5, A.key);
   int block = p->block;
-  while (transport_lds_bytes(p->host.n_tables, p->host.stack_cap, block, nb) +
+  while (transport_lds_bytes(p->host.n_tables, p->host.stack_cap, block, nb, 0) +
                  transport_static_lds() > 160 * 1024 && block > 64)
     block -= 64;
-  if (transport_lds_bytes(p->host.n_tables, p->host.stack_cap, block, nb) +
+  if (transport_lds_bytes(p->host.n_tables, p->host.stack_cap, block, nb, 0) +
           transport_static_lds() > 160 * 1024)
     return fail(MCV_EUNSUPPORTED, "adjoint partials do not fit in LDS");
   A.block = block;
@@ -826,7 +843,7 @@ mcv_status mcv_loss_grad(const double* I, const double* T, const double* w, int6
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int64_t grid = (n / 2 + 255) / 256;
-  if (grid > (int64_t)cus * 16) grid = (int64_t)cus * 16;
+  if (grid > (int64_t)cus * 8) grid = (int64_t)cus * 8;
   if (grid < 1) grid = 1;
   hipError_t e = launch_loss_grad(I, T, w, n, dL_dI, loss, (int)grid, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(e, "loss launch");
@@ -839,7 +856,7 @@ mcv_status mcv_loss_grad(const double* I, const double* T, const double* w, int6
 namespace mcv {
 hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32_t n_chunks,
                         uint32_t* cursor, double* const* zero_ptrs, const uint64_t* zero_sizes,
-                        int n_zero, int grid, int block, size_t lds, int reset_grid,
+                        int n_zero, int grid, int block, size_t lds, int hot_n, int reset_grid,
                         hipStream_t stream);
 int batch_occupancy(int block, size_t lds);
 }  // namespace mcv
@@ -855,6 +872,7 @@ struct mcv_batch_s {
   int n_zero = 0;
   int grid = 0, block = 0;
   size_t lds = 0;
+  int hot_n = kHotMin;
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -936,13 +954,17 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
                    [](const auto& a, const auto& b) { return a.first > b.first; });
   std::vector<BatchChunk> cl;
   for (auto& c : hchunks) cl.push_back(c.second);
-  size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, 0);
+  size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, kHotMin);
   while (lds + transport_static_lds() + 64 > 160 * 1024 && block > 64) {
     block -= 64;
-    lds = transport_lds_bytes(n_tables_max, stack_max, block, 0);
+    lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, kHotMin);
   }
   if (lds + transport_static_lds() + 64 > 160 * 1024)
     return fail(MCV_EUNSUPPORTED, "batch tables and stacks exceed LDS");
+  const int hot_n = hot_slots(transport_static_lds() + 64 +
+                                  transport_lds_bytes(n_tables_max, stack_max, block, 0, 0),
+                              block, batch_waves_per_eu());
+  lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, hot_n);
 
   auto* b = new (std::nothrow) mcv_batch_s();
   if (!b) return fail(MCV_ENOMEM, "host allocation failed");
@@ -952,6 +974,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   b->device = device;
   b->block = block;
   b->lds = lds;
+  b->hot_n = hot_n;
   b->n_chunks = (uint32_t)cl.size();
   b->n_zero = (int)zp.size();
   int cus = 256;
@@ -982,7 +1005,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
       (e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
     hipError_t el = launch_batch(b->d_items, b->d_chunks, b->n_chunks, b->d_cursor,
                                  b->d_zero_ptrs, b->d_zero_sizes, b->n_zero, b->grid, b->block,
-                                 b->lds, cus * 4, b->capture);
+                                 b->lds, b->hot_n, cus * 4, b->capture);
     e = hipStreamEndCapture(b->capture, &b->graph);
     if (e == hipSuccess) e = el;
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);

@@ -85,6 +85,14 @@ struct DevDet {
   int32_t t_cols;    // offset of (x_c, z_c) per column
 };
 
+// LDS histogram bin cache of a workgroup: slots (a power of two) and size in
+// 32-bit words (double v[n], double v2[n], int tag[n])
+constexpr int kHotMin = 64;
+constexpr int kHotMax = 1024;
+constexpr int hot_words(int n) { return 5 * n; }
+// histograms up to this many bins send every update through the cache
+constexpr int64_t kHotAllBins = 1 << 18;
+
 // 16-byte aligned and sized: the kernels place their dynamic LDS (which holds
 // binary64 partial sums in adjoint mode) right after a copy of the plan, and
 // binary64 LDS accesses must be 8-byte aligned.
@@ -95,6 +103,8 @@ struct alignas(16) DevPlan {
   int32_t stack_cap;  // stacked packets per lane = (smax - 1) * K
   float min_prob;
   int32_t n_tables;   // binary32 words in the table blob
+  int32_t hot_n;      // slots of the LDS histogram bin cache (power of two)
+  int32_t hot_all;    // 1: every histogram update tries the cache (small histograms)
   DevScat s[kMaxScat];
   DevDet det;
 };

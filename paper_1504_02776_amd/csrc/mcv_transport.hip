@@ -554,9 +554,17 @@ __device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, c
   const float dyr = 1.25f * D.radius * fabsf(P.dy) / ra + 1e-4f;
   float best = kBig, best_hi = 0.0f, best_len = 0.0f;
   int best_tube = -1, best_row = 0;
+  // rows whose height range the ray can meet; the row index is data, so
+  // lanes in different rows share one pass of the tests below
+  uint32_t rows = 0u;
   for (int r = 0; r < D.nrows; ++r) {
     const float yc = D.row_y[r];
-    if (yR + dyr < yc - D.half_len || yR - dyr > yc + D.half_len) continue;
+    if (!(yR + dyr < yc - D.half_len || yR - dyr > yc + D.half_len)) rows |= 1u << r;
+  }
+  while (rows != 0u) {
+    const int r = __ffs(rows) - 1;
+    rows &= rows - 1u;
+    const float yc = D.row_y[r];
 #pragma unroll
     for (int dc = -1; dc <= 1; ++dc) {
       const int cc = col + dc;
@@ -919,50 +927,65 @@ struct Sinks {
 // Histogram bins that many lanes of a wave hit at the same step (the
 // unscattered beam lands in one pixel and one time bin for every history)
 // would serialise on one global address.  Such lanes combine their values
-// with a wave sum, and the group's first lane adds the sum into a small
-// per-workgroup LDS cache (direct mapped on the bin index, a slot claimed by
-// compare-and-swap of its tag), which is flushed with one global atomic per
-// slot when the workgroup ends.  Lanes alone in their bin add directly.
-// Cache layout in LDS: double v[kHotSlots], double v2[kHotSlots],
-// int tag[kHotSlots] (-1 = free).
-constexpr int kHotSlots = 64;
+// with a wave sum, and the group's first lane adds the sum into a
+// per-workgroup LDS cache of n slots (direct mapped on the bin index, a slot
+// claimed by compare-and-swap of its tag), which is flushed with one global
+// atomic per slot when the workgroup ends.  For small histograms (`all`)
+// lanes alone in their bin go through the cache as well, since a few hundred
+// bins then take most updates; otherwise they add directly.
+// Cache layout in LDS: double v[n], double v2[n], int tag[n] (-1 = free),
+// n a power of two.
 constexpr int kHotRounds = 2;
-constexpr int kHotWords = 5 * kHotSlots;
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
 
-__device__ __forceinline__ void hot_init(double* hot, int nthreads, int tid) {
-  int* tag = reinterpret_cast<int*>(hot + 2 * kHotSlots);
-  for (int i = tid; i < kHotSlots; i += nthreads) {
+__device__ __forceinline__ void hot_init(double* hot, int n, int nthreads, int tid) {
+  int* tag = reinterpret_cast<int*>(hot + 2 * n);
+  for (int i = tid; i < n; i += nthreads) {
     hot[i] = 0.0;
-    hot[kHotSlots + i] = 0.0;
+    hot[n + i] = 0.0;
     tag[i] = -1;
   }
 }
 
 // adds the cache into the histogram and clears it (after a barrier)
-__device__ __forceinline__ void hot_flush(double* hot, double* hist, double* hist_w2,
+__device__ __forceinline__ void hot_flush(double* hot, int n, double* hist, double* hist_w2,
                                           int nthreads, int tid) {
-  int* tag = reinterpret_cast<int*>(hot + 2 * kHotSlots);
-  for (int i = tid; i < kHotSlots; i += nthreads) {
+  int* tag = reinterpret_cast<int*>(hot + 2 * n);
+  for (int i = tid; i < n; i += nthreads) {
     const int b = tag[i];
     if (b >= 0) {
       if (hist) unsafeAtomicAdd(hist + b, hot[i]);
-      if (hist_w2) unsafeAtomicAdd(hist_w2 + b, hot[kHotSlots + i]);
+      if (hist_w2) unsafeAtomicAdd(hist_w2 + b, hot[n + i]);
     }
     hot[i] = 0.0;
-    hot[kHotSlots + i] = 0.0;
+    hot[n + i] = 0.0;
     tag[i] = -1;
   }
 }
 
+// adds (s, s2) for bin b into its cache slot if the slot holds b or is free;
+// false if another bin owns it
+__device__ __forceinline__ bool hot_put(double* hot, int n, int b, double s, double s2) {
+  int* tag = reinterpret_cast<int*>(hot + 2 * n);
+  const int slot = b & (n - 1);
+  int t = tag[slot];
+  if (t < 0) {
+    const int old = atomicCAS(&tag[slot], -1, b);
+    t = old < 0 ? b : old;
+  }
+  if (t != b) return false;
+  atomicAdd(&hot[slot], s);
+  atomicAdd(&hot[n + slot], s2);
+  return true;
+}
+
 // one histogram contribution per lane (bin < 0: none); whole wave active
-__device__ __forceinline__ void hist_add(double* hist, double* hist_w2, double* hot, int bin,
-                                         float value) {
-  int* tag = reinterpret_cast<int*>(hot + 2 * kHotSlots);
+__device__ __forceinline__ void hist_add(double* hist, double* hist_w2, double* hot, int n,
+                                         bool all, int bin, float value) {
   uint64_t pend = __ballot(bin >= 0);
   bool done = bin < 0;
   for (int r = 0; r < kHotRounds && pend != 0ull; ++r) {
@@ -976,25 +999,17 @@ __device__ __forceinline__ void hist_add(double* hist, double* hist_w2, double* 
     const double s = wave_sum(d);
     const double s2 = hist_w2 ? wave_sum(d * d) : 0.0;
     done = done || mine;
-    if ((int)__lane_id() == lead) {
-      const int slot = lb & (kHotSlots - 1);
-      int t = tag[slot];
-      if (t < 0) {
-        const int old = atomicCAS(&tag[slot], -1, lb);
-        t = old < 0 ? lb : old;
-      }
-      if (t == lb) {
-        atomicAdd(&hot[slot], s);
-        atomicAdd(&hot[kHotSlots + slot], s2);
-      } else {
-        if (hist) unsafeAtomicAdd(hist + lb, s);
-        if (hist_w2) unsafeAtomicAdd(hist_w2 + lb, s2);
-      }
+    if ((int)__lane_id() == lead && !hot_put(hot, n, lb, s, s2)) {
+      if (hist) unsafeAtomicAdd(hist + lb, s);
+      if (hist_w2) unsafeAtomicAdd(hist_w2 + lb, s2);
     }
   }
   if (!done) {
-    if (hist) unsafeAtomicAdd(hist + bin, (double)value);
-    if (hist_w2) unsafeAtomicAdd(hist_w2 + bin, (double)value * (double)value);
+    const double v = (double)value;
+    if (!(all && hot_put(hot, n, bin, v, v * v))) {
+      if (hist) unsafeAtomicAdd(hist + bin, v);
+      if (hist_w2) unsafeAtomicAdd(hist_w2 + bin, v * v);
+    }
   }
 }
 
@@ -1008,8 +1023,8 @@ template <int MODE, int NSC, bool TWO>
 __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab, float* st,
                                             const DevBeam& beam, uint64_t seed, uint64_t first,
                                             uint64_t begin, uint64_t end, const Sinks& out,
-                                            const AdjArgs& AA, double* acc, int nthreads,
-                                            int tid) {
+                                            const AdjArgs& AA, double* acc, int hot_n,
+                                            int nthreads, int tid) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
   const uint64_t lt = lanemask_lt();
   Pk cur;
@@ -1097,7 +1112,7 @@ __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab,
         has = false;
       }
     }
-    if (!ADJ) hist_add(out.hist, out.hist_w2, acc, hbin, hval);
+    if (!ADJ) hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
   }
 }
 
@@ -1131,21 +1146,23 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   // adjoint partials: [nb] per DOS bin (sum of g), then sigma_abs, sigma, A,
   // n_phonon; otherwise the histogram bin cache
   double* acc = reinterpret_cast<double*>(dyn + tab_words);
-  const int acc_words = ADJ ? 2 * (((AA.nb + 4) + 1) & ~1) : kHotWords;
+  const int hot_n = gplan->hot_n;
+  const int acc_words = ADJ ? 2 * (((AA.nb + 4) + 1) & ~1) : hot_words(hot_n);
   if (ADJ)
     for (int i = tid; i < AA.nb + 4; i += nthreads) acc[i] = 0.0;
   else
-    hot_init(acc, nthreads, tid);
+    hot_init(acc, hot_n, nthreads, tid);
   __syncthreads();
   float* st = dyn + tab_words + acc_words;
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
   if (begin < n)  // uniform per wave
     trace_range<MODE, NSC, TWO>(PL, dyn, st, beam, seed, first, begin,
-                      begin + per_wave < n ? begin + per_wave : n, out, AA, acc, nthreads, tid);
+                                begin + per_wave < n ? begin + per_wave : n, out, AA, acc, hot_n,
+                                nthreads, tid);
   if (!ADJ) {
     __syncthreads();
-    hot_flush(acc, out.hist, out.hist_w2, nthreads, tid);
+    hot_flush(acc, hot_n, out.hist, out.hist_w2, nthreads, tid);
   }
   if (ADJ) {
     __syncthreads();
@@ -1168,7 +1185,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
 // estimated cost, longest first.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MCV_WAVES_PER_EU)))
 batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restrict__ chunks,
-                 uint32_t n_chunks, uint32_t* __restrict__ cursor) {
+                 uint32_t n_chunks, uint32_t* __restrict__ cursor, int hot_n) {
   __shared__ DevPlan PL;
   __shared__ uint32_t s_chunk;
   extern __shared__ __align__(16) float dyn[];
@@ -1179,7 +1196,7 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
   int staged = -1;
   AdjArgs AA = {};
   double* hot = reinterpret_cast<double*>(dyn);
-  hot_init(hot, nthreads, tid);
+  hot_init(hot, hot_n, nthreads, tid);
   for (;;) {
     if (tid == 0) s_chunk = atomicAdd(cursor, 1u);
     __syncthreads();
@@ -1188,12 +1205,12 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const BatchChunk ch = chunks[c];
     const BatchItem& it = items[ch.item];
     if ((int)ch.item != staged) {
-      stage_plan(PL, dyn + kHotWords, it.plan, it.tables, nthreads, tid);
+      stage_plan(PL, dyn + hot_words(hot_n), it.plan, it.tables, nthreads, tid);
       staged = (int)ch.item;
     }
     __syncthreads();
     const int tab_words = (PL.n_tables + 3) & ~3;
-    float* tab = dyn + kHotWords;
+    float* tab = dyn + hot_words(hot_n);
     float* st = tab + tab_words;
     const uint64_t per = (ch.count + nwaves - 1) / nwaves;
     const uint64_t b = ch.first + per * wid;
@@ -1205,7 +1222,7 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const bool two = PL.smax > PL.nscat;
 #define MCV_BATCH_TRACE(NSC_, TWO_)                                                        \
   trace_range<MODE_RUN, NSC_, TWO_>(PL, tab, st, it.beam, it.seed, it.id0, b, ee, out, AA, \
-                                    hot, nthreads, tid)
+                                    hot, hot_n, nthreads, tid)
     if (b < e) {
       if (PL.nscat <= 1) {
         if (two) MCV_BATCH_TRACE(1, true);
@@ -1220,7 +1237,7 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     }
 #undef MCV_BATCH_TRACE
     __syncthreads();
-    hot_flush(hot, it.hist, nullptr, nthreads, tid);
+    hot_flush(hot, hot_n, it.hist, nullptr, nthreads, tid);
   }
 }
 
@@ -1254,7 +1271,21 @@ __global__ void zero2(double* p) {
 }
 
 // L = sum_b w_b (I_b - T_b)^2 and dL/dI_b = 2 w_b (I_b - T_b), streaming;
-// one atomic per workgroup for L
+// one atomic per workgroup for L.  Every element is touched once, so loads
+// and stores are non-temporal, and each thread issues the loads of two
+// 16-byte groups before it uses any of them.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double loss_pair(const dvec2 a, const dvec2 b, const dvec2 c,
+                                            dvec2* o) {
+  const double d0 = a.x - b.x, d1 = a.y - b.y;
+  dvec2 g;
+  g.x = 2.0 * c.x * d0;
+  g.y = 2.0 * c.y * d1;
+  __builtin_nontemporal_store(g, o);
+  return c.x * d0 * d0 + c.y * d1 * d1;
+}
+
 __global__ void __launch_bounds__(256) loss_grad(const double* __restrict__ I,
                                                  const double* __restrict__ T,
                                                  const double* __restrict__ w, int64_t n,
@@ -1262,23 +1293,31 @@ __global__ void __launch_bounds__(256) loss_grad(const double* __restrict__ I,
                                                  double* __restrict__ loss) {
   __shared__ double part[4];
   double acc = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 2;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; i < n; i += stride) {
-    if (i + 1 < n) {
-      const double2 a = *reinterpret_cast<const double2*>(I + i);
-      const double2 b = *reinterpret_cast<const double2*>(T + i);
-      const double2 c = *reinterpret_cast<const double2*>(w + i);
-      const double d0 = a.x - b.x, d1 = a.y - b.y;
-      double2 o;
-      o.x = 2.0 * c.x * d0;
-      o.y = 2.0 * c.y * d1;
-      *reinterpret_cast<double2*>(dLdI + i) = o;
-      acc += c.x * d0 * d0 + c.y * d1 * d1;
-    } else {
-      const double d0 = I[i] - T[i];
-      dLdI[i] = 2.0 * w[i] * d0;
-      acc += w[i] * d0 * d0;
-    }
+  const dvec2* I2 = reinterpret_cast<const dvec2*>(I);
+  const dvec2* T2 = reinterpret_cast<const dvec2*>(T);
+  const dvec2* w2 = reinterpret_cast<const dvec2*>(w);
+  dvec2* o2 = reinterpret_cast<dvec2*>(dLdI);
+  const int64_t n2 = n / 2;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; q + stride < n2; q += 2 * stride) {
+    const dvec2 a0 = __builtin_nontemporal_load(I2 + q);
+    const dvec2 b0 = __builtin_nontemporal_load(T2 + q);
+    const dvec2 c0 = __builtin_nontemporal_load(w2 + q);
+    const dvec2 a1 = __builtin_nontemporal_load(I2 + q + stride);
+    const dvec2 b1 = __builtin_nontemporal_load(T2 + q + stride);
+    const dvec2 c1 = __builtin_nontemporal_load(w2 + q + stride);
+    acc += loss_pair(a0, b0, c0, o2 + q);
+    acc += loss_pair(a1, b1, c1, o2 + q + stride);
+  }
+  if (q < n2)
+    acc += loss_pair(__builtin_nontemporal_load(I2 + q), __builtin_nontemporal_load(T2 + q),
+                     __builtin_nontemporal_load(w2 + q), o2 + q);
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t i = n - 1;
+    const double d0 = I[i] - T[i];
+    dLdI[i] = 2.0 * w[i] * d0;
+    acc += w[i] * d0 * d0;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
@@ -1293,9 +1332,10 @@ __global__ void __launch_bounds__(256) loss_grad(const double* __restrict__ I,
 }  // namespace dev
 
 // ------------------------------------------------------------------ launch
-size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb) {
+size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, int hot_n) {
   const size_t tab = (size_t)((n_tables + 3) & ~3);
-  const size_t acc = adj_nb > 0 ? 2 * (size_t)(((adj_nb + 4) + 1) & ~1) : (size_t)dev::kHotWords;
+  const size_t acc = adj_nb > 0 ? 2 * (size_t)(((adj_nb + 4) + 1) & ~1)
+                                : (size_t)hot_words(hot_n);
   const size_t nf = kFields + (adj_nb > 0 ? kAdjFields : 0);
   return sizeof(float) * (tab + acc + (size_t)stack_cap * nf * block);
 }
@@ -1343,7 +1383,8 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
   if (adj) AA = *adj;
   dev::Sinks out = {hist, hist_w2, rec, cap, n_out};
   const size_t lds =
-      transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, adj ? adj->nb : 0);
+      transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, adj ? adj->nb : 0,
+                          host_plan.hot_n);
   const int nsc = host_plan.nscat;
   const bool two = host_plan.smax > host_plan.nscat;
   if (adj) {
@@ -1362,12 +1403,12 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
 
 hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32_t n_chunks,
                         uint32_t* cursor, double* const* zero_ptrs, const uint64_t* zero_sizes,
-                        int n_zero, int grid, int block, size_t lds, int reset_grid,
+                        int n_zero, int grid, int block, size_t lds, int hot_n, int reset_grid,
                         hipStream_t stream) {
   hipLaunchKernelGGL(dev::batch_reset, dim3(reset_grid), dim3(256), 0, stream, zero_ptrs,
                      zero_sizes, n_zero, cursor);
   hipLaunchKernelGGL(dev::batch_persistent, dim3(grid), dim3(block), lds, stream, items, chunks,
-                     n_chunks, cursor);
+                     n_chunks, cursor, hot_n);
   return hipGetLastError();
 }
 
@@ -1393,6 +1434,12 @@ hipError_t launch_loss_grad(const double* I, const double* T, const double* w, i
 }
 
 size_t transport_static_lds() { return sizeof(DevPlan); }
+
+// resident waves per SIMD the transport kernel of a plan is compiled for
+int transport_waves_per_eu(int nscat, int smax) {
+  return nscat <= 1 && smax <= nscat ? MCV_WAVES_PER_EU_SIMPLE : MCV_WAVES_PER_EU;
+}
+int batch_waves_per_eu() { return MCV_WAVES_PER_EU; }
 
 namespace {
 template <int MODE>

@@ -15,7 +15,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmcv.so")
+# the in-tree build; MCV_LIBRARY names another build of the same sources
+LIB_PATH = os.environ.get("MCV_LIBRARY") or os.path.join(HERE, "libmcv.so")
 
 MCV_OK, MCV_EINVAL, MCV_EUNSUPPORTED, MCV_EOVERLAP, MCV_ENOMEM, MCV_ECAPACITY, MCV_EHIP = range(7)
 STATUS_NAMES = ["MCV_OK", "MCV_EINVAL", "MCV_EUNSUPPORTED", "MCV_EOVERLAP", "MCV_ENOMEM",
