@@ -83,7 +83,7 @@ inline double speed_from_k(double k) { return k * std::sqrt(kHbar2over2mn / kEpe
 // ----------------------------------------------------------------- ABI types
 // (mirrored by ctypes in oracle.py)
 enum { SHAPE_BOX = 1, SHAPE_CYLINDER = 2, SHAPE_ANNULUS = 3 };
-enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5 };
+enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5, K_MULTIPHONON = 6 };
 enum { BEAM_MONO = 1, BEAM_GAUSS = 2 };
 enum { DET_SPHERE = 1, DET_TUBES = 2 };
 enum { STREAM_SOURCE = 0, STREAM_SCATTER = 1, STREAM_DETECT = 2 };
@@ -110,11 +110,11 @@ struct OKernel {
   int32_t pad0;
   const double* d;   // d-spacings, A
   const double* F2;  // multiplicity * |F|^2 per cell, barn
-  // PHONON
+  // PHONON and MULTIPHONON
   double M;        // amu
   double T;        // K
   int32_t nbins;
-  int32_t pad1;
+  int32_t nmax;    // MULTIPHONON: highest phonon order N (orders 2..N)
   double emax;     // meV, DOS defined on [0, emax]
   const double* dos;  // raw (unnormalised) DOS values, one per bin
   // SPINWAVE
@@ -204,7 +204,7 @@ struct OTally {
       n_table_steps, n_hist_updates;
   uint64_t n_segments;      // material intervals crossed
   uint64_t n_splits;        // scattered children drawn
-  uint64_t n_kernel[6];     // kernel draws by type
+  uint64_t n_kernel[8];     // kernel draws by type
   uint64_t n_detect;        // detector calls (escaping packets)
   double w_start[8];        // sum of weight at the start of each flight, per order
   double w_scat[8];         // weight split off to scattering (before the kernel factor)
@@ -447,8 +447,12 @@ double surface_cos(const OShape& sh, V3 q, V3 d) {
 struct KernelInfo {
   // host-side derived data for one kernel (FP64)
   std::vector<double> d_sorted, f2_sorted;  // powder, by descending d
-  std::vector<double> cdf;                  // phonon, cumulative DOS (normalised)
+  std::vector<double> cdf;                  // phonon: cumulative DOS (normalised);
+                                            // multi-phonon: cumulative A_1 masses
   double de = 0.0;                          // phonon bin width
+  std::vector<double> a1;                   // multi-phonon: A_1 masses (see a1_masses)
+  double a1_sum = 0.0;                      // their sum before normalisation (1 exactly)
+  double dw_self = 0.0;                     // multi-phonon: 2W / Q^2 of its own DOS
 };
 
 struct ScatInfo {
@@ -472,6 +476,38 @@ double gamma0(const OKernel& k) {
 }
 
 double hbar2_over_2M(double M_amu) { return kHbar2over2mn * kNeutronMassAmu / M_amu; }
+
+// Multi-phonon scattering in the incoherent approximation (Supplement S4):
+// S(Q,E) = sum_{n=2..N} S_n(Q) A_n(E), S_n = (2W)^n/n! e^{-2W}, A_n = A_1 * A_{n-1}
+// (convolution), A_1 from the DOS.  With e the energy the neutron loses,
+// A_1(e) = Z(|e|)/(|e| gamma_0) (n(|e|) + 1) for e > 0 (one phonon created)
+// and Z(|e|)/(|e| gamma_0) n(|e|) for e < 0 (one absorbed), n the Bose
+// occupation: the paper's expression with its E = -e, which obeys detailed
+// balance A_1(-e) = exp(-e/kT) A_1(e).  On the DOS bins (midpoint rule, as
+// gamma_0) A_1 is a histogram with 2 nbins bins over [-emax, emax]: index j
+// < nbins covers e in [-(nbins - j) de, -(nbins - j - 1) de], index nbins + b
+// covers [b de, (b+1) de].  mass_j = Z_b de / (e_b gamma_0) x (n_b or n_b+1),
+// which sums to 1 (2n + 1 = coth(e/2kT)).
+void a1_masses(const OKernel& k, std::vector<double>& m, double* sum) {
+  const int nb = k.nbins;
+  const double de = k.emax / nb;
+  double area = 0.0;
+  for (int b = 0; b < nb; ++b) area += k.dos[b] * de;
+  const double g0 = gamma0(k);
+  const double kT = kBoltzmann * k.T;
+  m.assign(2 * nb, 0.0);
+  for (int b = 0; b < nb; ++b) {
+    const double e = (b + 0.5) * de;
+    const double z = k.dos[b] / area;
+    const double nbose = 1.0 / std::expm1(e / kT);
+    const double base = z * de / (e * g0);
+    m[nb + b] = base * (nbose + 1.0);  // neutron loses e
+    m[nb - 1 - b] = base * nbose;      // neutron gains e
+  }
+  double t = 0.0;
+  for (double x : m) t += x;
+  *sum = t;
+}
 
 void prepare(const OSetup& S, std::vector<ScatInfo>& info) {
   info.assign(S.nscat, ScatInfo());
@@ -499,6 +535,15 @@ void prepare(const OSetup& S, std::vector<ScatInfo>& info) {
           ki.cdf.push_back(c);
         }
         info[s].dw_coef = hbar2_over_2M(k.M) * gamma0(k);
+      } else if (k.type == K_MULTIPHONON) {
+        ki.de = k.emax / k.nbins;
+        a1_masses(k, ki.a1, &ki.a1_sum);
+        double c = 0.0;
+        for (double m : ki.a1) {
+          c += m / ki.a1_sum;
+          ki.cdf.push_back(c);
+        }
+        ki.dw_self = hbar2_over_2M(k.M) * gamma0(k);
       }
     }
   }
@@ -747,6 +792,60 @@ Scatter k_sqe(const OKernel& k, const Packet& P, const double* u, double* margin
     return r;
   }
   r.factor = (k_f / k_i) * k.sqe[iq * k.nE + ie] * (k.Emax - k.Emin);
+  return r;
+}
+
+// Multi-phonon kernel: order n uniform on 2..N (u2), direction isotropic
+// (u3, u4), energy loss e = sum of n independent draws from the A_1
+// histogram (bin by inverse CDF, position uniform within the bin), so that e
+// follows A_n exactly; weight (k_f/k_i) S_n(Q) (N - 1) against that proposal.
+// Phonon i takes words 2(i mod 2), 2(i mod 2)+1 of extra block i/2 (blocks
+// 2, 3, ... of the scattering stream).
+template <class Extra>
+Scatter k_multiphonon(const OKernel& k, const KernelInfo& ki, const Packet& P, const double* u,
+                      Extra extra, double* margin) {
+  Scatter r;
+  r.dq_sens = 0.0;
+  r.dw_q2 = 0.0;
+  r.dos_bin = -1;
+  const int N = k.nmax;
+  double fn = u[2] * (N - 1);
+  *margin = std::min(*margin, std::fabs(fn - std::nearbyint(fn)) / (kTauU * (N - 1)));
+  int n = 2 + std::min((int)std::floor(fn), N - 2);
+  r.dir = isotropic_direction(u[3], u[4]);
+  const int nb = k.nbins;
+  double e = 0.0;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < n; ++i) {
+    if ((i & 1) == 0) extra(i / 2, v);
+    const double ub = v[2 * (i & 1)], up = v[2 * (i & 1) + 1];
+    int j = 0;
+    for (; j < 2 * nb; ++j)
+      if (ub < ki.cdf[j]) break;
+    if (j == 2 * nb) j = 2 * nb - 1;
+    *margin = std::min(*margin, std::fabs(ub - ki.cdf[j]) / kTauU);
+    if (j > 0) *margin = std::min(*margin, std::fabs(ub - ki.cdf[j - 1]) / kTauU);
+    e += (j - nb + up) * ki.de;
+  }
+  const double Ei = kEperV2 * P.speed * P.speed;
+  const double Ef = Ei - e;
+  *margin = std::min(*margin, std::fabs(Ef) / (kTauRel * Ei));
+  r.speed = P.speed;
+  if (Ef <= 0.0) {
+    r.factor = 0.0;
+    return r;
+  }
+  const double k_i = k_from_speed(P.speed);
+  const double k_f = std::sqrt(Ef / kHbar2over2mn);
+  r.speed = speed_from_k(k_f);
+  const V3 Q = sub(scale(P.dir, k_i), scale(r.dir, k_f));
+  const double Q2 = dot(Q, Q);
+  const double w2 = ki.dw_self * Q2;  // 2W
+  double sn = std::exp(-w2);
+  for (int m = 1; m <= n; ++m) sn *= w2 / m;
+  r.factor = (k_f / k_i) * sn * (N - 1);
+  const double q = std::sqrt(Q2);
+  r.dq_sens = q > 0.0 ? std::fabs(2.0 * n / q - 2.0 * ki.dw_self * q) : 0.0;
   return r;
 }
 
@@ -1107,6 +1206,12 @@ struct Sim {
           case K_POWDER: r = k_powder(kp, sip.k[kk], sip, Pin, u, &child_margin); break;
           case K_PHONON: r = k_phonon(kp, sip.k[kk], sip, Pin, u, &child_margin); break;
           case K_SPINWAVE: r = k_spinwave(kp, Pin, u); break;
+          case K_MULTIPHONON:
+            r = k_multiphonon(
+                kp, sip.k[kk], Pin, u,
+                [&](int b, double v[4]) { rng.draw(id, STREAM_SCATTER, lin, 2u + b, v); },
+                &child_margin);
+            break;
           default: r = k_sqe(kp, Pin, u, &child_margin); break;
         }
         // evaluation-point Debye-Waller factor and DOS over the proposal's
@@ -1227,7 +1332,19 @@ struct Sim {
 
 extern "C" {
 
-int oracle_abi_version(void) { return 3; }
+int oracle_abi_version(void) { return 4; }
+
+// A_1 masses of a multi-phonon kernel (2 nbins values, index as in
+// a1_masses, before normalisation) and their sum; returns 0, or 2 if the
+// kernel is not a multi-phonon kernel.
+int oracle_multiphonon_a1(const OSetup* S, int s, int j, double* masses, double* sum) {
+  const OKernel& k = S->s[s].k[j];
+  if (k.type != K_MULTIPHONON) return 2;
+  std::vector<double> m;
+  a1_masses(k, m, sum);
+  for (size_t i = 0; i < m.size(); ++i) masses[i] = m[i];
+  return 0;
+}
 int oracle_sizeof_setup(void) { return (int)sizeof(OSetup); }
 int oracle_sizeof_record(void) { return (int)sizeof(ORecord); }
 int oracle_sizeof_tally(void) { return (int)sizeof(OTally); }
@@ -1270,11 +1387,12 @@ double oracle_dw_coef(const OSetup* S, int s) {
 double oracle_gamma0(const OKernel* k) { return gamma0(*k); }
 
 // One kernel draw for an incident packet with speed v along dir, with the
-// eight uniforms u[0..7] (u[2..7] are the kernel's).  out = {vx,vy,vz,factor}.
-void oracle_kernel_sample(const OSetup* S, int s, int j, const double dir[3], double speed,
-                          const double u[8], double out[4]) {
-  std::vector<ScatInfo> info;
-  prepare(*S, info);
+// eight uniforms u[0..7] (u[2..7] are the kernel's) and, for the
+// multi-phonon kernel, the uniforms of its extra blocks (4 per block, up to
+// 4 blocks; may be null otherwise).  out = {vx,vy,vz,factor}.
+void kernel_sample_prepared(const OSetup* S, const std::vector<ScatInfo>& info, int s, int j,
+                            const double dir[3], double speed, const double u[8],
+                            const double* extra, double out[4]) {
   Packet P{};
   P.dir = {dir[0], dir[1], dir[2]};
   P.speed = speed;
@@ -1286,12 +1404,37 @@ void oracle_kernel_sample(const OSetup* S, int s, int j, const double dir[3], do
     case K_POWDER: r = k_powder(k, info[s].k[j], info[s], P, u, &m); break;
     case K_PHONON: r = k_phonon(k, info[s].k[j], info[s], P, u, &m); break;
     case K_SPINWAVE: r = k_spinwave(k, P, u); break;
+    case K_MULTIPHONON:
+      r = k_multiphonon(k, info[s].k[j], P, u,
+                        [&](int b, double v[4]) {
+                          for (int i = 0; i < 4; ++i) v[i] = extra[4 * b + i];
+                        },
+                        &m);
+      break;
     default: r = k_sqe(k, P, u, &m); break;
   }
   out[0] = r.dir.x * r.speed;
   out[1] = r.dir.y * r.speed;
   out[2] = r.dir.z * r.speed;
   out[3] = r.factor;
+}
+
+void oracle_kernel_sample(const OSetup* S, int s, int j, const double dir[3], double speed,
+                          const double u[8], const double* extra, double out[4]) {
+  std::vector<ScatInfo> info;
+  prepare(*S, info);
+  kernel_sample_prepared(S, info, s, j, dir, speed, u, extra, out);
+}
+
+// n draws with the same incident state: u is n x 8, extra n x 16 (or null),
+// out n x 4.
+void oracle_kernel_sample_many(const OSetup* S, int s, int j, const double dir[3], double speed,
+                               int64_t n, const double* u, const double* extra, double* out) {
+  std::vector<ScatInfo> info;
+  prepare(*S, info);
+  for (int64_t i = 0; i < n; ++i)
+    kernel_sample_prepared(S, info, s, j, dir, speed, u + 8 * i,
+                           extra ? extra + 16 * i : nullptr, out + 4 * i);
 }
 
 // Full transport of histories [first, first+n).  hist (and hist_w2 if not

@@ -40,7 +40,7 @@ class OKernel(C.Structure):
                 ("v0", C.c_double), ("nrefl", C.c_int32), ("pad0", C.c_int32),
                 ("d", C.POINTER(C.c_double)), ("F2", C.POINTER(C.c_double)),
                 ("M", C.c_double), ("T", C.c_double), ("nbins", C.c_int32),
-                ("pad1", C.c_int32), ("emax", C.c_double), ("dos", C.POINTER(C.c_double)),
+                ("nmax", C.c_int32), ("emax", C.c_double), ("dos", C.POINTER(C.c_double)),
                 ("J", C.c_double), ("S", C.c_double), ("a", C.c_double), ("gamma", C.c_double),
                 ("crot", C.c_double * 9), ("nQ", C.c_int32), ("nE", C.c_int32),
                 ("Qmax", C.c_double), ("Emin", C.c_double), ("Emax", C.c_double),
@@ -85,7 +85,7 @@ class OTally(C.Structure):
                 ("n_shape_tests", C.c_uint64), ("n_tube_tests", C.c_uint64),
                 ("n_table_steps", C.c_uint64), ("n_hist_updates", C.c_uint64),
                 ("n_segments", C.c_uint64), ("n_splits", C.c_uint64),
-                ("n_kernel", C.c_uint64 * 6), ("n_detect", C.c_uint64),
+                ("n_kernel", C.c_uint64 * 8), ("n_detect", C.c_uint64),
                 ("w_start", C.c_double * 8), ("w_scat", C.c_double * 8),
                 ("w_abs", C.c_double * 8), ("w_lost", C.c_double * 8)]
 
@@ -100,7 +100,7 @@ RECORD_DTYPE = np.dtype([
     ("ddir", np.float64), ("dpos", np.float64), ("dtime", np.float64)])
 
 SHAPES = {"box": 1, "cylinder": 2, "annulus": 3}
-KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5}
+KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6}
 
 _lib = None
 
@@ -135,7 +135,13 @@ def lib():
         L.oracle_gamma0.restype = C.c_double
         L.oracle_gamma0.argtypes = [C.POINTER(OKernel)]
         L.oracle_kernel_sample.argtypes = [C.POINTER(OSetup), C.c_int, C.c_int, C.c_void_p,
-                                           C.c_double, C.c_void_p, C.c_void_p]
+                                           C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oracle_kernel_sample_many.argtypes = [C.POINTER(OSetup), C.c_int, C.c_int, C.c_void_p,
+                                                C.c_double, C.c_int64, C.c_void_p, C.c_void_p,
+                                                C.c_void_p]
+        L.oracle_multiphonon_a1.restype = C.c_int
+        L.oracle_multiphonon_a1.argtypes = [C.POINTER(OSetup), C.c_int, C.c_int, C.c_void_p,
+                                            C.POINTER(C.c_double)]
         assert L.oracle_sizeof_setup() == C.sizeof(OSetup), "OSetup layout mismatch"
         assert L.oracle_sizeof_record() == RECORD_DTYPE.itemsize, "ORecord layout mismatch"
         assert L.oracle_sizeof_tally() == C.sizeof(OTally), "OTally layout mismatch"
@@ -200,10 +206,11 @@ class Setup:
             o.nrefl = len(k["d"])
             o.d = self._arr(k["d"])
             o.F2 = self._arr(k["F2"])
-        elif t == "phonon":
+        elif t in ("phonon", "multiphonon"):
             o.M, o.T, o.emax = k["M"], k["T"], k["emax"]
             o.nbins = len(k["dos"])
             o.dos = self._arr(k["dos"])
+            o.nmax = int(k.get("nmax", 0))
         elif t == "spinwave":
             o.J, o.S, o.a, o.gamma = k["J"], k["S"], k["a"], k["gamma"]
             o.crot[:] = k["crot"]
@@ -335,12 +342,41 @@ def gamma0(kernel_dict):
     return lib().oracle_gamma0(C.byref(st.S.s[0].k[0]))
 
 
-def kernel_sample(cfg, s, j, direction, speed, u):
-    """One kernel draw; returns (v_out[3], weight factor)."""
+def kernel_sample(cfg, s, j, direction, speed, u, extra=None):
+    """One kernel draw; returns (v_out[3], weight factor).  `extra`: the
+    uniforms of the multi-phonon kernel's extra blocks (16)."""
     st = Setup(cfg)
     D = np.ascontiguousarray(direction, dtype=np.float64)
     U = np.ascontiguousarray(u, dtype=np.float64)
+    X = None if extra is None else np.ascontiguousarray(extra, dtype=np.float64)
     out = np.zeros(4)
     lib().oracle_kernel_sample(C.byref(st.S), s, j, D.ctypes.data, float(speed),
-                               U.ctypes.data, out.ctypes.data)
+                               U.ctypes.data, None if X is None else X.ctypes.data,
+                               out.ctypes.data)
     return out[:3], out[3]
+
+
+def kernel_samples(cfg, s, j, direction, speed, U, extra=None):
+    """Many kernel draws with one incident state: U is (n, 8), extra (n, 16)
+    or None; returns (v_out (n, 3), factor (n,))."""
+    st = Setup(cfg)
+    D = np.ascontiguousarray(direction, dtype=np.float64)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    X = None if extra is None else np.ascontiguousarray(extra, dtype=np.float64)
+    n = U.shape[0]
+    out = np.zeros((n, 4))
+    lib().oracle_kernel_sample_many(C.byref(st.S), s, j, D.ctypes.data, float(speed), n,
+                                    U.ctypes.data, None if X is None else X.ctypes.data,
+                                    out.ctypes.data)
+    return out[:, :3], out[:, 3]
+
+
+def multiphonon_a1(cfg, s, j):
+    """A_1 masses of a multi-phonon kernel (before normalisation) and their sum."""
+    st = Setup(cfg)
+    nb = len(cfg["scatterers"][s]["kernels"][j]["dos"])
+    m = np.zeros(2 * nb)
+    tot = C.c_double()
+    rc = lib().oracle_multiphonon_a1(C.byref(st.S), s, j, m.ctypes.data, C.byref(tot))
+    assert rc == 0, "not a multi-phonon kernel"
+    return m, tot.value

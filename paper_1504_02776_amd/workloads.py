@@ -74,6 +74,12 @@ def phonon(sigma, M, T, emax, dos, dw=1):
             "emax": float(emax), "dos": _f32(dos), "dw": int(dw)}
 
 
+def multiphonon(sigma, M, T, emax, dos, nmax=4):
+    """Incoherent multi-phonon kernel (orders 2..nmax) from a DOS."""
+    return {"type": "multiphonon", "sigma": float(sigma), "M": float(M), "T": float(T),
+            "emax": float(emax), "dos": _f32(dos), "nmax": int(nmax), "dw": 0}
+
+
 def spinwave(sigma, J, S, a, gamma, crot=IDENTITY):
     return {"type": "spinwave", "sigma": float(sigma), "J": float(J), "S": float(S),
             "a": float(a), "gamma": float(gamma), "crot": list(crot), "dw": 0}
@@ -193,6 +199,17 @@ def powder_config(N=10_000_000, seed=0, dos_shift=1.0):
         "detector": tube_detector(4, 250, 128, 1000, lo, hi),
         "K": 3, "min_prob": 0.0, "N": N, "seed": seed,
     }
+
+
+def powder_mp_config(N=10_000_000, seed=0):
+    """The powder cylinder with a third kernel: incoherent multi-phonon
+    scattering (orders 2..4) from the same DOS."""
+    cfg = powder_config(N=N, seed=seed)
+    k = cfg["scatterers"][0]["kernels"]
+    ph = k[1]
+    k.append(multiphonon(1.0, ph["M"], ph["T"], ph["emax"], ph["dos"], nmax=4))
+    cfg["name"] = "powder-multiphonon-tubes"
+    return cfg
 
 
 def crystal_config(N=100_000_000, seed=0):
