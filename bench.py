@@ -11,7 +11,8 @@ is the powder cylinder (1e7 histories, Bragg + one-phonon kernels, 3 orders,
 - adjoint: seconds per gradient step (forward + loss/dL/dI + adjoint) on the
   powder sample against 500 DOS bins, sigma_abs and sigma_inc, and its ratio
   to the forward step;
-- plate at 1e9 histories and the crystal-with-can workload at 1e8.
+- plate at 1e9 histories, the crystal-with-can workload at 1e8, and the
+  powder with a multi-phonon kernel at 1e7.
 
 Roofline: the transport kernel is bound by VALU issue.  Its work per history
 is the sum over primitives of (count per history in the algorithm, from the
@@ -55,6 +56,8 @@ def workload(name, n=None):
         cfg = W.plate_config(N=1_000_000_000)
     elif name == "crystal":
         cfg = W.crystal_config()
+    elif name == "powder-mp":
+        cfg = W.powder_mp_config()
     else:
         raise SystemExit(f"unknown workload {name}")
     if n is not None:
@@ -332,7 +335,8 @@ def main():
                                "kind": "oracle", "cpu": cpu_model(),
                                "sample": f"first {n_s} histories of the same workload (seed "
                                          f"{cfg['seed']}), serial binary64 oracle, {el:.1f} s"}
-        costs = load_costs(args.workload.split("-")[0])
+        costs = load_costs({"powder-mp": "powder_mp"}.get(args.workload,
+                                                          args.workload.split("-")[0]))
         if costs is not None:
             w_hist = work_per_history(costs, tally, n_s, cfg)
             achieved = N * w_hist / kern_avg_s
@@ -353,6 +357,8 @@ def main():
         out["plate_scaled"] = bench_single(torch, mcv, W.plate_config(N=1_000_000_000), stream,
                                            reps, "plate")
         out["crystal"] = bench_single(torch, mcv, W.crystal_config(), stream, reps, "crystal")
+        out["powder_multiphonon"] = bench_single(torch, mcv, W.powder_mp_config(), stream, reps,
+                                                 "powder_mp")
     print(json.dumps(out), flush=True)
 
 

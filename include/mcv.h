@@ -84,7 +84,8 @@ enum {
   MCV_K_POWDER = 2,    /* coherent elastic powder, Debye-Scherrer cones (S4)  */
   MCV_K_PHONON = 3,    /* incoherent one-phonon from a DOS (S4)               */
   MCV_K_SPINWAVE = 4,  /* dispersion surface E(Q), S(Q) = 1, Lorentzian (S4)  */
-  MCV_K_SQE = 5        /* tabulated isotropic S(Q,E) (Sec. 2.4.2)             */
+  MCV_K_SQE = 5,       /* tabulated isotropic S(Q,E) (Sec. 2.4.2)             */
+  MCV_K_MULTIPHONON = 6 /* incoherent multi-phonon, orders 2..N (S4)          */
 };
 
 /* One scattering kernel.  Only the fields of `type` are read.
@@ -99,6 +100,14 @@ enum {
  *   PHONON: mass M_amu, temperature T_K (> 0), nbins DOS values dos[] (raw,
  *     >= 0, normalised by the library) on bins of width emax/nbins over
  *     [0, emax].
+ *   MULTIPHONON: the same DOS fields, and max_phonons = N (2..8): S(Q,E) =
+ *     sum_{n=2..N} (2W)^n/n! e^{-2W} A_n(E) with A_n the n-fold convolution
+ *     of the one-phonon spectrum A_1 (Supplement S4, incoherent
+ *     approximation); 2W and A_1 from this kernel's own DOS, M and T.  Its
+ *     Debye-Waller factor is part of S_n, so dw must be 0.  Draws beyond the
+ *     eight uniforms of a split come from blocks 2, 3, ... of the packet's
+ *     scattering stream.  The adjoint does not differentiate through this
+ *     kernel's DOS.
  *   SPINWAVE: E(Q) = 4 J S (3 - sum_a cos(Q_a a)), Q in the crystal frame
  *     crot * Q_lab; gamma = Lorentzian HWHM.
  *   SQE: S(Q,E) on nQ x nE cells over [0, Qmax] x [Emin, Emax], row major
@@ -115,7 +124,7 @@ typedef struct {
   double M_amu;
   double T_K;
   int32_t nbins;
-  int32_t reserved1;
+  int32_t max_phonons;
   double emax;
   const double* dos;
   double J, S, a, gamma;

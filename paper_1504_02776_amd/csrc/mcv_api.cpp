@@ -199,6 +199,20 @@ mcv_status check_kernel(const mcv_kernel& k) {
       if (!(s > 0.0)) return fail(MCV_EINVAL, "DOS must have positive area");
       return MCV_OK;
     }
+    case MCV_K_MULTIPHONON: {
+      if (!(k.sigma_b >= 0.0) || !(k.M_amu > 0.0) || !(k.T_K > 0.0) || !(k.emax > 0.0) ||
+          k.nbins < 1 || k.nbins > 4096 || !k.dos || k.max_phonons < 2 || k.max_phonons > 8)
+        return fail(MCV_EINVAL,
+                    "multi-phonon kernel needs M > 0, T > 0, emax > 0, 1..4096 bins, N in 2..8");
+      if (k.dw) return fail(MCV_EUNSUPPORTED, "the multi-phonon kernel carries its own Debye-Waller factor");
+      double s = 0.0;
+      for (int i = 0; i < k.nbins; ++i) {
+        if (!(k.dos[i] >= 0.0) || !std::isfinite(k.dos[i])) return fail(MCV_EINVAL, "DOS values must be >= 0");
+        s += k.dos[i];
+      }
+      if (!(s > 0.0)) return fail(MCV_EINVAL, "DOS must have positive area");
+      return MCV_OK;
+    }
     case MCV_K_SPINWAVE:
       if (!(k.sigma_b >= 0.0) || !(k.gamma > 0.0) || !(k.a > 0.0) || !finite_all(k.crot, 9))
         return fail(MCV_EINVAL, "spin-wave kernel needs gamma > 0 and a > 0");
@@ -310,7 +324,7 @@ mcv_status mcv_assembly_add(mcv_assembly a, const mcv_shape* shape, const mcv_ma
     if (k.type == MCV_K_POWDER) {
       kc.d.assign(k.d, k.d + k.nrefl);
       kc.F2.assign(k.F2, k.F2 + k.nrefl);
-    } else if (k.type == MCV_K_PHONON) {
+    } else if (k.type == MCV_K_PHONON || k.type == MCV_K_MULTIPHONON) {
       kc.dos.assign(k.dos, k.dos + k.nbins);
     } else if (k.type == MCV_K_SQE) {
       kc.sqe.assign(k.sqe, k.sqe + (size_t)k.nQ * k.nE);
@@ -477,6 +491,44 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
         K.de = (float)(k.emax / k.nbins);
         K.kT = (float)(kBoltzmann * k.T_K);
         K.h2m = (float)(kHbar2over2mn * kNeutronMassAmu / k.M_amu);
+      } else if (k.type == MCV_K_MULTIPHONON) {
+        // One-phonon spectrum A_1 on 2 nbins bins over [-emax, emax] of the
+        // energy the neutron loses (bin nbins + b: loss in [b de, (b+1) de];
+        // bin nbins - 1 - b: the same gain), midpoint rule on the DOS bins:
+        // Z_b de / (e_b gamma_0) times n(e_b) + 1 for a loss and n(e_b) for
+        // a gain, n the Bose occupation; the masses sum to 1 because
+        // 2n + 1 = coth(e/2kT).  Stored as a cumulative table.
+        const int nb = k.nbins;
+        const double de = k.emax / nb, kT = kBoltzmann * k.T_K;
+        double area = 0.0;
+        for (double v : kc.dos) area += v * de;
+        double g0 = 0.0;
+        for (int b = 0; b < nb; ++b) {
+          const double e = (b + 0.5) * de;
+          g0 += kc.dos[b] / area / e * de / std::tanh(e / (2.0 * kT));
+        }
+        std::vector<double> mass(2 * (size_t)nb);
+        for (int b = 0; b < nb; ++b) {
+          const double e = (b + 0.5) * de;
+          const double occ = 1.0 / std::expm1(e / kT);
+          const double base = kc.dos[b] / area * de / (e * g0);
+          mass[nb + b] = base * (occ + 1.0);
+          mass[nb - 1 - b] = base * occ;
+        }
+        double tot = 0.0;
+        for (double v : mass) tot += v;
+        K.t_cdf = (int)T.size();
+        double acc = 0.0;
+        for (int j = 0; j < 2 * nb; ++j) {
+          acc += mass[j];
+          T.push_back(j == 2 * nb - 1 ? 1.0f : (float)(acc / tot));
+        }
+        K.nbins = nb;
+        K.de = (float)de;
+        K.kT = (float)kT;
+        K.h2m = (float)(kHbar2over2mn * kNeutronMassAmu / k.M_amu);
+        K.dw_self = (float)(kHbar2over2mn * kNeutronMassAmu / k.M_amu * g0);
+        K.nmax = k.max_phonons;
       } else if (k.type == MCV_K_SPINWAVE) {
         K.j4s = (float)(4.0 * k.J * k.S);
         K.wmax = (float)(24.0 * k.J * k.S);

@@ -20,7 +20,7 @@ constexpr int kMaxOrders = 7;
 constexpr int kFields = 10;              // words per stacked packet
 
 enum { SHAPE_BOX = 1, SHAPE_CYLINDER = 2, SHAPE_ANNULUS = 3 };
-enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5 };
+enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5, K_MULTIPHONON = 6 };
 enum { DET_SPHERE = 1, DET_TUBES = 2 };
 enum { STREAM_SOURCE = 0u, STREAM_SCATTER = 1u, STREAM_DETECT = 2u };
 
@@ -33,12 +33,15 @@ struct DevKernel {
   int32_t t_d;       // offset of d-spacings sorted by descending d
   int32_t t_pref;    // offset of prefix sums of d |F|^2 in that order
   int32_t nrefl;
-  // PHONON
+  // PHONON (and MULTIPHONON: t_cdf = cumulative A_1 over 2 nbins bins)
   int32_t t_cdf;     // offset of the normalised cumulative DOS
   int32_t nbins;
   float de;          // bin width, meV
   float kT;          // meV
   float h2m;         // hbar^2 / 2M, meV A^2
+  // MULTIPHONON
+  float dw_self;     // 2W / Q^2 from the kernel's own DOS, A^2
+  int32_t nmax;      // highest order N
   // SPINWAVE
   float j4s;         // 4 J S
   float a;           // lattice constant

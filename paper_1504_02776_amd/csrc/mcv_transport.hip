@@ -493,6 +493,56 @@ __device__ __forceinline__ Out k_sqe(const DevKernel& K, const float* tab, const
   return o;
 }
 
+// Incoherent multi-phonon scattering (incoherent approximation, Supplement
+// S4): order n uniform on 2..N, direction isotropic, energy loss the sum of
+// n independent draws from the one-phonon spectrum A_1 (so that it follows
+// the n-fold convolution A_n exactly), weight (k_f/k_i) S_n(Q) (N - 1) with
+// S_n = (2W)^n/n! e^{-2W}.  Phonon i uses words 2(i mod 2) and 2(i mod 2)+1
+// of block 2 + i/2 of the packet's scattering stream.  The loss is summed
+// as whole bins (exact) plus the in-bin fractions, then scaled once.
+__device__ __forceinline__ Out k_multiphonon(const DevKernel& K, const float* tab, const Pk& P,
+                                             const float* u, uint64_t id, uint32_t lin,
+                                             uint64_t seed) {
+  Out o;
+  o.bin = -1;
+  o.dwq2 = 0.0f;
+  const int N = K.nmax;
+  int n = 2 + (int)floorf(u[2] * (float)(N - 1));
+  n = n > N ? N : n;
+  iso_dir(u[3], u[4], o.dx, o.dy, o.dz);
+  const int nb2 = 2 * K.nbins;
+  int whole = 0;
+  float frac = 0.0f;
+  float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int i = 0; i < n; ++i) {
+    if ((i & 1) == 0) draw4(id, STREAM_SCATTER, lin, 2u + (uint32_t)(i >> 1), seed, v);
+    const float ub = (i & 1) ? v[2] : v[0];
+    const float up = (i & 1) ? v[3] : v[1];
+    int j = first_above(tab + K.t_cdf, nb2, ub);
+    j = j > nb2 - 1 ? nb2 - 1 : j;
+    whole += j - K.nbins;
+    frac += up;
+  }
+  const float e = ((float)whole + frac) * K.de;
+  const float Ei = kEperV2 * P.sp * P.sp;
+  const float Ef = Ei - e;
+  o.sp = P.sp;
+  if (!(Ef > 0.0f)) {
+    o.f = 0.0f;
+    return o;
+  }
+  const float ki = P.sp * kKperV;
+  const float kf = sqrtf(Ef / kHb2m);
+  const float dk = e / (kHb2m * (ki + kf));  // k_i - k_f
+  const float q2 = q2_of(ki, kf, dk, P, o.dx, o.dy, o.dz);
+  const float w2 = K.dw_self * q2;
+  float sn = expf(-w2);
+  for (int m = 1; m <= n; ++m) sn *= w2 / (float)m;
+  o.sp = kf * kVperK;
+  o.f = (kf / ki) * sn * (float)(N - 1);
+  return o;
+}
+
 // ------------------------------------------------------------------ detectors
 struct Hit {
   int64_t bin;
@@ -723,13 +773,17 @@ __device__ __forceinline__ void segment_terms(const DevScat& S, const float* tab
   pint = -expm1f(-ml);
 }
 
+// (id, lin, seed): the packet's scattering stream, for kernels that draw
+// beyond the split's eight uniforms
 __device__ __forceinline__ Out kernel_eval(const DevKernel& K, const DevScat& S,
-                                           const float* tab, const Pk& P, const float* u) {
+                                           const float* tab, const Pk& P, const float* u,
+                                           uint64_t id, uint32_t lin, uint64_t seed) {
   switch (K.type) {
     case K_ISO_EL: return k_iso(K, S, P, u);
     case K_POWDER: return k_powder(K, S, tab, P, u);
     case K_PHONON: return k_phonon(K, S, tab, P, u);
     case K_SPINWAVE: return k_spinwave(K, P, u);
+    case K_MULTIPHONON: return k_multiphonon(K, tab, P, u, id, lin, seed);
     default: return k_sqe(K, tab, P, u);
   }
 }
@@ -857,7 +911,7 @@ __device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, const A
       const int kk = split_child(S, mu, pint, P, sx, sy, sz, t0, slo,
                                  (int)((codes >> (4 * j)) & 0xFu), u, lin, C, x);
       const DevKernel& K = S.k[kk];
-      const Out o = kernel_eval(K, S, tab, P, u);
+      const Out o = kernel_eval(K, S, tab, P, u, id, lin, seed);
       C.dx = o.dx;
       C.dy = o.dy;
       C.dz = o.dz;

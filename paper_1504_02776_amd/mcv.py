@@ -23,7 +23,7 @@ STATUS_NAMES = ["MCV_OK", "MCV_EINVAL", "MCV_EUNSUPPORTED", "MCV_EOVERLAP", "MCV
                 "MCV_ECAPACITY", "MCV_EHIP"]
 
 SHAPES = {"box": 1, "cylinder": 2, "annulus": 3}
-KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5}
+KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6}
 
 
 class MCVError(RuntimeError):
@@ -46,7 +46,8 @@ class mcv_kernel(C.Structure):
                 ("v0", C.c_double), ("nrefl", C.c_int32), ("reserved0", C.c_int32),
                 ("d", C.POINTER(C.c_double)), ("F2", C.POINTER(C.c_double)),
                 ("M_amu", C.c_double), ("T_K", C.c_double), ("nbins", C.c_int32),
-                ("reserved1", C.c_int32), ("emax", C.c_double), ("dos", C.POINTER(C.c_double)),
+                ("max_phonons", C.c_int32), ("emax", C.c_double),
+                ("dos", C.POINTER(C.c_double)),
                 ("J", C.c_double), ("S", C.c_double), ("a", C.c_double), ("gamma", C.c_double),
                 ("crot", C.c_double * 9), ("nQ", C.c_int32), ("nE", C.c_int32),
                 ("Qmax", C.c_double), ("Emin", C.c_double), ("Emax", C.c_double),
@@ -166,11 +167,12 @@ def _kernel_struct(k, keep):
         F2 = np.ascontiguousarray(k["F2"], dtype=np.float64)
         keep += [d, F2]
         s.v0, s.nrefl, s.d, s.F2 = k["v0"], len(d), _dptr(d), _dptr(F2)
-    elif t == "phonon":
+    elif t in ("phonon", "multiphonon"):
         dos = np.ascontiguousarray(k["dos"], dtype=np.float64)
         keep.append(dos)
         s.M_amu, s.T_K, s.emax = k["M"], k["T"], k["emax"]
         s.nbins, s.dos = len(dos), _dptr(dos)
+        s.max_phonons = int(k.get("nmax", 0))
     elif t == "spinwave":
         s.J, s.S, s.a, s.gamma = k["J"], k["S"], k["a"], k["gamma"]
         s.crot[:] = k["crot"]

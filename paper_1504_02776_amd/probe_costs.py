@@ -30,7 +30,7 @@ ITERS = 2048         # calls per lane
 REPS = 3
 
 PR_NULL, PR_RNG, PR_SOURCE, PR_SHAPE, PR_SEGMENT, PR_SPLIT, PR_KERNEL, PR_DETECT = range(8)
-KERNEL_TYPES = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5}
+KERNEL_TYPES = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6}
 
 
 def _bind():
@@ -94,7 +94,8 @@ def main():
            "cus": props.multi_processor_count, "valu_peak_lane_ops": VALU_PEAK,
            "grid": GRID, "iters": ITERS, "unit": "VALU lane-op slots per call", "workloads": {}}
     for name, cfg in [("powder", W.powder_config()), ("plate", W.plate_config()),
-                      ("crystal", W.crystal_config()), ("sqe", W.sqe_config())]:
+                      ("crystal", W.crystal_config()), ("sqe", W.sqe_config()),
+                      ("powder_mp", W.powder_mp_config())]:
         res["workloads"][name] = probe_workload(cfg)
         print(f"[probe] {name}: {json.dumps(res['workloads'][name])}", flush=True)
     with open(args.out, "w") as f:

@@ -20,6 +20,7 @@ def _cases():
         "powder": (W.powder_config(), 3_000 + 11),
         "crystal": (W.crystal_config(), 600 + 3),
         "sqe": (W.sqe_config(), 4_000 + 1),
+        "powder-multiphonon": (W.powder_mp_config(), 3_000 + 7),
     }
 
 
