@@ -607,52 +607,41 @@ __device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, c
   const float dyr = 1.25f * D.radius * fabsf(P.dy) / ra + 1e-4f;
   float best = kBig, best_hi = 0.0f, best_len = 0.0f;
   int best_tube = -1, best_row = 0;
-  // Candidates: columns col-1..col+1 of the rows whose height range the ray
-  // can meet, kept only if the ray passes within the tube radius (plus a
-  // margin far above binary32 rounding) of the tube axis in the horizontal
-  // plane, which every hit requires.  The exact tests then run over the
-  // kept list; its index is data, so lanes with different candidates share
-  // one pass.  Candidates are visited row by row, columns ascending.
-  uint32_t cand = 0u;
-  const float rlim = D.radius * 1.0001f + 1e-6f;
+  // rows whose height range the ray can meet; the row index is data, so
+  // lanes in different rows share one pass of the tests below
+  uint32_t rows = 0u;
   for (int r = 0; r < D.nrows; ++r) {
     const float yc = D.row_y[r];
-    if (yR + dyr < yc - D.half_len || yR - dyr > yc + D.half_len) continue;
+    if (!(yR + dyr < yc - D.half_len || yR - dyr > yc + D.half_len)) rows |= 1u << r;
+  }
+  while (rows != 0u) {
+    const int r = __ffs(rows) - 1;
+    rows &= rows - 1u;
+    const float yc = D.row_y[r];
 #pragma unroll
     for (int dc = -1; dc <= 1; ++dc) {
       const int cc = col + dc;
       if (cc < 0 || cc >= D.ncols) continue;
-      const float qx = tab[D.t_cols + 2 * cc] - P.px;
-      const float qz = tab[D.t_cols + 2 * cc + 1] - P.pz;
-      const float cr = P.dx * qz - P.dz * qx;  // |d_h x q| = distance * |d_h|
-      if (cr * cr <= rlim * rlim * a) cand |= 1u << (3 * r + dc + 1);
-    }
-  }
-  while (cand != 0u) {
-    const uint32_t k = (uint32_t)(__ffs(cand) - 1);
-    cand &= cand - 1u;
-    const int r = (int)(k / 3u);
-    const int cc = col + (int)(k - 3u * (uint32_t)r) - 1;
-    const float yc = D.row_y[r];
-    const float qx = P.px - tab[D.t_cols + 2 * cc];
-    const float qz = P.pz - tab[D.t_cols + 2 * cc + 1];
-    const float qy = P.py - yc;
-    Iv iv;
-    float sq, aa;
-    int lr, hr;
-    if (!cyl(qx, qy, qz, P.dx, P.dy, P.dz, D.radius, D.half_len, iv, sq, aa, lr, hr)) continue;
-    if (!(iv.hi > 0.0f)) continue;
-    float lo = iv.lo, len = iv.len;
-    if (lo < 0.0f) {
-      lo = 0.0f;
-      len = iv.hi;
-    }
-    if (lo < best) {
-      best = lo;
-      best_hi = iv.hi;
-      best_len = len;
-      best_tube = r * D.ncols + cc;
-      best_row = r;
+      const float qx = P.px - tab[D.t_cols + 2 * cc];
+      const float qz = P.pz - tab[D.t_cols + 2 * cc + 1];
+      const float qy = P.py - yc;
+      Iv iv;
+      float sq, aa;
+      int lr, hr;
+      if (!cyl(qx, qy, qz, P.dx, P.dy, P.dz, D.radius, D.half_len, iv, sq, aa, lr, hr)) continue;
+      if (!(iv.hi > 0.0f)) continue;
+      float lo = iv.lo, len = iv.len;
+      if (lo < 0.0f) {
+        lo = 0.0f;
+        len = iv.hi;
+      }
+      if (lo < best) {
+        best = lo;
+        best_hi = iv.hi;
+        best_len = len;
+        best_tube = r * D.ncols + cc;
+        best_row = r;
+      }
     }
   }
   if (best_tube < 0) return h;
