@@ -73,9 +73,12 @@ const double kTauTof = 4e-6;     // relative time of flight
 const double kTauImpact = 4e-4;  // relative impact parameter in a tube
 const double kTauU = 2e-6;       // absolute, for u < p tests on computed p
 // Conditioning of a single-precision implementation (reported, not used by
-// the method): a position of ~1 cm is known to ~2e-9 m in binary32, which
-// makes a chord L uncertain by 2e-9 m / |cos| at each surface it crosses.
-const double kEpsPos = 2e-9;
+// the method): a position of ~1 cm is known to ~3e-9 m in binary32 (half an
+// ulp, 4.7e-10 m, per coordinate from each of the roundings of a birth point
+// -- entry point, x d, and their sum -- plus the squared radius of the next
+// shape test, whose cancellation near a surface adds about as much), which
+// makes a chord L uncertain by 3e-9 m / |cos| at each surface it crosses.
+const double kEpsPos = 3e-9;
 
 inline double k_from_speed(double v) { return v * std::sqrt(kEperV2 / kHbar2over2mn); }
 inline double speed_from_k(double k) { return k * std::sqrt(kHbar2over2mn / kEperV2); }

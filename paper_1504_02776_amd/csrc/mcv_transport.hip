@@ -826,141 +826,165 @@ __device__ __forceinline__ int split_child(const DevScat& S, const Mu& mu, float
   return kk;
 }
 
-template <bool ADJ, int NSC, bool TWO>
-__device__ __forceinline__ void fly(const DevPlan& PL, const float* tab, const AdjArgs& AA,
-                                    Pk& P, Adj& pa, uint64_t id, uint64_t seed, Pk& nxt,
-                                    Adj& na, bool& has_nxt, float* st, int& nst, int nthreads,
-                                    int tid) {
-  using SL = Slots<NSC, TWO>;
-  constexpr int NS = SL::N;
+// The material intervals of one packet's ray, walked nearest first; the
+// arrays have static indices (registers).  Intervals that end behind the
+// packet are dropped; a packet inside a scatterer starts its interval at 0.
+template <int NSC, bool TWO>
+struct Flight {
+  static constexpr int NS = Slots<NSC, TWO>::N;
   float lo[NS], hi[NS], len[NS];
-  uint32_t valid = 0u, codes = 0u;
+  uint32_t valid, codes;
+  float sx, sy, sz, t0, s_end;
+  uint32_t g;  // intervals crossed so far (segment index of the next child)
+};
+
+template <int NSC, bool TWO>
+__device__ __forceinline__ void flight_setup(const DevPlan& PL, const Pk& P, Flight<NSC, TWO>& F) {
+  using SL = Slots<NSC, TWO>;
+  F.valid = 0u;
+  F.codes = 0u;
 #pragma unroll
   for (int s = 0; s < NSC; ++s) {
     Iv a, b;
     a.lo = a.hi = a.len = b.lo = b.hi = b.len = 0.0f;
     a.entry = b.entry = ENTRY_NONE;
     const int n = s < PL.nscat ? shape_iv(PL.s[s], P, a, b) : 0;
-    constexpr int dummy = 0;
-    (void)dummy;
     const int j0 = SL::of(s, 0);
-    lo[j0] = a.lo;
-    hi[j0] = a.hi;
-    len[j0] = a.len;
-    codes |= (uint32_t)a.entry << (4 * j0);
-    if (n > 0 && a.hi > kSurf) valid |= 1u << j0;
+    F.lo[j0] = a.lo;
+    F.hi[j0] = a.hi;
+    F.len[j0] = a.len;
+    F.codes |= (uint32_t)a.entry << (4 * j0);
+    if (n > 0 && a.hi > kSurf) F.valid |= 1u << j0;
     if (TWO) {
       const int j1 = SL::of(s, 1);
-      lo[j1] = b.lo;
-      hi[j1] = b.hi;
-      len[j1] = b.len;
-      codes |= (uint32_t)b.entry << (4 * j1);
-      if (n > 1 && b.hi > kSurf) valid |= 1u << j1;
+      F.lo[j1] = b.lo;
+      F.hi[j1] = b.hi;
+      F.len[j1] = b.len;
+      F.codes |= (uint32_t)b.entry << (4 * j1);
+      if (n > 1 && b.hi > kSurf) F.valid |= 1u << j1;
     }
   }
-  // a packet inside a scatterer starts its interval at 0
 #pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    if (lo[j] <= 0.0f) {
-      lo[j] = 0.0f;
-      len[j] = hi[j];
-      codes &= ~(0xFu << (4 * j));
+  for (int j = 0; j < SL::N; ++j) {
+    if (F.lo[j] <= 0.0f) {
+      F.lo[j] = 0.0f;
+      F.len[j] = F.hi[j];
+      F.codes &= ~(0xFu << (4 * j));
     }
   }
-  const int order = order_of(P.lin);
-  const float sx = P.px, sy = P.py, sz = P.pz, t0 = P.t;
-  float s_end = 0.0f;
-  uint32_t g = 0;
-  while (valid) {
-    // nearest remaining interval; ties to the lower scatterer index
-    int j = 0;
-    float best = kBig;
+  F.sx = P.px;
+  F.sy = P.py;
+  F.sz = P.pz;
+  F.t0 = P.t;
+  F.s_end = 0.0f;
+  F.g = 0u;
+}
+
+// moves the packet to the exit of the last interval it crossed
+template <int NSC, bool TWO>
+__device__ __forceinline__ void flight_exit(Pk& P, const Flight<NSC, TWO>& F) {
+  if (F.g > 0u) {
+    P.px = F.sx + F.s_end * P.dx;
+    P.py = F.sy + F.s_end * P.dy;
+    P.pz = F.sz + F.s_end * P.dz;
+    P.t = F.t0 + F.s_end / P.sp;
+  }
+}
+
+// The nearest remaining interval of a flight: the packet is attenuated by
+// e^{-mu L}; with SPLIT (and order < K, w >= min_prob, mu_s > 0) a
+// forced-collision child is born in it, its kernel drawn and evaluated.  The
+// first child of a flight is kept in `nxt`, further ones go to the stack.
+template <bool ADJ, bool SPLIT, int NSC, bool TWO>
+__device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
+                                            const AdjArgs& AA, Pk& P, Adj& pa,
+                                            Flight<NSC, TWO>& F, uint64_t id, uint64_t seed,
+                                            Pk& nxt, Adj& na, bool& has_nxt, float* st, int& nst,
+                                            int nthreads, int tid) {
+  using SL = Slots<NSC, TWO>;
+  constexpr int NS = SL::N;
+  // nearest remaining interval; ties to the lower scatterer index
+  int j = 0;
+  float best = kBig;
 #pragma unroll
-    for (int q = 0; q < NS; ++q) {
-      if ((valid >> q) & 1u) {
-        if (lo[q] < best) {
-          best = lo[q];
-          j = q;
-        }
+  for (int q = 0; q < NS; ++q) {
+    if ((F.valid >> q) & 1u) {
+      if (F.lo[q] < best) {
+        best = F.lo[q];
+        j = q;
       }
     }
-    valid &= ~(1u << j);
-    float slo = 0.0f, shi = 0.0f, sl = 0.0f;
+  }
+  F.valid &= ~(1u << j);
+  float slo = 0.0f, shi = 0.0f, sl = 0.0f;
 #pragma unroll
-    for (int q = 0; q < NS; ++q) {
-      if (q == j) {
-        slo = lo[q];
-        shi = hi[q];
-        sl = len[q];
-      }
+  for (int q = 0; q < NS; ++q) {
+    if (q == j) {
+      slo = F.lo[q];
+      shi = F.hi[q];
+      sl = F.len[q];
     }
-    const int si = SL::scat(j);
-    const DevScat& S = PL.s[si];
-    Mu mu;
-    float att, pint;
-    segment_terms(S, tab, P.sp, sl, mu, att, pint);
-    float dmu_abs = 0.0f, dmu_sig = 0.0f;
+  }
+  const int si = SL::scat(j);
+  const DevScat& S = PL.s[si];
+  Mu mu;
+  float att, pint;
+  segment_terms(S, tab, P.sp, sl, mu, att, pint);
+  float dmu_abs = 0.0f, dmu_sig = 0.0f;
+  if (ADJ) {
+    if (si == AA.abs_s) dmu_abs = S.n100 * 2200.0f / P.sp;
+    if (si == AA.sig_s) dmu_sig = S.n100;
+  }
+  if (SPLIT && order_of(P.lin) < PL.K && P.w >= PL.min_prob && mu.scat > 0.0f) {
+    const uint32_t lin = P.lin * 8u + F.g + 1u;
+    float u[8];
+    draw4(id, STREAM_SCATTER, lin, 0u, seed, u);
+    draw4(id, STREAM_SCATTER, lin, 1u, seed, u + 4);
+    Pk C;
+    float x;
+    const int kk = split_child(S, mu, pint, P, F.sx, F.sy, F.sz, F.t0, slo,
+                               (int)((F.codes >> (4 * j)) & 0xFu), u, lin, C, x);
+    const DevKernel& K = S.k[kk];
+    const Out o = kernel_eval(K, S, tab, P, u, id, lin, seed);
+    C.dx = o.dx;
+    C.dy = o.dy;
+    C.dz = o.dz;
+    C.sp = o.sp;
+    C.w *= o.f;
+    Adj ca;
     if (ADJ) {
-      if (si == AA.abs_s) dmu_abs = S.n100 * 2200.0f / P.sp;
-      if (si == AA.sig_s) dmu_sig = S.n100;
-    }
-    if (order < PL.K && P.w >= PL.min_prob && mu.scat > 0.0f) {
-      const uint32_t lin = P.lin * 8u + g + 1u;
-      float u[8];
-      draw4(id, STREAM_SCATTER, lin, 0u, seed, u);
-      draw4(id, STREAM_SCATTER, lin, 1u, seed, u + 4);
-      Pk C;
-      float x;
-      const int kk = split_child(S, mu, pint, P, sx, sy, sz, t0, slo,
-                                 (int)((codes >> (4 * j)) & 0xFu), u, lin, C, x);
-      const DevKernel& K = S.k[kk];
-      const Out o = kernel_eval(K, S, tab, P, u, id, lin, seed);
-      C.dx = o.dx;
-      C.dy = o.dy;
-      C.dz = o.dz;
-      C.sp = o.sp;
-      C.w *= o.f;
-      Adj ca;
-      if (ADJ) {
-        ca = pa;
-        ca.dabs -= x * dmu_abs;
-        ca.dsig -= x * dmu_sig;
-        if (si == AA.sig_s && kk == AA.sig_k) ca.dsig += S.n100 / K.mu;
-        if (si == AA.dos_s) {
-          ca.A += o.dwq2;
-          if (kk == AA.dos_k && o.bin >= 0) {
-            const uint32_t sh = 16u * (ca.nph & 1u);
-            if (ca.nph < 2u) ca.b01 |= (uint32_t)o.bin << sh;
-            else ca.b23 |= (uint32_t)o.bin << sh;
-            ++ca.nph;
-          }
-        }
-      }
-      if (C.w > 0.0f) {
-        if (!has_nxt) {
-          nxt = C;
-          if (ADJ) na = ca;
-          has_nxt = true;
-        } else if (nst < PL.stack_cap) {
-          push<ADJ>(st, nst, nthreads, tid, C, ca);
-          ++nst;
+      ca = pa;
+      ca.dabs -= x * dmu_abs;
+      ca.dsig -= x * dmu_sig;
+      if (si == AA.sig_s && kk == AA.sig_k) ca.dsig += S.n100 / K.mu;
+      if (si == AA.dos_s) {
+        ca.A += o.dwq2;
+        if (kk == AA.dos_k && o.bin >= 0) {
+          const uint32_t sh = 16u * (ca.nph & 1u);
+          if (ca.nph < 2u) ca.b01 |= (uint32_t)o.bin << sh;
+          else ca.b23 |= (uint32_t)o.bin << sh;
+          ++ca.nph;
         }
       }
     }
-    P.w *= att;
-    if (ADJ) {
-      pa.dabs -= sl * dmu_abs;
-      pa.dsig -= sl * dmu_sig;
+    if (C.w > 0.0f) {
+      if (!has_nxt) {
+        nxt = C;
+        if (ADJ) na = ca;
+        has_nxt = true;
+      } else if (nst < PL.stack_cap) {
+        push<ADJ>(st, nst, nthreads, tid, C, ca);
+        ++nst;
+      }
     }
-    s_end = shi;
-    ++g;
   }
-  if (g > 0) {
-    P.px = sx + s_end * P.dx;
-    P.py = sy + s_end * P.dy;
-    P.pz = sz + s_end * P.dz;
-    P.t = t0 + s_end / P.sp;
+  P.w *= att;
+  if (ADJ) {
+    pa.dabs -= sl * dmu_abs;
+    pa.dsig -= sl * dmu_sig;
   }
+  F.s_end = shi;
+  ++F.g;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -1070,18 +1094,176 @@ __device__ __forceinline__ void hist_add(double* hist, double* hist_w2, double* 
   }
 }
 
-// One wave traces histories first+begin .. first+end-1: every lane walks
-// the packet tree of one history depth first and takes the next history of
-// the range as soon as it is done (ballot + prefix count), so lanes stay busy
-// until the range is exhausted.  Called with the whole wave active.  `acc`
-// is the workgroup's LDS block: adjoint partials (MODE_ADJOINT) or the
-// histogram bin cache (otherwise).
+// Lane states of the transport loop
+enum { LANE_NEED = 0, LANE_SETUP = 1, LANE_FLY = 2, LANE_DET = 3, LANE_DONE = 4 };
+
+// Recording of one packet leaving the sample: detector, histogram value or
+// adjoint gather, and the packet record in MODE_TRACE.
+template <int MODE>
+__device__ __forceinline__ void record_packet(const DevPlan& PL, const float* tab,
+                                              const Sinks& out, const AdjArgs& AA, double* acc,
+                                              const Pk& cur, const Adj& ca, uint64_t hid,
+                                              uint64_t seed, int& hbin, float& hval) {
+  constexpr bool ADJ = MODE == MODE_ADJOINT;
+  const Hit hh = PL.det.type == DET_SPHERE ? detect_sphere(PL.det, cur)
+                                           : detect_tubes(PL.det, tab, cur, hid, seed);
+  if (hh.bin >= 0) {
+    if (ADJ) {
+      const double gv = AA.dLdI[hh.bin] * (double)hh.value;
+      if (gv != 0.0) {
+        atomicAdd(&acc[AA.nb + 0], gv * (double)ca.dabs);
+        atomicAdd(&acc[AA.nb + 1], gv * (double)ca.dsig);
+        atomicAdd(&acc[AA.nb + 2], gv * (double)ca.A);
+        atomicAdd(&acc[AA.nb + 3], gv * (double)ca.nph);
+        for (uint32_t e = 0; e < ca.nph && e < (uint32_t)kAdjMaxOrders; ++e) {
+          const uint32_t w = e < 2u ? ca.b01 : ca.b23;
+          atomicAdd(&acc[(w >> (16u * (e & 1u))) & 0xFFFFu], gv);
+        }
+      }
+    } else {
+      hbin = hh.bin;
+      hval = hh.value;
+    }
+  }
+  if (MODE == MODE_TRACE) {
+    const unsigned long long slot = atomicAdd(out.n_out, 1ull);
+    if (slot < out.cap) {
+      DevRecord r;
+      r.id = hid;
+      r.lineage = cur.lin;
+      r.order = order_of(cur.lin);
+      r.pos[0] = cur.px;
+      r.pos[1] = cur.py;
+      r.pos[2] = cur.pz;
+      r.vel[0] = cur.dx * cur.sp;
+      r.vel[1] = cur.dy * cur.sp;
+      r.vel[2] = cur.dz * cur.sp;
+      r.t = cur.t;
+      r.w = cur.w;
+      r.bin = hh.bin;
+      r.value = hh.value;
+      r.tof = hh.tof;
+      r.tube = hh.tube;
+      r.pixel = hh.pixel;
+      out.rec[slot] = r;
+    }
+  }
+}
+
+// One wave traces histories first+begin .. first+end-1.  Every lane walks
+// the packet tree of one history depth first (first child in registers,
+// further children on its LDS stack) and takes the next history of the range
+// when its tree is done (ballot + prefix count).  Two loop shapes:
+//
+// trace_walk: every iteration, each lane takes one packet through all the
+// material intervals of its ray (splitting where it may) and records it.
+// Lanes stay in step when the packets of a history are alike (one scatterer
+// and single scattering, or several scatterers whose flights vary anyway).
+//
+// trace_phased: the work of a packet is split into two phases that the wave
+// runs one at a time, whichever has more lanes waiting, so that lanes in the
+// same phase run together:
+//   I: one material interval of a packet that can still scatter
+//      (attenuation, forced-collision child, kernel);
+//   D: detection and histogram of a finished packet, then the next packet
+//      (first child, stack, or a new history) and the intervals of its ray;
+//      a packet that can no longer scatter crosses all of them here with
+//      attenuation only and waits for the next D phase.
+// Called with the whole wave active.  `acc` is the workgroup's LDS block:
+// adjoint partials (MODE_ADJOINT) or the histogram bin cache (otherwise).
 template <int MODE, int NSC, bool TWO>
-__device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab, float* st,
-                                            const DevBeam& beam, uint64_t seed, uint64_t first,
-                                            uint64_t begin, uint64_t end, const Sinks& out,
-                                            const AdjArgs& AA, double* acc, int hot_n,
-                                            int nthreads, int tid) {
+__device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab, float* st,
+                                             const DevBeam& beam, uint64_t seed, uint64_t first,
+                                             uint64_t begin, uint64_t end, const Sinks& out,
+                                             const AdjArgs& AA, double* acc, int hot_n,
+                                             int nthreads, int tid) {
+  constexpr bool ADJ = MODE == MODE_ADJOINT;
+  const uint64_t lt = lanemask_lt();
+  Pk cur;
+  cur.lin = 0u;
+  Pk nxt;
+  nxt.lin = 0u;
+  Adj ca = {0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+  Adj na = ca;
+  bool has_nxt = false;
+  Flight<NSC, TWO> F;
+  F.valid = 0u;
+  F.g = 0u;
+  uint64_t hid = 0;
+  int nst = 0;
+  int state = LANE_NEED;
+  uint64_t next = begin;
+  while (true) {
+    const uint64_t mI = __ballot(state == LANE_FLY);
+    const uint64_t mD = __ballot(state == LANE_NEED || state == LANE_DET);
+    if ((mI | mD) == 0ull) break;
+    if (__popcll(mI) >= __popcll(mD)) {
+      if (state == LANE_FLY) {
+        flight_step<ADJ, true, NSC, TWO>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
+                                         st, nst, nthreads, tid);
+        if (F.valid == 0u) {
+          flight_exit(cur, F);
+          state = LANE_DET;
+        }
+      }
+      continue;
+    }
+    int hbin = -1;
+    float hval = 0.0f;
+    if (state == LANE_DET) {
+      record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
+      if (has_nxt) {
+        cur = nxt;
+        if (ADJ) ca = na;
+        has_nxt = false;
+        state = LANE_SETUP;
+      } else {
+        state = LANE_NEED;
+      }
+    }
+    if (state == LANE_NEED && nst > 0) {
+      --nst;
+      pop<ADJ>(st, nst, nthreads, tid, cur, ca);
+      state = LANE_SETUP;
+    }
+    const bool need = state == LANE_NEED;
+    const uint64_t m = __ballot(need);
+    if (need) {
+      const uint64_t h = next + (uint64_t)__popcll(m & lt);
+      if (h < end) {
+        hid = first + h;
+        cur = source(beam, hid, seed);
+        ca = Adj{0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+        if (cur.w > 0.0f) state = LANE_SETUP;
+      } else {
+        state = LANE_DONE;
+      }
+    }
+    next += (uint64_t)__popcll(m);
+    if (state == LANE_SETUP) {
+      flight_setup(PL, cur, F);
+      if (order_of(cur.lin) >= PL.K || cur.w < PL.min_prob) {
+        while (F.valid != 0u)
+          flight_step<ADJ, false, NSC, TWO>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
+                                            st, nst, nthreads, tid);
+      }
+      if (F.valid != 0u) {
+        state = LANE_FLY;
+      } else {
+        flight_exit(cur, F);
+        state = LANE_DET;
+      }
+    }
+    if (!ADJ) hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
+  }
+}
+
+template <int MODE, int NSC, bool TWO>
+__device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, float* st,
+                                           const DevBeam& beam, uint64_t seed, uint64_t first,
+                                           uint64_t begin, uint64_t end, const Sinks& out,
+                                           const AdjArgs& AA, double* acc, int hot_n,
+                                           int nthreads, int tid) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
   const uint64_t lt = lanemask_lt();
   Pk cur;
@@ -1117,51 +1299,13 @@ __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab,
       nxt.lin = 0u;
       Adj na = ca;
       bool has_nxt = false;
-      fly<ADJ, NSC, TWO>(PL, tab, AA, cur, ca, hid, seed, nxt, na, has_nxt, st, nst, nthreads,
-                         tid);
-      const Hit hh = PL.det.type == DET_SPHERE ? detect_sphere(PL.det, cur)
-                                               : detect_tubes(PL.det, tab, cur, hid, seed);
-      if (hh.bin >= 0) {
-        if (ADJ) {
-          const double gv = AA.dLdI[hh.bin] * (double)hh.value;
-          if (gv != 0.0) {
-            atomicAdd(&acc[AA.nb + 0], gv * (double)ca.dabs);
-            atomicAdd(&acc[AA.nb + 1], gv * (double)ca.dsig);
-            atomicAdd(&acc[AA.nb + 2], gv * (double)ca.A);
-            atomicAdd(&acc[AA.nb + 3], gv * (double)ca.nph);
-            for (uint32_t e = 0; e < ca.nph && e < (uint32_t)kAdjMaxOrders; ++e) {
-              const uint32_t w = e < 2u ? ca.b01 : ca.b23;
-              atomicAdd(&acc[(w >> (16u * (e & 1u))) & 0xFFFFu], gv);
-            }
-          }
-        } else {
-          hbin = hh.bin;
-          hval = hh.value;
-        }
-      }
-      if (MODE == MODE_TRACE) {
-        const unsigned long long slot = atomicAdd(out.n_out, 1ull);
-        if (slot < out.cap) {
-          DevRecord r;
-          r.id = hid;
-          r.lineage = cur.lin;
-          r.order = order_of(cur.lin);
-          r.pos[0] = cur.px;
-          r.pos[1] = cur.py;
-          r.pos[2] = cur.pz;
-          r.vel[0] = cur.dx * cur.sp;
-          r.vel[1] = cur.dy * cur.sp;
-          r.vel[2] = cur.dz * cur.sp;
-          r.t = cur.t;
-          r.w = cur.w;
-          r.bin = hh.bin;
-          r.value = hh.value;
-          r.tof = hh.tof;
-          r.tube = hh.tube;
-          r.pixel = hh.pixel;
-          out.rec[slot] = r;
-        }
-      }
+      Flight<NSC, TWO> F;
+      flight_setup(PL, cur, F);
+      while (F.valid != 0u)
+        flight_step<ADJ, true, NSC, TWO>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
+                                         st, nst, nthreads, tid);
+      flight_exit(cur, F);
+      record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
       if (has_nxt) {
         cur = nxt;
         if (ADJ) ca = na;
@@ -1171,6 +1315,28 @@ __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab,
     }
     if (!ADJ) hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
   }
+}
+
+// The phased loop pays off for one convex scatterer with multiple
+// scattering (every flight one interval, a quarter to a half of the packets
+// unable to scatter); the walk is faster for single scattering and for
+// assemblies whose flights cross several intervals (measured).
+__host__ __device__ constexpr bool use_phased(int nscat, bool two, int K) {
+  return nscat <= 1 && !two && K >= 2;
+}
+
+template <int MODE, int NSC, bool TWO, bool PHASED>
+__device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab, float* st,
+                                            const DevBeam& beam, uint64_t seed, uint64_t first,
+                                            uint64_t begin, uint64_t end, const Sinks& out,
+                                            const AdjArgs& AA, double* acc, int hot_n,
+                                            int nthreads, int tid) {
+  if constexpr (PHASED)
+    trace_phased<MODE, NSC, TWO>(PL, tab, st, beam, seed, first, begin, end, out, AA, acc, hot_n,
+                                 nthreads, tid);
+  else
+    trace_walk<MODE, NSC, TWO>(PL, tab, st, beam, seed, first, begin, end, out, AA, acc, hot_n,
+                               nthreads, tid);
 }
 
 // copies a plan and its tables into LDS (whole workgroup)
@@ -1188,7 +1354,7 @@ __device__ __forceinline__ void stage_plan(DevPlan& PL, float* dyn, const DevPla
 // numbers) and accumulates dL/dtheta = sum over recorded packets of
 // dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
 // per workgroup.
-template <int MODE, int NSC, bool TWO>
+template <int MODE, int NSC, bool TWO, bool PHASED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     NSC == 1 && !TWO ? MCV_WAVES_PER_EU_SIMPLE : MCV_WAVES_PER_EU)))
 transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
@@ -1214,7 +1380,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
   if (begin < n)  // uniform per wave
-    trace_range<MODE, NSC, TWO>(PL, dyn, st, beam, seed, first, begin,
+    trace_range<MODE, NSC, TWO, PHASED>(PL, dyn, st, beam, seed, first, begin,
                                 begin + per_wave < n ? begin + per_wave : n, out, AA, acc, hot_n,
                                 nthreads, tid);
   if (!ADJ) {
@@ -1277,19 +1443,20 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     // the same specialisation as a plain launch of this plan, so that both
     // evaluate identical arithmetic
     const bool two = PL.smax > PL.nscat;
-#define MCV_BATCH_TRACE(NSC_, TWO_)                                                        \
-  trace_range<MODE_RUN, NSC_, TWO_>(PL, tab, st, it.beam, it.seed, it.id0, b, ee, out, AA, \
-                                    hot, hot_n, nthreads, tid)
+#define MCV_BATCH_TRACE(NSC_, TWO_, PH_)                                                        \
+  trace_range<MODE_RUN, NSC_, TWO_, PH_>(PL, tab, st, it.beam, it.seed, it.id0, b, ee, out, AA, \
+                                         hot, hot_n, nthreads, tid)
     if (b < e) {
       if (PL.nscat <= 1) {
-        if (two) MCV_BATCH_TRACE(1, true);
-        else MCV_BATCH_TRACE(1, false);
+        if (two) MCV_BATCH_TRACE(1, true, false);
+        else if (use_phased(PL.nscat, two, PL.K)) MCV_BATCH_TRACE(1, false, true);
+        else MCV_BATCH_TRACE(1, false, false);
       } else if (PL.nscat == 2) {
-        if (two) MCV_BATCH_TRACE(2, true);
-        else MCV_BATCH_TRACE(2, false);
+        if (two) MCV_BATCH_TRACE(2, true, false);
+        else MCV_BATCH_TRACE(2, false, false);
       } else {
-        if (two) MCV_BATCH_TRACE(4, true);
-        else MCV_BATCH_TRACE(4, false);
+        if (two) MCV_BATCH_TRACE(4, true, false);
+        else MCV_BATCH_TRACE(4, false, false);
       }
     }
 #undef MCV_BATCH_TRACE
@@ -1399,31 +1566,32 @@ size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, i
 
 namespace {
 
-template <int MODE, int NSC, bool TWO>
+template <int MODE, int NSC, bool TWO, bool PHASED>
 void launch_one(int grid, int block, size_t lds, hipStream_t stream, const DevPlan* plan,
                 const float* tables, const DevBeam& beam, uint64_t seed, uint64_t first,
                 uint64_t n, uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
-  hipLaunchKernelGGL((dev::transport<MODE, NSC, TWO>), dim3(grid), dim3(block), lds, stream, plan,
+  hipLaunchKernelGGL((dev::transport<MODE, NSC, TWO, PHASED>), dim3(grid), dim3(block), lds, stream, plan,
                      tables, beam, seed, first, n, per_wave, out, AA);
 }
 
 template <int MODE>
-void launch_mode(int nsc, bool two, int grid, int block, size_t lds, hipStream_t stream,
-                 const DevPlan* plan, const float* tables, const DevBeam& beam, uint64_t seed,
-                 uint64_t first, uint64_t n, uint64_t per_wave, const dev::Sinks& out,
-                 const AdjArgs& AA) {
-#define MCV_LAUNCH(NSC_, TWO_)                                                                 \
-  launch_one<MODE, NSC_, TWO_>(grid, block, lds, stream, plan, tables, beam, seed, first, n,  \
-                               per_wave, out, AA)
+void launch_mode(int nsc, bool two, bool phased, int grid, int block, size_t lds,
+                 hipStream_t stream, const DevPlan* plan, const float* tables,
+                 const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
+                 uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
+#define MCV_LAUNCH(NSC_, TWO_, PH_)                                                            \
+  launch_one<MODE, NSC_, TWO_, PH_>(grid, block, lds, stream, plan, tables, beam, seed, first, \
+                                    n, per_wave, out, AA)
   if (nsc <= 1) {
-    if (two) MCV_LAUNCH(1, true);
-    else MCV_LAUNCH(1, false);
+    if (two) MCV_LAUNCH(1, true, false);
+    else if (phased) MCV_LAUNCH(1, false, true);
+    else MCV_LAUNCH(1, false, false);
   } else if (nsc == 2) {
-    if (two) MCV_LAUNCH(2, true);
-    else MCV_LAUNCH(2, false);
+    if (two) MCV_LAUNCH(2, true, false);
+    else MCV_LAUNCH(2, false, false);
   } else {
-    if (two) MCV_LAUNCH(4, true);
-    else MCV_LAUNCH(4, false);
+    if (two) MCV_LAUNCH(4, true, false);
+    else MCV_LAUNCH(4, false, false);
   }
 #undef MCV_LAUNCH
 }
@@ -1444,15 +1612,16 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                           host_plan.hot_n);
   const int nsc = host_plan.nscat;
   const bool two = host_plan.smax > host_plan.nscat;
+  const bool phased = dev::use_phased(nsc, two, host_plan.K);
   if (adj) {
     hipLaunchKernelGGL(dev::zero2, dim3(1), dim3(64), 0, stream, AA.sums);
-    launch_mode<dev::MODE_ADJOINT>(nsc, two, grid, block, lds, stream, plan, tables, beam, seed,
+    launch_mode<dev::MODE_ADJOINT>(nsc, two, phased, grid, block, lds, stream, plan, tables, beam, seed,
                                    first, n, per_wave, out, AA);
   } else if (rec) {
-    launch_mode<dev::MODE_TRACE>(nsc, two, grid, block, lds, stream, plan, tables, beam, seed,
+    launch_mode<dev::MODE_TRACE>(nsc, two, phased, grid, block, lds, stream, plan, tables, beam, seed,
                                  first, n, per_wave, out, AA);
   } else {
-    launch_mode<dev::MODE_RUN>(nsc, two, grid, block, lds, stream, plan, tables, beam, seed,
+    launch_mode<dev::MODE_RUN>(nsc, two, phased, grid, block, lds, stream, plan, tables, beam, seed,
                                first, n, per_wave, out, AA);
   }
   return hipGetLastError();
@@ -1501,12 +1670,13 @@ int batch_waves_per_eu() { return MCV_WAVES_PER_EU; }
 namespace {
 template <int MODE>
 void push_mode(std::vector<const void*>& v) {
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, true>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, false>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, true>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, false>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, true>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, false>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, true>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, true, false>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, false, false>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, true, false>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, false, false>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, true, false>));
 }
 }  // namespace
 

@@ -4,9 +4,9 @@ Tolerances (binary32 packet state on the GPU against the binary64 oracle),
 scaled per packet by the conditioning the oracle reports for it:
   cond  = product over its inelastic scatterings of max(1, E_i/E_f): E_f =
           E_i - e loses digits when a phonon takes most of the energy;
-  wsens = relative weight error that position rounding (~2e-9 m at 1 cm in
+  wsens = relative weight error that position rounding (~3e-9 m at 1 cm in
           binary32) causes through the chords it crossed and was born on
-          (2e-9 m / |cos| at each surface, times d log(factor)/dL).
+          (3e-9 m / |cos| at each surface, times d log(factor)/dL).
   dpos, dtime = position and time uncertainty carried along the packet's
           history (direction uncertainty times distance flown, and the
           along-ray uncertainty of each exit point);
