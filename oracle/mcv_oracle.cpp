@@ -72,6 +72,7 @@ const double kTauCos = 2e-6;     // in cos(2theta), sphere rings
 const double kTauTof = 4e-6;     // relative time of flight
 const double kTauImpact = 4e-4;  // relative impact parameter in a tube
 const double kTauU = 2e-6;       // absolute, for u < p tests on computed p
+const double kTauJ = 5e-2;       // |dG/dE_f| of a delta-function root (tangency)
 // Conditioning of a single-precision implementation (reported, not used by
 // the method): a position of ~1 cm is known to ~3e-9 m in binary32 (half an
 // ulp, 4.7e-10 m, per coordinate from each of the roundings of a birth point
@@ -86,7 +87,8 @@ inline double speed_from_k(double k) { return k * std::sqrt(kHbar2over2mn / kEpe
 // ----------------------------------------------------------------- ABI types
 // (mirrored by ctypes in oracle.py)
 enum { SHAPE_BOX = 1, SHAPE_CYLINDER = 2, SHAPE_ANNULUS = 3 };
-enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5, K_MULTIPHONON = 6 };
+enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5, K_MULTIPHONON = 6,
+       K_DISPERSION = 7 };
 enum { BEAM_MONO = 1, BEAM_GAUSS = 2 };
 enum { DET_SPHERE = 1, DET_TUBES = 2 };
 enum { STREAM_SOURCE = 0, STREAM_SCATTER = 1, STREAM_DETECT = 2 };
@@ -595,6 +597,8 @@ struct Scatter {
   double dw_q2 = 0.0;    // Q^2 entering the Debye-Waller factor (0 if none)
   int dos_bin = -1;      // DOS bin of a one-phonon draw (-1 otherwise)
   double dq_sens = 0.0;  // |d log(factor) / dQ| (per 1/A of error in Q), for conditioning
+  double wsens_add = 0.0;  // further relative weight uncertainty of binary32 (conditioning)
+  double dk_rel = 0.0;     // relative uncertainty of the outgoing wave number (conditioning)
 };
 
 V3 isotropic_direction(double u_cos, double u_phi) {
@@ -759,6 +763,78 @@ Scatter k_spinwave(const OKernel& k, const Packet& P, const double* u) {
               (std::fabs(std::sin(Qc.x * k.a)) + std::fabs(std::sin(Qc.y * k.a)) +
                std::fabs(std::sin(Qc.z * k.a)));
   r.dq_sens = 2.0 * std::fabs(x) / (x * x + k.gamma * k.gamma) * gw;
+  return r;
+}
+
+// Dispersion surface with an exact delta function (Supplement S4, E_vQ
+// kernel): S(Q,E) = S(Q) delta(E - omega(Q)) with S(Q) = 1 and omega the
+// spin-wave surface above.  For an isotropic outgoing direction d (u3, u4)
+// energy conservation E_i - c k^2 = omega(k_i - k d) (c = hbar^2/2m_n) fixes
+// the outgoing wave number: the roots of g(k) = E_i - c k^2 - omega(k_i - k d)
+// on [0, k_i] (omega >= 0).  They are bracketed by the sign changes of g
+// (g > 0 against g <= 0) at kDispGrid + 1 equally spaced k and refined by
+// bisection; root floor(u2 n) of the n found is taken, and the weight
+// n (k_f/k_i) / |dG/dE_f| with dG/dE_f = -1 + (grad omega . d) / (2 c k_f)
+// carries the integral of the delta function over E_f.  No root: weight 0.
+constexpr int kDispGrid = 256;
+
+Scatter k_dispersion(const OKernel& k, const Packet& P, const double* u, double* margin) {
+  Scatter r;
+  r.dw_q2 = 0.0;
+  r.dos_bin = -1;
+  r.dir = isotropic_direction(u[3], u[4]);
+  r.speed = P.speed;
+  r.factor = 0.0;
+  const double Ei = kEperV2 * P.speed * P.speed;
+  const double k_i = k_from_speed(P.speed);
+  const double c = kHbar2over2mn;
+  const double wmax = 24.0 * k.J * k.S;
+  const V3 q0 = matvec(k.crot, scale(P.dir, k_i));   // crystal frame
+  const V3 dc = matvec(k.crot, r.dir);
+  auto omega = [&](double kk) {
+    const V3 Q = sub(q0, scale(dc, kk));
+    return 4.0 * k.J * k.S *
+           (3.0 - std::cos(Q.x * k.a) - std::cos(Q.y * k.a) - std::cos(Q.z * k.a));
+  };
+  auto g = [&](double kk) { return Ei - c * kk * kk - omega(kk); };
+  std::vector<int> cells;
+  double gprev = g(0.0);
+  *margin = std::min(*margin, std::fabs(gprev) / (kTauRel * (Ei + wmax)));
+  for (int j = 1; j <= kDispGrid; ++j) {
+    const double gj = g(k_i * j / kDispGrid);
+    *margin = std::min(*margin, std::fabs(gj) / (kTauRel * (Ei + wmax)));
+    if ((gprev > 0.0) != (gj > 0.0)) cells.push_back(j - 1);
+    gprev = gj;
+  }
+  const int n = (int)cells.size();
+  if (n == 0) return r;
+  const double fu = u[2] * n;
+  if (n > 1) *margin = std::min(*margin, std::fabs(fu - std::nearbyint(fu)) / (kTauU * n));
+  const int pick = std::min((int)std::floor(fu), n - 1);
+  double lo = k_i * cells[pick] / kDispGrid, hi = k_i * (cells[pick] + 1) / kDispGrid;
+  const bool slo = g(lo) > 0.0;
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * k_i; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if ((g(mid) > 0.0) == slo) lo = mid;
+    else hi = mid;
+  }
+  const double k_f = 0.5 * (lo + hi);
+  const V3 Q = sub(q0, scale(dc, k_f));
+  const double s4 = 4.0 * k.J * k.S * k.a;
+  const V3 grad = {s4 * std::sin(Q.x * k.a), s4 * std::sin(Q.y * k.a), s4 * std::sin(Q.z * k.a)};
+  const double A = dot(grad, dc) / (2.0 * c * k_f);
+  const double J = -1.0 + A;
+  *margin = std::min(*margin, std::fabs(J) / kTauJ);
+  if (!(k_f > 0.0) || J == 0.0) return r;
+  r.speed = speed_from_k(k_f);
+  r.factor = n * (k_f / k_i) / std::fabs(J);
+  // conditioning: a binary32 evaluation of g is uncertain by ~4e-7 (E_i +
+  // wmax), which moves the root by that over |dg/dk| = 2 c k_f |J|, and the
+  // phases Q_a a (up to ~40 rad) by ~2.4e-6 rad
+  const double eg = 4e-7 * (Ei + wmax);
+  r.dk_rel = eg / (2.0 * c * k_f * k_f * std::fabs(J));
+  r.wsens_add = std::fabs(A) * (2.4e-6 + r.dk_rel) / std::fabs(J) + r.dk_rel;
+  r.dq_sens = 0.0;
   return r;
 }
 
@@ -1215,6 +1291,7 @@ struct Sim {
                 [&](int b, double v[4]) { rng.draw(id, STREAM_SCATTER, lin, 2u + b, v); },
                 &child_margin);
             break;
+          case K_DISPERSION: r = k_dispersion(kp, Pin, u, &child_margin); break;
           default: r = k_sqe(kp, Pin, u, &child_margin); break;
         }
         // evaluation-point Debye-Waller factor and DOS over the proposal's
@@ -1255,6 +1332,8 @@ struct Sim {
             double dq = kin * (P.ddir + 2e-7) + kout * 2e-7 + (kin + kout) * 2e-7 * P.cond;
             C.wsens += r.dq_sens * dq;
           }
+          C.wsens += r.wsens_add;
+          C.cond *= 1.0 + r.dk_rel / 1e-5;
           if (k.type == K_POWDER) {
             // the cone angle 2 asin(lambda/2d) from a binary32 wavelength:
             // d(2 theta) = 2 tan(theta) d lambda / lambda
@@ -1414,6 +1493,7 @@ void kernel_sample_prepared(const OSetup* S, const std::vector<ScatInfo>& info, 
                         },
                         &m);
       break;
+    case K_DISPERSION: r = k_dispersion(k, P, u, &m); break;
     default: r = k_sqe(k, P, u, &m); break;
   }
   out[0] = r.dir.x * r.speed;

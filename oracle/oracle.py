@@ -100,7 +100,8 @@ RECORD_DTYPE = np.dtype([
     ("ddir", np.float64), ("dpos", np.float64), ("dtime", np.float64)])
 
 SHAPES = {"box": 1, "cylinder": 2, "annulus": 3}
-KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6}
+KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6,
+           "dispersion": 7}
 
 _lib = None
 
@@ -211,8 +212,8 @@ class Setup:
             o.nbins = len(k["dos"])
             o.dos = self._arr(k["dos"])
             o.nmax = int(k.get("nmax", 0))
-        elif t == "spinwave":
-            o.J, o.S, o.a, o.gamma = k["J"], k["S"], k["a"], k["gamma"]
+        elif t in ("spinwave", "dispersion"):
+            o.J, o.S, o.a, o.gamma = k["J"], k["S"], k["a"], k.get("gamma", 0.0)
             o.crot[:] = k["crot"]
         elif t == "sqe":
             o.nQ, o.nE = k["nQ"], k["nE"]

@@ -85,6 +85,20 @@ def spinwave(sigma, J, S, a, gamma, crot=IDENTITY):
             "a": float(a), "gamma": float(gamma), "crot": list(crot), "dw": 0}
 
 
+def dispersion(sigma, J, S, a, crot=IDENTITY):
+    """Dispersion surface omega(Q) = 4JS(3 - sum cos(Q_a a)) with an exact
+    delta function in energy (S(Q) = 1)."""
+    return {"type": "dispersion", "sigma": float(sigma), "J": float(J), "S": float(S),
+            "a": float(a), "crot": list(crot), "dw": 0}
+
+
+def rot_y(deg):
+    """Lab -> crystal rotation for a crystal turned by `deg` about the
+    vertical axis (a goniometer angle), row major."""
+    c, s = math.cos(math.radians(deg)), math.sin(math.radians(deg))
+    return [c, 0.0, -s, 0.0, 1.0, 0.0, s, 0.0, c]
+
+
 def sqe_grid(sigma, Qmax, Emin, Emax, S):
     S = _f32(S)
     return {"type": "sqe", "sigma": float(sigma), "Qmax": float(Qmax), "Emin": float(Emin),
@@ -210,6 +224,29 @@ def powder_mp_config(N=10_000_000, seed=0):
     k.append(multiphonon(1.0, ph["M"], ph["T"], ph["emax"], ph["dos"], nmax=4))
     cfg["name"] = "powder-multiphonon-tubes"
     return cfg
+
+
+def crystal_delta_config(N=10_000_000, seed=0, psi_deg=0.0):
+    """The crystal in its can with the slab's dispersion taken as an exact
+    delta function (no Lorentzian), crystal turned by psi about y."""
+    cfg = crystal_config(N=N, seed=seed)
+    k = cfg["scatterers"][0]["kernels"]
+    sw = k[0]
+    k[0] = dispersion(sw["sigma"], sw["J"], sw["S"], sw["a"], crot=rot_y(psi_deg))
+    cfg["name"] = f"crystal-delta-can-tubes-psi{psi_deg:g}"
+    return cfg
+
+
+def goniometer_scan_configs(n_angles=64, N=1_000_000, seed=0, span_deg=90.0):
+    """A goniometer scan: the crystal-delta sample at n_angles rotations
+    psi in [0, span) about the vertical axis, one simulation each (transport
+    seed = angle index + seed)."""
+    out = []
+    for i in range(n_angles):
+        c = crystal_delta_config(N=N, seed=seed + i, psi_deg=span_deg * i / n_angles)
+        c["name"] = f"scan-{i}"
+        out.append(c)
+    return out
 
 
 def crystal_config(N=100_000_000, seed=0):
