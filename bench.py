@@ -11,8 +11,9 @@ is the powder cylinder (1e7 histories, Bragg + one-phonon kernels, 3 orders,
 - adjoint: seconds per gradient step (forward + loss/dL/dI + adjoint) on the
   powder sample against 500 DOS bins, sigma_abs and sigma_inc, and its ratio
   to the forward step;
-- plate at 1e9 histories, the crystal-with-can workload at 1e8, and the
-  powder with a multi-phonon kernel at 1e7.
+- plate at 1e9 histories, the crystal-with-can workload at 1e8, the powder
+  with a multi-phonon kernel at 1e7, the crystal with an exact-delta
+  dispersion at 1e7, and a 64-angle goniometer scan of it in one batch.
 
 Roofline: the transport kernel is bound by VALU issue.  Its work per history
 is the sum over primitives of (count per history in the algorithm, from the
@@ -166,6 +167,33 @@ def bench_batched(torch, mcv, W, stream, reps):
            "histories_per_s_batched": total / (t_graph / 1e3),
            "histories_per_s_sequential": total / (t_seq / 1e3),
            "speedup": t_seq / t_graph,
+           "tuning": {"block_size": tuning.block_size, "chunk": tuning.chunk,
+                      "from_cache": bool(cached)}}
+    del plans, hists
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_scan(torch, mcv, W, stream, reps):
+    """Goniometer scan: the crystal-delta sample at 64 rotations, 1e6
+    histories each, in one graph-captured batch vs 64 plain launches."""
+    cfgs = W.goniometer_scan_configs(n_angles=64, N=1_000_000)
+    plans = [mcv.Plan(c) for c in cfgs]
+    hists = [p.zeros() for p in plans]
+    total = sum(c["N"] for c in cfgs)
+    tuning, _, cached = mcv.autotune(plans, hists)
+    b = mcv.Batch(plans, hists, tuning)
+    t_graph = timed(torch, stream, lambda: b.run(stream), reps)
+
+    def sequential():
+        for p, h in zip(plans, hists):
+            h.zero_()
+            p.run(h, stream=stream)
+    t_seq = timed(torch, stream, sequential, reps)
+    b.close()
+    out = {"angles": len(cfgs), "histories": total, "graph_ms": t_graph, "sequential_ms": t_seq,
+           "histories_per_s_batched": total / (t_graph / 1e3),
+           "histories_per_s_sequential": total / (t_seq / 1e3), "speedup": t_seq / t_graph,
            "tuning": {"block_size": tuning.block_size, "chunk": tuning.chunk,
                       "from_cache": bool(cached)}}
     del plans, hists
@@ -359,6 +387,9 @@ def main():
         out["crystal"] = bench_single(torch, mcv, W.crystal_config(), stream, reps, "crystal")
         out["powder_multiphonon"] = bench_single(torch, mcv, W.powder_mp_config(), stream, reps,
                                                  "powder_mp")
+        out["crystal_delta"] = bench_single(torch, mcv, W.crystal_delta_config(), stream, reps,
+                                            "crystal_delta")
+        out["goniometer_scan"] = bench_scan(torch, mcv, W, stream, reps)
     print(json.dumps(out), flush=True)
 
 

@@ -85,7 +85,8 @@ enum {
   MCV_K_PHONON = 3,    /* incoherent one-phonon from a DOS (S4)               */
   MCV_K_SPINWAVE = 4,  /* dispersion surface E(Q), S(Q) = 1, Lorentzian (S4)  */
   MCV_K_SQE = 5,       /* tabulated isotropic S(Q,E) (Sec. 2.4.2)             */
-  MCV_K_MULTIPHONON = 6 /* incoherent multi-phonon, orders 2..N (S4)          */
+  MCV_K_MULTIPHONON = 6, /* incoherent multi-phonon, orders 2..N (S4)         */
+  MCV_K_DISPERSION = 7   /* dispersion surface E(Q), exact delta (S4)         */
 };
 
 /* One scattering kernel.  Only the fields of `type` are read.
@@ -110,6 +111,11 @@ enum {
  *     kernel's DOS.
  *   SPINWAVE: E(Q) = 4 J S (3 - sum_a cos(Q_a a)), Q in the crystal frame
  *     crot * Q_lab; gamma = Lorentzian HWHM.
+ *   DISPERSION: the same E(Q) (J S >= 0) with an exact delta function in
+ *     energy, S(Q) = 1: for an isotropic outgoing direction the outgoing
+ *     wave numbers solving E_i - E_f = E(Q) are bracketed on 256 equal cells
+ *     of [0, k_i] (root pairs closer than a cell are not resolved) and one is
+ *     taken at random; weight n k_f/k_i / |dG/dE_f|.  gamma is not read.
  *   SQE: S(Q,E) on nQ x nE cells over [0, Qmax] x [Emin, Emax], row major
  *     with Q slow; E is the energy transfer to the sample. */
 typedef struct {

@@ -73,6 +73,7 @@ const double kTauTof = 4e-6;     // relative time of flight
 const double kTauImpact = 4e-4;  // relative impact parameter in a tube
 const double kTauU = 2e-6;       // absolute, for u < p tests on computed p
 const double kTauJ = 5e-2;       // |dG/dE_f| of a delta-function root (tangency)
+const double kTauDk = 1e-4;      // relative uncertainty of a delta-function root
 // Conditioning of a single-precision implementation (reported, not used by
 // the method): a position of ~1 cm is known to ~3e-9 m in binary32 (half an
 // ulp, 4.7e-10 m, per coordinate from each of the roundings of a birth point
@@ -308,6 +309,7 @@ struct Packet {
   double ddir;        // see ORecord
   double dpos;        // see ORecord
   double dtime;       // see ORecord
+  double dsp = 2e-7;  // relative uncertainty of the speed in binary32 (conditioning)
   std::vector<double> dlogw;  // d log(w) / d(parameters), when gradients are on
 };
 
@@ -831,8 +833,14 @@ Scatter k_dispersion(const OKernel& k, const Packet& P, const double* u, double*
   // conditioning: a binary32 evaluation of g is uncertain by ~4e-7 (E_i +
   // wmax), which moves the root by that over |dg/dk| = 2 c k_f |J|, and the
   // phases Q_a a (up to ~40 rad) by ~2.4e-6 rad
-  const double eg = 4e-7 * (Ei + wmax);
+  // and the incident direction's own uncertainty moves Q by k_i ddir,
+  // omega by |grad omega| times that, and the root accordingly; a root
+  // known to worse than kTauDk is a near decision for what follows (the
+  // outgoing speed sets cone angles and cross sections downstream)
+  const double dq = k_i * (P.ddir + 2e-7 + P.dsp) + k_f * 2e-7 + (k_i + k_f) * 2e-7 * P.cond;
+  const double eg = 4e-7 * (Ei + wmax) + norm(grad) * dq;
   r.dk_rel = eg / (2.0 * c * k_f * k_f * std::fabs(J));
+  *margin = std::min(*margin, kTauDk / r.dk_rel);
   r.wsens_add = std::fabs(A) * (2.4e-6 + r.dk_rel) / std::fabs(J) + r.dk_rel;
   r.dq_sens = 0.0;
   return r;
@@ -1325,8 +1333,14 @@ struct Sim {
           double Ein = kEperV2 * P.speed * P.speed;
           double Eout = kEperV2 * C.speed * C.speed;
           C.cond = P.cond * (Eout > 0.0 ? std::max(1.0, Ein / Eout) : 1.0);
-          C.dpos = P.dpos + P.ddir * (iv.s_in + x) + kEpsPos + dL;
-          C.dtime = P.dtime + (dL + kEpsPos) / P.speed;
+          // the birth point sits x into the interval, with x ~ 1/mu(speed)
+          C.dpos = P.dpos + P.ddir * (iv.s_in + x) + kEpsPos + dL + x * P.dsp;
+          C.dtime = P.dtime + (dL + kEpsPos) / P.speed + (iv.s_in + x) / P.speed * P.dsp;
+          // the child's speed: unchanged by elastic kernels, amplified by
+          // E_i/E_f through an energy loss, plus a delta-function root
+          C.dsp = Eout == Ein ? P.dsp
+                              : P.dsp * (Eout > 0.0 ? std::max(1.0, Ein / Eout) : 1.0) + 2e-7;
+          C.dsp += r.dk_rel;
           if (r.dq_sens > 0.0) {
             double kin = k_from_speed(P.speed), kout = k_from_speed(C.speed);
             double dq = kin * (P.ddir + 2e-7) + kout * 2e-7 + (kin + kout) * 2e-7 * P.cond;
@@ -1340,7 +1354,7 @@ struct Sim {
             double c = dot(P.dir, C.dir);
             double th = 0.5 * std::acos(std::max(-1.0, std::min(1.0, c)));
             double tn = std::tan(std::min(th, 0.5 * kPi - 1e-6));
-            C.ddir = P.ddir + 2e-7 + 2.0 * tn * 2e-7 * P.cond;
+            C.ddir = P.ddir + 2e-7 + 2.0 * tn * std::max(2e-7 * P.cond, P.dsp);
           } else {
             C.ddir = 2e-7;  // a fresh isotropic direction
           }
@@ -1360,7 +1374,7 @@ struct Sim {
       P.pos = add(start, scale(P.dir, s_end));
       P.t = t0 + s_end / P.speed;
       P.dpos += P.ddir * s_end + last_dL_exit;
-      P.dtime += last_dL_exit / P.speed;
+      P.dtime += last_dL_exit / P.speed + s_end / P.speed * P.dsp;
     }
   }
 
@@ -1406,6 +1420,7 @@ struct Sim {
     P.ddir = 0.0;
     P.dpos = 0.0;
     P.dtime = 0.0;
+    P.dsp = 2e-7;
     if (tangent) P.dlogw.assign(np, 0.0);
   }
 };

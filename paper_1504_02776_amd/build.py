@@ -38,16 +38,20 @@ def build(verbose: bool = False, out: str = LIB, extra=(), sources=None) -> str:
               # correctly rounded sequences are ~10 instructions each
               "-fno-hip-fp32-correctly-rounded-divide-sqrt",
               "-I", os.path.join(HERE, "..", "include"), "-Wall"] + list(extra)
+    cmds = []
     for src in sources:
         obj = os.path.join(bdir, src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [hipcc()] + common + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-        if verbose and r.stderr.strip():
-            print(r.stderr)
+        cmds.append([hipcc()] + common + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # the translation units are independent: compile them side by side
+    procs = [subprocess.Popen(c, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+             for c in cmds]
+    for c, pr in zip(cmds, procs):
+        so, err = pr.communicate()
+        if pr.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(c)}\n{so}\n{err}")
+        if verbose and err.strip():
+            print(err)
     tmp = out + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -62,6 +66,14 @@ def build_probe(verbose: bool = False) -> str:
     return build(verbose, out=PROBE_LIB, sources=PROBE_SOURCES)
 
 
+def build_all(verbose: bool = False):
+    """libmcv.so and libmcv_probe.so, built concurrently."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(2) as ex:
+        a = ex.submit(build, verbose)
+        b = ex.submit(build_probe, verbose)
+        return a.result(), b.result()
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
-    print(build_probe(verbose=True))
+    print(build_all(verbose=True))

@@ -213,6 +213,12 @@ mcv_status check_kernel(const mcv_kernel& k) {
       if (!(s > 0.0)) return fail(MCV_EINVAL, "DOS must have positive area");
       return MCV_OK;
     }
+    case MCV_K_DISPERSION:
+      if (!(k.sigma_b >= 0.0) || !(k.a > 0.0) || !std::isfinite(k.J) || !std::isfinite(k.S) ||
+          !(k.J * k.S >= 0.0) || !finite_all(k.crot, 9))
+        return fail(MCV_EINVAL, "dispersion kernel needs a > 0 and J S >= 0");
+      if (k.dw) return fail(MCV_EUNSUPPORTED, "Debye-Waller factor not supported for the dispersion kernel");
+      return MCV_OK;
     case MCV_K_SPINWAVE:
       if (!(k.sigma_b >= 0.0) || !(k.gamma > 0.0) || !(k.a > 0.0) || !finite_all(k.crot, 9))
         return fail(MCV_EINVAL, "spin-wave kernel needs gamma > 0 and a > 0");
@@ -529,7 +535,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
         K.h2m = (float)(kHbar2over2mn * kNeutronMassAmu / k.M_amu);
         K.dw_self = (float)(kHbar2over2mn * kNeutronMassAmu / k.M_amu * g0);
         K.nmax = k.max_phonons;
-      } else if (k.type == MCV_K_SPINWAVE) {
+      } else if (k.type == MCV_K_SPINWAVE || k.type == MCV_K_DISPERSION) {
         K.j4s = (float)(4.0 * k.J * k.S);
         K.wmax = (float)(24.0 * k.J * k.S);
         K.a = (float)k.a;
@@ -607,6 +613,10 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
                                                                     block, 0, 0),
                       block, transport_waves_per_eu(P.nscat, P.smax));
   P.hot_all = mcv_detector_nbins(d) <= kHotAllBins ? 1 : 0;
+  P.heavy = 0;
+  for (int si = 0; si < P.nscat; ++si)
+    for (int j = 0; j < P.s[si].nk; ++j)
+      P.heavy |= P.s[si].k[j].type == K_DISPERSION;
   p->block = block;
   p->device = device;
   p->scat = a->scat;

@@ -470,6 +470,109 @@ __device__ __forceinline__ Out k_spinwave(const DevKernel& K, const Pk& P, const
   return o;
 }
 
+// Dispersion surface with an exact delta function (Supplement S4, E_vQ
+// kernel, S(Q) = 1): for the isotropic outgoing direction d, the outgoing
+// wave numbers are the roots of g(k) = E_i - c k^2 - omega(k_i - k d) on
+// [0, k_i].  They are bracketed by the sign changes of g (g > 0 against
+// g <= 0) at kDispCells + 1 equally spaced k, one is picked (u2), refined by
+// bisection, and the weight n (k_f/k_i) / |dG/dE_f| with dG/dE_f = -1 +
+// (grad omega . d) / (2 c k_f) carries the delta function.  The scan steps
+// the phases Q_a a linearly in k with a rotation recurrence, restarted from
+// sincos every 32 cells; the cells with a sign change are kept as a bit mask.
+constexpr int kDispCells = 256;
+
+__device__ __forceinline__ float disp_g(float Ei, float k, float q0x, float q0y, float q0z,
+                                        float dcx, float dcy, float dcz, float a, float j4s) {
+  return Ei - kHb2m * k * k -
+         j4s * (3.0f - cosf((q0x - k * dcx) * a) - cosf((q0y - k * dcy) * a) -
+                cosf((q0z - k * dcz) * a));
+}
+
+__device__ __forceinline__ Out k_dispersion(const DevKernel& K, const Pk& P, const float* u) {
+  Out o;
+  o.bin = -1;
+  o.dwq2 = 0.0f;
+  o.f = 0.0f;
+  o.sp = P.sp;
+  iso_dir(u[3], u[4], o.dx, o.dy, o.dz);
+  const float Ei = kEperV2 * P.sp * P.sp;
+  const float ki = P.sp * kKperV;
+  const float* C = K.crot;
+  const float q0x = ki * (C[0] * P.dx + C[1] * P.dy + C[2] * P.dz);
+  const float q0y = ki * (C[3] * P.dx + C[4] * P.dy + C[5] * P.dz);
+  const float q0z = ki * (C[6] * P.dx + C[7] * P.dy + C[8] * P.dz);
+  const float dcx = C[0] * o.dx + C[1] * o.dy + C[2] * o.dz;
+  const float dcy = C[3] * o.dx + C[4] * o.dy + C[5] * o.dz;
+  const float dcz = C[6] * o.dx + C[7] * o.dy + C[8] * o.dz;
+  const float a = K.a, j4s = K.j4s;
+  const float h = ki * (1.0f / (float)kDispCells);
+  float sdx, cdx, sdy, cdy, sdz, cdz;  // rotation by one cell
+  sincosf(-h * dcx * a, &sdx, &cdx);
+  sincosf(-h * dcy * a, &sdy, &cdy);
+  sincosf(-h * dcz * a, &sdz, &cdz);
+  uint32_t mask[kDispCells / 32];
+  bool prev = false;
+  int n = 0;
+#pragma unroll
+  for (int w = 0; w < kDispCells / 32; ++w) {
+    const float k0 = (float)(32 * w) * h;
+    float sx, cx, sy, cy, sz, cz;
+    sincosf((q0x - k0 * dcx) * a, &sx, &cx);
+    sincosf((q0y - k0 * dcy) * a, &sy, &cy);
+    sincosf((q0z - k0 * dcz) * a, &sz, &cz);
+    if (w == 0) prev = Ei - j4s * (3.0f - cx - cy - cz) > 0.0f;
+    uint32_t bits = 0u;
+    for (int j = 0; j < 32; ++j) {
+      float t = cx * cdx - sx * sdx;
+      sx = sx * cdx + cx * sdx;
+      cx = t;
+      t = cy * cdy - sy * sdy;
+      sy = sy * cdy + cy * sdy;
+      cy = t;
+      t = cz * cdz - sz * sdz;
+      sz = sz * cdz + cz * sdz;
+      cz = t;
+      const float k = (float)(32 * w + j + 1) * h;
+      const bool pos = Ei - kHb2m * k * k - j4s * (3.0f - cx - cy - cz) > 0.0f;
+      bits |= (uint32_t)(pos != prev) << j;
+      prev = pos;
+    }
+    mask[w] = bits;
+    n += __popc(bits);
+  }
+  if (n == 0) return o;
+  int pick = (int)floorf(u[2] * (float)n);
+  pick = pick > n - 1 ? n - 1 : pick;
+  int cell = 0;
+#pragma unroll
+  for (int w = 0; w < kDispCells / 32; ++w) {
+    const int c = __popc(mask[w]);
+    if (pick >= 0 && pick < c) {
+      uint32_t b = mask[w];
+      for (int q = 0; q < pick; ++q) b &= b - 1u;
+      cell = 32 * w + __ffs(b) - 1;
+    }
+    pick -= c;
+  }
+  float lo = (float)cell * h, hi = (float)(cell + 1) * h;
+  const bool slo = disp_g(Ei, lo, q0x, q0y, q0z, dcx, dcy, dcz, a, j4s) > 0.0f;
+  for (int it = 0; it < 24; ++it) {
+    const float mid = 0.5f * (lo + hi);
+    if ((disp_g(Ei, mid, q0x, q0y, q0z, dcx, dcy, dcz, a, j4s) > 0.0f) == slo) lo = mid;
+    else hi = mid;
+  }
+  const float kf = 0.5f * (lo + hi);
+  if (!(kf > 0.0f)) return o;
+  const float ga = j4s * a;
+  const float A = ga * (sinf((q0x - kf * dcx) * a) * dcx + sinf((q0y - kf * dcy) * a) * dcy +
+                        sinf((q0z - kf * dcz) * a) * dcz) / (2.0f * kHb2m * kf);
+  const float J = A - 1.0f;
+  if (J == 0.0f) return o;
+  o.sp = kf * kVperK;
+  o.f = (float)n * (kf / ki) / fabsf(J);
+  return o;
+}
+
 __device__ __forceinline__ Out k_sqe(const DevKernel& K, const float* tab, const Pk& P,
                                      const float* u) {
   Out o;
@@ -777,10 +880,16 @@ __device__ __forceinline__ void segment_terms(const DevScat& S, const float* tab
 }
 
 // (id, lin, seed): the packet's scattering stream, for kernels that draw
-// beyond the split's eight uniforms
+// beyond the split's eight uniforms.  HEAVY: also the exact-delta kernel,
+// whose root scan would otherwise raise the register count of every plan
+// (plans without it use the instantiations without that case).
+template <bool HEAVY>
 __device__ __forceinline__ Out kernel_eval(const DevKernel& K, const DevScat& S,
                                            const float* tab, const Pk& P, const float* u,
                                            uint64_t id, uint32_t lin, uint64_t seed) {
+  if constexpr (HEAVY) {
+    if (K.type == K_DISPERSION) return k_dispersion(K, P, u);
+  }
   switch (K.type) {
     case K_ISO_EL: return k_iso(K, S, P, u);
     case K_POWDER: return k_powder(K, S, tab, P, u);
@@ -895,7 +1004,7 @@ __device__ __forceinline__ void flight_exit(Pk& P, const Flight<NSC, TWO>& F) {
 // e^{-mu L}; with SPLIT (and order < K, w >= min_prob, mu_s > 0) a
 // forced-collision child is born in it, its kernel drawn and evaluated.  The
 // first child of a flight is kept in `nxt`, further ones go to the stack.
-template <bool ADJ, bool SPLIT, int NSC, bool TWO>
+template <bool ADJ, bool SPLIT, int NSC, bool TWO, bool HEAVY>
 __device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
                                             const AdjArgs& AA, Pk& P, Adj& pa,
                                             Flight<NSC, TWO>& F, uint64_t id, uint64_t seed,
@@ -945,7 +1054,7 @@ __device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
     const int kk = split_child(S, mu, pint, P, F.sx, F.sy, F.sz, F.t0, slo,
                                (int)((F.codes >> (4 * j)) & 0xFu), u, lin, C, x);
     const DevKernel& K = S.k[kk];
-    const Out o = kernel_eval(K, S, tab, P, u, id, lin, seed);
+    const Out o = kernel_eval<HEAVY>(K, S, tab, P, u, id, lin, seed);
     C.dx = o.dx;
     C.dy = o.dy;
     C.dz = o.dz;
@@ -1171,7 +1280,7 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
 //      attenuation only and waits for the next D phase.
 // Called with the whole wave active.  `acc` is the workgroup's LDS block:
 // adjoint partials (MODE_ADJOINT) or the histogram bin cache (otherwise).
-template <int MODE, int NSC, bool TWO>
+template <int MODE, int NSC, bool TWO, bool HEAVY>
 __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab, float* st,
                                              const DevBeam& beam, uint64_t seed, uint64_t first,
                                              uint64_t begin, uint64_t end, const Sinks& out,
@@ -1199,7 +1308,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
     if ((mI | mD) == 0ull) break;
     if (__popcll(mI) >= __popcll(mD)) {
       if (state == LANE_FLY) {
-        flight_step<ADJ, true, NSC, TWO>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
+        flight_step<ADJ, true, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
                                          st, nst, nthreads, tid);
         if (F.valid == 0u) {
           flight_exit(cur, F);
@@ -1244,7 +1353,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
       flight_setup(PL, cur, F);
       if (order_of(cur.lin) >= PL.K || cur.w < PL.min_prob) {
         while (F.valid != 0u)
-          flight_step<ADJ, false, NSC, TWO>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
+          flight_step<ADJ, false, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
                                             st, nst, nthreads, tid);
       }
       if (F.valid != 0u) {
@@ -1258,7 +1367,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
   }
 }
 
-template <int MODE, int NSC, bool TWO>
+template <int MODE, int NSC, bool TWO, bool HEAVY>
 __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, float* st,
                                            const DevBeam& beam, uint64_t seed, uint64_t first,
                                            uint64_t begin, uint64_t end, const Sinks& out,
@@ -1302,7 +1411,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
       Flight<NSC, TWO> F;
       flight_setup(PL, cur, F);
       while (F.valid != 0u)
-        flight_step<ADJ, true, NSC, TWO>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
+        flight_step<ADJ, true, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
                                          st, nst, nthreads, tid);
       flight_exit(cur, F);
       record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
@@ -1325,17 +1434,17 @@ __host__ __device__ constexpr bool use_phased(int nscat, bool two, int K) {
   return nscat <= 1 && !two && K >= 2;
 }
 
-template <int MODE, int NSC, bool TWO, bool PHASED>
+template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY>
 __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab, float* st,
                                             const DevBeam& beam, uint64_t seed, uint64_t first,
                                             uint64_t begin, uint64_t end, const Sinks& out,
                                             const AdjArgs& AA, double* acc, int hot_n,
                                             int nthreads, int tid) {
   if constexpr (PHASED)
-    trace_phased<MODE, NSC, TWO>(PL, tab, st, beam, seed, first, begin, end, out, AA, acc, hot_n,
+    trace_phased<MODE, NSC, TWO, HEAVY>(PL, tab, st, beam, seed, first, begin, end, out, AA, acc, hot_n,
                                  nthreads, tid);
   else
-    trace_walk<MODE, NSC, TWO>(PL, tab, st, beam, seed, first, begin, end, out, AA, acc, hot_n,
+    trace_walk<MODE, NSC, TWO, HEAVY>(PL, tab, st, beam, seed, first, begin, end, out, AA, acc, hot_n,
                                nthreads, tid);
 }
 
@@ -1354,7 +1463,7 @@ __device__ __forceinline__ void stage_plan(DevPlan& PL, float* dyn, const DevPla
 // numbers) and accumulates dL/dtheta = sum over recorded packets of
 // dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
 // per workgroup.
-template <int MODE, int NSC, bool TWO, bool PHASED>
+template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     NSC == 1 && !TWO ? MCV_WAVES_PER_EU_SIMPLE : MCV_WAVES_PER_EU)))
 transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
@@ -1380,7 +1489,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
   if (begin < n)  // uniform per wave
-    trace_range<MODE, NSC, TWO, PHASED>(PL, dyn, st, beam, seed, first, begin,
+    trace_range<MODE, NSC, TWO, PHASED, HEAVY>(PL, dyn, st, beam, seed, first, begin,
                                 begin + per_wave < n ? begin + per_wave : n, out, AA, acc, hot_n,
                                 nthreads, tid);
   if (!ADJ) {
@@ -1443,22 +1552,29 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     // the same specialisation as a plain launch of this plan, so that both
     // evaluate identical arithmetic
     const bool two = PL.smax > PL.nscat;
-#define MCV_BATCH_TRACE(NSC_, TWO_, PH_)                                                        \
-  trace_range<MODE_RUN, NSC_, TWO_, PH_>(PL, tab, st, it.beam, it.seed, it.id0, b, ee, out, AA, \
-                                         hot, hot_n, nthreads, tid)
+#define MCV_BATCH_TRACE(NSC_, TWO_, PH_, HV_)                                          \
+  trace_range<MODE_RUN, NSC_, TWO_, PH_, HV_>(PL, tab, st, it.beam, it.seed, it.id0, b, ee, \
+                                              out, AA, hot, hot_n, nthreads, tid)
+#define MCV_BATCH_SHAPES(HV_)                                                       \
+  if (PL.nscat <= 1) {                                                              \
+    if (two) MCV_BATCH_TRACE(1, true, false, HV_);                                  \
+    else if (use_phased(PL.nscat, two, PL.K)) MCV_BATCH_TRACE(1, false, true, HV_); \
+    else MCV_BATCH_TRACE(1, false, false, HV_);                                     \
+  } else if (PL.nscat == 2) {                                                       \
+    if (two) MCV_BATCH_TRACE(2, true, false, HV_);                                  \
+    else MCV_BATCH_TRACE(2, false, false, HV_);                                     \
+  } else {                                                                          \
+    if (two) MCV_BATCH_TRACE(4, true, false, HV_);                                  \
+    else MCV_BATCH_TRACE(4, false, false, HV_);                                     \
+  }
     if (b < e) {
-      if (PL.nscat <= 1) {
-        if (two) MCV_BATCH_TRACE(1, true, false);
-        else if (use_phased(PL.nscat, two, PL.K)) MCV_BATCH_TRACE(1, false, true);
-        else MCV_BATCH_TRACE(1, false, false);
-      } else if (PL.nscat == 2) {
-        if (two) MCV_BATCH_TRACE(2, true, false);
-        else MCV_BATCH_TRACE(2, false, false);
+      if (PL.heavy) {
+        MCV_BATCH_SHAPES(true)
       } else {
-        if (two) MCV_BATCH_TRACE(4, true, false);
-        else MCV_BATCH_TRACE(4, false, false);
+        MCV_BATCH_SHAPES(false)
       }
     }
+#undef MCV_BATCH_SHAPES
 #undef MCV_BATCH_TRACE
     __syncthreads();
     hot_flush(hot, hot_n, it.hist, nullptr, nthreads, tid);
@@ -1566,22 +1682,23 @@ size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, i
 
 namespace {
 
-template <int MODE, int NSC, bool TWO, bool PHASED>
+template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY>
 void launch_one(int grid, int block, size_t lds, hipStream_t stream, const DevPlan* plan,
                 const float* tables, const DevBeam& beam, uint64_t seed, uint64_t first,
                 uint64_t n, uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
-  hipLaunchKernelGGL((dev::transport<MODE, NSC, TWO, PHASED>), dim3(grid), dim3(block), lds, stream, plan,
+  hipLaunchKernelGGL((dev::transport<MODE, NSC, TWO, PHASED, HEAVY>), dim3(grid), dim3(block), lds,
+                     stream, plan,
                      tables, beam, seed, first, n, per_wave, out, AA);
 }
 
-template <int MODE>
-void launch_mode(int nsc, bool two, bool phased, int grid, int block, size_t lds,
-                 hipStream_t stream, const DevPlan* plan, const float* tables,
-                 const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
-                 uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
-#define MCV_LAUNCH(NSC_, TWO_, PH_)                                                            \
-  launch_one<MODE, NSC_, TWO_, PH_>(grid, block, lds, stream, plan, tables, beam, seed, first, \
-                                    n, per_wave, out, AA)
+template <int MODE, bool HEAVY>
+void launch_shapes(int nsc, bool two, bool phased, int grid, int block, size_t lds,
+                   hipStream_t stream, const DevPlan* plan, const float* tables,
+                   const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
+                   uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
+#define MCV_LAUNCH(NSC_, TWO_, PH_)                                                          \
+  launch_one<MODE, NSC_, TWO_, PH_, HEAVY>(grid, block, lds, stream, plan, tables, beam, seed, \
+                                           first, n, per_wave, out, AA)
   if (nsc <= 1) {
     if (two) MCV_LAUNCH(1, true, false);
     else if (phased) MCV_LAUNCH(1, false, true);
@@ -1594,6 +1711,19 @@ void launch_mode(int nsc, bool two, bool phased, int grid, int block, size_t lds
     else MCV_LAUNCH(4, false, false);
   }
 #undef MCV_LAUNCH
+}
+
+template <int MODE>
+void launch_mode(int nsc, bool two, bool phased, bool heavy, int grid, int block, size_t lds,
+                 hipStream_t stream, const DevPlan* plan, const float* tables,
+                 const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
+                 uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
+  if (heavy)
+    launch_shapes<MODE, true>(nsc, two, phased, grid, block, lds, stream, plan, tables, beam,
+                              seed, first, n, per_wave, out, AA);
+  else
+    launch_shapes<MODE, false>(nsc, two, phased, grid, block, lds, stream, plan, tables, beam,
+                               seed, first, n, per_wave, out, AA);
 }
 
 }  // namespace
@@ -1613,15 +1743,16 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
   const int nsc = host_plan.nscat;
   const bool two = host_plan.smax > host_plan.nscat;
   const bool phased = dev::use_phased(nsc, two, host_plan.K);
+  const bool heavy = host_plan.heavy != 0;
   if (adj) {
     hipLaunchKernelGGL(dev::zero2, dim3(1), dim3(64), 0, stream, AA.sums);
-    launch_mode<dev::MODE_ADJOINT>(nsc, two, phased, grid, block, lds, stream, plan, tables, beam, seed,
+    launch_mode<dev::MODE_ADJOINT>(nsc, two, phased, heavy, grid, block, lds, stream, plan, tables, beam, seed,
                                    first, n, per_wave, out, AA);
   } else if (rec) {
-    launch_mode<dev::MODE_TRACE>(nsc, two, phased, grid, block, lds, stream, plan, tables, beam, seed,
+    launch_mode<dev::MODE_TRACE>(nsc, two, phased, heavy, grid, block, lds, stream, plan, tables, beam, seed,
                                  first, n, per_wave, out, AA);
   } else {
-    launch_mode<dev::MODE_RUN>(nsc, two, phased, grid, block, lds, stream, plan, tables, beam, seed,
+    launch_mode<dev::MODE_RUN>(nsc, two, phased, heavy, grid, block, lds, stream, plan, tables, beam, seed,
                                first, n, per_wave, out, AA);
   }
   return hipGetLastError();
@@ -1668,15 +1799,20 @@ int transport_waves_per_eu(int nscat, int smax) {
 int batch_waves_per_eu() { return MCV_WAVES_PER_EU; }
 
 namespace {
+template <int MODE, bool HV>
+void push_shapes(std::vector<const void*>& v) {
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, false, HV>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, true, HV>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, true, false, HV>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, false, false, HV>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, true, false, HV>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, false, false, HV>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, true, false, HV>));
+}
 template <int MODE>
 void push_mode(std::vector<const void*>& v) {
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, false>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, true>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, true, false>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, false, false>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, true, false>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, false, false>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, true, false>));
+  push_shapes<MODE, false>(v);
+  push_shapes<MODE, true>(v);
 }
 }  // namespace
 

@@ -23,7 +23,8 @@ STATUS_NAMES = ["MCV_OK", "MCV_EINVAL", "MCV_EUNSUPPORTED", "MCV_EOVERLAP", "MCV
                 "MCV_ECAPACITY", "MCV_EHIP"]
 
 SHAPES = {"box": 1, "cylinder": 2, "annulus": 3}
-KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6}
+KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6,
+           "dispersion": 7}
 
 
 class MCVError(RuntimeError):
@@ -173,8 +174,8 @@ def _kernel_struct(k, keep):
         s.M_amu, s.T_K, s.emax = k["M"], k["T"], k["emax"]
         s.nbins, s.dos = len(dos), _dptr(dos)
         s.max_phonons = int(k.get("nmax", 0))
-    elif t == "spinwave":
-        s.J, s.S, s.a, s.gamma = k["J"], k["S"], k["a"], k["gamma"]
+    elif t in ("spinwave", "dispersion"):
+        s.J, s.S, s.a, s.gamma = k["J"], k["S"], k["a"], k.get("gamma", 0.0)
         s.crot[:] = k["crot"]
     elif t == "sqe":
         g = np.ascontiguousarray(np.asarray(k["S"], dtype=np.float64).reshape(-1))

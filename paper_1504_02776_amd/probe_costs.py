@@ -30,7 +30,8 @@ ITERS = 2048         # calls per lane
 REPS = 3
 
 PR_NULL, PR_RNG, PR_SOURCE, PR_SHAPE, PR_SEGMENT, PR_SPLIT, PR_KERNEL, PR_DETECT = range(8)
-KERNEL_TYPES = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6}
+KERNEL_TYPES = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6,
+                "dispersion": 7}
 
 
 def _bind():
@@ -95,7 +96,8 @@ def main():
            "grid": GRID, "iters": ITERS, "unit": "VALU lane-op slots per call", "workloads": {}}
     for name, cfg in [("powder", W.powder_config()), ("plate", W.plate_config()),
                       ("crystal", W.crystal_config()), ("sqe", W.sqe_config()),
-                      ("powder_mp", W.powder_mp_config())]:
+                      ("powder_mp", W.powder_mp_config()),
+                      ("crystal_delta", W.crystal_delta_config())]:
         res["workloads"][name] = probe_workload(cfg)
         print(f"[probe] {name}: {json.dumps(res['workloads'][name])}", flush=True)
     with open(args.out, "w") as f:
