@@ -171,13 +171,22 @@ mcv_status mcv_detector_sphere(mcv_detector* out, double R, int32_t n_2theta, in
  * value = weight * (1 - exp(-mu_He chord)); the absorption point is drawn
  * on the chord; pixel = floor(n_pix (y_abs - y_bottom) / length); bin =
  * ((tube * n_pix + pixel) * n_tof + tof_bin), tube = r * ncols + c.
+ * Packs (Sec. 2.4.1-2.4.3: 8 tubes make an 8-pack, packs make the detector
+ * system): with tubes_per_pack = P > 0 the columns form ncols / P packs with
+ * pack_gap radians of extra azimuth between neighbouring packs, and the tube
+ * pitch d = (phi_hi - phi_lo - (ncols/P - 1) pack_gap) / ncols puts column c
+ * at phi_c = phi_lo + floor(c/P) pack_gap + (c + 1/2) d; P = 0: evenly
+ * spaced columns (pack_gap not read).
  * Requirements: row_y ascending, nrows <= 8, neighbouring tubes do not
- * overlap, R >= 10 radius. */
+ * overlap, R >= 10 radius, P divides ncols, pack_gap >= 0. */
 typedef struct {
   int32_t nrows, ncols;
   double R, phi_lo, phi_hi;
   double row_y[8];
   double length, radius, n_he;
+  int32_t tubes_per_pack;
+  int32_t reserved;
+  double pack_gap;
 } mcv_tube_layout;
 
 mcv_status mcv_detector_tubes(mcv_detector* out, const mcv_tube_layout* layout, int32_t n_pix,

@@ -157,7 +157,22 @@ struct ODetector {
   double phi_lo, phi_hi;  // rad, tube columns
   double row_y[8];
   double length, radius, n_he;
+  int32_t tubes_per_pack;  // 0: evenly spaced columns; else packs of this many tubes
+  int32_t pad;
+  double pack_gap;         // rad, extra azimuth between neighbouring packs
 };
+
+// Azimuth of the axis of tube column c.  Columns are grouped in packs of
+// tubes_per_pack tubes (the instruments' 8-packs, Sec. 2.4.1-2.4.3) with a gap
+// between packs; the tube pitch d fills [phi_lo, phi_hi] with the packs and
+// their gaps: phi_c = phi_lo + floor(c / P) gap + (c + 1/2) d.
+double column_phi(const ODetector& D, int c) {
+  const int P = D.tubes_per_pack;
+  if (P <= 0) return D.phi_lo + (c + 0.5) * (D.phi_hi - D.phi_lo) / D.ncols;
+  const int npack = D.ncols / P;
+  const double d = (D.phi_hi - D.phi_lo - (npack - 1) * D.pack_gap) / D.ncols;
+  return D.phi_lo + (c / P) * D.pack_gap + (c + 0.5) * d;
+}
 
 struct OSetup {
   OBeam beam;
@@ -1046,11 +1061,10 @@ struct Sim {
     double best = kHuge, second = kHuge;
     int best_tube = -1;
     double best_out = 0.0, best_b = 0.0, best_dperp = 0.0;
-    double dphi = (D.phi_hi - D.phi_lo) / D.ncols;
     for (int row = 0; row < D.nrows; ++row) {
       for (int col = 0; col < D.ncols; ++col) {
         tally->n_tube_tests++;
-        double phi = D.phi_lo + (col + 0.5) * dphi;
+        double phi = column_phi(D, col);
         V3 c = {D.R * std::sin(phi), D.row_y[row], D.R * std::cos(phi)};
         V3 p = sub(P.pos, c);
         double lo, hi, m = kHuge;
@@ -1115,7 +1129,7 @@ struct Sim {
       (void)best_b;
       (void)best_dperp;
       int brow = best_tube / D.ncols, bcol = best_tube % D.ncols;
-      double phi = D.phi_lo + (bcol + 0.5) * dphi;
+      double phi = column_phi(D, bcol);
       V3 c = {D.R * std::sin(phi), D.row_y[brow], D.R * std::cos(phi)};
       V3 e1, e2;
       double mdummy = kHuge;

@@ -63,7 +63,8 @@ class ODetector(C.Structure):
                 ("nrows", C.c_int32), ("ncols", C.c_int32), ("npix", C.c_int32),
                 ("R", C.c_double), ("tof_lo", C.c_double), ("tof_hi", C.c_double),
                 ("phi_lo", C.c_double), ("phi_hi", C.c_double), ("row_y", C.c_double * 8),
-                ("length", C.c_double), ("radius", C.c_double), ("n_he", C.c_double)]
+                ("length", C.c_double), ("radius", C.c_double), ("n_he", C.c_double),
+                ("tubes_per_pack", C.c_int32), ("pad", C.c_int32), ("pack_gap", C.c_double)]
 
 
 class OSetup(C.Structure):
@@ -190,6 +191,8 @@ class Setup:
             D.phi_lo, D.phi_hi = d["phi_lo"], d["phi_hi"]
             D.row_y[:len(d["row_y"])] = d["row_y"]
             D.length, D.radius, D.n_he = d["length"], d["radius"], d["n_he"]
+            D.tubes_per_pack = int(d.get("tubes_per_pack", 0))
+            D.pack_gap = float(d.get("pack_gap", 0.0))
         self.S = S
 
     def _arr(self, x):

@@ -89,6 +89,18 @@ int hot_slots(size_t base, int block, int waves_per_simd) {
   return n;
 }
 
+// Azimuthal pitch of neighbouring tubes within a pack, and the azimuth of
+// column c: phi_lo + floor(c / P) gap + (c + 1/2) pitch (P = 0: no packs).
+double tube_pitch(const mcv_tube_layout& L) {
+  const int P = L.tubes_per_pack;
+  const int npack = P > 0 ? L.ncols / P : 1;
+  return (L.phi_hi - L.phi_lo - (P > 0 ? (npack - 1) * L.pack_gap : 0.0)) / L.ncols;
+}
+double column_azimuth(const mcv_tube_layout& L, int c) {
+  const int P = L.tubes_per_pack;
+  return L.phi_lo + (P > 0 ? (c / P) * L.pack_gap : 0.0) + (c + 0.5) * tube_pitch(L);
+}
+
 int intervals_of(const mcv_shape& s) { return s.type == MCV_SHAPE_ANNULUS ? 2 : 1; }
 
 // lab-frame corners of the bounding box of a shape
@@ -370,7 +382,11 @@ mcv_status mcv_detector_tubes(mcv_detector* out, const mcv_tube_layout* L, int32
       !(L->phi_hi > L->phi_lo) || !(tof_hi > tof_lo))
     return fail(MCV_EINVAL, "tube layout needs R, radius, length > 0, phi_hi > phi_lo");
   if (L->R < 10.0 * L->radius) return fail(MCV_EUNSUPPORTED, "tube circle radius must be >= 10 tube radii");
-  const double dphi = (L->phi_hi - L->phi_lo) / L->ncols;
+  if (L->tubes_per_pack < 0 || (L->tubes_per_pack > 0 && L->ncols % L->tubes_per_pack != 0) ||
+      (L->tubes_per_pack > 0 && !(L->pack_gap >= 0.0)))
+    return fail(MCV_EINVAL, "tubes per pack must divide the columns, with a gap >= 0");
+  const double dphi = tube_pitch(*L);
+  if (!(dphi > 0.0)) return fail(MCV_EINVAL, "pack gaps leave no room for the tubes");
   if (L->ncols > 1 && 2.0 * L->R * std::sin(0.5 * dphi) < 2.0 * L->radius)
     return fail(MCV_EINVAL, "neighbouring tubes overlap");
   if (L->phi_hi - L->phi_lo > 2.0 * kPi) return fail(MCV_EINVAL, "tube columns span more than 2 pi");
@@ -581,15 +597,18 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     D.npix = d->npix;
     D.phi_lo = (float)L.phi_lo;
     D.inv_dphi = (float)(L.ncols / (L.phi_hi - L.phi_lo));
+    D.tpp = L.tubes_per_pack;
+    D.pack_pitch = (float)(L.tubes_per_pack * tube_pitch(L) + L.pack_gap);
+    D.inv_pack_pitch = (float)(1.0 / (L.tubes_per_pack * tube_pitch(L) + L.pack_gap));
+    D.inv_tube_pitch = (float)(1.0 / tube_pitch(L));
     for (int r = 0; r < L.nrows; ++r) D.row_y[r] = (float)L.row_y[r];
     D.half_len = (float)(0.5 * L.length);
     D.radius = (float)L.radius;
     D.mu_he2200 = (float)(100.0 * L.n_he * kHe3SigmaAbs * 2200.0);
     D.pix_scale = (float)(d->npix / L.length);
     D.t_cols = (int)T.size();
-    const double dphi = (L.phi_hi - L.phi_lo) / L.ncols;
     for (int c = 0; c < L.ncols; ++c) {
-      const double phi = L.phi_lo + (c + 0.5) * dphi;
+      const double phi = column_azimuth(L, c);
       T.push_back((float)(L.R * std::sin(phi)));
       T.push_back((float)(L.R * std::cos(phi)));
     }

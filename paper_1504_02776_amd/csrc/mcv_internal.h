@@ -81,6 +81,10 @@ struct DevDet {
   // tubes
   int32_t nrows, ncols, npix;
   float phi_lo, inv_dphi;
+  int32_t tpp;          // tubes per pack (0: evenly spaced columns)
+  float pack_pitch;     // azimuth of one pack plus its gap
+  float inv_pack_pitch;
+  float inv_tube_pitch;
   float row_y[kMaxRows];
   float half_len;
   float radius;

@@ -703,7 +703,16 @@ __device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, c
   const float cq = P.px * P.px + P.pz * P.pz - D.R * D.R;
   const float sR = (-bq + sqrtf(bq * bq - a * cq)) / a;
   const float xR = P.px + sR * P.dx, zR = P.pz + sR * P.dz, yR = P.py + sR * P.dy;
-  const float fc = (atan2f(xR, zR) - D.phi_lo) * D.inv_dphi;
+  // fractional column at the azimuth where the ray crosses radius R; with
+  // packs, a ray in the gap after a pack counts as its last column (the
+  // neighbours tested below include the next pack's first tube)
+  const float ax = atan2f(xR, zR) - D.phi_lo;
+  float fc = ax * D.inv_dphi;
+  if (D.tpp > 0) {
+    const float pk = floorf(ax * D.inv_pack_pitch);
+    const float within = (ax - pk * D.pack_pitch) * D.inv_tube_pitch;
+    fc = pk * (float)D.tpp + fminf(within, (float)D.tpp - 0.5f);
+  }
   if (!(fc > -2.0f && fc < (float)D.ncols + 1.0f)) return h;
   const int col = (int)floorf(fc);
   const float ra = sqrtf(a);

@@ -58,7 +58,9 @@ class mcv_kernel(C.Structure):
 class mcv_tube_layout(C.Structure):
     _fields_ = [("nrows", C.c_int32), ("ncols", C.c_int32), ("R", C.c_double),
                 ("phi_lo", C.c_double), ("phi_hi", C.c_double), ("row_y", C.c_double * 8),
-                ("length", C.c_double), ("radius", C.c_double), ("n_he", C.c_double)]
+                ("length", C.c_double), ("radius", C.c_double), ("n_he", C.c_double),
+                ("tubes_per_pack", C.c_int32), ("reserved", C.c_int32),
+                ("pack_gap", C.c_double)]
 
 
 class mcv_opts(C.Structure):
@@ -226,6 +228,8 @@ class Detector:
             L.nrows, L.ncols = det["nrows"], det["ncols"]
             L.R, L.phi_lo, L.phi_hi = det["R"], det["phi_lo"], det["phi_hi"]
             L.row_y[:len(det["row_y"])] = det["row_y"]
+            L.tubes_per_pack = int(det.get("tubes_per_pack", 0))
+            L.pack_gap = float(det.get("pack_gap", 0.0))
             L.length, L.radius, L.n_he = det["length"], det["radius"], det["n_he"]
             check(lib().mcv_detector_tubes(C.byref(self.h), C.byref(L), det["npix"],
                                            det["ntof"], det["tof_lo"], det["tof_hi"]))

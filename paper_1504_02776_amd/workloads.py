@@ -116,15 +116,31 @@ def sphere_detector(R, n2t, ntof, tof_lo, tof_hi):
 
 def tube_detector(nrows, ncols, npix, ntof, tof_lo, tof_hi, R=3.0, radius=0.0127,
                   length=1.0, phi_lo_deg=10.0, phi_hi_deg=134.0,
-                  row_y=(-1.53, -0.51, 0.51, 1.53), n_he=2.44634e-4):
-    """Vertical 3He tubes on a cylinder of radius R about the vertical axis.
+                  row_y=(-1.53, -0.51, 0.51, 1.53), n_he=2.44634e-4, tubes_per_pack=0,
+                  pack_gap_deg=0.0):
+    """Vertical 3He tubes on a cylinder of radius R about the vertical axis,
+    optionally grouped in packs of `tubes_per_pack` columns with a gap of
+    `pack_gap_deg` of azimuth between packs.
 
     n_he: 3He number density in atoms/A^3 (10 atm at 300 K is 2.44634e-4).
     """
     return {"type": "tubes", "R": R, "nrows": nrows, "ncols": ncols, "npix": npix,
             "ntof": ntof, "tof_lo": tof_lo, "tof_hi": tof_hi, "radius": radius,
             "length": length, "phi_lo": math.radians(phi_lo_deg),
-            "phi_hi": math.radians(phi_hi_deg), "row_y": list(row_y), "n_he": n_he}
+            "phi_hi": math.radians(phi_hi_deg), "row_y": list(row_y), "n_he": n_he,
+            "tubes_per_pack": int(tubes_per_pack), "pack_gap": math.radians(pack_gap_deg)}
+
+
+def eightpack_detector(npix, ntof, tof_lo, tof_hi, npacks=32, R=3.0, radius=0.0127,
+                       length=1.0, phi_lo_deg=-30.0, phi_hi_deg=135.0, gap_deg=0.6,
+                       row_y=(-1.02, 0.0, 1.02)):
+    """Three rows of 8-packs (8 one-inch 3He tubes each) on a cylinder about
+    the vertical axis, with gaps between packs: the layout of the paper's
+    direct-geometry instruments, reduced in size."""
+    return tube_detector(len(row_y), 8 * npacks, npix, ntof, tof_lo, tof_hi, R=R,
+                         radius=radius, length=length, phi_lo_deg=phi_lo_deg,
+                         phi_hi_deg=phi_hi_deg, row_y=row_y, tubes_per_pack=8,
+                         pack_gap_deg=gap_deg)
 
 
 # --------------------------------------------------------------- tables
@@ -247,6 +263,16 @@ def goniometer_scan_configs(n_angles=64, N=1_000_000, seed=0, span_deg=90.0):
         c["name"] = f"scan-{i}"
         out.append(c)
     return out
+
+
+def powder_8pack_config(N=10_000_000, seed=0):
+    """The powder cylinder seen by three rows of 8-packs with gaps
+    (32 packs x 8 tubes x 128 pixels x 1000 tof bins)."""
+    cfg = powder_config(N=N, seed=seed)
+    d = cfg["detector"]
+    cfg["detector"] = eightpack_detector(128, 1000, d["tof_lo"], d["tof_hi"])
+    cfg["name"] = "powder-cylinder-8packs"
+    return cfg
 
 
 def crystal_config(N=100_000_000, seed=0):

@@ -71,3 +71,25 @@ def test_autotune_returns_and_caches(torch_cuda, tmp_path):
     assert ms > 0 and not cached
     t2, ms2, cached2 = mcv.autotune(plans, hb, reps=1, cache=cache)
     assert cached2 and (t2.block_size, t2.chunk) == (t.block_size, t.chunk)
+
+
+def test_goniometer_scan_batch_equals_plain_launches(torch_cuda):
+    """A rotation scan of the crystal with the exact-delta kernel, as one
+    batch: each angle's histogram equals its plain launch."""
+    from paper_1504_02776_amd import mcv
+    torch = torch_cuda
+    cfgs = W.goniometer_scan_configs(n_angles=4, N=3_000)
+    plans = [mcv.Plan(c) for c in cfgs]
+    hb = [p.zeros() for p in plans]
+    print(f"[batch] scan {len(cfgs)} angles", flush=True)
+    b = mcv.Batch(plans, hb, mcv.mcv_tuning(256, 1024, 0, 1))
+    b.run()
+    torch.cuda.synchronize()
+    for p, h, c in zip(plans, hb, cfgs):
+        ref = p.zeros()
+        p.run(ref)
+        torch.cuda.synchronize()
+        a, r = h.cpu().numpy(), ref.cpu().numpy()
+        assert r.sum() > 0, c["name"]
+        assert np.allclose(a, r, rtol=1e-9, atol=1e-14), c["name"]
+    b.close()

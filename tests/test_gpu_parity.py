@@ -22,6 +22,7 @@ def _cases():
         "sqe": (W.sqe_config(), 4_000 + 1),
         "powder-multiphonon": (W.powder_mp_config(), 3_000 + 7),
         "crystal-delta": (W.crystal_delta_config(psi_deg=23.0), 600 + 9),
+        "powder-8packs": (W.powder_8pack_config(), 3_000 + 13),
     }
 
 

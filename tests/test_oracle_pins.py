@@ -599,6 +599,47 @@ def test_tube_pencil_beam_brute_force(oracle_lib):
     assert abs(d.mean() - mean_depth) < 5 * d.std() / math.sqrt(len(d))
 
 
+def _pencil(det, E=60.0, N=400):
+    return {"beam": {"type": "mono", "E": E, "sigma_rel": 0.0, "W": 0.0, "H": 0.9, "z0": -0.1},
+            "scatterers": [], "detector": det, "K": 0, "N": N, "seed": 5}
+
+
+def test_tube_packs_place_columns_by_hand(oracle_lib):
+    """Packs of 2 tubes, 2 packs, pack gap g: the tube pitch is
+    d = (span - g) / 4 and the column centres sit at phi_lo + (0.5, 1.5,
+    2.5 + g/d, 3.5 + g/d) d.  A pencil beam along +z (azimuth 0) placed by
+    hand on column 2 hits exactly that tube with the analytic absorption;
+    placed in the middle of the gap it hits nothing; an azimuth range that
+    centres a tube on the beam without packs misses with them."""
+    R, r = 3.0, 0.0127
+    d = 2.4 * r / R
+    g = 3.0 * d
+    E = 60.0
+    v = speed(E)
+    pabs = 1 - math.exp(-100 * 2.44634e-4 * 5333.0 * 2200.0 / v * 2 * r)
+
+    def det(phi_lo, packs=True):
+        return W.tube_detector(1, 4, 64, 100, 0.0, 2e-3, R=R, radius=r, length=1.0,
+                               phi_lo_deg=math.degrees(phi_lo),
+                               phi_hi_deg=math.degrees(phi_lo + 4 * d + g), row_y=(0.0,),
+                               tubes_per_pack=2 if packs else 0,
+                               pack_gap_deg=math.degrees(g) if packs else 0.0)
+
+    _, _, rec, _ = oracle_lib.run(_pencil(det(-(g + 2.5 * d))))
+    assert len(rec) == 400 and (rec["tube"] == 2).all()
+    assert np.allclose(rec["value"], pabs, rtol=1e-12)
+    # mid-gap: the nearest tube centres are 2d away, the tube half-width d / 2.4
+    _, _, rec, _ = oracle_lib.run(_pencil(det(-(2 * d + 0.5 * g))))
+    assert len(rec) == 400 and (rec["tube"] < 0).all() and (rec["bin"] < 0).all()
+    # without packs the even pitch is (4d + g) / 4 = 1.75 d: phi_lo = -4.375 d
+    # centres column 2 on azimuth 0, where with packs no tube is (the nearest
+    # pack columns sit at -2.875 d and +1.125 d)
+    _, _, rec, _ = oracle_lib.run(_pencil(det(-4.375 * d, packs=False)))
+    assert len(rec) == 400 and (rec["tube"] == 2).all()
+    _, _, rec, _ = oracle_lib.run(_pencil(det(-4.375 * d)))
+    assert (rec["tube"] < 0).all()
+
+
 def test_ms_magnitude_sanity(oracle_lib):
     """A thin weak scatterer has small multiple scattering: for the
     vanadium-like plate the second-order weight is a few per cent of the
