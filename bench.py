@@ -271,6 +271,57 @@ def bench_single(torch, mcv, cfg, stream, reps, costs_name=None, cpu_budget_s=4.
     return out
 
 
+def bench_events_and_reduction(torch, mcv, W, stream, reps):
+    """Event mode and the (Q, E) reduction on the 1e7-history powder
+    workload (1.28e8 bins): the run with events against the plain run, the
+    histogram reduction of the run's histogram and of a dense histogram, and
+    the reduction of the run's events."""
+    cfg = W.powder_config()
+    N = cfg["N"]
+    plan = mcv.Plan(cfg)
+    hist = plan.zeros()
+    cap = 3 * N
+    ev = torch.empty(cap * mcv.EVENT_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+
+    def run_plain():
+        hist.zero_()
+        plan.run(hist, stream=stream)
+
+    def run_events():
+        cnt.zero_()
+        plan.run_events(ev, cnt, stream=stream)
+    t_plain = timed(torch, stream, run_plain, reps)
+    t_ev = timed(torch, stream, run_events, reps)
+    n_ev = int(cnt.item())
+    grid = W.qe_grid(cfg["beam"]["E"], nq=200, ne=180)
+    iqe = torch.zeros(200 * 180, dtype=torch.float64, device="cuda:0")
+
+    def red_hist(h):
+        return lambda: plan.reduce_qe(grid, h, iqe, stream=stream)
+    t_red = timed(torch, stream, red_hist(hist), reps)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(3)
+    dense = torch.rand(plan.nbins, dtype=torch.float64, device="cuda:0", generator=g)
+    t_dense = timed(torch, stream, red_hist(dense), reps)
+    del dense
+    t_red_ev = timed(torch, stream,
+                     lambda: plan.reduce_events_qe(grid, ev, cnt, iqe, stream=stream), reps)
+    nb = plan.nbins
+    out = {"workload": f"{cfg['name']} 1e7 histories, {nb} bins, (Q, E) grid 200 x 180",
+           "run_ms": t_plain, "run_events_ms": t_ev, "events": n_ev,
+           "event_overhead": t_ev / t_plain - 1.0,
+           "reduce_hist_ms": t_red, "reduce_hist_GBps": 8 * nb / (t_red / 1e3) / 1e9,
+           "reduce_dense_ms": t_dense,
+           "reduce_dense_GBps": 8 * nb / (t_dense / 1e3) / 1e9,
+           "reduce_dense_hbm_frac": 8 * nb / (t_dense / 1e3) / HBM_PEAK,
+           "reduce_events_ms": t_red_ev,
+           "reduce_events_per_s": n_ev / (t_red_ev / 1e3)}
+    del plan, hist, ev, iqe
+    torch.cuda.empty_cache()
+    return out
+
+
 def load_costs(name):
     if not os.path.exists(COSTS):
         return None
@@ -287,6 +338,10 @@ def main():
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--sections", default=None,
+                    help="comma-separated extra sections to run (batched, adjoint, plate, "
+                         "crystal, multiphonon, delta, scan, 8packs, events); default: all "
+                         "unless --quick")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (PMC byte calibration)")
     args = ap.parse_args()
@@ -375,21 +430,40 @@ def main():
                                "kernel": "transport (run mode)",
                                "work_per_history": w_hist,
                                "histories_per_launch": N}
-    if not args.quick:
-        reps = 3
-        fwd_ms = ms_per_step
-        out["batched"] = bench_batched(torch, mcv, W, stream, reps)
-        print(f"[bench] batched done", file=sys.stderr, flush=True)
-        out["adjoint"] = bench_adjoint(torch, mcv, W, stream, reps, fwd_ms)
-        print(f"[bench] adjoint done", file=sys.stderr, flush=True)
-        out["plate_scaled"] = bench_single(torch, mcv, W.plate_config(N=1_000_000_000), stream,
-                                           reps, "plate")
-        out["crystal"] = bench_single(torch, mcv, W.crystal_config(), stream, reps, "crystal")
-        out["powder_multiphonon"] = bench_single(torch, mcv, W.powder_mp_config(), stream, reps,
-                                                 "powder_mp")
-        out["crystal_delta"] = bench_single(torch, mcv, W.crystal_delta_config(), stream, reps,
-                                            "crystal_delta")
-        out["goniometer_scan"] = bench_scan(torch, mcv, W, stream, reps)
+    all_sections = ["batched", "adjoint", "plate", "crystal", "multiphonon", "delta", "scan",
+                    "8packs", "events"]
+    if args.sections is not None:
+        sections = [x for x in args.sections.split(",") if x]
+        unknown = set(sections) - set(all_sections)
+        if unknown:
+            raise SystemExit(f"unknown sections {sorted(unknown)}")
+    else:
+        sections = [] if args.quick else all_sections
+    reps = 3
+    for sec in sections:
+        if sec == "batched":
+            out["batched"] = bench_batched(torch, mcv, W, stream, reps)
+        elif sec == "adjoint":
+            out["adjoint"] = bench_adjoint(torch, mcv, W, stream, reps, ms_per_step)
+        elif sec == "plate":
+            out["plate_scaled"] = bench_single(torch, mcv, W.plate_config(N=1_000_000_000),
+                                               stream, reps, "plate")
+        elif sec == "crystal":
+            out["crystal"] = bench_single(torch, mcv, W.crystal_config(), stream, reps, "crystal")
+        elif sec == "multiphonon":
+            out["powder_multiphonon"] = bench_single(torch, mcv, W.powder_mp_config(), stream,
+                                                     reps, "powder_mp")
+        elif sec == "delta":
+            out["crystal_delta"] = bench_single(torch, mcv, W.crystal_delta_config(), stream,
+                                                reps, "crystal_delta")
+        elif sec == "scan":
+            out["goniometer_scan"] = bench_scan(torch, mcv, W, stream, reps)
+        elif sec == "8packs":
+            out["powder_8packs"] = bench_single(torch, mcv, W.powder_8pack_config(), stream, reps,
+                                                "powder_8pack")
+        elif sec == "events":
+            out["events_and_reduction"] = bench_events_and_reduction(torch, mcv, W, stream, reps)
+        print(f"[bench] {sec} done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

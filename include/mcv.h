@@ -269,6 +269,63 @@ mcv_status mcv_trace(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t f
                      double* hist, mcv_packet_record* records, uint64_t capacity,
                      uint64_t* n_out_dev, void* stream);
 
+/* ----------------------------------------------------------- event mode */
+/* One detector event (Sec. 2.4.3 and Sec. 3 step 3: a packet that a
+ * detector records becomes an event of the virtual detector electronics,
+ * with pixel identifier, time of flight and probability). */
+typedef struct {
+  uint32_t pixel;  /* bin / n_tof: tube * n_pix + pixel (tubes), ring (sphere) */
+  float tof;       /* s, since the incident packet crossed z = 0 */
+  float value;     /* recorded value (the packet's probability times the
+                      absorption probability for tubes) */
+  int32_t order;   /* number of scattering events of the packet */
+} mcv_event;
+
+/* Same transport as mcv_run, also appending one event per recorded packet
+ * (bin >= 0) to events (device array of `capacity`) in arbitrary order.
+ * *n_events_dev (device uint64) is advanced by the number of events: zeroed
+ * by the caller, it receives the count, which may exceed capacity (then only
+ * `capacity` events are written; the caller sees the overflow); not zeroed,
+ * successive calls append.  hist and hist_w2 may be NULL (events only).
+ * Errors as mcv_run; MCV_EINVAL for a null event buffer or counter. */
+mcv_status mcv_run_events(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t first,
+                          uint64_t n, double* hist, double* hist_w2, mcv_event* events,
+                          uint64_t capacity, uint64_t* n_events_dev, void* stream);
+
+/* ------------------------------------------------------------ reduction */
+/* Powder reduction to I(Q, E) (Sec. 3, "Reduction": intensities are sums of
+ * packet probabilities and are reduced exactly like measured counts).
+ * Direct geometry with the scattering at the sample position: for a pixel
+ * centre r_p (tubes: on the tube axis at the pixel's mid height; sphere:
+ * ring centre (ring + 1/2) pi / n_2theta at radius R) and a time t (bin
+ * centre tof_lo + (b + 1/2) dt, or the event's time): v_f = |r_p| / t,
+ * E = Ei - m v_f^2 / 2, Q = |k_i - k_f| with k_i along +z of magnitude
+ * sqrt(Ei / (hbar^2/2m)) and k_f along r_p.  Bins: iq = floor((Q - q_lo)
+ * nq / (q_hi - q_lo)), ie likewise in E; entries outside the grid are
+ * dropped.  Q and E are evaluated in binary32, the sums in binary64. */
+typedef struct {
+  double Ei;          /* meV: incident energy assumed by the reduction */
+  double q_lo, q_hi;  /* 1/A */
+  double e_lo, e_hi;  /* meV: energy transfer Ei - Ef */
+  int32_t nq, ne;     /* >= 1 each */
+} mcv_qe_grid;
+
+/* Adds the histogram hist[mcv_plan_nbins(p)] (device binary64, laid out as
+ * the plan's detector bins, 16-byte aligned) into iqe[nq * ne] (device
+ * binary64, row-major in Q, zeroed by the caller), and, if both are given,
+ * hist_w2 into iqe_w2.  Errors: MCV_EINVAL (null arguments, bad grid,
+ * Ei <= 0, misaligned histogram), MCV_EHIP. */
+mcv_status mcv_reduce_qe(mcv_plan p, const mcv_qe_grid* grid, const double* hist,
+                         const double* hist_w2, double* iqe, double* iqe_w2, void* stream);
+
+/* Adds events[0 .. min(*n_events_dev, capacity)) (device, as written by
+ * mcv_run_events with this plan's detector) into iqe[nq * ne], and their
+ * squared values into iqe_w2 when it is not NULL.  Events whose pixel is
+ * outside the detector are ignored.  Errors as mcv_reduce_qe. */
+mcv_status mcv_reduce_events_qe(mcv_plan p, const mcv_qe_grid* grid, const mcv_event* events,
+                                const uint64_t* n_events_dev, uint64_t capacity, double* iqe,
+                                double* iqe_w2, void* stream);
+
 /* ------------------------------------------------------------- adjoint */
 /* Parameters of a gradient (an extension of the paper's method: the
  * derivatives of the Monte Carlo estimate of I with every random choice held

@@ -26,6 +26,7 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                             const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
                             int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
+                            DevEvent* ev, uint64_t ev_cap, unsigned long long* n_ev,
                             const AdjArgs* adj, hipStream_t stream);
 hipError_t launch_adjoint_finalize(double* grad, const double* sums, const double* dense_a,
                                    double dnorm, int nb, hipStream_t stream);
@@ -36,6 +37,13 @@ size_t transport_static_lds();
 int transport_waves_per_eu(int nscat, int smax);
 int batch_waves_per_eu();
 hipError_t set_transport_lds_limit(size_t bytes);
+hipError_t launch_reduce_hist(const DevPlan* plan, const float* tables, const QEMap& M,
+                              const double* hist, const double* hist_w2, uint64_t nbins,
+                              double* iqe, double* iqe_w2, int grid, hipStream_t stream);
+hipError_t launch_reduce_events(const DevPlan* plan, const float* tables, const QEMap& M,
+                                const DevEvent* ev, const unsigned long long* n_dev, uint64_t cap,
+                                double* iqe, double* iqe_w2, int grid, hipStream_t stream);
+int reduce_tile_bins();
 }  // namespace mcv
 
 using namespace mcv;
@@ -60,6 +68,7 @@ const double kBoltzmann = 0.08617333;    // meV / K
 const double kNeutronMassAmu = 1.00866491595;
 const double kPi = 3.14159265358979323846;
 const double kHe3SigmaAbs = 5333.0;      // barn at 2200 m/s
+const double kEperV2 = 5.22703759e-6;    // meV per (m/s)^2, m_n / 2
 
 struct KernelCopy {
   mcv_kernel k;
@@ -285,6 +294,7 @@ struct mcv_plan_s {
   int waves_per_simd = 4;
   int64_t nbins = 0;
   double R = 0;
+  double tof_lo = 0, tof_hi = 0;  // detector time window (binary64)
 };
 
 extern "C" {
@@ -617,6 +627,8 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   if (T.empty()) T.push_back(0.0f);
   p->nbins = mcv_detector_nbins(d);
   p->R = d->R;
+  p->tof_lo = d->tof_lo;
+  p->tof_hi = d->tof_hi;
 
   // LDS: plan + tables + bin cache + per-lane stack
   size_t lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, kHotMin);
@@ -730,7 +742,8 @@ void grid_shape(const mcv_plan_s* p, uint64_t n, int block, uint64_t* grid, uint
 
 mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t first, uint64_t n,
                   double* hist, double* hist_w2, DevRecord* rec, uint64_t cap,
-                  unsigned long long* n_out, void* stream) {
+                  unsigned long long* n_out, void* stream, DevEvent* ev = nullptr,
+                  uint64_t ev_cap = 0, unsigned long long* n_ev = nullptr) {
   DevBeam B;
   mcv_status st = make_beam(p, beam, &B);
   if (st != MCV_OK) return st;
@@ -744,7 +757,7 @@ mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t firs
   if (cur != p->device) (void)hipSetDevice(p->device);
   hipError_t e = launch_transport(p->d_plan, p->host, p->d_tables, B,
                                   seed, first, n, (int)grid, p->block, per_wave, hist, hist_w2,
-                                  rec, cap, n_out, nullptr, (hipStream_t)stream);
+                                  rec, cap, n_out, ev, ev_cap, n_ev, nullptr, (hipStream_t)stream);
   if (cur != p->device) (void)hipSetDevice(cur);
   if (e != hipSuccess) return hipfail(e, "transport launch");
   return MCV_OK;
@@ -769,6 +782,105 @@ mcv_status mcv_trace(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t f
   if (!records || !n_out_dev) return fail(MCV_EINVAL, "null record buffer or counter");
   return launch(p, beam, seed, first, n, hist, nullptr, reinterpret_cast<DevRecord*>(records),
                 capacity, reinterpret_cast<unsigned long long*>(n_out_dev), stream);
+}
+
+mcv_status mcv_run_events(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t first,
+                          uint64_t n, double* hist, double* hist_w2, mcv_event* events,
+                          uint64_t capacity, uint64_t* n_events_dev, void* stream) {
+  static_assert(sizeof(mcv_event) == sizeof(DevEvent), "event layout");
+  if (!p) return fail(MCV_EINVAL, "null plan");
+  if (!events || !n_events_dev) return fail(MCV_EINVAL, "null event buffer or counter");
+  if (p->nbins > (int64_t)0xFFFFFFFF)
+    return fail(MCV_EUNSUPPORTED, "event mode needs fewer than 2^32 detector bins");
+  return launch(p, beam, seed, first, n, hist, hist_w2, nullptr, 0, nullptr, stream,
+                reinterpret_cast<DevEvent*>(events), capacity,
+                reinterpret_cast<unsigned long long*>(n_events_dev));
+}
+
+}  // extern "C"
+
+namespace {
+
+mcv_status make_qe_map(const mcv_plan_s* p, const mcv_qe_grid* g, QEMap* M) {
+  if (!g) return fail(MCV_EINVAL, "null grid");
+  if (!(g->Ei > 0.0) || !std::isfinite(g->Ei)) return fail(MCV_EINVAL, "reduction needs Ei > 0");
+  if (g->nq < 1 || g->ne < 1 || (int64_t)g->nq * g->ne > ((int64_t)1 << 31) - 1)
+    return fail(MCV_EINVAL, "grid needs nq, ne >= 1 and fewer than 2^31 bins");
+  if (!(g->q_hi > g->q_lo) || !(g->e_hi > g->e_lo) || !std::isfinite(g->q_lo) ||
+      !std::isfinite(g->q_hi) || !std::isfinite(g->e_lo) || !std::isfinite(g->e_hi))
+    return fail(MCV_EINVAL, "grid needs finite q_lo < q_hi, e_lo < e_hi");
+  const DevDet& D = p->host.det;
+  const double ki = std::sqrt(g->Ei / kHbar2over2mn);
+  M->Ei = (float)g->Ei;
+  M->ki2 = (float)(ki * ki);
+  M->two_ki = (float)(2.0 * ki);
+  M->e_per_v2 = (float)kEperV2;
+  M->k_per_v = (float)std::sqrt(kEperV2 / kHbar2over2mn);
+  M->q_lo = (float)g->q_lo;
+  M->q_scale = (float)(g->nq / (g->q_hi - g->q_lo));
+  M->e_lo = (float)g->e_lo;
+  M->e_scale = (float)(g->ne / (g->e_hi - g->e_lo));
+  M->nq = g->nq;
+  M->ne = g->ne;
+  M->ntof = D.ntof;
+  M->tof_lo = (float)p->tof_lo;
+  M->dt = (float)((p->tof_hi - p->tof_lo) / D.ntof);
+  M->npixels = (uint32_t)(p->nbins / D.ntof);
+  M->pad = 0;
+  return MCV_OK;
+}
+
+int reduce_grid(const mcv_plan_s* p, uint64_t work_items, uint64_t per_block) {
+  const uint64_t blocks = (work_items + per_block - 1) / per_block;
+  const uint64_t cap = (uint64_t)p->cus * 8;
+  return (int)(blocks < 1 ? 1 : blocks < cap ? blocks : cap);
+}
+
+}  // namespace
+
+extern "C" {
+
+mcv_status mcv_reduce_qe(mcv_plan p, const mcv_qe_grid* grid, const double* hist,
+                         const double* hist_w2, double* iqe, double* iqe_w2, void* stream) {
+  if (!p || !hist || !iqe) return fail(MCV_EINVAL, "null plan, histogram or output");
+  if (p->nbins / p->host.det.ntof > (int64_t)0xFFFFFFFF)
+    return fail(MCV_EUNSUPPORTED, "reduction needs fewer than 2^32 pixels");
+  if (((uintptr_t)hist & 15u) != 0 || ((uintptr_t)hist_w2 & 15u) != 0)
+    return fail(MCV_EINVAL, "histograms must be 16-byte aligned");
+  QEMap M;
+  mcv_status st = make_qe_map(p, grid, &M);
+  if (st != MCV_OK) return st;
+  const int g = reduce_grid(p, (uint64_t)p->nbins, (uint64_t)reduce_tile_bins());
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  hipError_t e = launch_reduce_hist(p->d_plan, p->d_tables, M, hist, hist_w2, (uint64_t)p->nbins,
+                                    iqe, iqe_w2, g, (hipStream_t)stream);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  return e == hipSuccess ? MCV_OK : hipfail(e, "reduction launch");
+}
+
+mcv_status mcv_reduce_events_qe(mcv_plan p, const mcv_qe_grid* grid, const mcv_event* events,
+                                const uint64_t* n_events_dev, uint64_t capacity, double* iqe,
+                                double* iqe_w2, void* stream) {
+  if (!p || !events || !n_events_dev || !iqe)
+    return fail(MCV_EINVAL, "null plan, events, counter or output");
+  if (p->nbins / p->host.det.ntof > (int64_t)0xFFFFFFFF)
+    return fail(MCV_EUNSUPPORTED, "reduction needs fewer than 2^32 pixels");
+  QEMap M;
+  mcv_status st = make_qe_map(p, grid, &M);
+  if (st != MCV_OK) return st;
+  if (capacity == 0) return MCV_OK;
+  const int g = reduce_grid(p, capacity, 256);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  hipError_t e = launch_reduce_events(
+      p->d_plan, p->d_tables, M, reinterpret_cast<const DevEvent*>(events),
+      reinterpret_cast<const unsigned long long*>(n_events_dev), capacity, iqe, iqe_w2, g,
+      (hipStream_t)stream);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  return e == hipSuccess ? MCV_OK : hipfail(e, "reduction launch");
 }
 
 mcv_status mcv_sync(void* stream) {
@@ -904,7 +1016,8 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
     grid_shape(p, n, p->adj.block, &grid, &per_wave);
     hipError_t e = launch_transport(p->d_plan, p->host, p->d_tables,
                                     B, seed, first, n, (int)grid, p->adj.block, per_wave, nullptr,
-                                    nullptr, nullptr, 0, nullptr, &AA, (hipStream_t)stream);
+                                    nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, &AA,
+                                    (hipStream_t)stream);
     if (e == hipSuccess)
       e = launch_adjoint_finalize(grad, p->adj.sums, p->adj.dense_a, p->adj.dnorm, p->adj.nb,
                                   (hipStream_t)stream);

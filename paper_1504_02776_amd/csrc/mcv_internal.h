@@ -171,6 +171,29 @@ struct DevRecord {  // mirrors mcv_packet_record
   int32_t pixel;
 };
 
+struct DevEvent {  // mirrors mcv_event
+  uint32_t pixel;
+  float tof;
+  float value;
+  int32_t order;
+};
+
+// Mapping of detector data to (Q, E) bins, binary32 (the reduction)
+struct QEMap {
+  float Ei;         // meV
+  float ki2;        // k_i^2, 1/A^2
+  float two_ki;     // 2 k_i
+  float e_per_v2;   // meV per (m/s)^2
+  float k_per_v;    // 1/A per m/s
+  float q_lo, q_scale;  // nq / (q_hi - q_lo)
+  float e_lo, e_scale;
+  int32_t nq, ne;
+  float tof_lo, dt;     // time bins of the detector
+  int32_t ntof;
+  uint32_t npixels;
+  int32_t pad;
+};
+
 }  // namespace mcv
 
 #endif

@@ -16,6 +16,7 @@
 // not part of the transport path.
 
 #include "mcv_transport.hip"
+#include "mcv_reduce.hip"
 #include "mcv_api.cpp"
 
 namespace mcv {

@@ -1121,7 +1121,69 @@ struct Sinks {
   DevRecord* rec;
   uint64_t cap;
   unsigned long long* n_out;
+  DevEvent* ev;  // event mode (MODE_RUN only; NULL: off)
+  uint64_t ev_cap;
+  unsigned long long* n_ev;
+  int ev_hot_n;              // bin cache slots of event launches
+  DevEvent* stage;           // this wave's LDS event stage (set in the kernel)
+  volatile int* stage_n;     // events in the stage
 };
+
+// Event mode: every wave stages its events in LDS (kEvStage entries) and
+// copies the stage to the output with one counter atomic per kEvStage
+// events or fewer, instead of one atomic per recording step, since all
+// waves of the device share the one counter.
+constexpr int kEvStage = 64;
+constexpr int kEvStageWords = kEvStage * 4 + 4;  // per wave: events, count
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// copies the first n staged events to the output; the active lanes of the
+// wave (any subset) share the copy
+__device__ __forceinline__ void ev_flush(const Sinks& out, int n) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const uint64_t act = __ballot(1);
+  const int lead = __ffsll((unsigned long long)act) - 1;
+  const int na = __popcll(act);
+  const int me = __popcll(act & lanemask_lt());
+  unsigned long long base = 0ull;
+  if ((int)__lane_id() == lead) base = atomicAdd(out.n_ev, (unsigned long long)n);
+  base = readlane64(base, lead);
+  for (int i = me; i < n; i += na) {
+    const uint64_t slot = base + (uint64_t)i;
+    if (slot < out.ev_cap) out.ev[slot] = out.stage[i];
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// stages one event per active lane with a recorded packet (divergent code)
+__device__ __forceinline__ void event_append(const Sinks& out, int ntof, const Hit& hh,
+                                             int order) {
+  const bool rec = hh.bin >= 0;
+  const uint64_t m = __ballot(rec);
+  if (m == 0ull) return;
+  const uint64_t act = __ballot(1);
+  const int k = __popcll(m);
+  int n = *out.stage_n;
+  if (n + k > kEvStage) {
+    ev_flush(out, n);
+    n = 0;
+  }
+  if (rec) {
+    DevEvent e;
+    e.pixel = (uint32_t)hh.bin / (uint32_t)ntof;
+    e.tof = hh.tof;
+    e.value = hh.value;
+    e.order = order;
+    out.stage[n + __popcll(m & lanemask_lt())] = e;
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if ((int)__lane_id() == __ffsll((unsigned long long)act) - 1) *out.stage_n = n + k;
+}
 
 // Histogram bins that many lanes of a wave hit at the same step (the
 // unscattered beam lands in one pixel and one time bin for every history)
@@ -1243,6 +1305,7 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
       hval = hh.value;
     }
   }
+  if (MODE == MODE_RUN && out.ev != nullptr) event_append(out, PL.det.ntof, hh, order_of(cur.lin));
   if (MODE == MODE_TRACE) {
     const unsigned long long slot = atomicAdd(out.n_out, 1ull);
     if (slot < out.cap) {
@@ -1372,7 +1435,8 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
         state = LANE_DET;
       }
     }
-    if (!ADJ) hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
+    if (!ADJ && (out.hist != nullptr || out.hist_w2 != nullptr))
+      hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
   }
 }
 
@@ -1431,7 +1495,8 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
         has = false;
       }
     }
-    if (!ADJ) hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
+    if (!ADJ && (out.hist != nullptr || out.hist_w2 != nullptr))
+      hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
   }
 }
 
@@ -1487,7 +1552,8 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   // adjoint partials: [nb] per DOS bin (sum of g), then sigma_abs, sigma, A,
   // n_phonon; otherwise the histogram bin cache
   double* acc = reinterpret_cast<double*>(dyn + tab_words);
-  const int hot_n = gplan->hot_n;
+  const bool events = MODE == MODE_RUN && out.ev != nullptr;
+  const int hot_n = events ? out.ev_hot_n : gplan->hot_n;
   const int acc_words = ADJ ? 2 * (((AA.nb + 4) + 1) & ~1) : hot_words(hot_n);
   if (ADJ)
     for (int i = tid; i < AA.nb + 4; i += nthreads) acc[i] = 0.0;
@@ -1497,10 +1563,23 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   float* st = dyn + tab_words + acc_words;
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
-  if (begin < n)  // uniform per wave
+  Sinks o = out;
+  if (events) {
+    // event stages after the packet stacks, one per wave of the workgroup
+    float* sw = st + (size_t)PL.stack_cap * kFields * nthreads + (tid >> 6) * kEvStageWords;
+    o.stage = reinterpret_cast<DevEvent*>(sw);
+    o.stage_n = reinterpret_cast<volatile int*>(sw + kEvStage * 4);
+    if ((tid & 63) == 0) *o.stage_n = 0;
+  }
+  if (begin < n) {  // uniform per wave
     trace_range<MODE, NSC, TWO, PHASED, HEAVY>(PL, dyn, st, beam, seed, first, begin,
-                                begin + per_wave < n ? begin + per_wave : n, out, AA, acc, hot_n,
+                                begin + per_wave < n ? begin + per_wave : n, o, AA, acc, hot_n,
                                 nthreads, tid);
+    if (events) {
+      const int left = *o.stage_n;
+      if (left > 0) ev_flush(o, left);
+    }
+  }
   if (!ADJ) {
     __syncthreads();
     hot_flush(acc, hot_n, out.hist, out.hist_w2, nthreads, tid);
@@ -1556,7 +1635,7 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const uint64_t per = (ch.count + nwaves - 1) / nwaves;
     const uint64_t b = ch.first + per * wid;
     const uint64_t e = ch.first + ch.count;
-    Sinks out = {it.hist, nullptr, nullptr, 0, nullptr};
+    Sinks out = {it.hist, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr};
     const uint64_t ee = b + per < e ? b + per : e;
     // the same specialisation as a plain launch of this plan, so that both
     // evaluate identical arithmetic
@@ -1741,14 +1820,30 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                             const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
                             int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
+                            DevEvent* ev, uint64_t ev_cap, unsigned long long* n_ev,
                             const AdjArgs* adj, hipStream_t stream) {
   AdjArgs AA = {};
   AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = -1;
   if (adj) AA = *adj;
-  dev::Sinks out = {hist, hist_w2, rec, cap, n_out};
-  const size_t lds =
+  dev::Sinks out = {hist, hist_w2, rec, cap, n_out, ev, ev_cap, n_ev, 0, nullptr, nullptr};
+  size_t lds =
       transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, adj ? adj->nb : 0,
                           host_plan.hot_n);
+  if (ev) {
+    // room for the event stages: a smaller bin cache, at most the same LDS
+    // if the cache can give it
+    const size_t stages = sizeof(float) * (size_t)dev::kEvStageWords * (block / 64);
+    int hot = host_plan.hot_n;
+    size_t need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, 0, hot) +
+                  stages;
+    while (hot > kHotMin && need > lds) {
+      hot >>= 1;
+      need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, 0, hot) + stages;
+    }
+    if (need + sizeof(DevPlan) > 160 * 1024) return hipErrorInvalidConfiguration;
+    out.ev_hot_n = hot;
+    lds = need;
+  }
   const int nsc = host_plan.nscat;
   const bool two = host_plan.smax > host_plan.nscat;
   const bool phased = dev::use_phased(nsc, two, host_plan.K);

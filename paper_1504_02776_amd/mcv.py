@@ -93,13 +93,29 @@ RECORD_DTYPE = np.dtype([
     ("value", np.float32), ("tof", np.float32), ("tube", np.int32), ("pixel", np.int32)])
 assert RECORD_DTYPE.itemsize == 72
 
+EVENT_DTYPE = np.dtype([("pixel", np.uint32), ("tof", np.float32), ("value", np.float32),
+                        ("order", np.int32)])
+
+
+class mcv_qe_grid(C.Structure):
+    _fields_ = [("Ei", C.c_double), ("q_lo", C.c_double), ("q_hi", C.c_double),
+                ("e_lo", C.c_double), ("e_hi", C.c_double), ("nq", C.c_int32),
+                ("ne", C.c_int32)]
+
+
+def qe_grid(g):
+    """mcv_qe_grid from {"Ei", "q_lo", "q_hi", "nq", "e_lo", "e_hi", "ne"}."""
+    return mcv_qe_grid(float(g["Ei"]), float(g["q_lo"]), float(g["q_hi"]), float(g["e_lo"]),
+                       float(g["e_hi"]), int(g["nq"]), int(g["ne"]))
+
 # every symbol include/mcv.h declares (checked by the CPU test-suite)
 EXPORTS = ["mcv_assembly_create", "mcv_assembly_add", "mcv_assembly_destroy",
            "mcv_detector_sphere", "mcv_detector_tubes", "mcv_detector_nbins",
            "mcv_detector_destroy", "mcv_plan_create", "mcv_plan_destroy", "mcv_plan_nbins",
            "mcv_run", "mcv_trace", "mcv_sync", "mcv_last_error", "mcv_abi_version",
            "mcv_adjoint_nparams", "mcv_adjoint", "mcv_loss_grad", "mcv_batch_create",
-           "mcv_batch_run", "mcv_batch_destroy", "mcv_autotune"]
+           "mcv_batch_run", "mcv_batch_destroy", "mcv_autotune", "mcv_run_events",
+           "mcv_reduce_qe", "mcv_reduce_events_qe"]
 
 _lib = None
 
@@ -133,6 +149,10 @@ def lib():
             "mcv_adjoint": [P, C.POINTER(mcv_param_map), C.POINTER(mcv_beam), C.c_uint64,
                             C.c_uint64, C.c_uint64, P, P, P],
             "mcv_loss_grad": [P, P, P, C.c_int64, P, P, P],
+            "mcv_run_events": [P, C.POINTER(mcv_beam), C.c_uint64, C.c_uint64, C.c_uint64, P,
+                               P, P, C.c_uint64, P, P],
+            "mcv_reduce_qe": [P, C.POINTER(mcv_qe_grid), P, P, P, P, P],
+            "mcv_reduce_events_qe": [P, C.POINTER(mcv_qe_grid), P, P, C.c_uint64, P, P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -317,6 +337,52 @@ class Plan:
                             dtype=RECORD_DTYPE)
         return out, count
 
+    def run_events(self, events, count, n=None, first=0, seed=None, hist=None, hist_w2=None,
+                   stream=None, beam=None):
+        """Runs histories [first, first+n) and appends their detector events
+        to `events` (uint8 CUDA tensor of capacity * 16 bytes); `count` (int64
+        CUDA tensor of one element) is advanced by the number of events."""
+        n = self.cfg["N"] if n is None else n
+        seed = self.cfg["seed"] if seed is None else seed
+        b = self.beam if beam is None else make_beam(beam)
+        for h in (hist, hist_w2):
+            if h is not None:
+                self._check_hist(h)
+        cap = events.numel() // EVENT_DTYPE.itemsize
+        check(lib().mcv_run_events(self.h, C.byref(b), seed, first, n,
+                                   C.c_void_p(hist.data_ptr()) if hist is not None else None,
+                                   C.c_void_p(hist_w2.data_ptr()) if hist_w2 is not None else None,
+                                   C.c_void_p(events.data_ptr()), cap,
+                                   C.c_void_p(count.data_ptr()), _stream_ptr(stream)))
+
+    def reduce_qe(self, grid, hist, iqe, hist_w2=None, iqe_w2=None, stream=None):
+        """Adds the (pixel, tof) histogram into iqe (float64 CUDA tensor of
+        nq * ne, row-major in Q); squares likewise when both w2 are given."""
+        self._check_hist(hist)
+        g = qe_grid(grid)
+        for t, n in ((iqe, g.nq * g.ne), (iqe_w2, g.nq * g.ne)):
+            if t is not None:
+                _check_f64(t, n)
+        if hist_w2 is not None:
+            self._check_hist(hist_w2)
+        check(lib().mcv_reduce_qe(self.h, C.byref(g), C.c_void_p(hist.data_ptr()),
+                                  C.c_void_p(hist_w2.data_ptr()) if hist_w2 is not None else None,
+                                  C.c_void_p(iqe.data_ptr()),
+                                  C.c_void_p(iqe_w2.data_ptr()) if iqe_w2 is not None else None,
+                                  _stream_ptr(stream)))
+
+    def reduce_events_qe(self, grid, events, count, iqe, iqe_w2=None, stream=None):
+        """Adds the first min(count, capacity) events into iqe."""
+        g = qe_grid(grid)
+        for t in (iqe, iqe_w2):
+            if t is not None:
+                _check_f64(t, g.nq * g.ne)
+        cap = events.numel() // EVENT_DTYPE.itemsize
+        check(lib().mcv_reduce_events_qe(
+            self.h, C.byref(g), C.c_void_p(events.data_ptr()), C.c_void_p(count.data_ptr()), cap,
+            C.c_void_p(iqe.data_ptr()),
+            C.c_void_p(iqe_w2.data_ptr()) if iqe_w2 is not None else None, _stream_ptr(stream)))
+
     def nparams(self, pm):
         n = lib().mcv_adjoint_nparams(self.h, C.byref(pm))
         if n < 0:
@@ -348,7 +414,24 @@ class Plan:
             lib().mcv_plan_destroy(self.h)
             self.h = C.c_void_p()
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except TypeError:  # module globals already torn down at interpreter exit
+            pass
+
+
+def _check_f64(t, n):
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda or t.numel() < n or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous float64 CUDA tensor of {n} entries")
+
+
+def events_to_numpy(events, count):
+    """The written events of an event buffer as a numpy EVENT_DTYPE array."""
+    m = min(int(count.item()), events.numel() // EVENT_DTYPE.itemsize)
+    return np.frombuffer(events[:m * EVENT_DTYPE.itemsize].cpu().numpy().tobytes(),
+                         dtype=EVENT_DTYPE)
 
 
 def sync(stream=None):

@@ -97,7 +97,8 @@ def main():
     for name, cfg in [("powder", W.powder_config()), ("plate", W.plate_config()),
                       ("crystal", W.crystal_config()), ("sqe", W.sqe_config()),
                       ("powder_mp", W.powder_mp_config()),
-                      ("crystal_delta", W.crystal_delta_config())]:
+                      ("crystal_delta", W.crystal_delta_config()),
+                      ("powder_8pack", W.powder_8pack_config())]:
         res["workloads"][name] = probe_workload(cfg)
         print(f"[probe] {name}: {json.dumps(res['workloads'][name])}", flush=True)
     with open(args.out, "w") as f:

@@ -132,11 +132,13 @@ def tube_detector(nrows, ncols, npix, ntof, tof_lo, tof_hi, R=3.0, radius=0.0127
 
 
 def eightpack_detector(npix, ntof, tof_lo, tof_hi, npacks=32, R=3.0, radius=0.0127,
-                       length=1.0, phi_lo_deg=-30.0, phi_hi_deg=135.0, gap_deg=0.6,
+                       length=1.0, phi_lo_deg=3.0, phi_hi_deg=135.0, gap_deg=0.6,
                        row_y=(-1.02, 0.0, 1.02)):
     """Three rows of 8-packs (8 one-inch 3He tubes each) on a cylinder about
     the vertical axis, with gaps between packs: the layout of the paper's
-    direct-geometry instruments, reduced in size."""
+    direct-geometry instruments, reduced in size.  The array starts 3 degrees
+    off the beam axis, leaving the hole through which the direct beam leaves
+    the detector vessel."""
     return tube_detector(len(row_y), 8 * npacks, npix, ntof, tof_lo, tof_hi, R=R,
                          radius=radius, length=length, phi_lo_deg=phi_lo_deg,
                          phi_hi_deg=phi_hi_deg, row_y=row_y, tubes_per_pack=8,
@@ -360,3 +362,48 @@ def batch_configs(n_sims=64, seed=4, n_scale=1.0):
                     "scatterers": [scatterer(shape, 0.08, 2.0, kernels)],
                     "detector": det, "K": K, "min_prob": 0.0, "N": max(1, N), "seed": s})
     return out
+
+
+# ------------------------------------------------------ reduction inputs
+def qe_grid(Ei, q_hi=12.0, nq=120, e_lo_frac=-0.3, e_hi_frac=0.9, ne=120):
+    """A powder (Q, E) grid: |Q| in [0, q_hi) 1/A, energy transfer in
+    [e_lo_frac, e_hi_frac) * Ei."""
+    return {"Ei": float(Ei), "q_lo": 0.0, "q_hi": float(q_hi), "nq": int(nq),
+            "e_lo": e_lo_frac * Ei, "e_hi": e_hi_frac * Ei, "ne": int(ne)}
+
+
+def synthetic_histogram(nbins, density, seed):
+    """A seeded (pixel, tof) histogram: exponential values on a random
+    `density` fraction of the bins, zero elsewhere (float64)."""
+    rng = np.random.default_rng(seed)
+    h = rng.exponential(1.0, nbins)
+    h[rng.random(nbins) >= density] = 0.0
+    return h
+
+
+def synthetic_sparse_entries(nbins, n, seed):
+    """n distinct random bins of a histogram and exponential values (the
+    histogram is zero elsewhere)."""
+    rng = np.random.default_rng(seed)
+    idx = np.unique(rng.integers(0, nbins, int(n * 1.1) + 16))[:n]
+    rng.shuffle(idx)
+    return idx.astype(np.int64), rng.exponential(1.0, len(idx))
+
+
+EVENT_FIELDS = [("pixel", np.uint32), ("tof", np.float32), ("value", np.float32),
+                ("order", np.int32)]
+
+
+def synthetic_events(n_pixels, tof_lo, tof_hi, n, seed, bad_pixels=0):
+    """n seeded detector events: pixel uniform over [0, n_pixels) (plus
+    `bad_pixels` events with pixel ids past the end), time uniform over the
+    window, binary32 exponential values, orders 1..3."""
+    rng = np.random.default_rng(seed)
+    ev = np.zeros(n, dtype=EVENT_FIELDS)
+    ev["pixel"] = rng.integers(0, n_pixels, n)
+    if bad_pixels:
+        ev["pixel"][rng.choice(n, bad_pixels, replace=False)] = n_pixels + rng.integers(0, 100, bad_pixels)
+    ev["tof"] = rng.uniform(tof_lo, tof_hi, n).astype(np.float32)
+    ev["value"] = rng.exponential(1.0, n).astype(np.float32)
+    ev["order"] = rng.integers(1, 4, n)
+    return ev
