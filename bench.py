@@ -45,6 +45,9 @@ COSTS = os.path.join(ROOT, "paper_1504_02776_amd", "primitive_costs.json")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "transport_powder_1e7_pmc.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1504_02776_amd", "csrc", f)
                   for f in ("mcv_transport.hip", "mcv_internal.h")]
+REDUCE_PMC_SUMMARY = os.path.join(ROOT, "profiles", "reduce_qe_powder_1e7_pmc.md")
+REDUCE_SOURCES = [os.path.join(ROOT, "paper_1504_02776_amd", "csrc", f)
+                  for f in ("mcv_reduce.hip", "mcv_internal.h")]
 
 
 def workload(name, n=None):
@@ -66,9 +69,9 @@ def workload(name, n=None):
     return cfg
 
 
-def kernel_source_sha1():
+def kernel_source_sha1(sources=None):
     h = hashlib.sha1()
-    for p in KERNEL_SOURCES:
+    for p in (KERNEL_SOURCES if sources is None else sources):
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -92,15 +95,15 @@ def work_per_history(costs, tally, n, cfg):
     return w / n
 
 
-def traffic_per_launch():
-    """HBM bytes per launch of the headline kernel from the committed PMC
-    summary, if it was taken on the current kernel sources."""
-    if not os.path.exists(PMC_SUMMARY):
+def traffic_per_launch(summary=PMC_SUMMARY, sources=None, key="traffic_bytes_per_launch"):
+    """HBM bytes per launch of a kernel from its committed PMC summary, if it
+    was taken on the current kernel sources."""
+    if not os.path.exists(summary):
         return None
-    txt = open(PMC_SUMMARY).read()
+    txt = open(summary).read()
     m = re.search(r"kernel_sources_sha1:\s*([0-9a-f]{40})", txt)
-    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not t or m.group(1) != kernel_source_sha1():
+    t = re.search(key + r":\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_source_sha1(sources):
         return None
     return float(t.group(1))
 
@@ -317,6 +320,13 @@ def bench_events_and_reduction(torch, mcv, W, stream, reps):
            "reduce_dense_hbm_frac": 8 * nb / (t_dense / 1e3) / HBM_PEAK,
            "reduce_events_ms": t_red_ev,
            "reduce_events_per_s": n_ev / (t_red_ev / 1e3)}
+    # roofline of the histogram reduction on the dense input: 8 bytes read
+    # per bin (the (Q, E) grid, 288 KB, stays in L2)
+    out["roofline"] = {"bound": "hbm", "kernel": "reduce_hist_qe (dense histogram)",
+                       "achieved": 8 * nb / (t_dense / 1e3) / 1e9, "peak": HBM_PEAK / 1e9,
+                       "unit": "GB/s", "frac": 8 * nb / (t_dense / 1e3) / HBM_PEAK,
+                       "traffic": traffic_per_launch(REDUCE_PMC_SUMMARY, REDUCE_SOURCES,
+                                                     "dense_traffic_bytes_per_launch")}
     del plan, hist, ev, iqe
     torch.cuda.empty_cache()
     return out

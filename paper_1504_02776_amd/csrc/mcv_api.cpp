@@ -37,10 +37,11 @@ size_t transport_static_lds();
 int transport_waves_per_eu(int nscat, int smax);
 int batch_waves_per_eu();
 hipError_t set_transport_lds_limit(size_t bytes);
-hipError_t launch_reduce_hist(const DevPlan* plan, const float* tables, const QEMap& M,
+hipError_t launch_reduce_hist(const float* geo, const QEMap& M,
                               const double* hist, const double* hist_w2, uint64_t nbins,
-                              double* iqe, double* iqe_w2, int grid, hipStream_t stream);
-hipError_t launch_reduce_events(const DevPlan* plan, const float* tables, const QEMap& M,
+                              double* iqe, double* iqe_w2, int grid, int cus,
+                              hipStream_t stream);
+hipError_t launch_reduce_events(const float* geo, const QEMap& M,
                                 const DevEvent* ev, const unsigned long long* n_dev, uint64_t cap,
                                 double* iqe, double* iqe_w2, int grid, hipStream_t stream);
 int reduce_tile_bins();
@@ -289,6 +290,7 @@ struct mcv_plan_s {
   std::vector<float> tables;
   DevPlan* d_plan = nullptr;
   float* d_tables = nullptr;
+  float* d_pixgeo = nullptr;     // per pixel id: |r_p|, cos(2theta) (reduction)
   int block = 256;
   int cus = 256;
   int waves_per_simd = 4;
@@ -625,6 +627,28 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   }
   P.n_tables = (int)T.size();
   if (T.empty()) T.push_back(0.0f);
+  // pixel centres for the (Q, E) reduction, in binary64: tube pixels on the
+  // tube axis at the pixel's mid height, sphere rings at their centre angle
+  std::vector<float> G;
+  if (d->type == DET_SPHERE) {
+    for (int i = 0; i < d->n2t; ++i) {
+      G.push_back((float)d->R);
+      G.push_back((float)std::cos((i + 0.5) * kPi / d->n2t));
+    }
+  } else {
+    const mcv_tube_layout& L = d->tubes;
+    for (int r = 0; r < L.nrows; ++r)
+      for (int c = 0; c < L.ncols; ++c) {
+        const double phi = column_azimuth(L, c);
+        const double x = L.R * std::sin(phi), z = L.R * std::cos(phi);
+        for (int j = 0; j < d->npix; ++j) {
+          const double y = L.row_y[r] - 0.5 * L.length + (j + 0.5) * L.length / d->npix;
+          const double L2 = std::sqrt(x * x + y * y + z * z);
+          G.push_back((float)L2);
+          G.push_back((float)(z / L2));
+        }
+      }
+  }
   p->nbins = mcv_detector_nbins(d);
   p->R = d->R;
   p->tof_lo = d->tof_lo;
@@ -669,17 +693,22 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     return hipfail(e, "hipFuncSetAttribute");
   }
   if ((e = hipMalloc(&p->d_plan, sizeof(DevPlan))) != hipSuccess ||
-      (e = hipMalloc(&p->d_tables, T.size() * sizeof(float))) != hipSuccess) {
+      (e = hipMalloc(&p->d_tables, T.size() * sizeof(float))) != hipSuccess ||
+      (e = hipMalloc(&p->d_pixgeo, G.size() * sizeof(float))) != hipSuccess) {
     if (p->d_plan) (void)hipFree(p->d_plan);
+    if (p->d_tables) (void)hipFree(p->d_tables);
     (void)hipSetDevice(cur);
     delete p;
     return fail(MCV_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
   if ((e = hipMemcpy(p->d_plan, &P, sizeof(DevPlan), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->d_tables, T.data(), T.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(p->d_pixgeo, G.data(), G.size() * sizeof(float), hipMemcpyHostToDevice)) !=
           hipSuccess) {
     (void)hipFree(p->d_plan);
     (void)hipFree(p->d_tables);
+    (void)hipFree(p->d_pixgeo);
     (void)hipSetDevice(cur);
     delete p;
     return hipfail(e, "hipMemcpy");
@@ -696,6 +725,7 @@ mcv_status mcv_plan_destroy(mcv_plan p) {
   (void)hipSetDevice(p->device);
   (void)hipFree(p->d_plan);
   (void)hipFree(p->d_tables);
+  (void)hipFree(p->d_pixgeo);
   if (p->adj.inv_theta) (void)hipFree(p->adj.inv_theta);
   if (p->adj.dense_a) (void)hipFree(p->adj.dense_a);
   if (p->adj.sums) (void)hipFree(p->adj.sums);
@@ -854,8 +884,8 @@ mcv_status mcv_reduce_qe(mcv_plan p, const mcv_qe_grid* grid, const double* hist
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
-  hipError_t e = launch_reduce_hist(p->d_plan, p->d_tables, M, hist, hist_w2, (uint64_t)p->nbins,
-                                    iqe, iqe_w2, g, (hipStream_t)stream);
+  hipError_t e = launch_reduce_hist(p->d_pixgeo, M, hist, hist_w2, (uint64_t)p->nbins,
+                                    iqe, iqe_w2, g, p->cus, (hipStream_t)stream);
   if (cur != p->device) (void)hipSetDevice(cur);
   return e == hipSuccess ? MCV_OK : hipfail(e, "reduction launch");
 }
@@ -876,7 +906,7 @@ mcv_status mcv_reduce_events_qe(mcv_plan p, const mcv_qe_grid* grid, const mcv_e
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
   hipError_t e = launch_reduce_events(
-      p->d_plan, p->d_tables, M, reinterpret_cast<const DevEvent*>(events),
+      p->d_pixgeo, M, reinterpret_cast<const DevEvent*>(events),
       reinterpret_cast<const unsigned long long*>(n_events_dev), capacity, iqe, iqe_w2, g,
       (hipStream_t)stream);
   if (cur != p->device) (void)hipSetDevice(cur);

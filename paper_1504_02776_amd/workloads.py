@@ -131,7 +131,7 @@ def tube_detector(nrows, ncols, npix, ntof, tof_lo, tof_hi, R=3.0, radius=0.0127
             "tubes_per_pack": int(tubes_per_pack), "pack_gap": math.radians(pack_gap_deg)}
 
 
-def eightpack_detector(npix, ntof, tof_lo, tof_hi, npacks=32, R=3.0, radius=0.0127,
+def eightpack_detector(npix, ntof, tof_lo, tof_hi, npacks=28, R=3.0, radius=0.0127,
                        length=1.0, phi_lo_deg=3.0, phi_hi_deg=135.0, gap_deg=0.6,
                        row_y=(-1.02, 0.0, 1.02)):
     """Three rows of 8-packs (8 one-inch 3He tubes each) on a cylinder about
@@ -269,7 +269,7 @@ def goniometer_scan_configs(n_angles=64, N=1_000_000, seed=0, span_deg=90.0):
 
 def powder_8pack_config(N=10_000_000, seed=0):
     """The powder cylinder seen by three rows of 8-packs with gaps
-    (32 packs x 8 tubes x 128 pixels x 1000 tof bins)."""
+    (28 packs x 8 tubes per row x 128 pixels x 1000 tof bins)."""
     cfg = powder_config(N=N, seed=seed)
     d = cfg["detector"]
     cfg["detector"] = eightpack_detector(128, 1000, d["tof_lo"], d["tof_hi"])

@@ -75,3 +75,32 @@ def test_multiphonon_kernel_validation():
         with pytest.raises(mcv.MCVError) as e:
             b.add(W.scatterer(W.box(0.01, 0.01, 0.01), 0.08, 1.0, [bad]))
         assert e.value.status in (status, mcv.MCV_EUNSUPPORTED)
+
+
+def test_every_workload_detector_is_valid():
+    """The detectors of all named workloads pass the library's layout
+    checks (tube overlap, pack gaps, rows) on the host."""
+    from paper_1504_02776_amd import mcv, workloads as W
+    if not os.path.exists(mcv.LIB_PATH):
+        pytest.skip("libmcv.so not built")
+    cfgs = [W.plate_config(), W.powder_config(), W.powder_mp_config(), W.crystal_config(),
+            W.sqe_config(), W.crystal_delta_config(), W.powder_8pack_config()]
+    cfgs += W.batch_configs(n_sims=64) + W.goniometer_scan_configs(n_angles=4)
+    for c in cfgs:
+        d = mcv.Detector(c["detector"])
+        assert d.nbins == W.detector_nbins(c["detector"])
+        d.close()
+
+
+def test_pack_layout_validation():
+    from paper_1504_02776_amd import mcv, workloads as W
+    if not os.path.exists(mcv.LIB_PATH):
+        pytest.skip("libmcv.so not built")
+    ok = W.eightpack_detector(16, 10, 1e-3, 2e-3, npacks=4)
+    mcv.Detector(ok).close()
+    for bad in (dict(ok, tubes_per_pack=5),                      # does not divide the columns
+                dict(ok, pack_gap=-0.01),                        # negative gap
+                dict(ok, pack_gap=1.0),                          # gaps leave no room
+                W.eightpack_detector(16, 10, 1e-3, 2e-3, npacks=32)):  # tubes overlap
+        with pytest.raises(mcv.MCVError):
+            mcv.Detector(bad)
