@@ -37,6 +37,10 @@ def build(verbose: bool = False, out: str = LIB, extra=(), sources=None) -> str:
               # correctly rounded: far inside the 1e-5 parity bars, and the
               # correctly rounded sequences are ~10 instructions each
               "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+              # multiply-adds fused only within one source expression: every
+              # kernel that inlines the same device code (plain, trace, event
+              # and batched launches) then rounds it the same way
+              "-ffp-contract=on",
               "-I", os.path.join(HERE, "..", "include"), "-Wall"] + list(extra)
     cmds = []
     for src in sources:

@@ -60,17 +60,15 @@ def test_events_are_the_recorded_packets(torch_cuda, name):
     hb = np.bincount(e["pixel"].astype(np.int64) * ntof + tb,
                      weights=e["value"].astype(np.float64), minlength=plan.nbins)
     assert np.allclose(hb, hist.cpu().numpy(), rtol=1e-12, atol=1e-300)
-    # the same packets as the trace records: per pixel the same orders
-    # exactly, times and values to the rounding by which the separately
-    # compiled run and trace kernels differ (binary32 along a packet's path;
-    # up to 1e-3 relative on spin-wave weights far in a Lorentzian's tail);
-    # each field is compared on its own sort within the pixel
+    # the same packets as the trace records, bit for bit (the run and trace
+    # kernels inline the same device code, fused identically): per pixel the
+    # same orders, times and values, each field compared on its own sort
     rp = (rec["bin"][m] // ntof).astype(np.uint32)
     assert (np.sort(e["pixel"]) == np.sort(rp)).all()
-    for field, tol in (("order", 0.0), ("tof", 1e-5), ("value", 2e-3)):
+    for field in ("order", "tof", "value"):
         a = e[field][np.lexsort((e[field], e["pixel"]))]
         b = rec[field][m][np.lexsort((rec[field][m], rp))]
-        assert np.allclose(a, b, rtol=tol, atol=0), field
+        assert (a == b).all(), field
 
 
 def test_events_only_and_appending_calls(torch_cuda):
