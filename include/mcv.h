@@ -171,7 +171,7 @@ mcv_status mcv_detector_sphere(mcv_detector* out, double R, int32_t n_2theta, in
  * value = weight * (1 - exp(-mu_He chord)); the absorption point is drawn
  * on the chord; pixel = floor(n_pix (y_abs - y_bottom) / length); bin =
  * ((tube * n_pix + pixel) * n_tof + tof_bin), tube = r * ncols + c.
- * Packs (Sec. 2.4.1-2.4.3: 8 tubes make an 8-pack, packs make the detector
+ * Packs (Sec. 2.1 and 2.4.1: 8 tubes make an 8-pack, packs make the detector
  * system): with tubes_per_pack = P > 0 the columns form ncols / P packs with
  * pack_gap radians of extra azimuth between neighbouring packs, and the tube
  * pitch d = (phi_hi - phi_lo - (ncols/P - 1) pack_gap) / ncols puts column c

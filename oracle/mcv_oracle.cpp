@@ -163,7 +163,7 @@ struct ODetector {
 };
 
 // Azimuth of the axis of tube column c.  Columns are grouped in packs of
-// tubes_per_pack tubes (the instruments' 8-packs, Sec. 2.4.1-2.4.3) with a gap
+// tubes_per_pack tubes (the instruments' 8-packs, Sec. 2.1 and 2.4.1) with a gap
 // between packs; the tube pitch d fills [phi_lo, phi_hi] with the packs and
 // their gaps: phi_c = phi_lo + floor(c / P) gap + (c + 1/2) d.
 double column_phi(const ODetector& D, int c) {
