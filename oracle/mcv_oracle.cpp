@@ -89,7 +89,7 @@ inline double speed_from_k(double k) { return k * std::sqrt(kHbar2over2mn / kEpe
 // (mirrored by ctypes in oracle.py)
 enum { SHAPE_BOX = 1, SHAPE_CYLINDER = 2, SHAPE_ANNULUS = 3 };
 enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5, K_MULTIPHONON = 6,
-       K_DISPERSION = 7 };
+       K_DISPERSION = 7, K_COH_PHONON = 8 };
 enum { BEAM_MONO = 1, BEAM_GAUSS = 2 };
 enum { DET_SPHERE = 1, DET_TUBES = 2 };
 enum { STREAM_SOURCE = 0, STREAM_SCATTER = 1, STREAM_DETECT = 2 };
@@ -130,6 +130,11 @@ struct OKernel {
   int32_t nQ, nE;
   double Qmax, Emin, Emax;
   const double* sqe;      // nQ x nE, row major (Q slow)
+  // COH_PHONON (also M, T)
+  int32_t grid_n;         // modes on grid_n^3 points of the reciprocal cell
+  int32_t pad1;
+  double cell[9];         // direct lattice vectors a_1, a_2, a_3 (rows), A
+  const double* modes;    // per point: E_0..E_2 (meV), then e_0, e_1, e_2
 };
 
 struct OScatterer {
@@ -225,7 +230,7 @@ struct OTally {
       n_table_steps, n_hist_updates;
   uint64_t n_segments;      // material intervals crossed
   uint64_t n_splits;        // scattered children drawn
-  uint64_t n_kernel[8];     // kernel draws by type
+  uint64_t n_kernel[9];     // kernel draws by type
   uint64_t n_detect;        // detector calls (escaping packets)
   double w_start[8];        // sum of weight at the start of each flight, per order
   double w_scat[8];         // weight split off to scattering (before the kernel factor)
@@ -475,6 +480,7 @@ struct KernelInfo {
   std::vector<double> a1;                   // multi-phonon: A_1 masses (see a1_masses)
   double a1_sum = 0.0;                      // their sum before normalisation (1 exactly)
   double dw_self = 0.0;                     // multi-phonon: 2W / Q^2 of its own DOS
+  double mode_emax = 0.0;                   // coherent one-phonon: largest mode energy
 };
 
 struct ScatInfo {
@@ -557,6 +563,10 @@ void prepare(const OSetup& S, std::vector<ScatInfo>& info) {
           ki.cdf.push_back(c);
         }
         info[s].dw_coef = hbar2_over_2M(k.M) * gamma0(k);
+      } else if (k.type == K_COH_PHONON) {
+        const int64_t np = (int64_t)k.grid_n * k.grid_n * k.grid_n;
+        for (int64_t i = 0; i < np; ++i)
+          for (int b = 0; b < 3; ++b) ki.mode_emax = std::max(ki.mode_emax, k.modes[12 * i + b]);
       } else if (k.type == K_MULTIPHONON) {
         ki.de = k.emax / k.nbins;
         a1_masses(k, ki.a1, &ki.a1_sum);
@@ -616,6 +626,7 @@ struct Scatter {
   double dq_sens = 0.0;  // |d log(factor) / dQ| (per 1/A of error in Q), for conditioning
   double wsens_add = 0.0;  // further relative weight uncertainty of binary32 (conditioning)
   double dk_rel = 0.0;     // relative uncertainty of the outgoing wave number (conditioning)
+  double ddir_add = -1.0;  // direction uncertainty of a cone kernel (< 0: fresh direction)
 };
 
 V3 isotropic_direction(double u_cos, double u_phi) {
@@ -858,6 +869,92 @@ Scatter k_dispersion(const OKernel& k, const Packet& P, const double* u, double*
   *margin = std::min(*margin, kTauDk / r.dk_rel);
   r.wsens_add = std::fabs(A) * (2.4e-6 + r.dk_rel) / std::fabs(J) + r.dk_rel;
   r.dq_sens = 0.0;
+  return r;
+}
+
+// coherent inelastic one-phonon scattering from a powder (Supplement S4).
+// Averaging the lattice delta function over crystallite orientations turns
+// each point K of reciprocal space (crystal frame) and branch s into a cone
+// of final states with |Q| = |K| and E_f = E_i -+ E_s(K), whose cross section
+// per unit sigma_coh, per unit volume of K space, is
+//   (1/4pi)(k_f/k_i) e^{-2W} hbar^2 (K.e_s)^2/(2M E_s) {coth -+ 1}/2 / (2 k_i k_f K)
+// (the paper's sigma_Q; the (2pi)^3/v0 of the lattice sum cancels against
+// the density of K points).  Proposal: K uniform in the ball of radius
+// Q_max = k_i + k_f,max (k_f,max for E_i plus the largest mode energy: no
+// larger |Q| is reachable), branch uniform, phonon creation with probability
+// (n+1)/(2n+1), azimuth of the cone uniform.  The weight, cross section over
+// proposal density, is Q_max^3 coth(E_s/2kT) e^{-2W} hbar^2 (K.e_s)^2 /
+// (2M E_s) / (2 k_i^2 K).  Modes come from the grid point nearest to K in
+// fractional coordinates K.a_j/2pi (periodic); modes below 1e-3 meV (the
+// acoustic branches at the zone centre) scatter with weight 0.
+// grid point nearest to K: fractional coordinates g_j = n K.a_j / 2pi rounded
+// (floor(g + 1/2)) and taken modulo n; returns ((i0 n + i1) n + i2)
+int64_t cohphonon_index(const OKernel& k, const V3& K, double* margin) {
+  const int n = k.grid_n;
+  const double Km = std::sqrt(dot(K, K));
+  int64_t idx[3];
+  for (int j = 0; j < 3; ++j) {
+    const V3 a = {k.cell[3 * j], k.cell[3 * j + 1], k.cell[3 * j + 2]};
+    const double g = dot(K, a) / (2.0 * kPi) * n;
+    const double fl = std::floor(g + 0.5);
+    // distance to the cell boundary against a binary32 evaluation of g
+    const double tau = kTauRel * (Km * std::sqrt(dot(a, a)) / (2.0 * kPi) * n + 1.0);
+    *margin = std::min(*margin, (0.5 - std::fabs(g - fl)) / tau);
+    idx[j] = (((int64_t)fl % n) + n) % n;
+  }
+  return (idx[0] * n + idx[1]) * n + idx[2];
+}
+
+Scatter k_cohphonon(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
+                    const Packet& P, const double* u, double* margin) {
+  Scatter r;
+  r.dq_sens = 0.0;
+  r.dw_q2 = 0.0;
+  r.dos_bin = -1;
+  r.dir = P.dir;
+  r.speed = P.speed;
+  r.factor = 0.0;
+  const double k_i = k_from_speed(P.speed);
+  const double Ei = kEperV2 * P.speed * P.speed;
+  const double Qmax = k_i + std::sqrt((Ei + ki.mode_emax) / kHbar2over2mn);
+  const double Km = Qmax * std::cbrt(u[2]);
+  const V3 K = scale(isotropic_direction(u[3], u[4]), Km);
+  const double* m = k.modes + 12 * cohphonon_index(k, K, margin);
+  const int s = (int)std::floor(3.0 * u[5]);  // exact: 3u is exact in binary64
+  const double Es = m[s];
+  const V3 e = {m[3 + 3 * s], m[4 + 3 * s], m[5 + 3 * s]};
+  if (!(Es >= 1e-3)) return r;
+  const double kT = kBoltzmann * k.T;
+  const double nb = 1.0 / std::expm1(Es / kT);
+  const double p_create = (nb + 1.0) / (2.0 * nb + 1.0);
+  *margin = std::min(*margin, std::fabs(u[6] - p_create) / kTauU);
+  const bool create = u[6] < p_create;
+  const double Ef = create ? Ei - Es : Ei + Es;
+  *margin = std::min(*margin, std::fabs(Ef) / (kTauRel * Ei));
+  if (Ef <= 0.0) return r;
+  const double k_f = std::sqrt(Ef / kHbar2over2mn);
+  const double scale_c = (k_i * k_i + k_f * k_f + Km * Km) / (2.0 * k_i * k_f);
+  const double c = (k_i * k_i + k_f * k_f - Km * Km) / (2.0 * k_i * k_f);
+  *margin = std::min(*margin, (1.0 - std::fabs(c)) / (kTauRel * scale_c));
+  if (!(std::fabs(c) <= 1.0)) return r;
+  const double sn = std::sqrt(std::max(0.0, 1.0 - c * c));
+  const double phi = 2.0 * kPi * u[7];
+  V3 e1, e2;
+  perp_basis(P.dir, &e1, &e2, margin);
+  const V3 lateral = add(scale(e1, std::cos(phi)), scale(e2, std::sin(phi)));
+  r.dir = add(scale(P.dir, c), scale(lateral, sn));
+  r.speed = speed_from_k(k_f);
+  const double ke = dot(K, e);
+  const double dw = k.dw ? std::exp(-si.dw_coef * Km * Km) : 1.0;
+  r.dw_q2 = k.dw ? Km * Km : 0.0;
+  const double coth = 1.0 / std::tanh(Es / (2.0 * kT));
+  r.factor = Qmax * Qmax * Qmax * coth * dw * hbar2_over_2M(k.M) * ke * ke / Es /
+             (2.0 * k_i * k_i * Km);
+  // binary32 conditioning: the projection K.e loses digits when K is nearly
+  // perpendicular to e; the cone angle acos(c) is steep near c = +-1
+  r.wsens_add = 2.0 * 8.0 * 6e-8 * Km / std::max(std::fabs(ke), 1e-30);
+  const double dc = scale_c * (8.0 * 6e-8 + 2.0 * P.dsp);
+  r.ddir_add = dc / std::max(sn, std::sqrt(dc));
   return r;
 }
 
@@ -1314,6 +1411,7 @@ struct Sim {
                 &child_margin);
             break;
           case K_DISPERSION: r = k_dispersion(kp, Pin, u, &child_margin); break;
+          case K_COH_PHONON: r = k_cohphonon(kp, sip.k[kk], sip, Pin, u, &child_margin); break;
           default: r = k_sqe(kp, Pin, u, &child_margin); break;
         }
         // evaluation-point Debye-Waller factor and DOS over the proposal's
@@ -1369,6 +1467,8 @@ struct Sim {
             double th = 0.5 * std::acos(std::max(-1.0, std::min(1.0, c)));
             double tn = std::tan(std::min(th, 0.5 * kPi - 1e-6));
             C.ddir = P.ddir + 2e-7 + 2.0 * tn * std::max(2e-7 * P.cond, P.dsp);
+          } else if (r.ddir_add >= 0.0) {
+            C.ddir = P.ddir + 2e-7 + r.ddir_add;  // a cone about the incident direction
           } else {
             C.ddir = 2e-7;  // a fresh isotropic direction
           }
@@ -1443,7 +1543,16 @@ struct Sim {
 
 extern "C" {
 
-int oracle_abi_version(void) { return 4; }
+int oracle_abi_version(void) { return 5; }
+
+// grid index the coherent one-phonon kernel (scatterer s, kernel j) reads for
+// a point K of reciprocal space (crystal frame, 1/A); -1 for another kernel
+int64_t oracle_cohphonon_index(const OSetup* S, int s, int j, const double K[3]) {
+  const OKernel& k = S->s[s].k[j];
+  if (k.type != K_COH_PHONON) return -1;
+  double m = kHuge;
+  return cohphonon_index(k, {K[0], K[1], K[2]}, &m);
+}
 
 // A_1 masses of a multi-phonon kernel (2 nbins values, index as in
 // a1_masses, before normalisation) and their sum; returns 0, or 2 if the
@@ -1523,6 +1632,7 @@ void kernel_sample_prepared(const OSetup* S, const std::vector<ScatInfo>& info, 
                         &m);
       break;
     case K_DISPERSION: r = k_dispersion(k, P, u, &m); break;
+    case K_COH_PHONON: r = k_cohphonon(k, info[s].k[j], info[s], P, u, &m); break;
     default: r = k_sqe(k, P, u, &m); break;
   }
   out[0] = r.dir.x * r.speed;

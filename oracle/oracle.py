@@ -44,7 +44,8 @@ class OKernel(C.Structure):
                 ("J", C.c_double), ("S", C.c_double), ("a", C.c_double), ("gamma", C.c_double),
                 ("crot", C.c_double * 9), ("nQ", C.c_int32), ("nE", C.c_int32),
                 ("Qmax", C.c_double), ("Emin", C.c_double), ("Emax", C.c_double),
-                ("sqe", C.POINTER(C.c_double))]
+                ("sqe", C.POINTER(C.c_double)), ("grid_n", C.c_int32), ("pad1", C.c_int32),
+                ("cell", C.c_double * 9), ("modes", C.POINTER(C.c_double))]
 
 
 class OScatterer(C.Structure):
@@ -86,7 +87,7 @@ class OTally(C.Structure):
                 ("n_shape_tests", C.c_uint64), ("n_tube_tests", C.c_uint64),
                 ("n_table_steps", C.c_uint64), ("n_hist_updates", C.c_uint64),
                 ("n_segments", C.c_uint64), ("n_splits", C.c_uint64),
-                ("n_kernel", C.c_uint64 * 8), ("n_detect", C.c_uint64),
+                ("n_kernel", C.c_uint64 * 9), ("n_detect", C.c_uint64),
                 ("w_start", C.c_double * 8), ("w_scat", C.c_double * 8),
                 ("w_abs", C.c_double * 8), ("w_lost", C.c_double * 8)]
 
@@ -102,7 +103,7 @@ RECORD_DTYPE = np.dtype([
 
 SHAPES = {"box": 1, "cylinder": 2, "annulus": 3}
 KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6,
-           "dispersion": 7}
+           "dispersion": 7, "coh_phonon": 8}
 
 _lib = None
 
@@ -141,6 +142,8 @@ def lib():
         L.oracle_kernel_sample_many.argtypes = [C.POINTER(OSetup), C.c_int, C.c_int, C.c_void_p,
                                                 C.c_double, C.c_int64, C.c_void_p, C.c_void_p,
                                                 C.c_void_p]
+        L.oracle_cohphonon_index.restype = C.c_int64
+        L.oracle_cohphonon_index.argtypes = [C.POINTER(OSetup), C.c_int, C.c_int, C.c_void_p]
         L.oracle_multiphonon_a1.restype = C.c_int
         L.oracle_multiphonon_a1.argtypes = [C.POINTER(OSetup), C.c_int, C.c_int, C.c_void_p,
                                             C.POINTER(C.c_double)]
@@ -222,6 +225,11 @@ class Setup:
             o.nQ, o.nE = k["nQ"], k["nE"]
             o.Qmax, o.Emin, o.Emax = k["Qmax"], k["Emin"], k["Emax"]
             o.sqe = self._arr(np.asarray(k["S"]).reshape(-1))
+        elif t == "coh_phonon":
+            o.M, o.T = k["M"], k["T"]
+            o.grid_n = int(k["grid_n"])
+            o.cell[:] = list(np.asarray(k["cell"], dtype=np.float64).reshape(-1))
+            o.modes = self._arr(np.asarray(k["modes"]).reshape(-1))
 
     def nbins(self):
         d = self.cfg["detector"]
@@ -373,6 +381,17 @@ def kernel_samples(cfg, s, j, direction, speed, U, extra=None):
                                     U.ctypes.data, None if X is None else X.ctypes.data,
                                     out.ctypes.data)
     return out[:, :3], out[:, 3]
+
+
+def cohphonon_index(cfg, s, j, K):
+    """Grid index the coherent one-phonon kernel reads for each point K
+    (rows, 1/A, crystal frame)."""
+    st = Setup(cfg)
+    K = np.ascontiguousarray(K, dtype=np.float64).reshape(-1, 3)
+    out = np.empty(len(K), dtype=np.int64)
+    for i, k in enumerate(K):
+        out[i] = lib().oracle_cohphonon_index(C.byref(st.S), s, j, k.ctypes.data)
+    return out
 
 
 def multiphonon_a1(cfg, s, j):

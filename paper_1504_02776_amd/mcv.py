@@ -24,7 +24,7 @@ STATUS_NAMES = ["MCV_OK", "MCV_EINVAL", "MCV_EUNSUPPORTED", "MCV_EOVERLAP", "MCV
 
 SHAPES = {"box": 1, "cylinder": 2, "annulus": 3}
 KERNELS = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6,
-           "dispersion": 7}
+           "dispersion": 7, "coh_phonon": 8}
 
 
 class MCVError(RuntimeError):

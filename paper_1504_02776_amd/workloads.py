@@ -85,6 +85,16 @@ def spinwave(sigma, J, S, a, gamma, crot=IDENTITY):
             "a": float(a), "gamma": float(gamma), "crot": list(crot), "dw": 0}
 
 
+def coh_phonon(sigma, M, T, cell, modes, dw=1):
+    """Coherent one-phonon powder kernel: `modes` (n, n, n, 12) = per point
+    of the reciprocal-cell grid three mode energies (meV) and three unit
+    polarization vectors; `cell` = direct lattice vectors as rows (A)."""
+    modes = np.asarray(modes)
+    return {"type": "coh_phonon", "sigma": float(sigma), "M": float(M), "T": float(T),
+            "cell": [float(x) for x in np.asarray(cell, dtype=np.float64).reshape(-1)],
+            "grid_n": int(modes.shape[0]), "modes": _f32(modes.reshape(-1)), "dw": int(dw)}
+
+
 def dispersion(sigma, J, S, a, crot=IDENTITY):
     """Dispersion surface omega(Q) = 4JS(3 - sum cos(Q_a a)) with an exact
     delta function in energy (S(Q) = 1)."""
@@ -195,6 +205,53 @@ def fcc_shells(a=4.05, dmin=0.5, bc_fm=3.449):
     return _f32(d), _f32(F2)
 
 
+def fcc_cell(a=4.05):
+    """Primitive vectors of the fcc lattice (rows, A)."""
+    return 0.5 * a * np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
+
+
+def fcc_nn_modes(n=32, a=4.05, emax=38.0):
+    """Phonon energies and polarization vectors on the n^3 grid of the
+    reciprocal cell of an fcc crystal with one nearest-neighbour central
+    force constant (a Born-von Karman model, the kind of input the paper's
+    phonon kernels read), scaled so that the highest mode is `emax` meV.
+    Returns (n, n, n, 12): E_0 <= E_1 <= E_2, then e_0, e_1, e_2 (Cartesian,
+    crystal frame)."""
+    cell = fcc_cell(a)
+    recip = 2.0 * np.pi * np.linalg.inv(cell).T          # rows b_i, b_i . a_j = 2 pi delta
+    f = np.arange(n) / n
+    F = np.stack(np.meshgrid(f, f, f, indexing="ij"), axis=-1).reshape(-1, 3)
+    q = F @ recip
+    nn = []
+    for i in range(3):
+        for j in range(i + 1, 3):
+            for si in (1.0, -1.0):
+                for sj in (1.0, -1.0):
+                    r = np.zeros(3)
+                    r[i], r[j] = si * 0.5 * a, sj * 0.5 * a
+                    nn.append(r)
+    nn = np.array(nn)                                    # the 12 neighbours
+    rr = nn / np.linalg.norm(nn, axis=1)[:, None]
+    c = 1.0 - np.cos(q @ nn.T)                           # (points, 12)
+    D = np.einsum("pk,ka,kb->pab", c, rr, rr)
+    lam, vec = np.linalg.eigh(D)
+    lam = np.maximum(lam, 0.0)
+    E = np.sqrt(lam)
+    E *= emax / E.max()
+    out = np.concatenate([E, vec.transpose(0, 2, 1).reshape(-1, 9)], axis=1)
+    return _f32(out.reshape(n, n, n, 12))
+
+
+def grid_dos(modes, nbins=200, emax=None):
+    """Histogram of the mode energies of a grid, zone-centre acoustic modes
+    (below 1e-3 meV) left out: a raw DOS on [0, emax]."""
+    E = np.asarray(modes).reshape(-1, 12)[:, :3].reshape(-1).astype(np.float64)
+    E = E[E >= 1e-3]
+    emax = float(np.float32(E.max() * 1.0001)) if emax is None else emax
+    h, _ = np.histogram(E, bins=nbins, range=(0.0, emax))
+    return _f32(h.astype(np.float64)), emax
+
+
 # --------------------------------------------------------------- workloads
 def plate_config(N=100_000, seed=0):
     """Plain method, small: isotropic incoherent plate, single scattering,
@@ -275,6 +332,29 @@ def powder_8pack_config(N=10_000_000, seed=0):
     cfg["detector"] = eightpack_detector(128, 1000, d["tof_lo"], d["tof_hi"])
     cfg["name"] = "powder-cylinder-8packs"
     return cfg
+
+
+def al_coherent_config(N=10_000_000, seed=0, n_grid=32):
+    """Aluminium-like powder plate at E_i = 80.5 meV: Debye-Scherrer cones of
+    the fcc shells, coherent one-phonon scattering from a nearest-neighbour
+    fcc force-constant model on a 32^3 grid (highest mode 38 meV), and the
+    incoherent one-phonon kernel from the same model's DOS (which also sets
+    the Debye-Waller factor); 300 K, up to 3 orders; three rows of 8-packs."""
+    modes = fcc_nn_modes(n=n_grid)
+    dos, emax = grid_dos(modes)
+    d, F2 = fcc_shells(a=4.05, dmin=0.5, bc_fm=3.449)
+    E = 80.5
+    lo, hi = _tof_window(E, 3.0, 0.7, 2.0)
+    return {
+        "name": "al-coherent-phonon-8packs",
+        "beam": beam(E),
+        "scatterers": [scatterer(box(0.05, 0.05, 0.002), 0.0602, 0.231,
+                                 [powder(66.43, d, F2, dw=1),
+                                  coh_phonon(1.495, 26.98, 300.0, fcc_cell(4.05), modes),
+                                  phonon(0.0082, 26.98, 300.0, emax, dos, dw=1)])],
+        "detector": eightpack_detector(128, 1000, lo, hi),
+        "K": 3, "min_prob": 0.0, "N": N, "seed": seed,
+    }
 
 
 def crystal_config(N=100_000_000, seed=0):
