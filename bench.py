@@ -350,8 +350,8 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--sections", default=None,
                     help="comma-separated extra sections to run (batched, adjoint, plate, "
-                         "crystal, multiphonon, delta, scan, 8packs, events); default: all "
-                         "unless --quick")
+                         "crystal, multiphonon, delta, scan, 8packs, coherent, events); "
+                         "default: all unless --quick")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (PMC byte calibration)")
     args = ap.parse_args()
@@ -441,7 +441,7 @@ def main():
                                "work_per_history": w_hist,
                                "histories_per_launch": N}
     all_sections = ["batched", "adjoint", "plate", "crystal", "multiphonon", "delta", "scan",
-                    "8packs", "events"]
+                    "8packs", "coherent", "events"]
     if args.sections is not None:
         sections = [x for x in args.sections.split(",") if x]
         unknown = set(sections) - set(all_sections)
@@ -471,6 +471,9 @@ def main():
         elif sec == "8packs":
             out["powder_8packs"] = bench_single(torch, mcv, W.powder_8pack_config(), stream, reps,
                                                 "powder_8pack")
+        elif sec == "coherent":
+            out["al_coherent_phonon"] = bench_single(torch, mcv, W.al_coherent_config(), stream,
+                                                     reps, "al_coherent")
         elif sec == "events":
             out["events_and_reduction"] = bench_events_and_reduction(torch, mcv, W, stream, reps)
         print(f"[bench] {sec} done", file=sys.stderr, flush=True)

@@ -86,7 +86,8 @@ enum {
   MCV_K_SPINWAVE = 4,  /* dispersion surface E(Q), S(Q) = 1, Lorentzian (S4)  */
   MCV_K_SQE = 5,       /* tabulated isotropic S(Q,E) (Sec. 2.4.2)             */
   MCV_K_MULTIPHONON = 6, /* incoherent multi-phonon, orders 2..N (S4)         */
-  MCV_K_DISPERSION = 7   /* dispersion surface E(Q), exact delta (S4)         */
+  MCV_K_DISPERSION = 7,  /* dispersion surface E(Q), exact delta (S4)         */
+  MCV_K_COH_PHONON = 8   /* coherent one-phonon, powder, from BZ modes (S4)    */
 };
 
 /* One scattering kernel.  Only the fields of `type` are read.
@@ -117,7 +118,23 @@ enum {
  *     of [0, k_i] (root pairs closer than a cell are not resolved) and one is
  *     taken at random; weight n k_f/k_i / |dG/dE_f|.  gamma is not read.
  *   SQE: S(Q,E) on nQ x nE cells over [0, Qmax] x [Emin, Emax], row major
- *     with Q slow; E is the energy transfer to the sample. */
+ *     with Q slow; E is the energy transfer to the sample.
+ *   COH_PHONON: coherent one-phonon scattering from a powder of a crystal
+ *     with one atom of mass M_amu per primitive cell, temperature T_K (> 0).
+ *     cell = the primitive lattice vectors a_1, a_2, a_3 (rows, A, crystal
+ *     frame); modes = the phonons on the grid_n^3 points (2..128 per axis)
+ *     of the reciprocal cell, point (i, j, k) = (i b_1 + j b_2 + k b_3) /
+ *     grid_n with b_i . a_j = 2 pi delta_ij, at index ((i grid_n + j) grid_n
+ *     + k) * 12: three mode energies (meV, >= 0) then their three unit
+ *     polarization vectors (crystal frame).  A draw takes K uniform in the
+ *     ball |K| <= k_i + k_f,max (k_f,max for E_i plus the largest mode
+ *     energy), the modes of the grid point nearest to K (fractional
+ *     coordinates K . a_j / 2 pi rounded, periodic), a branch at random,
+ *     phonon creation with probability (n+1)/(2n+1), and the outgoing
+ *     direction on the cone |k_i - k_f| = |K| about the incident direction;
+ *     weight Q_max^3 coth(E_s/2kT) e^{-2W} (hbar^2/2M)(K.e_s)^2 / E_s /
+ *     (2 k_i^2 |K|) (Supplement S4, per unit sigma_b).  Modes below 1e-3 meV
+ *     scatter with weight 0.  The table lives in device memory (not LDS). */
 typedef struct {
   int32_t type;
   int32_t dw;
@@ -138,6 +155,10 @@ typedef struct {
   int32_t nQ, nE;
   double Qmax, Emin, Emax;
   const double* sqe;
+  int32_t grid_n;
+  int32_t reserved1;
+  double cell[9];
+  const double* modes;
 } mcv_kernel;
 
 /* ------------------------------------------------------------- assembly */

@@ -73,7 +73,7 @@ const double kEperV2 = 5.22703759e-6;    // meV per (m/s)^2, m_n / 2
 
 struct KernelCopy {
   mcv_kernel k;
-  std::vector<double> d, F2, dos, sqe;
+  std::vector<double> d, F2, dos, sqe, modes;
 };
 
 struct Scatterer {
@@ -254,6 +254,29 @@ mcv_status check_kernel(const mcv_kernel& k) {
         if (!(k.sqe[i] >= 0.0) || !std::isfinite(k.sqe[i])) return fail(MCV_EINVAL, "S(Q,E) values must be >= 0");
       if (k.dw) return fail(MCV_EUNSUPPORTED, "Debye-Waller factor not supported for the S(Q,E) kernel");
       return MCV_OK;
+    case MCV_K_COH_PHONON: {
+      if (!(k.sigma_b >= 0.0) || !(k.M_amu > 0.0) || !(k.T_K > 0.0) || k.grid_n < 2 ||
+          k.grid_n > 128 || !k.modes || !finite_all(k.cell, 9))
+        return fail(MCV_EINVAL, "coherent phonon kernel needs M > 0, T > 0, 2..128 grid points per axis");
+      const double* c = k.cell;
+      const double det = c[0] * (c[4] * c[8] - c[5] * c[7]) - c[1] * (c[3] * c[8] - c[5] * c[6]) +
+                         c[2] * (c[3] * c[7] - c[4] * c[6]);
+      if (!(std::fabs(det) > 1e-6)) return fail(MCV_EINVAL, "cell vectors are degenerate");
+      const int64_t np = (int64_t)k.grid_n * k.grid_n * k.grid_n;
+      double emax = 0.0;
+      for (int64_t i = 0; i < np; ++i) {
+        const double* m = k.modes + 12 * i;
+        for (int b = 0; b < 3; ++b) {
+          if (!(m[b] >= 0.0) || !std::isfinite(m[b])) return fail(MCV_EINVAL, "mode energies must be >= 0");
+          emax = std::max(emax, m[b]);
+          const double* e = m + 3 + 3 * b;
+          const double nn = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+          if (!(std::fabs(nn - 1.0) < 1e-3)) return fail(MCV_EINVAL, "polarization vectors must be unit vectors");
+        }
+      }
+      if (!(emax > 0.0)) return fail(MCV_EINVAL, "all mode energies are zero");
+      return MCV_OK;
+    }
     default:
       return fail(MCV_EINVAL, "unknown kernel type");
   }
@@ -291,6 +314,7 @@ struct mcv_plan_s {
   DevPlan* d_plan = nullptr;
   float* d_tables = nullptr;
   float* d_pixgeo = nullptr;     // per pixel id: |r_p|, cos(2theta) (reduction)
+  std::vector<float*> d_grids;   // mode tables of coherent phonon kernels
   int block = 256;
   int cus = 256;
   int waves_per_simd = 4;
@@ -358,8 +382,10 @@ mcv_status mcv_assembly_add(mcv_assembly a, const mcv_shape* shape, const mcv_ma
       kc.dos.assign(k.dos, k.dos + k.nbins);
     } else if (k.type == MCV_K_SQE) {
       kc.sqe.assign(k.sqe, k.sqe + (size_t)k.nQ * k.nE);
+    } else if (k.type == MCV_K_COH_PHONON) {
+      kc.modes.assign(k.modes, k.modes + (size_t)12 * k.grid_n * k.grid_n * k.grid_n);
     }
-    kc.k.d = kc.k.F2 = kc.k.dos = kc.k.sqe = nullptr;
+    kc.k.d = kc.k.F2 = kc.k.dos = kc.k.sqe = kc.k.modes = nullptr;
     sc.kernels.push_back(std::move(kc));
   }
   a->scat.push_back(std::move(sc));
@@ -448,6 +474,8 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   std::memset(&p->host, 0, sizeof(DevPlan));
   DevPlan& P = p->host;
   std::vector<float>& T = p->tables;
+  // mode tables of coherent phonon kernels, uploaded to device memory below
+  std::vector<std::pair<DevKernel*, std::vector<float>>> grids;
   P.nscat = (int)a->scat.size();
   P.K = o.max_orders;
   P.min_prob = (float)o.min_prob;
@@ -569,6 +597,20 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
         K.a = (float)k.a;
         K.gamma = (float)k.gamma;
         for (int i = 0; i < 9; ++i) K.crot[i] = (float)k.crot[i];
+      } else if (k.type == MCV_K_COH_PHONON) {
+        const int n = k.grid_n;
+        K.nbins = n;
+        K.kT = (float)(kBoltzmann * k.T_K);
+        K.h2m = (float)(kHbar2over2mn * kNeutronMassAmu / k.M_amu);
+        double emax = 0.0;
+        std::vector<float> g(kc.modes.size());
+        for (size_t i = 0; i < kc.modes.size(); ++i) {
+          g[i] = (float)kc.modes[i];
+          if (i % 12 < 3) emax = std::max(emax, kc.modes[i]);
+        }
+        K.wmax = (float)emax;
+        for (int i = 0; i < 9; ++i) K.crot[i] = (float)(k.cell[i] * n / (2.0 * kPi));
+        grids.push_back({&K, std::move(g)});
       } else if (k.type == MCV_K_SQE) {
         K.t_s = (int)T.size();
         for (double v : kc.sqe) T.push_back((float)v);
@@ -671,7 +713,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   P.heavy = 0;
   for (int si = 0; si < P.nscat; ++si)
     for (int j = 0; j < P.s[si].nk; ++j)
-      P.heavy |= P.s[si].k[j].type == K_DISPERSION;
+      P.heavy |= P.s[si].k[j].type == K_DISPERSION || P.s[si].k[j].type == K_COH_PHONON;
   p->block = block;
   p->device = device;
   p->scat = a->scat;
@@ -701,11 +743,28 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     delete p;
     return fail(MCV_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
+  for (auto& gk : grids) {
+    float* dg = nullptr;
+    if ((e = hipMalloc(&dg, gk.second.size() * sizeof(float))) == hipSuccess) p->d_grids.push_back(dg);
+    if (e != hipSuccess || (e = hipMemcpy(dg, gk.second.data(), gk.second.size() * sizeof(float),
+                                          hipMemcpyHostToDevice)) != hipSuccess) {
+      for (float* x : p->d_grids) (void)hipFree(x);
+      (void)hipFree(p->d_plan);
+      (void)hipFree(p->d_tables);
+      (void)hipFree(p->d_pixgeo);
+      (void)hipSetDevice(cur);
+      delete p;
+      return hipfail(e, "mode table upload");
+    }
+    gk.first->grid_lo = (uint32_t)(uintptr_t)dg;
+    gk.first->grid_hi = (uint32_t)((uintptr_t)dg >> 32);
+  }
   if ((e = hipMemcpy(p->d_plan, &P, sizeof(DevPlan), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(p->d_tables, T.data(), T.size() * sizeof(float), hipMemcpyHostToDevice)) !=
           hipSuccess ||
       (e = hipMemcpy(p->d_pixgeo, G.data(), G.size() * sizeof(float), hipMemcpyHostToDevice)) !=
           hipSuccess) {
+    for (float* x : p->d_grids) (void)hipFree(x);
     (void)hipFree(p->d_plan);
     (void)hipFree(p->d_tables);
     (void)hipFree(p->d_pixgeo);
@@ -726,6 +785,7 @@ mcv_status mcv_plan_destroy(mcv_plan p) {
   (void)hipFree(p->d_plan);
   (void)hipFree(p->d_tables);
   (void)hipFree(p->d_pixgeo);
+  for (float* x : p->d_grids) (void)hipFree(x);
   if (p->adj.inv_theta) (void)hipFree(p->adj.inv_theta);
   if (p->adj.dense_a) (void)hipFree(p->adj.dense_a);
   if (p->adj.sums) (void)hipFree(p->adj.sums);

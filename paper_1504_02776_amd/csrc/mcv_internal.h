@@ -21,7 +21,7 @@ constexpr int kFields = 10;              // words per stacked packet
 
 enum { SHAPE_BOX = 1, SHAPE_CYLINDER = 2, SHAPE_ANNULUS = 3 };
 enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5, K_MULTIPHONON = 6,
-       K_DISPERSION = 7 };
+       K_DISPERSION = 7, K_COH_PHONON = 8 };
 enum { DET_SPHERE = 1, DET_TUBES = 2 };
 enum { STREAM_SOURCE = 0u, STREAM_SCATTER = 1u, STREAM_DETECT = 2u };
 
@@ -43,7 +43,8 @@ struct DevKernel {
   // MULTIPHONON
   float dw_self;     // 2W / Q^2 from the kernel's own DOS, A^2
   int32_t nmax;      // highest order N
-  // SPINWAVE and DISPERSION
+  // SPINWAVE and DISPERSION (COH_PHONON: wmax = largest mode energy, crot =
+  // rows n a_j / 2 pi giving grid coordinates, nbins = n, kT, h2m)
   float j4s;         // 4 J S
   float a;           // lattice constant
   float gamma;       // HWHM
@@ -55,6 +56,8 @@ struct DevKernel {
   float Qmax, Emin, Emax;
   float q_scale;     // nQ / Qmax
   float e_scale;     // nE / (Emax - Emin)
+  // COH_PHONON: device address of the mode table (12 floats per grid point)
+  uint32_t grid_lo, grid_hi;
 };
 
 struct DevScat {
@@ -113,7 +116,7 @@ struct alignas(16) DevPlan {
   int32_t n_tables;   // binary32 words in the table blob
   int32_t hot_n;      // slots of the LDS histogram bin cache (power of two)
   int32_t hot_all;    // 1: every histogram update tries the cache (small histograms)
-  int32_t heavy;      // 1: an exact-delta dispersion kernel is present
+  int32_t heavy;      // 1: an exact-delta dispersion or coherent phonon kernel is present
   int32_t pad0;
   DevScat s[kMaxScat];
   DevDet det;

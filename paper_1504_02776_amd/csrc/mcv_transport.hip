@@ -441,6 +441,81 @@ __device__ __forceinline__ Out k_phonon(const DevKernel& K, const DevScat& S, co
   return o;
 }
 
+// Coherent one-phonon scattering from a powder (Supplement S4).  Averaging
+// over crystallite orientations turns every point K of reciprocal space
+// (crystal frame) and branch s into a cone of final states with |Q| = |K|
+// and E_f = E_i -+ E_s(K); per unit sigma and unit K volume its cross
+// section is (1/4pi)(k_f/k_i) e^{-2W} hbar^2 (K.e_s)^2/(2M E_s) {coth -+ 1}/2
+// / (2 k_i k_f |K|).  Draw: K uniform in the ball |K| <= Q_max = k_i +
+// k_f,max (u2 radial, u3 u4 direction), the modes of the grid point nearest
+// to K (grid coordinates K . (n a_j / 2pi) rounded, periodic; a 48-byte
+// gather from the table in device memory), branch s = floor(3 u5) taken
+// exactly from the integer behind u5, creation with probability
+// (n+1)/(2n+1) (u6), azimuth of the cone u7.  Weight = cross section over
+// that density.  Modes below 1e-3 meV scatter with weight 0.
+__device__ __forceinline__ Out k_cohphonon(const DevKernel& K, const DevScat& S, const Pk& P,
+                                           const float* u) {
+  Out o;
+  o.dx = P.dx;
+  o.dy = P.dy;
+  o.dz = P.dz;
+  o.sp = P.sp;
+  o.f = 0.0f;
+  o.dwq2 = 0.0f;
+  o.bin = -1;
+  const float ki = P.sp * kKperV;
+  const float Ei = kEperV2 * P.sp * P.sp;
+  const float qmax = ki + sqrtf((Ei + K.wmax) / kHb2m);
+  const float km = qmax * cbrtf(u[2]);
+  float kx, ky, kz;
+  iso_dir(u[3], u[4], kx, ky, kz);
+  kx *= km;
+  ky *= km;
+  kz *= km;
+  const int n = K.nbins;
+  int idx = 0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const float g = kx * K.crot[3 * j] + ky * K.crot[3 * j + 1] + kz * K.crot[3 * j + 2];
+    int i = (int)floorf(g + 0.5f) % n;
+    if (i < 0) i += n;
+    idx = idx * n + i;
+  }
+  typedef float fv4 __attribute__((ext_vector_type(4)));
+  const fv4* m = reinterpret_cast<const fv4*>(
+      (const float*)(((uint64_t)K.grid_hi << 32) | (uint64_t)K.grid_lo) + 12 * (size_t)idx);
+  const fv4 m0 = m[0], m1 = m[1], m2 = m[2];
+  // u5 = (j + 1/2) 2^-23 exactly: floor(3 u5) = (6 j + 3) >> 24
+  const int s = (6 * (int)(u[5] * 8388608.0f) + 3) >> 24;
+  const float Es = s == 0 ? m0.x : (s == 1 ? m0.y : m0.z);
+  const float ex = s == 0 ? m0.w : (s == 1 ? m1.z : m2.y);
+  const float ey = s == 0 ? m1.x : (s == 1 ? m1.w : m2.z);
+  const float ez = s == 0 ? m1.y : (s == 1 ? m2.x : m2.w);
+  if (!(Es >= 1e-3f)) return o;
+  const float mm = -expm1f(-Es / K.kT);
+  const bool create = u[6] < 1.0f / (2.0f - mm);
+  const float Ef = create ? Ei - Es : Ei + Es;
+  if (!(Ef > 0.0f)) return o;
+  const float kf = sqrtf(Ef / kHb2m);
+  const float c = (ki * ki + kf * kf - km * km) / (2.0f * ki * kf);
+  if (!(fabsf(c) <= 1.0f)) return o;
+  const float sn2 = sqrtf(fmaxf(0.0f, (1.0f - c) * (1.0f + c)));
+  float e1x, e1y, e1z, e2x, e2y, e2z;
+  perp_basis(P.dx, P.dy, P.dz, e1x, e1y, e1z, e2x, e2y, e2z);
+  float sn, cs;
+  sincospif(2.0f * u[7], &sn, &cs);
+  o.dx = c * P.dx + sn2 * (cs * e1x + sn * e2x);
+  o.dy = c * P.dy + sn2 * (cs * e1y + sn * e2y);
+  o.dz = c * P.dz + sn2 * (cs * e1z + sn * e2z);
+  o.sp = kf * kVperK;
+  const float ke = kx * ex + ky * ey + kz * ez;
+  const float dw = K.dw ? expf(-S.dw_coef * km * km) : 1.0f;
+  o.dwq2 = K.dw ? km * km : 0.0f;
+  const float coth = (2.0f - mm) / mm;
+  o.f = qmax * qmax * qmax * coth * dw * K.h2m * ke * ke / Es / (2.0f * ki * ki * km);
+  return o;
+}
+
 __device__ __forceinline__ Out k_spinwave(const DevKernel& K, const Pk& P, const float* u) {
   Out o;
   const float Ei = kEperV2 * P.sp * P.sp;
@@ -889,15 +964,17 @@ __device__ __forceinline__ void segment_terms(const DevScat& S, const float* tab
 }
 
 // (id, lin, seed): the packet's scattering stream, for kernels that draw
-// beyond the split's eight uniforms.  HEAVY: also the exact-delta kernel,
-// whose root scan would otherwise raise the register count of every plan
-// (plans without it use the instantiations without that case).
+// beyond the split's eight uniforms.  HEAVY: also the exact-delta kernel
+// and the coherent one-phonon kernel, whose root scan and table gather
+// would otherwise raise the register count of every plan (plans without
+// them use the instantiations without those cases).
 template <bool HEAVY>
 __device__ __forceinline__ Out kernel_eval(const DevKernel& K, const DevScat& S,
                                            const float* tab, const Pk& P, const float* u,
                                            uint64_t id, uint32_t lin, uint64_t seed) {
   if constexpr (HEAVY) {
     if (K.type == K_DISPERSION) return k_dispersion(K, P, u);
+    if (K.type == K_COH_PHONON) return k_cohphonon(K, S, P, u);
   }
   switch (K.type) {
     case K_ISO_EL: return k_iso(K, S, P, u);

@@ -52,7 +52,8 @@ class mcv_kernel(C.Structure):
                 ("J", C.c_double), ("S", C.c_double), ("a", C.c_double), ("gamma", C.c_double),
                 ("crot", C.c_double * 9), ("nQ", C.c_int32), ("nE", C.c_int32),
                 ("Qmax", C.c_double), ("Emin", C.c_double), ("Emax", C.c_double),
-                ("sqe", C.POINTER(C.c_double))]
+                ("sqe", C.POINTER(C.c_double)), ("grid_n", C.c_int32), ("reserved1", C.c_int32),
+                ("cell", C.c_double * 9), ("modes", C.POINTER(C.c_double))]
 
 
 class mcv_tube_layout(C.Structure):
@@ -205,6 +206,13 @@ def _kernel_struct(k, keep):
         s.nQ, s.nE = k["nQ"], k["nE"]
         s.Qmax, s.Emin, s.Emax = k["Qmax"], k["Emin"], k["Emax"]
         s.sqe = _dptr(g)
+    elif t == "coh_phonon":
+        g = np.ascontiguousarray(np.asarray(k["modes"], dtype=np.float64).reshape(-1))
+        keep.append(g)
+        s.M_amu, s.T_K = k["M"], k["T"]
+        s.grid_n = int(k["grid_n"])
+        s.cell[:] = [float(x) for x in k["cell"]]
+        s.modes = _dptr(g)
     return s
 
 

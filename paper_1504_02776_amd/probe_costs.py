@@ -30,8 +30,7 @@ ITERS = 2048         # calls per lane
 REPS = 3
 
 PR_NULL, PR_RNG, PR_SOURCE, PR_SHAPE, PR_SEGMENT, PR_SPLIT, PR_KERNEL, PR_DETECT = range(8)
-KERNEL_TYPES = {"iso_el": 1, "powder": 2, "phonon": 3, "spinwave": 4, "sqe": 5, "multiphonon": 6,
-                "dispersion": 7}
+from paper_1504_02776_amd.mcv import KERNELS as KERNEL_TYPES  # noqa: E402
 
 
 def _bind():
@@ -98,7 +97,8 @@ def main():
                       ("crystal", W.crystal_config()), ("sqe", W.sqe_config()),
                       ("powder_mp", W.powder_mp_config()),
                       ("crystal_delta", W.crystal_delta_config()),
-                      ("powder_8pack", W.powder_8pack_config())]:
+                      ("powder_8pack", W.powder_8pack_config()),
+                      ("al_coherent", W.al_coherent_config())]:
         res["workloads"][name] = probe_workload(cfg)
         print(f"[probe] {name}: {json.dumps(res['workloads'][name])}", flush=True)
     with open(args.out, "w") as f:

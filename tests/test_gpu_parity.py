@@ -23,6 +23,7 @@ def _cases():
         "powder-multiphonon": (W.powder_mp_config(), 3_000 + 7),
         "crystal-delta": (W.crystal_delta_config(psi_deg=23.0), 600 + 9),
         "powder-8packs": (W.powder_8pack_config(), 3_000 + 13),
+        "al-coherent-phonon": (W.al_coherent_config(), 3_000 + 17),
     }
 
 
