@@ -778,6 +778,18 @@ __device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, c
   const float cq = P.px * P.px + P.pz * P.pz - D.R * D.R;
   const float sR = (-bq + sqrtf(bq * bq - a * cq)) / a;
   const float xR = P.px + sR * P.dx, zR = P.pz + sR * P.dz, yR = P.py + sR * P.dy;
+  const float ra = sqrtf(a);
+  const float dyr = 1.25f * D.radius * fabsf(P.dy) / ra + 1e-4f;
+  // rows whose height range the ray can meet (most rays that miss the
+  // detector pass above or below every row: they leave here, before the
+  // azimuth); the row index is data, so lanes in different rows share one
+  // pass of the tests below
+  uint32_t rows = 0u;
+  for (int r = 0; r < D.nrows; ++r) {
+    const float yc = D.row_y[r];
+    if (!(yR + dyr < yc - D.half_len || yR - dyr > yc + D.half_len)) rows |= 1u << r;
+  }
+  if (rows == 0u) return h;
   // fractional column at the azimuth where the ray crosses radius R; with
   // packs, a ray in the gap after a pack counts as its last column (the
   // neighbours tested below include the next pack's first tube)
@@ -790,17 +802,8 @@ __device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, c
   }
   if (!(fc > -2.0f && fc < (float)D.ncols + 1.0f)) return h;
   const int col = (int)floorf(fc);
-  const float ra = sqrtf(a);
-  const float dyr = 1.25f * D.radius * fabsf(P.dy) / ra + 1e-4f;
   float best = kBig, best_hi = 0.0f, best_len = 0.0f;
   int best_tube = -1, best_row = 0;
-  // rows whose height range the ray can meet; the row index is data, so
-  // lanes in different rows share one pass of the tests below
-  uint32_t rows = 0u;
-  for (int r = 0; r < D.nrows; ++r) {
-    const float yc = D.row_y[r];
-    if (!(yR + dyr < yc - D.half_len || yR - dyr > yc + D.half_len)) rows |= 1u << r;
-  }
   while (rows != 0u) {
     const int r = __ffs(rows) - 1;
     rows &= rows - 1u;
