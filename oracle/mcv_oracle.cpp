@@ -90,7 +90,7 @@ inline double speed_from_k(double k) { return k * std::sqrt(kHbar2over2mn / kEpe
 enum { SHAPE_BOX = 1, SHAPE_CYLINDER = 2, SHAPE_ANNULUS = 3 };
 enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5, K_MULTIPHONON = 6,
        K_DISPERSION = 7, K_COH_PHONON = 8 };
-enum { BEAM_MONO = 1, BEAM_GAUSS = 2 };
+enum { BEAM_MONO = 1, BEAM_GAUSS = 2, BEAM_SAVED = 3 };
 enum { DET_SPHERE = 1, DET_TUBES = 2 };
 enum { STREAM_SOURCE = 0, STREAM_SCATTER = 1, STREAM_DETECT = 2 };
 
@@ -150,6 +150,10 @@ struct OBeam {
   int32_t type;
   int32_t pad;
   double E, sigma_rel, W, H, z0;
+  // SAVED: neutrons saved at the sample position by an earlier step (Sec. 3
+  // workflow): rows x, y, z (m), vx, vy, vz (m/s), t (s), p, n_saved each
+  const double* saved;
+  uint64_t n_saved;
 };
 
 struct ODetector {
@@ -1506,6 +1510,38 @@ struct Sim {
 
   void source(uint64_t id, Packet& P) {
     const OBeam& B = S.beam;
+    P.lineage = 1u;
+    P.order = 0;
+    P.margin_anc = kHuge;
+    P.kinds = 0u;
+    P.cond = 1.0;
+    P.wsens = 0.0;
+    P.ddir = 0.0;
+    P.dpos = 0.0;
+    P.dtime = 0.0;
+    P.dsp = 2e-7;
+    if (tangent) P.dlogw.assign(np, 0.0);
+    if (B.type == BEAM_SAVED) {
+      // entry `id` of the saved neutrons: position, velocity, time, weight
+      const uint64_t n = B.n_saved;
+      const double* r = B.saved;
+      P.pos = {r[id], r[n + id], r[2 * n + id]};
+      const V3 v = {r[3 * n + id], r[4 * n + id], r[5 * n + id]};
+      const double sp = std::sqrt(dot(v, v));
+      P.t = r[6 * n + id];
+      P.w = r[7 * n + id];
+      if (!(sp > 0.0) || !std::isfinite(sp) || !(P.w > 0.0) || !std::isfinite(P.w) ||
+          !std::isfinite(P.t)) {
+        P.dir = {0.0, 0.0, 1.0};
+        P.speed = 1.0;
+        P.w = 0.0;
+        return;
+      }
+      P.dir = scale(v, 1.0 / sp);
+      P.speed = sp;
+      P.ddir = 2e-7;  // a binary32 normalisation of the velocity
+      return;
+    }
     double u[4];
     double E = B.E;
     uint32_t block = 0;
@@ -1525,17 +1561,6 @@ struct Sim {
     P.speed = std::sqrt(E / kEperV2);
     P.t = B.z0 / P.speed;
     P.w = 1.0;
-    P.lineage = 1u;
-    P.order = 0;
-    P.margin_anc = kHuge;
-    P.kinds = 0u;
-    P.cond = 1.0;
-    P.wsens = 0.0;
-    P.ddir = 0.0;
-    P.dpos = 0.0;
-    P.dtime = 0.0;
-    P.dsp = 2e-7;
-    if (tangent) P.dlogw.assign(np, 0.0);
   }
 };
 
@@ -1685,7 +1710,7 @@ int oracle_run2(const OSetup* S, const OSetup* Sp, uint64_t seed, uint64_t first
     uint64_t id = first + i;
     Packet P;
     sim.source(id, P);
-    sim.process(P, id);
+    if (P.w > 0.0) sim.process(P, id);  // invalid saved entries carry no history
   }
   if (n_rec) *n_rec = sim.n_rec;
   return 0;
@@ -1726,7 +1751,7 @@ int oracle_gradient(const OSetup* S, const OParamMap* pm, uint64_t seed, uint64_
     uint64_t id = first + i;
     Packet P;
     sim.source(id, P);
-    sim.process(P, id);
+    if (P.w > 0.0) sim.process(P, id);  // invalid saved entries carry no history
   }
   return 0;
 }

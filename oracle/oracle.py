@@ -56,7 +56,7 @@ class OScatterer(C.Structure):
 class OBeam(C.Structure):
     _fields_ = [("type", C.c_int32), ("pad", C.c_int32), ("E", C.c_double),
                 ("sigma_rel", C.c_double), ("W", C.c_double), ("H", C.c_double),
-                ("z0", C.c_double)]
+                ("z0", C.c_double), ("saved", C.POINTER(C.c_double)), ("n_saved", C.c_uint64)]
 
 
 class ODetector(C.Structure):
@@ -166,9 +166,15 @@ class Setup:
         self.keep = []
         S = OSetup()
         b = cfg["beam"]
-        S.beam.type = 2 if b["type"] == "gauss" else 1
-        S.beam.E, S.beam.sigma_rel = b["E"], b["sigma_rel"]
-        S.beam.W, S.beam.H, S.beam.z0 = b["W"], b["H"], b["z0"]
+        if b["type"] == "saved":
+            rows = np.asarray(b["rows"], dtype=np.float32).astype(np.float64)
+            S.beam.type = 3
+            S.beam.saved = self._arr(rows.reshape(-1))
+            S.beam.n_saved = rows.shape[1]
+        else:
+            S.beam.type = 2 if b["type"] == "gauss" else 1
+            S.beam.E, S.beam.sigma_rel = b["E"], b["sigma_rel"]
+            S.beam.W, S.beam.H, S.beam.z0 = b["W"], b["H"], b["z0"]
         S.nscat = len(cfg["scatterers"])
         S.K = cfg["K"]
         S.min_prob = cfg.get("min_prob", 0.0)
@@ -238,11 +244,18 @@ class Setup:
         return d["nrows"] * d["ncols"] * d["npix"] * d["ntof"]
 
 
+def _check_ids(cfg, first, n):
+    b = cfg["beam"]
+    if b["type"] == "saved" and first + n > np.asarray(b["rows"]).shape[1]:
+        raise ValueError("history ids beyond the saved neutrons")
+
+
 def run(cfg, n=None, first=0, seed=None, records=True, rec_cap=None, w2=False):
     """Run the oracle; returns (hist, hist_w2 or None, records or None, tally)."""
     L = lib()
     st = Setup(cfg)
     n = cfg["N"] if n is None else n
+    _check_ids(cfg, first, n)
     seed = cfg["seed"] if seed is None else seed
     hist = np.zeros(st.nbins(), dtype=np.float64)
     hw2 = np.zeros_like(hist) if w2 else None

@@ -48,6 +48,37 @@ def beam(E, sigma_rel=0.0, W=0.02, H=0.02, z0=-0.1):
             "sigma_rel": float(sigma_rel), "W": W, "H": H, "z0": z0}
 
 
+def saved_beam(rows):
+    """Neutrons saved at the sample position by an earlier simulation step:
+    rows x, y, z (m), vx, vy, vz (m/s), t (s), p, as binary32 (8, n)."""
+    rows = np.asarray(rows, dtype=np.float32)
+    assert rows.ndim == 2 and rows.shape[0] == 8
+    return {"type": "saved", "rows": rows}
+
+
+def divergent_beam_rows(n, E=60.0, sigma_rel=0.02, W=0.02, H=0.02, z0=-0.1, div=0.01,
+                        seed=0):
+    """n seeded stand-ins for neutrons saved at the sample position: uniform
+    over W x H at z0, Gaussian divergence `div` (rad) in both planes, energy
+    E (1 + sigma_rel g), times of a straight flight from z = 0 back to z0,
+    weights uniform in [0.5, 1]."""
+    rng = np.random.default_rng(seed)
+    Ee = E * (1.0 + sigma_rel * rng.standard_normal(n))
+    Ee = np.maximum(Ee, 0.05 * E)
+    v = np.sqrt(Ee / 5.22703759e-6)
+    ax, ay = div * rng.standard_normal(n), div * rng.standard_normal(n)
+    d = np.stack([np.tan(ax), np.tan(ay), np.ones(n)])
+    d /= np.linalg.norm(d, axis=0)
+    rows = np.empty((8, n))
+    rows[0] = (rng.random(n) - 0.5) * W
+    rows[1] = (rng.random(n) - 0.5) * H
+    rows[2] = z0
+    rows[3:6] = d * v
+    rows[6] = z0 / (v * d[2])
+    rows[7] = rng.uniform(0.5, 1.0, n)
+    return _f32(rows)
+
+
 def box(x, y, z, pos=(0.0, 0.0, 0.0), rot=IDENTITY):
     return {"type": "box", "dims": [x, y, z], "pos": list(pos), "rot": list(rot)}
 
@@ -355,6 +386,15 @@ def al_coherent_config(N=10_000_000, seed=0, n_grid=32):
         "detector": eightpack_detector(128, 1000, lo, hi),
         "K": 3, "min_prob": 0.0, "N": N, "seed": seed,
     }
+
+
+def saved_beam_powder_config(n=200_000, seed=0):
+    """The powder sample fed by n saved neutrons (a divergent 100 meV beam
+    with 2 % energy spread) instead of the synthetic beam."""
+    cfg = powder_config(N=n, seed=seed)
+    cfg["beam"] = saved_beam(divergent_beam_rows(n, E=100.0, sigma_rel=0.02, seed=seed + 17))
+    cfg["name"] = "powder-cylinder-saved-beam"
+    return cfg
 
 
 def crystal_config(N=100_000_000, seed=0):
