@@ -241,15 +241,25 @@ mcv_status mcv_plan_destroy(mcv_plan p);
 int64_t mcv_plan_nbins(mcv_plan p);
 
 /* ------------------------------------------------------------------ beam */
-enum { MCV_BEAM_MONO = 1, MCV_BEAM_GAUSS = 2 };
+enum { MCV_BEAM_MONO = 1, MCV_BEAM_GAUSS = 2, MCV_BEAM_SAVED = 3 };
 
 /* Uniform W x H rectangle at z = z0 < 0, collimated along +z.  MONO: energy
  * E.  GAUSS: E (1 + sigma_rel g), g standard normal by Box-Muller, redrawn
- * while E <= 0 (sigma_rel <= 0.2). */
+ * while E <= 0 (sigma_rel <= 0.2).
+ * SAVED: neutrons saved at the sample position by an earlier step of the
+ * workflow (Sec. 3: the beam simulation's neutrons are saved and reused):
+ * `saved` = device binary32 rows x, y, z (m), vx, vy, vz (m/s), t (s), p
+ * (weight), each of n_saved entries (row r of entry i at saved[r * n_saved
+ * + i]); history id i starts from entry i (ids must stay below n_saved;
+ * the source stream is not used).  Entries with p <= 0, zero speed or a
+ * non-finite value carry no history.  E, sigma_rel, W, H, z0 are not read;
+ * the caller keeps the array alive and inside the detector's volume. */
 typedef struct {
   int32_t type;
   int32_t reserved;
   double E, sigma_rel, W, H, z0;
+  const float* saved;
+  uint64_t n_saved;
 } mcv_beam;
 
 /* ------------------------------------------------------------ transport */

@@ -665,6 +665,8 @@ Scatter k_iso(const OKernel& k, const ScatInfo& si, const Packet& P, const doubl
     V3 Q = sub(scale(P.dir, kk), scale(r.dir, kk));
     r.dw_q2 = dot(Q, Q);
     r.factor = std::exp(-si.dw_coef * r.dw_q2);
+    // the Debye-Waller factor depends on |Q|: d log f / dQ = -2 (2W/Q^2) Q
+    r.dq_sens = 2.0 * si.dw_coef * std::sqrt(r.dw_q2);
   }
   return r;
 }
@@ -757,6 +759,10 @@ Scatter k_phonon(const OKernel& k, const KernelInfo& ki, const ScatInfo& si,
   r.dw_q2 = k.dw ? Q2 : 0.0;
   double coth = 1.0 / std::tanh(e / (2.0 * kT));
   r.factor = (k_f / k_i) * h2m * Q2 * dw * coth / e;
+  // the weight depends on |Q| through Q^2 and the Debye-Waller factor:
+  // d log f / dQ = 2/Q - 2 (2W/Q^2) Q
+  const double q = std::sqrt(Q2);
+  r.dq_sens = q > 0.0 ? std::fabs(2.0 / q - (k.dw ? 2.0 * si.dw_coef * q : 0.0)) : 0.0;
   return r;
 }
 
@@ -1539,7 +1545,9 @@ struct Sim {
       }
       P.dir = scale(v, 1.0 / sp);
       P.speed = sp;
-      P.ddir = 2e-7;  // a binary32 normalisation of the velocity
+      // a binary32 normalisation of the velocity: |v| by a square root and
+      // three divisions of up to 2.5 ulp each (about 3e-7 per component)
+      P.ddir = 5e-7;
       return;
     }
     double u[4];

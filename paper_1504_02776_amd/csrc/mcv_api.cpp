@@ -802,6 +802,14 @@ namespace {
 
 mcv_status make_beam(const mcv_plan_s* p, const mcv_beam* b, DevBeam* out) {
   if (!b) return fail(MCV_EINVAL, "null beam");
+  if (b->type == MCV_BEAM_SAVED) {
+    if (!b->saved || b->n_saved == 0) return fail(MCV_EINVAL, "saved beam needs rows and n_saved > 0");
+    *out = DevBeam{};
+    out->type = b->type;
+    out->saved = b->saved;
+    out->n_saved = b->n_saved;
+    return MCV_OK;
+  }
   if (b->type != MCV_BEAM_MONO && b->type != MCV_BEAM_GAUSS) return fail(MCV_EINVAL, "unknown beam type");
   if (!(b->E > 0.0) || !std::isfinite(b->E)) return fail(MCV_EINVAL, "beam energy must be > 0");
   if (!(b->W >= 0.0) || !(b->H >= 0.0) || !std::isfinite(b->W) || !std::isfinite(b->H))
@@ -811,12 +819,22 @@ mcv_status make_beam(const mcv_plan_s* p, const mcv_beam* b, DevBeam* out) {
   if (std::hypot(0.5 * b->W, 0.5 * b->H) > 0.05 * p->R) return fail(MCV_EINVAL, "beam too wide for the detector");
   if (b->type == MCV_BEAM_GAUSS && !(b->sigma_rel >= 0.0 && b->sigma_rel <= 0.2))
     return fail(MCV_EINVAL, "sigma_rel must be in [0, 0.2]");
+  *out = DevBeam{};
   out->type = b->type;
   out->E = (float)b->E;
   out->sigma_rel = (float)b->sigma_rel;
   out->W = (float)b->W;
   out->H = (float)b->H;
   out->z0 = (float)b->z0;
+  return MCV_OK;
+}
+
+// history ids [first, first + n) against the limits of the beam
+mcv_status check_ids(const DevBeam& B, uint64_t first, uint64_t n) {
+  if (n > ((uint64_t)1 << 62) || first > ((uint64_t)1 << 62) - n)
+    return fail(MCV_EINVAL, "history ids must stay below 2^62");
+  if (B.type == MCV_BEAM_SAVED && (first > B.n_saved || n > B.n_saved - first))
+    return fail(MCV_EINVAL, "history ids must stay below the number of saved neutrons");
   return MCV_OK;
 }
 
@@ -837,8 +855,7 @@ mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t firs
   DevBeam B;
   mcv_status st = make_beam(p, beam, &B);
   if (st != MCV_OK) return st;
-  if (n > ((uint64_t)1 << 62) || first > ((uint64_t)1 << 62) - n)
-    return fail(MCV_EINVAL, "history ids must stay below 2^62");
+  if ((st = check_ids(B, first, n)) != MCV_OK) return st;
   if (n == 0) return MCV_OK;
   uint64_t grid, per_wave;
   grid_shape(p, n, p->block, &grid, &per_wave);
@@ -1084,8 +1101,7 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
   if (!dL_dI || !grad) return fail(MCV_EINVAL, "null dL_dI or grad");
   DevBeam B;
   if ((st = make_beam(p, beam, &B)) != MCV_OK) return st;
-  if (n > ((uint64_t)1 << 62) || first > ((uint64_t)1 << 62) - n)
-    return fail(MCV_EINVAL, "history ids must stay below 2^62");
+  if ((st = check_ids(B, first, n)) != MCV_OK) return st;
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
@@ -1210,8 +1226,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
     DevBeam B;
     mcv_status st = make_beam(it.plan, &it.beam, &B);
     if (st != MCV_OK) return st;
-    if (it.n > ((uint64_t)1 << 62) || it.first > ((uint64_t)1 << 62) - it.n)
-      return fail(MCV_EINVAL, "history ids must stay below 2^62");
+    if ((st = check_ids(B, it.first, it.n)) != MCV_OK) return st;
     hitems[i].plan = it.plan->d_plan;
     hitems[i].tables = it.plan->d_tables;
     hitems[i].beam = B;

@@ -138,8 +138,10 @@ constexpr int kAdjFields = 6;  // extra words per stacked packet in adjoint mode
 constexpr int kAdjMaxOrders = 4;
 
 struct DevBeam {
-  int32_t type;  // 1 mono, 2 gauss
+  int32_t type;  // 1 mono, 2 gauss, 3 saved
   float E, sigma_rel, W, H, z0;
+  const float* saved;  // SAVED: rows x, y, z, vx, vy, vz, t, p of n_saved entries
+  uint64_t n_saved;
 };
 
 // one simulation of a batch

@@ -856,6 +856,34 @@ __device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, c
 
 // ------------------------------------------------------------------ source
 __device__ __forceinline__ Pk source(const DevBeam& B, uint64_t id, uint64_t seed) {
+  if (B.type == 3) {
+    // a neutron saved at the sample position: entry id of the rows
+    const uint64_t n = B.n_saved;
+    const float* r = B.saved;
+    Pk P;
+    P.px = r[id];
+    P.py = r[n + id];
+    P.pz = r[2 * n + id];
+    const float vx = r[3 * n + id], vy = r[4 * n + id], vz = r[5 * n + id];
+    P.t = r[6 * n + id];
+    P.w = r[7 * n + id];
+    const float sp = sqrtf(vx * vx + vy * vy + vz * vz);
+    P.lin = 1u;
+    if (!(sp > 0.0f) || !(sp < 3.0e38f) || !(P.w > 0.0f) || !(P.w < 3.0e38f) ||
+        !(fabsf(P.t) < 3.0e38f)) {
+      P.dx = 0.0f;
+      P.dy = 0.0f;
+      P.dz = 1.0f;
+      P.sp = 1.0f;
+      P.w = 0.0f;
+      return P;
+    }
+    P.dx = vx / sp;
+    P.dy = vy / sp;
+    P.dz = vz / sp;
+    P.sp = sp;
+    return P;
+  }
   float u[4];
   draw4(id, STREAM_SOURCE, 1u, 0u, seed, u);
   Pk P;

@@ -72,7 +72,7 @@ class mcv_opts(C.Structure):
 class mcv_beam(C.Structure):
     _fields_ = [("type", C.c_int32), ("reserved", C.c_int32), ("E", C.c_double),
                 ("sigma_rel", C.c_double), ("W", C.c_double), ("H", C.c_double),
-                ("z0", C.c_double)]
+                ("z0", C.c_double), ("saved", C.c_void_p), ("n_saved", C.c_uint64)]
 
 
 class mcv_param_map(C.Structure):
@@ -274,9 +274,24 @@ class Detector:
     __del__ = close
 
 
-def make_beam(b):
+def make_beam(b, device=0):
+    """mcv_beam for a beam description; a saved beam's rows (binary32, 8 x n)
+    are copied to device memory that the returned struct keeps alive, unless
+    they already are a CUDA tensor."""
+    if b["type"] == "saved":
+        import torch
+        rows = b["rows"]
+        if not (isinstance(rows, torch.Tensor) and rows.is_cuda):
+            rows = torch.as_tensor(np.ascontiguousarray(rows, dtype=np.float32),
+                                   device=f"cuda:{device}")
+        if rows.dtype != torch.float32 or rows.dim() != 2 or rows.shape[0] != 8 or \
+                not rows.is_contiguous():
+            raise ValueError("saved beam rows must be a contiguous float32 8 x n array")
+        s = mcv_beam(3, 0, 0.0, 0.0, 0.0, 0.0, 0.0, C.c_void_p(rows.data_ptr()), rows.shape[1])
+        s.keep = rows
+        return s
     return mcv_beam(2 if b["type"] == "gauss" else 1, 0, b["E"], b["sigma_rel"], b["W"],
-                    b["H"], b["z0"])
+                    b["H"], b["z0"], None, 0)
 
 
 def _stream_ptr(stream):
@@ -305,7 +320,7 @@ class Plan:
         asm.close()
         det.close()
         self.nbins = lib().mcv_plan_nbins(self.h)
-        self.beam = make_beam(cfg["beam"])
+        self.beam = make_beam(cfg["beam"], device)
 
     def zeros(self):
         import torch
@@ -315,7 +330,7 @@ class Plan:
         """Adds histories [first, first+n) into `hist` (float64 device tensor)."""
         n = self.cfg["N"] if n is None else n
         seed = self.cfg["seed"] if seed is None else seed
-        b = self.beam if beam is None else make_beam(beam)
+        b = self.beam if beam is None else make_beam(beam, self.device)
         self._check_hist(hist)
         if hist_w2 is not None:
             self._check_hist(hist_w2)
@@ -352,7 +367,7 @@ class Plan:
         CUDA tensor of one element) is advanced by the number of events."""
         n = self.cfg["N"] if n is None else n
         seed = self.cfg["seed"] if seed is None else seed
-        b = self.beam if beam is None else make_beam(beam)
+        b = self.beam if beam is None else make_beam(beam, self.device)
         for h in (hist, hist_w2):
             if h is not None:
                 self._check_hist(h)
@@ -402,7 +417,7 @@ class Plan:
         sum_b dLdI[b] I_b with respect to the parameters of `pm`."""
         n = self.cfg["N"] if n is None else n
         seed = self.cfg["seed"] if seed is None else seed
-        b = self.beam if beam is None else make_beam(beam)
+        b = self.beam if beam is None else make_beam(beam, self.device)
         self._check_hist(dLdI)
         import torch
         if grad.dtype != torch.float64 or not grad.is_cuda or grad.numel() < self.nparams(pm):

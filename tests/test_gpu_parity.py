@@ -24,6 +24,7 @@ def _cases():
         "crystal-delta": (W.crystal_delta_config(psi_deg=23.0), 600 + 9),
         "powder-8packs": (W.powder_8pack_config(), 3_000 + 13),
         "al-coherent-phonon": (W.al_coherent_config(), 3_000 + 17),
+        "powder-saved-beam": (W.saved_beam_powder_config(n=20_000), 3_000 + 19),
     }
 
 
@@ -128,3 +129,26 @@ def test_invalid_arguments_raise(torch_cuda):
         plan.run(h, n=10, beam=bad)
     with pytest.raises(mcv.MCVError):
         plan.run(h, n=10, first=(1 << 62))
+
+
+def test_saved_beam_ids_and_batch(torch_cuda):
+    """A saved beam limits the history ids to its entries; a batch of
+    saved-beam simulations adds the same values as their plain launches."""
+    from paper_1504_02776_amd import mcv
+    cfgs = [W.saved_beam_powder_config(n=5_000, seed=s) for s in (1, 2)]
+    plans = [mcv.Plan(c) for c in cfgs]
+    with pytest.raises(mcv.MCVError):
+        plans[0].run(plans[0].zeros(), n=5_001)
+    with pytest.raises(mcv.MCVError):
+        plans[0].run(plans[0].zeros(), n=10, first=4_995)
+    hists = [p.zeros() for p in plans]
+    b = mcv.Batch(plans, hists, mcv.mcv_tuning(256, 1024, 0, 1))
+    b.run()
+    torch_cuda.cuda.synchronize()
+    for p, h in zip(plans, hists):
+        ref = p.zeros()
+        p.run(ref)
+        torch_cuda.cuda.synchronize()
+        assert np.allclose(h.cpu().numpy(), ref.cpu().numpy(), rtol=1e-9, atol=1e-15)
+        assert float(ref.sum()) > 0
+    b.close()
