@@ -433,9 +433,10 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
 mcv_status mcv_batch_run(mcv_batch b, void* stream);
 mcv_status mcv_batch_destroy(mcv_batch b);
 
-/* Times mcv_batch_run for block sizes {128, 256} x chunks {1024, 4096,
- * 16384, 65536} (reps runs each after one warm-up) and returns the fastest
- * tuning and its time per run (ms).  The histograms are overwritten. */
+/* Times mcv_batch_run for block sizes {64, 128, 192, 256} x chunks {1024,
+ * 4096, 16384, 65536} (reps runs each after one warm-up) and returns the
+ * fastest tuning and its time per run (ms).  The histograms are
+ * overwritten. */
 mcv_status mcv_autotune(const mcv_batch_item* items, int32_t n, int32_t device, int32_t reps,
                         mcv_tuning* best, double* best_ms);
 

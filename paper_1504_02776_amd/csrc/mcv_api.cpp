@@ -1343,7 +1343,7 @@ mcv_status mcv_autotune(const mcv_batch_item* items, int32_t n, int32_t device, 
                         mcv_tuning* best, double* best_ms) {
   if (!items || n < 1 || !best) return fail(MCV_EINVAL, "autotune needs items and an output");
   if (reps < 1) reps = 3;
-  const int blocks[] = {128, 256};
+  const int blocks[] = {64, 128, 192, 256};
   const int chunks[] = {1024, 4096, 16384, 65536};
   int cur = 0;
   (void)hipGetDevice(&cur);

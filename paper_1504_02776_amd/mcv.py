@@ -536,7 +536,7 @@ def autotune(plans, hists, device=0, reps=3, cache=None):
     import torch
     props = torch.cuda.get_device_properties(device)
     arch = getattr(props, "gcnArchName", "unknown")
-    desc = json.dumps([[p.cfg.get("name"), p.cfg["N"], p.cfg["K"], p.cfg["beam"]["E"],
+    desc = json.dumps([[p.cfg.get("name"), p.cfg["N"], p.cfg["K"], p.cfg["beam"].get("E"),
                         p.cfg["scatterers"][0]["shape"]["type"], p.cfg["detector"]["type"]]
                        for p in plans], sort_keys=True)
     key = f"{arch}|{props.multi_processor_count}|{hashlib.sha1(desc.encode()).hexdigest()[:16]}"

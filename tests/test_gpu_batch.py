@@ -67,7 +67,7 @@ def test_autotune_returns_and_caches(torch_cuda, tmp_path):
     hb = [p.zeros() for p in plans]
     cache = str(tmp_path / "tune.json")
     t, ms, cached = mcv.autotune(plans, hb, reps=1, cache=cache)
-    assert t.block_size in (128, 256) and t.chunk in (1024, 4096, 16384, 65536)
+    assert t.block_size in (64, 128, 192, 256) and t.chunk in (1024, 4096, 16384, 65536)
     assert ms > 0 and not cached
     t2, ms2, cached2 = mcv.autotune(plans, hb, reps=1, cache=cache)
     assert cached2 and (t2.block_size, t2.chunk) == (t.block_size, t.chunk)
