@@ -28,18 +28,27 @@ def test_batch_equals_plain_launches(torch_cuda):
     plans = [mcv.Plan(c) for c in cfgs]
     hb = [p.zeros() for p in plans]
     print(f"[batch] {len(cfgs)} sims, {sum(c['N'] for c in cfgs)} histories", flush=True)
-    for tuning in [mcv.mcv_tuning(256, 1024, 0, 1), mcv.mcv_tuning(128, 333, 0, 1)]:
-        b = mcv.Batch(plans, hb, tuning)
-        b.run()
-        b.run()  # replay: histograms are zeroed inside the graph
+    refs = []
+    for p, c in zip(plans, cfgs):
+        ref = p.zeros()
+        p.run(ref)
         torch.cuda.synchronize()
-        for p, h, c in zip(plans, hb, cfgs):
-            ref = p.zeros()
-            p.run(ref)
+        refs.append(ref.cpu().numpy())
+        assert refs[-1].sum() > 0, c["name"]
+    scratch = plans[0].zeros()
+    for tuning in [mcv.mcv_tuning(256, 1024, 0, 1), mcv.mcv_tuning(128, 333, 0, 1),
+                   mcv.mcv_tuning(64, 2048, 0, 1)]:
+        b = mcv.Batch(plans, hb, tuning)
+        # every replay of the graph (histograms zeroed inside it) against the
+        # eager launches, with eager work and synchronisation between replays
+        for rep in range(3):
+            b.run()
             torch.cuda.synchronize()
-            a, r = h.cpu().numpy(), ref.cpu().numpy()
-            assert r.sum() > 0, c["name"]
-            assert np.allclose(a, r, rtol=1e-9, atol=1e-14), c["name"]
+            for h, r, c in zip(hb, refs, cfgs):
+                assert np.allclose(h.cpu().numpy(), r, rtol=1e-9, atol=1e-14), (c["name"], rep)
+            scratch.zero_()
+            plans[0].run(scratch, n=1000)
+            torch.cuda.synchronize()
         b.close()
 
 
