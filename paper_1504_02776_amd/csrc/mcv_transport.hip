@@ -919,9 +919,12 @@ struct Adj {
   uint32_t nph, b01, b23;
 };
 
+// A stacked packet: position, direction, speed, time, weight, lineage and
+// the code of a kernel still to be evaluated for it (scatterer 4 s + kernel
+// k, or -1), then the adjoint carry in adjoint mode.
 template <bool ADJ>
 __device__ __forceinline__ void push(float* st, int slot, int nthreads, int tid, const Pk& C,
-                                     const Adj& a) {
+                                     const Adj& a, int code) {
   constexpr int NF = kFields + (ADJ ? kAdjFields : 0);
   float* b = st + (size_t)slot * NF * nthreads + tid;
   b[0 * nthreads] = C.px;
@@ -934,19 +937,20 @@ __device__ __forceinline__ void push(float* st, int slot, int nthreads, int tid,
   b[7 * nthreads] = C.t;
   b[8 * nthreads] = C.w;
   b[9 * nthreads] = __uint_as_float(C.lin);
+  b[10 * nthreads] = __uint_as_float((uint32_t)code);
   if (ADJ) {
-    b[10 * nthreads] = a.dabs;
-    b[11 * nthreads] = a.dsig;
-    b[12 * nthreads] = a.A;
-    b[13 * nthreads] = __uint_as_float(a.nph);
-    b[14 * nthreads] = __uint_as_float(a.b01);
-    b[15 * nthreads] = __uint_as_float(a.b23);
+    b[11 * nthreads] = a.dabs;
+    b[12 * nthreads] = a.dsig;
+    b[13 * nthreads] = a.A;
+    b[14 * nthreads] = __uint_as_float(a.nph);
+    b[15 * nthreads] = __uint_as_float(a.b01);
+    b[16 * nthreads] = __uint_as_float(a.b23);
   }
 }
 
 template <bool ADJ>
 __device__ __forceinline__ void pop(const float* st, int slot, int nthreads, int tid, Pk& C,
-                                    Adj& a) {
+                                    Adj& a, int& code) {
   constexpr int NF = kFields + (ADJ ? kAdjFields : 0);
   const float* b = st + (size_t)slot * NF * nthreads + tid;
   C.px = b[0 * nthreads];
@@ -959,13 +963,14 @@ __device__ __forceinline__ void pop(const float* st, int slot, int nthreads, int
   C.t = b[7 * nthreads];
   C.w = b[8 * nthreads];
   C.lin = __float_as_uint(b[9 * nthreads]);
+  code = (int)__float_as_uint(b[10 * nthreads]);
   if (ADJ) {
-    a.dabs = b[10 * nthreads];
-    a.dsig = b[11 * nthreads];
-    a.A = b[12 * nthreads];
-    a.nph = __float_as_uint(b[13 * nthreads]);
-    a.b01 = __float_as_uint(b[14 * nthreads]);
-    a.b23 = __float_as_uint(b[15 * nthreads]);
+    a.dabs = b[11 * nthreads];
+    a.dsig = b[12 * nthreads];
+    a.A = b[13 * nthreads];
+    a.nph = __float_as_uint(b[14 * nthreads]);
+    a.b01 = __float_as_uint(b[15 * nthreads]);
+    a.b23 = __float_as_uint(b[16 * nthreads]);
   }
 }
 
@@ -1117,16 +1122,59 @@ __device__ __forceinline__ void flight_exit(Pk& P, const Flight<NSC, TWO>& F) {
   }
 }
 
+// The adjoint terms of a kernel event: d log(mu_k)/d sigma for the
+// differentiated kernel, and the Debye-Waller sum and DOS bin of a one-phonon
+// draw of the DOS scatterer.
+__device__ __forceinline__ void kernel_carries(const AdjArgs& AA, const DevScat& S,
+                                               const DevKernel& K, int si, int kk, const Out& o,
+                                               Adj& ca) {
+  if (si == AA.sig_s && kk == AA.sig_k) ca.dsig += S.n100 / K.mu;
+  if (si == AA.dos_s) {
+    ca.A += o.dwq2;
+    if (kk == AA.dos_k && o.bin >= 0) {
+      const uint32_t sh = 16u * (ca.nph & 1u);
+      if (ca.nph < 2u) ca.b01 |= (uint32_t)o.bin << sh;
+      else ca.b23 |= (uint32_t)o.bin << sh;
+      ++ca.nph;
+    }
+  }
+}
+
+// Evaluates the kernel of a child born with DEFER (code = 4 s + k): the same
+// uniforms (blocks 0 and 1 of its scattering stream) and the same incoming
+// direction and speed as at its birth, so the result is the one an immediate
+// evaluation gives.
+template <bool ADJ, bool HEAVY>
+__device__ __forceinline__ void eval_deferred(const DevPlan& PL, const float* tab,
+                                              const AdjArgs& AA, Pk& C, Adj& ca, int code,
+                                              uint64_t id, uint64_t seed) {
+  const int si = code >> 2, kk = code & 3;
+  const DevScat& S = PL.s[si];
+  const DevKernel& K = S.k[kk];
+  float u[8];
+  draw4(id, STREAM_SCATTER, C.lin, 0u, seed, u);
+  draw4(id, STREAM_SCATTER, C.lin, 1u, seed, u + 4);
+  const Out o = kernel_eval<HEAVY>(K, S, tab, C, u, id, C.lin, seed);
+  C.dx = o.dx;
+  C.dy = o.dy;
+  C.dz = o.dz;
+  C.sp = o.sp;
+  C.w *= o.f;
+  if (ADJ) kernel_carries(AA, S, K, si, kk, o, ca);
+}
+
 // The nearest remaining interval of a flight: the packet is attenuated by
 // e^{-mu L}; with SPLIT (and order < K, w >= min_prob, mu_s > 0) a
-// forced-collision child is born in it, its kernel drawn and evaluated.  The
-// first child of a flight is kept in `nxt`, further ones go to the stack.
-template <bool ADJ, bool SPLIT, int NSC, bool TWO, bool HEAVY>
+// forced-collision child is born in it and its kernel drawn.  The kernel is
+// evaluated at once, or, with DEFER, when the child is taken up (its code
+// travels with it; `nxt_code`).  The first child of a flight is kept in
+// `nxt`, further ones go to the stack.
+template <bool ADJ, bool SPLIT, bool DEFER, int NSC, bool TWO, bool HEAVY>
 __device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
                                             const AdjArgs& AA, Pk& P, Adj& pa,
                                             Flight<NSC, TWO>& F, uint64_t id, uint64_t seed,
-                                            Pk& nxt, Adj& na, bool& has_nxt, float* st, int& nst,
-                                            int nthreads, int tid) {
+                                            Pk& nxt, Adj& na, int& nxt_code, bool& has_nxt,
+                                            float* st, int& nst, int nthreads, int tid) {
   using SL = Slots<NSC, TWO>;
   constexpr int NS = SL::N;
   // nearest remaining interval; ties to the lower scatterer index
@@ -1165,41 +1213,42 @@ __device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
     const uint32_t lin = P.lin * 8u + F.g + 1u;
     float u[8];
     draw4(id, STREAM_SCATTER, lin, 0u, seed, u);
-    draw4(id, STREAM_SCATTER, lin, 1u, seed, u + 4);
+    if (!DEFER) draw4(id, STREAM_SCATTER, lin, 1u, seed, u + 4);
     Pk C;
     float x;
     const int kk = split_child(S, mu, pint, P, F.sx, F.sy, F.sz, F.t0, slo,
                                (int)((F.codes >> (4 * j)) & 0xFu), u, lin, C, x);
-    const DevKernel& K = S.k[kk];
-    const Out o = kernel_eval<HEAVY>(K, S, tab, P, u, id, lin, seed);
-    C.dx = o.dx;
-    C.dy = o.dy;
-    C.dz = o.dz;
-    C.sp = o.sp;
-    C.w *= o.f;
     Adj ca;
     if (ADJ) {
       ca = pa;
       ca.dabs -= x * dmu_abs;
       ca.dsig -= x * dmu_sig;
-      if (si == AA.sig_s && kk == AA.sig_k) ca.dsig += S.n100 / K.mu;
-      if (si == AA.dos_s) {
-        ca.A += o.dwq2;
-        if (kk == AA.dos_k && o.bin >= 0) {
-          const uint32_t sh = 16u * (ca.nph & 1u);
-          if (ca.nph < 2u) ca.b01 |= (uint32_t)o.bin << sh;
-          else ca.b23 |= (uint32_t)o.bin << sh;
-          ++ca.nph;
-        }
-      }
+    }
+    int code = -1;
+    if (DEFER) {
+      C.dx = P.dx;
+      C.dy = P.dy;
+      C.dz = P.dz;
+      C.sp = P.sp;
+      code = 4 * si + kk;
+    } else {
+      const DevKernel& K = S.k[kk];
+      const Out o = kernel_eval<HEAVY>(K, S, tab, P, u, id, lin, seed);
+      C.dx = o.dx;
+      C.dy = o.dy;
+      C.dz = o.dz;
+      C.sp = o.sp;
+      C.w *= o.f;
+      if (ADJ) kernel_carries(AA, S, K, si, kk, o, ca);
     }
     if (C.w > 0.0f) {
       if (!has_nxt) {
         nxt = C;
+        nxt_code = code;
         if (ADJ) na = ca;
         has_nxt = true;
       } else if (nst < PL.stack_cap) {
-        push<ADJ>(st, nst, nthreads, tid, C, ca);
+        push<ADJ>(st, nst, nthreads, tid, C, ca, code);
         ++nst;
       }
     }
@@ -1448,6 +1497,10 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
 // material intervals of its ray (splitting where it may) and records it.
 // Lanes stay in step when the packets of a history are alike (one scatterer
 // and single scattering, or several scatterers whose flights vary anyway).
+// With several scatterers, an annulus or the heavy kernels, a child's kernel
+// is evaluated when the child is taken up, at the top of an iteration where
+// most lanes take up a child together, rather than inside the interval loop
+// where only the lanes that split in that interval are active.
 //
 // trace_phased: the work of a packet is split into two phases that the wave
 // runs one at a time, whichever has more lanes waiting, so that lanes in the
@@ -1475,6 +1528,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
   Adj ca = {0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
   Adj na = ca;
   bool has_nxt = false;
+  int code = -1;  // kernels are evaluated at birth in this loop (no deferral)
   Flight<NSC, TWO> F;
   F.valid = 0u;
   F.g = 0u;
@@ -1488,8 +1542,8 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
     if ((mI | mD) == 0ull) break;
     if (__popcll(mI) >= __popcll(mD)) {
       if (state == LANE_FLY) {
-        flight_step<ADJ, true, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
-                                         st, nst, nthreads, tid);
+        flight_step<ADJ, true, false, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na,
+                                                     code, has_nxt, st, nst, nthreads, tid);
         if (F.valid == 0u) {
           flight_exit(cur, F);
           state = LANE_DET;
@@ -1512,7 +1566,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
     }
     if (state == LANE_NEED && nst > 0) {
       --nst;
-      pop<ADJ>(st, nst, nthreads, tid, cur, ca);
+      pop<ADJ>(st, nst, nthreads, tid, cur, ca, code);
       state = LANE_SETUP;
     }
     const bool need = state == LANE_NEED;
@@ -1533,8 +1587,8 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
       flight_setup(PL, cur, F);
       if (order_of(cur.lin) >= PL.K || cur.w < PL.min_prob) {
         while (F.valid != 0u)
-          flight_step<ADJ, false, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
-                                            st, nst, nthreads, tid);
+          flight_step<ADJ, false, false, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt,
+                                                        na, code, has_nxt, st, nst, nthreads, tid);
       }
       if (F.valid != 0u) {
         state = LANE_FLY;
@@ -1555,18 +1609,20 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
                                            const AdjArgs& AA, double* acc, int hot_n,
                                            int nthreads, int tid) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
+  constexpr bool DEFER = NSC > 1 || TWO || HEAVY;
   const uint64_t lt = lanemask_lt();
   Pk cur;
   cur.lin = 0u;
   Adj ca = {0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
   bool has = false;
+  int code = -1;
   uint64_t hid = 0;
   int nst = 0;
   uint64_t next = begin;
   while (true) {
     if (!has && nst > 0) {
       --nst;
-      pop<ADJ>(st, nst, nthreads, tid, cur, ca);
+      pop<ADJ>(st, nst, nthreads, tid, cur, ca, code);
       has = true;
     }
     const bool need = !has;
@@ -1577,27 +1633,35 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
         hid = first + h;
         cur = source(beam, hid, seed);
         ca = Adj{0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+        code = -1;
         has = cur.w > 0.0f;
       }
     }
     next += (uint64_t)__popcll(m);
     if (__ballot(has) == 0ull) break;
+    if (DEFER && has && code >= 0) {
+      eval_deferred<ADJ, HEAVY>(PL, tab, AA, cur, ca, code, hid, seed);
+      code = -1;
+      has = cur.w > 0.0f;  // a kernel of weight zero ends the child
+    }
     int hbin = -1;
     float hval = 0.0f;
     if (has) {
       Pk nxt;
       nxt.lin = 0u;
       Adj na = ca;
+      int nxt_code = -1;
       bool has_nxt = false;
       Flight<NSC, TWO> F;
       flight_setup(PL, cur, F);
       while (F.valid != 0u)
-        flight_step<ADJ, true, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na, has_nxt,
-                                         st, nst, nthreads, tid);
+        flight_step<ADJ, true, DEFER, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na,
+                                                      nxt_code, has_nxt, st, nst, nthreads, tid);
       flight_exit(cur, F);
       record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
       if (has_nxt) {
         cur = nxt;
+        code = nxt_code;
         if (ADJ) ca = na;
       } else {
         has = false;
