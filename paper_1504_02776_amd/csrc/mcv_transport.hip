@@ -549,11 +549,16 @@ __device__ __forceinline__ Out k_spinwave(const DevKernel& K, const Pk& P, const
 // kernel, S(Q) = 1): for the isotropic outgoing direction d, the outgoing
 // wave numbers are the roots of g(k) = E_i - c k^2 - omega(k_i - k d) on
 // [0, k_i].  They are bracketed by the sign changes of g (g > 0 against
-// g <= 0) at kDispCells + 1 equally spaced k, one is picked (u2), refined by
-// bisection, and the weight n (k_f/k_i) / |dG/dE_f| with dG/dE_f = -1 +
-// (grad omega . d) / (2 c k_f) carries the delta function.  The scan steps
-// the phases Q_a a linearly in k with a rotation recurrence, restarted from
-// sincos every 32 cells; the cells with a sign change are kept as a bit mask.
+// g <= 0) at kDispCells + 1 equally spaced k, one is picked (u2) and refined
+// to the root in its cell, and the weight n (k_f/k_i) / |dG/dE_f| with
+// dG/dE_f = -1 + (grad omega . d) / (2 c k_f) carries the delta function.
+// The scan steps
+// the cosines of the phases Q_a a, linear in k, with Reinsch's form of the
+// cosine recurrence (c_{m+1} = c_m + e_m, e_{m+1} = e_m + lambda c_{m+1},
+// lambda = -4 sin^2(theta/2) for a step theta; stable for small theta),
+// restarted from sincos every 32 cells, and evaluates g at cell j as
+// j4s (cos_x + cos_y + cos_z) - (c h^2 j^2 + 3 j4s - E_i), exact in j^2;
+// the cells with a sign change are kept as a bit mask.
 constexpr int kDispCells = 256;
 
 __device__ __forceinline__ float disp_g(float Ei, float k, float q0x, float q0y, float q0z,
@@ -561,6 +566,14 @@ __device__ __forceinline__ float disp_g(float Ei, float k, float q0x, float q0y,
   return Ei - kHb2m * k * k -
          j4s * (3.0f - cosf((q0x - k * dcx) * a) - cosf((q0y - k * dcy) * a) -
                 cosf((q0z - k * dcz) * a));
+}
+
+// one step theta of the phase: lambda = 2 (cos theta - 1) and sin theta
+__device__ __forceinline__ void reinsch_step(float theta, float& lam, float& st) {
+  float s, c;
+  sincosf(0.5f * theta, &s, &c);
+  lam = -4.0f * s * s;
+  st = 2.0f * s * c;
 }
 
 __device__ __forceinline__ Out k_dispersion(const DevKernel& K, const Pk& P, const float* u) {
@@ -581,10 +594,11 @@ __device__ __forceinline__ Out k_dispersion(const DevKernel& K, const Pk& P, con
   const float dcz = C[6] * o.dx + C[7] * o.dy + C[8] * o.dz;
   const float a = K.a, j4s = K.j4s;
   const float h = ki * (1.0f / (float)kDispCells);
-  float sdx, cdx, sdy, cdy, sdz, cdz;  // rotation by one cell
-  sincosf(-h * dcx * a, &sdx, &cdx);
-  sincosf(-h * dcy * a, &sdy, &cdy);
-  sincosf(-h * dcz * a, &sdz, &cdz);
+  float lx, ly, lz, tx, ty, tz;  // per cell: lambda and sin(theta) of each phase
+  reinsch_step(-h * dcx * a, lx, tx);
+  reinsch_step(-h * dcy * a, ly, ty);
+  reinsch_step(-h * dcz * a, lz, tz);
+  const float ch2 = kHb2m * h * h, r0 = 3.0f * j4s - Ei;
   uint32_t mask[kDispCells / 32];
   bool prev = false;
   int n = 0;
@@ -595,20 +609,22 @@ __device__ __forceinline__ Out k_dispersion(const DevKernel& K, const Pk& P, con
     sincosf((q0x - k0 * dcx) * a, &sx, &cx);
     sincosf((q0y - k0 * dcy) * a, &sy, &cy);
     sincosf((q0z - k0 * dcz) * a, &sz, &cz);
-    if (w == 0) prev = Ei - j4s * (3.0f - cx - cy - cz) > 0.0f;
+    if (w == 0) prev = fmaf(j4s, cx + cy + cz, -r0) > 0.0f;
+    // e = cos(phase + theta) - cos(phase)
+    float ex = fmaf(0.5f * lx, cx, -sx * tx);
+    float ey = fmaf(0.5f * ly, cy, -sy * ty);
+    float ez = fmaf(0.5f * lz, cz, -sz * tz);
     uint32_t bits = 0u;
+#pragma unroll 4
     for (int j = 0; j < 32; ++j) {
-      float t = cx * cdx - sx * sdx;
-      sx = sx * cdx + cx * sdx;
-      cx = t;
-      t = cy * cdy - sy * sdy;
-      sy = sy * cdy + cy * sdy;
-      cy = t;
-      t = cz * cdz - sz * sdz;
-      sz = sz * cdz + cz * sdz;
-      cz = t;
-      const float k = (float)(32 * w + j + 1) * h;
-      const bool pos = Ei - kHb2m * k * k - j4s * (3.0f - cx - cy - cz) > 0.0f;
+      cx += ex;
+      ex = fmaf(lx, cx, ex);
+      cy += ey;
+      ey = fmaf(ly, cy, ey);
+      cz += ez;
+      ez = fmaf(lz, cz, ez);
+      const float jf = (float)(32 * w + j + 1);
+      const bool pos = fmaf(j4s, cx + cy + cz, -fmaf(ch2, jf * jf, r0)) > 0.0f;
       bits |= (uint32_t)(pos != prev) << j;
       prev = pos;
     }
@@ -629,14 +645,28 @@ __device__ __forceinline__ Out k_dispersion(const DevKernel& K, const Pk& P, con
     }
     pick -= c;
   }
+  // refinement: bisection down to h/256 (one root left in the bracket
+  // unless g is tangent there), then two Newton steps from its midpoint
+  // (a step longer than the bracket, as at a tangency, is not taken)
   float lo = (float)cell * h, hi = (float)(cell + 1) * h;
   const bool slo = disp_g(Ei, lo, q0x, q0y, q0z, dcx, dcy, dcz, a, j4s) > 0.0f;
-  for (int it = 0; it < 24; ++it) {
+  for (int it = 0; it < 8; ++it) {
     const float mid = 0.5f * (lo + hi);
     if ((disp_g(Ei, mid, q0x, q0y, q0z, dcx, dcy, dcz, a, j4s) > 0.0f) == slo) lo = mid;
     else hi = mid;
   }
-  const float kf = 0.5f * (lo + hi);
+  float kf = 0.5f * (lo + hi);
+  const float wb = hi - lo;
+  for (int it = 0; it < 2; ++it) {
+    float sx, cx, sy, cy, sz, cz;
+    sincosf((q0x - kf * dcx) * a, &sx, &cx);
+    sincosf((q0y - kf * dcy) * a, &sy, &cy);
+    sincosf((q0z - kf * dcz) * a, &sz, &cz);
+    const float g = Ei - kHb2m * kf * kf - j4s * (3.0f - cx - cy - cz);
+    const float dg = j4s * a * (sx * dcx + sy * dcy + sz * dcz) - 2.0f * kHb2m * kf;
+    const float step = g / dg;
+    if (fabsf(step) <= wb) kf -= step;
+  }
   if (!(kf > 0.0f)) return o;
   const float ga = j4s * a;
   const float A = ga * (sinf((q0x - kf * dcx) * a) * dcx + sinf((q0y - kf * dcy) * a) * dcy +
