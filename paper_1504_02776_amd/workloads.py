@@ -321,6 +321,17 @@ def powder_config(N=10_000_000, seed=0, dos_shift=1.0):
     }
 
 
+def powder_in_can_config(N=10_000_000, seed=0, dos_shift=1.0):
+    """The powder cylinder inside an aluminium-like annular can (r 1.5 /
+    1.6 cm, h 6 cm): two scatterers, the can crossed twice by most rays."""
+    cfg = powder_config(N=N, seed=seed, dos_shift=dos_shift)
+    d, F2 = fcc_shells()
+    cfg["scatterers"].append(scatterer(annulus(0.015, 0.016, 0.06), 0.0602, 0.23,
+                                       [powder(4.05 ** 3, d, F2, dw=0), iso_el(0.008)]))
+    cfg["name"] = "powder-cylinder-in-can-tubes"
+    return cfg
+
+
 def powder_mp_config(N=10_000_000, seed=0):
     """The powder cylinder with a third kernel: incoherent multi-phonon
     scattering (orders 2..4) from the same DOS."""

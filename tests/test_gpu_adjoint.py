@@ -18,9 +18,8 @@ def torch_cuda():
     return torch
 
 
-def _target(oracle_lib, N):
-    tgt, _, _, _ = oracle_lib.run(W.with_n(W.powder_config(dos_shift=1.05), N), seed=1,
-                                  records=False)
+def _target(oracle_lib, make, N):
+    tgt, _, _, _ = oracle_lib.run(W.with_n(make(dos_shift=1.05), N), seed=1, records=False)
     return tgt
 
 
@@ -42,21 +41,17 @@ def test_loss_grad_kernel(torch_cuda):
     assert float(loss.item()) == pytest.approx(float(np.sum(w * (I - T) ** 2)), rel=1e-12)
 
 
-def test_adjoint_matches_oracle_forward_mode(torch_cuda, oracle_lib):
-    """Same histories, same seed: the HIP adjoint (reverse accumulation over
-    re-traced paths) equals the oracle's dense forward-mode gradient."""
+def _check_adjoint(torch, oracle_lib, make, PMx, N):
     from paper_1504_02776_amd import mcv
-    torch = torch_cuda
-    N = 3000
-    cfg = W.powder_config()
-    print(f"[adjoint] oracle forward-mode N={N}", flush=True)
+    cfg = make()
+    print(f"[adjoint] {cfg['name']}: oracle forward-mode N={N}", flush=True)
     I0, _, _, _ = oracle_lib.run(cfg, n=N, records=False)
-    tgt = _target(oracle_lib, N)
+    tgt = _target(oracle_lib, make, N)
     wgt = 1.0 / (tgt + 1e-3 * tgt.mean())
     dLdI = 2.0 * wgt * (I0 - tgt)
-    g_o = oracle_lib.gradient(cfg, PM, dLdI, n=N)
+    g_o = oracle_lib.gradient(cfg, PMx, dLdI, n=N)
     plan = mcv.Plan(cfg)
-    pm = mcv.param_map(PM["dos"], PM["abs"], PM["sig"])
+    pm = mcv.param_map(PMx["dos"], PMx["abs"], PMx["sig"])
     g = torch.zeros(plan.nparams(pm), dtype=torch.float64, device="cuda")
     print("[adjoint] GPU adjoint", flush=True)
     plan.adjoint(pm, torch.from_numpy(dLdI).cuda(), g, n=N)
@@ -72,6 +67,21 @@ def test_adjoint_matches_oracle_forward_mode(torch_cuda, oracle_lib):
     assert np.all(err[:-2] <= 1e-3 * np.abs(g_o[:-2]) + 1e-3 * scale)
     # the dense Debye-Waller/normalisation terms reach bins that no packet drew
     assert np.count_nonzero(g_g[:-2]) == len(g_g) - 2
+
+
+def test_adjoint_matches_oracle_forward_mode(torch_cuda, oracle_lib):
+    """Same histories, same seed: the HIP adjoint (reverse accumulation over
+    re-traced paths) equals the oracle's dense forward-mode gradient."""
+    _check_adjoint(torch_cuda, oracle_lib, W.powder_config, PM, 3000)
+
+
+def test_adjoint_two_scatterers(torch_cuda, oracle_lib):
+    """The same check on the powder cylinder inside a can: two scatterers and
+    an annulus, so the adjoint runs the walk loop, whose children evaluate
+    their kernels (and the kernels' adjoint terms) when taken up; sigma_abs
+    is taken on the can."""
+    _check_adjoint(torch_cuda, oracle_lib, W.powder_in_can_config,
+                   {"dos": (0, 1), "abs": 1, "sig": (0, 1)}, 3000)
 
 
 def test_autograd_backward_is_the_adjoint(torch_cuda):

@@ -19,6 +19,7 @@ def _cases():
         "plate-K3": (dict(W.plate_config(), K=3), 6_000 + 5),
         "powder": (W.powder_config(), 3_000 + 11),
         "crystal": (W.crystal_config(), 600 + 3),
+        "powder-in-can": (W.powder_in_can_config(), 1_500 + 11),
         "sqe": (W.sqe_config(), 4_000 + 1),
         "powder-multiphonon": (W.powder_mp_config(), 3_000 + 7),
         "crystal-delta": (W.crystal_delta_config(psi_deg=23.0), 600 + 9),
