@@ -41,6 +41,11 @@ def build(verbose: bool = False, out: str = LIB, extra=(), sources=None) -> str:
               # kernel that inlines the same device code (plain, trace, event
               # and batched launches) then rounds it the same way
               "-ffp-contract=on",
+              # binary32 denormals flushed: division and square root then
+              # need no frexp/ldexp range scaling (identical results for
+              # normal operands; nothing on the path is that small, and
+              # histograms and tables are binary64, which keeps denormals)
+              "-fgpu-flush-denormals-to-zero",
               "-I", os.path.join(HERE, "..", "include"), "-Wall"] + list(extra)
     cmds = []
     for src in sources:
