@@ -33,6 +33,8 @@ hipError_t launch_adjoint_finalize(double* grad, const double* sums, const doubl
 hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
                             double* dLdI, double* loss, int grid, hipStream_t stream);
 size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, int hot_n);
+bool transport_uses_dq(const DevPlan& P);
+size_t transport_dq_bytes(int block);
 size_t transport_static_lds();
 int transport_waves_per_eu(int nscat, int smax);
 int batch_waves_per_eu();
@@ -706,8 +708,9 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     delete p;
     return fail(MCV_EUNSUPPORTED, "tables and packet stack exceed the 160 KiB of LDS");
   }
-  P.hot_n = hot_slots(transport_static_lds() + transport_lds_bytes(P.n_tables, P.stack_cap,
-                                                                    block, 0, 0),
+  P.hot_n = hot_slots(transport_static_lds() +
+                          transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, 0) +
+                          (transport_uses_dq(P) ? transport_dq_bytes(block) : 0),
                       block, transport_waves_per_eu(P.nscat, P.smax));
   P.hot_all = mcv_detector_nbins(d) <= kHotAllBins ? 1 : 0;
   P.heavy = 0;
@@ -1156,8 +1159,8 @@ mcv_status mcv_loss_grad(const double* I, const double* T, const double* w, int6
 namespace mcv {
 hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32_t n_chunks,
                         uint32_t* cursor, double* const* zero_ptrs, const uint64_t* zero_sizes,
-                        int n_zero, int grid, int block, size_t lds, int hot_n, int reset_grid,
-                        hipStream_t stream);
+                        int n_zero, int grid, int block, size_t lds, int hot_n, int dq_off,
+                        int reset_grid, hipStream_t stream);
 int batch_occupancy(int block, size_t lds);
 }  // namespace mcv
 
@@ -1173,6 +1176,7 @@ struct mcv_batch_s {
   int grid = 0, block = 0;
   size_t lds = 0;
   int hot_n = kHotMin;
+  int dq_off = 0;  // words from the start of dynamic LDS to the detection queues
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1253,17 +1257,23 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
                    [](const auto& a, const auto& b) { return a.first > b.first; });
   std::vector<BatchChunk> cl;
   for (auto& c : hchunks) cl.push_back(c.second);
-  size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, kHotMin);
+  // dynamic LDS: bin cache, largest tables, largest stacks, then the waves'
+  // detection queues (phased items with tube detectors)
+  size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, kHotMin) +
+               transport_dq_bytes(block);
   while (lds + transport_static_lds() + 64 > 160 * 1024 && block > 64) {
     block -= 64;
-    lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, kHotMin);
+    lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, kHotMin) +
+          transport_dq_bytes(block);
   }
   if (lds + transport_static_lds() + 64 > 160 * 1024)
     return fail(MCV_EUNSUPPORTED, "batch tables and stacks exceed LDS");
   const int hot_n = hot_slots(transport_static_lds() + 64 +
-                                  transport_lds_bytes(n_tables_max, stack_max, block, 0, 0),
+                                  transport_lds_bytes(n_tables_max, stack_max, block, 0, 0) +
+                                  transport_dq_bytes(block),
                               block, batch_waves_per_eu());
-  lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, hot_n);
+  const size_t lds_q = transport_lds_bytes(n_tables_max, stack_max, block, 0, hot_n);
+  lds = lds_q + transport_dq_bytes(block);
 
   auto* b = new (std::nothrow) mcv_batch_s();
   if (!b) return fail(MCV_ENOMEM, "host allocation failed");
@@ -1274,6 +1284,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   b->block = block;
   b->lds = lds;
   b->hot_n = hot_n;
+  b->dq_off = (int)(lds_q / sizeof(float));
   b->n_chunks = (uint32_t)cl.size();
   b->n_zero = (int)zp.size();
   int cus = 256;
@@ -1304,7 +1315,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
       (e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
     hipError_t el = launch_batch(b->d_items, b->d_chunks, b->n_chunks, b->d_cursor,
                                  b->d_zero_ptrs, b->d_zero_sizes, b->n_zero, b->grid, b->block,
-                                 b->lds, b->hot_n, cus * 4, b->capture);
+                                 b->lds, b->hot_n, b->dq_off, cus * 4, b->capture);
     e = hipStreamEndCapture(b->capture, &b->graph);
     if (e == hipSuccess) e = el;
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);

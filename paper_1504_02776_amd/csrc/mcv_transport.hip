@@ -794,16 +794,14 @@ __device__ __forceinline__ Hit detect_sphere(const DevDet& D, const Pk& P) {
 // First tube on the ray among the few whose axis can come within a radius
 // of it: the columns around the azimuth where the ray crosses radius R, in
 // the rows its height range overlaps.  Exact cylinder tests decide.
-__device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, const Pk& P,
-                                            uint64_t id, uint64_t seed) {
-  Hit h;
-  h.bin = -1;
-  h.value = 0.0f;
-  h.tof = 0.0f;
-  h.tube = -1;
-  h.pixel = -1;
-  const float a = P.dx * P.dx + P.dz * P.dz;
-  if (a == 0.0f) return h;
+// The first steps of the tube test: the rows (bit mask) whose height range
+// the ray meets at radius R and the column at its azimuth there.  False if
+// the ray can meet no tube; detect_tubes takes these steps first, so a
+// packet for which this is false is one detect_tubes records no hit for.
+__device__ __forceinline__ bool tube_column(const DevDet& D, const Pk& P, float& a, uint32_t& rows,
+                                            int& col) {
+  a = P.dx * P.dx + P.dz * P.dz;
+  if (a == 0.0f) return false;
   const float bq = P.px * P.dx + P.pz * P.dz;
   const float cq = P.px * P.px + P.pz * P.pz - D.R * D.R;
   const float sR = (-bq + sqrtf(bq * bq - a * cq)) / a;
@@ -813,16 +811,16 @@ __device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, c
   // rows whose height range the ray can meet (most rays that miss the
   // detector pass above or below every row: they leave here, before the
   // azimuth); the row index is data, so lanes in different rows share one
-  // pass of the tests below
-  uint32_t rows = 0u;
+  // pass of the candidate tests
+  rows = 0u;
   for (int r = 0; r < D.nrows; ++r) {
     const float yc = D.row_y[r];
     if (!(yR + dyr < yc - D.half_len || yR - dyr > yc + D.half_len)) rows |= 1u << r;
   }
-  if (rows == 0u) return h;
+  if (rows == 0u) return false;
   // fractional column at the azimuth where the ray crosses radius R; with
   // packs, a ray in the gap after a pack counts as its last column (the
-  // neighbours tested below include the next pack's first tube)
+  // neighbours tested in detect_tubes include the next pack's first tube)
   const float ax = atan2f(xR, zR) - D.phi_lo;
   float fc = ax * D.inv_dphi;
   if (D.tpp > 0) {
@@ -830,8 +828,23 @@ __device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, c
     const float within = (ax - pk * D.pack_pitch) * D.inv_tube_pitch;
     fc = pk * (float)D.tpp + fminf(within, (float)D.tpp - 0.5f);
   }
-  if (!(fc > -2.0f && fc < (float)D.ncols + 1.0f)) return h;
-  const int col = (int)floorf(fc);
+  if (!(fc > -2.0f && fc < (float)D.ncols + 1.0f)) return false;
+  col = (int)floorf(fc);
+  return true;
+}
+
+__device__ __forceinline__ Hit detect_tubes(const DevDet& D, const float* tab, const Pk& P,
+                                            uint64_t id, uint64_t seed) {
+  Hit h;
+  h.bin = -1;
+  h.value = 0.0f;
+  h.tof = 0.0f;
+  h.tube = -1;
+  h.pixel = -1;
+  float a;
+  uint32_t rows;
+  int col;
+  if (!tube_column(D, P, a, rows, col)) return h;
   float best = kBig, best_hi = 0.0f, best_len = 0.0f;
   int best_tube = -1, best_row = 0;
   while (rows != 0u) {
@@ -1518,6 +1531,70 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
   }
 }
 
+// Detection queue of a wave (phased loop, tube detectors, run and trace
+// modes): of the packets recorded in a D phase, only those whose ray passes
+// the first steps of the tube test (tube_column: about one in six for the
+// powder) need the rest of it (candidate tubes, absorption, a Philox block,
+// bin).  Run in the D phase, that rest would take the whole wave for the few
+// lanes holding such packets; instead they are appended to a per-wave LDS
+// queue of kDqEntries packets, which the wave records together (one packet
+// per lane) when the next D phase would overflow it, and at the end.
+// Layout: [field][entry], 12 fields (position, direction, speed, time,
+// weight, lineage, history id low and high words).
+constexpr int kDqEntries = 64;
+constexpr int kDqFields = 12;
+constexpr int kDqWords = kDqEntries * kDqFields;
+
+__device__ __forceinline__ void dq_put(float* q, int slot, const Pk& P, uint64_t hid) {
+  float* b = q + slot;
+  b[0 * kDqEntries] = P.px;
+  b[1 * kDqEntries] = P.py;
+  b[2 * kDqEntries] = P.pz;
+  b[3 * kDqEntries] = P.dx;
+  b[4 * kDqEntries] = P.dy;
+  b[5 * kDqEntries] = P.dz;
+  b[6 * kDqEntries] = P.sp;
+  b[7 * kDqEntries] = P.t;
+  b[8 * kDqEntries] = P.w;
+  b[9 * kDqEntries] = __uint_as_float(P.lin);
+  b[10 * kDqEntries] = __uint_as_float((uint32_t)hid);
+  b[11 * kDqEntries] = __uint_as_float((uint32_t)(hid >> 32));
+}
+
+// records the n queued packets, one per lane (called with the whole wave
+// active; a wave of fewer lanes takes several passes)
+template <int MODE>
+__device__ __forceinline__ void dq_run(const DevPlan& PL, const float* tab, const Sinks& out,
+                                       const AdjArgs& AA, double* acc, int hot_n, const float* q,
+                                       int n, uint64_t seed) {
+  const int nl = __popcll(__ballot(1));
+  for (int base = 0; base < n; base += nl) {
+    const int i = base + (int)__lane_id();
+    int hbin = -1;
+    float hval = 0.0f;
+    if (i < n) {
+      const float* b = q + i;
+      Pk P;
+      P.px = b[0 * kDqEntries];
+      P.py = b[1 * kDqEntries];
+      P.pz = b[2 * kDqEntries];
+      P.dx = b[3 * kDqEntries];
+      P.dy = b[4 * kDqEntries];
+      P.dz = b[5 * kDqEntries];
+      P.sp = b[6 * kDqEntries];
+      P.t = b[7 * kDqEntries];
+      P.w = b[8 * kDqEntries];
+      P.lin = __float_as_uint(b[9 * kDqEntries]);
+      const uint64_t hid = (uint64_t)__float_as_uint(b[10 * kDqEntries]) |
+                           ((uint64_t)__float_as_uint(b[11 * kDqEntries]) << 32);
+      const Adj ca = {0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+      record_packet<MODE>(PL, tab, out, AA, acc, P, ca, hid, seed, hbin, hval);
+    }
+    if (out.hist != nullptr || out.hist_w2 != nullptr)
+      hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
+  }
+}
+
 // One wave traces histories first+begin .. first+end-1.  Every lane walks
 // the packet tree of one history depth first (first child in registers,
 // further children on its LDS stack) and takes the next history of the range
@@ -1543,13 +1620,14 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
 //      attenuation only and waits for the next D phase.
 // Called with the whole wave active.  `acc` is the workgroup's LDS block:
 // adjoint partials (MODE_ADJOINT) or the histogram bin cache (otherwise).
-template <int MODE, int NSC, bool TWO, bool HEAVY>
+template <int MODE, int NSC, bool TWO, bool HEAVY, bool DQ>
 __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab, float* st,
                                              const DevBeam& beam, uint64_t seed, uint64_t first,
                                              uint64_t begin, uint64_t end, const Sinks& out,
                                              const AdjArgs& AA, double* acc, int hot_n,
-                                             int nthreads, int tid) {
+                                             int nthreads, int tid, float* dq) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
+  static_assert(!(DQ && ADJ), "the adjoint records its packets at once");
   const uint64_t lt = lanemask_lt();
   Pk cur;
   cur.lin = 0u;
@@ -1566,10 +1644,14 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
   int nst = 0;
   int state = LANE_NEED;
   uint64_t next = begin;
+  int qn = 0;  // packets in the detection queue (the same in every lane)
   while (true) {
     const uint64_t mI = __ballot(state == LANE_FLY);
     const uint64_t mD = __ballot(state == LANE_NEED || state == LANE_DET);
-    if ((mI | mD) == 0ull) break;
+    if ((mI | mD) == 0ull) {
+      if (DQ && qn > 0) dq_run<MODE>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
+      break;
+    }
     if (__popcll(mI) >= __popcll(mD)) {
       if (state == LANE_FLY) {
         flight_step<ADJ, true, false, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na,
@@ -1583,8 +1665,26 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
     }
     int hbin = -1;
     float hval = 0.0f;
+    if constexpr (DQ) {
+      float a;
+      uint32_t rows;
+      int col;
+      const bool q = state == LANE_DET && tube_column(PL.det, cur, a, rows, col);
+      const uint64_t mq = __ballot(q);
+      const int k = __popcll(mq);
+      if (qn + k > kDqEntries) {
+        dq_run<MODE>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
+        qn = 0;
+      }
+      if (q) dq_put(dq, qn + __popcll(mq & lt), cur, hid);
+      qn += k;
+      // a packet that meets no tube leaves no histogram entry; trace mode
+      // still writes its record
+      if (MODE == MODE_TRACE && state == LANE_DET && !q)
+        record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
+    }
     if (state == LANE_DET) {
-      record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
+      if (!DQ) record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
       if (has_nxt) {
         cur = nxt;
         if (ADJ) ca = na;
@@ -1627,7 +1727,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
         state = LANE_DET;
       }
     }
-    if (!ADJ && (out.hist != nullptr || out.hist_w2 != nullptr))
+    if (!ADJ && !DQ && (out.hist != nullptr || out.hist_w2 != nullptr))
       hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
   }
 }
@@ -1710,15 +1810,16 @@ __host__ __device__ constexpr bool use_phased(int nscat, bool two, int K) {
   return nscat <= 1 && !two && K >= 2;
 }
 
-template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY>
+template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, bool DQ = false>
 __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab, float* st,
                                             const DevBeam& beam, uint64_t seed, uint64_t first,
                                             uint64_t begin, uint64_t end, const Sinks& out,
                                             const AdjArgs& AA, double* acc, int hot_n,
-                                            int nthreads, int tid) {
+                                            int nthreads, int tid, float* dq = nullptr) {
+  static_assert(PHASED || !DQ, "the detection queue belongs to the phased loop");
   if constexpr (PHASED)
-    trace_phased<MODE, NSC, TWO, HEAVY>(PL, tab, st, beam, seed, first, begin, end, out, AA, acc, hot_n,
-                                 nthreads, tid);
+    trace_phased<MODE, NSC, TWO, HEAVY, DQ>(PL, tab, st, beam, seed, first, begin, end, out, AA,
+                                            acc, hot_n, nthreads, tid, dq);
   else
     trace_walk<MODE, NSC, TWO, HEAVY>(PL, tab, st, beam, seed, first, begin, end, out, AA, acc, hot_n,
                                nthreads, tid);
@@ -1739,7 +1840,7 @@ __device__ __forceinline__ void stage_plan(DevPlan& PL, float* dyn, const DevPla
 // numbers) and accumulates dL/dtheta = sum over recorded packets of
 // dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
 // per workgroup.
-template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY>
+template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, bool DQ = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     NSC == 1 && !TWO ? MCV_WAVES_PER_EU_SIMPLE : MCV_WAVES_PER_EU)))
 transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
@@ -1766,17 +1867,21 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
   Sinks o = out;
+  // after the packet stacks: the waves' detection queues, then their event
+  // stages
+  float* dqs = st + (size_t)PL.stack_cap * kFields * nthreads;
+  float* dq = dqs + (tid >> 6) * kDqWords;
+  float* evs = DQ ? dqs + (nthreads >> 6) * kDqWords : dqs;
   if (events) {
-    // event stages after the packet stacks, one per wave of the workgroup
-    float* sw = st + (size_t)PL.stack_cap * kFields * nthreads + (tid >> 6) * kEvStageWords;
+    float* sw = evs + (tid >> 6) * kEvStageWords;
     o.stage = reinterpret_cast<DevEvent*>(sw);
     o.stage_n = reinterpret_cast<volatile int*>(sw + kEvStage * 4);
     if ((tid & 63) == 0) *o.stage_n = 0;
   }
   if (begin < n) {  // uniform per wave
-    trace_range<MODE, NSC, TWO, PHASED, HEAVY>(PL, dyn, st, beam, seed, first, begin,
-                                begin + per_wave < n ? begin + per_wave : n, o, AA, acc, hot_n,
-                                nthreads, tid);
+    trace_range<MODE, NSC, TWO, PHASED, HEAVY, DQ>(PL, dyn, st, beam, seed, first, begin,
+                                                   begin + per_wave < n ? begin + per_wave : n, o,
+                                                   AA, acc, hot_n, nthreads, tid, dq);
     if (events) {
       const int left = *o.stage_n;
       if (left > 0) ev_flush(o, left);
@@ -1807,7 +1912,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
 // estimated cost, longest first.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MCV_WAVES_PER_EU)))
 batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restrict__ chunks,
-                 uint32_t n_chunks, uint32_t* __restrict__ cursor, int hot_n) {
+                 uint32_t n_chunks, uint32_t* __restrict__ cursor, int hot_n, int dq_off) {
   __shared__ DevPlan PL;
   __shared__ uint32_t s_chunk;
   extern __shared__ __align__(16) float dyn[];
@@ -1839,6 +1944,8 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const uint64_t e = ch.first + ch.count;
     Sinks out = {it.hist, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr};
     const uint64_t ee = b + per < e ? b + per : e;
+    // the waves' detection queues sit behind the largest tables and stacks
+    float* dq = dyn + dq_off + wid * kDqWords;
     // the same specialisation as a plain launch of this plan, so that both
     // evaluate identical arithmetic
     const bool two = PL.smax > PL.nscat;
@@ -1848,6 +1955,10 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
 #define MCV_BATCH_SHAPES(HV_)                                                       \
   if (PL.nscat <= 1) {                                                              \
     if (two) MCV_BATCH_TRACE(1, true, false, HV_);                                  \
+    else if (use_phased(PL.nscat, two, PL.K) && PL.det.type == DET_TUBES)          \
+      trace_range<MODE_RUN, 1, false, true, HV_, true>(PL, tab, st, it.beam, it.seed,  \
+                                                       it.id0, b, ee, out, AA, hot,    \
+                                                       hot_n, nthreads, tid, dq);      \
     else if (use_phased(PL.nscat, two, PL.K)) MCV_BATCH_TRACE(1, false, true, HV_); \
     else MCV_BATCH_TRACE(1, false, false, HV_);                                     \
   } else if (PL.nscat == 2) {                                                       \
@@ -1962,6 +2073,15 @@ __global__ void __launch_bounds__(256) loss_grad(const double* __restrict__ I,
 }  // namespace dev
 
 // ------------------------------------------------------------------ launch
+// LDS of the waves' detection queues, for plans that use them: phased loop
+// (one convex scatterer, K >= 2) and a tube detector, outside the adjoint
+bool transport_uses_dq(const DevPlan& P) {
+  return dev::use_phased(P.nscat, P.smax > P.nscat, P.K) && P.det.type == DET_TUBES;
+}
+size_t transport_dq_bytes(int block) {
+  return sizeof(float) * (size_t)dev::kDqWords * (size_t)(block / 64);
+}
+
 size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, int hot_n) {
   const size_t tab = (size_t)((n_tables + 3) & ~3);
   const size_t acc = adj_nb > 0 ? 2 * (size_t)(((adj_nb + 4) + 1) & ~1)
@@ -1972,17 +2092,17 @@ size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, i
 
 namespace {
 
-template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY>
+template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, bool DQ = false>
 void launch_one(int grid, int block, size_t lds, hipStream_t stream, const DevPlan* plan,
                 const float* tables, const DevBeam& beam, uint64_t seed, uint64_t first,
                 uint64_t n, uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
-  hipLaunchKernelGGL((dev::transport<MODE, NSC, TWO, PHASED, HEAVY>), dim3(grid), dim3(block), lds,
+  hipLaunchKernelGGL((dev::transport<MODE, NSC, TWO, PHASED, HEAVY, DQ>), dim3(grid), dim3(block), lds,
                      stream, plan,
                      tables, beam, seed, first, n, per_wave, out, AA);
 }
 
 template <int MODE, bool HEAVY>
-void launch_shapes(int nsc, bool two, bool phased, int grid, int block, size_t lds,
+void launch_shapes(int nsc, bool two, bool phased, bool dq, int grid, int block, size_t lds,
                    hipStream_t stream, const DevPlan* plan, const float* tables,
                    const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
                    uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
@@ -1991,6 +2111,9 @@ void launch_shapes(int nsc, bool two, bool phased, int grid, int block, size_t l
                                            first, n, per_wave, out, AA)
   if (nsc <= 1) {
     if (two) MCV_LAUNCH(1, true, false);
+    else if (phased && dq && MODE != dev::MODE_ADJOINT)
+      launch_one<MODE, 1, false, true, HEAVY, MODE != dev::MODE_ADJOINT>(
+          grid, block, lds, stream, plan, tables, beam, seed, first, n, per_wave, out, AA);
     else if (phased) MCV_LAUNCH(1, false, true);
     else MCV_LAUNCH(1, false, false);
   } else if (nsc == 2) {
@@ -2004,15 +2127,15 @@ void launch_shapes(int nsc, bool two, bool phased, int grid, int block, size_t l
 }
 
 template <int MODE>
-void launch_mode(int nsc, bool two, bool phased, bool heavy, int grid, int block, size_t lds,
-                 hipStream_t stream, const DevPlan* plan, const float* tables,
+void launch_mode(int nsc, bool two, bool phased, bool dq, bool heavy, int grid, int block,
+                 size_t lds, hipStream_t stream, const DevPlan* plan, const float* tables,
                  const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
                  uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
   if (heavy)
-    launch_shapes<MODE, true>(nsc, two, phased, grid, block, lds, stream, plan, tables, beam,
+    launch_shapes<MODE, true>(nsc, two, phased, dq, grid, block, lds, stream, plan, tables, beam,
                               seed, first, n, per_wave, out, AA);
   else
-    launch_shapes<MODE, false>(nsc, two, phased, grid, block, lds, stream, plan, tables, beam,
+    launch_shapes<MODE, false>(nsc, two, phased, dq, grid, block, lds, stream, plan, tables, beam,
                                seed, first, n, per_wave, out, AA);
 }
 
@@ -2028,50 +2151,53 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
   AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = -1;
   if (adj) AA = *adj;
   dev::Sinks out = {hist, hist_w2, rec, cap, n_out, ev, ev_cap, n_ev, 0, nullptr, nullptr};
+  const bool dq = !adj && transport_uses_dq(host_plan);
+  const size_t qbytes = dq ? transport_dq_bytes(block) : 0;
   size_t lds =
       transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, adj ? adj->nb : 0,
-                          host_plan.hot_n);
+                          host_plan.hot_n) + qbytes;
   if (ev) {
     // room for the event stages: a smaller bin cache, at most the same LDS
     // if the cache can give it
     const size_t stages = sizeof(float) * (size_t)dev::kEvStageWords * (block / 64);
     int hot = host_plan.hot_n;
     size_t need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, 0, hot) +
-                  stages;
+                  qbytes + stages;
     while (hot > kHotMin && need > lds) {
       hot >>= 1;
-      need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, 0, hot) + stages;
+      need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, 0, hot) +
+             qbytes + stages;
     }
-    if (need + sizeof(DevPlan) > 160 * 1024) return hipErrorInvalidConfiguration;
     out.ev_hot_n = hot;
     lds = need;
   }
+  if (lds + sizeof(DevPlan) > 160 * 1024) return hipErrorInvalidConfiguration;
   const int nsc = host_plan.nscat;
   const bool two = host_plan.smax > host_plan.nscat;
   const bool phased = dev::use_phased(nsc, two, host_plan.K);
   const bool heavy = host_plan.heavy != 0;
   if (adj) {
     hipLaunchKernelGGL(dev::zero2, dim3(1), dim3(64), 0, stream, AA.sums);
-    launch_mode<dev::MODE_ADJOINT>(nsc, two, phased, heavy, grid, block, lds, stream, plan, tables, beam, seed,
-                                   first, n, per_wave, out, AA);
+    launch_mode<dev::MODE_ADJOINT>(nsc, two, phased, false, heavy, grid, block, lds, stream, plan,
+                                   tables, beam, seed, first, n, per_wave, out, AA);
   } else if (rec) {
-    launch_mode<dev::MODE_TRACE>(nsc, two, phased, heavy, grid, block, lds, stream, plan, tables, beam, seed,
-                                 first, n, per_wave, out, AA);
+    launch_mode<dev::MODE_TRACE>(nsc, two, phased, dq, heavy, grid, block, lds, stream, plan,
+                                 tables, beam, seed, first, n, per_wave, out, AA);
   } else {
-    launch_mode<dev::MODE_RUN>(nsc, two, phased, heavy, grid, block, lds, stream, plan, tables, beam, seed,
-                               first, n, per_wave, out, AA);
+    launch_mode<dev::MODE_RUN>(nsc, two, phased, dq, heavy, grid, block, lds, stream, plan,
+                               tables, beam, seed, first, n, per_wave, out, AA);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32_t n_chunks,
                         uint32_t* cursor, double* const* zero_ptrs, const uint64_t* zero_sizes,
-                        int n_zero, int grid, int block, size_t lds, int hot_n, int reset_grid,
-                        hipStream_t stream) {
+                        int n_zero, int grid, int block, size_t lds, int hot_n, int dq_off,
+                        int reset_grid, hipStream_t stream) {
   hipLaunchKernelGGL(dev::batch_reset, dim3(reset_grid), dim3(256), 0, stream, zero_ptrs,
                      zero_sizes, n_zero, cursor);
   hipLaunchKernelGGL(dev::batch_persistent, dim3(grid), dim3(block), lds, stream, items, chunks,
-                     n_chunks, cursor, hot_n);
+                     n_chunks, cursor, hot_n, dq_off);
   return hipGetLastError();
 }
 
@@ -2109,6 +2235,9 @@ template <int MODE, bool HV>
 void push_shapes(std::vector<const void*>& v) {
   v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, false, HV>));
   v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, true, HV>));
+  if (MODE != dev::MODE_ADJOINT)
+    v.push_back(reinterpret_cast<const void*>(
+        &dev::transport<MODE, 1, false, true, HV, MODE != dev::MODE_ADJOINT>));
   v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, true, false, HV>));
   v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, false, false, HV>));
   v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, true, false, HV>));
