@@ -33,8 +33,8 @@ hipError_t launch_adjoint_finalize(double* grad, const double* sums, const doubl
 hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
                             double* dLdI, double* loss, int grid, hipStream_t stream);
 size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, int hot_n);
-bool transport_uses_dq(const DevPlan& P);
-size_t transport_dq_bytes(int block);
+int transport_dq_entries(const DevPlan& P);
+size_t transport_dq_bytes(int block, int entries);
 size_t transport_static_lds();
 int transport_waves_per_eu(int nscat, int smax);
 int batch_waves_per_eu();
@@ -698,11 +698,14 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   p->tof_lo = d->tof_lo;
   p->tof_hi = d->tof_hi;
 
-  // LDS: plan + tables + bin cache + per-lane stack
-  size_t lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, kHotMin);
+  // LDS: plan + tables + bin cache + per-lane stack + detection queues
+  const int dq_n = transport_dq_entries(P);
+  size_t lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, kHotMin) +
+                   transport_dq_bytes(block, dq_n);
   while (lds_dyn + transport_static_lds() > 160 * 1024 && block > 64) {
     block -= 64;
-    lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, kHotMin);
+    lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, kHotMin) +
+              transport_dq_bytes(block, dq_n);
   }
   if (lds_dyn + transport_static_lds() > 160 * 1024) {
     delete p;
@@ -710,7 +713,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   }
   P.hot_n = hot_slots(transport_static_lds() +
                           transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, 0) +
-                          (transport_uses_dq(P) ? transport_dq_bytes(block) : 0),
+                          transport_dq_bytes(block, dq_n),
                       block, transport_waves_per_eu(P.nscat, P.smax));
   P.hot_all = mcv_detector_nbins(d) <= kHotAllBins ? 1 : 0;
   P.heavy = 0;
@@ -1222,7 +1225,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   std::vector<std::pair<double, BatchChunk>> hchunks;
   std::vector<double*> zp;
   std::vector<uint64_t> zs;
-  int n_tables_max = 0, stack_max = 0;
+  int n_tables_max = 0, stack_max = 0, dq_max = 0;
   for (int i = 0; i < n; ++i) {
     const mcv_batch_item& it = items[i];
     if (!it.plan || !it.hist) return fail(MCV_EINVAL, "batch item needs a plan and a histogram");
@@ -1239,6 +1242,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
     hitems[i].hist = it.hist;
     n_tables_max = std::max(n_tables_max, it.plan->host.n_tables);
     stack_max = std::max(stack_max, it.plan->host.stack_cap);
+    dq_max = std::max(dq_max, transport_dq_entries(it.plan->host));
     const double c = history_cost(it.plan);
     for (uint64_t f = 0; f < it.n; f += chunk) {
       BatchChunk ch;
@@ -1258,22 +1262,22 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   std::vector<BatchChunk> cl;
   for (auto& c : hchunks) cl.push_back(c.second);
   // dynamic LDS: bin cache, largest tables, largest stacks, then the waves'
-  // detection queues (phased items with tube detectors)
+  // detection queues (the largest any item uses)
   size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, kHotMin) +
-               transport_dq_bytes(block);
+               transport_dq_bytes(block, dq_max);
   while (lds + transport_static_lds() + 64 > 160 * 1024 && block > 64) {
     block -= 64;
     lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, kHotMin) +
-          transport_dq_bytes(block);
+          transport_dq_bytes(block, dq_max);
   }
   if (lds + transport_static_lds() + 64 > 160 * 1024)
     return fail(MCV_EUNSUPPORTED, "batch tables and stacks exceed LDS");
   const int hot_n = hot_slots(transport_static_lds() + 64 +
                                   transport_lds_bytes(n_tables_max, stack_max, block, 0, 0) +
-                                  transport_dq_bytes(block),
+                                  transport_dq_bytes(block, dq_max),
                               block, batch_waves_per_eu());
   const size_t lds_q = transport_lds_bytes(n_tables_max, stack_max, block, 0, hot_n);
-  lds = lds_q + transport_dq_bytes(block);
+  lds = lds_q + transport_dq_bytes(block, dq_max);
 
   auto* b = new (std::nothrow) mcv_batch_s();
   if (!b) return fail(MCV_ENOMEM, "host allocation failed");

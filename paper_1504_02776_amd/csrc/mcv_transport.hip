@@ -1537,15 +1537,18 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
 // powder) need the rest of it (candidate tubes, absorption, a Philox block,
 // bin).  Run in the D phase, that rest would take the whole wave for the few
 // lanes holding such packets; instead they are appended to a per-wave LDS
-// queue of kDqEntries packets, which the wave records together (one packet
-// per lane) when the next D phase would overflow it, and at the end.
-// Layout: [field][entry], 12 fields (position, direction, speed, time,
-// weight, lineage, history id low and high words).
-constexpr int kDqEntries = 64;
+// queue of Q packets, which the wave records together (one packet per lane)
+// when the next D phase would overflow it, and at the end.  The walk loop
+// does the same with its recording step (Q = 32 there, beside the packet
+// stacks).  Layout: [field][entry], 12 fields (position, direction, speed,
+// time, weight, lineage, history id low and high words).
 constexpr int kDqFields = 12;
-constexpr int kDqWords = kDqEntries * kDqFields;
+constexpr int kDqPhased = 64;  // entries per wave, phased loop
+constexpr int kDqWalk = 32;    // entries per wave, walk loop
 
+template <int Q>
 __device__ __forceinline__ void dq_put(float* q, int slot, const Pk& P, uint64_t hid) {
+  constexpr int kDqEntries = Q;
   float* b = q + slot;
   b[0 * kDqEntries] = P.px;
   b[1 * kDqEntries] = P.py;
@@ -1563,10 +1566,11 @@ __device__ __forceinline__ void dq_put(float* q, int slot, const Pk& P, uint64_t
 
 // records the n queued packets, one per lane (called with the whole wave
 // active; a wave of fewer lanes takes several passes)
-template <int MODE>
+template <int MODE, int Q>
 __device__ __forceinline__ void dq_run(const DevPlan& PL, const float* tab, const Sinks& out,
                                        const AdjArgs& AA, double* acc, int hot_n, const float* q,
                                        int n, uint64_t seed) {
+  constexpr int kDqEntries = Q;
   const int nl = __popcll(__ballot(1));
   for (int base = 0; base < n; base += nl) {
     const int i = base + (int)__lane_id();
@@ -1620,7 +1624,7 @@ __device__ __forceinline__ void dq_run(const DevPlan& PL, const float* tab, cons
 //      attenuation only and waits for the next D phase.
 // Called with the whole wave active.  `acc` is the workgroup's LDS block:
 // adjoint partials (MODE_ADJOINT) or the histogram bin cache (otherwise).
-template <int MODE, int NSC, bool TWO, bool HEAVY, bool DQ>
+template <int MODE, int NSC, bool TWO, bool HEAVY, int DQ>
 __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab, float* st,
                                              const DevBeam& beam, uint64_t seed, uint64_t first,
                                              uint64_t begin, uint64_t end, const Sinks& out,
@@ -1628,6 +1632,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
                                              int nthreads, int tid, float* dq) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
   static_assert(!(DQ && ADJ), "the adjoint records its packets at once");
+  static_assert(DQ == 0 || DQ == kDqPhased, "phased-loop queue size");
   const uint64_t lt = lanemask_lt();
   Pk cur;
   cur.lin = 0u;
@@ -1649,7 +1654,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
     const uint64_t mI = __ballot(state == LANE_FLY);
     const uint64_t mD = __ballot(state == LANE_NEED || state == LANE_DET);
     if ((mI | mD) == 0ull) {
-      if (DQ && qn > 0) dq_run<MODE>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
+      if (DQ && qn > 0) dq_run<MODE, DQ>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
       break;
     }
     if (__popcll(mI) >= __popcll(mD)) {
@@ -1665,18 +1670,18 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
     }
     int hbin = -1;
     float hval = 0.0f;
-    if constexpr (DQ) {
+    if constexpr (DQ > 0) {
       float a;
       uint32_t rows;
       int col;
       const bool q = state == LANE_DET && tube_column(PL.det, cur, a, rows, col);
       const uint64_t mq = __ballot(q);
       const int k = __popcll(mq);
-      if (qn + k > kDqEntries) {
-        dq_run<MODE>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
+      if (qn + k > DQ) {
+        dq_run<MODE, DQ>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
         qn = 0;
       }
-      if (q) dq_put(dq, qn + __popcll(mq & lt), cur, hid);
+      if (q) dq_put<DQ>(dq, qn + __popcll(mq & lt), cur, hid);
       qn += k;
       // a packet that meets no tube leaves no histogram entry; trace mode
       // still writes its record
@@ -1732,13 +1737,15 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
   }
 }
 
-template <int MODE, int NSC, bool TWO, bool HEAVY>
+template <int MODE, int NSC, bool TWO, bool HEAVY, int DQ>
 __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, float* st,
                                            const DevBeam& beam, uint64_t seed, uint64_t first,
                                            uint64_t begin, uint64_t end, const Sinks& out,
                                            const AdjArgs& AA, double* acc, int hot_n,
-                                           int nthreads, int tid) {
+                                           int nthreads, int tid, float* dq) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
+  static_assert(!(DQ && ADJ), "the adjoint records its packets at once");
+  static_assert(DQ == 0 || DQ == kDqWalk, "walk-loop queue size");
   constexpr bool DEFER = NSC > 1 || TWO || HEAVY;
   const uint64_t lt = lanemask_lt();
   Pk cur;
@@ -1749,6 +1756,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
   uint64_t hid = 0;
   int nst = 0;
   uint64_t next = begin;
+  int qn = 0;  // packets in the detection queue (the same in every lane)
   while (true) {
     if (!has && nst > 0) {
       --nst;
@@ -1768,7 +1776,10 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
       }
     }
     next += (uint64_t)__popcll(m);
-    if (__ballot(has) == 0ull) break;
+    if (__ballot(has) == 0ull) {
+      if (DQ && qn > 0) dq_run<MODE, DQ>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
+      break;
+    }
     if (DEFER && has && code >= 0) {
       eval_deferred<ADJ, HEAVY>(PL, tab, AA, cur, ca, code, hid, seed);
       code = -1;
@@ -1776,19 +1787,37 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
     }
     int hbin = -1;
     float hval = 0.0f;
+    Pk nxt;
+    nxt.lin = 0u;
+    Adj na = ca;
+    int nxt_code = -1;
+    bool has_nxt = false;
     if (has) {
-      Pk nxt;
-      nxt.lin = 0u;
-      Adj na = ca;
-      int nxt_code = -1;
-      bool has_nxt = false;
       Flight<NSC, TWO> F;
       flight_setup(PL, cur, F);
       while (F.valid != 0u)
         flight_step<ADJ, true, DEFER, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na,
                                                       nxt_code, has_nxt, st, nst, nthreads, tid);
       flight_exit(cur, F);
-      record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
+      if (!DQ) record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
+    }
+    if constexpr (DQ > 0) {
+      float a;
+      uint32_t rows;
+      int col;
+      const bool q = has && tube_column(PL.det, cur, a, rows, col);
+      const uint64_t mq = __ballot(q);
+      const int k = __popcll(mq);
+      if (qn + k > DQ) {
+        dq_run<MODE, DQ>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
+        qn = 0;
+      }
+      if (q) dq_put<DQ>(dq, qn + __popcll(mq & lt), cur, hid);
+      qn += k;
+      if (MODE == MODE_TRACE && has && !q)
+        record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
+    }
+    if (has) {
       if (has_nxt) {
         cur = nxt;
         code = nxt_code;
@@ -1797,7 +1826,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
         has = false;
       }
     }
-    if (!ADJ && (out.hist != nullptr || out.hist_w2 != nullptr))
+    if (!ADJ && !DQ && (out.hist != nullptr || out.hist_w2 != nullptr))
       hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
   }
 }
@@ -1810,19 +1839,18 @@ __host__ __device__ constexpr bool use_phased(int nscat, bool two, int K) {
   return nscat <= 1 && !two && K >= 2;
 }
 
-template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, bool DQ = false>
+template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, int DQ = 0>
 __device__ __forceinline__ void trace_range(const DevPlan& PL, const float* tab, float* st,
                                             const DevBeam& beam, uint64_t seed, uint64_t first,
                                             uint64_t begin, uint64_t end, const Sinks& out,
                                             const AdjArgs& AA, double* acc, int hot_n,
                                             int nthreads, int tid, float* dq = nullptr) {
-  static_assert(PHASED || !DQ, "the detection queue belongs to the phased loop");
   if constexpr (PHASED)
     trace_phased<MODE, NSC, TWO, HEAVY, DQ>(PL, tab, st, beam, seed, first, begin, end, out, AA,
                                             acc, hot_n, nthreads, tid, dq);
   else
-    trace_walk<MODE, NSC, TWO, HEAVY>(PL, tab, st, beam, seed, first, begin, end, out, AA, acc, hot_n,
-                               nthreads, tid);
+    trace_walk<MODE, NSC, TWO, HEAVY, DQ>(PL, tab, st, beam, seed, first, begin, end, out, AA, acc,
+                                          hot_n, nthreads, tid, dq);
 }
 
 // copies a plan and its tables into LDS (whole workgroup)
@@ -1840,7 +1868,7 @@ __device__ __forceinline__ void stage_plan(DevPlan& PL, float* dyn, const DevPla
 // numbers) and accumulates dL/dtheta = sum over recorded packets of
 // dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
 // per workgroup.
-template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, bool DQ = false>
+template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, int DQ = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
     NSC == 1 && !TWO ? MCV_WAVES_PER_EU_SIMPLE : MCV_WAVES_PER_EU)))
 transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
@@ -1870,8 +1898,8 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   // after the packet stacks: the waves' detection queues, then their event
   // stages
   float* dqs = st + (size_t)PL.stack_cap * kFields * nthreads;
-  float* dq = dqs + (tid >> 6) * kDqWords;
-  float* evs = DQ ? dqs + (nthreads >> 6) * kDqWords : dqs;
+  float* dq = dqs + (tid >> 6) * DQ * kDqFields;
+  float* evs = dqs + (nthreads >> 6) * DQ * kDqFields;
   if (events) {
     float* sw = evs + (tid >> 6) * kEvStageWords;
     o.stage = reinterpret_cast<DevEvent*>(sw);
@@ -1945,20 +1973,26 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     Sinks out = {it.hist, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr};
     const uint64_t ee = b + per < e ? b + per : e;
     // the waves' detection queues sit behind the largest tables and stacks
-    float* dq = dyn + dq_off + wid * kDqWords;
+    float* dq = dyn + dq_off;  // this wave's queue: dq + wid Q kDqFields
     // the same specialisation as a plain launch of this plan, so that both
     // evaluate identical arithmetic
     const bool two = PL.smax > PL.nscat;
-#define MCV_BATCH_TRACE(NSC_, TWO_, PH_, HV_)                                          \
-  trace_range<MODE_RUN, NSC_, TWO_, PH_, HV_>(PL, tab, st, it.beam, it.seed, it.id0, b, ee, \
-                                              out, AA, hot, hot_n, nthreads, tid)
+#define MCV_BATCH_TRACE(NSC_, TWO_, PH_, HV_)                                            \
+  do {                                                                                     \
+    constexpr int Q_ = PH_ ? kDqPhased : kDqWalk;                                          \
+    if (PL.det.type == DET_TUBES)                                                          \
+      trace_range<MODE_RUN, NSC_, TWO_, PH_, HV_, Q_>(PL, tab, st, it.beam, it.seed,       \
+                                                      it.id0, b, ee, out, AA, hot, hot_n,  \
+                                                      nthreads, tid,                       \
+                                                      dq + wid * Q_ * kDqFields);          \
+    else                                                                                   \
+      trace_range<MODE_RUN, NSC_, TWO_, PH_, HV_>(PL, tab, st, it.beam, it.seed, it.id0,   \
+                                                  b, ee, out, AA, hot, hot_n, nthreads,    \
+                                                  tid);                                    \
+  } while (0)
 #define MCV_BATCH_SHAPES(HV_)                                                       \
   if (PL.nscat <= 1) {                                                              \
     if (two) MCV_BATCH_TRACE(1, true, false, HV_);                                  \
-    else if (use_phased(PL.nscat, two, PL.K) && PL.det.type == DET_TUBES)          \
-      trace_range<MODE_RUN, 1, false, true, HV_, true>(PL, tab, st, it.beam, it.seed,  \
-                                                       it.id0, b, ee, out, AA, hot,    \
-                                                       hot_n, nthreads, tid, dq);      \
     else if (use_phased(PL.nscat, two, PL.K)) MCV_BATCH_TRACE(1, false, true, HV_); \
     else MCV_BATCH_TRACE(1, false, false, HV_);                                     \
   } else if (PL.nscat == 2) {                                                       \
@@ -2075,11 +2109,12 @@ __global__ void __launch_bounds__(256) loss_grad(const double* __restrict__ I,
 // ------------------------------------------------------------------ launch
 // LDS of the waves' detection queues, for plans that use them: phased loop
 // (one convex scatterer, K >= 2) and a tube detector, outside the adjoint
-bool transport_uses_dq(const DevPlan& P) {
-  return dev::use_phased(P.nscat, P.smax > P.nscat, P.K) && P.det.type == DET_TUBES;
+int transport_dq_entries(const DevPlan& P) {
+  if (P.det.type != DET_TUBES) return 0;
+  return dev::use_phased(P.nscat, P.smax > P.nscat, P.K) ? dev::kDqPhased : dev::kDqWalk;
 }
-size_t transport_dq_bytes(int block) {
-  return sizeof(float) * (size_t)dev::kDqWords * (size_t)(block / 64);
+size_t transport_dq_bytes(int block, int entries) {
+  return sizeof(float) * (size_t)entries * dev::kDqFields * (size_t)(block / 64);
 }
 
 size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, int hot_n) {
@@ -2092,7 +2127,7 @@ size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, i
 
 namespace {
 
-template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, bool DQ = false>
+template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, int DQ = 0>
 void launch_one(int grid, int block, size_t lds, hipStream_t stream, const DevPlan* plan,
                 const float* tables, const DevBeam& beam, uint64_t seed, uint64_t first,
                 uint64_t n, uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
@@ -2106,14 +2141,19 @@ void launch_shapes(int nsc, bool two, bool phased, bool dq, int grid, int block,
                    hipStream_t stream, const DevPlan* plan, const float* tables,
                    const DevBeam& beam, uint64_t seed, uint64_t first, uint64_t n,
                    uint64_t per_wave, const dev::Sinks& out, const AdjArgs& AA) {
-#define MCV_LAUNCH(NSC_, TWO_, PH_)                                                          \
-  launch_one<MODE, NSC_, TWO_, PH_, HEAVY>(grid, block, lds, stream, plan, tables, beam, seed, \
-                                           first, n, per_wave, out, AA)
+  // with a detection queue (dq: run and trace modes, tube detectors) or without
+#define MCV_LAUNCH(NSC_, TWO_, PH_)                                                            \
+  do {                                                                                         \
+    if (dq)                                                                                    \
+      launch_one<MODE, NSC_, TWO_, PH_, HEAVY,                                                 \
+                 MODE == dev::MODE_ADJOINT ? 0 : (PH_ ? dev::kDqPhased : dev::kDqWalk)>(       \
+          grid, block, lds, stream, plan, tables, beam, seed, first, n, per_wave, out, AA);    \
+    else                                                                                       \
+      launch_one<MODE, NSC_, TWO_, PH_, HEAVY>(grid, block, lds, stream, plan, tables, beam,   \
+                                               seed, first, n, per_wave, out, AA);             \
+  } while (0)
   if (nsc <= 1) {
     if (two) MCV_LAUNCH(1, true, false);
-    else if (phased && dq && MODE != dev::MODE_ADJOINT)
-      launch_one<MODE, 1, false, true, HEAVY, MODE != dev::MODE_ADJOINT>(
-          grid, block, lds, stream, plan, tables, beam, seed, first, n, per_wave, out, AA);
     else if (phased) MCV_LAUNCH(1, false, true);
     else MCV_LAUNCH(1, false, false);
   } else if (nsc == 2) {
@@ -2151,8 +2191,9 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
   AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = -1;
   if (adj) AA = *adj;
   dev::Sinks out = {hist, hist_w2, rec, cap, n_out, ev, ev_cap, n_ev, 0, nullptr, nullptr};
-  const bool dq = !adj && transport_uses_dq(host_plan);
-  const size_t qbytes = dq ? transport_dq_bytes(block) : 0;
+  const int dq_n = adj ? 0 : transport_dq_entries(host_plan);
+  const bool dq = dq_n > 0;
+  const size_t qbytes = transport_dq_bytes(block, dq_n);
   size_t lds =
       transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, adj ? adj->nb : 0,
                           host_plan.hot_n) + qbytes;
@@ -2231,18 +2272,22 @@ int transport_waves_per_eu(int nscat, int smax) {
 int batch_waves_per_eu() { return MCV_WAVES_PER_EU; }
 
 namespace {
+template <int MODE, bool HV, int QP, int QW>
+void push_shapes_q(std::vector<const void*>& v) {
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, false, HV, QW>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, true, HV, QP>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, true, false, HV, QW>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, false, false, HV, QW>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, true, false, HV, QW>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, false, false, HV, QW>));
+  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, true, false, HV, QW>));
+}
 template <int MODE, bool HV>
 void push_shapes(std::vector<const void*>& v) {
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, false, HV>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, false, true, HV>));
+  push_shapes_q<MODE, HV, 0, 0>(v);
   if (MODE != dev::MODE_ADJOINT)
-    v.push_back(reinterpret_cast<const void*>(
-        &dev::transport<MODE, 1, false, true, HV, MODE != dev::MODE_ADJOINT>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 1, true, false, HV>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, false, false, HV>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 2, true, false, HV>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, false, false, HV>));
-  v.push_back(reinterpret_cast<const void*>(&dev::transport<MODE, 4, true, false, HV>));
+    push_shapes_q<MODE, HV, MODE != dev::MODE_ADJOINT ? dev::kDqPhased : 0,
+                  MODE != dev::MODE_ADJOINT ? dev::kDqWalk : 0>(v);
 }
 template <int MODE>
 void push_mode(std::vector<const void*>& v) {
