@@ -91,7 +91,14 @@ def work_per_history(costs, tally, n, cfg):
     w += tally.n_segments * mean(c["segment"])
     w += tally.n_splits * mean(c["split"])
     w += sum(tally.n_kernel[t] * mean(by_type[t]) for t in by_type)
-    w += tally.n_detect * (c["detect"] - c["detect_draws_per_call"] * c["rng_block"])
+    if "detect_hit" in c:
+        # tube detectors: the first steps for every escaping packet, the rest
+        # (without its Philox block, counted above) for those that hit a tube
+        n_hit = tally.n_detect - tally.n_missed
+        w += tally.n_detect * c["detect_col"]
+        w += n_hit * (c["detect_hit"] - c["detect_col"] - c["detect_hit_draws"] * c["rng_block"])
+    else:
+        w += tally.n_detect * (c["detect"] - c["detect_draws_per_call"] * c["rng_block"])
     return w / n
 
 

@@ -32,7 +32,9 @@ enum {
   PR_SEGMENT = 4,
   PR_SPLIT = 5,
   PR_KERNEL = 6,
-  PR_DETECT = 7
+  PR_DETECT = 7,
+  PR_DETECT_COL = 8,  // tube detectors: the first steps only (tube_column)
+  PR_DETECT_HIT = 9   // tube detectors: the whole test on rays aimed at a tube
 };
 
 // 32-bit integer mix (the "lowbias32" constants of C. Wellons' hash search)
@@ -138,6 +140,29 @@ probe_kernel(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, 
                          : detect_tubes(PL.det, dyn, P, (uint64_t)gid * iters + it, seed);
       acc += hh.value + hh.tof + (float)hh.bin;
       if (PL.det.type != DET_SPHERE && hh.tube >= 0) ++nh;
+    } else if (PR == PR_DETECT_COL) {
+      float a;
+      uint32_t rows;
+      int col;
+      const bool pass = tube_column(PL.det, P, a, rows, col);
+      acc += a + (float)rows + (float)col;
+      nh += pass ? 1u : 0u;
+    } else if (PR == PR_DETECT_HIT) {
+      // every lane's ray aimed at a point on the axis of a random tube, so
+      // that the whole wave runs the candidate tests and the absorption
+      const DevDet& D = PL.det;
+      const int cc = min((int)(u[0] * (float)D.ncols), D.ncols - 1);
+      const int rr = min((int)(u[1] * (float)D.nrows), D.nrows - 1);
+      const float ex = dyn[D.t_cols + 2 * cc] - P.px;
+      const float ey = D.row_y[rr] + 1.8f * (u[2] - 0.5f) * D.half_len - P.py;
+      const float ez = dyn[D.t_cols + 2 * cc + 1] - P.pz;
+      const float inv = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
+      P.dx = ex * inv;
+      P.dy = ey * inv;
+      P.dz = ez * inv;
+      const Hit hh = detect_tubes(D, dyn, P, (uint64_t)gid * iters + it, seed);
+      acc += hh.value + hh.tof + (float)hh.bin;
+      if (hh.tube >= 0) ++nh;
     }
   }
   sink[gid] = acc;
@@ -161,7 +186,9 @@ extern "C" {
 // Runs probe `kind` (PR_*) with argument `arg` (scatterer index; for
 // kernels scatterer * 4 + kernel) on `grid` workgroups of 256 lanes,
 // `iters` calls per lane, `reps` timed repetitions after one warm-up.
-// Writes the best time in ms and the number of detector draws per call.
+// Writes the best time in ms and, for the detector probes, the fraction of
+// calls that hit a tube (PR_DETECT, PR_DETECT_HIT: one Philox block each) or
+// pass tube_column (PR_DETECT_COL).
 // Returns MCV_OK or an error status (bad kind, argument or launch).
 mcv_status mcv_probe_time(mcv_plan p, const mcv_beam* beam, uint64_t seed, int32_t kind,
                           int32_t arg, uint32_t iters, int32_t grid, int32_t reps,
@@ -175,7 +202,9 @@ mcv_status mcv_probe_time(mcv_plan p, const mcv_beam* beam, uint64_t seed, int32
   if (kind == PR_KERNEL &&
       (arg < 0 || (arg >> 2) >= p->host.nscat || (arg & 3) >= p->host.s[arg >> 2].nk))
     return fail(MCV_EINVAL, "kernel index out of range");
-  if (kind < PR_NULL || kind > PR_DETECT) return fail(MCV_EINVAL, "unknown probe");
+  if (kind < PR_NULL || kind > PR_DETECT_HIT) return fail(MCV_EINVAL, "unknown probe");
+  if ((kind == PR_DETECT_COL || kind == PR_DETECT_HIT) && p->host.det.type != DET_TUBES)
+    return fail(MCV_EINVAL, "tube-detector probe on a plan without tubes");
   DevBeam B;
   mcv_status st = make_beam(p, beam, &B);
   if (st != MCV_OK) return st;
@@ -210,6 +239,8 @@ mcv_status mcv_probe_time(mcv_plan p, const mcv_beam* beam, uint64_t seed, int32
       MCV_PROBE_CASE(PR_SPLIT)
       MCV_PROBE_CASE(PR_KERNEL)
       MCV_PROBE_CASE(PR_DETECT)
+      MCV_PROBE_CASE(PR_DETECT_COL)
+      MCV_PROBE_CASE(PR_DETECT_HIT)
 #undef MCV_PROBE_CASE
     }
     (void)hipEventRecord(b, nullptr);

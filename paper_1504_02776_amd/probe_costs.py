@@ -5,8 +5,11 @@ cost = (t_probe - t_null) * VALU issue rate / calls, where the VALU issue
 rate is 256 CUs x 64 lanes x 2.4 GHz (one binary32 lane operation per lane
 per clock) and t_null is the same probe loop without the primitive.  A
 detector probe's own Philox draws are reported beside it so that they are
-not counted twice.  Writes a JSON file (default: primitive_costs.json next
-to this module).
+not counted twice.  For tube detectors the test is also timed in the two
+parts the transport kernels run separately: its first steps (every packet)
+and the whole test on rays aimed at a tube (the packets that reach the
+tubes, recorded together one per lane).  Writes a JSON file (default:
+primitive_costs.json next to this module).
 
     python -m paper_1504_02776_amd.probe_costs [--out FILE]
 """
@@ -29,7 +32,8 @@ GRID = 2048          # workgroups of 256 lanes: 8 per CU
 ITERS = 2048         # calls per lane
 REPS = 3
 
-PR_NULL, PR_RNG, PR_SOURCE, PR_SHAPE, PR_SEGMENT, PR_SPLIT, PR_KERNEL, PR_DETECT = range(8)
+(PR_NULL, PR_RNG, PR_SOURCE, PR_SHAPE, PR_SEGMENT, PR_SPLIT, PR_KERNEL, PR_DETECT,
+ PR_DETECT_COL, PR_DETECT_HIT) = range(10)
 from paper_1504_02776_amd.mcv import KERNELS as KERNEL_TYPES  # noqa: E402
 
 
@@ -79,6 +83,16 @@ def probe_workload(cfg):
     c, d = cost(PR_DETECT)
     out["detect"] = c
     out["detect_draws_per_call"] = d
+    if cfg["detector"]["type"] == "tubes":
+        # the same test split the way the transport kernels run it: its first
+        # steps for every packet, the rest (a queue of packets that reach
+        # the tubes, one per lane) on rays that all hit a tube
+        c, d = cost(PR_DETECT_COL)
+        out["detect_col"] = c
+        out["detect_col_pass"] = d
+        c, d = cost(PR_DETECT_HIT)
+        out["detect_hit"] = c
+        out["detect_hit_draws"] = d
     plan.close() if hasattr(plan, "close") else None
     return out
 
