@@ -167,7 +167,7 @@ def bench_batched(torch, mcv, W, stream, reps):
 
     def sequential():
         for p, h in zip(plans, hists):
-            h.zero_()
+            mcv.zero(h, stream=stream)
             p.run(h, stream=stream)
     t_seq = timed(torch, stream, sequential, reps)
     b.close()
@@ -197,7 +197,7 @@ def bench_scan(torch, mcv, W, stream, reps):
 
     def sequential():
         for p, h in zip(plans, hists):
-            h.zero_()
+            mcv.zero(h, stream=stream)
             p.run(h, stream=stream)
     t_seq = timed(torch, stream, sequential, reps)
     b.close()
@@ -227,7 +227,7 @@ def bench_adjoint(torch, mcv, W, stream, reps, forward_ms):
     grad = torch.zeros(plan.nparams(pm), dtype=torch.float64, device=I.device)
 
     def step():
-        I.zero_()
+        mcv.zero(I, stream=stream)
         loss.zero_()
         grad.zero_()
         plan.run(I, stream=stream)
@@ -258,7 +258,7 @@ def bench_single(torch, mcv, cfg, stream, reps, costs_name=None, cpu_budget_s=4.
     ev = []
 
     def step():
-        h.zero_()
+        mcv.zero(h, stream=stream)
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -295,7 +295,7 @@ def bench_events_and_reduction(torch, mcv, W, stream, reps):
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda:0")
 
     def run_plain():
-        hist.zero_()
+        mcv.zero(hist, stream=stream)
         plan.run(hist, stream=stream)
 
     def run_events():
@@ -376,7 +376,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
-        hist.zero_()
+        mcv.zero(hist, stream=stream)
         plan.run(hist, n=N, stream=stream)
     torch.cuda.synchronize()
     # per-launch events on the stream the kernel runs on
@@ -388,7 +388,7 @@ def main():
     wall0 = time.perf_counter()
     t_begin.record(stream)
     for k in range(args.steps):
-        hist.zero_()
+        mcv.zero(hist, stream=stream)
         ev[k][0].record(stream)
         plan.run(hist, n=N, stream=stream)
         ev[k][1].record(stream)

@@ -388,6 +388,14 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
                        uint64_t first, uint64_t n, const double* dL_dI, double* grad,
                        void* stream);
 
+/* Sets n binary64 values of device memory to zero: the histogram that an
+ * accumulation of recorded probabilities starts from (Sec. 3, the detector
+ * result is the sum of the recorded packets' probabilities; mcv_run adds).
+ * A fill kernel, not a memset, so that it may be captured in a HIP graph.
+ * p: device, 8-byte aligned (any n >= 0).  Asynchronous on `stream`.
+ * Errors: MCV_EINVAL (n < 0, NULL p with n > 0, misaligned p), MCV_EHIP. */
+mcv_status mcv_zero(double* p, int64_t n, void* stream);
+
 /* Weighted L2 loss of a histogram against a target (streaming): *loss +=
  * sum_b w_b (I_b - T_b)^2 and dL_dI_b = 2 w_b (I_b - T_b).  Device binary64
  * arrays of n entries, 16-byte aligned; *loss is accumulated into. */

@@ -32,6 +32,7 @@ hipError_t launch_adjoint_finalize(double* grad, const double* sums, const doubl
                                    double dnorm, int nb, hipStream_t stream);
 hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
                             double* dLdI, double* loss, int grid, hipStream_t stream);
+hipError_t launch_fill_zero(double* p, uint64_t n, int grid, hipStream_t stream);
 size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, int hot_n);
 int transport_dq_entries(const DevPlan& P);
 size_t transport_dq_bytes(int block, int entries);
@@ -1153,6 +1154,19 @@ mcv_status mcv_loss_grad(const double* I, const double* T, const double* w, int6
   if (grid < 1) grid = 1;
   hipError_t e = launch_loss_grad(I, T, w, n, dL_dI, loss, (int)grid, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(e, "loss launch");
+  return MCV_OK;
+}
+
+mcv_status mcv_zero(double* p, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && !p)) return fail(MCV_EINVAL, "bad zero arguments");
+  if ((uintptr_t)p & 7u) return fail(MCV_EINVAL, "array must be 8-byte aligned");
+  if (n == 0) return MCV_OK;
+  // one 16-byte store per lane (larger arrays loop)
+  int64_t grid = (n / 2 + 255) / 256;
+  if (grid > ((int64_t)1 << 30)) grid = (int64_t)1 << 30;
+  if (grid < 1) grid = 1;
+  hipError_t e = launch_fill_zero(p, (uint64_t)n, (int)grid, (hipStream_t)stream);
+  if (e != hipSuccess) return hipfail(e, "zero launch");
   return MCV_OK;
 }
 

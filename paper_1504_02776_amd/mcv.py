@@ -116,7 +116,7 @@ EXPORTS = ["mcv_assembly_create", "mcv_assembly_add", "mcv_assembly_destroy",
            "mcv_run", "mcv_trace", "mcv_sync", "mcv_last_error", "mcv_abi_version",
            "mcv_adjoint_nparams", "mcv_adjoint", "mcv_loss_grad", "mcv_batch_create",
            "mcv_batch_run", "mcv_batch_destroy", "mcv_autotune", "mcv_run_events",
-           "mcv_reduce_qe", "mcv_reduce_events_qe"]
+           "mcv_reduce_qe", "mcv_reduce_events_qe", "mcv_zero"]
 
 _lib = None
 
@@ -150,6 +150,7 @@ def lib():
             "mcv_adjoint": [P, C.POINTER(mcv_param_map), C.POINTER(mcv_beam), C.c_uint64,
                             C.c_uint64, C.c_uint64, P, P, P],
             "mcv_loss_grad": [P, P, P, C.c_int64, P, P, P],
+            "mcv_zero": [P, C.c_int64, P],
             "mcv_run_events": [P, C.POINTER(mcv_beam), C.c_uint64, C.c_uint64, C.c_uint64, P,
                                P, P, C.c_uint64, P, P],
             "mcv_reduce_qe": [P, C.POINTER(mcv_qe_grid), P, P, P, P, P],
@@ -459,6 +460,15 @@ def events_to_numpy(events, count):
 
 def sync(stream=None):
     check(lib().mcv_sync(_stream_ptr(stream)))
+
+
+def zero(t, stream=None):
+    """Zeroes a float64 device tensor (contiguous) with the library's fill
+    kernel (capture-safe, unlike a memset)."""
+    import torch
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("zero needs a contiguous float64 tensor")
+    check(lib().mcv_zero(C.c_void_p(t.data_ptr()), t.numel(), _stream_ptr(stream)))
 
 
 def loss_grad(I, T, w, dLdI, loss, stream=None):

@@ -41,6 +41,24 @@ def test_loss_grad_kernel(torch_cuda):
     assert float(loss.item()) == pytest.approx(float(np.sum(w * (I - T) ** 2)), rel=1e-12)
 
 
+def test_zero_kernel(torch_cuda):
+    """mcv_zero: every element of the range, 16-byte aligned or not, odd or
+    even length, and nothing outside it."""
+    from paper_1504_02776_amd import mcv
+    torch = torch_cuda
+    buf = torch.full((1_000_011,), 7.0, dtype=torch.float64, device="cuda")
+    for off, n in [(0, 1_000_000), (1, 999_999), (1, 1_000_008), (2, 1), (3, 0), (0, 2)]:
+        buf.fill_(7.0)
+        print(f"[zero] offset={off} n={n}", flush=True)
+        mcv.zero(buf[off:off + n])
+        torch.cuda.synchronize()
+        b = buf.cpu().numpy()
+        assert (b[off:off + n] == 0.0).all()
+        assert (b[:off] == 7.0).all() and (b[off + n:] == 7.0).all()
+    with pytest.raises(mcv.MCVError):
+        mcv.check(mcv.lib().mcv_zero(None, 5, None))
+
+
 def _check_adjoint(torch, oracle_lib, make, PMx, N):
     from paper_1504_02776_amd import mcv
     cfg = make()
