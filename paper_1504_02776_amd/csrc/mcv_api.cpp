@@ -1177,7 +1177,7 @@ namespace mcv {
 hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32_t n_chunks,
                         uint32_t* cursor, double* const* zero_ptrs, const uint64_t* zero_sizes,
                         int n_zero, int grid, int block, size_t lds, int hot_n, int dq_off,
-                        int reset_grid, hipStream_t stream);
+                        hipStream_t stream);
 int batch_occupancy(int block, size_t lds);
 }  // namespace mcv
 
@@ -1186,8 +1186,6 @@ struct mcv_batch_s {
   BatchItem* d_items = nullptr;
   BatchChunk* d_chunks = nullptr;
   uint32_t* d_cursor = nullptr;
-  double** d_zero_ptrs = nullptr;
-  uint64_t* d_zero_sizes = nullptr;
   uint32_t n_chunks = 0;
   int n_zero = 0;
   int grid = 0, block = 0;
@@ -1209,8 +1207,6 @@ void batch_free(mcv_batch_s* b) {
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_chunks) (void)hipFree(b->d_chunks);
   if (b->d_cursor) (void)hipFree(b->d_cursor);
-  if (b->d_zero_ptrs) (void)hipFree(b->d_zero_ptrs);
-  if (b->d_zero_sizes) (void)hipFree(b->d_zero_sizes);
   delete b;
 }
 
@@ -1321,8 +1317,6 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   up((void**)&b->d_chunks, cl.data(), cl.size() * sizeof(BatchChunk));
   uint32_t zero = 0;
   up((void**)&b->d_cursor, &zero, sizeof(uint32_t));
-  up((void**)&b->d_zero_ptrs, zp.data(), zp.size() * sizeof(double*));
-  up((void**)&b->d_zero_sizes, zs.data(), zs.size() * sizeof(uint64_t));
   if (e != hipSuccess) {
     batch_free(b);
     (void)hipSetDevice(cur);
@@ -1331,9 +1325,9 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   // capture reset + persistent kernel once; runs replay the graph
   if ((e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking)) == hipSuccess &&
       (e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
-    hipError_t el = launch_batch(b->d_items, b->d_chunks, b->n_chunks, b->d_cursor,
-                                 b->d_zero_ptrs, b->d_zero_sizes, b->n_zero, b->grid, b->block,
-                                 b->lds, b->hot_n, b->dq_off, cus * 4, b->capture);
+    hipError_t el = launch_batch(b->d_items, b->d_chunks, b->n_chunks, b->d_cursor, zp.data(),
+                                 zs.data(), b->n_zero, b->grid, b->block, b->lds, b->hot_n,
+                                 b->dq_off, b->capture);
     e = hipStreamEndCapture(b->capture, &b->graph);
     if (e == hipSuccess) e = el;
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);

@@ -2018,18 +2018,8 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
 
 // zeroes a list of FP64 arrays and the chunk cursor (graph-capturable; no
 // memset nodes)
-__global__ void batch_reset(double* const* __restrict__ ptrs, const uint64_t* __restrict__ sizes,
-                            int n, uint32_t* __restrict__ cursor) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *cursor = 0u;
-  for (int k = 0; k < n; ++k) {
-    double* p = ptrs[k];
-    const uint64_t m = sizes[k];
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 2;
-    for (uint64_t i = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; i < m; i += stride) {
-      if (i + 1 < m) *reinterpret_cast<double2*>(p + i) = make_double2(0.0, 0.0);
-      else p[i] = 0.0;
-    }
-  }
+__global__ void batch_cursor_reset(uint32_t* cursor) {
+  if (threadIdx.x == 0) *cursor = 0u;
 }
 
 // grad[j] += dense_a[j] * sum(g A) + dnorm * sum(g n_phonon): the terms of
@@ -2249,12 +2239,21 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
   return hipGetLastError();
 }
 
+// zero_ptrs, zero_sizes: host arrays (device pointers and lengths of the
+// histograms to zero); the fills and the cursor reset are kernels, so the
+// whole sequence can be captured in a graph without memset nodes
 hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32_t n_chunks,
                         uint32_t* cursor, double* const* zero_ptrs, const uint64_t* zero_sizes,
                         int n_zero, int grid, int block, size_t lds, int hot_n, int dq_off,
-                        int reset_grid, hipStream_t stream) {
-  hipLaunchKernelGGL(dev::batch_reset, dim3(reset_grid), dim3(256), 0, stream, zero_ptrs,
-                     zero_sizes, n_zero, cursor);
+                        hipStream_t stream) {
+  hipLaunchKernelGGL(dev::batch_cursor_reset, dim3(1), dim3(64), 0, stream, cursor);
+  for (int k = 0; k < n_zero; ++k) {
+    uint64_t g = (zero_sizes[k] / 2 + 255) / 256;
+    if (g > ((uint64_t)1 << 30)) g = (uint64_t)1 << 30;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(dev::fill_zero, dim3((unsigned)g), dim3(256), 0, stream, zero_ptrs[k],
+                       zero_sizes[k]);
+  }
   hipLaunchKernelGGL(dev::batch_persistent, dim3(grid), dim3(block), lds, stream, items, chunks,
                      n_chunks, cursor, hot_n, dq_off);
   return hipGetLastError();
