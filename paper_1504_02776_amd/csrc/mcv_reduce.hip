@@ -157,41 +157,70 @@ reduce_hist_qe(const float* __restrict__ geo, QEMap M,
       load_run(hist, i0 + kTile, nbins, nv);
       if (W2) load_run(hw2, i0 + kTile, nbins, nw);
     }
-    if (i0 >= nbins) continue;
+    // runs of equal (Q, E) cells along this lane's bins: the middle ones are
+    // put at once; the first (if the lane has more than one) and the last
+    // wait, because a cell often spans the boundary between neighbouring
+    // lanes (about 2.6 time bins per energy bin at the powder's grid): a lane
+    // whose first cell is its left neighbour's last cell hands its first
+    // partial sum to that lane, which puts both with one update
+    int first_cell = -1, last_cell = -1, ncell = 0;
+    double fa = 0.0, fa2 = 0.0, acc = 0.0, acc2 = 0.0;
     bool any = false;
+    if (i0 < nbins) {
 #pragma unroll
-    for (int q = 0; q < kPerLane; ++q) any = any || v[q] != 0.0 || (W2 && w[q] != 0.0);
-    if (!any) continue;
-    uint32_t pid, tb;
-    pixel_of(i0, ntof, inv_ntof, pid, tb);
-    float L2, c2t;
-    pixel_geom(geo, pid, L2, c2t);
-    int cur = -1;
-    double acc = 0.0, acc2 = 0.0;
-    const int nk = nbins - i0 < (uint64_t)kPerLane ? (int)(nbins - i0) : kPerLane;
+      for (int q = 0; q < kPerLane; ++q) any = any || v[q] != 0.0 || (W2 && w[q] != 0.0);
+    }
+    if (any) {
+      uint32_t pid, tb;
+      pixel_of(i0, ntof, inv_ntof, pid, tb);
+      float L2, c2t;
+      pixel_geom(geo, pid, L2, c2t);
+      const int nk = nbins - i0 < (uint64_t)kPerLane ? (int)(nbins - i0) : kPerLane;
 #pragma unroll
-    for (int k = 0; k < kPerLane; ++k) {
-      if (k >= nk) break;
-      const double x = v[k];
-      const double x2 = W2 ? w[k] : 0.0;
-      if (x != 0.0 || x2 != 0.0) {
-        const int dst = qe_bin(M, L2, c2t, M.tof_lo + ((float)tb + 0.5f) * M.dt);
-        if (dst != cur) {
-          if (cur >= 0) put<W2>(cv, cw, ct, iqe, iqe_w2, cur, acc, acc2);
-          cur = dst;
-          acc = 0.0;
-          acc2 = 0.0;
+      for (int k = 0; k < kPerLane; ++k) {
+        if (k >= nk) break;
+        const double x = v[k];
+        const double x2 = W2 ? w[k] : 0.0;
+        if (x != 0.0 || x2 != 0.0) {
+          const int dst = qe_bin(M, L2, c2t, M.tof_lo + ((float)tb + 0.5f) * M.dt);
+          if (dst != last_cell) {
+            if (ncell == 1) {
+              first_cell = last_cell;
+              fa = acc;
+              fa2 = acc2;
+            } else if (ncell > 1 && last_cell >= 0) {
+              put<W2>(cv, cw, ct, iqe, iqe_w2, last_cell, acc, acc2);
+            }
+            last_cell = dst;
+            acc = 0.0;
+            acc2 = 0.0;
+            ++ncell;
+          }
+          acc += x;
+          if (W2) acc2 += x2;
         }
-        acc += x;
-        if (W2) acc2 += x2;
-      }
-      if (++tb == (uint32_t)ntof) {
-        tb = 0;
-        ++pid;
-        if (k + 1 < nk) pixel_geom(geo, pid, L2, c2t);
+        if (++tb == (uint32_t)ntof) {
+          tb = 0;
+          ++pid;
+          if (k + 1 < nk) pixel_geom(geo, pid, L2, c2t);
+        }
       }
     }
-    if (cur >= 0) put<W2>(cv, cw, ct, iqe, iqe_w2, cur, acc, acc2);
+    // whole wave: hand-over between neighbouring lanes (a wave of fewer
+    // lanes, as in a host build, hands nothing over)
+    const int nl = __popcll(__ballot(1));
+    const int lane = (int)__lane_id();
+    const int left_last = __shfl_up(last_cell, 1);
+    const bool give = ncell > 1 && lane > 0 && first_cell >= 0 && left_last == first_cell;
+    const int right_gives = __shfl_down(give ? 1 : 0, 1);
+    const double got = __shfl_down(give ? fa : 0.0, 1);
+    const double got2 = W2 ? __shfl_down(give ? fa2 : 0.0, 1) : 0.0;
+    if (lane + 1 < nl && right_gives) {
+      acc += got;
+      if (W2) acc2 += got2;
+    }
+    if (ncell > 1 && !give && first_cell >= 0) put<W2>(cv, cw, ct, iqe, iqe_w2, first_cell, fa, fa2);
+    if (last_cell >= 0) put<W2>(cv, cw, ct, iqe, iqe_w2, last_cell, acc, acc2);
   }
   __syncthreads();
   for (int i = tid; i < kCache; i += kBlock) {
