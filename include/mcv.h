@@ -222,13 +222,24 @@ mcv_status mcv_detector_destroy(mcv_detector d);
  * attenuation only.  min_prob: packets below it are not split (0 = off).
  * block_size: threads per workgroup (0 = default 256; multiple of 64, <=
  * 1024).  waves_per_simd: target resident waves per SIMD used to size the
- * grid (0 = default). */
+ * grid (0 = default).
+ * deterministic: 1 = mcv_run sums every histogram bin in a fixed order, so
+ *   that two runs with the same arguments give bitwise equal histograms
+ *   (Sec. 3: a bin's intensity is the sum of the probabilities of the
+ *   packets recorded in it; the packets are sorted by bin and, within a bin,
+ *   by (history id, lineage), and each bin is summed in that order).  Slower,
+ *   and it needs a plan-owned device workspace; 0 = binary64 atomics in
+ *   arrival order (sums equal up to rounding order).
+ * max_waves: upper bound on the wavefronts a launch spreads its histories
+ *   over (each wave then traces about n / max_waves histories one after
+ *   another); 0 = enough waves to fill the device. */
 typedef struct {
   int32_t max_orders;
   int32_t block_size;
   double min_prob;
   int32_t waves_per_simd;
-  int32_t reserved;
+  int32_t deterministic;
+  int64_t max_waves;
 } mcv_opts;
 
 /* Validates the assembly with the detector and uploads the device tables to

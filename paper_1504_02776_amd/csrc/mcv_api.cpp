@@ -321,6 +321,8 @@ struct mcv_plan_s {
   int block = 256;
   int cus = 256;
   int waves_per_simd = 4;
+  int64_t max_waves = 0;  // 0: fill the device
+  int deterministic = 0;
   int64_t nbins = 0;
   double R = 0;
   double tof_lo = 0, tof_hi = 0;  // detector time window (binary64)
@@ -402,6 +404,8 @@ mcv_status mcv_detector_sphere(mcv_detector* out, double R, int32_t n_2theta, in
   if (!(R > 0.0) || n_2theta < 1 || n_tof < 1 || !(tof_hi > tof_lo) || !std::isfinite(tof_lo) ||
       !std::isfinite(tof_hi))
     return fail(MCV_EINVAL, "sphere detector needs R > 0, bins >= 1, tof_hi > tof_lo");
+  if ((int64_t)n_2theta * n_tof >= kMaxBins)
+    return fail(MCV_EUNSUPPORTED, "histogram too large: n_2theta * n_tof must stay below 2^31");
   auto* d = new (std::nothrow) mcv_detector_s();
   if (!d) return fail(MCV_ENOMEM, "host allocation failed");
   d->type = DET_SPHERE;
@@ -434,8 +438,10 @@ mcv_status mcv_detector_tubes(mcv_detector* out, const mcv_tube_layout* L, int32
   for (int r = 1; r < L->nrows; ++r)
     if (!(L->row_y[r] - L->row_y[r - 1] >= L->length))
       return fail(MCV_EINVAL, "rows must be ascending and must not overlap");
-  if ((int64_t)L->nrows * L->ncols * n_pix * n_tof > (int64_t)1 << 40)
-    return fail(MCV_EUNSUPPORTED, "histogram too large");
+  // bins are 32-bit indices on the device (histogram updates, bin cache
+  // tags, event pixels)
+  if ((int64_t)L->nrows * L->ncols * n_pix * n_tof >= kMaxBins)
+    return fail(MCV_EUNSUPPORTED, "histogram too large: nrows * ncols * n_pix * n_tof must stay below 2^31");
   auto* d = new (std::nothrow) mcv_detector_s();
   if (!d) return fail(MCV_ENOMEM, "host allocation failed");
   d->type = DET_TUBES;
@@ -469,6 +475,8 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   if (opts) o = *opts;
   if (o.max_orders < 0 || o.max_orders > kMaxOrders) return fail(MCV_EUNSUPPORTED, "max_orders must be 0..7");
   if (!(o.min_prob >= 0.0)) return fail(MCV_EINVAL, "min_prob must be >= 0");
+  if (o.max_waves < 0) return fail(MCV_EINVAL, "max_waves must be >= 0");
+  if (o.deterministic != 0 && o.deterministic != 1) return fail(MCV_EINVAL, "deterministic must be 0 or 1");
   int block = o.block_size ? o.block_size : 256;
   if (block < 64 || block > 256 || block % 64) return fail(MCV_EINVAL, "block_size must be 64, 128, 192 or 256");
 
@@ -725,6 +733,8 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   p->device = device;
   p->scat = a->scat;
   p->waves_per_simd = o.waves_per_simd > 0 ? o.waves_per_simd : 4;
+  p->max_waves = o.max_waves;
+  p->deterministic = o.deterministic;
 
   hipError_t e;
   int cur = 0;
@@ -847,7 +857,8 @@ mcv_status check_ids(const DevBeam& B, uint64_t first, uint64_t n) {
 
 void grid_shape(const mcv_plan_s* p, uint64_t n, int block, uint64_t* grid, uint64_t* per_wave) {
   const uint64_t waves_per_block = (uint64_t)block / 64;
-  const uint64_t target = (uint64_t)p->cus * 4 * p->waves_per_simd * 2;
+  uint64_t target = (uint64_t)p->cus * 4 * p->waves_per_simd * 2;
+  if (p->max_waves > 0 && (uint64_t)p->max_waves < target) target = (uint64_t)p->max_waves;
   uint64_t waves = (n + 63) / 64;
   if (waves > target) waves = target;
   *per_wave = (n + waves - 1) / waves;

@@ -96,6 +96,9 @@ struct DevDet {
   int32_t t_cols;    // offset of (x_c, z_c) per column
 };
 
+// histogram bins are addressed with 32-bit indices on the device
+constexpr int64_t kMaxBins = (int64_t)1 << 31;
+
 // LDS histogram bin cache of a workgroup: slots (a power of two) and size in
 // 32-bit words (double v[n], double v2[n], int tag[n])
 constexpr int kHotMin = 64;

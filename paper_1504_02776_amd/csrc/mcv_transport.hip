@@ -1777,6 +1777,10 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
     }
     next += (uint64_t)__popcll(m);
     if (__ballot(has) == 0ull) {
+      // every lane drew a history that carries nothing (a saved-beam entry
+      // of weight zero) while ids remain: draw again (next is the same in
+      // every lane, so the whole wave takes this branch together)
+      if (next < end) continue;
       if (DQ && qn > 0) dq_run<MODE, DQ>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
       break;
     }

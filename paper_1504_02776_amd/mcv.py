@@ -66,7 +66,8 @@ class mcv_tube_layout(C.Structure):
 
 class mcv_opts(C.Structure):
     _fields_ = [("max_orders", C.c_int32), ("block_size", C.c_int32), ("min_prob", C.c_double),
-                ("waves_per_simd", C.c_int32), ("reserved", C.c_int32)]
+                ("waves_per_simd", C.c_int32), ("deterministic", C.c_int32),
+                ("max_waves", C.c_int64)]
 
 
 class mcv_beam(C.Structure):
@@ -307,7 +308,8 @@ def _stream_ptr(stream):
 class Plan:
     """A device plan for one workload description (sample + detector + orders)."""
 
-    def __init__(self, cfg, device=0, block_size=0, waves_per_simd=0):
+    def __init__(self, cfg, device=0, block_size=0, waves_per_simd=0, max_waves=0,
+                 deterministic=False):
         self.cfg = cfg
         self.device = device
         asm = Assembly()
@@ -315,7 +317,7 @@ class Plan:
             asm.add(sc)
         det = Detector(cfg["detector"])
         opts = mcv_opts(int(cfg["K"]), int(block_size), float(cfg.get("min_prob", 0.0)),
-                        int(waves_per_simd), 0)
+                        int(waves_per_simd), int(bool(deterministic)), int(max_waves))
         self.h = C.c_void_p()
         check(lib().mcv_plan_create(C.byref(self.h), asm.h, det.h, C.byref(opts), device))
         asm.close()

@@ -408,6 +408,36 @@ def saved_beam_powder_config(n=200_000, seed=0):
     return cfg
 
 
+def with_invalid_runs(rows, run=100, period=3):
+    """A copy of saved-beam rows in which entries i with (i // run) % period
+    == 1 carry weight 0 (runs of `run` consecutive entries that start no
+    history)."""
+    rows = np.array(rows, dtype=np.float32, copy=True)
+    i = np.arange(rows.shape[1])
+    rows[7, (i // run) % period == 1] = 0.0
+    return rows
+
+
+def saved_beam_crystal_config(n=1_200, seed=0, run=100):
+    """The crystal in its can fed by n saved 50 meV neutrons, with runs of
+    `run` entries of weight zero (a beam file with holes)."""
+    cfg = crystal_config(N=n, seed=seed)
+    cfg["beam"] = saved_beam(with_invalid_runs(
+        divergent_beam_rows(n, E=50.0, sigma_rel=0.0, seed=seed + 29), run=run))
+    cfg["name"] = "crystal-can-saved-beam-gaps"
+    return cfg
+
+
+def saved_beam_plate_config(n=6_000, seed=0, run=200):
+    """The plate fed by n saved 60 meV neutrons with runs of `run` entries of
+    weight zero."""
+    cfg = plate_config(N=n, seed=seed)
+    cfg["beam"] = saved_beam(with_invalid_runs(
+        divergent_beam_rows(n, E=60.0, sigma_rel=0.01, seed=seed + 31), run=run))
+    cfg["name"] = "plate-saved-beam-gaps"
+    return cfg
+
+
 def crystal_config(N=100_000_000, seed=0):
     """Single-crystal slab with a nearest-neighbour cubic spin wave inside an
     aluminium-like annular can; 3 orders; 2000 tubes x 128 x 500."""

@@ -148,3 +148,51 @@ def test_coherent_phonon_kernel_validation():
     # with the phonon kernel beside it the Debye-Waller factor is accepted
     mcv.Assembly().add(W.scatterer(box, 0.06, 0.2, [dict(ok, dw=1),
                                                     W.phonon(0.01, 27.0, 300.0, 40.0, dos)]))
+
+
+def test_histograms_beyond_32bit_bins_are_rejected():
+    """The device addresses histogram bins with 32-bit indices: a detector
+    whose bin count reaches 2^31 is refused on the host instead of wrapping
+    its high bins."""
+    from paper_1504_02776_amd import mcv, workloads as W
+    if not os.path.exists(mcv.LIB_PATH):
+        pytest.skip("libmcv.so not built")
+    # 8 rows x 500 columns x 128 pixels: 4195 tof bins give 2^31 + 356 352
+    # bins, 4194 give 2^31 - 155 648
+    for ntof, ok in ((4195, False), (4194, True)):
+        det = W.tube_detector(8, 500, 128, ntof, 1e-3, 2e-3, radius=0.00635)
+        det["row_y"] = [-4.08 + 1.02 * i for i in range(8)]
+        if ok:
+            d = mcv.Detector(det)
+            assert d.nbins == 8 * 500 * 128 * ntof < 2 ** 31
+            d.close()
+        else:
+            with pytest.raises(mcv.MCVError) as e:
+                mcv.Detector(det)
+            assert e.value.status == mcv.MCV_EUNSUPPORTED
+    with pytest.raises(mcv.MCVError) as e:
+        mcv.Detector(W.sphere_detector(3.0, 65536, 32768, 1e-3, 2e-3))
+    assert e.value.status == mcv.MCV_EUNSUPPORTED
+    d = mcv.Detector(W.sphere_detector(3.0, 65536, 32767, 1e-3, 2e-3))
+    assert d.nbins == 65536 * 32767
+    d.close()
+
+
+def test_plan_option_validation():
+    """Negative wave caps and deterministic flags other than 0/1 are refused
+    before any device work."""
+    from paper_1504_02776_amd import mcv, workloads as W
+    if not os.path.exists(mcv.LIB_PATH):
+        pytest.skip("libmcv.so not built")
+    import ctypes as C
+    cfg = W.plate_config()
+    asm = mcv.Assembly()
+    for sc in cfg["scatterers"]:
+        asm.add(sc)
+    det = mcv.Detector(cfg["detector"])
+    for opts in (mcv.mcv_opts(1, 0, 0.0, 0, 0, -1), mcv.mcv_opts(1, 0, 0.0, 0, 2, 0),
+                 mcv.mcv_opts(8, 0, 0.0, 0, 0, 0), mcv.mcv_opts(1, 0, -1.0, 0, 0, 0)):
+        h = C.c_void_p()
+        st = mcv.lib().mcv_plan_create(C.byref(h), asm.h, det.h, C.byref(opts), 0)
+        assert st in (mcv.MCV_EINVAL, mcv.MCV_EUNSUPPORTED)
+        assert not h

@@ -12,20 +12,45 @@ from tests.parity_tools import compare_hist, compare_packets
 pytestmark = pytest.mark.gpu
 
 
+# name -> (workload, histories, plan options, caps).  Every case spans
+# several workgroups and ends in a ragged tail.  The "-refill" cases cap the
+# wave count (max_waves) so that each wave traces hundreds to thousands of
+# histories one after another, as the full-size launches do: the lanes' refill
+# from the wave's id range then runs under the oracle comparison.  The caps
+# are (near-decision fraction, poorly-conditioned fraction, differing
+# fraction), each just above what the case measures (design notes,
+# Tolerances).
 def _cases():
     return {
-        # several tiles and a ragged tail in every case
-        "plate": (W.plate_config(), 20_000 + 37),
-        "plate-K3": (dict(W.plate_config(), K=3), 6_000 + 5),
-        "powder": (W.powder_config(), 3_000 + 11),
-        "crystal": (W.crystal_config(), 600 + 3),
-        "powder-in-can": (W.powder_in_can_config(), 1_500 + 11),
-        "sqe": (W.sqe_config(), 4_000 + 1),
-        "powder-multiphonon": (W.powder_mp_config(), 3_000 + 7),
-        "crystal-delta": (W.crystal_delta_config(psi_deg=23.0), 600 + 9),
-        "powder-8packs": (W.powder_8pack_config(), 3_000 + 13),
-        "al-coherent-phonon": (W.al_coherent_config(), 3_000 + 17),
-        "powder-saved-beam": (W.saved_beam_powder_config(n=20_000), 3_000 + 19),
+        "plate": (W.plate_config(), 20_000 + 37, {}, (1.0e-3, 1e-3, 1e-3)),
+        "plate-K3": (dict(W.plate_config(), K=3), 6_000 + 5, {}, (7.5e-3, 5e-3, 7.5e-3)),
+        "powder": (W.powder_config(), 3_000 + 11, {}, (8.5e-3, 1.5e-2, 8.5e-3)),
+        "crystal": (W.crystal_config(), 600 + 3, {}, (2.0e-2, 2.0e-2, 2.0e-2)),
+        "powder-in-can": (W.powder_in_can_config(), 1_500 + 11, {}, (1.9e-2, 1e-2, 1.9e-2)),
+        "sqe": (W.sqe_config(), 4_000 + 1, {}, (5.5e-3, 2.0e-2, 5.5e-3)),
+        "powder-multiphonon": (W.powder_mp_config(), 3_000 + 7, {}, (1.3e-2, 2.7e-2, 1.3e-2)),
+        "crystal-delta": (W.crystal_delta_config(psi_deg=23.0), 600 + 9, {},
+                          (3.2e-2, 3.2e-2, 3.2e-2)),
+        "powder-8packs": (W.powder_8pack_config(), 3_000 + 13, {}, (8e-3, 1.5e-2, 8e-3)),
+        "al-coherent-phonon": (W.al_coherent_config(), 3_000 + 17, {}, (2.2e-2, 6e-3, 2.2e-2)),
+        "powder-saved-beam": (W.saved_beam_powder_config(n=20_000), 3_000 + 19, {},
+                              (7.5e-3, 1.3e-2, 7.5e-3)),
+        # walk loop (single scattering, one plate): 3340 histories per wave
+        "plate-refill": (W.plate_config(), 20_000 + 37, {"max_waves": 6}, (1.0e-3, 1e-3, 1e-3)),
+        # walk loop over two scatterers with deferred kernels: ~300 per wave
+        "crystal-refill": (W.crystal_config(), 1_200 + 7, {"max_waves": 4},
+                           (2.0e-2, 2.0e-2, 2.0e-2)),
+        "powder-in-can-refill": (W.powder_in_can_config(), 1_500 + 11, {"max_waves": 4},
+                                 (1.9e-2, 1e-2, 1.9e-2)),
+        # phased loop: ~750 per wave
+        "powder-refill": (W.powder_config(), 3_000 + 11, {"max_waves": 4},
+                          (8.5e-3, 1.5e-2, 8.5e-3)),
+        # saved beams with runs of 100 / 200 entries of weight zero (more than
+        # a wave's 64 lanes draw at once) on walk-loop plans, 2 waves
+        "crystal-saved-beam-gaps": (W.saved_beam_crystal_config(n=1_200), 1_200, {"max_waves": 2},
+                                    (2.4e-2, 2.5e-2, 2.4e-2)),
+        "plate-saved-beam-gaps": (W.saved_beam_plate_config(n=6_000), 6_000, {"max_waves": 2},
+                                  (1.4e-2, 1e-3, 1.4e-2)),
     }
 
 
@@ -40,17 +65,25 @@ def torch_cuda():
 @pytest.mark.parametrize("name", list(_cases()))
 def test_packets_and_histogram_match_oracle(torch_cuda, oracle_lib, name):
     from paper_1504_02776_amd import mcv
-    cfg, n = _cases()[name]
-    print(f"[parity] case={name} n={n}", flush=True)
-    plan = mcv.Plan(cfg)
+    cfg, n, kw, (cap_flag, cap_poor, cap_differ) = _cases()[name]
+    print(f"[parity] case={name} n={n} {kw}", flush=True)
+    plan = mcv.Plan(cfg, **kw)
     hist = plan.zeros()
     rec, count = plan.trace(n=n, hist=hist)
     assert count == len(rec)
     hg = hist.cpu().numpy()
     ho, _, orc, tally = oracle_lib.run(cfg, n=n)
-    st = compare_packets(rec, orc)
+    st = compare_packets(rec, orc, max_flag_frac=cap_flag, max_poor_frac=cap_poor,
+                         max_differ_frac=cap_differ)
     hs = compare_hist(hg, ho, rec, orc)
     print(f"[parity] {name}: {st} {hs}", flush=True)
+    if "gaps" in name:
+        # histories of the weightless entries leave nothing; every other id
+        # does, on both sides
+        w = np.asarray(cfg["beam"]["rows"])[7, :n]
+        live = np.flatnonzero(w > 0)
+        assert np.array_equal(np.unique(rec["id"]), live.astype(np.uint64))
+        assert np.array_equal(np.unique(orc["id"]), live.astype(np.uint64))
     # the histogram is the sum of the recorded values (same launch)
     m = rec["bin"] >= 0
     self_sum = np.bincount(rec["bin"][m], weights=rec["value"][m].astype(np.float64),
@@ -103,8 +136,53 @@ def test_full_size_powder_sampled(torch_cuda, oracle_lib):
         _, _, o, _ = oracle_lib.run(cfg, n=1, first=int(i))
         orcs.append(o)
     orc = np.concatenate(orcs)
-    st = compare_packets(rec[sel], orc)
+    st = compare_packets(rec[sel], orc, max_flag_frac=1.5e-2, max_poor_frac=2e-2,
+                         max_differ_frac=1.5e-2)
     print(f"[parity] full-size sampled: {st}", flush=True)
+
+
+def _sampled_launch_shape(torch_cuda, oracle_lib, cfg, n, max_waves, cap_flag, cap_differ,
+                          n_samples=150):
+    """Runs n histories with the wave count capped so that every wave traces
+    as many histories as in the full-size benchmark launch, checks that the
+    plain run's histogram is the sum of the trace's records, and compares the
+    records of sampled histories with the oracle."""
+    from paper_1504_02776_amd import mcv
+    plan = mcv.Plan(cfg, max_waves=max_waves)
+    hist = plan.zeros()
+    plan.run(hist, n=n)
+    rec, count = plan.trace(n=n, capacity=24 * n)
+    assert count == len(rec)
+    assert np.array_equal(np.unique(rec["id"]), np.arange(n, dtype=np.uint64))
+    m = rec["bin"] >= 0
+    ref = np.bincount(rec["bin"][m], weights=rec["value"][m].astype(np.float64),
+                      minlength=plan.nbins)
+    hg = hist.cpu().numpy()
+    assert np.allclose(hg, ref, rtol=1e-9, atol=1e-15)
+    rng = np.random.default_rng(2)
+    ids = np.unique(np.concatenate([rng.integers(0, n, n_samples), [0, n - 1]]))
+    sel = np.isin(rec["id"], ids)
+    orc = np.concatenate([oracle_lib.run(cfg, n=1, first=int(i))[2] for i in ids])
+    st = compare_packets(rec[sel], orc, max_flag_frac=cap_flag, max_poor_frac=cap_flag,
+                         max_differ_frac=cap_differ)
+    return st
+
+
+def test_crystal_sampled_at_full_launch_shape(torch_cuda, oracle_lib):
+    """The crystal's full 1e8-history launch gives each wave 12 208 histories;
+    1e6 histories on 82 waves (12 196 each) run the same walk-loop refill,
+    deferred kernels and detection queue over that many histories per wave."""
+    st = _sampled_launch_shape(torch_cuda, oracle_lib, W.crystal_config(N=1_000_000),
+                               1_000_000, 82, 3e-2, 3e-2)
+    print(f"[parity] crystal, full launch shape, sampled: {st}", flush=True)
+
+
+def test_plate_sampled_at_full_launch_shape(torch_cuda, oracle_lib):
+    """The plate's 1e9-history throughput launch gives each wave 122 071
+    histories; 2e6 histories on 16 waves (125 000 each) run that refill."""
+    st = _sampled_launch_shape(torch_cuda, oracle_lib, W.plate_config(N=2_000_000),
+                               2_000_000, 16, 5e-3, 5e-3)
+    print(f"[parity] plate, full launch shape, sampled: {st}", flush=True)
 
 
 def test_empty_and_single(torch_cuda):
