@@ -18,39 +18,45 @@ pytestmark = pytest.mark.gpu
 # histories one after another, as the full-size launches do: the lanes' refill
 # from the wave's id range then runs under the oracle comparison.  The caps
 # are (near-decision fraction, poorly-conditioned fraction, differing
-# fraction), each just above what the case measures (design notes,
-# Tolerances).
+# fraction): the first two just above what the oracle reports for the case;
+# the differing cap is 4e-4 everywhere (one to four packets at these sizes),
+# and pooled over all cases the differing fraction must stay below 1e-4
+# (test_pooled_differing_fraction).
+DIFFER = 4e-4
+_POOLED = {}
+
+
 def _cases():
     return {
-        "plate": (W.plate_config(), 20_000 + 37, {}, (1.0e-3, 1e-3, 1e-3)),
-        "plate-K3": (dict(W.plate_config(), K=3), 6_000 + 5, {}, (7.5e-3, 5e-3, 7.5e-3)),
-        "powder": (W.powder_config(), 3_000 + 11, {}, (8.5e-3, 1.5e-2, 8.5e-3)),
-        "crystal": (W.crystal_config(), 600 + 3, {}, (2.0e-2, 2.0e-2, 2.0e-2)),
-        "powder-in-can": (W.powder_in_can_config(), 1_500 + 11, {}, (1.9e-2, 1e-2, 1.9e-2)),
-        "sqe": (W.sqe_config(), 4_000 + 1, {}, (5.5e-3, 2.0e-2, 5.5e-3)),
-        "powder-multiphonon": (W.powder_mp_config(), 3_000 + 7, {}, (1.3e-2, 2.7e-2, 1.3e-2)),
+        "plate": (W.plate_config(), 20_000 + 37, {}, (1.0e-3, 1e-3, DIFFER)),
+        "plate-K3": (dict(W.plate_config(), K=3), 6_000 + 5, {}, (7.5e-3, 5e-3, DIFFER)),
+        "powder": (W.powder_config(), 3_000 + 11, {}, (8.5e-3, 1.5e-2, DIFFER)),
+        "crystal": (W.crystal_config(), 600 + 3, {}, (2.0e-2, 2.0e-2, DIFFER)),
+        "powder-in-can": (W.powder_in_can_config(), 1_500 + 11, {}, (1.9e-2, 1e-2, DIFFER)),
+        "sqe": (W.sqe_config(), 4_000 + 1, {}, (5.5e-3, 2.0e-2, DIFFER)),
+        "powder-multiphonon": (W.powder_mp_config(), 3_000 + 7, {}, (1.3e-2, 2.7e-2, DIFFER)),
         "crystal-delta": (W.crystal_delta_config(psi_deg=23.0), 600 + 9, {},
-                          (3.2e-2, 3.2e-2, 3.2e-2)),
-        "powder-8packs": (W.powder_8pack_config(), 3_000 + 13, {}, (8e-3, 1.5e-2, 8e-3)),
-        "al-coherent-phonon": (W.al_coherent_config(), 3_000 + 17, {}, (2.2e-2, 6e-3, 2.2e-2)),
+                          (3.2e-2, 3.2e-2, DIFFER)),
+        "powder-8packs": (W.powder_8pack_config(), 3_000 + 13, {}, (8e-3, 1.5e-2, DIFFER)),
+        "al-coherent-phonon": (W.al_coherent_config(), 3_000 + 17, {}, (2.2e-2, 6e-3, DIFFER)),
         "powder-saved-beam": (W.saved_beam_powder_config(n=20_000), 3_000 + 19, {},
-                              (7.5e-3, 1.3e-2, 7.5e-3)),
+                              (7.5e-3, 1.3e-2, DIFFER)),
         # walk loop (single scattering, one plate): 3340 histories per wave
-        "plate-refill": (W.plate_config(), 20_000 + 37, {"max_waves": 6}, (1.0e-3, 1e-3, 1e-3)),
+        "plate-refill": (W.plate_config(), 20_000 + 37, {"max_waves": 6}, (1.0e-3, 1e-3, DIFFER)),
         # walk loop over two scatterers with deferred kernels: ~300 per wave
         "crystal-refill": (W.crystal_config(), 1_200 + 7, {"max_waves": 4},
-                           (2.0e-2, 2.0e-2, 2.0e-2)),
+                           (2.0e-2, 2.0e-2, DIFFER)),
         "powder-in-can-refill": (W.powder_in_can_config(), 1_500 + 11, {"max_waves": 4},
-                                 (1.9e-2, 1e-2, 1.9e-2)),
+                                 (1.9e-2, 1e-2, DIFFER)),
         # phased loop: ~750 per wave
         "powder-refill": (W.powder_config(), 3_000 + 11, {"max_waves": 4},
-                          (8.5e-3, 1.5e-2, 8.5e-3)),
+                          (8.5e-3, 1.5e-2, DIFFER)),
         # saved beams with runs of 100 / 200 entries of weight zero (more than
         # a wave's 64 lanes draw at once) on walk-loop plans, 2 waves
         "crystal-saved-beam-gaps": (W.saved_beam_crystal_config(n=1_200), 1_200, {"max_waves": 2},
-                                    (2.4e-2, 2.5e-2, 2.4e-2)),
+                                    (2.4e-2, 2.5e-2, DIFFER)),
         "plate-saved-beam-gaps": (W.saved_beam_plate_config(n=6_000), 6_000, {"max_waves": 2},
-                                  (1.4e-2, 1e-3, 1.4e-2)),
+                                  (1.4e-2, 1e-3, DIFFER)),
     }
 
 
@@ -75,6 +81,7 @@ def test_packets_and_histogram_match_oracle(torch_cuda, oracle_lib, name):
     ho, _, orc, tally = oracle_lib.run(cfg, n=n)
     st = compare_packets(rec, orc, max_flag_frac=cap_flag, max_poor_frac=cap_poor,
                          max_differ_frac=cap_differ)
+    _POOLED[name] = (st["n_differ"], st["n_oracle"])
     hs = compare_hist(hg, ho, rec, orc)
     print(f"[parity] {name}: {st} {hs}", flush=True)
     if "gaps" in name:
@@ -89,6 +96,18 @@ def test_packets_and_histogram_match_oracle(torch_cuda, oracle_lib, name):
     self_sum = np.bincount(rec["bin"][m], weights=rec["value"][m].astype(np.float64),
                            minlength=len(hg))
     assert np.allclose(self_sum, hg, rtol=1e-6, atol=1e-12)
+
+
+def test_pooled_differing_fraction():
+    """Over all parity cases run before it in this session, the packets whose
+    discrete outcome differs between the HIP path and the oracle stay below
+    1e-4 of the packets (the near-decision bar of the contract)."""
+    if len(_POOLED) < len(_cases()):
+        pytest.skip("needs every parity case of this module in the same session")
+    nd = sum(v[0] for v in _POOLED.values())
+    n = sum(v[1] for v in _POOLED.values())
+    print(f"[parity] pooled: {nd} of {n} packets differ ({nd / n:.2e})", flush=True)
+    assert nd / n < 1e-4
 
 
 def test_run_equals_trace_and_is_additive(torch_cuda):
