@@ -216,13 +216,16 @@ struct ORecord {
   double dtime;                 // binary32 uncertainty of the time (s)
 };
 
-// Parameters of a gradient: the raw DOS values of kernel dos_k of scatterer
-// dos_s (one parameter per bin), sigma_abs of scatterer abs_s, and the
-// nominal sigma of kernel sig_k of scatterer sig_s.  Gradient layout:
-// [DOS bins..., sigma_abs, sigma].
+// Parameters of a gradient: the raw DOS values of the one-phonon kernel
+// dos_k of scatterer dos_s (one parameter per bin; -1: none), the cells of
+// the S(Q,E) grid of kernel sqe_k of scatterer sqe_s (-1: none), sigma_abs
+// of scatterer abs_s, and the nominal sigma of kernel sig_k of scatterer
+// sig_s.  mp_k: a multi-phonon kernel of scatterer dos_s whose DOS is the
+// same parameter vector (its A_1 and S_n follow the DOS; -1: none).
+// Gradient layout: [DOS bins..., S(Q,E) cells..., sigma_abs, sigma].
 struct OParamMap {
   int32_t dos_s, dos_k, abs_s, sig_s, sig_k;
-  int32_t pad;
+  int32_t sqe_s, sqe_k, mp_k;
 };
 
 struct OTally {
@@ -631,6 +634,10 @@ struct Scatter {
   double wsens_add = 0.0;  // further relative weight uncertainty of binary32 (conditioning)
   double dk_rel = 0.0;     // relative uncertainty of the outgoing wave number (conditioning)
   double ddir_add = -1.0;  // direction uncertainty of a cone kernel (< 0: fresh direction)
+  int cell = -1;           // S(Q,E) grid cell of a tabulated draw (-1 otherwise)
+  int n_a1 = 0;            // multi-phonon: phonons drawn, their A_1 bins, and Q^2
+  int a1_bin[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double q2 = 0.0;
 };
 
 V3 isotropic_direction(double u_cos, double u_phi) {
@@ -1000,7 +1007,8 @@ Scatter k_sqe(const OKernel& k, const Packet& P, const double* u, double* margin
     r.factor = 0.0;
     return r;
   }
-  r.factor = (k_f / k_i) * k.sqe[iq * k.nE + ie] * (k.Emax - k.Emin);
+  r.cell = iq * k.nE + ie;
+  r.factor = (k_f / k_i) * k.sqe[r.cell] * (k.Emax - k.Emin);
   return r;
 }
 
@@ -1035,7 +1043,9 @@ Scatter k_multiphonon(const OKernel& k, const KernelInfo& ki, const Packet& P, c
     *margin = std::min(*margin, std::fabs(ub - ki.cdf[j]) / kTauU);
     if (j > 0) *margin = std::min(*margin, std::fabs(ub - ki.cdf[j - 1]) / kTauU);
     e += (j - nb + up) * ki.de;
+    r.a1_bin[i] = j;
   }
+  r.n_a1 = n;
   const double Ei = kEperV2 * P.speed * P.speed;
   const double Ef = Ei - e;
   *margin = std::min(*margin, std::fabs(Ef) / (kTauRel * Ei));
@@ -1049,6 +1059,7 @@ Scatter k_multiphonon(const OKernel& k, const KernelInfo& ki, const Packet& P, c
   r.speed = speed_from_k(k_f);
   const V3 Q = sub(scale(P.dir, k_i), scale(r.dir, k_f));
   const double Q2 = dot(Q, Q);
+  r.q2 = Q2;
   const double w2 = ki.dw_self * Q2;  // 2W
   double sn = std::exp(-w2);
   for (int m = 1; m <= n; ++m) sn *= w2 / m;
@@ -1078,8 +1089,12 @@ struct Sim {
   bool tangent = false;
   OParamMap pm;
   int np = 0;
+  int nb = 0;  // DOS parameters (first in the gradient), then nc S(Q,E) cells
+  int nc = 0;
   const double* dLdI = nullptr;
   double* grad = nullptr;
+  double* gabs = nullptr;   // sum of |dL/dI value d log(w)| per parameter (or null)
+  double* gflag = nullptr;  // the same over near-decision packets (or null)
   Rng rng;
   double* hist;
   double* hist_w2;
@@ -1113,6 +1128,35 @@ struct Sim {
       double c = de / (e * std::tanh(e / (2.0 * kBoltzmann * k.T)));
       g[b] += -h2m * q2 * (c - g0 * de) / Ssum;
     }
+  }
+
+  // d log(weight) / d theta of a multi-phonon draw (kernel k, whose DOS
+  // values are the parameters): every phonon i comes from A_1 bin j_i with
+  // mass m_j = Z_b de / (e_b gamma0) (n_b or n_b + 1), Z = theta / S, so that
+  // d log m_j / d theta = delta_b / theta_b - de / S - d log gamma0 / d theta;
+  // S_n(Q) = (2W)^n / n! e^{-2W} with 2W = (hbar^2/2M) gamma0 Q^2 adds
+  // (n - 2W) d log gamma0 / d theta; gamma0 = sum_b c_b theta_b / S with
+  // c_b = coth(e_b/2kT) de / e_b (Supplement S4, multi-phonon kernel).
+  void add_dmultiphonon(std::vector<double>& g, const OKernel& k, const Scatter& r) const {
+    const int nbk = k.nbins;
+    const double de = k.emax / nbk;
+    double Ssum = 0.0;
+    for (int b = 0; b < nbk; ++b) Ssum += k.dos[b] * de;
+    const double g0 = gamma0(k);
+    std::vector<double> dlg0(nbk);
+    for (int b = 0; b < nbk; ++b) {
+      const double e = (b + 0.5) * de;
+      const double c = de / (e * std::tanh(e / (2.0 * kBoltzmann * k.T)));
+      dlg0[b] = (c - g0 * de) / (Ssum * g0);
+    }
+    for (int i = 0; i < r.n_a1; ++i) {
+      const int j = r.a1_bin[i];
+      const int b = j >= nbk ? j - nbk : nbk - 1 - j;
+      g[b] += 1.0 / k.dos[b];
+      for (int q = 0; q < nbk; ++q) g[q] += -de / Ssum - dlg0[q];
+    }
+    const double w2 = hbar2_over_2M(k.M) * g0 * r.q2;
+    for (int q = 0; q < nbk; ++q) g[q] += (r.n_a1 - w2) * dlg0[q];
   }
 
   // d log Z(e) / d theta for a draw from DOS bin b: Z_b = theta_b / S
@@ -1295,7 +1339,12 @@ struct Sim {
     tally->w_escaped[P.order] += P.w;
     if (rec.bin >= 0 && tangent) {
       double g = dLdI[rec.bin] * rec.value;
-      for (int j = 0; j < np; ++j) grad[j] += g * P.dlogw[j];
+      const bool near = std::min(rec.margin_anc, rec.margin_own) < 1.0;
+      for (int j = 0; j < np; ++j) {
+        grad[j] += g * P.dlogw[j];
+        if (gabs) gabs[j] += std::fabs(g * P.dlogw[j]);
+        if (gflag && near) gflag[j] += std::fabs(g * P.dlogw[j]);
+      }
     }
     if (rec.bin >= 0 && hist) {
       hist[rec.bin] += rec.value;
@@ -1434,6 +1483,20 @@ struct Sim {
           }
           r.factor *= (k.dos[r.dos_bin] / ssum) / (kp.dos[r.dos_bin] / psum);
         }
+        // tabulated S(Q,E): the evaluation grid's cell over the proposal's
+        if (r.cell >= 0 && kp.sqe[r.cell] != 0.0) r.factor *= k.sqe[r.cell] / kp.sqe[r.cell];
+        // multi-phonon: the A_1 masses of the drawn phonons and S_n at the
+        // evaluation DOS over those of the proposal DOS
+        if (k.type == K_MULTIPHONON && r.factor > 0.0) {
+          const KernelInfo& ke = si.k[kk];
+          const KernelInfo& kq = sip.k[kk];
+          for (int i = 0; i < r.n_a1; ++i) {
+            const int j = r.a1_bin[i];
+            r.factor *= (ke.a1[j] / ke.a1_sum) / (kq.a1[j] / kq.a1_sum);
+          }
+          r.factor *= std::pow(ke.dw_self / kq.dw_self, r.n_a1) *
+                      std::exp(-(ke.dw_self - kq.dw_self) * r.q2);
+        }
         tally->n_transcend += 4;
         C.dir = r.dir;
         C.speed = r.speed;
@@ -1444,6 +1507,10 @@ struct Sim {
           add_dmu(C.dlogw, iv.scat, P.speed, -x);
           if (r.dw_q2 > 0.0 && iv.scat == pm.dos_s) add_ddw(C.dlogw, r.dw_q2);
           if (r.dos_bin >= 0 && iv.scat == pm.dos_s && kk == pm.dos_k) add_dlogz(C.dlogw, r.dos_bin);
+          if (r.cell >= 0 && iv.scat == pm.sqe_s && kk == pm.sqe_k)
+            C.dlogw[nb + r.cell] += 1.0 / k.sqe[r.cell];
+          if (k.type == K_MULTIPHONON && iv.scat == pm.dos_s && kk == pm.mp_k)
+            add_dmultiphonon(C.dlogw, k, r);
         }
         C.lineage = lin;
         C.order = P.order + 1;
@@ -1732,21 +1799,44 @@ int oracle_run(const OSetup* S, uint64_t seed, uint64_t first, uint64_t n, doubl
 // Forward-mode gradient of sum_b dLdI[b] I_b with respect to the parameters
 // of `pm`, with every random choice frozen at S (the weights of a path are
 // its true density over the proposal density at S).  grad[] is accumulated
-// into; its length is nbins(DOS) + 2.
+// into; its length is nbins(DOS) + cells(S(Q,E)) + 2.  gabs and gflag
+// (nullable, same length, accumulated into) receive the sums of the
+// absolute per-packet terms over all recorded packets and over the
+// near-decision ones.
 int oracle_gradient(const OSetup* S, const OParamMap* pm, uint64_t seed, uint64_t first,
-                    uint64_t n, const double* dLdI, double* grad, OTally* tally) {
+                    uint64_t n, const double* dLdI, double* grad, double* gabs, double* gflag,
+                    OTally* tally) {
   if (S->K < 0 || S->K > 7) return 1;
-  const OKernel& kd = S->s[pm->dos_s].k[pm->dos_k];
-  if (kd.type != K_PHONON) return 2;
+  int nb = 0, nc = 0;
+  if (pm->dos_s >= 0) {
+    const OKernel& kd = S->s[pm->dos_s].k[pm->dos_k];
+    if (kd.type != K_PHONON) return 2;
+    nb = kd.nbins;
+    if (pm->mp_k >= 0) {
+      const OKernel& km = S->s[pm->dos_s].k[pm->mp_k];
+      if (km.type != K_MULTIPHONON || km.nbins != nb) return 2;
+    }
+  } else if (pm->mp_k >= 0) {
+    return 2;
+  }
+  if (pm->sqe_s >= 0) {
+    const OKernel& kq = S->s[pm->sqe_s].k[pm->sqe_k];
+    if (kq.type != K_SQE) return 2;
+    nc = kq.nQ * kq.nE;
+  }
   std::memset(tally, 0, sizeof(OTally));
   Sim sim(*S, *S);
   prepare(*S, sim.info);
   prepare(*S, sim.pinfo);
   sim.tangent = true;
   sim.pm = *pm;
-  sim.np = kd.nbins + 2;
+  sim.nb = nb;
+  sim.nc = nc;
+  sim.np = nb + nc + 2;
   sim.dLdI = dLdI;
   sim.grad = grad;
+  sim.gabs = gabs;
+  sim.gflag = gflag;
   sim.rng.seed = seed;
   sim.rng.tally = tally;
   sim.hist = nullptr;

@@ -75,7 +75,8 @@ class OSetup(C.Structure):
 
 class OParamMap(C.Structure):
     _fields_ = [("dos_s", C.c_int32), ("dos_k", C.c_int32), ("abs_s", C.c_int32),
-                ("sig_s", C.c_int32), ("sig_k", C.c_int32), ("pad", C.c_int32)]
+                ("sig_s", C.c_int32), ("sig_k", C.c_int32), ("sqe_s", C.c_int32),
+                ("sqe_k", C.c_int32), ("mp_k", C.c_int32)]
 
 
 class OTally(C.Structure):
@@ -125,7 +126,7 @@ def lib():
         L.oracle_gradient.restype = C.c_int
         L.oracle_gradient.argtypes = [C.POINTER(OSetup), C.POINTER(OParamMap), C.c_uint64,
                                       C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p,
-                                      C.POINTER(OTally)]
+                                      C.c_void_p, C.c_void_p, C.POINTER(OTally)]
         L.oracle_philox.argtypes = [C.c_uint32] * 6 + [C.POINTER(C.c_uint32)]
         L.oracle_uniform.restype = C.c_double
         L.oracle_uniform.argtypes = [C.c_uint32]
@@ -296,26 +297,39 @@ def run_reweighted(cfg_eval, cfg_prop, n=None, first=0, seed=None):
     return hist
 
 
-def gradient(cfg, param_map, dLdI, n=None, first=0, seed=None):
-    """Forward-mode gradient of sum_b dLdI[b] I_b w.r.t. (DOS bins..., sigma_abs,
-    sigma) of the parameter map {dos: (s, k), abs: s, sig: (s, k)}, with the
-    random choices frozen at cfg."""
+def gradient(cfg, param_map, dLdI, n=None, first=0, seed=None, bounds=False):
+    """Forward-mode gradient of sum_b dLdI[b] I_b w.r.t. (DOS bins..., S(Q,E)
+    cells..., sigma_abs, sigma) of the parameter map {dos: (s, k) or None,
+    abs: s, sig: (s, k) or None, sqe: (s, k) (optional), mp: k (optional)},
+    with the random choices frozen at cfg.  bounds=True also returns the sums
+    of |per-packet term| over all recorded packets and over near-decision
+    packets."""
     L = lib()
     st = Setup(cfg)
     n = cfg["N"] if n is None else n
     seed = cfg["seed"] if seed is None else seed
-    pm = OParamMap(param_map["dos"][0], param_map["dos"][1], param_map["abs"],
-                   param_map["sig"][0], param_map["sig"][1], 0)
-    nb = len(cfg["scatterers"][pm.dos_s]["kernels"][pm.dos_k]["dos"])
-    g = np.zeros(nb + 2)
+    dos = param_map.get("dos") or (-1, -1)
+    sig = param_map.get("sig") or (-1, -1)
+    sqe = param_map.get("sqe") or (-1, -1)
+    mp = param_map.get("mp")
+    pm = OParamMap(dos[0], dos[1], param_map.get("abs", -1), sig[0], sig[1], sqe[0], sqe[1],
+                   -1 if mp is None else mp)
+    nb = len(cfg["scatterers"][dos[0]]["kernels"][dos[1]]["dos"]) if dos[0] >= 0 else 0
+    nc = 0
+    if sqe[0] >= 0:
+        k = cfg["scatterers"][sqe[0]]["kernels"][sqe[1]]
+        nc = int(k["nQ"]) * int(k["nE"])
+    g = np.zeros(nb + nc + 2)
+    ga = np.zeros_like(g)
+    gf = np.zeros_like(g)
     d = np.ascontiguousarray(dLdI, dtype=np.float64)
     assert d.shape[0] == st.nbins()
     tally = OTally()
     rc = L.oracle_gradient(C.byref(st.S), C.byref(pm), seed, first, n, d.ctypes.data,
-                           g.ctypes.data, C.byref(tally))
+                           g.ctypes.data, ga.ctypes.data, gf.ctypes.data, C.byref(tally))
     if rc != 0:
         raise RuntimeError(f"oracle_gradient failed: {rc}")
-    return g
+    return (g, ga, gf) if bounds else g
 
 
 def philox(ctr, key):
