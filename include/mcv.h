@@ -371,19 +371,32 @@ mcv_status mcv_reduce_events_qe(mcv_plan p, const mcv_qe_grid* grid, const mcv_e
 /* ------------------------------------------------------------- adjoint */
 /* Parameters of a gradient (an extension of the paper's method: the
  * derivatives of the Monte Carlo estimate of I with every random choice held
- * fixed): the raw values theta_b of the DOS of one one-phonon kernel (the
- * kernel samples Z = theta / sum(theta de)), sigma_abs of one scatterer, and
- * the nominal sigma of one non-powder kernel.  -1 in abs_scatterer /
- * sigma_scatterer leaves that parameter out (its gradient entry stays 0).
- * Gradient layout: [theta_0 .. theta_{nb-1}, sigma_abs, sigma]. */
+ * fixed):
+ *   - the raw values theta_b of the DOS of one one-phonon kernel (the kernel
+ *     samples Z = theta / sum(theta de); Supplement S4), with
+ *     multiphonon_kernel naming a multi-phonon kernel of the same scatterer
+ *     that reads the same DOS (equal values, emax, M and T: its A_1 and S_n
+ *     then follow theta as well), or -1;
+ *   - the cells S_c of the grid of one tabulated S(Q,E) kernel (Sec. 2.4.2,
+ *     the S(Q,omega) histogram kernel; the grid is the kernel's weight, its
+ *     proposal does not depend on it);
+ *   - sigma_abs of one scatterer and the nominal sigma of one non-powder
+ *     kernel.
+ * -1 in a *_scatterer field leaves that parameter group out.
+ * Gradient layout: [theta_0 .. theta_{nb-1}, S_0 .. S_{nc-1}, sigma_abs,
+ * sigma], nb = DOS bins (0 without DOS), nc = nQ nE cells (0 without a grid);
+ * entries of parameters left out stay 0.  A table entry of value 0 gets
+ * gradient 0 (the frozen proposal never draws a zero DOS bin; a packet that
+ * reads a zero S(Q,E) cell has weight 0 and is not traced). */
 typedef struct {
   int32_t dos_scatterer, dos_kernel;
   int32_t abs_scatterer;
   int32_t sigma_scatterer, sigma_kernel;
-  int32_t reserved;
+  int32_t sqe_scatterer, sqe_kernel;
+  int32_t multiphonon_kernel;
 } mcv_param_map;
 
-/* number of gradient entries (nb + 2), or -1 for an invalid map */
+/* number of gradient entries (nb + nc + 2), or -1 for an invalid map */
 int64_t mcv_adjoint_nparams(mcv_plan p, const mcv_param_map* pm);
 
 /* Re-traces histories first .. first+n-1 with the same random numbers as
@@ -392,9 +405,11 @@ int64_t mcv_adjoint_nparams(mcv_plan p, const mcv_param_map* pm);
  * where a packet's weight is its path density at theta over the density the
  * path was drawn from at the plan's parameters (at theta = the plan's values
  * this is the derivative of the estimate of sum_b dL_dI[b] I_b).  dL_dI:
- * device binary64 [nbins].  The plan keeps a small FP64 workspace:
- * concurrent adjoint calls on one plan race.  Supports max_orders <= 4.
- * Errors: MCV_EINVAL, MCV_EUNSUPPORTED, MCV_ENOMEM, MCV_EHIP. */
+ * device binary64 [nbins].  The plan keeps a binary64 workspace (4 + 2 nb +
+ * nc values, allocated on first use): concurrent adjoint calls on one plan
+ * race.  A packet carries at most 12 table indices, so max_orders times the
+ * phonons of one draw (1, or max_phonons of a tied multi-phonon kernel) must
+ * not exceed 12.  Errors: MCV_EINVAL, MCV_EUNSUPPORTED, MCV_ENOMEM, MCV_EHIP. */
 mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam, uint64_t seed,
                        uint64_t first, uint64_t n, const double* dL_dI, double* grad,
                        void* stream);

@@ -1,6 +1,6 @@
 """torch.autograd binding of the transport: I(pixel, tof) as a function of a
-one-phonon kernel's raw DOS, a scatterer's sigma_abs and a kernel's nominal
-sigma.  forward() runs the HIP transport; backward() runs the HIP adjoint
+one-phonon kernel's raw DOS and/or a tabulated S(Q,E) grid, a scatterer's
+sigma_abs and a kernel's nominal sigma.  forward() runs the HIP transport; backward() runs the HIP adjoint
 kernel, which re-traces the same histories (same random numbers, choices
 drawn at the forward's parameter values) instead of storing their paths."""
 
@@ -17,7 +17,10 @@ from . import mcv
 class Simulation:
     """A workload with named differentiable parameters.
 
-    pm: {"dos": (s, k), "abs": s, "sig": (s, k)} as in mcv.param_map.
+    pm: {"dos": (s, k) or None, "abs": s, "sig": (s, k) or None, "sqe": (s,
+    k) (optional), "mp": k (optional)}, as in mcv.param_map_of.  The table
+    parameter is one vector: the DOS values, then the S(Q,E) cells (row major
+    in Q); a multi-phonon kernel tied to the DOS receives the same values.
     """
 
     def __init__(self, cfg, pm=None, n=None, seed=None, device=0):
@@ -27,41 +30,65 @@ class Simulation:
         self.seed = cfg["seed"] if seed is None else seed
         self.device = device
 
-    def params(self):
-        s, k = self.pm["dos"]
-        dos = torch.tensor(np.asarray(self.cfg["scatterers"][s]["kernels"][k]["dos"]),
-                           dtype=torch.float64)
-        sa = torch.tensor(self.cfg["scatterers"][self.pm["abs"]]["sigma_abs"],
-                          dtype=torch.float64)
-        s2, k2 = self.pm["sig"]
-        sg = torch.tensor(self.cfg["scatterers"][s2]["kernels"][k2]["sigma"], dtype=torch.float64)
-        return dos, sa, sg
+    def _kernel(self, c, key):
+        s, k = self.pm[key]
+        return c["scatterers"][s]["kernels"][k]
 
-    def config_at(self, dos, sigma_abs, sigma):
+    def params(self):
+        parts = []
+        if self.pm.get("dos") is not None:
+            parts.append(np.asarray(self._kernel(self.cfg, "dos")["dos"], dtype=np.float64))
+        if self.pm.get("sqe") is not None:
+            parts.append(np.asarray(self._kernel(self.cfg, "sqe")["S"], dtype=np.float64).reshape(-1))
+        table = torch.tensor(np.concatenate(parts) if parts else np.zeros(0), dtype=torch.float64)
+        a = self.pm.get("abs", -1)
+        sa = torch.tensor(self.cfg["scatterers"][a]["sigma_abs"] if a >= 0 else 0.0,
+                          dtype=torch.float64)
+        sg = torch.tensor(self._kernel(self.cfg, "sig")["sigma"] if self.pm.get("sig") else 0.0,
+                          dtype=torch.float64)
+        return table, sa, sg
+
+    def config_at(self, table, sigma_abs, sigma):
         c = copy.deepcopy(self.cfg)
-        s, k = self.pm["dos"]
-        c["scatterers"][s]["kernels"][k]["dos"] = dos.detach().cpu().double().numpy()
-        c["scatterers"][self.pm["abs"]]["sigma_abs"] = float(sigma_abs)
-        s2, k2 = self.pm["sig"]
-        c["scatterers"][s2]["kernels"][k2]["sigma"] = float(sigma)
+        t = table.detach().cpu().double().numpy()
+        off = 0
+        if self.pm.get("dos") is not None:
+            k = self._kernel(c, "dos")
+            nb = len(k["dos"])
+            k["dos"] = t[off:off + nb].copy()
+            if self.pm.get("mp") is not None:
+                c["scatterers"][self.pm["dos"][0]]["kernels"][self.pm["mp"]]["dos"] = k["dos"]
+            off += nb
+        if self.pm.get("sqe") is not None:
+            k = self._kernel(c, "sqe")
+            nc = int(k["nQ"]) * int(k["nE"])
+            k["S"] = t[off:off + nc].reshape(int(k["nQ"]), int(k["nE"])).copy()
+            off += nc
+        if self.pm.get("abs", -1) >= 0:
+            c["scatterers"][self.pm["abs"]]["sigma_abs"] = float(sigma_abs)
+        if self.pm.get("sig") is not None:
+            self._kernel(c, "sig")["sigma"] = float(sigma)
         return c
 
     def param_map(self):
-        return mcv.param_map(self.pm["dos"], self.pm["abs"], self.pm["sig"])
+        return mcv.param_map_of(self.pm)
 
-    def __call__(self, dos, sigma_abs, sigma):
-        return TransportFunction.apply(dos, sigma_abs, sigma, self)
+    def __call__(self, table, sigma_abs, sigma):
+        return TransportFunction.apply(table, sigma_abs, sigma, self)
 
 
 class TransportFunction(torch.autograd.Function):
+    """I = transport(table, sigma_abs, sigma): forward runs mcv_run at the
+    given values; backward runs mcv_adjoint with grad_I as dL/dI."""
+
     @staticmethod
-    def forward(ctx, dos, sigma_abs, sigma, sim):
-        plan = mcv.Plan(sim.config_at(dos, sigma_abs, sigma), device=sim.device)
+    def forward(ctx, table, sigma_abs, sigma, sim):
+        plan = mcv.Plan(sim.config_at(table, sigma_abs, sigma), device=sim.device)
         hist = plan.zeros()
         plan.run(hist, n=sim.n, seed=sim.seed)
         ctx.plan = plan
         ctx.sim = sim
-        ctx.meta = (dos.dtype, dos.device, dos.numel())
+        ctx.meta = (table.dtype, table.device, table.numel())
         return hist
 
     @staticmethod
@@ -70,7 +97,7 @@ class TransportFunction(torch.autograd.Function):
         pm = sim.param_map()
         g = torch.zeros(plan.nparams(pm), dtype=torch.float64, device=grad_I.device)
         plan.adjoint(pm, grad_I.detach().double().contiguous(), g, n=sim.n, seed=sim.seed)
-        dtype, device, nb = ctx.meta
-        gd = g[:nb].to(device=device, dtype=dtype)
-        return gd, g[nb].to(device=device, dtype=dtype), g[nb + 1].to(device=device,
+        dtype, device, nt = ctx.meta
+        gd = g[:nt].to(device=device, dtype=dtype)
+        return gd, g[nt].to(device=device, dtype=dtype), g[nt + 1].to(device=device,
                                                                       dtype=dtype), None

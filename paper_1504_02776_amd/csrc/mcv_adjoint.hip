@@ -1,0 +1,100 @@
+// mcv_adjoint.hip -- binary64 tables and the dense terms of the adjoint.
+//
+// The adjoint differentiates the Monte Carlo estimate of I with every random
+// choice held fixed (an extension of the paper's method).  A packet's weight
+// is its path density at theta over the density it was drawn from at the
+// plan's values theta0.  For the raw DOS values theta_b of a one-phonon
+// kernel (Supplement S4: Z = theta / S, S = sum theta de, the Debye-Waller
+// exponent 2W = (hbar^2/2M) gamma0 Q^2 with gamma0 = sum_b c_b theta_b / S,
+// c_b = coth(e_b/2kT) de / e_b) the derivative of log(weight) splits into
+//   sparse terms 1/theta_b for every DOS draw from bin b,
+//   dnorm = -de/S per DOS draw (the normalisation S),
+//   dense_a[b] = -(hbar^2/2M)(c_b - gamma0 de)/S per unit of sum Q^2 over
+//     the packet's Debye-Waller factors (gamma0 through 2W);
+// for the cells S_c of a tabulated S(Q,E) grid (Sec. 2.4.2) a draw that reads
+// cell c contributes 1/S_c.  The transport kernel gathers dL/dI at each
+// recorded packet and accumulates g = dL/dI value per table entry and the two
+// scalars sum(g A), sum(g n_draws); this file prepares the 1/theta and dense
+// tables on the device from the plan's raw binary64 tables and applies the
+// dense terms at the end.
+//
+// Workspace layout (binary64): [0] sum g A, [1] sum g n_draws, [2] dnorm,
+// [3] unused, [4, 4 + nt) 1/table value (nt = nb + nc: DOS bins then grid
+// cells; 0 for a zero entry), [4 + nt, 4 + nt + nb) dense_a.
+
+#include <hip/hip_runtime.h>
+
+#include "mcv_internal.h"
+
+namespace mcv {
+namespace dev {
+
+constexpr int kPrepThreads = 256;
+
+// One workgroup: S and sum c_b theta_b by a fixed-order reduction (the same
+// result on every call), then the tables.
+__global__ void __launch_bounds__(kPrepThreads)
+adjoint_prepare(const double* __restrict__ theta, int nb, double de, double kT, double h2m,
+                const double* __restrict__ cells, int nc, double* __restrict__ ws) {
+  __shared__ double red_s[kPrepThreads], red_g[kPrepThreads];
+  const int tid = threadIdx.x;
+  double ps = 0.0, pg = 0.0;
+  for (int b = tid; b < nb; b += kPrepThreads) {
+    const double e = (b + 0.5) * de;
+    ps += theta[b] * de;
+    pg += theta[b] * de / (e * tanh(e / (2.0 * kT)));
+  }
+  red_s[tid] = ps;
+  red_g[tid] = pg;
+  __syncthreads();
+  for (int o = kPrepThreads / 2; o > 0; o >>= 1) {
+    if (tid < o) {
+      red_s[tid] += red_s[tid + o];
+      red_g[tid] += red_g[tid + o];
+    }
+    __syncthreads();
+  }
+  const double S = red_s[0];
+  const double g0 = nb > 0 && S > 0.0 ? red_g[0] / S : 0.0;
+  const int nt = nb + nc;
+  if (tid == 0) {
+    ws[0] = 0.0;
+    ws[1] = 0.0;
+    ws[2] = nb > 0 && S > 0.0 ? -de / S : 0.0;
+    ws[3] = 0.0;
+  }
+  for (int b = tid; b < nb; b += kPrepThreads) {
+    const double e = (b + 0.5) * de;
+    const double c = de / (e * tanh(e / (2.0 * kT)));
+    ws[4 + b] = theta[b] > 0.0 ? 1.0 / theta[b] : 0.0;
+    ws[4 + nt + b] = S > 0.0 ? -h2m * (c - g0 * de) / S : 0.0;
+  }
+  for (int i = tid; i < nc; i += kPrepThreads) ws[4 + nb + i] = cells[i] != 0.0 ? 1.0 / cells[i] : 0.0;
+}
+
+// grad[b] += dense_a[b] sum(g A) + dnorm sum(g n_draws) for the DOS bins:
+// the terms of the normalisation and of gamma0, which touch every bin
+__global__ void adjoint_finalize(double* __restrict__ grad, const double* __restrict__ ws, int nb,
+                                 int nc) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) grad[b] += ws[4 + nb + nc + b] * ws[0] + ws[2] * ws[1];
+}
+
+}  // namespace dev
+
+hipError_t launch_adjoint_prepare(const double* theta, int nb, double de, double kT, double h2m,
+                                  const double* cells, int nc, double* ws, hipStream_t stream) {
+  hipLaunchKernelGGL(dev::adjoint_prepare, dim3(1), dim3(dev::kPrepThreads), 0, stream, theta, nb,
+                     de, kT, h2m, cells, nc, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_finalize(double* grad, const double* ws, int nb, int nc,
+                                   hipStream_t stream) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::adjoint_finalize, dim3((nb + 255) / 256), dim3(256), 0, stream, grad, ws,
+                     nb, nc);
+  return hipGetLastError();
+}
+
+}  // namespace mcv

@@ -28,12 +28,14 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
                             DevEvent* ev, uint64_t ev_cap, unsigned long long* n_ev,
                             const AdjArgs* adj, hipStream_t stream);
-hipError_t launch_adjoint_finalize(double* grad, const double* sums, const double* dense_a,
-                                   double dnorm, int nb, hipStream_t stream);
+hipError_t launch_adjoint_prepare(const double* theta, int nb, double de, double kT, double h2m,
+                                  const double* cells, int nc, double* ws, hipStream_t stream);
+hipError_t launch_adjoint_finalize(double* grad, const double* ws, int nb, int nc,
+                                   hipStream_t stream);
 hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
                             double* dLdI, double* loss, int grid, hipStream_t stream);
 hipError_t launch_fill_zero(double* p, uint64_t n, int grid, hipStream_t stream);
-size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, int hot_n);
+size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_ntab, int hot_n);
 int transport_dq_entries(const DevPlan& P);
 size_t transport_dq_bytes(int block, int entries);
 size_t transport_static_lds();
@@ -298,22 +300,23 @@ struct mcv_detector_s {
   mcv_tube_layout tubes;
 };
 
-struct AdjointTables {
-  int key[5] = {-9, -9, -9, -9, -9};
-  int nb = 0;
-  double* inv_theta = nullptr;  // device [nb]
-  double* dense_a = nullptr;    // device [nb]
-  double* sums = nullptr;       // device [2]
-  double dnorm = 0.0;
-  int block = 0;
+// The adjoint's plan-owned binary64 workspace (see mcv_adjoint.hip for its
+// layout), grown on demand.
+struct AdjointWork {
+  double* ws = nullptr;
+  size_t cap = 0;  // doubles
 };
 
 struct mcv_plan_s {
   int device = 0;
   DevPlan host;
   std::vector<Scatterer> scat;  // host copy (adjoint tables)
-  AdjointTables adj;
+  AdjointWork adj;
   std::vector<float> tables;
+  // binary64 copies of the adjoint's table parameters (one-phonon DOS, S(Q,E)
+  // grids) in device memory, at raw_off[s][k] (-1: none)
+  double* d_raw = nullptr;
+  int64_t raw_off[kMaxScat][kMaxKern];
   DevPlan* d_plan = nullptr;
   float* d_tables = nullptr;
   float* d_pixgeo = nullptr;     // per pixel id: |r_p|, cos(2theta) (reduction)
@@ -709,11 +712,11 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
 
   // LDS: plan + tables + bin cache + per-lane stack + detection queues
   const int dq_n = transport_dq_entries(P);
-  size_t lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, kHotMin) +
+  size_t lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, kLdsNoAdjoint, kHotMin) +
                    transport_dq_bytes(block, dq_n);
   while (lds_dyn + transport_static_lds() > 160 * 1024 && block > 64) {
     block -= 64;
-    lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, kHotMin) +
+    lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, kLdsNoAdjoint, kHotMin) +
               transport_dq_bytes(block, dq_n);
   }
   if (lds_dyn + transport_static_lds() > 160 * 1024) {
@@ -721,7 +724,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     return fail(MCV_EUNSUPPORTED, "tables and packet stack exceed the 160 KiB of LDS");
   }
   P.hot_n = hot_slots(transport_static_lds() +
-                          transport_lds_bytes(P.n_tables, P.stack_cap, block, 0, 0) +
+                          transport_lds_bytes(P.n_tables, P.stack_cap, block, kLdsNoAdjoint, 0) +
                           transport_dq_bytes(block, dq_n),
                       block, transport_waves_per_eu(P.nscat, P.smax));
   P.hot_all = mcv_detector_nbins(d) <= kHotAllBins ? 1 : 0;
@@ -789,6 +792,31 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     delete p;
     return hipfail(e, "hipMemcpy");
   }
+  // binary64 table parameters of the adjoint (one-phonon DOS, S(Q,E) grids)
+  {
+    std::vector<double> raw;
+    for (int si = 0; si < kMaxScat; ++si)
+      for (int j = 0; j < kMaxKern; ++j) p->raw_off[si][j] = -1;
+    for (size_t si = 0; si < p->scat.size(); ++si)
+      for (size_t j = 0; j < p->scat[si].kernels.size(); ++j) {
+        const KernelCopy& kc = p->scat[si].kernels[j];
+        const std::vector<double>* v = kc.k.type == MCV_K_PHONON ? &kc.dos
+                                       : kc.k.type == MCV_K_SQE  ? &kc.sqe
+                                                                 : nullptr;
+        if (!v) continue;
+        p->raw_off[si][j] = (int64_t)raw.size();
+        raw.insert(raw.end(), v->begin(), v->end());
+      }
+    if (!raw.empty()) {
+      if ((e = hipMalloc(&p->d_raw, raw.size() * sizeof(double))) != hipSuccess ||
+          (e = hipMemcpy(p->d_raw, raw.data(), raw.size() * sizeof(double),
+                         hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipSetDevice(cur);
+        mcv_plan_destroy(p);
+        return hipfail(e, "adjoint table upload");
+      }
+    }
+  }
   (void)hipSetDevice(cur);
   *out = p;
   return MCV_OK;
@@ -803,9 +831,8 @@ mcv_status mcv_plan_destroy(mcv_plan p) {
   (void)hipFree(p->d_tables);
   (void)hipFree(p->d_pixgeo);
   for (float* x : p->d_grids) (void)hipFree(x);
-  if (p->adj.inv_theta) (void)hipFree(p->adj.inv_theta);
-  if (p->adj.dense_a) (void)hipFree(p->adj.dense_a);
-  if (p->adj.sums) (void)hipFree(p->adj.sums);
+  if (p->adj.ws) (void)hipFree(p->adj.ws);
+  if (p->d_raw) (void)hipFree(p->d_raw);
   (void)hipSetDevice(cur);
   delete p;
   return MCV_OK;
@@ -1022,82 +1049,119 @@ namespace {
 
 const double kBoltzmannA = 0.08617333;
 
-// FP64 tables of the adjoint for one parameter map (cached in the plan):
-// 1/theta_b for the sparse DOS terms; for the dense terms, with S = sum
-// theta de, c_b = de / (e_b tanh(e_b / 2kT)), gamma0 = sum c_b theta_b / S:
-// dense_a[b] = -(hbar^2/2M)(c_b - gamma0 de)/S (per unit of sum Q^2 over
-// Debye-Waller events) and dnorm = -de/S (per one-phonon draw).
-mcv_status adjoint_tables(mcv_plan p, const mcv_param_map* pm) {
-  AdjointTables& A = p->adj;
-  int key[5] = {pm->dos_scatterer, pm->dos_kernel, pm->abs_scatterer, pm->sigma_scatterer,
-                pm->sigma_kernel};
-  if (A.inv_theta && std::equal(key, key + 5, A.key)) return MCV_OK;
-  const KernelCopy& kc = p->scat[pm->dos_scatterer].kernels[pm->dos_kernel];
-  const int nb = kc.k.nbins;
-  const double de = kc.k.emax / nb;
-  double S = 0.0;
-  for (double v : kc.dos) S += v * de;
-  const double kT = kBoltzmannA * kc.k.T_K;
-  std::vector<double> c(nb), inv(nb), dense(nb);
-  double g0 = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    const double e = (b + 0.5) * de;
-    c[b] = de / (e * std::tanh(e / (2.0 * kT)));
-    g0 += c[b] * kc.dos[b] / S;
-  }
-  const double h2m = kHbar2over2mn * kNeutronMassAmu / kc.k.M_amu;
-  for (int b = 0; b < nb; ++b) {
-    inv[b] = kc.dos[b] > 0.0 ? 1.0 / kc.dos[b] : 0.0;
-    dense[b] = -h2m * (c[b] - g0 * de) / S;
-  }
-  if (A.inv_theta) (void)hipFree(A.inv_theta);
-  if (A.dense_a) (void)hipFree(A.dense_a);
-  A.inv_theta = A.dense_a = nullptr;
-  hipError_t e;
-  if (!A.sums && (e = hipMalloc(&A.sums, 2 * sizeof(double))) != hipSuccess)
-    return fail(MCV_ENOMEM, "hipMalloc adjoint sums");
-  if ((e = hipMalloc(&A.inv_theta, nb * sizeof(double))) != hipSuccess ||
-      (e = hipMalloc(&A.dense_a, nb * sizeof(double))) != hipSuccess)
-    return fail(MCV_ENOMEM, "hipMalloc adjoint tables");
-  if ((e = hipMemcpy(A.inv_theta, inv.data(), nb * sizeof(double), hipMemcpyHostToDevice)) !=
-          hipSuccess ||
-      (e = hipMemcpy(A.dense_a, dense.data(), nb * sizeof(double), hipMemcpyHostToDevice)) !=
-          hipSuccess)
-    return hipfail(e, "hipMemcpy adjoint tables");
-  A.nb = nb;
-  A.dnorm = -de / S;
-  std::copy(key, key + 5, A.key);
-  int block = p->block;
-  while (transport_lds_bytes(p->host.n_tables, p->host.stack_cap, block, nb, 0) +
-                 transport_static_lds() > 160 * 1024 && block > 64)
-    block -= 64;
-  if (transport_lds_bytes(p->host.n_tables, p->host.stack_cap, block, nb, 0) +
-          transport_static_lds() > 160 * 1024)
-    return fail(MCV_EUNSUPPORTED, "adjoint partials do not fit in LDS");
-  A.block = block;
-  return MCV_OK;
-}
+// The parameter map resolved against a plan: table sizes, the scalars of the
+// DOS kernel for the device-side table preparation, and the LDS layout.
+struct AdjSetup {
+  int nb = 0, nc = 0;
+  double de = 1.0, kT = 1.0, h2m = 0.0;
+  const double* theta = nullptr;  // device
+  const double* cells = nullptr;  // device
+  int block = 0;
+  int sparse_lds = 1;
+};
 
-mcv_status check_param_map(mcv_plan p, const mcv_param_map* pm) {
+mcv_status check_param_map(mcv_plan p, const mcv_param_map* pm, AdjSetup* out) {
   if (!pm) return fail(MCV_EINVAL, "null parameter map");
   const int ns = (int)p->scat.size();
-  if (pm->dos_scatterer < 0 || pm->dos_scatterer >= ns || pm->dos_kernel < 0 ||
-      pm->dos_kernel >= (int)p->scat[pm->dos_scatterer].kernels.size() ||
-      p->scat[pm->dos_scatterer].kernels[pm->dos_kernel].k.type != MCV_K_PHONON)
-    return fail(MCV_EINVAL, "dos_scatterer/dos_kernel must name a one-phonon kernel");
-  if (p->scat[pm->dos_scatterer].kernels[pm->dos_kernel].k.nbins > 65535)
-    return fail(MCV_EUNSUPPORTED, "adjoint supports up to 65535 DOS bins");
+  auto kernel_of = [&](int si, int k) -> const KernelCopy* {
+    if (si < 0 || si >= ns || k < 0 || k >= (int)p->scat[si].kernels.size()) return nullptr;
+    return &p->scat[si].kernels[k];
+  };
+  AdjSetup A;
+  int per_event = 0;  // most table indices one kernel draw adds to a packet
+  if (pm->dos_scatterer != -1) {
+    const KernelCopy* kd = kernel_of(pm->dos_scatterer, pm->dos_kernel);
+    if (!kd || kd->k.type != MCV_K_PHONON)
+      return fail(MCV_EINVAL, "dos_scatterer/dos_kernel must name a one-phonon kernel (or -1)");
+    A.nb = kd->k.nbins;
+    A.de = kd->k.emax / kd->k.nbins;
+    A.kT = kBoltzmannA * kd->k.T_K;
+    A.h2m = kHbar2over2mn * kNeutronMassAmu / kd->k.M_amu;
+    A.theta = p->d_raw + p->raw_off[pm->dos_scatterer][pm->dos_kernel];
+    per_event = 1;
+    if (pm->multiphonon_kernel != -1) {
+      const KernelCopy* km = kernel_of(pm->dos_scatterer, pm->multiphonon_kernel);
+      if (!km || km->k.type != MCV_K_MULTIPHONON)
+        return fail(MCV_EINVAL, "multiphonon_kernel must name a multi-phonon kernel of dos_scatterer");
+      if (km->k.nbins != kd->k.nbins || km->k.emax != kd->k.emax || km->k.T_K != kd->k.T_K ||
+          km->k.M_amu != kd->k.M_amu || km->dos != kd->dos)
+        return fail(MCV_EINVAL,
+                    "a tied multi-phonon kernel needs the DOS values, emax, M and T of the one-phonon kernel");
+      per_event = std::max(per_event, km->k.max_phonons);
+    }
+  } else if (pm->multiphonon_kernel != -1) {
+    return fail(MCV_EINVAL, "multiphonon_kernel needs dos_scatterer/dos_kernel");
+  }
+  if (pm->sqe_scatterer != -1) {
+    const KernelCopy* kq = kernel_of(pm->sqe_scatterer, pm->sqe_kernel);
+    if (!kq || kq->k.type != MCV_K_SQE)
+      return fail(MCV_EINVAL, "sqe_scatterer/sqe_kernel must name an S(Q,E) kernel (or -1)");
+    A.nc = kq->k.nQ * kq->k.nE;
+    A.cells = p->d_raw + p->raw_off[pm->sqe_scatterer][pm->sqe_kernel];
+    per_event = std::max(per_event, 1);
+  }
+  if (A.nb + A.nc > kAdjMaxTable)
+    return fail(MCV_EUNSUPPORTED, "adjoint supports up to 65535 table parameters (DOS bins + S(Q,E) cells)");
   if (pm->abs_scatterer < -1 || pm->abs_scatterer >= ns)
     return fail(MCV_EINVAL, "abs_scatterer out of range");
   if (pm->sigma_scatterer < -1 || pm->sigma_scatterer >= ns)
     return fail(MCV_EINVAL, "sigma_scatterer out of range");
   if (pm->sigma_scatterer >= 0) {
-    const auto& ks = p->scat[pm->sigma_scatterer].kernels;
-    if (pm->sigma_kernel < 0 || pm->sigma_kernel >= (int)ks.size() ||
-        ks[pm->sigma_kernel].k.type == MCV_K_POWDER || !(ks[pm->sigma_kernel].k.sigma_b > 0.0))
+    const KernelCopy* ks = kernel_of(pm->sigma_scatterer, pm->sigma_kernel);
+    if (!ks || ks->k.type == MCV_K_POWDER || !(ks->k.sigma_b > 0.0))
       return fail(MCV_EINVAL, "sigma_kernel must name a non-powder kernel with sigma > 0");
   }
-  if (p->host.K > kAdjMaxOrders) return fail(MCV_EUNSUPPORTED, "adjoint supports max_orders <= 4");
+  if ((int64_t)p->host.K * per_event > kAdjMaxSparse)
+    return fail(MCV_EUNSUPPORTED,
+                "a packet would carry more than 12 table indices (max_orders x phonons per draw)");
+  // LDS: table partials when they fit beside tables and packet stacks with a
+  // workgroup of at least 128 lanes, otherwise global atomics per entry
+  const size_t lim = (size_t)160 * 1024 - transport_static_lds();
+  auto lds = [&](int block, int ntab) {
+    return transport_lds_bytes(p->host.n_tables, p->host.stack_cap, block, ntab, 0);
+  };
+  int block = p->block;
+  while (block > 128 && lds(block, A.nb + A.nc) > lim) block -= 64;
+  if (lds(block, A.nb + A.nc) > lim) {
+    A.sparse_lds = 0;
+    block = p->block;
+    while (block > 64 && lds(block, 0) > lim) block -= 64;
+    if (lds(block, 0) > lim) return fail(MCV_EUNSUPPORTED, "adjoint packet stacks do not fit in LDS");
+  }
+  A.block = block;
+  if (out) *out = A;
+  return MCV_OK;
+}
+
+// the workspace the adjoint kernels use: prepare -> transport -> finalize
+mcv_status adjoint_launch(mcv_plan p, const mcv_param_map* pm, const AdjSetup& A,
+                          const DevBeam& B, uint64_t seed, uint64_t first, uint64_t n,
+                          const double* dL_dI, double* grad, double* ws, hipStream_t stream) {
+  hipError_t e = launch_adjoint_prepare(A.theta, A.nb, A.de, A.kT, A.h2m, A.cells, A.nc, ws, stream);
+  if (e == hipSuccess && n > 0) {
+    AdjArgs AA = {};
+    AA.dos_s = A.nb > 0 ? pm->dos_scatterer : -1;
+    AA.dos_k = pm->dos_kernel;
+    AA.mp_k = A.nb > 0 ? pm->multiphonon_kernel : -1;
+    AA.sqe_s = A.nc > 0 ? pm->sqe_scatterer : -1;
+    AA.sqe_k = pm->sqe_kernel;
+    AA.abs_s = pm->abs_scatterer;
+    AA.sig_s = pm->sigma_scatterer;
+    AA.sig_k = pm->sigma_kernel;
+    AA.nb = A.nb;
+    AA.nc = A.nc;
+    AA.sparse_lds = A.sparse_lds;
+    AA.dLdI = dL_dI;
+    AA.grad = grad;
+    AA.ws = ws;
+    uint64_t grid, per_wave;
+    grid_shape(p, n, A.block, &grid, &per_wave);
+    e = launch_transport(p->d_plan, p->host, p->d_tables, B, seed, first, n, (int)grid, A.block,
+                         per_wave, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, &AA,
+                         stream);
+  }
+  if (e == hipSuccess) e = launch_adjoint_finalize(grad, ws, A.nb, A.nc, stream);
+  if (e != hipSuccess) return hipfail(e, "adjoint launch");
   return MCV_OK;
 }
 
@@ -1106,15 +1170,17 @@ mcv_status check_param_map(mcv_plan p, const mcv_param_map* pm) {
 extern "C" {
 
 int64_t mcv_adjoint_nparams(mcv_plan p, const mcv_param_map* pm) {
-  if (!p || check_param_map(p, pm) != MCV_OK) return -1;
-  return (int64_t)p->scat[pm->dos_scatterer].kernels[pm->dos_kernel].k.nbins + 2;
+  AdjSetup A;
+  if (!p || check_param_map(p, pm, &A) != MCV_OK) return -1;
+  return (int64_t)A.nb + A.nc + 2;
 }
 
 mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam, uint64_t seed,
                        uint64_t first, uint64_t n, const double* dL_dI, double* grad,
                        void* stream) {
   if (!p) return fail(MCV_EINVAL, "null plan");
-  mcv_status st = check_param_map(p, pm);
+  AdjSetup A;
+  mcv_status st = check_param_map(p, pm, &A);
   if (st != MCV_OK) return st;
   if (!dL_dI || !grad) return fail(MCV_EINVAL, "null dL_dI or grad");
   DevBeam B;
@@ -1123,30 +1189,18 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
-  st = adjoint_tables(p, pm);
-  if (st == MCV_OK && n > 0) {
-    AdjArgs AA;
-    AA.dos_s = pm->dos_scatterer;
-    AA.dos_k = pm->dos_kernel;
-    AA.abs_s = pm->abs_scatterer;
-    AA.sig_s = pm->sigma_scatterer;
-    AA.sig_k = pm->sigma_kernel;
-    AA.nb = p->adj.nb;
-    AA.dLdI = dL_dI;
-    AA.grad = grad;
-    AA.sums = p->adj.sums;
-    AA.inv_theta = p->adj.inv_theta;
-    uint64_t grid, per_wave;
-    grid_shape(p, n, p->adj.block, &grid, &per_wave);
-    hipError_t e = launch_transport(p->d_plan, p->host, p->d_tables,
-                                    B, seed, first, n, (int)grid, p->adj.block, per_wave, nullptr,
-                                    nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, &AA,
-                                    (hipStream_t)stream);
-    if (e == hipSuccess)
-      e = launch_adjoint_finalize(grad, p->adj.sums, p->adj.dense_a, p->adj.dnorm, p->adj.nb,
-                                  (hipStream_t)stream);
-    if (e != hipSuccess) st = hipfail(e, "adjoint launch");
+  const size_t need = 4 + 2 * (size_t)A.nb + (size_t)A.nc;
+  if (p->adj.cap < need) {
+    if (p->adj.ws) (void)hipFree(p->adj.ws);
+    p->adj.ws = nullptr;
+    p->adj.cap = 0;
+    if (hipMalloc(&p->adj.ws, need * sizeof(double)) != hipSuccess)
+      st = fail(MCV_ENOMEM, "hipMalloc adjoint workspace");
+    else
+      p->adj.cap = need;
   }
+  if (st == MCV_OK)
+    st = adjoint_launch(p, pm, A, B, seed, first, n, dL_dI, grad, p->adj.ws, (hipStream_t)stream);
   if (cur != p->device) (void)hipSetDevice(cur);
   return st;
 }
@@ -1284,20 +1338,20 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   for (auto& c : hchunks) cl.push_back(c.second);
   // dynamic LDS: bin cache, largest tables, largest stacks, then the waves'
   // detection queues (the largest any item uses)
-  size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, kHotMin) +
+  size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, kHotMin) +
                transport_dq_bytes(block, dq_max);
   while (lds + transport_static_lds() + 64 > 160 * 1024 && block > 64) {
     block -= 64;
-    lds = transport_lds_bytes(n_tables_max, stack_max, block, 0, kHotMin) +
+    lds = transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, kHotMin) +
           transport_dq_bytes(block, dq_max);
   }
   if (lds + transport_static_lds() + 64 > 160 * 1024)
     return fail(MCV_EUNSUPPORTED, "batch tables and stacks exceed LDS");
   const int hot_n = hot_slots(transport_static_lds() + 64 +
-                                  transport_lds_bytes(n_tables_max, stack_max, block, 0, 0) +
+                                  transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, 0) +
                                   transport_dq_bytes(block, dq_max),
                               block, batch_waves_per_eu());
-  const size_t lds_q = transport_lds_bytes(n_tables_max, stack_max, block, 0, hot_n);
+  const size_t lds_q = transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, hot_n);
   lds = lds_q + transport_dq_bytes(block, dq_max);
 
   auto* b = new (std::nothrow) mcv_batch_s();

@@ -126,19 +126,32 @@ struct alignas(16) DevPlan {
 };
 static_assert(sizeof(DevPlan) % 16 == 0, "plan copy must keep the dynamic LDS 16-byte aligned");
 
-// Parameters of an adjoint run (raw DOS bins of one phonon kernel, sigma_abs
-// of one scatterer, nominal sigma of one kernel) and where it accumulates.
+// Parameters of an adjoint run and where it accumulates.  The table
+// parameters form one vector [DOS values of one one-phonon kernel (nb) |
+// cells of one S(Q,E) grid (nc)]; a packet carries the indices into it of the
+// table entries its ancestry drew (one per one-phonon or S(Q,E) draw, n per
+// n-phonon draw of a multi-phonon kernel tied to the same DOS).
 struct AdjArgs {
   int32_t dos_s, dos_k, abs_s, sig_s, sig_k;
-  int32_t nb;               // DOS bins
-  const double* dLdI;       // per histogram bin
-  double* grad;             // [nb + 2]: DOS bins, sigma_abs, sigma
-  double* sums;             // [2]: sum g A, sum g n_phonon (dense DOS terms)
-  const double* inv_theta;  // [nb]: 1 / raw DOS value
+  int32_t sqe_s, sqe_k, mp_k;  // -1: none
+  int32_t nb, nc;              // DOS bins, S(Q,E) cells
+  int32_t sparse_lds;          // 1: table partials in LDS, 0: global atomics
+  int32_t pad;
+  const double* dLdI;          // per histogram bin
+  double* grad;                // [nb + nc + 2]: DOS bins, S(Q,E) cells, sigma_abs, sigma
+  // workspace (binary64): [0] sum g A, [1] sum g n_draws (the dense DOS
+  // terms), [2] dnorm, [3] unused, [4, 4 + nb + nc) 1 / table value,
+  // [4 + nb + nc, 4 + 2 nb + nc) dense_a (per unit of sum Q^2)
+  double* ws;
 };
 
-constexpr int kAdjFields = 6;  // extra words per stacked packet in adjoint mode
+constexpr int kAdjFields = 10;     // extra words per stacked packet in adjoint mode
 constexpr int kAdjMaxOrders = 4;
+constexpr int kAdjMaxSparse = 12;  // table indices a packet carries (16 bits each)
+constexpr int kAdjMaxTable = 65535;
+// the adjoint-partials argument of the LDS size computation for launches
+// that are not adjoint
+constexpr int kLdsNoAdjoint = -1;
 
 struct DevBeam {
   int32_t type;  // 1 mono, 2 gauss, 3 saved

@@ -348,7 +348,7 @@ __device__ __forceinline__ Mu attenuation(const DevScat& S, const float* tab, fl
 struct Out {
   float dx, dy, dz, sp, f;
   float dwq2;  // Q^2 of the Debye-Waller factor applied (0 if none)
-  int bin;     // DOS bin of a one-phonon draw (-1 otherwise)
+  int bin;     // DOS bin of a one-phonon draw, grid cell of an S(Q,E) draw (-1 otherwise)
 };
 
 // |k_i - k_f|^2 without cancellation: (ki - kf)^2 + ki kf |d_i - d_f|^2
@@ -700,6 +700,7 @@ __device__ __forceinline__ Out k_sqe(const DevKernel& K, const float* tab, const
   int ie = (int)floorf((E - K.Emin) * K.e_scale);
   ie = ie < 0 ? 0 : (ie > K.nE - 1 ? K.nE - 1 : ie);
   o.sp = kf * kVperK;
+  o.bin = iq < K.nQ ? iq * K.nE + ie : -1;  // the grid cell read (adjoint)
   o.f = iq < K.nQ ? (kf / ki) * tab[K.t_s + iq * K.nE + ie] * (K.Emax - K.Emin) : 0.0f;
   return o;
 }
@@ -749,6 +750,7 @@ __device__ __forceinline__ Out k_multiphonon(const DevKernel& K, const float* ta
   const float w2 = K.dw_self * q2;
   float sn = expf(-w2);
   for (int m = 1; m <= n; ++m) sn *= w2 / (float)m;
+  o.dwq2 = q2;  // Q^2 of 2W in S_n (adjoint of a tied DOS)
   o.sp = kf * kVperK;
   o.f = (kf / ki) * sn * (float)(N - 1);
   return o;
@@ -954,13 +956,37 @@ __device__ __forceinline__ Pk source(const DevBeam& B, uint64_t id, uint64_t see
 
 // ------------------------------------------------------------------ stack
 // Adjoint carry of a packet: d log(w)/d sigma_abs, d log(w)/d sigma, the sum
-// A of hbar^2 Q^2 / 2M ... over its Debye-Waller events (Q^2 only; the
-// constant is applied at the end), the number of one-phonon draws and their
-// DOS bins (16 bits each, up to kAdjMaxOrders).
+// A of Q^2 over its Debye-Waller events and tied multi-phonon draws (the
+// constant is applied at the end), the number of DOS draws (low 16 bits of
+// cnt) and of carried table indices (high 16 bits), and the indices into
+// the table parameter vector [DOS | S(Q,E) cells] of the entries its
+// ancestry drew (16 bits each, kAdjMaxSparse at most).
 struct Adj {
   float dabs, dsig, A;
-  uint32_t nph, b01, b23;
+  uint32_t cnt;
+  uint32_t s[kAdjMaxSparse / 2];
 };
+
+__device__ __forceinline__ Adj adj_zero() {
+  Adj a;
+  a.dabs = a.dsig = a.A = 0.0f;
+  a.cnt = 0u;
+#pragma unroll
+  for (int w = 0; w < kAdjMaxSparse / 2; ++w) a.s[w] = 0u;
+  return a;
+}
+
+// appends a table index (static register indexing; the host bounds the
+// count per packet by kAdjMaxSparse)
+__device__ __forceinline__ void adj_push(Adj& a, uint32_t idx) {
+  const uint32_t n = a.cnt >> 16;
+  if (n >= (uint32_t)kAdjMaxSparse) return;
+  const uint32_t sh = 16u * (n & 1u);
+#pragma unroll
+  for (int w = 0; w < kAdjMaxSparse / 2; ++w)
+    if ((n >> 1) == (uint32_t)w) a.s[w] |= idx << sh;
+  a.cnt += 1u << 16;
+}
 
 // A stacked packet: position, direction, speed, time, weight, lineage and
 // the code of a kernel still to be evaluated for it (scatterer 4 s + kernel
@@ -985,9 +1011,9 @@ __device__ __forceinline__ void push(float* st, int slot, int nthreads, int tid,
     b[11 * nthreads] = a.dabs;
     b[12 * nthreads] = a.dsig;
     b[13 * nthreads] = a.A;
-    b[14 * nthreads] = __uint_as_float(a.nph);
-    b[15 * nthreads] = __uint_as_float(a.b01);
-    b[16 * nthreads] = __uint_as_float(a.b23);
+    b[14 * nthreads] = __uint_as_float(a.cnt);
+#pragma unroll
+    for (int w = 0; w < kAdjMaxSparse / 2; ++w) b[(15 + w) * nthreads] = __uint_as_float(a.s[w]);
   }
 }
 
@@ -1011,9 +1037,9 @@ __device__ __forceinline__ void pop(const float* st, int slot, int nthreads, int
     a.dabs = b[11 * nthreads];
     a.dsig = b[12 * nthreads];
     a.A = b[13 * nthreads];
-    a.nph = __float_as_uint(b[14 * nthreads]);
-    a.b01 = __float_as_uint(b[15 * nthreads]);
-    a.b23 = __float_as_uint(b[16 * nthreads]);
+    a.cnt = __float_as_uint(b[14 * nthreads]);
+#pragma unroll
+    for (int w = 0; w < kAdjMaxSparse / 2; ++w) a.s[w] = __float_as_uint(b[(15 + w) * nthreads]);
   }
 }
 
@@ -1166,21 +1192,43 @@ __device__ __forceinline__ void flight_exit(Pk& P, const Flight<NSC, TWO>& F) {
 }
 
 // The adjoint terms of a kernel event: d log(mu_k)/d sigma for the
-// differentiated kernel, and the Debye-Waller sum and DOS bin of a one-phonon
-// draw of the DOS scatterer.
+// differentiated kernel; for the scatterer of the DOS parameters, the Q^2 of
+// its Debye-Waller factors and the DOS bin of a one-phonon draw; for a
+// multi-phonon kernel tied to that DOS, the Q^2 of S_n and the DOS bins of
+// its n phonons (replayed from the same words of blocks 2, 3, ... of the
+// packet's scattering stream that k_multiphonon drew), n draws in all; for
+// the S(Q,E) kernel of the grid parameters, the cell read.
 __device__ __forceinline__ void kernel_carries(const AdjArgs& AA, const DevScat& S,
-                                               const DevKernel& K, int si, int kk, const Out& o,
-                                               Adj& ca) {
+                                               const DevKernel& K, const float* tab, int si,
+                                               int kk, const Out& o, const float* u, uint64_t id,
+                                               uint32_t lin, uint64_t seed, Adj& ca) {
   if (si == AA.sig_s && kk == AA.sig_k) ca.dsig += S.n100 / K.mu;
   if (si == AA.dos_s) {
-    ca.A += o.dwq2;
-    if (kk == AA.dos_k && o.bin >= 0) {
-      const uint32_t sh = 16u * (ca.nph & 1u);
-      if (ca.nph < 2u) ca.b01 |= (uint32_t)o.bin << sh;
-      else ca.b23 |= (uint32_t)o.bin << sh;
-      ++ca.nph;
+    if (K.type == K_MULTIPHONON) {
+      if (kk == AA.mp_k) {
+        ca.A += o.dwq2;
+        const int N = K.nmax;
+        int n = 2 + (int)floorf(u[2] * (float)(N - 1));
+        n = n > N ? N : n;
+        const int nb2 = 2 * K.nbins;
+        float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int i = 0; i < n; ++i) {
+          if ((i & 1) == 0) draw4(id, STREAM_SCATTER, lin, 2u + (uint32_t)(i >> 1), seed, v);
+          int j = first_above(tab + K.t_cdf, nb2, (i & 1) ? v[2] : v[0]);
+          j = j > nb2 - 1 ? nb2 - 1 : j;
+          adj_push(ca, (uint32_t)(j >= K.nbins ? j - K.nbins : K.nbins - 1 - j));
+        }
+        ca.cnt += (uint32_t)n;
+      }
+    } else {
+      ca.A += o.dwq2;
+      if (kk == AA.dos_k && o.bin >= 0) {
+        adj_push(ca, (uint32_t)o.bin);
+        ca.cnt += 1u;
+      }
     }
   }
+  if (si == AA.sqe_s && kk == AA.sqe_k && o.bin >= 0) adj_push(ca, (uint32_t)(AA.nb + o.bin));
 }
 
 // Evaluates the kernel of a child born with DEFER (code = 4 s + k): the same
@@ -1203,7 +1251,7 @@ __device__ __forceinline__ void eval_deferred(const DevPlan& PL, const float* ta
   C.dz = o.dz;
   C.sp = o.sp;
   C.w *= o.f;
-  if (ADJ) kernel_carries(AA, S, K, si, kk, o, ca);
+  if (ADJ) kernel_carries(AA, S, K, tab, si, kk, o, u, id, C.lin, seed, ca);
 }
 
 // The nearest remaining interval of a flight: the packet is attenuated by
@@ -1282,7 +1330,7 @@ __device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
       C.dz = o.dz;
       C.sp = o.sp;
       C.w *= o.f;
-      if (ADJ) kernel_carries(AA, S, K, si, kk, o, ca);
+      if (ADJ) kernel_carries(AA, S, K, tab, si, kk, o, u, id, lin, seed, ca);
     }
     if (C.w > 0.0f) {
       if (!has_nxt) {
@@ -1491,13 +1539,23 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
     if (ADJ) {
       const double gv = AA.dLdI[hh.bin] * (double)hh.value;
       if (gv != 0.0) {
-        atomicAdd(&acc[AA.nb + 0], gv * (double)ca.dabs);
-        atomicAdd(&acc[AA.nb + 1], gv * (double)ca.dsig);
-        atomicAdd(&acc[AA.nb + 2], gv * (double)ca.A);
-        atomicAdd(&acc[AA.nb + 3], gv * (double)ca.nph);
-        for (uint32_t e = 0; e < ca.nph && e < (uint32_t)kAdjMaxOrders; ++e) {
-          const uint32_t w = e < 2u ? ca.b01 : ca.b23;
-          atomicAdd(&acc[(w >> (16u * (e & 1u))) & 0xFFFFu], gv);
+        // LDS partials: [table entries (when they fit) | 4 scalars]
+        double* sc = acc + (AA.sparse_lds ? AA.nb + AA.nc : 0);
+        atomicAdd(&sc[0], gv * (double)ca.dabs);
+        atomicAdd(&sc[1], gv * (double)ca.dsig);
+        atomicAdd(&sc[2], gv * (double)ca.A);
+        atomicAdd(&sc[3], gv * (double)(ca.cnt & 0xFFFFu));
+        const uint32_t ns = ca.cnt >> 16;
+#pragma unroll
+        for (int w = 0; w < kAdjMaxSparse / 2; ++w) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if ((uint32_t)(2 * w + h) < ns) {
+              const uint32_t idx = (ca.s[w] >> (16 * h)) & 0xFFFFu;
+              if (AA.sparse_lds) atomicAdd(&acc[idx], gv);
+              else unsafeAtomicAdd(&AA.grad[idx], gv * AA.ws[4 + idx]);
+            }
+          }
         }
       }
     } else {
@@ -1591,7 +1649,7 @@ __device__ __forceinline__ void dq_run(const DevPlan& PL, const float* tab, cons
       P.lin = __float_as_uint(b[9 * kDqEntries]);
       const uint64_t hid = (uint64_t)__float_as_uint(b[10 * kDqEntries]) |
                            ((uint64_t)__float_as_uint(b[11 * kDqEntries]) << 32);
-      const Adj ca = {0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+      const Adj ca = adj_zero();
       record_packet<MODE>(PL, tab, out, AA, acc, P, ca, hid, seed, hbin, hval);
     }
     if (out.hist != nullptr || out.hist_w2 != nullptr)
@@ -1638,7 +1696,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
   cur.lin = 0u;
   Pk nxt;
   nxt.lin = 0u;
-  Adj ca = {0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+  Adj ca = adj_zero();
   Adj na = ca;
   bool has_nxt = false;
   int code = -1;  // kernels are evaluated at birth in this loop (no deferral)
@@ -1711,7 +1769,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
       if (h < end) {
         hid = first + h;
         cur = source(beam, hid, seed);
-        ca = Adj{0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+        ca = adj_zero();
         if (cur.w > 0.0f) state = LANE_SETUP;
       } else {
         state = LANE_DONE;
@@ -1750,7 +1808,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
   const uint64_t lt = lanemask_lt();
   Pk cur;
   cur.lin = 0u;
-  Adj ca = {0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+  Adj ca = adj_zero();
   bool has = false;
   int code = -1;
   uint64_t hid = 0;
@@ -1770,7 +1828,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
       if (h < end) {
         hid = first + h;
         cur = source(beam, hid, seed);
-        ca = Adj{0.0f, 0.0f, 0.0f, 0u, 0u, 0u};
+        ca = adj_zero();
         code = -1;
         has = cur.w > 0.0f;
       }
@@ -1884,14 +1942,15 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   const int nthreads = blockDim.x;
   stage_plan(PL, dyn, gplan, gtab, nthreads, tid);
   const int tab_words = (gplan->n_tables + 3) & ~3;
-  // adjoint partials: [nb] per DOS bin (sum of g), then sigma_abs, sigma, A,
-  // n_phonon; otherwise the histogram bin cache
+  // adjoint partials: per table entry (sum of g; when they fit in LDS), then
+  // sigma_abs, sigma, A, DOS draws; otherwise the histogram bin cache
   double* acc = reinterpret_cast<double*>(dyn + tab_words);
   const bool events = MODE == MODE_RUN && out.ev != nullptr;
   const int hot_n = events ? out.ev_hot_n : gplan->hot_n;
-  const int acc_words = ADJ ? 2 * (((AA.nb + 4) + 1) & ~1) : hot_words(hot_n);
+  const int ntab = ADJ && AA.sparse_lds ? AA.nb + AA.nc : 0;
+  const int acc_words = ADJ ? 2 * (((ntab + 4) + 1) & ~1) : hot_words(hot_n);
   if (ADJ)
-    for (int i = tid; i < AA.nb + 4; i += nthreads) acc[i] = 0.0;
+    for (int i = tid; i < ntab + 4; i += nthreads) acc[i] = 0.0;
   else
     hot_init(acc, hot_n, nthreads, tid);
   __syncthreads();
@@ -1925,13 +1984,14 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   }
   if (ADJ) {
     __syncthreads();
-    for (int i = tid; i < AA.nb; i += nthreads)
-      if (acc[i] != 0.0) unsafeAtomicAdd(&AA.grad[i], acc[i] * AA.inv_theta[i]);
+    for (int i = tid; i < ntab; i += nthreads)
+      if (acc[i] != 0.0) unsafeAtomicAdd(&AA.grad[i], acc[i] * AA.ws[4 + i]);
     if (tid == 0) {
-      unsafeAtomicAdd(&AA.grad[AA.nb], acc[AA.nb]);
-      unsafeAtomicAdd(&AA.grad[AA.nb + 1], acc[AA.nb + 1]);
-      unsafeAtomicAdd(&AA.sums[0], acc[AA.nb + 2]);
-      unsafeAtomicAdd(&AA.sums[1], acc[AA.nb + 3]);
+      const int np = AA.nb + AA.nc;
+      unsafeAtomicAdd(&AA.grad[np], acc[ntab]);
+      unsafeAtomicAdd(&AA.grad[np + 1], acc[ntab + 1]);
+      unsafeAtomicAdd(&AA.ws[0], acc[ntab + 2]);
+      unsafeAtomicAdd(&AA.ws[1], acc[ntab + 3]);
     }
   }
 }
@@ -2026,15 +2086,6 @@ __global__ void batch_cursor_reset(uint32_t* cursor) {
   if (threadIdx.x == 0) *cursor = 0u;
 }
 
-// grad[j] += dense_a[j] * sum(g A) + dnorm * sum(g n_phonon): the terms of
-// the Debye-Waller factor (through gamma_0) and of the DOS normalisation,
-// which touch every bin
-__global__ void adjoint_finalize(double* __restrict__ grad, const double* __restrict__ sums,
-                                 const double* __restrict__ dense_a, double dnorm, int nb) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < nb) grad[j] += dense_a[j] * sums[0] + dnorm * sums[1];
-}
-
 // n binary64 zeros from p (8-byte aligned): one scalar store for a head
 // that is not 16-byte aligned, then one 16-byte store per lane over a grid
 // that covers the array (measured on 1.024 GB: 6.9 TB/s; a grid of 8
@@ -2051,10 +2102,6 @@ __global__ void __launch_bounds__(256) fill_zero(double* __restrict__ p, uint64_
   const zvec2 z = {0.0, 0.0};
   for (uint64_t i = gid; i < m; i += stride) q[i] = z;
   if (gid == 0 && ((n - head) & 1u)) p[n - 1] = 0.0;
-}
-
-__global__ void zero2(double* p) {
-  if (threadIdx.x < 2) p[threadIdx.x] = 0.0;
 }
 
 // L = sum_b w_b (I_b - T_b)^2 and dL/dI_b = 2 w_b (I_b - T_b), streaming;
@@ -2129,11 +2176,13 @@ size_t transport_dq_bytes(int block, int entries) {
   return sizeof(float) * (size_t)entries * dev::kDqFields * (size_t)(block / 64);
 }
 
-size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_nb, int hot_n) {
+// adj_ntab: kLdsNoAdjoint outside the adjoint, else the table partials kept
+// in LDS
+size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_ntab, int hot_n) {
   const size_t tab = (size_t)((n_tables + 3) & ~3);
-  const size_t acc = adj_nb > 0 ? 2 * (size_t)(((adj_nb + 4) + 1) & ~1)
-                                : (size_t)hot_words(hot_n);
-  const size_t nf = kFields + (adj_nb > 0 ? kAdjFields : 0);
+  const size_t acc = adj_ntab >= 0 ? 2 * (size_t)(((adj_ntab + 4) + 1) & ~1)
+                                   : (size_t)hot_words(hot_n);
+  const size_t nf = kFields + (adj_ntab >= 0 ? kAdjFields : 0);
   return sizeof(float) * (tab + acc + (size_t)stack_cap * nf * block);
 }
 
@@ -2200,25 +2249,26 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                             DevEvent* ev, uint64_t ev_cap, unsigned long long* n_ev,
                             const AdjArgs* adj, hipStream_t stream) {
   AdjArgs AA = {};
-  AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = -1;
+  AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = AA.sqe_s = AA.sqe_k = AA.mp_k = -1;
   if (adj) AA = *adj;
   dev::Sinks out = {hist, hist_w2, rec, cap, n_out, ev, ev_cap, n_ev, 0, nullptr, nullptr};
   const int dq_n = adj ? 0 : transport_dq_entries(host_plan);
   const bool dq = dq_n > 0;
   const size_t qbytes = transport_dq_bytes(block, dq_n);
   size_t lds =
-      transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, adj ? adj->nb : 0,
-                          host_plan.hot_n) + qbytes;
+      transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block,
+                          adj ? (adj->sparse_lds ? adj->nb + adj->nc : 0) : kLdsNoAdjoint, host_plan.hot_n) +
+      qbytes;
   if (ev) {
     // room for the event stages: a smaller bin cache, at most the same LDS
     // if the cache can give it
     const size_t stages = sizeof(float) * (size_t)dev::kEvStageWords * (block / 64);
     int hot = host_plan.hot_n;
-    size_t need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, 0, hot) +
+    size_t need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, kLdsNoAdjoint, hot) +
                   qbytes + stages;
     while (hot > kHotMin && need > lds) {
       hot >>= 1;
-      need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, 0, hot) +
+      need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, kLdsNoAdjoint, hot) +
              qbytes + stages;
     }
     out.ev_hot_n = hot;
@@ -2230,7 +2280,6 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
   const bool phased = dev::use_phased(nsc, two, host_plan.K);
   const bool heavy = host_plan.heavy != 0;
   if (adj) {
-    hipLaunchKernelGGL(dev::zero2, dim3(1), dim3(64), 0, stream, AA.sums);
     launch_mode<dev::MODE_ADJOINT>(nsc, two, phased, false, heavy, grid, block, lds, stream, plan,
                                    tables, beam, seed, first, n, per_wave, out, AA);
   } else if (rec) {
@@ -2274,13 +2323,6 @@ int batch_occupancy(int block, size_t lds) {
       hipSuccess)
     return 0;
   return nb;
-}
-
-hipError_t launch_adjoint_finalize(double* grad, const double* sums, const double* dense_a,
-                                   double dnorm, int nb, hipStream_t stream) {
-  hipLaunchKernelGGL(dev::adjoint_finalize, dim3((nb + 255) / 256), dim3(256), 0, stream, grad,
-                     sums, dense_a, dnorm, nb);
-  return hipGetLastError();
 }
 
 hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,

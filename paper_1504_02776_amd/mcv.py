@@ -79,14 +79,29 @@ class mcv_beam(C.Structure):
 class mcv_param_map(C.Structure):
     _fields_ = [("dos_scatterer", C.c_int32), ("dos_kernel", C.c_int32),
                 ("abs_scatterer", C.c_int32), ("sigma_scatterer", C.c_int32),
-                ("sigma_kernel", C.c_int32), ("reserved", C.c_int32)]
+                ("sigma_kernel", C.c_int32), ("sqe_scatterer", C.c_int32),
+                ("sqe_kernel", C.c_int32), ("multiphonon_kernel", C.c_int32)]
 
 
-def param_map(dos=(0, 1), abs_scatterer=0, sigma=(0, 1)):
-    """Gradient parameters: DOS of kernel dos=(scatterer, kernel), sigma_abs
-    of abs_scatterer, nominal sigma of kernel sigma=(scatterer, kernel)."""
-    return mcv_param_map(dos[0], dos[1], abs_scatterer,
-                         -1 if sigma is None else sigma[0], -1 if sigma is None else sigma[1], 0)
+def param_map(dos=(0, 1), abs_scatterer=0, sigma=(0, 1), sqe=None, mp=None):
+    """Gradient parameters: DOS of kernel dos=(scatterer, kernel) or None,
+    sigma_abs of abs_scatterer (-1: none), nominal sigma of kernel
+    sigma=(scatterer, kernel) or None, S(Q,E) grid of kernel sqe=(scatterer,
+    kernel) or None, and mp = a multi-phonon kernel of the DOS scatterer tied
+    to the same DOS (or None)."""
+    d = (-1, -1) if dos is None else dos
+    g = (-1, -1) if sigma is None else sigma
+    q = (-1, -1) if sqe is None else sqe
+    return mcv_param_map(d[0], d[1], abs_scatterer, g[0], g[1], q[0], q[1],
+                         -1 if mp is None else mp)
+
+
+def param_map_of(pm):
+    """mcv_param_map from the dict form the tests and the oracle use:
+    {"dos": (s, k) or None, "abs": s, "sig": (s, k) or None, "sqe": (s, k),
+    "mp": k}."""
+    return param_map(pm.get("dos"), pm.get("abs", -1), pm.get("sig"), pm.get("sqe"),
+                     pm.get("mp"))
 
 
 RECORD_DTYPE = np.dtype([

@@ -458,10 +458,9 @@ def crystal_config(N=100_000_000, seed=0):
     }
 
 
-def sqe_config(N=20_000, seed=0):
+def sqe_config(N=20_000, seed=0, nQ=100, nE=100):
     """Tabulated isotropic S(Q,E) in a plate (no measured workload uses it)."""
     rng = np.random.default_rng(7)
-    nQ, nE = 100, 100
     Q = (np.arange(nQ) + 0.5) * (12.0 / nQ)
     Ev = -10.0 + (np.arange(nE) + 0.5) * (60.0 / nE)
     S = np.exp(-((Ev[None, :] - 20.0 * np.sin(Q[:, None] / 4.0)) / 4.0) ** 2) + \

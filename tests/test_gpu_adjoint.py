@@ -59,38 +59,50 @@ def test_zero_kernel(torch_cuda):
         mcv.check(mcv.lib().mcv_zero(None, 5, None))
 
 
-def _check_adjoint(torch, oracle_lib, make, PMx, N):
+# Per entry j the GPU gradient may differ from the oracle's forward mode by
+# REL * sum_p |g_p v_p dlogw_pj| (binary32 weights and carries against
+# binary64; the packet contract allows 1e-5 cond + wsens relative per
+# weight) plus twice the same sum over near-decision packets (whose
+# discrete outcome may differ).
+REL = 2e-4
+
+
+def _check_adjoint(torch, oracle_lib, make, PMx, N, target=None):
     from paper_1504_02776_amd import mcv
     cfg = make()
-    print(f"[adjoint] {cfg['name']}: oracle forward-mode N={N}", flush=True)
+    print(f"[adjoint] {cfg['name']}: oracle forward-mode N={N} {PMx}", flush=True)
     I0, _, _, _ = oracle_lib.run(cfg, n=N, records=False)
-    tgt = _target(oracle_lib, make, N)
-    wgt = 1.0 / (tgt + 1e-3 * tgt.mean())
+    tgt = _target(oracle_lib, make, N) if target is None else target(N)
+    wgt = 1.0 / (tgt + 1e-3 * tgt.mean() + 1e-12)
     dLdI = 2.0 * wgt * (I0 - tgt)
-    g_o = oracle_lib.gradient(cfg, PMx, dLdI, n=N)
+    g_o, g_abs, g_flag = oracle_lib.gradient(cfg, PMx, dLdI, n=N, bounds=True)
     plan = mcv.Plan(cfg)
-    pm = mcv.param_map(PMx["dos"], PMx["abs"], PMx["sig"])
+    pm = mcv.param_map_of(PMx)
+    assert plan.nparams(pm) == len(g_o)
     g = torch.zeros(plan.nparams(pm), dtype=torch.float64, device="cuda")
     print("[adjoint] GPU adjoint", flush=True)
     plan.adjoint(pm, torch.from_numpy(dLdI).cuda(), g, n=N)
     torch.cuda.synchronize()
     g_g = g.cpu().numpy()
-    scale = np.abs(g_o).max()
     err = np.abs(g_g - g_o)
+    allow = REL * g_abs + 2.0 * g_flag + 1e-12 * np.abs(g_o).max()
+    ratio = err / np.maximum(g_abs, 1e-300)
     print(f"[adjoint] sigma_abs gpu={g_g[-2]:.9g} oracle={g_o[-2]:.9g}; sigma gpu={g_g[-1]:.9g} "
-          f"oracle={g_o[-1]:.9g}; max |err|/max|g| over DOS = {err[:-2].max() / scale:.3g}",
-          flush=True)
-    assert g_g[-2] == pytest.approx(g_o[-2], rel=1e-3)
-    assert g_g[-1] == pytest.approx(g_o[-1], rel=1e-3)
-    assert np.all(err[:-2] <= 1e-3 * np.abs(g_o[:-2]) + 1e-3 * scale)
-    # the dense Debye-Waller/normalisation terms reach bins that no packet drew
-    assert np.count_nonzero(g_g[:-2]) == len(g_g) - 2
+          f"oracle={g_o[-1]:.9g}; max |err|/sum|terms| = {ratio.max():.3g} "
+          f"(entry {int(ratio.argmax())}); max |err|/allowance = {(err / allow).max():.3g}; "
+          f"max |err|/max|g| = {err.max() / np.abs(g_o).max():.3g}", flush=True)
+    bad = err > allow
+    assert not bad.any(), (f"{int(bad.sum())} entries off, worst j={int(np.argmax(err / allow))}: "
+                           f"gpu={g_g[np.argmax(err / allow)]} oracle={g_o[np.argmax(err / allow)]}")
+    return g_g, g_o
 
 
 def test_adjoint_matches_oracle_forward_mode(torch_cuda, oracle_lib):
     """Same histories, same seed: the HIP adjoint (reverse accumulation over
     re-traced paths) equals the oracle's dense forward-mode gradient."""
-    _check_adjoint(torch_cuda, oracle_lib, W.powder_config, PM, 3000)
+    g_g, _ = _check_adjoint(torch_cuda, oracle_lib, W.powder_config, PM, 3000)
+    # the dense Debye-Waller/normalisation terms reach bins that no packet drew
+    assert np.count_nonzero(g_g[:-2]) == len(g_g) - 2
 
 
 def test_adjoint_two_scatterers(torch_cuda, oracle_lib):
@@ -100,6 +112,65 @@ def test_adjoint_two_scatterers(torch_cuda, oracle_lib):
     is taken on the can."""
     _check_adjoint(torch_cuda, oracle_lib, W.powder_in_can_config,
                    {"dos": (0, 1), "abs": 1, "sig": (0, 1)}, 3000)
+
+
+def _sqe_target(make):
+    def t(N):
+        c = W.with_n(make(), N)
+        k = c["scatterers"][0]["kernels"][0]
+        k["S"] = np.asarray(k["S"]) * 1.05
+        from oracle import oracle as O
+        return O.run(c, seed=1, records=False)[0]
+    return t
+
+
+def test_adjoint_sqe_grid(torch_cuda, oracle_lib):
+    """Gradient with respect to the 100 x 100 cells of a tabulated S(Q,E)
+    grid (Sec. 2.4.2), its scatterer's sigma_abs and the incoherent kernel's
+    sigma; the cell partials live in LDS."""
+    make = W.sqe_config
+    g_g, g_o = _check_adjoint(torch_cuda, oracle_lib, make,
+                              {"sqe": (0, 0), "abs": 0, "sig": (0, 1)}, 4000,
+                              target=_sqe_target(make))
+    assert np.count_nonzero(g_o[:-2]) > 1000
+
+
+def test_adjoint_sqe_grid_global_partials(torch_cuda, oracle_lib):
+    """A 200 x 150 grid: 30 000 cell partials do not fit in LDS beside the
+    grid itself, so cell terms go to global binary64 atomics."""
+    make = lambda: W.sqe_config(nQ=200, nE=150)  # noqa: E731
+    _check_adjoint(torch_cuda, oracle_lib, make, {"sqe": (0, 0), "abs": -1, "sig": None}, 3000,
+                   target=_sqe_target(make))
+
+
+def test_adjoint_multiphonon_tied_dos(torch_cuda, oracle_lib):
+    """The DOS as read by the one-phonon and the multi-phonon kernel (orders
+    2..4, A_1 and S_n from the same DOS): the multi-phonon draws' phonon bins
+    are replayed from their Philox words and carried with the packet."""
+    def target(N):
+        c = W.with_n(W.powder_mp_config(), N)
+        shifted = W.powder_config(dos_shift=1.05)["scatterers"][0]["kernels"][1]["dos"]
+        for k in c["scatterers"][0]["kernels"]:
+            if k["type"] in ("phonon", "multiphonon"):
+                k["dos"] = shifted
+        return oracle_lib.run(c, seed=1, records=False)[0]
+    _check_adjoint(torch_cuda, oracle_lib, W.powder_mp_config,
+                   {"dos": (0, 1), "mp": 2, "abs": 0, "sig": (0, 2)}, 3000, target=target)
+
+
+def test_adjoint_map_validation(torch_cuda):
+    from paper_1504_02776_amd import mcv
+    plan = mcv.Plan(W.powder_mp_config())
+    # a tie to a kernel that is not multi-phonon, a DOS that is not one-phonon
+    for bad in ({"dos": (0, 1), "mp": 0}, {"dos": (0, 2)}, {"sqe": (0, 1)},
+                {"dos": None, "mp": 2}):
+        with pytest.raises(mcv.MCVError):
+            plan.nparams(mcv.param_map_of(bad))
+    # 3 orders x 4 phonons fit the 12 carried indices; 4 orders would not
+    c = dict(W.powder_mp_config(), K=4)
+    with pytest.raises(mcv.MCVError):
+        mcv.Plan(c).nparams(mcv.param_map_of({"dos": (0, 1), "mp": 2}))
+    assert plan.nparams(mcv.param_map_of({"dos": (0, 1), "mp": 2})) == 502
 
 
 def test_autograd_backward_is_the_adjoint(torch_cuda):
