@@ -414,6 +414,20 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
                        uint64_t first, uint64_t n, const double* dL_dI, double* grad,
                        void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): mcv_adjoint with
+ * its binary64 workspace in static device memory of the library (32768
+ * values = 256 KiB per device, held until the process ends) instead of
+ * plan-owned memory; no allocation, no host-to-device copy.  Same arguments,
+ * kernels and result as mcv_adjoint.  The caller still provides dL_dI and
+ * grad.  Every call on one device shares that device's workspace, and each
+ * call re-initialises it: calls that overlap on one device (other streams,
+ * other threads) race.  Errors as mcv_adjoint, and MCV_ECAPACITY when 4 + 2
+ * nb + nc (nb DOS bins, nc S(Q,E) cells of the map) exceeds 32768. */
+mcv_status mcv_adjoint_noalloc(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam,
+                               uint64_t seed, uint64_t first, uint64_t n, const double* dL_dI,
+                               double* grad, void* stream);
+
 /* Sets n binary64 values of device memory to zero: the histogram that an
  * accumulation of recorded probabilities starts from (Sec. 3, the detector
  * result is the sum of the recorded packets' probabilities; mcv_run adds).

@@ -24,6 +24,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "mcv_internal.h"
 
 namespace mcv {
@@ -81,6 +84,40 @@ __global__ void adjoint_finalize(double* __restrict__ grad, const double* __rest
 }
 
 }  // namespace dev
+
+// The workspace of mcv_adjoint_noalloc, for callers that cannot allocate:
+// one copy per device, held until the process ends; every such call on a
+// device uses it (concurrent calls on one device race).  In host code the
+// name `scratch` stands for the host-side shadow, not the device address:
+// the address of each device's copy is taken once with hipGetSymbolAddress
+// and only that pointer is handed to kernels.
+static __device__ __align__(256) double scratch[kNoAllocWorkDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;  // per device, null until set up
+}  // namespace
+
+// Set-up, with `device` current (called by plan creation): records the
+// address of that device's copy of the workspace.
+hipError_t adjoint_scratch_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if (g_scratch_ptr.size() <= (size_t)device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return hipSuccess;
+}
+
+// the device address of the workspace on `device`, or null before set-up
+double* adjoint_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || (size_t)device >= g_scratch_ptr.size()) return nullptr;
+  return g_scratch_ptr[device];
+}
 
 hipError_t launch_adjoint_prepare(const double* theta, int nb, double de, double kT, double h2m,
                                   const double* cells, int nc, double* ws, hipStream_t stream) {

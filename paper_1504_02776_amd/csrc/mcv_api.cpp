@@ -32,6 +32,8 @@ hipError_t launch_adjoint_prepare(const double* theta, int nb, double de, double
                                   const double* cells, int nc, double* ws, hipStream_t stream);
 hipError_t launch_adjoint_finalize(double* grad, const double* ws, int nb, int nc,
                                    hipStream_t stream);
+hipError_t adjoint_scratch_setup(int device);
+double* adjoint_scratch(int device);
 hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
                             double* dLdI, double* loss, int grid, hipStream_t stream);
 hipError_t launch_fill_zero(double* p, uint64_t n, int grid, hipStream_t stream);
@@ -754,6 +756,12 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     delete p;
     return hipfail(e, "hipFuncSetAttribute");
   }
+  // the static workspace of mcv_adjoint_noalloc on this device
+  if ((e = adjoint_scratch_setup(device)) != hipSuccess) {
+    (void)hipSetDevice(cur);
+    delete p;
+    return hipfail(e, "hipGetSymbolAddress");
+  }
   if ((e = hipMalloc(&p->d_plan, sizeof(DevPlan))) != hipSuccess ||
       (e = hipMalloc(&p->d_tables, T.size() * sizeof(float))) != hipSuccess ||
       (e = hipMalloc(&p->d_pixgeo, G.size() * sizeof(float))) != hipSuccess) {
@@ -1201,6 +1209,30 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
   }
   if (st == MCV_OK)
     st = adjoint_launch(p, pm, A, B, seed, first, n, dL_dI, grad, p->adj.ws, (hipStream_t)stream);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  return st;
+}
+
+mcv_status mcv_adjoint_noalloc(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam,
+                               uint64_t seed, uint64_t first, uint64_t n, const double* dL_dI,
+                               double* grad, void* stream) {
+  if (!p) return fail(MCV_EINVAL, "null plan");
+  AdjSetup A;
+  mcv_status st = check_param_map(p, pm, &A);
+  if (st != MCV_OK) return st;
+  if (!dL_dI || !grad) return fail(MCV_EINVAL, "null dL_dI or grad");
+  if (4 + 2 * (int64_t)A.nb + A.nc > kNoAllocWorkDoubles)
+    return fail(MCV_ECAPACITY, "mcv_adjoint_noalloc: 4 + 2 DOS bins + S(Q,E) cells exceeds the "
+                               "32768 values of its static workspace");
+  DevBeam B;
+  if ((st = make_beam(p, beam, &B)) != MCV_OK) return st;
+  if ((st = check_ids(B, first, n)) != MCV_OK) return st;
+  double* ws = adjoint_scratch(p->device);
+  if (!ws) return fail(MCV_EHIP, "static adjoint workspace not set up on this device");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  st = adjoint_launch(p, pm, A, B, seed, first, n, dL_dI, grad, ws, (hipStream_t)stream);
   if (cur != p->device) (void)hipSetDevice(cur);
   return st;
 }

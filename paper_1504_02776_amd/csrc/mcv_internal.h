@@ -149,6 +149,9 @@ constexpr int kAdjFields = 10;     // extra words per stacked packet in adjoint 
 constexpr int kAdjMaxOrders = 4;
 constexpr int kAdjMaxSparse = 12;  // table indices a packet carries (16 bits each)
 constexpr int kAdjMaxTable = 65535;
+// binary64 values of the adjoint workspace that mcv_adjoint_noalloc keeps in
+// static device memory (4 + 2 nb + nc must fit): 256 KiB per device
+constexpr int kNoAllocWorkDoubles = 32768;
 // the adjoint-partials argument of the LDS size computation for launches
 // that are not adjoint
 constexpr int kLdsNoAdjoint = -1;

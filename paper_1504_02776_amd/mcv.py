@@ -132,7 +132,7 @@ EXPORTS = ["mcv_assembly_create", "mcv_assembly_add", "mcv_assembly_destroy",
            "mcv_run", "mcv_trace", "mcv_sync", "mcv_last_error", "mcv_abi_version",
            "mcv_adjoint_nparams", "mcv_adjoint", "mcv_loss_grad", "mcv_batch_create",
            "mcv_batch_run", "mcv_batch_destroy", "mcv_autotune", "mcv_run_events",
-           "mcv_reduce_qe", "mcv_reduce_events_qe", "mcv_zero"]
+           "mcv_reduce_qe", "mcv_reduce_events_qe", "mcv_zero", "mcv_adjoint_noalloc"]
 
 _lib = None
 
@@ -165,6 +165,8 @@ def lib():
             "mcv_sync": [P],
             "mcv_adjoint": [P, C.POINTER(mcv_param_map), C.POINTER(mcv_beam), C.c_uint64,
                             C.c_uint64, C.c_uint64, P, P, P],
+            "mcv_adjoint_noalloc": [P, C.POINTER(mcv_param_map), C.POINTER(mcv_beam),
+                                    C.c_uint64, C.c_uint64, C.c_uint64, P, P, P],
             "mcv_loss_grad": [P, P, P, C.c_int64, P, P, P],
             "mcv_zero": [P, C.c_int64, P],
             "mcv_run_events": [P, C.POINTER(mcv_beam), C.c_uint64, C.c_uint64, C.c_uint64, P,
@@ -443,6 +445,21 @@ class Plan:
         check(lib().mcv_adjoint(self.h, C.byref(pm), C.byref(b), seed, first, n,
                                 C.c_void_p(dLdI.data_ptr()), C.c_void_p(grad.data_ptr()),
                                 _stream_ptr(stream)))
+
+    def adjoint_noalloc(self, pm, dLdI, grad, n=None, first=0, seed=None, stream=None,
+                        beam=None):
+        """As adjoint(), through mcv_adjoint_noalloc (static device workspace;
+        the library allocates nothing)."""
+        n = self.cfg["N"] if n is None else n
+        seed = self.cfg["seed"] if seed is None else seed
+        b = self.beam if beam is None else make_beam(beam, self.device)
+        self._check_hist(dLdI)
+        import torch
+        if grad.dtype != torch.float64 or not grad.is_cuda or grad.numel() < self.nparams(pm):
+            raise ValueError("grad must be a float64 CUDA tensor of nparams entries")
+        check(lib().mcv_adjoint_noalloc(self.h, C.byref(pm), C.byref(b), seed, first, n,
+                                        C.c_void_p(dLdI.data_ptr()), C.c_void_p(grad.data_ptr()),
+                                        _stream_ptr(stream)))
 
     def _check_hist(self, h):
         import torch
