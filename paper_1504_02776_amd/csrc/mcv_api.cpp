@@ -27,7 +27,7 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                             int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
                             DevEvent* ev, uint64_t ev_cap, unsigned long long* n_ev,
-                            const AdjArgs* adj, hipStream_t stream);
+                            const AdjArgs* adj, float* gstack, hipStream_t stream);
 hipError_t launch_adjoint_prepare(const double* theta, int nb, double de, double kT, double h2m,
                                   const double* cells, int nc, double* ws, hipStream_t stream);
 hipError_t launch_adjoint_finalize(double* grad, const double* ws, int nb, int nc,
@@ -39,6 +39,7 @@ hipError_t launch_loss_grad(const double* I, const double* T, const double* w, i
 hipError_t launch_fill_zero(double* p, uint64_t n, int grid, hipStream_t stream);
 size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_ntab, int hot_n);
 int transport_dq_entries(const DevPlan& P);
+int batch_dq_entries(const DevPlan& P);
 size_t transport_dq_bytes(int block, int entries);
 size_t transport_static_lds();
 int transport_waves_per_eu(int nscat, int smax);
@@ -319,6 +320,9 @@ struct mcv_plan_s {
   // grids) in device memory, at raw_off[s][k] (-1: none)
   double* d_raw = nullptr;
   int64_t raw_off[kMaxScat][kMaxKern];
+  // per-lane packet stacks of the transport launches in device memory
+  float* d_stack = nullptr;
+  size_t stack_floats = 0;
   DevPlan* d_plan = nullptr;
   float* d_tables = nullptr;
   float* d_pixgeo = nullptr;     // per pixel id: |r_p|, cos(2theta) (reduction)
@@ -516,6 +520,8 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     }
     for (int i = 0; i < 3; ++i) S.pos[i] = (float)sc.shape.pos[i];
     for (int i = 0; i < 9; ++i) S.rot[i] = (float)sc.shape.rot[i];
+    S.ident = 1;
+    for (int i = 0; i < 9; ++i) S.ident &= S.rot[i] == (i % 4 == 0 ? 1.0f : 0.0f);
     S.mu_abs2200 = (float)(100.0 * sc.mat.n_per_A3 * sc.mat.sigma_abs_b * 2200.0);
     S.n100 = (float)(100.0 * sc.mat.n_per_A3);
     // Debye-Waller coefficient from the scatterer's phonon DOS:
@@ -714,11 +720,12 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
 
   // LDS: plan + tables + bin cache + per-lane stack + detection queues
   const int dq_n = transport_dq_entries(P);
-  size_t lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, kLdsNoAdjoint, kHotMin) +
+  const int stack_lds = 0;  // transport launches keep their packet stacks in device memory
+  size_t lds_dyn = transport_lds_bytes(P.n_tables, stack_lds, block, kLdsNoAdjoint, kHotMin) +
                    transport_dq_bytes(block, dq_n);
   while (lds_dyn + transport_static_lds() > 160 * 1024 && block > 64) {
     block -= 64;
-    lds_dyn = transport_lds_bytes(P.n_tables, P.stack_cap, block, kLdsNoAdjoint, kHotMin) +
+    lds_dyn = transport_lds_bytes(P.n_tables, stack_lds, block, kLdsNoAdjoint, kHotMin) +
               transport_dq_bytes(block, dq_n);
   }
   if (lds_dyn + transport_static_lds() > 160 * 1024) {
@@ -726,7 +733,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     return fail(MCV_EUNSUPPORTED, "tables and packet stack exceed the 160 KiB of LDS");
   }
   P.hot_n = hot_slots(transport_static_lds() +
-                          transport_lds_bytes(P.n_tables, P.stack_cap, block, kLdsNoAdjoint, 0) +
+                          transport_lds_bytes(P.n_tables, stack_lds, block, kLdsNoAdjoint, 0) +
                           transport_dq_bytes(block, dq_n),
                       block, transport_waves_per_eu(P.nscat, P.smax));
   P.hot_all = mcv_detector_nbins(d) <= kHotAllBins ? 1 : 0;
@@ -825,6 +832,17 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
       }
     }
   }
+  if (P.stack_cap > 0) {
+    // stacks of every wave of the largest grid (grid_shape: cus x 4 x
+    // waves_per_simd x 2 waves), adjoint fields included
+    const size_t waves = (size_t)p->cus * 4 * p->waves_per_simd * 2 + (size_t)block / 64;
+    p->stack_floats = waves * 64 * (size_t)P.stack_cap * (kFields + kAdjFields);
+    if ((e = hipMalloc(&p->d_stack, p->stack_floats * sizeof(float))) != hipSuccess) {
+      (void)hipSetDevice(cur);
+      mcv_plan_destroy(p);
+      return hipfail(e, "packet stack allocation");
+    }
+  }
   (void)hipSetDevice(cur);
   *out = p;
   return MCV_OK;
@@ -841,6 +859,7 @@ mcv_status mcv_plan_destroy(mcv_plan p) {
   for (float* x : p->d_grids) (void)hipFree(x);
   if (p->adj.ws) (void)hipFree(p->adj.ws);
   if (p->d_raw) (void)hipFree(p->d_raw);
+  if (p->d_stack) (void)hipFree(p->d_stack);
   (void)hipSetDevice(cur);
   delete p;
   return MCV_OK;
@@ -915,9 +934,12 @@ mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t firs
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
+  if (p->d_stack && grid * p->block * (size_t)p->host.stack_cap * kFields > p->stack_floats)
+    return fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
   hipError_t e = launch_transport(p->d_plan, p->host, p->d_tables, B,
                                   seed, first, n, (int)grid, p->block, per_wave, hist, hist_w2,
-                                  rec, cap, n_out, ev, ev_cap, n_ev, nullptr, (hipStream_t)stream);
+                                  rec, cap, n_out, ev, ev_cap, n_ev, nullptr, p->d_stack,
+                                  (hipStream_t)stream);
   if (cur != p->device) (void)hipSetDevice(cur);
   if (e != hipSuccess) return hipfail(e, "transport launch");
   return MCV_OK;
@@ -1126,7 +1148,7 @@ mcv_status check_param_map(mcv_plan p, const mcv_param_map* pm, AdjSetup* out) {
   // workgroup of at least 128 lanes, otherwise global atomics per entry
   const size_t lim = (size_t)160 * 1024 - transport_static_lds();
   auto lds = [&](int block, int ntab) {
-    return transport_lds_bytes(p->host.n_tables, p->host.stack_cap, block, ntab, 0);
+    return transport_lds_bytes(p->host.n_tables, 0, block, ntab, 0);
   };
   int block = p->block;
   while (block > 128 && lds(block, A.nb + A.nc) > lim) block -= 64;
@@ -1164,9 +1186,12 @@ mcv_status adjoint_launch(mcv_plan p, const mcv_param_map* pm, const AdjSetup& A
     AA.ws = ws;
     uint64_t grid, per_wave;
     grid_shape(p, n, A.block, &grid, &per_wave);
+    if (p->d_stack &&
+        grid * A.block * (size_t)p->host.stack_cap * (kFields + kAdjFields) > p->stack_floats)
+      return fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
     e = launch_transport(p->d_plan, p->host, p->d_tables, B, seed, first, n, (int)grid, A.block,
                          per_wave, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, &AA,
-                         stream);
+                         p->d_stack, stream);
   }
   if (e == hipSuccess) e = launch_adjoint_finalize(grad, ws, A.nb, A.nc, stream);
   if (e != hipSuccess) return hipfail(e, "adjoint launch");
@@ -1349,7 +1374,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
     hitems[i].hist = it.hist;
     n_tables_max = std::max(n_tables_max, it.plan->host.n_tables);
     stack_max = std::max(stack_max, it.plan->host.stack_cap);
-    dq_max = std::max(dq_max, transport_dq_entries(it.plan->host));
+    dq_max = std::max(dq_max, batch_dq_entries(it.plan->host));
     const double c = history_cost(it.plan);
     for (uint64_t f = 0; f < it.n; f += chunk) {
       BatchChunk ch;

@@ -63,6 +63,8 @@ struct DevKernel {
 struct DevScat {
   int32_t shape;
   int32_t nk;
+  int32_t ident;     // 1: rot is the identity (the shape frame is the lab frame shifted)
+  int32_t pad;
   float h[3];        // BOX: half lengths; CYLINDER: r, h/2, -; ANNULUS: r_in, r_out, h/2
   float pos[3];
   float rot[9];      // local -> lab, row major

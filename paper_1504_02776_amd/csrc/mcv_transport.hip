@@ -34,15 +34,17 @@
 
 #include "mcv_internal.h"
 
-// resident waves per SIMD the transport kernels are compiled for (register
-// budget 512 / N per lane): the single-scatterer, single-interval kernels
-// (short live ranges) run best with more waves in flight, the others with
-// fewer waves and no spills
+// resident waves per SIMD the kernels are compiled for (register budget
+// 512 / N per lane).  The transport kernels keep their packet stacks in
+// device memory, so LDS does not cap their occupancy: 4 waves per SIMD
+// (measured on the crystal in its can, 1e8 histories: 4 waves 111 ms, 5
+// waves 150 ms, 6 waves 173 ms, with the stacks in LDS and 2 waves 151 ms).
+// The persistent batch kernel keeps its stacks in LDS and runs 2.
 #ifndef MCV_WAVES_PER_EU
-#define MCV_WAVES_PER_EU 2
+#define MCV_WAVES_PER_EU 4
 #endif
-#ifndef MCV_WAVES_PER_EU_SIMPLE
-#define MCV_WAVES_PER_EU_SIMPLE 4
+#ifndef MCV_BATCH_WAVES_PER_EU
+#define MCV_BATCH_WAVES_PER_EU 2
 #endif
 
 namespace mcv {
@@ -147,14 +149,10 @@ __device__ __forceinline__ bool radial(float qx, float qz, float dx, float dz, f
   return true;
 }
 
-// finite cylinder (radial x slab in y); which: 0 both ends radial, 1 both
-// slab, 2 mixed
-__device__ __forceinline__ bool cyl(float qx, float qy, float qz, float dx, float dy, float dz,
-                                    float r, float hh, Iv& iv, float& sq, float& a, int& lo_rad,
-                                    int& hi_rad) {
-  float cr, hr, cs, hs;
-  if (!radial(qx, qz, dx, dz, r, cr, hr, sq, a)) return false;
-  if (!slab(qy, dy, hh, cs, hs)) return false;
+// finite cylinder (radial x slab in y) from its radial and axial parts;
+// lo_rad / hi_rad: the interval starts / ends on the radial surface
+__device__ __forceinline__ bool cyl_of(float cr, float hr, float cs, float hs, Iv& iv, int& lo_rad,
+                                       int& hi_rad) {
   const float l1 = cr - hr, l2 = cs - hs, h1 = cr + hr, h2 = cs + hs;
   lo_rad = l1 >= l2;
   hi_rad = h1 <= h2;
@@ -167,17 +165,43 @@ __device__ __forceinline__ bool cyl(float qx, float qy, float qz, float dx, floa
   return true;
 }
 
+// finite cylinder (radial x slab in y)
+__device__ __forceinline__ bool cyl(float qx, float qy, float qz, float dx, float dy, float dz,
+                                    float r, float hh, Iv& iv, float& sq, float& a, int& lo_rad,
+                                    int& hi_rad) {
+  float cr, hr, cs, hs;
+  if (!radial(qx, qz, dx, dz, r, cr, hr, sq, a)) return false;
+  if (!slab(qy, dy, hh, cs, hs)) return false;
+  return cyl_of(cr, hr, cs, hs, iv, lo_rad, hi_rad);
+}
+
+// the shape frame: local = R^T (p - pos); identity rotations (flagged in the
+// plan) skip the products, which give the same values
+__device__ __forceinline__ void to_local(const DevScat& S, const Pk& P, float& qx, float& qy,
+                                         float& qz, float& dx, float& dy, float& dz) {
+  const float rx = P.px - S.pos[0], ry = P.py - S.pos[1], rz = P.pz - S.pos[2];
+  if (S.ident) {
+    qx = rx;
+    qy = ry;
+    qz = rz;
+    dx = P.dx;
+    dy = P.dy;
+    dz = P.dz;
+    return;
+  }
+  const float* R = S.rot;
+  qx = R[0] * rx + R[3] * ry + R[6] * rz;
+  qy = R[1] * rx + R[4] * ry + R[7] * rz;
+  qz = R[2] * rx + R[5] * ry + R[8] * rz;
+  dx = R[0] * P.dx + R[3] * P.dy + R[6] * P.dz;
+  dy = R[1] * P.dx + R[4] * P.dy + R[7] * P.dz;
+  dz = R[2] * P.dx + R[5] * P.dy + R[8] * P.dz;
+}
+
 // intervals of scatterer S along p + s d (lab); returns count (0..2)
 __device__ __forceinline__ int shape_iv(const DevScat& S, const Pk& P, Iv& i0, Iv& i1) {
-  const float rx = P.px - S.pos[0], ry = P.py - S.pos[1], rz = P.pz - S.pos[2];
-  const float* R = S.rot;
-  // local = R^T (p - pos)
-  const float qx = R[0] * rx + R[3] * ry + R[6] * rz;
-  const float qy = R[1] * rx + R[4] * ry + R[7] * rz;
-  const float qz = R[2] * rx + R[5] * ry + R[8] * rz;
-  const float dx = R[0] * P.dx + R[3] * P.dy + R[6] * P.dz;
-  const float dy = R[1] * P.dx + R[4] * P.dy + R[7] * P.dz;
-  const float dz = R[2] * P.dx + R[5] * P.dy + R[8] * P.dz;
+  float qx, qy, qz, dx, dy, dz;
+  to_local(S, P, qx, qy, qz, dx, dy, dz);
   if (S.shape == SHAPE_BOX) {
     float c0, h0, c1, h1, c2, h2;
     if (!slab(qx, dx, S.h[0], c0, h0) || !slab(qy, dy, S.h[1], c1, h1) ||
@@ -200,15 +224,34 @@ __device__ __forceinline__ int shape_iv(const DevScat& S, const Pk& P, Iv& i0, I
   int lr_o, hr_o, lr_i, hr_i;
   const float r_out = S.shape == SHAPE_CYLINDER ? S.h[0] : S.h[1];
   const float hh = S.shape == SHAPE_CYLINDER ? S.h[1] : S.h[2];
+  // radial and axial parts of the outer cylinder; the inner one of an
+  // annulus shares the axis, the caps and every term but the radius
+  float cr, hr, cs, hs;
+  if (!radial(qx, qz, dx, dz, r_out, cr, hr, sq_o, a)) return 0;
+  if (!slab(qy, dy, hh, cs, hs)) return 0;
   Iv o;
-  if (!cyl(qx, qy, qz, dx, dy, dz, r_out, hh, o, sq_o, a, lr_o, hr_o)) return 0;
+  if (!cyl_of(cr, hr, cs, hs, o, lr_o, hr_o)) return 0;
   o.entry = lr_o ? ENTRY_OUTER : ENTRY_CAP;
   if (S.shape == SHAPE_CYLINDER) {
     i0 = o;
     return 1;
   }
   Iv in;
-  const bool hit_in = cyl(qx, qy, qz, dx, dy, dz, S.h[0], hh, in, sq_i, a, lr_i, hr_i);
+  bool hit_in;
+  {
+    const float r_in = S.h[0];
+    if (a == 0.0f) {
+      hit_in = qx * qx + qz * qz <= r_in * r_in;
+      sq_i = 0.0f;
+      if (hit_in) hit_in = cyl_of(0.0f, kBig, cs, hs, in, lr_i, hr_i);
+    } else {
+      const float xr = qx * dz - qz * dx;
+      const float disc = r_in * r_in * a - xr * xr;
+      hit_in = disc > 0.0f;
+      sq_i = hit_in ? sqrtf(disc) : 0.0f;
+      if (hit_in) hit_in = cyl_of(cr, sq_i / a, cs, hs, in, lr_i, hr_i);
+    }
+  }
   if (!hit_in || in.hi <= o.lo || in.lo >= o.hi) {
     i0 = o;
     return 1;
@@ -240,12 +283,25 @@ __device__ __forceinline__ int shape_iv(const DevScat& S, const Pk& P, Iv& i0, I
 // birth point of its children, which grazing exits amplify.
 __device__ __forceinline__ void snap_entry(const DevScat& S, int code, float dx, float dy,
                                            float dz, float& x, float& y, float& z) {
+  if (code == ENTRY_NONE) return;
   const float* R = S.rot;
   const float rx = x - S.pos[0], ry = y - S.pos[1], rz = z - S.pos[2];
-  float q[3] = {R[0] * rx + R[3] * ry + R[6] * rz, R[1] * rx + R[4] * ry + R[7] * rz,
-                R[2] * rx + R[5] * ry + R[8] * rz};
-  const float dl[3] = {R[0] * dx + R[3] * dy + R[6] * dz, R[1] * dx + R[4] * dy + R[7] * dz,
-                       R[2] * dx + R[5] * dy + R[8] * dz};
+  float q[3], dl[3];
+  if (S.ident) {
+    q[0] = rx;
+    q[1] = ry;
+    q[2] = rz;
+    dl[0] = dx;
+    dl[1] = dy;
+    dl[2] = dz;
+  } else {
+    q[0] = R[0] * rx + R[3] * ry + R[6] * rz;
+    q[1] = R[1] * rx + R[4] * ry + R[7] * rz;
+    q[2] = R[2] * rx + R[5] * ry + R[8] * rz;
+    dl[0] = R[0] * dx + R[3] * dy + R[6] * dz;
+    dl[1] = R[1] * dx + R[4] * dy + R[7] * dz;
+    dl[2] = R[2] * dx + R[5] * dy + R[8] * dz;
+  }
   if (code >= ENTRY_BOX_X && code <= ENTRY_BOX_X + 2) {
     const int a = code - ENTRY_BOX_X;
 #pragma unroll
@@ -260,6 +316,12 @@ __device__ __forceinline__ void snap_entry(const DevScat& S, int code, float dx,
     const float hh = S.shape == SHAPE_CYLINDER ? S.h[1] : S.h[2];
     q[1] = dl[1] > 0.0f ? -hh : hh;
   } else {
+    return;
+  }
+  if (S.ident) {
+    x = S.pos[0] + q[0];
+    y = S.pos[1] + q[1];
+    z = S.pos[2] + q[2];
     return;
   }
   x = S.pos[0] + R[0] * q[0] + R[1] * q[1] + R[2] * q[2];
@@ -1375,6 +1437,7 @@ struct Sinks {
   int ev_hot_n;              // bin cache slots of event launches
   DevEvent* stage;           // this wave's LDS event stage (set in the kernel)
   volatile int* stage_n;     // events in the stage
+  float* gstack;             // per-lane packet stacks in device memory (plan-owned)
 };
 
 // Event mode: every wave stages its events in LDS (kEvStage entries) and
@@ -1597,12 +1660,14 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
 // lanes holding such packets; instead they are appended to a per-wave LDS
 // queue of Q packets, which the wave records together (one packet per lane)
 // when the next D phase would overflow it, and at the end.  The walk loop
-// does the same with its recording step (Q = 32 there, beside the packet
-// stacks).  Layout: [field][entry], 12 fields (position, direction, speed,
-// time, weight, lineage, history id low and high words).
+// does the same with its recording step (Q = 64 as well; 32 in the batch
+// kernel, whose packet stacks share the LDS).  Layout: [field][entry], 12
+// fields (position, direction, speed, time, weight, lineage, history id low
+// and high words).
 constexpr int kDqFields = 12;
-constexpr int kDqPhased = 64;  // entries per wave, phased loop
-constexpr int kDqWalk = 32;    // entries per wave, walk loop
+constexpr int kDqPhased = 64;     // entries per wave, phased loop
+constexpr int kDqWalk = 64;       // entries per wave, walk loop
+constexpr int kDqBatchWalk = 32;  // walk loop of the batch kernel (beside its LDS stacks)
 
 template <int Q>
 __device__ __forceinline__ void dq_put(float* q, int slot, const Pk& P, uint64_t hid) {
@@ -1803,7 +1868,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
                                            int nthreads, int tid, float* dq) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
   static_assert(!(DQ && ADJ), "the adjoint records its packets at once");
-  static_assert(DQ == 0 || DQ == kDqWalk, "walk-loop queue size");
+  static_assert(DQ == 0 || DQ == kDqWalk || DQ == kDqBatchWalk, "walk-loop queue size");
   constexpr bool DEFER = NSC > 1 || TWO || HEAVY;
   const uint64_t lt = lanemask_lt();
   Pk cur;
@@ -1931,8 +1996,7 @@ __device__ __forceinline__ void stage_plan(DevPlan& PL, float* dyn, const DevPla
 // dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
 // per workgroup.
 template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, int DQ = 0>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(
-    NSC == 1 && !TWO ? MCV_WAVES_PER_EU_SIMPLE : MCV_WAVES_PER_EU)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MCV_WAVES_PER_EU)))
 transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
           uint64_t seed, uint64_t first, uint64_t n, uint64_t per_wave, Sinks out, AdjArgs AA) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
@@ -1954,13 +2018,17 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   else
     hot_init(acc, hot_n, nthreads, tid);
   __syncthreads();
-  float* st = dyn + tab_words + acc_words;
+  // the workgroup's packet stacks in device memory ([slot][field][lane],
+  // consecutive lanes at consecutive addresses; a lane pushes only the
+  // second and later children of a flight)
+  constexpr int NFS = kFields + (ADJ ? kAdjFields : 0);
+  float* st = out.gstack + (size_t)blockIdx.x * PL.stack_cap * NFS * nthreads;
+  // LDS after the bin cache: the waves' detection queues, then their event
+  // stages
+  float* dqs = dyn + tab_words + acc_words;
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
   Sinks o = out;
-  // after the packet stacks: the waves' detection queues, then their event
-  // stages
-  float* dqs = st + (size_t)PL.stack_cap * kFields * nthreads;
   float* dq = dqs + (tid >> 6) * DQ * kDqFields;
   float* evs = dqs + (nthreads >> 6) * DQ * kDqFields;
   if (events) {
@@ -2002,7 +2070,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
 // workgroup re-stages plan and tables in LDS only when the simulation
 // changes; its waves split the chunk's ids.  The list is sorted by
 // estimated cost, longest first.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MCV_WAVES_PER_EU)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MCV_BATCH_WAVES_PER_EU)))
 batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restrict__ chunks,
                  uint32_t n_chunks, uint32_t* __restrict__ cursor, int hot_n, int dq_off) {
   __shared__ DevPlan PL;
@@ -2034,7 +2102,8 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const uint64_t per = (ch.count + nwaves - 1) / nwaves;
     const uint64_t b = ch.first + per * wid;
     const uint64_t e = ch.first + ch.count;
-    Sinks out = {it.hist, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr};
+    Sinks out = {it.hist, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr,
+                 nullptr};
     const uint64_t ee = b + per < e ? b + per : e;
     // the waves' detection queues sit behind the largest tables and stacks
     float* dq = dyn + dq_off;  // this wave's queue: dq + wid Q kDqFields
@@ -2043,7 +2112,7 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const bool two = PL.smax > PL.nscat;
 #define MCV_BATCH_TRACE(NSC_, TWO_, PH_, HV_)                                            \
   do {                                                                                     \
-    constexpr int Q_ = PH_ ? kDqPhased : kDqWalk;                                          \
+    constexpr int Q_ = PH_ ? kDqPhased : kDqBatchWalk;                                     \
     if (PL.det.type == DET_TUBES)                                                          \
       trace_range<MODE_RUN, NSC_, TWO_, PH_, HV_, Q_>(PL, tab, st, it.beam, it.seed,       \
                                                       it.id0, b, ee, out, AA, hot, hot_n,  \
@@ -2172,6 +2241,10 @@ int transport_dq_entries(const DevPlan& P) {
   if (P.det.type != DET_TUBES) return 0;
   return dev::use_phased(P.nscat, P.smax > P.nscat, P.K) ? dev::kDqPhased : dev::kDqWalk;
 }
+int batch_dq_entries(const DevPlan& P) {
+  if (P.det.type != DET_TUBES) return 0;
+  return dev::use_phased(P.nscat, P.smax > P.nscat, P.K) ? dev::kDqPhased : dev::kDqBatchWalk;
+}
 size_t transport_dq_bytes(int block, int entries) {
   return sizeof(float) * (size_t)entries * dev::kDqFields * (size_t)(block / 64);
 }
@@ -2247,16 +2320,17 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                             int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
                             DevEvent* ev, uint64_t ev_cap, unsigned long long* n_ev,
-                            const AdjArgs* adj, hipStream_t stream) {
+                            const AdjArgs* adj, float* gstack, hipStream_t stream) {
   AdjArgs AA = {};
   AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = AA.sqe_s = AA.sqe_k = AA.mp_k = -1;
   if (adj) AA = *adj;
-  dev::Sinks out = {hist, hist_w2, rec, cap, n_out, ev, ev_cap, n_ev, 0, nullptr, nullptr};
+  dev::Sinks out = {hist, hist_w2, rec, cap, n_out, ev, ev_cap, n_ev, 0, nullptr, nullptr, gstack};
   const int dq_n = adj ? 0 : transport_dq_entries(host_plan);
   const bool dq = dq_n > 0;
   const size_t qbytes = transport_dq_bytes(block, dq_n);
+  const int stack_lds = 0;  // the packet stacks live in device memory
   size_t lds =
-      transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block,
+      transport_lds_bytes(host_plan.n_tables, stack_lds, block,
                           adj ? (adj->sparse_lds ? adj->nb + adj->nc : 0) : kLdsNoAdjoint, host_plan.hot_n) +
       qbytes;
   if (ev) {
@@ -2264,11 +2338,11 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
     // if the cache can give it
     const size_t stages = sizeof(float) * (size_t)dev::kEvStageWords * (block / 64);
     int hot = host_plan.hot_n;
-    size_t need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, kLdsNoAdjoint, hot) +
+    size_t need = transport_lds_bytes(host_plan.n_tables, stack_lds, block, kLdsNoAdjoint, hot) +
                   qbytes + stages;
     while (hot > kHotMin && need > lds) {
       hot >>= 1;
-      need = transport_lds_bytes(host_plan.n_tables, host_plan.stack_cap, block, kLdsNoAdjoint, hot) +
+      need = transport_lds_bytes(host_plan.n_tables, stack_lds, block, kLdsNoAdjoint, hot) +
              qbytes + stages;
     }
     out.ev_hot_n = hot;
@@ -2333,11 +2407,9 @@ hipError_t launch_loss_grad(const double* I, const double* T, const double* w, i
 
 size_t transport_static_lds() { return sizeof(DevPlan); }
 
-// resident waves per SIMD the transport kernel of a plan is compiled for
-int transport_waves_per_eu(int nscat, int smax) {
-  return nscat <= 1 && smax <= nscat ? MCV_WAVES_PER_EU_SIMPLE : MCV_WAVES_PER_EU;
-}
-int batch_waves_per_eu() { return MCV_WAVES_PER_EU; }
+// resident waves per SIMD the transport kernels are compiled for
+int transport_waves_per_eu(int, int) { return MCV_WAVES_PER_EU; }
+int batch_waves_per_eu() { return MCV_BATCH_WAVES_PER_EU; }
 
 namespace {
 template <int MODE, bool HV, int QP, int QW>
