@@ -40,7 +40,7 @@ hipError_t launch_fill_zero(double* p, uint64_t n, int grid, hipStream_t stream)
 size_t transport_lds_bytes(int n_tables, int stack_cap, int block, int adj_ntab, int hot_n);
 int transport_dq_entries(const DevPlan& P);
 int batch_dq_entries(const DevPlan& P);
-size_t transport_dq_bytes(int block, int entries);
+size_t transport_dq_bytes(int block, int entries, bool adjoint);
 size_t transport_static_lds();
 int transport_waves_per_eu(int nscat, int smax);
 int batch_waves_per_eu();
@@ -722,11 +722,11 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   const int dq_n = transport_dq_entries(P);
   const int stack_lds = 0;  // transport launches keep their packet stacks in device memory
   size_t lds_dyn = transport_lds_bytes(P.n_tables, stack_lds, block, kLdsNoAdjoint, kHotMin) +
-                   transport_dq_bytes(block, dq_n);
+                   transport_dq_bytes(block, dq_n, false);
   while (lds_dyn + transport_static_lds() > 160 * 1024 && block > 64) {
     block -= 64;
     lds_dyn = transport_lds_bytes(P.n_tables, stack_lds, block, kLdsNoAdjoint, kHotMin) +
-              transport_dq_bytes(block, dq_n);
+              transport_dq_bytes(block, dq_n, false);
   }
   if (lds_dyn + transport_static_lds() > 160 * 1024) {
     delete p;
@@ -734,7 +734,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   }
   P.hot_n = hot_slots(transport_static_lds() +
                           transport_lds_bytes(P.n_tables, stack_lds, block, kLdsNoAdjoint, 0) +
-                          transport_dq_bytes(block, dq_n),
+                          transport_dq_bytes(block, dq_n, false),
                       block, transport_waves_per_eu(P.nscat, P.smax));
   P.hot_all = mcv_detector_nbins(d) <= kHotAllBins ? 1 : 0;
   P.heavy = 0;
@@ -1147,8 +1147,10 @@ mcv_status check_param_map(mcv_plan p, const mcv_param_map* pm, AdjSetup* out) {
   // LDS: table partials when they fit beside tables and packet stacks with a
   // workgroup of at least 128 lanes, otherwise global atomics per entry
   const size_t lim = (size_t)160 * 1024 - transport_static_lds();
+  const int dq_n = transport_dq_entries(p->host);
   auto lds = [&](int block, int ntab) {
-    return transport_lds_bytes(p->host.n_tables, 0, block, ntab, 0);
+    return transport_lds_bytes(p->host.n_tables, 0, block, ntab, 0) +
+           transport_dq_bytes(block, dq_n, true);
   };
   int block = p->block;
   while (block > 128 && lds(block, A.nb + A.nc) > lim) block -= 64;
@@ -1396,20 +1398,20 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   // dynamic LDS: bin cache, largest tables, largest stacks, then the waves'
   // detection queues (the largest any item uses)
   size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, kHotMin) +
-               transport_dq_bytes(block, dq_max);
+               transport_dq_bytes(block, dq_max, false);
   while (lds + transport_static_lds() + 64 > 160 * 1024 && block > 64) {
     block -= 64;
     lds = transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, kHotMin) +
-          transport_dq_bytes(block, dq_max);
+          transport_dq_bytes(block, dq_max, false);
   }
   if (lds + transport_static_lds() + 64 > 160 * 1024)
     return fail(MCV_EUNSUPPORTED, "batch tables and stacks exceed LDS");
   const int hot_n = hot_slots(transport_static_lds() + 64 +
                                   transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, 0) +
-                                  transport_dq_bytes(block, dq_max),
+                                  transport_dq_bytes(block, dq_max, false),
                               block, batch_waves_per_eu());
   const size_t lds_q = transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, hot_n);
-  lds = lds_q + transport_dq_bytes(block, dq_max);
+  lds = lds_q + transport_dq_bytes(block, dq_max, false);
 
   auto* b = new (std::nothrow) mcv_batch_s();
   if (!b) return fail(MCV_ENOMEM, "host allocation failed");

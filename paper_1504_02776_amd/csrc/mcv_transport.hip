@@ -1590,11 +1590,15 @@ enum { LANE_NEED = 0, LANE_SETUP = 1, LANE_FLY = 2, LANE_DET = 3, LANE_DONE = 4 
 
 // Recording of one packet leaving the sample: detector, histogram value or
 // adjoint gather, and the packet record in MODE_TRACE.
+// In adjoint mode with `sc` given, the four scalar partials (g d log w /
+// d sigma_abs, d sigma, g A, g n_draws) are returned there for the caller to
+// combine over the wave; otherwise they are added to the LDS partials here.
 template <int MODE>
 __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* tab,
                                               const Sinks& out, const AdjArgs& AA, double* acc,
                                               const Pk& cur, const Adj& ca, uint64_t hid,
-                                              uint64_t seed, int& hbin, float& hval) {
+                                              uint64_t seed, int& hbin, float& hval,
+                                              double* sc_out = nullptr) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
   const Hit hh = PL.det.type == DET_SPHERE ? detect_sphere(PL.det, cur)
                                            : detect_tubes(PL.det, tab, cur, hid, seed);
@@ -1603,11 +1607,18 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
       const double gv = AA.dLdI[hh.bin] * (double)hh.value;
       if (gv != 0.0) {
         // LDS partials: [table entries (when they fit) | 4 scalars]
-        double* sc = acc + (AA.sparse_lds ? AA.nb + AA.nc : 0);
-        atomicAdd(&sc[0], gv * (double)ca.dabs);
-        atomicAdd(&sc[1], gv * (double)ca.dsig);
-        atomicAdd(&sc[2], gv * (double)ca.A);
-        atomicAdd(&sc[3], gv * (double)(ca.cnt & 0xFFFFu));
+        if (sc_out) {
+          sc_out[0] = gv * (double)ca.dabs;
+          sc_out[1] = gv * (double)ca.dsig;
+          sc_out[2] = gv * (double)ca.A;
+          sc_out[3] = gv * (double)(ca.cnt & 0xFFFFu);
+        } else {
+          double* sc = acc + (AA.sparse_lds ? AA.nb + AA.nc : 0);
+          atomicAdd(&sc[0], gv * (double)ca.dabs);
+          atomicAdd(&sc[1], gv * (double)ca.dsig);
+          atomicAdd(&sc[2], gv * (double)ca.A);
+          atomicAdd(&sc[3], gv * (double)(ca.cnt & 0xFFFFu));
+        }
         const uint32_t ns = ca.cnt >> 16;
 #pragma unroll
         for (int w = 0; w < kAdjMaxSparse / 2; ++w) {
@@ -1665,12 +1676,14 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
 // fields (position, direction, speed, time, weight, lineage, history id low
 // and high words).
 constexpr int kDqFields = 12;
+constexpr int kDqAdjFields = kDqFields + kAdjFields;  // adjoint: the carry follows
 constexpr int kDqPhased = 64;     // entries per wave, phased loop
 constexpr int kDqWalk = 64;       // entries per wave, walk loop
 constexpr int kDqBatchWalk = 32;  // walk loop of the batch kernel (beside its LDS stacks)
 
-template <int Q>
-__device__ __forceinline__ void dq_put(float* q, int slot, const Pk& P, uint64_t hid) {
+template <int Q, bool ADJ>
+__device__ __forceinline__ void dq_put(float* q, int slot, const Pk& P, uint64_t hid,
+                                       const Adj& a) {
   constexpr int kDqEntries = Q;
   float* b = q + slot;
   b[0 * kDqEntries] = P.px;
@@ -1685,20 +1698,33 @@ __device__ __forceinline__ void dq_put(float* q, int slot, const Pk& P, uint64_t
   b[9 * kDqEntries] = __uint_as_float(P.lin);
   b[10 * kDqEntries] = __uint_as_float((uint32_t)hid);
   b[11 * kDqEntries] = __uint_as_float((uint32_t)(hid >> 32));
+  if (ADJ) {
+    b[12 * kDqEntries] = a.dabs;
+    b[13 * kDqEntries] = a.dsig;
+    b[14 * kDqEntries] = a.A;
+    b[15 * kDqEntries] = __uint_as_float(a.cnt);
+#pragma unroll
+    for (int w = 0; w < kAdjMaxSparse / 2; ++w)
+      b[(16 + w) * kDqEntries] = __uint_as_float(a.s[w]);
+  }
 }
 
 // records the n queued packets, one per lane (called with the whole wave
-// active; a wave of fewer lanes takes several passes)
+// active; a wave of fewer lanes takes several passes).  In adjoint mode the
+// scalar partials of the pass are summed over the wave and added to LDS by
+// one lane.
 template <int MODE, int Q>
 __device__ __forceinline__ void dq_run(const DevPlan& PL, const float* tab, const Sinks& out,
                                        const AdjArgs& AA, double* acc, int hot_n, const float* q,
                                        int n, uint64_t seed) {
+  constexpr bool ADJ = MODE == MODE_ADJOINT;
   constexpr int kDqEntries = Q;
   const int nl = __popcll(__ballot(1));
   for (int base = 0; base < n; base += nl) {
     const int i = base + (int)__lane_id();
     int hbin = -1;
     float hval = 0.0f;
+    double sc[4] = {0.0, 0.0, 0.0, 0.0};
     if (i < n) {
       const float* b = q + i;
       Pk P;
@@ -1714,11 +1740,29 @@ __device__ __forceinline__ void dq_run(const DevPlan& PL, const float* tab, cons
       P.lin = __float_as_uint(b[9 * kDqEntries]);
       const uint64_t hid = (uint64_t)__float_as_uint(b[10 * kDqEntries]) |
                            ((uint64_t)__float_as_uint(b[11 * kDqEntries]) << 32);
-      const Adj ca = adj_zero();
-      record_packet<MODE>(PL, tab, out, AA, acc, P, ca, hid, seed, hbin, hval);
+      Adj ca = adj_zero();
+      if (ADJ) {
+        ca.dabs = b[12 * kDqEntries];
+        ca.dsig = b[13 * kDqEntries];
+        ca.A = b[14 * kDqEntries];
+        ca.cnt = __float_as_uint(b[15 * kDqEntries]);
+#pragma unroll
+        for (int w = 0; w < kAdjMaxSparse / 2; ++w)
+          ca.s[w] = __float_as_uint(b[(16 + w) * kDqEntries]);
+      }
+      record_packet<MODE>(PL, tab, out, AA, acc, P, ca, hid, seed, hbin, hval,
+                          ADJ ? sc : nullptr);
     }
-    if (out.hist != nullptr || out.hist_w2 != nullptr)
+    if (ADJ) {
+      double* dst = acc + (AA.sparse_lds ? AA.nb + AA.nc : 0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double v = wave_sum(sc[k]);
+        if (__lane_id() == 0 && v != 0.0) atomicAdd(&dst[k], v);
+      }
+    } else if (out.hist != nullptr || out.hist_w2 != nullptr) {
       hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
+    }
   }
 }
 
@@ -1754,7 +1798,6 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
                                              const AdjArgs& AA, double* acc, int hot_n,
                                              int nthreads, int tid, float* dq) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
-  static_assert(!(DQ && ADJ), "the adjoint records its packets at once");
   static_assert(DQ == 0 || DQ == kDqPhased, "phased-loop queue size");
   const uint64_t lt = lanemask_lt();
   Pk cur;
@@ -1804,7 +1847,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
         dq_run<MODE, DQ>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
         qn = 0;
       }
-      if (q) dq_put<DQ>(dq, qn + __popcll(mq & lt), cur, hid);
+      if (q) dq_put<DQ, ADJ>(dq, qn + __popcll(mq & lt), cur, hid, ca);
       qn += k;
       // a packet that meets no tube leaves no histogram entry; trace mode
       // still writes its record
@@ -1867,7 +1910,6 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
                                            const AdjArgs& AA, double* acc, int hot_n,
                                            int nthreads, int tid, float* dq) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
-  static_assert(!(DQ && ADJ), "the adjoint records its packets at once");
   static_assert(DQ == 0 || DQ == kDqWalk || DQ == kDqBatchWalk, "walk-loop queue size");
   constexpr bool DEFER = NSC > 1 || TWO || HEAVY;
   const uint64_t lt = lanemask_lt();
@@ -1939,7 +1981,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
         dq_run<MODE, DQ>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
         qn = 0;
       }
-      if (q) dq_put<DQ>(dq, qn + __popcll(mq & lt), cur, hid);
+      if (q) dq_put<DQ, ADJ>(dq, qn + __popcll(mq & lt), cur, hid, ca);
       qn += k;
       if (MODE == MODE_TRACE && has && !q)
         record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
@@ -2029,8 +2071,9 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
   Sinks o = out;
-  float* dq = dqs + (tid >> 6) * DQ * kDqFields;
-  float* evs = dqs + (nthreads >> 6) * DQ * kDqFields;
+  constexpr int DQF = ADJ ? kDqAdjFields : kDqFields;
+  float* dq = dqs + (tid >> 6) * DQ * DQF;
+  float* evs = dqs + (nthreads >> 6) * DQ * DQF;
   if (events) {
     float* sw = evs + (tid >> 6) * kEvStageWords;
     o.stage = reinterpret_cast<DevEvent*>(sw);
@@ -2245,8 +2288,9 @@ int batch_dq_entries(const DevPlan& P) {
   if (P.det.type != DET_TUBES) return 0;
   return dev::use_phased(P.nscat, P.smax > P.nscat, P.K) ? dev::kDqPhased : dev::kDqBatchWalk;
 }
-size_t transport_dq_bytes(int block, int entries) {
-  return sizeof(float) * (size_t)entries * dev::kDqFields * (size_t)(block / 64);
+size_t transport_dq_bytes(int block, int entries, bool adjoint) {
+  return sizeof(float) * (size_t)entries * (adjoint ? dev::kDqAdjFields : dev::kDqFields) *
+         (size_t)(block / 64);
 }
 
 // adj_ntab: kLdsNoAdjoint outside the adjoint, else the table partials kept
@@ -2279,8 +2323,7 @@ void launch_shapes(int nsc, bool two, bool phased, bool dq, int grid, int block,
 #define MCV_LAUNCH(NSC_, TWO_, PH_)                                                            \
   do {                                                                                         \
     if (dq)                                                                                    \
-      launch_one<MODE, NSC_, TWO_, PH_, HEAVY,                                                 \
-                 MODE == dev::MODE_ADJOINT ? 0 : (PH_ ? dev::kDqPhased : dev::kDqWalk)>(       \
+      launch_one<MODE, NSC_, TWO_, PH_, HEAVY, PH_ ? dev::kDqPhased : dev::kDqWalk>(            \
           grid, block, lds, stream, plan, tables, beam, seed, first, n, per_wave, out, AA);    \
     else                                                                                       \
       launch_one<MODE, NSC_, TWO_, PH_, HEAVY>(grid, block, lds, stream, plan, tables, beam,   \
@@ -2325,9 +2368,9 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
   AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = AA.sqe_s = AA.sqe_k = AA.mp_k = -1;
   if (adj) AA = *adj;
   dev::Sinks out = {hist, hist_w2, rec, cap, n_out, ev, ev_cap, n_ev, 0, nullptr, nullptr, gstack};
-  const int dq_n = adj ? 0 : transport_dq_entries(host_plan);
+  const int dq_n = transport_dq_entries(host_plan);
   const bool dq = dq_n > 0;
-  const size_t qbytes = transport_dq_bytes(block, dq_n);
+  const size_t qbytes = transport_dq_bytes(block, dq_n, adj != nullptr);
   const int stack_lds = 0;  // the packet stacks live in device memory
   size_t lds =
       transport_lds_bytes(host_plan.n_tables, stack_lds, block,
@@ -2354,7 +2397,7 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
   const bool phased = dev::use_phased(nsc, two, host_plan.K);
   const bool heavy = host_plan.heavy != 0;
   if (adj) {
-    launch_mode<dev::MODE_ADJOINT>(nsc, two, phased, false, heavy, grid, block, lds, stream, plan,
+    launch_mode<dev::MODE_ADJOINT>(nsc, two, phased, dq, heavy, grid, block, lds, stream, plan,
                                    tables, beam, seed, first, n, per_wave, out, AA);
   } else if (rec) {
     launch_mode<dev::MODE_TRACE>(nsc, two, phased, dq, heavy, grid, block, lds, stream, plan,
@@ -2425,9 +2468,7 @@ void push_shapes_q(std::vector<const void*>& v) {
 template <int MODE, bool HV>
 void push_shapes(std::vector<const void*>& v) {
   push_shapes_q<MODE, HV, 0, 0>(v);
-  if (MODE != dev::MODE_ADJOINT)
-    push_shapes_q<MODE, HV, MODE != dev::MODE_ADJOINT ? dev::kDqPhased : 0,
-                  MODE != dev::MODE_ADJOINT ? dev::kDqWalk : 0>(v);
+  push_shapes_q<MODE, HV, dev::kDqPhased, dev::kDqWalk>(v);
 }
 template <int MODE>
 void push_mode(std::vector<const void*>& v) {
