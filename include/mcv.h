@@ -226,10 +226,14 @@ mcv_status mcv_detector_destroy(mcv_detector d);
  * deterministic: 1 = mcv_run sums every histogram bin in a fixed order, so
  *   that two runs with the same arguments give bitwise equal histograms
  *   (Sec. 3: a bin's intensity is the sum of the probabilities of the
- *   packets recorded in it; the packets are sorted by bin and, within a bin,
- *   by (history id, lineage), and each bin is summed in that order).  Slower,
- *   and it needs a plan-owned device workspace; 0 = binary64 atomics in
- *   arrival order (sums equal up to rounding order).
+ *   packets recorded in it).  The ids are taken in chunks (at most 2^16
+ *   histories); per chunk the packets recorded are sorted by (bin, history
+ *   id, lineage), each bin's run is summed in that order in binary64 and
+ *   added to the bin, chunks in id order.  mcv_run then waits for the
+ *   stream once per chunk (it reads the number of recorded packets) and is
+ *   several times slower; the plan holds a device workspace for it.  Other
+ *   calls (mcv_trace, mcv_run_events, batches, the adjoint) are unaffected.
+ *   0 = binary64 atomics in arrival order (sums equal up to rounding order).
  * max_waves: upper bound on the wavefronts a launch spreads its histories
  *   over (each wave then traces about n / max_waves histories one after
  *   another); 0 = enough waves to fill the device. */

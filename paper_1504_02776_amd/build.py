@@ -10,7 +10,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmcv.so")
-SOURCES = ["mcv_transport.hip", "mcv_reduce.hip", "mcv_adjoint.hip", "mcv_api.cpp"]
+SOURCES = ["mcv_transport.hip", "mcv_reduce.hip", "mcv_adjoint.hip", "mcv_determ.hip",
+           "mcv_api.cpp"]
 PROBE_LIB = os.path.join(HERE, "libmcv_probe.so")
 PROBE_SOURCES = ["mcv_probe.hip"]
 ARCH = os.environ.get("MCV_OFFLOAD_ARCH", "gfx950")

@@ -27,7 +27,14 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                             int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
                             DevEvent* ev, uint64_t ev_cap, unsigned long long* n_ev,
-                            const AdjArgs* adj, float* gstack, hipStream_t stream);
+                            const AdjArgs* adj, float* gstack, const DetArgs* det,
+                            hipStream_t stream);
+hipError_t det_zero(unsigned long long* n, hipStream_t stream);
+hipError_t det_sort(void* temp, size_t* temp_bytes, const uint64_t* kin, uint64_t* kout,
+                    const float* vin, float* vout, uint64_t count, int end_bit,
+                    hipStream_t stream);
+hipError_t det_sums(const uint64_t* keys, const float* vals, uint64_t count, int bin_shift,
+                    double* hist, double* hist_w2, hipStream_t stream);
 hipError_t launch_adjoint_prepare(const double* theta, int nb, double de, double kT, double h2m,
                                   const double* cells, int nc, double* ws, hipStream_t stream);
 hipError_t launch_adjoint_finalize(double* grad, const double* ws, int nb, int nc,
@@ -323,6 +330,15 @@ struct mcv_plan_s {
   // per-lane packet stacks of the transport launches in device memory
   float* d_stack = nullptr;
   size_t stack_floats = 0;
+  // deterministic summation: chunk of histories, entry capacity, key layout
+  // and the (key, value) buffers, sort workspace and entry counter
+  uint64_t det_chunk = 0, det_cap = 0;
+  int det_lin_bits = 0, det_id_bits = 0;
+  uint64_t* d_keys[2] = {nullptr, nullptr};
+  float* d_vals[2] = {nullptr, nullptr};
+  void* d_sort_tmp = nullptr;
+  size_t sort_tmp_bytes = 0;
+  unsigned long long* d_det_n = nullptr;
   DevPlan* d_plan = nullptr;
   float* d_tables = nullptr;
   float* d_pixgeo = nullptr;     // per pixel id: |r_p|, cos(2theta) (reduction)
@@ -832,6 +848,34 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
       }
     }
   }
+  if (p->deterministic) {
+    // key = bin (31 bits) | id - chunk first | lineage (3K + 1 bits: a child
+    // of lineage L is 8 L + g + 1, g < 7); entries <= histories x packets
+    // per history <= chunk x sum_{j <= K} smax^j
+    p->det_lin_bits = 3 * P.K + 1;
+    p->det_id_bits = 64 - 31 - p->det_lin_bits;
+    uint64_t maxpk = 0, pw = 1;
+    for (int j = 0; j <= P.K; ++j, pw *= (uint64_t)std::max(1, P.smax)) maxpk += pw;
+    uint64_t chunk = (uint64_t)1 << 16;
+    chunk = std::min<uint64_t>(chunk, (uint64_t)1 << p->det_id_bits);
+    chunk = std::max<uint64_t>(1, std::min<uint64_t>(chunk, ((uint64_t)1 << 22) / maxpk));
+    p->det_chunk = chunk;
+    p->det_cap = chunk * maxpk;
+    size_t tb = 0;
+    e = det_sort(nullptr, &tb, nullptr, nullptr, nullptr, nullptr, p->det_cap, 64, nullptr);
+    p->sort_tmp_bytes = tb;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = hipMalloc(&p->d_keys[i], p->det_cap * sizeof(uint64_t));
+      if (e == hipSuccess) e = hipMalloc(&p->d_vals[i], p->det_cap * sizeof(float));
+    }
+    if (e == hipSuccess) e = hipMalloc(&p->d_sort_tmp, std::max<size_t>(tb, 16));
+    if (e == hipSuccess) e = hipMalloc(&p->d_det_n, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+      (void)hipSetDevice(cur);
+      mcv_plan_destroy(p);
+      return hipfail(e, "deterministic summation workspace");
+    }
+  }
   if (P.stack_cap > 0) {
     // stacks of every wave of the largest grid (grid_shape: cus x 4 x
     // waves_per_simd x 2 waves), adjoint fields included
@@ -860,6 +904,12 @@ mcv_status mcv_plan_destroy(mcv_plan p) {
   if (p->adj.ws) (void)hipFree(p->adj.ws);
   if (p->d_raw) (void)hipFree(p->d_raw);
   if (p->d_stack) (void)hipFree(p->d_stack);
+  for (int i = 0; i < 2; ++i) {
+    if (p->d_keys[i]) (void)hipFree(p->d_keys[i]);
+    if (p->d_vals[i]) (void)hipFree(p->d_vals[i]);
+  }
+  if (p->d_sort_tmp) (void)hipFree(p->d_sort_tmp);
+  if (p->d_det_n) (void)hipFree(p->d_det_n);
   (void)hipSetDevice(cur);
   delete p;
   return MCV_OK;
@@ -938,7 +988,7 @@ mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t firs
     return fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
   hipError_t e = launch_transport(p->d_plan, p->host, p->d_tables, B,
                                   seed, first, n, (int)grid, p->block, per_wave, hist, hist_w2,
-                                  rec, cap, n_out, ev, ev_cap, n_ev, nullptr, p->d_stack,
+                                  rec, cap, n_out, ev, ev_cap, n_ev, nullptr, p->d_stack, nullptr,
                                   (hipStream_t)stream);
   if (cur != p->device) (void)hipSetDevice(cur);
   if (e != hipSuccess) return hipfail(e, "transport launch");
@@ -949,10 +999,65 @@ mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t firs
 
 extern "C" {
 
+// Deterministic summation (plan option): chunks of det_chunk histories in id
+// order; per chunk the transport writes (key, value) entries, the host reads
+// their number (the stream is synchronised once per chunk), the entries are
+// sorted by key and every bin's run is summed in key order and added.
+static mcv_status run_deterministic(mcv_plan p, const mcv_beam* beam, uint64_t seed,
+                                    uint64_t first,
+                                    uint64_t n, double* hist, double* hist_w2,
+                                    hipStream_t stream) {
+  DevBeam B;
+  mcv_status st = make_beam(p, beam, &B);
+  if (st != MCV_OK) return st;
+  if ((st = check_ids(B, first, n)) != MCV_OK) return st;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  const int shift = p->det_id_bits + p->det_lin_bits;
+  for (uint64_t cf = first; cf < first + n && st == MCV_OK; cf += p->det_chunk) {
+    const uint64_t m = std::min<uint64_t>(p->det_chunk, first + n - cf);
+    uint64_t grid, per_wave;
+    grid_shape(p, m, p->block, &grid, &per_wave);
+    if (p->d_stack && grid * p->block * (size_t)p->host.stack_cap * kFields > p->stack_floats) {
+      st = fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
+      break;
+    }
+    DetArgs D = {p->d_keys[0], p->d_vals[0], p->det_cap, p->d_det_n, cf, p->det_lin_bits,
+                 p->det_id_bits};
+    hipError_t e = det_zero(p->d_det_n, stream);
+    if (e == hipSuccess)
+      e = launch_transport(p->d_plan, p->host, p->d_tables, B, seed, cf, m, (int)grid, p->block,
+                           per_wave, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr,
+                           nullptr, p->d_stack, &D, stream);
+    unsigned long long count = 0;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&count, p->d_det_n, sizeof(count), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      st = hipfail(e, "deterministic transport");
+      break;
+    }
+    if (count > p->det_cap) {
+      st = fail(MCV_ECAPACITY, "deterministic entries exceed their bound");
+      break;
+    }
+    size_t tb = p->sort_tmp_bytes;
+    e = det_sort(p->d_sort_tmp, &tb, p->d_keys[0], p->d_keys[1], p->d_vals[0], p->d_vals[1], count,
+                 31 + shift, stream);
+    if (e == hipSuccess) e = det_sums(p->d_keys[1], p->d_vals[1], count, shift, hist, hist_w2, stream);
+    if (e != hipSuccess) st = hipfail(e, "deterministic summation");
+  }
+  if (cur != p->device) (void)hipSetDevice(cur);
+  return st;
+}
+
 mcv_status mcv_run(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t first, uint64_t n,
                    double* hist, double* hist_w2, void* stream) {
   if (!p) return fail(MCV_EINVAL, "null plan");
   if (!hist) return fail(MCV_EINVAL, "null histogram");
+  if (p->deterministic)
+    return run_deterministic(p, beam, seed, first, n, hist, hist_w2, (hipStream_t)stream);
   return launch(p, beam, seed, first, n, hist, hist_w2, nullptr, 0, nullptr, stream);
 }
 
@@ -1193,7 +1298,7 @@ mcv_status adjoint_launch(mcv_plan p, const mcv_param_map* pm, const AdjSetup& A
       return fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
     e = launch_transport(p->d_plan, p->host, p->d_tables, B, seed, first, n, (int)grid, A.block,
                          per_wave, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, &AA,
-                         p->d_stack, stream);
+                         p->d_stack, nullptr, stream);
   }
   if (e == hipSuccess) e = launch_adjoint_finalize(grad, ws, A.nb, A.nc, stream);
   if (e != hipSuccess) return hipfail(e, "adjoint launch");

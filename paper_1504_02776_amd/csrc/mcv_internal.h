@@ -158,6 +158,19 @@ constexpr int kNoAllocWorkDoubles = 32768;
 // that are not adjoint
 constexpr int kLdsNoAdjoint = -1;
 
+// Deterministic summation of one chunk of histories: the transport appends
+// (key, value) per recorded packet, key = bin << (id_bits + lin_bits) |
+// (id - first) << lin_bits | lineage; sorted, each bin's run is summed in
+// key order.
+struct DetArgs {
+  uint64_t* keys;
+  float* vals;
+  uint64_t cap;
+  unsigned long long* n;  // device counter of entries (zeroed before the chunk)
+  uint64_t first;
+  int32_t lin_bits, id_bits;
+};
+
 struct DevBeam {
   int32_t type;  // 1 mono, 2 gauss, 3 saved
   float E, sigma_rel, W, H, z0;

@@ -1438,6 +1438,15 @@ struct Sinks {
   DevEvent* stage;           // this wave's LDS event stage (set in the kernel)
   volatile int* stage_n;     // events in the stage
   float* gstack;             // per-lane packet stacks in device memory (plan-owned)
+  // deterministic summation (MODE_RUN; NULL: off): one (key, value) entry
+  // per recorded packet, key = bin << (id_bits + lin_bits) | (id - det_first)
+  // << lin_bits | lineage, staged like events
+  uint64_t* dkeys;
+  float* dvals;
+  uint64_t det_cap;
+  unsigned long long* n_det;
+  uint64_t det_first;
+  int det_lin_bits, det_id_bits;
 };
 
 // Event mode: every wave stages its events in LDS (kEvStage entries) and
@@ -1490,6 +1499,56 @@ __device__ __forceinline__ void event_append(const Sinks& out, int ntof, const H
     e.tof = hh.tof;
     e.value = hh.value;
     e.order = order;
+    out.stage[n + __popcll(m & lanemask_lt())] = e;
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if ((int)__lane_id() == __ffsll((unsigned long long)act) - 1) *out.stage_n = n + k;
+}
+
+// Deterministic summation: the wave's staged (key, value) entries are
+// copied to the caller-sized arrays with one counter atomic per stage (the
+// order they land in does not matter: they are sorted by key afterwards)
+__device__ __forceinline__ void det_flush(const Sinks& out, int n) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  const uint64_t act = __ballot(1);
+  const int lead = __ffsll((unsigned long long)act) - 1;
+  const int na = __popcll(act);
+  const int me = __popcll(act & lanemask_lt());
+  unsigned long long base = 0ull;
+  if ((int)__lane_id() == lead) base = atomicAdd(out.n_det, (unsigned long long)n);
+  base = readlane64(base, lead);
+  for (int i = me; i < n; i += na) {
+    const uint64_t slot = base + (uint64_t)i;
+    if (slot < out.det_cap) {
+      const DevEvent e = out.stage[i];
+      out.dkeys[slot] = ((uint64_t)(uint32_t)__float_as_uint(e.tof) << 32) | e.pixel;
+      out.dvals[slot] = e.value;
+    }
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// stages one (key, value) entry per active lane with a recorded packet
+__device__ __forceinline__ void det_append(const Sinks& out, const Hit& hh, uint64_t hid,
+                                           uint32_t lin) {
+  const bool rec = hh.bin >= 0;
+  const uint64_t m = __ballot(rec);
+  if (m == 0ull) return;
+  const uint64_t act = __ballot(1);
+  const int k = __popcll(m);
+  int n = *out.stage_n;
+  if (n + k > kEvStage) {
+    det_flush(out, n);
+    n = 0;
+  }
+  if (rec) {
+    const uint64_t key = ((uint64_t)hh.bin << (out.det_id_bits + out.det_lin_bits)) |
+                         ((hid - out.det_first) << out.det_lin_bits) | (uint64_t)lin;
+    DevEvent e;
+    e.pixel = (uint32_t)key;
+    e.tof = __uint_as_float((uint32_t)(key >> 32));
+    e.value = hh.value;
+    e.order = 0;
     out.stage[n + __popcll(m & lanemask_lt())] = e;
   }
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -1638,6 +1697,7 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
     }
   }
   if (MODE == MODE_RUN && out.ev != nullptr) event_append(out, PL.det.ntof, hh, order_of(cur.lin));
+  if (MODE == MODE_RUN && out.dkeys != nullptr) det_append(out, hh, hid, cur.lin);
   if (MODE == MODE_TRACE) {
     const unsigned long long slot = atomicAdd(out.n_out, 1ull);
     if (slot < out.cap) {
@@ -2051,7 +2111,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   // adjoint partials: per table entry (sum of g; when they fit in LDS), then
   // sigma_abs, sigma, A, DOS draws; otherwise the histogram bin cache
   double* acc = reinterpret_cast<double*>(dyn + tab_words);
-  const bool events = MODE == MODE_RUN && out.ev != nullptr;
+  const bool events = MODE == MODE_RUN && (out.ev != nullptr || out.dkeys != nullptr);
   const int hot_n = events ? out.ev_hot_n : gplan->hot_n;
   const int ntab = ADJ && AA.sparse_lds ? AA.nb + AA.nc : 0;
   const int acc_words = ADJ ? 2 * (((ntab + 4) + 1) & ~1) : hot_words(hot_n);
@@ -2086,7 +2146,10 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
                                                    AA, acc, hot_n, nthreads, tid, dq);
     if (events) {
       const int left = *o.stage_n;
-      if (left > 0) ev_flush(o, left);
+      if (left > 0) {
+        if (o.dkeys != nullptr) det_flush(o, left);
+        else ev_flush(o, left);
+      }
     }
   }
   if (!ADJ) {
@@ -2146,7 +2209,7 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const uint64_t b = ch.first + per * wid;
     const uint64_t e = ch.first + ch.count;
     Sinks out = {it.hist, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr,
-                 nullptr};
+                 nullptr, nullptr, nullptr, 0, nullptr, 0, 0, 0};
     const uint64_t ee = b + per < e ? b + per : e;
     // the waves' detection queues sit behind the largest tables and stacks
     float* dq = dyn + dq_off;  // this wave's queue: dq + wid Q kDqFields
@@ -2363,11 +2426,22 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                             int grid, int block, uint64_t per_wave, double* hist, double* hist_w2,
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
                             DevEvent* ev, uint64_t ev_cap, unsigned long long* n_ev,
-                            const AdjArgs* adj, float* gstack, hipStream_t stream) {
+                            const AdjArgs* adj, float* gstack, const DetArgs* det,
+                            hipStream_t stream) {
   AdjArgs AA = {};
   AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = AA.sqe_s = AA.sqe_k = AA.mp_k = -1;
   if (adj) AA = *adj;
-  dev::Sinks out = {hist, hist_w2, rec, cap, n_out, ev, ev_cap, n_ev, 0, nullptr, nullptr, gstack};
+  dev::Sinks out = {hist, hist_w2, rec, cap, n_out, ev, ev_cap, n_ev, 0, nullptr, nullptr, gstack,
+                    nullptr, nullptr, 0, nullptr, 0, 0, 0};
+  if (det) {
+    out.dkeys = det->keys;
+    out.dvals = det->vals;
+    out.det_cap = det->cap;
+    out.n_det = det->n;
+    out.det_first = det->first;
+    out.det_lin_bits = det->lin_bits;
+    out.det_id_bits = det->id_bits;
+  }
   const int dq_n = transport_dq_entries(host_plan);
   const bool dq = dq_n > 0;
   const size_t qbytes = transport_dq_bytes(block, dq_n, adj != nullptr);
@@ -2376,7 +2450,7 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
       transport_lds_bytes(host_plan.n_tables, stack_lds, block,
                           adj ? (adj->sparse_lds ? adj->nb + adj->nc : 0) : kLdsNoAdjoint, host_plan.hot_n) +
       qbytes;
-  if (ev) {
+  if (ev || det) {
     // room for the event stages: a smaller bin cache, at most the same LDS
     // if the cache can give it
     const size_t stages = sizeof(float) * (size_t)dev::kEvStageWords * (block / 64);
