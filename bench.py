@@ -3,17 +3,29 @@
 One step = zero the binary64 I(pixel, tof) histogram + trace one batch of
 synthetic histories through source -> sample assembly -> detector -> histogram
 (every step of the hot path), inputs resident in HBM.  The headline workload
-is the powder cylinder (1e7 histories, Bragg + one-phonon kernels, 3 orders,
-1000 tubes x 128 pixels x 1000 tof bins).  Beside it, unless --quick:
+is the largest single-GPU configuration: a single-crystal slab with a
+nearest-neighbour spin-wave kernel inside an aluminium-like annular can (1e8
+histories at 50 meV, 3 orders, 2000 tubes x 128 pixels x 500 tof bins).
+Beside it, unless --quick:
 
+- powder: the powder cylinder (1e7 histories, Gaussian incident energy,
+  Bragg + one-phonon kernels, 1000 tubes x 128 x 1000), with its own
+  roofline and oracle baseline;
+- plate: the small plate case at 1e5 histories (latency; below one fill of
+  the GPU) and the same physics at 1e9 histories (throughput);
 - batched: 64 uneven simulations in one graph-captured persistent launch
-  (autotuned) against 64 sequential plain launches;
+  (autotuned) against 64 sequential plain launches, with its roofline (the
+  simulations' arithmetic against VALU issue, their histogram zeroing
+  against HBM);
 - adjoint: seconds per gradient step (forward + loss/dL/dI + adjoint) on the
   powder sample against 500 DOS bins, sigma_abs and sigma_inc, and its ratio
   to the forward step;
-- plate at 1e9 histories, the crystal-with-can workload at 1e8, the powder
-  with a multi-phonon kernel at 1e7, the crystal with an exact-delta
-  dispersion at 1e7, and a 64-angle goniometer scan of it in one batch.
+- atomics: the measured binary64 atomic ceilings (probe_costs.py) beside the
+  histogram updates of the headline launch and the event reduction;
+- the powder with a multi-phonon kernel at 1e7, the crystal with an
+  exact-delta dispersion at 1e7 and a 64-angle goniometer scan of it in one
+  batch, the powder on 8-packs, the aluminium coherent-phonon plate, event
+  mode and the (Q, E) reduction.
 
 Roofline: the transport kernel is bound by VALU issue.  Its work per history
 is the sum over primitives of (count per history in the algorithm, from the
@@ -42,7 +54,9 @@ sys.path.insert(0, ROOT)
 VALU_PEAK = 256 * 64 * 2.4e9
 HBM_PEAK = 8e12
 COSTS = os.path.join(ROOT, "paper_1504_02776_amd", "primitive_costs.json")
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "transport_powder_1e7_pmc.md")
+PMC_SUMMARIES = {"crystal": os.path.join(ROOT, "profiles", "transport_crystal_1e8_pmc.md"),
+                 "powder": os.path.join(ROOT, "profiles", "transport_powder_1e7_pmc.md")}
+PMC_SUMMARY = PMC_SUMMARIES["powder"]
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1504_02776_amd", "csrc", f)
                   for f in ("mcv_transport.hip", "mcv_internal.h")]
 REDUCE_PMC_SUMMARY = os.path.join(ROOT, "profiles", "reduce_qe_powder_1e7_pmc.md")
@@ -115,10 +129,10 @@ def traffic_per_launch(summary=PMC_SUMMARY, sources=None, key="traffic_bytes_per
     return float(t.group(1))
 
 
-def cpu_baseline(cfg, budget_s=12.0):
+def cpu_baseline(cfg, budget_s=12.0, n0=200):
     """The oracle as it stands, one host core, on a bounded sample."""
     from oracle import oracle as O
-    n = 200
+    n = min(n0, cfg["N"])
     while True:
         t0 = time.perf_counter()
         _, _, _, tally = O.run(cfg, n=n, records=False)
@@ -137,6 +151,36 @@ def cpu_model():
     except OSError:
         pass
     return platform.processor()
+
+
+def host_cpu():
+    """Model, logical CPUs, cores per socket, sockets and clock from lscpu."""
+    import subprocess
+    info = {"model": cpu_model()}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        keys = {"CPU(s)": "logical_cpus", "Core(s) per socket": "cores_per_socket",
+                "Socket(s)": "sockets", "CPU max MHz": "max_mhz", "CPU MHz": "mhz",
+                "Thread(s) per core": "threads_per_core"}
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in keys:
+                info[keys[k.strip()]] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline_entry(cfg, budget_s):
+    """The cpu_baseline object: oracle rate on one core over a bounded
+    sample, with the time the oracle would take for the full workload."""
+    n_s, el, tally = cpu_baseline(cfg, budget_s=budget_s)
+    rate = n_s / el
+    return {"value": rate, "unit": "histories/s", "cores": 1, "kind": "oracle",
+            "cpu": host_cpu(),
+            "sample": f"first {n_s} histories of the same workload (seed {cfg['seed']}), "
+                      f"serial binary64 oracle, {el:.1f} s",
+            "full_workload_s": cfg["N"] / rate}, n_s, tally
 
 
 def timed(torch, stream, fn, reps):
@@ -171,17 +215,61 @@ def bench_batched(torch, mcv, W, stream, reps):
             p.run(h, stream=stream)
     t_seq = timed(torch, stream, sequential, reps)
     b.close()
-    out = {"sims": len(cfgs), "histories": total,
-           "hist_bytes": int(sum(h.numel() for h in hists) * 8),
-           "graph_ms": t_graph, "sequential_ms": t_seq,
+    # the zeroing alone (the graph's fill kernels, one per histogram)
+    def zero_all():
+        for h in hists:
+            mcv.zero(h, stream=stream)
+    t_zero = timed(torch, stream, zero_all, reps)
+    hist_bytes = int(sum(h.numel() for h in hists) * 8)
+    out = {"sims": len(cfgs), "histories": total, "hist_bytes": hist_bytes,
+           "graph_ms": t_graph, "sequential_ms": t_seq, "zero_ms": t_zero,
            "histories_per_s_batched": total / (t_graph / 1e3),
            "histories_per_s_sequential": total / (t_seq / 1e3),
            "speedup": t_seq / t_graph,
            "tuning": {"block_size": tuning.block_size, "chunk": tuning.chunk,
                       "from_cache": bool(cached)}}
+    work = batch_work(cfgs)
+    if work is not None:
+        # the simulations' arithmetic (sum of N_s W_s) over the graph time,
+        # against VALU issue; the zeroing's 8 bytes per bin against HBM
+        out["roofline"] = {"bound": "alu", "achieved": work / (t_graph / 1e3) / 1e12,
+                           "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
+                           "frac": work / (t_graph / 1e3) / VALU_PEAK,
+                           "work_lane_ops": work, "traffic": None,
+                           "kernel": "batch_persistent + fill_zero (graph)",
+                           "zero_hbm_frac": hist_bytes / (t_zero / 1e3) / HBM_PEAK,
+                           "zero_share_of_graph": t_zero / t_graph}
     del plans, hists
     torch.cuda.empty_cache()
     return out
+
+
+def batch_work(cfgs, n_sample=32):
+    """Sum over the batch's simulations of N_s W_s (lane-op slots): the
+    primitive counts per history from an oracle sample of each simulation,
+    priced with the costs of the probe workload of the same kernel set and
+    shape (plate: iso plate; powder: powder cylinder; spin-wave slab: the
+    crystal's slab)."""
+    from oracle import oracle as O
+    costs = {k: load_costs(k) for k in ("plate", "powder", "crystal")}
+    if any(v is None for v in costs.values()):
+        return None
+    shape_cost = {"box": costs["plate"]["shape"][0], "cylinder": costs["powder"]["shape"][0],
+                  "annulus": costs["crystal"]["shape"][1]}
+    total = 0.0
+    for cfg in cfgs:
+        ktypes = [k["type"] for k in cfg["scatterers"][0]["kernels"]]
+        base = "plate" if ktypes == ["iso_el"] else ("powder" if "powder" in ktypes else "crystal")
+        c = dict(costs[base])
+        c["shape"] = [shape_cost[cfg["scatterers"][0]["shape"]["type"]]]
+        c["segment"] = [c["segment"][0]]
+        c["split"] = [c["split"][0]]
+        if base == "crystal":
+            c["kernel"] = {k: v for k, v in c["kernel"].items() if k.startswith("0.")}
+        n = min(n_sample, cfg["N"])
+        _, _, _, tally = O.run(cfg, n=n, records=False)
+        total += cfg["N"] * work_per_history(c, tally, n, cfg)
+    return total
 
 
 def bench_scan(torch, mcv, W, stream, reps):
@@ -211,7 +299,7 @@ def bench_scan(torch, mcv, W, stream, reps):
     return out
 
 
-def bench_adjoint(torch, mcv, W, stream, reps, forward_ms):
+def bench_adjoint(torch, mcv, W, stream, reps):
     cfg = W.powder_config()
     plan = mcv.Plan(cfg)
     target = mcv.Plan(W.powder_config(dos_shift=1.05))
@@ -226,6 +314,10 @@ def bench_adjoint(torch, mcv, W, stream, reps, forward_ms):
     pm = mcv.param_map((0, 1), 0, (0, 1))
     grad = torch.zeros(plan.nparams(pm), dtype=torch.float64, device=I.device)
 
+    def forward():
+        mcv.zero(I, stream=stream)
+        plan.run(I, stream=stream)
+
     def step():
         mcv.zero(I, stream=stream)
         loss.zero_()
@@ -233,6 +325,7 @@ def bench_adjoint(torch, mcv, W, stream, reps, forward_ms):
         plan.run(I, stream=stream)
         mcv.loss_grad(I, T, wgt, dLdI, loss, stream=stream)
         plan.adjoint(pm, dLdI, grad, stream=stream)
+    forward_ms = timed(torch, stream, forward, reps)
     t_step = timed(torch, stream, step, reps)
     t_loss = timed(torch, stream, lambda: mcv.loss_grad(I, T, wgt, dLdI, loss, stream=stream),
                    reps)
@@ -250,9 +343,11 @@ def bench_adjoint(torch, mcv, W, stream, reps, forward_ms):
     return out
 
 
-def bench_single(torch, mcv, cfg, stream, reps, costs_name=None, cpu_budget_s=4.0):
+def bench_single(torch, mcv, cfg, stream, reps, costs_name=None, cpu_budget_s=4.0,
+                 full_cpu=False, pmc=None):
     """Plain launches of another workload; with its probe costs, also its
-    roofline fraction (work per history from a short oracle sample)."""
+    roofline fraction (work per history from a short oracle sample); with
+    full_cpu, the oracle baseline object as for the headline."""
     plan = mcv.Plan(cfg)
     h = plan.zeros()
     ev = []
@@ -274,10 +369,41 @@ def bench_single(torch, mcv, cfg, stream, reps, costs_name=None, cpu_budget_s=4.
     torch.cuda.empty_cache()
     costs = load_costs(costs_name) if costs_name else None
     if costs is not None:
-        n_s, _, tally = cpu_baseline(cfg, budget_s=cpu_budget_s)
+        if full_cpu:
+            out["cpu_baseline"], n_s, tally = cpu_baseline_entry(cfg, cpu_budget_s)
+        else:
+            n_s, _, tally = cpu_baseline(cfg, budget_s=cpu_budget_s)
         w = work_per_history(costs, tally, n_s, cfg)
-        out["roofline"] = {"bound": "alu", "work_per_history": w,
-                           "frac": cfg["N"] * w / (kern / 1e3) / VALU_PEAK}
+        achieved = cfg["N"] * w / (kern / 1e3)
+        out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
+                           "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
+                           "frac": achieved / VALU_PEAK,
+                           "traffic": traffic_per_launch(pmc) if pmc else None,
+                           "kernel": "transport (run mode)", "work_per_history": w,
+                           "histories_per_launch": cfg["N"]}
+        out["hist_updates_per_history"] = tally.n_hist_updates / n_s
+    return out
+
+
+def bench_plate(torch, mcv, W, stream, reps):
+    """The small plate case (1e5 histories, single scattering, sphere
+    detector): latency of one step at its own size, which is below one fill
+    of the GPU's lanes, its oracle rate over the whole workload, and the same
+    physics at 1e9 histories for throughput and roofline."""
+    cfg = W.plate_config()
+    plan = mcv.Plan(cfg)
+    h = plan.zeros()
+
+    def step():
+        mcv.zero(h, stream=stream)
+        plan.run(h, stream=stream)
+    lat = timed(torch, stream, step, 20)
+    del plan, h
+    out = {"workload": cfg["name"], "histories": cfg["N"], "latency_ms": lat,
+           "histories_per_s": cfg["N"] / (lat / 1e3)}
+    out["cpu_baseline"], _, _ = cpu_baseline_entry(cfg, 6.0)
+    out["scaled"] = bench_single(torch, mcv, W.plate_config(N=1_000_000_000), stream, reps,
+                                 "plate")
     return out
 
 
@@ -346,19 +472,26 @@ def load_costs(name):
         return json.load(f)["workloads"].get(name)
 
 
+def load_atomics():
+    if not os.path.exists(COSTS):
+        return None
+    with open(COSTS) as f:
+        return json.load(f).get("atomics")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="powder")
+    ap.add_argument("--workload", default="crystal")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--sections", default=None,
-                    help="comma-separated extra sections to run (batched, adjoint, plate, "
-                         "crystal, multiphonon, delta, scan, 8packs, coherent, events); "
-                         "default: all unless --quick")
+                    help="comma-separated extra sections to run (powder, plate, batched, "
+                         "adjoint, crystal, multiphonon, delta, scan, 8packs, coherent, events, "
+                         "atomics); default: all unless --quick")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (PMC byte calibration)")
     args = ap.parse_args()
@@ -429,26 +562,24 @@ def main():
         "kernel_ms": sum(kern_ms) / len(kern_ms),
         "wall_s": wall,
     }
+    base = args.workload.split("-")[0]
+    hist_updates_per_s = None
     if not args.no_cpu_baseline:
-        n_s, el, tally = cpu_baseline(cfg)
-        out["cpu_baseline"] = {"value": n_s / el, "unit": "histories/s", "cores": 1,
-                               "kind": "oracle", "cpu": cpu_model(),
-                               "sample": f"first {n_s} histories of the same workload (seed "
-                                         f"{cfg['seed']}), serial binary64 oracle, {el:.1f} s"}
-        costs = load_costs({"powder-mp": "powder_mp"}.get(args.workload,
-                                                          args.workload.split("-")[0]))
+        out["cpu_baseline"], n_s, tally = cpu_baseline_entry(cfg, 12.0)
+        costs = load_costs({"powder-mp": "powder_mp"}.get(args.workload, base))
         if costs is not None:
             w_hist = work_per_history(costs, tally, n_s, cfg)
             achieved = N * w_hist / kern_avg_s
-            tb = traffic_per_launch()
+            tb = traffic_per_launch(PMC_SUMMARIES[base]) if base in PMC_SUMMARIES else None
             out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
                                "peak": VALU_PEAK / 1e12, "unit": "Tlane-op/s",
                                "frac": achieved / VALU_PEAK, "traffic": tb,
                                "kernel": "transport (run mode)",
                                "work_per_history": w_hist,
                                "histories_per_launch": N}
-    all_sections = ["batched", "adjoint", "plate", "crystal", "multiphonon", "delta", "scan",
-                    "8packs", "coherent", "events"]
+        hist_updates_per_s = tally.n_hist_updates / n_s * N / kern_avg_s
+    all_sections = ["powder", "plate", "batched", "adjoint", "crystal", "multiphonon", "delta",
+                    "scan", "8packs", "coherent", "events", "atomics"]
     if args.sections is not None:
         sections = [x for x in args.sections.split(",") if x]
         unknown = set(sections) - set(all_sections)
@@ -458,15 +589,21 @@ def main():
         sections = [] if args.quick else all_sections
     reps = 3
     for sec in sections:
-        if sec == "batched":
+        if sec == "powder":
+            if base != "powder":
+                out["powder"] = bench_single(torch, mcv, W.powder_config(), stream, reps, "powder",
+                                             cpu_budget_s=8.0, full_cpu=True,
+                                             pmc=PMC_SUMMARIES["powder"])
+        elif sec == "batched":
             out["batched"] = bench_batched(torch, mcv, W, stream, reps)
         elif sec == "adjoint":
-            out["adjoint"] = bench_adjoint(torch, mcv, W, stream, reps, ms_per_step)
+            out["adjoint"] = bench_adjoint(torch, mcv, W, stream, reps)
         elif sec == "plate":
-            out["plate_scaled"] = bench_single(torch, mcv, W.plate_config(N=1_000_000_000),
-                                               stream, reps, "plate")
+            out["plate"] = bench_plate(torch, mcv, W, stream, reps)
         elif sec == "crystal":
-            out["crystal"] = bench_single(torch, mcv, W.crystal_config(), stream, reps, "crystal")
+            if base != "crystal":
+                out["crystal"] = bench_single(torch, mcv, W.crystal_config(), stream, reps,
+                                              "crystal")
         elif sec == "multiphonon":
             out["powder_multiphonon"] = bench_single(torch, mcv, W.powder_mp_config(), stream,
                                                      reps, "powder_mp")
@@ -483,6 +620,21 @@ def main():
                                                      reps, "al_coherent")
         elif sec == "events":
             out["events_and_reduction"] = bench_events_and_reduction(torch, mcv, W, stream, reps)
+        elif sec == "atomics":
+            a = load_atomics()
+            if a is not None:
+                ceil_1gb = a.get("1GB_uniform")
+                out["atomics"] = {
+                    "ceilings_per_s": {k: v for k, v in a.items() if k.endswith(("uniform", "hot10"))},
+                    "source": "probe_costs.py (random binary64 atomicAdd, grid 2048 x 256 lanes)"}
+                if hist_updates_per_s is not None and ceil_1gb:
+                    out["atomics"]["headline_hist_updates_per_s"] = hist_updates_per_s
+                    out["atomics"]["headline_frac_of_1GB_uniform"] = hist_updates_per_s / ceil_1gb
+                er = out.get("events_and_reduction")
+                if er is not None and a.get("4MB_uniform"):
+                    out["atomics"]["reduce_events_per_s"] = er["reduce_events_per_s"]
+                    out["atomics"]["reduce_events_frac_of_4MB_uniform"] = \
+                        er["reduce_events_per_s"] / a["4MB_uniform"]
         print(f"[bench] {sec} done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 

@@ -1379,7 +1379,7 @@ mcv_status mcv_loss_grad(const double* I, const double* T, const double* w, int6
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int64_t grid = (n / 2 + 255) / 256;
-  if (grid > (int64_t)cus * 8) grid = (int64_t)cus * 8;
+  if (grid > (int64_t)cus * 64) grid = (int64_t)cus * 64;
   if (grid < 1) grid = 1;
   hipError_t e = launch_loss_grad(I, T, w, n, dL_dI, loss, (int)grid, (hipStream_t)stream);
   if (e != hipSuccess) return hipfail(e, "loss launch");
@@ -1406,8 +1406,8 @@ namespace mcv {
 hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32_t n_chunks,
                         uint32_t* cursor, double* const* zero_ptrs, const uint64_t* zero_sizes,
                         int n_zero, int grid, int block, size_t lds, int hot_n, int dq_off,
-                        hipStream_t stream);
-int batch_occupancy(int block, size_t lds);
+                        float* gstack, int stack_max, bool heavy, hipStream_t stream);
+int batch_occupancy(int block, size_t lds, bool heavy);
 }  // namespace mcv
 
 struct mcv_batch_s {
@@ -1421,6 +1421,9 @@ struct mcv_batch_s {
   size_t lds = 0;
   int hot_n = kHotMin;
   int dq_off = 0;  // words from the start of dynamic LDS to the detection queues
+  float* d_stack = nullptr;  // packet stacks of the resident workgroups (device memory)
+  int stack_max = 0;
+  bool heavy = false;  // some plan has an exact-delta or coherent-phonon kernel
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1436,6 +1439,7 @@ void batch_free(mcv_batch_s* b) {
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_chunks) (void)hipFree(b->d_chunks);
   if (b->d_cursor) (void)hipFree(b->d_cursor);
+  if (b->d_stack) (void)hipFree(b->d_stack);
   delete b;
 }
 
@@ -1465,6 +1469,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   std::vector<double*> zp;
   std::vector<uint64_t> zs;
   int n_tables_max = 0, stack_max = 0, dq_max = 0;
+  bool heavy = false;
   for (int i = 0; i < n; ++i) {
     const mcv_batch_item& it = items[i];
     if (!it.plan || !it.hist) return fail(MCV_EINVAL, "batch item needs a plan and a histogram");
@@ -1480,6 +1485,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
     hitems[i].id0 = it.first;
     hitems[i].hist = it.hist;
     n_tables_max = std::max(n_tables_max, it.plan->host.n_tables);
+    heavy = heavy || it.plan->host.heavy != 0;
     stack_max = std::max(stack_max, it.plan->host.stack_cap);
     dq_max = std::max(dq_max, batch_dq_entries(it.plan->host));
     const double c = history_cost(it.plan);
@@ -1500,22 +1506,22 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
                    [](const auto& a, const auto& b) { return a.first > b.first; });
   std::vector<BatchChunk> cl;
   for (auto& c : hchunks) cl.push_back(c.second);
-  // dynamic LDS: bin cache, largest tables, largest stacks, then the waves'
-  // detection queues (the largest any item uses)
-  size_t lds = transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, kHotMin) +
+  // dynamic LDS: bin cache, largest tables, then the waves' detection queues
+  // (the largest any item uses); the packet stacks live in device memory
+  size_t lds = transport_lds_bytes(n_tables_max, 0, block, kLdsNoAdjoint, kHotMin) +
                transport_dq_bytes(block, dq_max, false);
   while (lds + transport_static_lds() + 64 > 160 * 1024 && block > 64) {
     block -= 64;
-    lds = transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, kHotMin) +
+    lds = transport_lds_bytes(n_tables_max, 0, block, kLdsNoAdjoint, kHotMin) +
           transport_dq_bytes(block, dq_max, false);
   }
   if (lds + transport_static_lds() + 64 > 160 * 1024)
-    return fail(MCV_EUNSUPPORTED, "batch tables and stacks exceed LDS");
+    return fail(MCV_EUNSUPPORTED, "batch tables exceed LDS");
   const int hot_n = hot_slots(transport_static_lds() + 64 +
-                                  transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, 0) +
+                                  transport_lds_bytes(n_tables_max, 0, block, kLdsNoAdjoint, 0) +
                                   transport_dq_bytes(block, dq_max, false),
                               block, batch_waves_per_eu());
-  const size_t lds_q = transport_lds_bytes(n_tables_max, stack_max, block, kLdsNoAdjoint, hot_n);
+  const size_t lds_q = transport_lds_bytes(n_tables_max, 0, block, kLdsNoAdjoint, hot_n);
   lds = lds_q + transport_dq_bytes(block, dq_max, false);
 
   auto* b = new (std::nothrow) mcv_batch_s();
@@ -1532,7 +1538,8 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   b->n_zero = (int)zp.size();
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-  int occ = batch_occupancy(block, lds);
+  b->heavy = heavy;
+  int occ = batch_occupancy(block, lds, heavy);
   if (occ < 1) occ = 1;
   if (t.wgs_per_cu > 0) occ = std::min(occ, (int)t.wgs_per_cu);
   b->grid = std::max(1, std::min<int>(cus * occ, (int)cl.size()));
@@ -1542,6 +1549,9 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
     if ((e = hipMalloc(dst, std::max<size_t>(bytes, 8))) != hipSuccess) return;
     if (bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
   };
+  b->stack_max = stack_max;
+  if (stack_max > 0 && e == hipSuccess)
+    e = hipMalloc(&b->d_stack, (size_t)b->grid * block * stack_max * kFields * sizeof(float));
   up((void**)&b->d_items, hitems.data(), hitems.size() * sizeof(BatchItem));
   up((void**)&b->d_chunks, cl.data(), cl.size() * sizeof(BatchChunk));
   uint32_t zero = 0;
@@ -1556,7 +1566,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
       (e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
     hipError_t el = launch_batch(b->d_items, b->d_chunks, b->n_chunks, b->d_cursor, zp.data(),
                                  zs.data(), b->n_zero, b->grid, b->block, b->lds, b->hot_n,
-                                 b->dq_off, b->capture);
+                                 b->dq_off, b->d_stack, b->stack_max, b->heavy, b->capture);
     e = hipStreamEndCapture(b->capture, &b->graph);
     if (e == hipSuccess) e = el;
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);

@@ -17,6 +17,8 @@
 
 #include "mcv_transport.hip"
 #include "mcv_reduce.hip"
+#include "mcv_adjoint.hip"
+#include "mcv_determ.hip"
 #include "mcv_api.cpp"
 
 namespace mcv {
@@ -169,6 +171,25 @@ probe_kernel(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, 
   hits[gid] = nh;
 }
 
+// Binary64 atomic add rate: every lane adds 1.0 `iters` times into a
+// histogram of nbins (< 2^32) doubles, at bins from a hash of (lane,
+// iteration), uniform over the histogram, except that hot_permille of the
+// updates go to bin 0 (the direct beam's one pixel and time bin).  The
+// global atomics execute at the memory side.
+__global__ void __launch_bounds__(256)
+atomic_probe(double* __restrict__ hist, uint32_t nbins, uint32_t iters, uint32_t hot_permille,
+             uint32_t seed) {
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t h = mix32(gid ^ seed);
+  for (uint32_t it = 0; it < iters; ++it) {
+    h = mix32(h + 0x9e3779b9u);
+    const uint32_t g = mix32(h ^ 0x85ebca6bu);
+    uint32_t b = (uint32_t)(((uint64_t)h * nbins) >> 32);  // < nbins
+    if (g % 1000u < hot_permille) b = 0u;
+    unsafeAtomicAdd(hist + b, 1.0);
+  }
+}
+
 template <int PR>
 hipError_t launch_probe(mcv_plan p, const DevBeam& B, uint64_t seed, int arg, uint32_t iters,
                         float sp0, int grid, float* sink, uint32_t* hits, hipStream_t s) {
@@ -260,6 +281,53 @@ mcv_status mcv_probe_time(mcv_plan p, const mcv_beam* beam, uint64_t seed, int32
   for (uint32_t v : hh) tot += v;
   *ms_out = best;
   *draws_per_call = tot / ((double)lanes * iters);
+  return MCV_OK;
+}
+
+// Times the binary64 atomic probe: grid workgroups of 256 lanes, iters
+// adds per lane into hist[nbins] (device, zeroed by the call), best of reps
+// after one warm-up; *ms_out is the best time, *total the sum of the
+// histogram after the last repetition (grid 256 iters when every add landed).
+mcv_status mcv_probe_atomics(double* hist, uint64_t nbins, uint32_t iters, uint32_t hot_permille,
+                             int32_t grid, int32_t reps, double* ms_out, double* total) {
+  using namespace mcv::probe;
+  if (!hist || !ms_out || !total) return fail(MCV_EINVAL, "null argument");
+  if (nbins == 0 || nbins >= ((uint64_t)1 << 32) || grid <= 0 || grid > 65536 || iters == 0 ||
+      reps <= 0 || hot_permille > 1000)
+    return fail(MCV_EINVAL, "bad size");
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  hipError_t e = hipSuccess;
+  double best = 1e30;
+  for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+    e = hipMemset(hist, 0, nbins * sizeof(double));
+    if (e != hipSuccess) break;
+    (void)hipEventRecord(a, nullptr);
+    hipLaunchKernelGGL(atomic_probe, dim3(grid), dim3(256), 0, nullptr, hist, (uint32_t)nbins,
+                       iters, hot_permille, 0x1234567u + (uint32_t)r);
+    e = hipGetLastError();
+    (void)hipEventRecord(b, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (r > 0 && ms < best) best = ms;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return hipfail(e, "atomic probe");
+  // the sum of the histogram: every add landed
+  std::vector<double> h(nbins < 4096 ? nbins : 0);
+  double t = 0.0;
+  if (!h.empty()) {
+    if ((e = hipMemcpy(h.data(), hist, nbins * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)
+      return hipfail(e, "atomic probe copy");
+    for (double v : h) t += v;
+  } else {
+    t = -1.0;  // not summed for large histograms
+  }
+  *ms_out = best;
+  *total = t;
   return MCV_OK;
 }
 

@@ -39,12 +39,15 @@
 // device memory, so LDS does not cap their occupancy: 4 waves per SIMD
 // (measured on the crystal in its can, 1e8 histories: 4 waves 111 ms, 5
 // waves 150 ms, 6 waves 173 ms, with the stacks in LDS and 2 waves 151 ms).
-// The persistent batch kernel keeps its stacks in LDS and runs 2.
+// The persistent batch kernel does the same.
 #ifndef MCV_WAVES_PER_EU
 #define MCV_WAVES_PER_EU 4
 #endif
+#ifndef MCV_WAVES_PER_EU_MAX
+#define MCV_WAVES_PER_EU_MAX 4
+#endif
 #ifndef MCV_BATCH_WAVES_PER_EU
-#define MCV_BATCH_WAVES_PER_EU 2
+#define MCV_BATCH_WAVES_PER_EU 4
 #endif
 
 namespace mcv {
@@ -1731,15 +1734,13 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
 // lanes holding such packets; instead they are appended to a per-wave LDS
 // queue of Q packets, which the wave records together (one packet per lane)
 // when the next D phase would overflow it, and at the end.  The walk loop
-// does the same with its recording step (Q = 64 as well; 32 in the batch
-// kernel, whose packet stacks share the LDS).  Layout: [field][entry], 12
-// fields (position, direction, speed, time, weight, lineage, history id low
-// and high words).
+// does the same with its recording step.  Layout: [field][entry], 12 fields
+// (position, direction, speed, time, weight, lineage, history id low and
+// high words), then the adjoint carry in adjoint launches.
 constexpr int kDqFields = 12;
 constexpr int kDqAdjFields = kDqFields + kAdjFields;  // adjoint: the carry follows
 constexpr int kDqPhased = 64;     // entries per wave, phased loop
 constexpr int kDqWalk = 64;       // entries per wave, walk loop
-constexpr int kDqBatchWalk = 32;  // walk loop of the batch kernel (beside its LDS stacks)
 
 template <int Q, bool ADJ>
 __device__ __forceinline__ void dq_put(float* q, int slot, const Pk& P, uint64_t hid,
@@ -1970,7 +1971,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
                                            const AdjArgs& AA, double* acc, int hot_n,
                                            int nthreads, int tid, float* dq) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
-  static_assert(DQ == 0 || DQ == kDqWalk || DQ == kDqBatchWalk, "walk-loop queue size");
+  static_assert(DQ == 0 || DQ == kDqWalk, "walk-loop queue size");
   constexpr bool DEFER = NSC > 1 || TWO || HEAVY;
   const uint64_t lt = lanemask_lt();
   Pk cur;
@@ -2098,7 +2099,8 @@ __device__ __forceinline__ void stage_plan(DevPlan& PL, float* dyn, const DevPla
 // dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
 // per workgroup.
 template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, int DQ = 0>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MCV_WAVES_PER_EU)))
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(MCV_WAVES_PER_EU, MCV_WAVES_PER_EU_MAX)))
 transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
           uint64_t seed, uint64_t first, uint64_t n, uint64_t per_wave, Sinks out, AdjArgs AA) {
   constexpr bool ADJ = MODE == MODE_ADJOINT;
@@ -2175,10 +2177,15 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
 // reads the same popped index after a barrier, so all leave together).  A
 // workgroup re-stages plan and tables in LDS only when the simulation
 // changes; its waves split the chunk's ids.  The list is sorted by
-// estimated cost, longest first.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MCV_BATCH_WAVES_PER_EU)))
+// estimated cost, longest first.  HV: some plan of the batch has an
+// exact-delta or coherent-phonon kernel (the instantiation without them
+// keeps their register budget out of the other batches).
+template <bool HV>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(MCV_BATCH_WAVES_PER_EU, MCV_WAVES_PER_EU_MAX)))
 batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restrict__ chunks,
-                 uint32_t n_chunks, uint32_t* __restrict__ cursor, int hot_n, int dq_off) {
+                 uint32_t n_chunks, uint32_t* __restrict__ cursor, int hot_n, int dq_off,
+                 float* __restrict__ gstack, int stack_max) {
   __shared__ DevPlan PL;
   __shared__ uint32_t s_chunk;
   extern __shared__ __align__(16) float dyn[];
@@ -2204,7 +2211,9 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     __syncthreads();
     const int tab_words = (PL.n_tables + 3) & ~3;
     float* tab = dyn + hot_words(hot_n);
-    float* st = tab + tab_words;
+    // the workgroup's packet stacks in device memory, sized for the largest
+    // stack of the batch's plans
+    float* st = gstack + (size_t)blockIdx.x * stack_max * kFields * nthreads;
     const uint64_t per = (ch.count + nwaves - 1) / nwaves;
     const uint64_t b = ch.first + per * wid;
     const uint64_t e = ch.first + ch.count;
@@ -2218,7 +2227,7 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     const bool two = PL.smax > PL.nscat;
 #define MCV_BATCH_TRACE(NSC_, TWO_, PH_, HV_)                                            \
   do {                                                                                     \
-    constexpr int Q_ = PH_ ? kDqPhased : kDqBatchWalk;                                     \
+    constexpr int Q_ = PH_ ? kDqPhased : kDqWalk;                                          \
     if (PL.det.type == DET_TUBES)                                                          \
       trace_range<MODE_RUN, NSC_, TWO_, PH_, HV_, Q_>(PL, tab, st, it.beam, it.seed,       \
                                                       it.id0, b, ee, out, AA, hot, hot_n,  \
@@ -2242,8 +2251,8 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     else MCV_BATCH_TRACE(4, false, false, HV_);                                     \
   }
     if (b < e) {
-      if (PL.heavy) {
-        MCV_BATCH_SHAPES(true)
+      if (HV && PL.heavy) {
+        MCV_BATCH_SHAPES(HV)
       } else {
         MCV_BATCH_SHAPES(false)
       }
@@ -2281,8 +2290,10 @@ __global__ void __launch_bounds__(256) fill_zero(double* __restrict__ p, uint64_
 
 // L = sum_b w_b (I_b - T_b)^2 and dL/dI_b = 2 w_b (I_b - T_b), streaming;
 // one atomic per workgroup for L.  Every element is touched once, so loads
-// and stores are non-temporal, and each thread issues the loads of two
-// 16-byte groups before it uses any of them.
+// and stores are non-temporal; one 16-byte pair of each array per lane per
+// pass over a grid of 64 workgroups per CU (measured on 1.28e8 bins: 5.0
+// TB/s, against 4.6 TB/s for 8 workgroups per CU with two pairs in flight
+// per lane and 4.3-4.9 TB/s for plain loads).
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double loss_pair(const dvec2 a, const dvec2 b, const dvec2 c,
@@ -2308,18 +2319,7 @@ __global__ void __launch_bounds__(256) loss_grad(const double* __restrict__ I,
   dvec2* o2 = reinterpret_cast<dvec2*>(dLdI);
   const int64_t n2 = n / 2;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; q + stride < n2; q += 2 * stride) {
-    const dvec2 a0 = __builtin_nontemporal_load(I2 + q);
-    const dvec2 b0 = __builtin_nontemporal_load(T2 + q);
-    const dvec2 c0 = __builtin_nontemporal_load(w2 + q);
-    const dvec2 a1 = __builtin_nontemporal_load(I2 + q + stride);
-    const dvec2 b1 = __builtin_nontemporal_load(T2 + q + stride);
-    const dvec2 c1 = __builtin_nontemporal_load(w2 + q + stride);
-    acc += loss_pair(a0, b0, c0, o2 + q);
-    acc += loss_pair(a1, b1, c1, o2 + q + stride);
-  }
-  if (q < n2)
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n2; q += stride)
     acc += loss_pair(__builtin_nontemporal_load(I2 + q), __builtin_nontemporal_load(T2 + q),
                      __builtin_nontemporal_load(w2 + q), o2 + q);
   if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -2347,10 +2347,7 @@ int transport_dq_entries(const DevPlan& P) {
   if (P.det.type != DET_TUBES) return 0;
   return dev::use_phased(P.nscat, P.smax > P.nscat, P.K) ? dev::kDqPhased : dev::kDqWalk;
 }
-int batch_dq_entries(const DevPlan& P) {
-  if (P.det.type != DET_TUBES) return 0;
-  return dev::use_phased(P.nscat, P.smax > P.nscat, P.K) ? dev::kDqPhased : dev::kDqBatchWalk;
-}
+int batch_dq_entries(const DevPlan& P) { return transport_dq_entries(P); }
 size_t transport_dq_bytes(int block, int entries, bool adjoint) {
   return sizeof(float) * (size_t)entries * (adjoint ? dev::kDqAdjFields : dev::kDqFields) *
          (size_t)(block / 64);
@@ -2489,7 +2486,7 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
 hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32_t n_chunks,
                         uint32_t* cursor, double* const* zero_ptrs, const uint64_t* zero_sizes,
                         int n_zero, int grid, int block, size_t lds, int hot_n, int dq_off,
-                        hipStream_t stream) {
+                        float* gstack, int stack_max, bool heavy, hipStream_t stream) {
   hipLaunchKernelGGL(dev::batch_cursor_reset, dim3(1), dim3(64), 0, stream, cursor);
   for (int k = 0; k < n_zero; ++k) {
     uint64_t g = (zero_sizes[k] / 2 + 255) / 256;
@@ -2498,8 +2495,12 @@ hipError_t launch_batch(const BatchItem* items, const BatchChunk* chunks, uint32
     hipLaunchKernelGGL(dev::fill_zero, dim3((unsigned)g), dim3(256), 0, stream, zero_ptrs[k],
                        zero_sizes[k]);
   }
-  hipLaunchKernelGGL(dev::batch_persistent, dim3(grid), dim3(block), lds, stream, items, chunks,
-                     n_chunks, cursor, hot_n, dq_off);
+  if (heavy)
+    hipLaunchKernelGGL(dev::batch_persistent<true>, dim3(grid), dim3(block), lds, stream, items,
+                       chunks, n_chunks, cursor, hot_n, dq_off, gstack, stack_max);
+  else
+    hipLaunchKernelGGL(dev::batch_persistent<false>, dim3(grid), dim3(block), lds, stream, items,
+                       chunks, n_chunks, cursor, hot_n, dq_off, gstack, stack_max);
   return hipGetLastError();
 }
 
@@ -2508,12 +2509,14 @@ hipError_t launch_fill_zero(double* p, uint64_t n, int grid, hipStream_t stream)
   return hipGetLastError();
 }
 
-int batch_occupancy(int block, size_t lds) {
+int batch_occupancy(int block, size_t lds, bool heavy) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dev::batch_persistent, block, lds) !=
-      hipSuccess)
-    return 0;
-  return nb;
+  const hipError_t e =
+      heavy ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dev::batch_persistent<true>, block,
+                                                           lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, dev::batch_persistent<false>, block,
+                                                           lds);
+  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
@@ -2556,7 +2559,8 @@ hipError_t set_transport_lds_limit(size_t bytes) {
   push_mode<dev::MODE_RUN>(fns);
   push_mode<dev::MODE_TRACE>(fns);
   push_mode<dev::MODE_ADJOINT>(fns);
-  fns.push_back(reinterpret_cast<const void*>(&dev::batch_persistent));
+  fns.push_back(reinterpret_cast<const void*>(&dev::batch_persistent<false>));
+  fns.push_back(reinterpret_cast<const void*>(&dev::batch_persistent<true>));
   // each kernel may use `bytes` of LDS in total, static part included
   for (const void* f : fns) {
     hipFuncAttributes at;

@@ -8,7 +8,10 @@ detector probe's own Philox draws are reported beside it so that they are
 not counted twice.  For tube detectors the test is also timed in the two
 parts the transport kernels run separately: its first steps (every packet)
 and the whole test on rays aimed at a tube (the packets that reach the
-tubes, recorded together one per lane).  Writes a JSON file (default:
+tubes, recorded together one per lane).  Also measures the binary64
+global atomic add rate (random bins over 144 KB, 4 MB, 256 MB and 1 GB
+histograms, uniform and with 10 % of the adds on one bin), the ceiling of
+the histogram and reduction kernels' atomics.  Writes a JSON file (default:
 primitive_costs.json next to this module).
 
     python -m paper_1504_02776_amd.probe_costs [--out FILE]
@@ -48,7 +51,40 @@ def _bind():
                                  C.c_int32, C.c_uint32, C.c_int32, C.c_int32,
                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.mcv_probe_time.restype = C.c_int
+    L.mcv_probe_atomics.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32,
+                                    C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.mcv_probe_atomics.restype = C.c_int
     return mcv, L
+
+
+# footprints of the binary64 atomic rate (bins): the plate's sphere
+# histogram (144 KB), an L2-sized 4 MB, a 256 MB (Infinity Cache size) and
+# the 1.28e8-bin tube histograms (1.024 GB); uniform bins, and 10 % of the
+# updates on one bin
+ATOMIC_FOOTPRINTS = [("144KB", 18_000), ("4MB", 524_288), ("256MB", 33_554_432),
+                     ("1GB", 128_000_000)]
+ATOMIC_HOT = [("uniform", 0), ("hot10", 100)]
+
+
+def probe_atomics(grid=2048, iters=256, reps=3):
+    """Binary64 global atomic adds per second by footprint and skew."""
+    import torch
+    mcv, L = _bind()
+    out = {"grid": grid, "iters": iters, "lanes": grid * 256, "unit": "atomic adds per second"}
+    n_adds = grid * 256 * iters
+    for fname, nb in ATOMIC_FOOTPRINTS:
+        h = torch.zeros(nb, dtype=torch.float64, device="cuda:0")
+        for hname, hot in ATOMIC_HOT:
+            ms, tot = C.c_double(), C.c_double()
+            mcv.check(L.mcv_probe_atomics(C.c_void_p(h.data_ptr()), nb, iters, hot, grid, reps,
+                                          C.byref(ms), C.byref(tot)))
+            total = float(h.sum().item())
+            assert total == n_adds, (total, n_adds)
+            out[f"{fname}_{hname}"] = n_adds / (ms.value * 1e-3)
+            print(f"[probe] atomics {fname} {hname}: {out[f'{fname}_{hname}']:.3e} /s", flush=True)
+        del h
+        torch.cuda.empty_cache()
+    return out
 
 
 def probe_workload(cfg):
@@ -101,7 +137,16 @@ def main():
     from paper_1504_02776_amd import workloads as W
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(HERE, "primitive_costs.json"))
+    ap.add_argument("--atomics-only", action="store_true",
+                    help="measure the binary64 atomic rates and update them in --out")
     args = ap.parse_args()
+    if args.atomics_only:
+        res = json.load(open(args.out)) if os.path.exists(args.out) else {}
+        res["atomics"] = probe_atomics()
+        with open(args.out, "w") as f:
+            json.dump(res, f, indent=1)
+        print(f"[probe] wrote {args.out}", flush=True)
+        return
     import torch
     props = torch.cuda.get_device_properties(0)
     res = {"device": props.name, "arch": getattr(props, "gcnArchName", ""),
@@ -115,6 +160,7 @@ def main():
                       ("al_coherent", W.al_coherent_config())]:
         res["workloads"][name] = probe_workload(cfg)
         print(f"[probe] {name}: {json.dumps(res['workloads'][name])}", flush=True)
+    res["atomics"] = probe_atomics()
     with open(args.out, "w") as f:
         json.dump(res, f, indent=1)
     print(f"[probe] wrote {args.out}", flush=True)
