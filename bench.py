@@ -325,20 +325,49 @@ def bench_adjoint(torch, mcv, W, stream, reps):
         plan.run(I, stream=stream)
         mcv.loss_grad(I, T, wgt, dLdI, loss, stream=stream)
         plan.adjoint(pm, dLdI, grad, stream=stream)
+    # the same step with the adjoint tape: the forward run writes one entry
+    # per recorded packet, the backward pass reads them (no re-trace)
+    tape = plan.tape(8_000_000)
+
+    def forward_tape():
+        mcv.zero(I, stream=stream)
+        tape[1].zero_()
+        plan.run_tape(pm, I, tape, stream=stream)
+
+    def step_tape():
+        forward_tape()
+        loss.zero_()
+        grad.zero_()
+        mcv.loss_grad(I, T, wgt, dLdI, loss, stream=stream)
+        plan.adjoint_tape(pm, tape, dLdI, grad, stream=stream)
     forward_ms = timed(torch, stream, forward, reps)
     t_step = timed(torch, stream, step, reps)
     t_loss = timed(torch, stream, lambda: mcv.loss_grad(I, T, wgt, dLdI, loss, stream=stream),
                    reps)
     t_adj = timed(torch, stream, lambda: plan.adjoint(pm, dLdI, grad, stream=stream), reps)
+    t_step_tape = timed(torch, stream, step_tape, reps)
+    t_fwd_tape = timed(torch, stream, forward_tape, reps)
+    entries = int(tape[1].item())
+    t_adj_tape = timed(torch, stream, lambda: plan.adjoint_tape(pm, tape, dLdI, grad,
+                                                                stream=stream), reps)
+    # a plain three-input stream of the same arrays (torch's elementwise
+    # kernel, 32 B per bin) as the practical ceiling of the loss pass
+    t_stream = timed(torch, stream, lambda: torch.addcmul(I, T, wgt, out=dLdI), reps)
     nb = I.numel()
     out = {"workload": f"powder cylinder 1e7, gradient w.r.t. {grad.numel()} parameters "
                        "(500 DOS bins, sigma_abs, sigma_inc)",
            "s_per_step": t_step / 1e3, "forward_s": forward_ms / 1e3,
            "ratio_to_forward": t_step / forward_ms, "adjoint_kernel_ms": t_adj,
+           "tape": {"s_per_step": t_step_tape / 1e3,
+                    "ratio_to_forward": t_step_tape / forward_ms,
+                    "forward_with_tape_ms": t_fwd_tape, "backward_ms": t_adj_tape,
+                    "entries": entries, "tape_bytes": 4 * 12 * entries,
+                    "backward_GBps": 4 * 12 * entries / (t_adj_tape / 1e3) / 1e9},
            "loss_grad_ms": t_loss,
            "loss_grad_GBps": 4 * 8 * nb / (t_loss / 1e3) / 1e9,
-           "loss_grad_hbm_frac": 4 * 8 * nb / (t_loss / 1e3) / HBM_PEAK}
-    del plan, I, dLdI, T, wgt
+           "loss_grad_hbm_frac": 4 * 8 * nb / (t_loss / 1e3) / HBM_PEAK,
+           "torch_addcmul_same_arrays_GBps": 4 * 8 * nb / (t_stream / 1e3) / 1e9}
+    del plan, I, dLdI, T, wgt, tape
     torch.cuda.empty_cache()
     return out
 

@@ -418,6 +418,46 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
                        uint64_t first, uint64_t n, const double* dL_dI, double* grad,
                        void* stream);
 
+/* Adjoint tape: the same gradient as mcv_adjoint without re-tracing.  A
+ * forward run writes, for every packet it records (bin >= 0), one entry with
+ * the bin, the recorded value and the packet's carry for the parameter map
+ * (d log w / d sigma_abs, d log w / d sigma, the Debye-Waller sum A, draw
+ * counts, table indices: the terms mcv_adjoint gathers at a detection); the
+ * backward pass reads the entries instead of tracing the histories again.
+ * Layout: MCV_TAPE_FIELDS x capacity uint32 words, field-major ([field]
+ * [entry]): 0 bin, 1 value (binary32 bits), 2 d sigma_abs, 3 d sigma, 4 A
+ * (binary32 bits), 5 counts (DOS draws low 16 bits, table indices high 16),
+ * 6..11 table indices (16 bits each, two per word).  48 bytes per recorded
+ * packet: 5.3e6 entries (254 MB) for 1e7 histories of the powder cylinder
+ * seen by tubes. */
+#define MCV_TAPE_FIELDS 12
+
+/* mcv_run (histogram hist, and Squared weights into hist_w2 when not NULL;
+ * either may be NULL) that also appends one tape entry per recorded packet
+ * to tape (device, capacity entries per field, 4-byte aligned), in
+ * arbitrary order.  *n_tape_dev (device uint64, 8-byte aligned) is advanced
+ * by the number of recorded packets: zeroed by the caller it receives their
+ * count, which may exceed capacity (entries beyond it are not written and
+ * the tape is incomplete).  The map must be the one later given to
+ * mcv_adjoint_tape.  Errors as mcv_adjoint; MCV_EINVAL for a null or
+ * misaligned tape or counter; MCV_EUNSUPPORTED for 2^32 or more bins. */
+mcv_status mcv_run_tape(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam, uint64_t seed,
+                        uint64_t first, uint64_t n, double* hist, double* hist_w2, uint32_t* tape,
+                        uint64_t capacity, uint64_t* n_tape_dev, void* stream);
+
+/* Adds to grad[nparams] (device binary64, zeroed by the caller) the
+ * gradient that mcv_adjoint computes for the histories of the run that
+ * wrote the tape: the sum over its entries of dL_dI[bin] * value *
+ * d log(value)/d theta (dL_dI: device binary64 [nbins]).  Reads the count
+ * from *n_tape_dev on the device (no host synchronisation); if it exceeds
+ * capacity (an incomplete tape) every entry of grad becomes NaN.  Uses the
+ * plan's binary64 workspace as mcv_adjoint does (concurrent adjoint calls
+ * on one plan race).  Errors: MCV_EINVAL, MCV_EUNSUPPORTED, MCV_ENOMEM,
+ * MCV_EHIP. */
+mcv_status mcv_adjoint_tape(mcv_plan p, const mcv_param_map* pm, const uint32_t* tape,
+                            uint64_t capacity, const uint64_t* n_tape_dev, const double* dL_dI,
+                            double* grad, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): mcv_adjoint with
  * its binary64 workspace in static device memory of the library (32768

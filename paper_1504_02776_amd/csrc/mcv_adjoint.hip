@@ -15,8 +15,9 @@
 // cell c contributes 1/S_c.  The transport kernel gathers dL/dI at each
 // recorded packet and accumulates g = dL/dI value per table entry and the two
 // scalars sum(g A), sum(g n_draws); this file prepares the 1/theta and dense
-// tables on the device from the plan's raw binary64 tables and applies the
-// dense terms at the end.
+// tables on the device from the plan's raw binary64 tables, applies the
+// dense terms at the end, and holds the pass that accumulates the same
+// partials from a tape written by a forward run instead of a re-trace.
 //
 // Workspace layout (binary64): [0] sum g A, [1] sum g n_draws, [2] dnorm,
 // [3] unused, [4, 4 + nt) 1/table value (nt = nb + nc: DOS bins then grid
@@ -83,7 +84,89 @@ __global__ void adjoint_finalize(double* __restrict__ grad, const double* __rest
   if (b < nb) grad[b] += ws[4 + nb + nc + b] * ws[0] + ws[2] * ws[1];
 }
 
+constexpr int kTapeThreads = 256;
+
+// The backward pass over an adjoint tape (one entry per packet a forward run
+// recorded, with its carry): per entry g = dL/dI[bin] * value, and the same
+// partials as the re-trace accumulates at a detection: g times the carried
+// d log w / d sigma_abs and d sigma, g A and g n_draws (wave sums into LDS),
+// and g per carried table index (LDS partials when the table fits, scaled
+// by 1/table at the flush; global atomics otherwise).  The entries are read
+// field by field ([field][entry], coalesced).  A tape whose counter exceeds
+// its capacity is incomplete: the gradient entries become NaN.
+template <bool LDS>
+__global__ void __launch_bounds__(kTapeThreads)
+tape_adjoint(const uint32_t* __restrict__ tape, uint64_t cap,
+             const unsigned long long* __restrict__ n_tape, const double* __restrict__ dLdI,
+             int nb, int nc, double* __restrict__ grad, double* __restrict__ ws) {
+  extern __shared__ double acc[];  // [table partials (LDS) | 4 scalars]
+  const int ntab = LDS ? nb + nc : 0;
+  const int np = nb + nc;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < ntab + 4; i += kTapeThreads) acc[i] = 0.0;
+  __syncthreads();
+  const unsigned long long count = *n_tape;
+  if (count > cap) {
+    if (blockIdx.x == 0)
+      for (int i = tid; i < np + 2; i += kTapeThreads) grad[i] = __builtin_nan("");
+    return;
+  }
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const uint64_t stride = (uint64_t)gridDim.x * kTapeThreads;
+  for (uint64_t i = (uint64_t)blockIdx.x * kTapeThreads + tid; i < count; i += stride) {
+    const uint32_t bin = tape[i];
+    const double gv = dLdI[bin] * (double)__uint_as_float(tape[cap + i]);
+    if (gv == 0.0) continue;
+    s0 += gv * (double)__uint_as_float(tape[2 * cap + i]);
+    s1 += gv * (double)__uint_as_float(tape[3 * cap + i]);
+    s2 += gv * (double)__uint_as_float(tape[4 * cap + i]);
+    const uint32_t cnt = tape[5 * cap + i];
+    s3 += gv * (double)(cnt & 0xFFFFu);
+    const uint32_t ns = cnt >> 16;
+    uint32_t word = 0u;
+    for (uint32_t k = 0; k < ns; ++k) {
+      if ((k & 1u) == 0u) word = tape[(6 + (k >> 1)) * cap + i];
+      const uint32_t idx = (word >> (16u * (k & 1u))) & 0xFFFFu;
+      if (LDS) atomicAdd(&acc[idx], gv);
+      else unsafeAtomicAdd(&grad[idx], gv * ws[4 + idx]);
+    }
+  }
+  const double sv[4] = {s0, s1, s2, s3};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double v = sv[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((tid & 63) == 0 && v != 0.0) atomicAdd(&acc[ntab + k], v);
+  }
+  __syncthreads();
+  for (int i = tid; i < ntab; i += kTapeThreads)
+    if (acc[i] != 0.0) unsafeAtomicAdd(&grad[i], acc[i] * ws[4 + i]);
+  if (tid == 0) {
+    if (acc[ntab] != 0.0) unsafeAtomicAdd(&grad[np], acc[ntab]);
+    if (acc[ntab + 1] != 0.0) unsafeAtomicAdd(&grad[np + 1], acc[ntab + 1]);
+    if (acc[ntab + 2] != 0.0) unsafeAtomicAdd(&ws[0], acc[ntab + 2]);
+    if (acc[ntab + 3] != 0.0) unsafeAtomicAdd(&ws[1], acc[ntab + 3]);
+  }
+}
+
 }  // namespace dev
+
+// LDS of the tape pass's table partials: at most this many entries
+constexpr int kTapeLdsTable = 8000;
+
+hipError_t launch_tape_adjoint(const uint32_t* tape, uint64_t cap, const unsigned long long* n,
+                               const double* dLdI, int nb, int nc, double* grad, double* ws,
+                               int grid, hipStream_t stream) {
+  const bool lds = nb + nc <= kTapeLdsTable;
+  const size_t bytes = sizeof(double) * (size_t)((lds ? nb + nc : 0) + 4);
+  if (lds)
+    hipLaunchKernelGGL(dev::tape_adjoint<true>, dim3(grid), dim3(dev::kTapeThreads), bytes, stream,
+                       tape, cap, n, dLdI, nb, nc, grad, ws);
+  else
+    hipLaunchKernelGGL(dev::tape_adjoint<false>, dim3(grid), dim3(dev::kTapeThreads), bytes,
+                       stream, tape, cap, n, dLdI, nb, nc, grad, ws);
+  return hipGetLastError();
+}
 
 // The workspace of mcv_adjoint_noalloc, for callers that cannot allocate:
 // one copy per device, held until the process ends; every such call on a

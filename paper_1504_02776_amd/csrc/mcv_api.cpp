@@ -28,7 +28,7 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
                             DevEvent* ev, uint64_t ev_cap, unsigned long long* n_ev,
                             const AdjArgs* adj, float* gstack, const DetArgs* det,
-                            hipStream_t stream);
+                            const TapeArgs* tape, hipStream_t stream);
 hipError_t det_zero(unsigned long long* n, hipStream_t stream);
 hipError_t det_sort(void* temp, size_t* temp_bytes, const uint64_t* kin, uint64_t* kout,
                     const float* vin, float* vout, uint64_t count, int end_bit,
@@ -39,6 +39,9 @@ hipError_t launch_adjoint_prepare(const double* theta, int nb, double de, double
                                   const double* cells, int nc, double* ws, hipStream_t stream);
 hipError_t launch_adjoint_finalize(double* grad, const double* ws, int nb, int nc,
                                    hipStream_t stream);
+hipError_t launch_tape_adjoint(const uint32_t* tape, uint64_t cap, const unsigned long long* n,
+                               const double* dLdI, int nb, int nc, double* grad, double* ws,
+                               int grid, hipStream_t stream);
 hipError_t adjoint_scratch_setup(int device);
 double* adjoint_scratch(int device);
 hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
@@ -989,7 +992,7 @@ mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t firs
   hipError_t e = launch_transport(p->d_plan, p->host, p->d_tables, B,
                                   seed, first, n, (int)grid, p->block, per_wave, hist, hist_w2,
                                   rec, cap, n_out, ev, ev_cap, n_ev, nullptr, p->d_stack, nullptr,
-                                  (hipStream_t)stream);
+                                  nullptr, (hipStream_t)stream);
   if (cur != p->device) (void)hipSetDevice(cur);
   if (e != hipSuccess) return hipfail(e, "transport launch");
   return MCV_OK;
@@ -1029,7 +1032,7 @@ static mcv_status run_deterministic(mcv_plan p, const mcv_beam* beam, uint64_t s
     if (e == hipSuccess)
       e = launch_transport(p->d_plan, p->host, p->d_tables, B, seed, cf, m, (int)grid, p->block,
                            per_wave, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr,
-                           nullptr, p->d_stack, &D, stream);
+                           nullptr, p->d_stack, &D, nullptr, stream);
     unsigned long long count = 0;
     if (e == hipSuccess)
       e = hipMemcpyAsync(&count, p->d_det_n, sizeof(count), hipMemcpyDeviceToHost, stream);
@@ -1270,27 +1273,48 @@ mcv_status check_param_map(mcv_plan p, const mcv_param_map* pm, AdjSetup* out) {
   return MCV_OK;
 }
 
+// the kernels' view of a checked parameter map
+AdjArgs adj_args(const mcv_param_map* pm, const AdjSetup& A, const double* dL_dI, double* grad,
+                 double* ws) {
+  AdjArgs AA = {};
+  AA.dos_s = A.nb > 0 ? pm->dos_scatterer : -1;
+  AA.dos_k = pm->dos_kernel;
+  AA.mp_k = A.nb > 0 ? pm->multiphonon_kernel : -1;
+  AA.sqe_s = A.nc > 0 ? pm->sqe_scatterer : -1;
+  AA.sqe_k = pm->sqe_kernel;
+  AA.abs_s = pm->abs_scatterer;
+  AA.sig_s = pm->sigma_scatterer;
+  AA.sig_k = pm->sigma_kernel;
+  AA.nb = A.nb;
+  AA.nc = A.nc;
+  AA.sparse_lds = A.sparse_lds;
+  AA.dLdI = dL_dI;
+  AA.grad = grad;
+  AA.ws = ws;
+  return AA;
+}
+
+// the plan-owned binary64 workspace of the adjoint (allocated on first use,
+// grown when a map needs more); device of the plan current
+mcv_status adjoint_workspace(mcv_plan p, const AdjSetup& A) {
+  const size_t need = 4 + 2 * (size_t)A.nb + (size_t)A.nc;
+  if (p->adj.cap >= need) return MCV_OK;
+  if (p->adj.ws) (void)hipFree(p->adj.ws);
+  p->adj.ws = nullptr;
+  p->adj.cap = 0;
+  if (hipMalloc(&p->adj.ws, need * sizeof(double)) != hipSuccess)
+    return fail(MCV_ENOMEM, "hipMalloc adjoint workspace");
+  p->adj.cap = need;
+  return MCV_OK;
+}
+
 // the workspace the adjoint kernels use: prepare -> transport -> finalize
 mcv_status adjoint_launch(mcv_plan p, const mcv_param_map* pm, const AdjSetup& A,
                           const DevBeam& B, uint64_t seed, uint64_t first, uint64_t n,
                           const double* dL_dI, double* grad, double* ws, hipStream_t stream) {
   hipError_t e = launch_adjoint_prepare(A.theta, A.nb, A.de, A.kT, A.h2m, A.cells, A.nc, ws, stream);
   if (e == hipSuccess && n > 0) {
-    AdjArgs AA = {};
-    AA.dos_s = A.nb > 0 ? pm->dos_scatterer : -1;
-    AA.dos_k = pm->dos_kernel;
-    AA.mp_k = A.nb > 0 ? pm->multiphonon_kernel : -1;
-    AA.sqe_s = A.nc > 0 ? pm->sqe_scatterer : -1;
-    AA.sqe_k = pm->sqe_kernel;
-    AA.abs_s = pm->abs_scatterer;
-    AA.sig_s = pm->sigma_scatterer;
-    AA.sig_k = pm->sigma_kernel;
-    AA.nb = A.nb;
-    AA.nc = A.nc;
-    AA.sparse_lds = A.sparse_lds;
-    AA.dLdI = dL_dI;
-    AA.grad = grad;
-    AA.ws = ws;
+    const AdjArgs AA = adj_args(pm, A, dL_dI, grad, ws);
     uint64_t grid, per_wave;
     grid_shape(p, n, A.block, &grid, &per_wave);
     if (p->d_stack &&
@@ -1298,7 +1322,7 @@ mcv_status adjoint_launch(mcv_plan p, const mcv_param_map* pm, const AdjSetup& A
       return fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
     e = launch_transport(p->d_plan, p->host, p->d_tables, B, seed, first, n, (int)grid, A.block,
                          per_wave, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, &AA,
-                         p->d_stack, nullptr, stream);
+                         p->d_stack, nullptr, nullptr, stream);
   }
   if (e == hipSuccess) e = launch_adjoint_finalize(grad, ws, A.nb, A.nc, stream);
   if (e != hipSuccess) return hipfail(e, "adjoint launch");
@@ -1329,18 +1353,87 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
-  const size_t need = 4 + 2 * (size_t)A.nb + (size_t)A.nc;
-  if (p->adj.cap < need) {
-    if (p->adj.ws) (void)hipFree(p->adj.ws);
-    p->adj.ws = nullptr;
-    p->adj.cap = 0;
-    if (hipMalloc(&p->adj.ws, need * sizeof(double)) != hipSuccess)
-      st = fail(MCV_ENOMEM, "hipMalloc adjoint workspace");
-    else
-      p->adj.cap = need;
-  }
+  st = adjoint_workspace(p, A);
   if (st == MCV_OK)
     st = adjoint_launch(p, pm, A, B, seed, first, n, dL_dI, grad, p->adj.ws, (hipStream_t)stream);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  return st;
+}
+
+mcv_status mcv_run_tape(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam, uint64_t seed,
+                        uint64_t first, uint64_t n, double* hist, double* hist_w2, uint32_t* tape,
+                        uint64_t capacity, uint64_t* n_tape_dev, void* stream) {
+  static_assert(MCV_TAPE_FIELDS == kTapeFields, "tape layout");
+  if (!p) return fail(MCV_EINVAL, "null plan");
+  AdjSetup A;
+  mcv_status st = check_param_map(p, pm, &A);
+  if (st != MCV_OK) return st;
+  if (!tape || !n_tape_dev) return fail(MCV_EINVAL, "null tape or counter");
+  if (((uintptr_t)tape & 3u) || ((uintptr_t)n_tape_dev & 7u))
+    return fail(MCV_EINVAL, "tape must be 4-byte and its counter 8-byte aligned");
+  if (p->nbins > (int64_t)0xFFFFFFFF)
+    return fail(MCV_EUNSUPPORTED, "the tape needs fewer than 2^32 detector bins");
+  DevBeam B;
+  if ((st = make_beam(p, beam, &B)) != MCV_OK) return st;
+  if ((st = check_ids(B, first, n)) != MCV_OK) return st;
+  if (n == 0) return MCV_OK;
+  // LDS: tables, the histogram bin cache and the detection queues with the
+  // carry
+  const size_t lim = (size_t)160 * 1024 - transport_static_lds();
+  const int dq_n = transport_dq_entries(p->host);
+  auto lds = [&](int b) {
+    return transport_lds_bytes(p->host.n_tables, 0, b, kLdsNoAdjoint, p->host.hot_n) +
+           transport_dq_bytes(b, dq_n, true);
+  };
+  int block = p->block;
+  while (block > 64 && lds(block) > lim) block -= 64;
+  if (lds(block) > lim) return fail(MCV_EUNSUPPORTED, "tape run does not fit in LDS");
+  uint64_t grid, per_wave;
+  grid_shape(p, n, block, &grid, &per_wave);
+  if (p->d_stack &&
+      grid * block * (size_t)p->host.stack_cap * (kFields + kAdjFields) > p->stack_floats)
+    return fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  const AdjArgs AA = adj_args(pm, A, nullptr, nullptr, nullptr);
+  const TapeArgs T = {tape, capacity, reinterpret_cast<unsigned long long*>(n_tape_dev)};
+  const hipError_t e = launch_transport(p->d_plan, p->host, p->d_tables, B, seed, first, n,
+                                        (int)grid, block, per_wave, hist, hist_w2, nullptr, 0,
+                                        nullptr, nullptr, 0, nullptr, &AA, p->d_stack, nullptr, &T,
+                                        (hipStream_t)stream);
+  if (cur != p->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return hipfail(e, "tape run launch");
+  return MCV_OK;
+}
+
+mcv_status mcv_adjoint_tape(mcv_plan p, const mcv_param_map* pm, const uint32_t* tape,
+                            uint64_t capacity, const uint64_t* n_tape_dev, const double* dL_dI,
+                            double* grad, void* stream) {
+  if (!p) return fail(MCV_EINVAL, "null plan");
+  AdjSetup A;
+  mcv_status st = check_param_map(p, pm, &A);
+  if (st != MCV_OK) return st;
+  if (!tape || !n_tape_dev || !dL_dI || !grad)
+    return fail(MCV_EINVAL, "null tape, counter, dL_dI or grad");
+  if (((uintptr_t)tape & 3u) || ((uintptr_t)n_tape_dev & 7u))
+    return fail(MCV_EINVAL, "tape must be 4-byte and its counter 8-byte aligned");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != p->device) (void)hipSetDevice(p->device);
+  st = adjoint_workspace(p, A);
+  if (st == MCV_OK) {
+    double* ws = p->adj.ws;
+    const hipStream_t s = (hipStream_t)stream;
+    hipError_t e =
+        launch_adjoint_prepare(A.theta, A.nb, A.de, A.kT, A.h2m, A.cells, A.nc, ws, s);
+    if (e == hipSuccess)
+      e = launch_tape_adjoint(tape, capacity,
+                              reinterpret_cast<const unsigned long long*>(n_tape_dev), dL_dI, A.nb,
+                              A.nc, grad, ws, p->cus * 4, s);
+    if (e == hipSuccess) e = launch_adjoint_finalize(grad, ws, A.nb, A.nc, s);
+    if (e != hipSuccess) st = hipfail(e, "tape adjoint launch");
+  }
   if (cur != p->device) (void)hipSetDevice(cur);
   return st;
 }

@@ -171,6 +171,17 @@ struct DetArgs {
   int32_t lin_bits, id_bits;
 };
 
+// Adjoint tape: one entry per recorded packet (bin >= 0) of a forward run,
+// [field][entry] with `cap` entries per field: bin, value (binary32 bits),
+// then the packet's adjoint carry (kAdjFields words: d log w / d sigma_abs,
+// d log w / d sigma, A, counts, packed table indices).
+constexpr int kTapeFields = 2 + kAdjFields;
+struct TapeArgs {
+  uint32_t* words;
+  uint64_t cap;
+  unsigned long long* n;  // device counter, advanced by the entries recorded
+};
+
 struct DevBeam {
   int32_t type;  // 1 mono, 2 gauss, 3 saved
   float E, sigma_rel, W, H, z0;

@@ -1031,6 +1031,7 @@ struct Adj {
   uint32_t cnt;
   uint32_t s[kAdjMaxSparse / 2];
 };
+static_assert(sizeof(Adj) == 4 * kAdjFields, "adjoint carry words");
 
 __device__ __forceinline__ Adj adj_zero() {
   Adj a;
@@ -1423,7 +1424,34 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-enum { MODE_RUN = 0, MODE_TRACE = 1, MODE_ADJOINT = 2 };
+// MODE_TAPE: the run's histogram plus, per recorded packet, a tape entry
+// with the adjoint carry (for a later pass that needs no re-trace).
+enum { MODE_RUN = 0, MODE_TRACE = 1, MODE_ADJOINT = 2, MODE_TAPE = 3 };
+
+// modes whose packets carry the adjoint terms
+__host__ __device__ constexpr bool carries(int mode) {
+  return mode == MODE_ADJOINT || mode == MODE_TAPE;
+}
+
+// Resident waves per SIMD a transport kernel is compiled for, i.e. its
+// register budget (512 / waves VGPRs per lane).  The run kernels take 4.
+// The adjoint carry (10 words per packet) and the trace records need more
+// registers: at 4 waves the walk-loop kernels of those modes spill 40-180
+// VGPRs.  Measured (ms; 4 / 3 / 2 waves): powder at 1e7, re-trace 1.67 /
+// 1.90 / 2.38 and histogram fill + tape run 2.18 / 1.99 / 2.49; crystal in
+// its can at 1e7, re-trace 29.3 / 23.8 / 19.4 and tape run 31.5 / 23.3 /
+// 19.3.  So walk loops take 2 waves outside the run mode, the phased loop 4
+// (3 for the tape run).
+__host__ __device__ constexpr int kernel_waves(int mode, bool phased) {
+  return mode == MODE_RUN ? MCV_WAVES_PER_EU
+         : !phased        ? 2
+         : mode == MODE_TAPE ? 3
+                             : 4;
+}
+__host__ __device__ constexpr int kernel_waves_max(int mode, bool phased) {
+  return kernel_waves(mode, phased) > MCV_WAVES_PER_EU_MAX ? kernel_waves(mode, phased)
+                                                           : MCV_WAVES_PER_EU_MAX;
+}
 
 // where recorded values go (global memory only: the backend takes pointers
 // that arrive in kernel arguments to be global, so LDS addresses never
@@ -1450,6 +1478,10 @@ struct Sinks {
   unsigned long long* n_det;
   uint64_t det_first;
   int det_lin_bits, det_id_bits;
+  // adjoint tape (MODE_TAPE)
+  uint32_t* tape;
+  uint64_t tape_cap;
+  unsigned long long* n_tape;
 };
 
 // Event mode: every wave stages its events in LDS (kEvStage entries) and
@@ -1647,6 +1679,33 @@ __device__ __forceinline__ void hist_add(double* hist, double* hist_w2, double* 
   }
 }
 
+// Appends one tape entry per active lane with a recorded packet (any subset
+// of the wave may be active): one counter atomic per call, entries of a call
+// at consecutive slots.  Entries beyond the capacity are counted, not
+// written.
+__device__ __forceinline__ void tape_append(const Sinks& out, int bin, float value, const Adj& a) {
+  const bool rec = bin >= 0;
+  const uint64_t m = __ballot(rec);
+  if (m == 0ull) return;
+  const int lead = __ffsll((unsigned long long)m) - 1;
+  unsigned long long base = 0ull;
+  if ((int)__lane_id() == lead) base = atomicAdd(out.n_tape, (unsigned long long)__popcll(m));
+  base = readlane64(base, lead);
+  if (!rec) return;
+  const uint64_t slot = base + (uint64_t)__popcll(m & lanemask_lt());
+  if (slot >= out.tape_cap) return;
+  const uint64_t c = out.tape_cap;
+  uint32_t* t = out.tape + slot;
+  __builtin_nontemporal_store((uint32_t)bin, t);
+  __builtin_nontemporal_store(__float_as_uint(value), t + c);
+  __builtin_nontemporal_store(__float_as_uint(a.dabs), t + 2 * c);
+  __builtin_nontemporal_store(__float_as_uint(a.dsig), t + 3 * c);
+  __builtin_nontemporal_store(__float_as_uint(a.A), t + 4 * c);
+  __builtin_nontemporal_store(a.cnt, t + 5 * c);
+#pragma unroll
+  for (int w = 0; w < kAdjMaxSparse / 2; ++w) __builtin_nontemporal_store(a.s[w], t + (6 + w) * c);
+}
+
 // Lane states of the transport loop
 enum { LANE_NEED = 0, LANE_SETUP = 1, LANE_FLY = 2, LANE_DET = 3, LANE_DONE = 4 };
 
@@ -1661,11 +1720,12 @@ __device__ __forceinline__ void record_packet(const DevPlan& PL, const float* ta
                                               const Pk& cur, const Adj& ca, uint64_t hid,
                                               uint64_t seed, int& hbin, float& hval,
                                               double* sc_out = nullptr) {
-  constexpr bool ADJ = MODE == MODE_ADJOINT;
+  constexpr bool GATHER = MODE == MODE_ADJOINT;
   const Hit hh = PL.det.type == DET_SPHERE ? detect_sphere(PL.det, cur)
                                            : detect_tubes(PL.det, tab, cur, hid, seed);
+  if (MODE == MODE_TAPE) tape_append(out, hh.bin, hh.value, ca);
   if (hh.bin >= 0) {
-    if (ADJ) {
+    if (GATHER) {
       const double gv = AA.dLdI[hh.bin] * (double)hh.value;
       if (gv != 0.0) {
         // LDS partials: [table entries (when they fit) | 4 scalars]
@@ -1778,7 +1838,8 @@ template <int MODE, int Q>
 __device__ __forceinline__ void dq_run(const DevPlan& PL, const float* tab, const Sinks& out,
                                        const AdjArgs& AA, double* acc, int hot_n, const float* q,
                                        int n, uint64_t seed) {
-  constexpr bool ADJ = MODE == MODE_ADJOINT;
+  constexpr bool ADJ = carries(MODE);
+  constexpr bool GATHER = MODE == MODE_ADJOINT;
   constexpr int kDqEntries = Q;
   const int nl = __popcll(__ballot(1));
   for (int base = 0; base < n; base += nl) {
@@ -1812,9 +1873,9 @@ __device__ __forceinline__ void dq_run(const DevPlan& PL, const float* tab, cons
           ca.s[w] = __float_as_uint(b[(16 + w) * kDqEntries]);
       }
       record_packet<MODE>(PL, tab, out, AA, acc, P, ca, hid, seed, hbin, hval,
-                          ADJ ? sc : nullptr);
+                          GATHER ? sc : nullptr);
     }
-    if (ADJ) {
+    if (GATHER) {
       double* dst = acc + (AA.sparse_lds ? AA.nb + AA.nc : 0);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -1858,7 +1919,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
                                              uint64_t begin, uint64_t end, const Sinks& out,
                                              const AdjArgs& AA, double* acc, int hot_n,
                                              int nthreads, int tid, float* dq) {
-  constexpr bool ADJ = MODE == MODE_ADJOINT;
+  constexpr bool ADJ = carries(MODE);
   static_assert(DQ == 0 || DQ == kDqPhased, "phased-loop queue size");
   const uint64_t lt = lanemask_lt();
   Pk cur;
@@ -1959,7 +2020,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
         state = LANE_DET;
       }
     }
-    if (!ADJ && !DQ && (out.hist != nullptr || out.hist_w2 != nullptr))
+    if (MODE != MODE_ADJOINT && !DQ && (out.hist != nullptr || out.hist_w2 != nullptr))
       hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
   }
 }
@@ -1970,7 +2031,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
                                            uint64_t begin, uint64_t end, const Sinks& out,
                                            const AdjArgs& AA, double* acc, int hot_n,
                                            int nthreads, int tid, float* dq) {
-  constexpr bool ADJ = MODE == MODE_ADJOINT;
+  constexpr bool ADJ = carries(MODE);
   static_assert(DQ == 0 || DQ == kDqWalk, "walk-loop queue size");
   constexpr bool DEFER = NSC > 1 || TWO || HEAVY;
   const uint64_t lt = lanemask_lt();
@@ -2056,7 +2117,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
         has = false;
       }
     }
-    if (!ADJ && !DQ && (out.hist != nullptr || out.hist_w2 != nullptr))
+    if (MODE != MODE_ADJOINT && !DQ && (out.hist != nullptr || out.hist_w2 != nullptr))
       hist_add(out.hist, out.hist_w2, acc, hot_n, PL.hot_all != 0, hbin, hval);
   }
 }
@@ -2097,13 +2158,15 @@ __device__ __forceinline__ void stage_plan(DevPlan& PL, float* dyn, const DevPla
 // the sample.  MODE_ADJOINT: re-traces the same histories (same random
 // numbers) and accumulates dL/dtheta = sum over recorded packets of
 // dL/dI[bin] * value * d log(w)/d theta into FP64 LDS partials, flushed once
-// per workgroup.
+// per workgroup.  MODE_TAPE: the run's histogram, and the packets carry the
+// adjoint terms as in MODE_ADJOINT, written to the tape when recorded.
 template <int MODE, int NSC, bool TWO, bool PHASED, bool HEAVY, int DQ = 0>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(MCV_WAVES_PER_EU, MCV_WAVES_PER_EU_MAX)))
+__attribute__((amdgpu_waves_per_eu(kernel_waves(MODE, PHASED), kernel_waves_max(MODE, PHASED))))
 transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, DevBeam beam,
           uint64_t seed, uint64_t first, uint64_t n, uint64_t per_wave, Sinks out, AdjArgs AA) {
-  constexpr bool ADJ = MODE == MODE_ADJOINT;
+  constexpr bool ADJ = MODE == MODE_ADJOINT;  // LDS partials instead of the bin cache
+  constexpr bool CARRY = carries(MODE);
   __shared__ DevPlan PL;
   extern __shared__ __align__(16) float dyn[];
   const int tid = threadIdx.x;
@@ -2125,7 +2188,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   // the workgroup's packet stacks in device memory ([slot][field][lane],
   // consecutive lanes at consecutive addresses; a lane pushes only the
   // second and later children of a flight)
-  constexpr int NFS = kFields + (ADJ ? kAdjFields : 0);
+  constexpr int NFS = kFields + (CARRY ? kAdjFields : 0);
   float* st = out.gstack + (size_t)blockIdx.x * PL.stack_cap * NFS * nthreads;
   // LDS after the bin cache: the waves' detection queues, then their event
   // stages
@@ -2133,7 +2196,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   const uint64_t wave = ((uint64_t)blockIdx.x * nthreads + tid) >> 6;
   const uint64_t begin = wave * per_wave;
   Sinks o = out;
-  constexpr int DQF = ADJ ? kDqAdjFields : kDqFields;
+  constexpr int DQF = CARRY ? kDqAdjFields : kDqFields;
   float* dq = dqs + (tid >> 6) * DQ * DQF;
   float* evs = dqs + (nthreads >> 6) * DQ * DQF;
   if (events) {
@@ -2424,7 +2487,7 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
                             DevRecord* rec, uint64_t cap, unsigned long long* n_out,
                             DevEvent* ev, uint64_t ev_cap, unsigned long long* n_ev,
                             const AdjArgs* adj, float* gstack, const DetArgs* det,
-                            hipStream_t stream) {
+                            const TapeArgs* tape, hipStream_t stream) {
   AdjArgs AA = {};
   AA.dos_s = AA.dos_k = AA.abs_s = AA.sig_s = AA.sig_k = AA.sqe_s = AA.sqe_k = AA.mp_k = -1;
   if (adj) AA = *adj;
@@ -2439,14 +2502,21 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
     out.det_lin_bits = det->lin_bits;
     out.det_id_bits = det->id_bits;
   }
+  if (tape) {
+    if (!adj) return hipErrorInvalidValue;  // the tape's carry follows a parameter map
+    out.tape = tape->words;
+    out.tape_cap = tape->cap;
+    out.n_tape = tape->n;
+  }
+  // adjoint partials in LDS only for the re-trace; the tape run keeps the
+  // histogram bin cache
+  const int adj_lds = adj && !tape ? (adj->sparse_lds ? adj->nb + adj->nc : 0) : kLdsNoAdjoint;
   const int dq_n = transport_dq_entries(host_plan);
   const bool dq = dq_n > 0;
   const size_t qbytes = transport_dq_bytes(block, dq_n, adj != nullptr);
   const int stack_lds = 0;  // the packet stacks live in device memory
-  size_t lds =
-      transport_lds_bytes(host_plan.n_tables, stack_lds, block,
-                          adj ? (adj->sparse_lds ? adj->nb + adj->nc : 0) : kLdsNoAdjoint, host_plan.hot_n) +
-      qbytes;
+  size_t lds = transport_lds_bytes(host_plan.n_tables, stack_lds, block, adj_lds, host_plan.hot_n) +
+               qbytes;
   if (ev || det) {
     // room for the event stages: a smaller bin cache, at most the same LDS
     // if the cache can give it
@@ -2467,7 +2537,10 @@ hipError_t launch_transport(const DevPlan* plan, const DevPlan& host_plan, const
   const bool two = host_plan.smax > host_plan.nscat;
   const bool phased = dev::use_phased(nsc, two, host_plan.K);
   const bool heavy = host_plan.heavy != 0;
-  if (adj) {
+  if (tape) {
+    launch_mode<dev::MODE_TAPE>(nsc, two, phased, dq, heavy, grid, block, lds, stream, plan,
+                                tables, beam, seed, first, n, per_wave, out, AA);
+  } else if (adj) {
     launch_mode<dev::MODE_ADJOINT>(nsc, two, phased, dq, heavy, grid, block, lds, stream, plan,
                                    tables, beam, seed, first, n, per_wave, out, AA);
   } else if (rec) {
@@ -2559,6 +2632,7 @@ hipError_t set_transport_lds_limit(size_t bytes) {
   push_mode<dev::MODE_RUN>(fns);
   push_mode<dev::MODE_TRACE>(fns);
   push_mode<dev::MODE_ADJOINT>(fns);
+  push_mode<dev::MODE_TAPE>(fns);
   fns.push_back(reinterpret_cast<const void*>(&dev::batch_persistent<false>));
   fns.push_back(reinterpret_cast<const void*>(&dev::batch_persistent<true>));
   // each kernel may use `bytes` of LDS in total, static part included

@@ -132,7 +132,11 @@ EXPORTS = ["mcv_assembly_create", "mcv_assembly_add", "mcv_assembly_destroy",
            "mcv_run", "mcv_trace", "mcv_sync", "mcv_last_error", "mcv_abi_version",
            "mcv_adjoint_nparams", "mcv_adjoint", "mcv_loss_grad", "mcv_batch_create",
            "mcv_batch_run", "mcv_batch_destroy", "mcv_autotune", "mcv_run_events",
-           "mcv_reduce_qe", "mcv_reduce_events_qe", "mcv_zero", "mcv_adjoint_noalloc"]
+           "mcv_reduce_qe", "mcv_reduce_events_qe", "mcv_zero", "mcv_run_tape",
+           "mcv_adjoint_tape", "mcv_adjoint_noalloc"]
+
+# 32-bit words per adjoint tape entry (MCV_TAPE_FIELDS)
+TAPE_FIELDS = 12
 
 _lib = None
 
@@ -167,6 +171,9 @@ def lib():
                             C.c_uint64, C.c_uint64, P, P, P],
             "mcv_adjoint_noalloc": [P, C.POINTER(mcv_param_map), C.POINTER(mcv_beam),
                                     C.c_uint64, C.c_uint64, C.c_uint64, P, P, P],
+            "mcv_run_tape": [P, C.POINTER(mcv_param_map), C.POINTER(mcv_beam), C.c_uint64,
+                             C.c_uint64, C.c_uint64, P, P, P, C.c_uint64, P, P],
+            "mcv_adjoint_tape": [P, C.POINTER(mcv_param_map), P, C.c_uint64, P, P, P, P],
             "mcv_loss_grad": [P, P, P, C.c_int64, P, P, P],
             "mcv_zero": [P, C.c_int64, P],
             "mcv_run_events": [P, C.POINTER(mcv_beam), C.c_uint64, C.c_uint64, C.c_uint64, P,
@@ -460,6 +467,45 @@ class Plan:
         check(lib().mcv_adjoint_noalloc(self.h, C.byref(pm), C.byref(b), seed, first, n,
                                         C.c_void_p(dLdI.data_ptr()), C.c_void_p(grad.data_ptr()),
                                         _stream_ptr(stream)))
+
+    def tape(self, capacity):
+        """An adjoint tape of `capacity` entries: (words, count), an int32
+        CUDA tensor of TAPE_FIELDS x capacity and a zeroed int64 counter."""
+        import torch
+        words = torch.empty((TAPE_FIELDS, int(capacity)), dtype=torch.int32, device=self.device)
+        count = torch.zeros(1, dtype=torch.int64, device=self.device)
+        return words, count
+
+    def run_tape(self, pm, hist, tape, n=None, first=0, seed=None, hist_w2=None, stream=None,
+                 beam=None):
+        """mcv_run into `hist` (may be None) that also writes the adjoint
+        tape (words, count) for the map `pm`; count is advanced by the number
+        of recorded packets."""
+        n = self.cfg["N"] if n is None else n
+        seed = self.cfg["seed"] if seed is None else seed
+        b = self.beam if beam is None else make_beam(beam, self.device)
+        for h in (hist, hist_w2):
+            if h is not None:
+                self._check_hist(h)
+        words, count = tape
+        check(lib().mcv_run_tape(self.h, C.byref(pm), C.byref(b), seed, first, n,
+                                 C.c_void_p(hist.data_ptr()) if hist is not None else None,
+                                 C.c_void_p(hist_w2.data_ptr()) if hist_w2 is not None else None,
+                                 C.c_void_p(words.data_ptr()), words.shape[1],
+                                 C.c_void_p(count.data_ptr()), _stream_ptr(stream)))
+
+    def adjoint_tape(self, pm, tape, dLdI, grad, stream=None):
+        """Adds to grad the gradient adjoint() gives for the histories of the
+        run that wrote `tape`, from the tape alone."""
+        self._check_hist(dLdI)
+        import torch
+        if grad.dtype != torch.float64 or not grad.is_cuda or grad.numel() < self.nparams(pm):
+            raise ValueError("grad must be a float64 CUDA tensor of nparams entries")
+        words, count = tape
+        check(lib().mcv_adjoint_tape(self.h, C.byref(pm), C.c_void_p(words.data_ptr()),
+                                     words.shape[1], C.c_void_p(count.data_ptr()),
+                                     C.c_void_p(dLdI.data_ptr()), C.c_void_p(grad.data_ptr()),
+                                     _stream_ptr(stream)))
 
     def _check_hist(self, h):
         import torch

@@ -67,21 +67,34 @@ def test_zero_kernel(torch_cuda):
 REL = 2e-4
 
 
-def _check_adjoint(torch, oracle_lib, make, PMx, N, target=None):
+def _check_adjoint(torch, oracle_lib, make, PMx, N, target=None, via="retrace", plan_kw=None):
+    """via: "retrace" (mcv_adjoint) or "tape" (mcv_run_tape, then
+    mcv_adjoint_tape); plan_kw: plan options (max_waves: launch shape)."""
     from paper_1504_02776_amd import mcv
     cfg = make()
-    print(f"[adjoint] {cfg['name']}: oracle forward-mode N={N} {PMx}", flush=True)
+    print(f"[adjoint] {cfg['name']}: oracle forward-mode N={N} {PMx} via {via} {plan_kw}",
+          flush=True)
     I0, _, _, _ = oracle_lib.run(cfg, n=N, records=False)
     tgt = _target(oracle_lib, make, N) if target is None else target(N)
     wgt = 1.0 / (tgt + 1e-3 * tgt.mean() + 1e-12)
     dLdI = 2.0 * wgt * (I0 - tgt)
     g_o, g_abs, g_flag = oracle_lib.gradient(cfg, PMx, dLdI, n=N, bounds=True)
-    plan = mcv.Plan(cfg)
+    plan = mcv.Plan(cfg, **(plan_kw or {}))
     pm = mcv.param_map_of(PMx)
     assert plan.nparams(pm) == len(g_o)
     g = torch.zeros(plan.nparams(pm), dtype=torch.float64, device="cuda")
-    print("[adjoint] GPU adjoint", flush=True)
-    plan.adjoint(pm, torch.from_numpy(dLdI).cuda(), g, n=N)
+    print(f"[adjoint] GPU adjoint ({via})", flush=True)
+    if via == "tape":
+        tape = plan.tape(4 * N + 1000)
+        h = plan.zeros()
+        plan.run_tape(pm, h, tape, n=N)
+        torch.cuda.synchronize()
+        assert 0 < int(tape[1].item()) <= tape[0].shape[1]
+        # the tape run's histogram is the forward estimate the oracle made
+        assert np.allclose(h.cpu().numpy(), plan_run(plan, N), rtol=1e-12, atol=0.0)
+        plan.adjoint_tape(pm, tape, torch.from_numpy(dLdI).cuda(), g)
+    else:
+        plan.adjoint(pm, torch.from_numpy(dLdI).cuda(), g, n=N)
     torch.cuda.synchronize()
     g_g = g.cpu().numpy()
     err = np.abs(g_g - g_o)
@@ -95,6 +108,12 @@ def _check_adjoint(torch, oracle_lib, make, PMx, N, target=None):
     assert not bad.any(), (f"{int(bad.sum())} entries off, worst j={int(np.argmax(err / allow))}: "
                            f"gpu={g_g[np.argmax(err / allow)]} oracle={g_o[np.argmax(err / allow)]}")
     return g_g, g_o
+
+
+def plan_run(plan, N):
+    h = plan.zeros()
+    plan.run(h, n=N)
+    return h.cpu().numpy()
 
 
 def test_adjoint_matches_oracle_forward_mode(torch_cuda, oracle_lib):
@@ -197,3 +216,122 @@ def test_autograd_backward_is_the_adjoint(torch_cuda):
     assert float(sa.grad) == pytest.approx(float(g[-2]), rel=1e-9)
     assert float(sg.grad) == pytest.approx(float(g[-1]), rel=1e-9)
     assert float(sa.grad) != 0.0
+
+
+# Launch shapes with few waves: each wave takes hundreds of histories one
+# after another (the refill, the detection queue's flushes and the stacks
+# reused), as at the benchmark's 1e7 histories where a wave traces about
+# 1200.
+@pytest.mark.parametrize("via", ["retrace", "tape"])
+def test_adjoint_refill_launch_shape(torch_cuda, oracle_lib, via):
+    _check_adjoint(torch_cuda, oracle_lib, W.powder_config, PM, 3000, via=via,
+                   plan_kw={"max_waves": 2})
+
+
+@pytest.mark.parametrize("via", ["retrace", "tape"])
+def test_adjoint_two_scatterers_refill_launch_shape(torch_cuda, oracle_lib, via):
+    _check_adjoint(torch_cuda, oracle_lib, W.powder_in_can_config,
+                   {"dos": (0, 1), "abs": 1, "sig": (0, 1)}, 1500, via=via,
+                   plan_kw={"max_waves": 2})
+
+
+def test_tape_adjoint_matches_oracle(torch_cuda, oracle_lib):
+    _check_adjoint(torch_cuda, oracle_lib, W.powder_config, PM, 3000, via="tape")
+
+
+def test_tape_adjoint_sqe_grid_and_multiphonon(torch_cuda, oracle_lib):
+    """Tape entries carry S(Q,E) cell indices (table partials in LDS, and in
+    global memory for a 200 x 150 grid) and the phonon bins of tied
+    multi-phonon draws."""
+    _check_adjoint(torch_cuda, oracle_lib, W.sqe_config, {"sqe": (0, 0), "abs": 0, "sig": (0, 1)},
+                   3000, target=_sqe_target(W.sqe_config), via="tape")
+    big = lambda: W.sqe_config(nQ=200, nE=150)  # noqa: E731
+    _check_adjoint(torch_cuda, oracle_lib, big, {"sqe": (0, 0), "abs": -1, "sig": None}, 2000,
+                   target=_sqe_target(big), via="tape")
+
+    def target(N):
+        c = W.with_n(W.powder_mp_config(), N)
+        shifted = W.powder_config(dos_shift=1.05)["scatterers"][0]["kernels"][1]["dos"]
+        for k in c["scatterers"][0]["kernels"]:
+            if k["type"] in ("phonon", "multiphonon"):
+                k["dos"] = shifted
+        return oracle_lib.run(c, seed=1, records=False)[0]
+    _check_adjoint(torch_cuda, oracle_lib, W.powder_mp_config,
+                   {"dos": (0, 1), "mp": 2, "abs": 0, "sig": (0, 2)}, 2000, target=target,
+                   via="tape")
+
+
+def test_tape_entries_are_the_recorded_packets(torch_cuda):
+    """One entry per packet the trace records in a bin, with its bin and
+    value, on the walk loop (crystal in its can, stacks and deferred kernels)
+    and the phased loop (powder)."""
+    from paper_1504_02776_amd import mcv
+    torch = torch_cuda
+    for make, n, pmx in ((W.crystal_config, 3000, {"abs": 1, "sig": (0, 0)}),
+                         (W.powder_config, 20000, PM)):
+        cfg = make()
+        print(f"[tape] {cfg['name']} n={n}", flush=True)
+        plan = mcv.Plan(cfg)
+        pm = mcv.param_map_of(pmx)
+        tape = plan.tape(8 * n)
+        plan.run_tape(pm, None, tape, n=n)
+        rec, _ = plan.trace(n=n)
+        torch.cuda.synchronize()
+        cnt = int(tape[1].item())
+        hit = rec["bin"] >= 0
+        assert cnt == int(hit.sum()) > 0
+        w = tape[0][:, :cnt].cpu().numpy()
+        tb = w[0].astype(np.int64)
+        tv = w[1].view(np.float32)
+        a = np.lexsort((tv, tb))
+        b = np.lexsort((rec["value"][hit], rec["bin"][hit]))
+        assert np.array_equal(tb[a], rec["bin"][hit][b])
+        assert np.array_equal(tv[a], rec["value"][hit][b].astype(np.float32))
+
+
+def test_tape_equals_retrace_at_full_size(torch_cuda):
+    """Powder cylinder, 1e7 histories in the benchmark's launch shape: the
+    tape pass and the re-trace sum the same binary32 terms (in another
+    order, in binary64)."""
+    from paper_1504_02776_amd import mcv
+    torch = torch_cuda
+    plan = mcv.Plan(W.powder_config())
+    pm = mcv.param_map_of(PM)
+    h = plan.zeros()
+    tape = plan.tape(8_000_000)
+    plan.run_tape(pm, h, tape)
+    torch.cuda.synchronize()
+    cnt = int(tape[1].item())
+    print(f"[tape] powder 1e7: {cnt} entries", flush=True)
+    assert 0 < cnt <= 8_000_000
+    T = plan.zeros()
+    mcv.Plan(W.powder_config(dos_shift=1.05)).run(T, seed=1)
+    wgt = 1.0 / (T + 1e-3 * T.mean())
+    dLdI = torch.empty_like(h)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    mcv.loss_grad(h, T, wgt, dLdI, loss)
+    g_t = torch.zeros(plan.nparams(pm), dtype=torch.float64, device="cuda")
+    g_r = torch.zeros_like(g_t)
+    plan.adjoint_tape(pm, tape, dLdI, g_t)
+    plan.adjoint(pm, dLdI, g_r)
+    g_t, g_r = g_t.cpu().numpy(), g_r.cpu().numpy()
+    scale = np.abs(g_r).max()
+    err = np.abs(g_t - g_r)
+    print(f"[tape] max |tape - retrace| / max|g| = {err.max() / scale:.3g}", flush=True)
+    assert np.all(err <= 1e-9 * np.abs(g_r) + 1e-12 * scale)
+    assert np.count_nonzero(g_r) == len(g_r)
+
+
+def test_tape_overflow_marks_the_gradient(torch_cuda):
+    from paper_1504_02776_amd import mcv
+    torch = torch_cuda
+    plan = mcv.Plan(W.powder_config())
+    pm = mcv.param_map_of(PM)
+    tape = plan.tape(100)
+    plan.run_tape(pm, None, tape, n=20000)
+    torch.cuda.synchronize()
+    assert int(tape[1].item()) > 100
+    dLdI = torch.ones(plan.nbins, dtype=torch.float64, device="cuda")
+    g = torch.zeros(plan.nparams(pm), dtype=torch.float64, device="cuda")
+    plan.adjoint_tape(pm, tape, dLdI, g)
+    assert torch.isnan(g).all()
