@@ -19,7 +19,8 @@ Beside it, unless --quick:
   against HBM);
 - adjoint: seconds per gradient step (forward + loss/dL/dI + adjoint) on the
   powder sample against 500 DOS bins, sigma_abs and sigma_inc, and its ratio
-  to the forward step;
+  to the forward step: with the re-trace, with the adjoint tape, and with the
+  tape and the weighted least squares loss formed at its entries;
 - atomics: the measured binary64 atomic ceilings (probe_costs.py) beside the
   histogram updates of the headline launch and the event reduction;
 - the powder with a multi-phonon kernel at 1e7, the crystal with an
@@ -340,12 +341,28 @@ def bench_adjoint(torch, mcv, W, stream, reps):
         grad.zero_()
         mcv.loss_grad(I, T, wgt, dLdI, loss, stream=stream)
         plan.adjoint_tape(pm, tape, dLdI, grad, stream=stream)
+
+    # the weighted least squares loss formed at the tape's entries: no dL/dI
+    # array; the loss is the target's constant sum w T^2 (computed once per
+    # target, outside the step) plus the entries' part
+    const = torch.zeros(1, dtype=torch.float64, device=I.device)
+    mcv.loss_grad(torch.zeros_like(I), T, wgt, dLdI, const, stream=stream)
+
+    def step_wl2():
+        forward_tape()
+        loss.zero_()
+        grad.zero_()
+        plan.adjoint_tape_wl2(pm, tape, I, T, wgt, loss, grad, stream=stream)
     forward_ms = timed(torch, stream, forward, reps)
     t_step = timed(torch, stream, step, reps)
     t_loss = timed(torch, stream, lambda: mcv.loss_grad(I, T, wgt, dLdI, loss, stream=stream),
                    reps)
     t_adj = timed(torch, stream, lambda: plan.adjoint(pm, dLdI, grad, stream=stream), reps)
     t_step_tape = timed(torch, stream, step_tape, reps)
+    t_step_wl2 = timed(torch, stream, step_wl2, reps)
+    loss_wl2 = float(loss.item() + const.item())
+    step_tape()
+    loss_full = float(loss.item())
     t_fwd_tape = timed(torch, stream, forward_tape, reps)
     entries = int(tape[1].item())
     t_adj_tape = timed(torch, stream, lambda: plan.adjoint_tape(pm, tape, dLdI, grad,
@@ -363,6 +380,9 @@ def bench_adjoint(torch, mcv, W, stream, reps):
                     "forward_with_tape_ms": t_fwd_tape, "backward_ms": t_adj_tape,
                     "entries": entries, "tape_bytes": 4 * 12 * entries,
                     "backward_GBps": 4 * 12 * entries / (t_adj_tape / 1e3) / 1e9},
+           "tape_wl2": {"s_per_step": t_step_wl2 / 1e3,
+                        "ratio_to_forward": t_step_wl2 / forward_ms,
+                        "loss": loss_wl2, "loss_from_loss_pass": loss_full},
            "loss_grad_ms": t_loss,
            "loss_grad_GBps": 4 * 8 * nb / (t_loss / 1e3) / 1e9,
            "loss_grad_hbm_frac": 4 * 8 * nb / (t_loss / 1e3) / HBM_PEAK,

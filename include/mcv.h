@@ -458,6 +458,23 @@ mcv_status mcv_adjoint_tape(mcv_plan p, const mcv_param_map* pm, const uint32_t*
                             uint64_t capacity, const uint64_t* n_tape_dev, const double* dL_dI,
                             double* grad, void* stream);
 
+/* mcv_adjoint_tape for the weighted least squares loss L = sum_b w_b (I_b -
+ * T_b)^2 of the histogram I that the run writing the tape produced (zeroed
+ * before that run) against a target T with weights w (device binary64
+ * [nbins] each): dL/dI_b = 2 w_b (I_b - T_b) is formed at each entry's bin,
+ * so no dL/dI array is read or written.  Since I_b is the sum of the values v
+ * of the entries in bin b, L = sum_b w_b T_b^2 + sum over entries of v w_b
+ * (I_b - 2 T_b); the second term is added to *loss (device binary64) and the
+ * first, a constant of the target, is the caller's (mcv_loss_grad of a zero
+ * histogram against T and w gives it).  When L is much smaller than that
+ * constant the two terms cancel: their binary64 sum keeps about 16 +
+ * log10(L / constant) digits.  Incomplete tape: grad and *loss become NaN.
+ * Errors as mcv_adjoint_tape. */
+mcv_status mcv_adjoint_tape_wl2(mcv_plan p, const mcv_param_map* pm, const uint32_t* tape,
+                                uint64_t capacity, const uint64_t* n_tape_dev, const double* I,
+                                const double* T, const double* w, double* loss, double* grad,
+                                void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): mcv_adjoint with
  * its binary64 workspace in static device memory of the library (32768

@@ -1,8 +1,10 @@
 """torch.autograd binding of the transport: I(pixel, tof) as a function of a
 one-phonon kernel's raw DOS and/or a tabulated S(Q,E) grid, a scatterer's
-sigma_abs and a kernel's nominal sigma.  forward() runs the HIP transport; backward() runs the HIP adjoint
-kernel, which re-traces the same histories (same random numbers, choices
-drawn at the forward's parameter values) instead of storing their paths."""
+sigma_abs and a kernel's nominal sigma.  forward() runs the HIP transport;
+backward() runs the HIP adjoint, which either re-traces the same histories
+(same random numbers, choices drawn at the forward's parameter values) or,
+with a tape capacity, reads the adjoint tape the forward run wrote (one
+entry per recorded packet; 48 bytes each)."""
 
 from __future__ import annotations
 
@@ -21,14 +23,18 @@ class Simulation:
     k) (optional), "mp": k (optional)}, as in mcv.param_map_of.  The table
     parameter is one vector: the DOS values, then the S(Q,E) cells (row major
     in Q); a multi-phonon kernel tied to the DOS receives the same values.
+    tape_capacity: entries of the adjoint tape a forward that needs
+    gradients writes (None: the backward re-traces); a tape that overflows
+    is dropped and the backward re-traces.
     """
 
-    def __init__(self, cfg, pm=None, n=None, seed=None, device=0):
+    def __init__(self, cfg, pm=None, n=None, seed=None, device=0, tape_capacity=None):
         self.cfg = cfg
         self.pm = pm or {"dos": (0, 1), "abs": 0, "sig": (0, 1)}
         self.n = cfg["N"] if n is None else n
         self.seed = cfg["seed"] if seed is None else seed
         self.device = device
+        self.tape_capacity = tape_capacity
 
     def _kernel(self, c, key):
         s, k = self.pm[key]
@@ -78,14 +84,20 @@ class Simulation:
 
 
 class TransportFunction(torch.autograd.Function):
-    """I = transport(table, sigma_abs, sigma): forward runs mcv_run at the
-    given values; backward runs mcv_adjoint with grad_I as dL/dI."""
+    """I = transport(table, sigma_abs, sigma): forward runs mcv_run (or
+    mcv_run_tape) at the given values; backward runs mcv_adjoint (or
+    mcv_adjoint_tape) with grad_I as dL/dI."""
 
     @staticmethod
     def forward(ctx, table, sigma_abs, sigma, sim):
         plan = mcv.Plan(sim.config_at(table, sigma_abs, sigma), device=sim.device)
         hist = plan.zeros()
-        plan.run(hist, n=sim.n, seed=sim.seed)
+        ctx.tape = None
+        if sim.tape_capacity and any(ctx.needs_input_grad[:3]):
+            ctx.tape = plan.tape(sim.tape_capacity)
+            plan.run_tape(sim.param_map(), hist, ctx.tape, n=sim.n, seed=sim.seed)
+        else:
+            plan.run(hist, n=sim.n, seed=sim.seed)
         ctx.plan = plan
         ctx.sim = sim
         ctx.meta = (table.dtype, table.device, table.numel())
@@ -96,7 +108,13 @@ class TransportFunction(torch.autograd.Function):
         plan, sim = ctx.plan, ctx.sim
         pm = sim.param_map()
         g = torch.zeros(plan.nparams(pm), dtype=torch.float64, device=grad_I.device)
-        plan.adjoint(pm, grad_I.detach().double().contiguous(), g, n=sim.n, seed=sim.seed)
+        dLdI = grad_I.detach().double().contiguous()
+        tape = ctx.tape
+        if tape is not None and int(tape[1].item()) <= tape[0].shape[1]:
+            plan.adjoint_tape(pm, tape, dLdI, g)
+        else:
+            plan.adjoint(pm, dLdI, g, n=sim.n, seed=sim.seed)
+        ctx.tape = None
         dtype, device, nt = ctx.meta
         gd = g[:nt].to(device=device, dtype=dtype)
         return gd, g[nt].to(device=device, dtype=dtype), g[nt + 1].to(device=device,

@@ -94,28 +94,47 @@ constexpr int kTapeThreads = 256;
 // by 1/table at the flush; global atomics otherwise).  The entries are read
 // field by field ([field][entry], coalesced).  A tape whose counter exceeds
 // its capacity is incomplete: the gradient entries become NaN.
-template <bool LDS>
+// WL2: the loss is the weighted least squares L = sum_b w_b (I_b - T_b)^2 of
+// the tape run's own histogram I against a target T: dL/dI_b = 2 w_b (I_b -
+// T_b) is formed at each entry from I, T and w at its bin (no dL/dI array),
+// and since I_b is the sum of the values v of its entries, L = sum_b w_b T_b^2
+// + sum over entries of v w_b (I_b - 2 T_b); the second sum is added to
+// *loss.
+template <bool LDS, bool WL2>
 __global__ void __launch_bounds__(kTapeThreads)
 tape_adjoint(const uint32_t* __restrict__ tape, uint64_t cap,
              const unsigned long long* __restrict__ n_tape, const double* __restrict__ dLdI,
-             int nb, int nc, double* __restrict__ grad, double* __restrict__ ws) {
-  extern __shared__ double acc[];  // [table partials (LDS) | 4 scalars]
+             const double* __restrict__ I, const double* __restrict__ T,
+             const double* __restrict__ w, double* __restrict__ loss, int nb, int nc,
+             double* __restrict__ grad, double* __restrict__ ws) {
+  extern __shared__ double acc[];  // [table partials (LDS) | 5 scalars]
   const int ntab = LDS ? nb + nc : 0;
   const int np = nb + nc;
   const int tid = threadIdx.x;
-  for (int i = tid; i < ntab + 4; i += kTapeThreads) acc[i] = 0.0;
+  for (int i = tid; i < ntab + 5; i += kTapeThreads) acc[i] = 0.0;
   __syncthreads();
   const unsigned long long count = *n_tape;
   if (count > cap) {
-    if (blockIdx.x == 0)
+    if (blockIdx.x == 0) {
       for (int i = tid; i < np + 2; i += kTapeThreads) grad[i] = __builtin_nan("");
+      if (WL2 && tid == 0) *loss = __builtin_nan("");
+    }
     return;
   }
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
   const uint64_t stride = (uint64_t)gridDim.x * kTapeThreads;
   for (uint64_t i = (uint64_t)blockIdx.x * kTapeThreads + tid; i < count; i += stride) {
     const uint32_t bin = tape[i];
-    const double gv = dLdI[bin] * (double)__uint_as_float(tape[cap + i]);
+    const double v = (double)__uint_as_float(tape[cap + i]);
+    double g;
+    if (WL2) {
+      const double ib = I[bin], tb = T[bin], wb = w[bin];
+      g = 2.0 * wb * (ib - tb);
+      s4 += v * wb * (ib - 2.0 * tb);
+    } else {
+      g = dLdI[bin];
+    }
+    const double gv = g * v;
     if (gv == 0.0) continue;
     s0 += gv * (double)__uint_as_float(tape[2 * cap + i]);
     s1 += gv * (double)__uint_as_float(tape[3 * cap + i]);
@@ -131,9 +150,9 @@ tape_adjoint(const uint32_t* __restrict__ tape, uint64_t cap,
       else unsafeAtomicAdd(&grad[idx], gv * ws[4 + idx]);
     }
   }
-  const double sv[4] = {s0, s1, s2, s3};
+  const double sv[5] = {s0, s1, s2, s3, s4};
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < (WL2 ? 5 : 4); ++k) {
     double v = sv[k];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if ((tid & 63) == 0 && v != 0.0) atomicAdd(&acc[ntab + k], v);
@@ -146,6 +165,7 @@ tape_adjoint(const uint32_t* __restrict__ tape, uint64_t cap,
     if (acc[ntab + 1] != 0.0) unsafeAtomicAdd(&grad[np + 1], acc[ntab + 1]);
     if (acc[ntab + 2] != 0.0) unsafeAtomicAdd(&ws[0], acc[ntab + 2]);
     if (acc[ntab + 3] != 0.0) unsafeAtomicAdd(&ws[1], acc[ntab + 3]);
+    if (WL2 && acc[ntab + 4] != 0.0) unsafeAtomicAdd(loss, acc[ntab + 4]);
   }
 }
 
@@ -154,17 +174,26 @@ tape_adjoint(const uint32_t* __restrict__ tape, uint64_t cap,
 // LDS of the tape pass's table partials: at most this many entries
 constexpr int kTapeLdsTable = 8000;
 
+// dLdI given: the general pass; dLdI null: the weighted least squares form
+// with I, T, w and loss
 hipError_t launch_tape_adjoint(const uint32_t* tape, uint64_t cap, const unsigned long long* n,
-                               const double* dLdI, int nb, int nc, double* grad, double* ws,
-                               int grid, hipStream_t stream) {
+                               const double* dLdI, const double* I, const double* T,
+                               const double* w, double* loss, int nb, int nc, double* grad,
+                               double* ws, int grid, hipStream_t stream) {
   const bool lds = nb + nc <= kTapeLdsTable;
-  const size_t bytes = sizeof(double) * (size_t)((lds ? nb + nc : 0) + 4);
-  if (lds)
-    hipLaunchKernelGGL(dev::tape_adjoint<true>, dim3(grid), dim3(dev::kTapeThreads), bytes, stream,
-                       tape, cap, n, dLdI, nb, nc, grad, ws);
-  else
-    hipLaunchKernelGGL(dev::tape_adjoint<false>, dim3(grid), dim3(dev::kTapeThreads), bytes,
-                       stream, tape, cap, n, dLdI, nb, nc, grad, ws);
+  const bool wl2 = dLdI == nullptr;
+  const size_t bytes = sizeof(double) * (size_t)((lds ? nb + nc : 0) + 5);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(dev::kTapeThreads), bytes, stream, tape, cap, n,
+                       dLdI, I, T, w, loss, nb, nc, grad, ws);
+  };
+  if (lds) {
+    if (wl2) go(dev::tape_adjoint<true, true>);
+    else go(dev::tape_adjoint<true, false>);
+  } else {
+    if (wl2) go(dev::tape_adjoint<false, true>);
+    else go(dev::tape_adjoint<false, false>);
+  }
   return hipGetLastError();
 }
 

@@ -40,8 +40,9 @@ hipError_t launch_adjoint_prepare(const double* theta, int nb, double de, double
 hipError_t launch_adjoint_finalize(double* grad, const double* ws, int nb, int nc,
                                    hipStream_t stream);
 hipError_t launch_tape_adjoint(const uint32_t* tape, uint64_t cap, const unsigned long long* n,
-                               const double* dLdI, int nb, int nc, double* grad, double* ws,
-                               int grid, hipStream_t stream);
+                               const double* dLdI, const double* I, const double* T,
+                               const double* w, double* loss, int nb, int nc, double* grad,
+                               double* ws, int grid, hipStream_t stream);
 hipError_t adjoint_scratch_setup(int device);
 double* adjoint_scratch(int device);
 hipError_t launch_loss_grad(const double* I, const double* T, const double* w, int64_t n,
@@ -1407,15 +1408,19 @@ mcv_status mcv_run_tape(mcv_plan p, const mcv_param_map* pm, const mcv_beam* bea
   return MCV_OK;
 }
 
-mcv_status mcv_adjoint_tape(mcv_plan p, const mcv_param_map* pm, const uint32_t* tape,
-                            uint64_t capacity, const uint64_t* n_tape_dev, const double* dL_dI,
-                            double* grad, void* stream) {
-  if (!p) return fail(MCV_EINVAL, "null plan");
+}  // extern "C"
+
+namespace {
+
+// prepare -> pass over the tape -> dense terms; dL_dI null: the weighted
+// least squares form (I, T, w, loss)
+mcv_status tape_backward(mcv_plan p, const mcv_param_map* pm, const uint32_t* tape,
+                         uint64_t capacity, const uint64_t* n_tape_dev, const double* dL_dI,
+                         const double* I, const double* T, const double* w, double* loss,
+                         double* grad, void* stream) {
   AdjSetup A;
   mcv_status st = check_param_map(p, pm, &A);
   if (st != MCV_OK) return st;
-  if (!tape || !n_tape_dev || !dL_dI || !grad)
-    return fail(MCV_EINVAL, "null tape, counter, dL_dI or grad");
   if (((uintptr_t)tape & 3u) || ((uintptr_t)n_tape_dev & 7u))
     return fail(MCV_EINVAL, "tape must be 4-byte and its counter 8-byte aligned");
   int cur = 0;
@@ -1429,13 +1434,37 @@ mcv_status mcv_adjoint_tape(mcv_plan p, const mcv_param_map* pm, const uint32_t*
         launch_adjoint_prepare(A.theta, A.nb, A.de, A.kT, A.h2m, A.cells, A.nc, ws, s);
     if (e == hipSuccess)
       e = launch_tape_adjoint(tape, capacity,
-                              reinterpret_cast<const unsigned long long*>(n_tape_dev), dL_dI, A.nb,
-                              A.nc, grad, ws, p->cus * 4, s);
+                              reinterpret_cast<const unsigned long long*>(n_tape_dev), dL_dI, I, T,
+                              w, loss, A.nb, A.nc, grad, ws, p->cus * 4, s);
     if (e == hipSuccess) e = launch_adjoint_finalize(grad, ws, A.nb, A.nc, s);
     if (e != hipSuccess) st = hipfail(e, "tape adjoint launch");
   }
   if (cur != p->device) (void)hipSetDevice(cur);
   return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcv_status mcv_adjoint_tape(mcv_plan p, const mcv_param_map* pm, const uint32_t* tape,
+                            uint64_t capacity, const uint64_t* n_tape_dev, const double* dL_dI,
+                            double* grad, void* stream) {
+  if (!p) return fail(MCV_EINVAL, "null plan");
+  if (!tape || !n_tape_dev || !dL_dI || !grad)
+    return fail(MCV_EINVAL, "null tape, counter, dL_dI or grad");
+  return tape_backward(p, pm, tape, capacity, n_tape_dev, dL_dI, nullptr, nullptr, nullptr,
+                       nullptr, grad, stream);
+}
+
+mcv_status mcv_adjoint_tape_wl2(mcv_plan p, const mcv_param_map* pm, const uint32_t* tape,
+                                uint64_t capacity, const uint64_t* n_tape_dev, const double* I,
+                                const double* T, const double* w, double* loss, double* grad,
+                                void* stream) {
+  if (!p) return fail(MCV_EINVAL, "null plan");
+  if (!tape || !n_tape_dev || !I || !T || !w || !loss || !grad)
+    return fail(MCV_EINVAL, "null tape, counter, I, T, w, loss or grad");
+  return tape_backward(p, pm, tape, capacity, n_tape_dev, nullptr, I, T, w, loss, grad, stream);
 }
 
 mcv_status mcv_adjoint_noalloc(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam,

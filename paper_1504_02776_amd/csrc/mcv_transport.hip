@@ -1441,7 +1441,11 @@ __host__ __device__ constexpr bool carries(int mode) {
 // 1.90 / 2.38 and histogram fill + tape run 2.18 / 1.99 / 2.49; crystal in
 // its can at 1e7, re-trace 29.3 / 23.8 / 19.4 and tape run 31.5 / 23.3 /
 // 19.3.  So walk loops take 2 waves outside the run mode, the phased loop 4
-// (3 for the tape run).
+// (3 for the tape run).  The run kernels keep 4 waves despite a few spilled
+// registers in the multi-interval and heavy ones: at 3 waves (no spills) the
+// crystal took 119.3 ms instead of 113.3 ms at 1e8, the exact-delta crystal
+// 30.0 ms instead of 26.9 ms at 1e7, and the batch kernel's graph 34.4 ms
+// instead of 32.8 ms.
 __host__ __device__ constexpr int kernel_waves(int mode, bool phased) {
   return mode == MODE_RUN ? MCV_WAVES_PER_EU
          : !phased        ? 2

@@ -133,7 +133,7 @@ EXPORTS = ["mcv_assembly_create", "mcv_assembly_add", "mcv_assembly_destroy",
            "mcv_adjoint_nparams", "mcv_adjoint", "mcv_loss_grad", "mcv_batch_create",
            "mcv_batch_run", "mcv_batch_destroy", "mcv_autotune", "mcv_run_events",
            "mcv_reduce_qe", "mcv_reduce_events_qe", "mcv_zero", "mcv_run_tape",
-           "mcv_adjoint_tape", "mcv_adjoint_noalloc"]
+           "mcv_adjoint_tape", "mcv_adjoint_tape_wl2", "mcv_adjoint_noalloc"]
 
 # 32-bit words per adjoint tape entry (MCV_TAPE_FIELDS)
 TAPE_FIELDS = 12
@@ -174,6 +174,8 @@ def lib():
             "mcv_run_tape": [P, C.POINTER(mcv_param_map), C.POINTER(mcv_beam), C.c_uint64,
                              C.c_uint64, C.c_uint64, P, P, P, C.c_uint64, P, P],
             "mcv_adjoint_tape": [P, C.POINTER(mcv_param_map), P, C.c_uint64, P, P, P, P],
+            "mcv_adjoint_tape_wl2": [P, C.POINTER(mcv_param_map), P, C.c_uint64, P, P, P, P, P,
+                                     P, P],
             "mcv_loss_grad": [P, P, P, C.c_int64, P, P, P],
             "mcv_zero": [P, C.c_int64, P],
             "mcv_run_events": [P, C.POINTER(mcv_beam), C.c_uint64, C.c_uint64, C.c_uint64, P,
@@ -506,6 +508,23 @@ class Plan:
                                      words.shape[1], C.c_void_p(count.data_ptr()),
                                      C.c_void_p(dLdI.data_ptr()), C.c_void_p(grad.data_ptr()),
                                      _stream_ptr(stream)))
+
+    def adjoint_tape_wl2(self, pm, tape, I, T, w, loss, grad, stream=None):
+        """Adds to grad the gradient of sum_b w_b (I_b - T_b)^2 (I: the
+        histogram of the run that wrote `tape`) and to loss that loss less
+        its target constant sum_b w_b T_b^2, from the tape alone."""
+        for h in (I, T, w):
+            self._check_hist(h)
+        import torch
+        if grad.dtype != torch.float64 or not grad.is_cuda or grad.numel() < self.nparams(pm):
+            raise ValueError("grad must be a float64 CUDA tensor of nparams entries")
+        _check_f64(loss, 1)
+        words, count = tape
+        check(lib().mcv_adjoint_tape_wl2(self.h, C.byref(pm), C.c_void_p(words.data_ptr()),
+                                         words.shape[1], C.c_void_p(count.data_ptr()),
+                                         C.c_void_p(I.data_ptr()), C.c_void_p(T.data_ptr()),
+                                         C.c_void_p(w.data_ptr()), C.c_void_p(loss.data_ptr()),
+                                         C.c_void_p(grad.data_ptr()), _stream_ptr(stream)))
 
     def _check_hist(self, h):
         import torch

@@ -192,12 +192,15 @@ def test_adjoint_map_validation(torch_cuda):
     assert plan.nparams(mcv.param_map_of({"dos": (0, 1), "mp": 2})) == 502
 
 
-def test_autograd_backward_is_the_adjoint(torch_cuda):
+@pytest.mark.parametrize("tape_capacity", [None, 50_000, 10])
+def test_autograd_backward_is_the_adjoint(torch_cuda, tape_capacity):
+    """Backward through the re-trace, through the tape, and through the
+    re-trace again when the tape (10 entries) overflowed."""
     from paper_1504_02776_amd import mcv
     from paper_1504_02776_amd.autograd import Simulation
     torch = torch_cuda
     N = 5000
-    sim = Simulation(W.powder_config(), PM, n=N)
+    sim = Simulation(W.powder_config(), PM, n=N, tape_capacity=tape_capacity)
     dos, sa, sg = sim.params()
     dos.requires_grad_(True)
     sa.requires_grad_(True)
@@ -320,6 +323,19 @@ def test_tape_equals_retrace_at_full_size(torch_cuda):
     print(f"[tape] max |tape - retrace| / max|g| = {err.max() / scale:.3g}", flush=True)
     assert np.all(err <= 1e-9 * np.abs(g_r) + 1e-12 * scale)
     assert np.count_nonzero(g_r) == len(g_r)
+    # the weighted least squares form: dL/dI formed at each entry, the loss
+    # from the entries and the target's constant sum w T^2
+    const = torch.zeros(1, dtype=torch.float64, device="cuda")
+    mcv.loss_grad(torch.zeros_like(h), T, wgt, torch.empty_like(h), const)
+    part = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g_w = torch.zeros(plan.nparams(pm), dtype=torch.float64, device="cuda")
+    plan.adjoint_tape_wl2(pm, tape, h, T, wgt, part, g_w)
+    L_tape = float(const.item() + part.item())
+    print(f"[tape] loss {float(loss.item())!r} from the tape {L_tape!r} "
+          f"(constant {float(const.item()):.6g})", flush=True)
+    assert L_tape == pytest.approx(float(loss.item()), rel=1e-10)
+    g_w = g_w.cpu().numpy()
+    assert np.all(np.abs(g_w - g_t) <= 1e-12 * np.abs(g_t) + 1e-14 * scale)
 
 
 def test_tape_overflow_marks_the_gradient(torch_cuda):
@@ -335,3 +351,7 @@ def test_tape_overflow_marks_the_gradient(torch_cuda):
     g = torch.zeros(plan.nparams(pm), dtype=torch.float64, device="cuda")
     plan.adjoint_tape(pm, tape, dLdI, g)
     assert torch.isnan(g).all()
+    part = torch.zeros(1, dtype=torch.float64, device="cuda")
+    g.zero_()
+    plan.adjoint_tape_wl2(pm, tape, dLdI, dLdI, dLdI, part, g)
+    assert torch.isnan(g).all() and torch.isnan(part).all()
