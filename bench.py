@@ -26,7 +26,9 @@ Beside it, unless --quick:
 - the powder with a multi-phonon kernel at 1e7, the crystal with an
   exact-delta dispersion at 1e7 and a 64-angle goniometer scan of it in one
   batch, the powder on 8-packs, the aluminium coherent-phonon plate, event
-  mode and the (Q, E) reduction.
+  mode and the (Q, E) reduction;
+- determinism: the powder at 1e7 with deterministic summation against the
+  binary64 atomics.
 
 Roofline: the transport kernel is bound by VALU issue.  Its work per history
 is the sum over primitives of (count per history in the algorithm, from the
@@ -434,6 +436,25 @@ def bench_single(torch, mcv, cfg, stream, reps, costs_name=None, cpu_budget_s=4.
     return out
 
 
+def bench_determinism(torch, mcv, W, stream, reps):
+    """Deterministic summation (plan option) against binary64 atomics on the
+    powder cylinder at 1e7: chunks of histories, one host wait per chunk."""
+    cfg = W.powder_config()
+    out = {"workload": f"{cfg['name']} 1e7 histories"}
+    for name, det in (("atomic", False), ("deterministic", True)):
+        plan = mcv.Plan(cfg, deterministic=det)
+        h = plan.zeros()
+
+        def step():
+            mcv.zero(h, stream=stream)
+            plan.run(h, stream=stream)
+        out[f"{name}_ms"] = timed(torch, stream, step, reps)
+        del plan, h
+        torch.cuda.empty_cache()
+    out["slowdown"] = out["deterministic_ms"] / out["atomic_ms"]
+    return out
+
+
 def bench_plate(torch, mcv, W, stream, reps):
     """The small plate case (1e5 histories, single scattering, sphere
     detector): latency of one step at its own size, which is below one fill
@@ -628,7 +649,7 @@ def main():
                                "histories_per_launch": N}
         hist_updates_per_s = tally.n_hist_updates / n_s * N / kern_avg_s
     all_sections = ["powder", "plate", "batched", "adjoint", "crystal", "multiphonon", "delta",
-                    "scan", "8packs", "coherent", "events", "atomics"]
+                    "scan", "8packs", "coherent", "events", "atomics", "determinism"]
     if args.sections is not None:
         sections = [x for x in args.sections.split(",") if x]
         unknown = set(sections) - set(all_sections)
@@ -669,6 +690,8 @@ def main():
                                                      reps, "al_coherent")
         elif sec == "events":
             out["events_and_reduction"] = bench_events_and_reduction(torch, mcv, W, stream, reps)
+        elif sec == "determinism":
+            out["determinism"] = bench_determinism(torch, mcv, W, stream, reps)
         elif sec == "atomics":
             a = load_atomics()
             if a is not None:

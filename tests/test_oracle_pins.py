@@ -459,6 +459,36 @@ def test_gamma0_debye_closed_forms(oracle_lib):
     assert oracle_lib.gamma0(k) == pytest.approx(6 * KB * T / eD ** 2, rel=1e-5)
 
 
+def test_iso_elastic_debye_waller_factor(oracle_lib):
+    """Incoherent elastic scattering with the Debye-Waller factor (Supplement
+    S4): every draw is elastic and isotropic and carries exp(-2W), 2W =
+    (hbar^2 Q^2 / 2M) gamma0 with Q = k (d_in - d_out) and gamma0 of the
+    scatterer's one-phonon DOS; for a Debye DOS near T = 0, gamma0 = 3/(2
+    eD).  Over isotropic directions the factor averages to (1 - exp(-4 c
+    k^2)) / (4 c k^2), c = (hbar^2/2M) gamma0.  A Q of k (d_in + d_out), a
+    dropped mass ratio or a gamma0 from another kernel fails it."""
+    eD, nb, M = 40.0, 400, 12.0
+    e = (np.arange(nb) + 0.5) * (eD / nb)
+    cfg = W.plate_config(N=1)
+    cfg["scatterers"][0]["kernels"] = [W.iso_el(1.0, dw=1),
+                                       W.phonon(1e-3, M, 1e-3, eD, e * e)]
+    c = HBAR2_2MN * MN_AMU / M * 1.5 / eD
+    din = np.array([0.36, -0.48, 0.8])
+    for E in (5.0, 80.0):
+        v = speed(E)
+        k = kvec(v)
+        U = _uniforms(20000, 8)
+        vo, f = oracle_lib.kernel_samples(cfg, 0, 0, din, v, U)
+        assert np.allclose(np.linalg.norm(vo, axis=1), v, rtol=1e-12)
+        q2 = k * k * np.sum((din[None, :] - vo / v) ** 2, axis=1)
+        # gamma0 from the midpoint-rule DOS agrees with 3/(2 eD) to 1e-5
+        assert np.allclose(f, np.exp(-c * q2), rtol=2e-5 * np.maximum(1.0, c * q2.max()))
+        mean = (1.0 - math.exp(-4 * c * k * k)) / (4 * c * k * k)
+        assert f.mean() == pytest.approx(mean, abs=5 * f.std() / math.sqrt(len(f)))
+    # at 80 meV the factor spans exp(-4 c k^2) = 0.37 .. 1
+    assert f.min() < 0.5 * f.max()
+
+
 def _spin_cfg():
     return W.crystal_config(N=1)
 
