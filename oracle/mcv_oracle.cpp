@@ -44,6 +44,12 @@
 // uncertainty scale.  Packets with a margin below 1 are "near-decision" in the
 // parity tests (a single-precision implementation may legitimately take the
 // other branch there).
+//
+// Reading guide: lines and helpers marked [bookkeeping] carry those margins
+// and the binary32 conditioning of each packet (the uncertainties the parity
+// bars are built from); `tally->` lines count primitives for the work model.
+// Neither changes what the method computes: skip both to read the method
+// against the paper.
 
 #include <algorithm>
 #include <cmath>
@@ -1361,6 +1367,69 @@ struct Sim {
   // Sec. 2.4.3 / Supplement S3: each material interval on the ray splits the
   // packet; the transmitted part keeps flying, the scattered part starts at a
   // point of the interval drawn from the truncated exponential.
+  // [bookkeeping] Binary32 conditioning of a child packet -- test
+  // bookkeeping beside the method, not part of it: the uncertainties the
+  // parity bars are built from (wsens: relative weight sensitivity to
+  // position rounding; cond: E_i/E_f amplification; dpos, dtime, dsp, ddir:
+  // position, time, speed and direction uncertainties).  P: the parent at
+  // the scattering point; birth at s_in + x on a chord of length L whose
+  // interaction probability is a = 1 - e^{-mu L}; dL: the chord's
+  // uncertainty.
+  static void child_conditioning(const Packet& P, const Scatter& r, int ktype, double s_in,
+                                 double x, double mu, double L, double a, double dL, Packet& C) {
+    // d log(1 - e^{-mu L}) / dL times the chord uncertainty
+    C.wsens = P.wsens + mu * std::exp(-mu * L) / a * dL;
+    double Ein = kEperV2 * P.speed * P.speed;
+    double Eout = kEperV2 * C.speed * C.speed;
+    C.cond = P.cond * (Eout > 0.0 ? std::max(1.0, Ein / Eout) : 1.0);
+    // the birth point sits x into the interval, with x ~ 1/mu(speed)
+    C.dpos = P.dpos + P.ddir * (s_in + x) + kEpsPos + dL + x * P.dsp;
+    C.dtime = P.dtime + (dL + kEpsPos) / P.speed + (s_in + x) / P.speed * P.dsp;
+    // the child's speed: unchanged by elastic kernels, amplified by
+    // E_i/E_f through an energy loss, plus a delta-function root
+    C.dsp = Eout == Ein ? P.dsp
+                        : P.dsp * (Eout > 0.0 ? std::max(1.0, Ein / Eout) : 1.0) + 2e-7;
+    C.dsp += r.dk_rel;
+    if (r.dq_sens > 0.0) {
+      double kin = k_from_speed(P.speed), kout = k_from_speed(C.speed);
+      double dq = kin * (P.ddir + 2e-7) + kout * 2e-7 + (kin + kout) * 2e-7 * P.cond;
+      C.wsens += r.dq_sens * dq;
+    }
+    C.wsens += r.wsens_add;
+    C.cond *= 1.0 + r.dk_rel / 1e-5;
+    if (ktype == K_POWDER) {
+      // the cone angle 2 asin(lambda/2d) from a binary32 wavelength:
+      // d(2 theta) = 2 tan(theta) d lambda / lambda
+      double c = dot(P.dir, C.dir);
+      double th = 0.5 * std::acos(std::max(-1.0, std::min(1.0, c)));
+      double tn = std::tan(std::min(th, 0.5 * kPi - 1e-6));
+      C.ddir = P.ddir + 2e-7 + 2.0 * tn * std::max(2e-7 * P.cond, P.dsp);
+    } else if (r.ddir_add >= 0.0) {
+      C.ddir = P.ddir + 2e-7 + r.ddir_add;  // a cone about the incident direction
+    } else {
+      C.ddir = 2e-7;  // a fresh isotropic direction
+    }
+  }
+
+  // [bookkeeping] chord uncertainty of a binary32 implementation: lateral
+  // uncertainty at the exit (and entry) surface -- position rounding plus
+  // the direction's uncertainty over the distance flown -- over the cosine of
+  // the surface crossing (sliding the start along the ray does not move the
+  // surfaces it meets)
+  static void chord_uncertainty(const OShape& sh, const Packet& P, V3 start, double s_in,
+                                double s_out, double* dL, double* dL_exit) {
+    V3 dl = matTvec(sh.rot, P.dir);
+    V3 q_out = matTvec(sh.rot, sub(add(start, scale(P.dir, s_out)),
+                                   {sh.pos[0], sh.pos[1], sh.pos[2]}));
+    *dL_exit = (kEpsPos + P.ddir * s_out) / std::max(surface_cos(sh, q_out, dl), 1e-9);
+    *dL = *dL_exit;
+    if (s_in > 0.0) {
+      V3 q_in = matTvec(sh.rot, sub(add(start, scale(P.dir, s_in)),
+                                    {sh.pos[0], sh.pos[1], sh.pos[2]}));
+      *dL += (kEpsPos + P.ddir * s_in) / std::max(surface_cos(sh, q_in, dl), 1e-9);
+    }
+  }
+
   void fly(Packet& P, uint64_t id, std::vector<Packet>& children, double* own_margin) {
     std::vector<Interval> segs;
     for (int s = 0; s < S.nscat; ++s) {
@@ -1371,9 +1440,9 @@ struct Sim {
       tally->n_shape_tests++;
       int n = shape_intervals(sh, pl, dl, lo, hi, own_margin);
       for (int i = 0; i < n; ++i) {
-        *own_margin = std::min(*own_margin, std::fabs(hi[i] - kSurfaceEps) / kTauGeom);
+        *own_margin = std::min(*own_margin, std::fabs(hi[i] - kSurfaceEps) / kTauGeom);  // [bookkeeping]
         if (hi[i] <= kSurfaceEps) continue;  // behind or leaving through this surface
-        *own_margin = std::min(*own_margin, std::fabs(lo[i]) / kTauGeom);
+        *own_margin = std::min(*own_margin, std::fabs(lo[i]) / kTauGeom);  // [bookkeeping]
         Interval iv = {std::max(lo[i], 0.0), hi[i], s, i};
         segs.push_back(iv);
       }
@@ -1395,27 +1464,10 @@ struct Sim {
       double m_mu = kHuge;
       Mu mu = attenuation(sc, si, P.speed, &m_mu);
       Mu mup = attenuation(scp, sip, P.speed, &m_mu);
-      *own_margin = std::min(*own_margin, m_mu);
+      *own_margin = std::min(*own_margin, m_mu);  // [bookkeeping]
       tally->n_segments++;
-      // chord uncertainty of a binary32 implementation (conditioning only)
-      double dL, dL_exit;
-      {
-        const OShape& sh = sc.shape;
-        V3 dl = matTvec(sh.rot, P.dir);
-        V3 q_out = matTvec(sh.rot, sub(add(start, scale(P.dir, iv.s_out)),
-                                       {sh.pos[0], sh.pos[1], sh.pos[2]}));
-        // lateral uncertainty at a surface: position rounding plus the
-        // direction's uncertainty over the distance flown
-        // (weights: lateral uncertainty only -- sliding the start along the
-        // ray does not move the surfaces it meets)
-        dL_exit = (kEpsPos + P.ddir * iv.s_out) / std::max(surface_cos(sh, q_out, dl), 1e-9);
-        dL = dL_exit;
-        if (iv.s_in > 0.0) {
-          V3 q_in = matTvec(sh.rot, sub(add(start, scale(P.dir, iv.s_in)),
-                                        {sh.pos[0], sh.pos[1], sh.pos[2]}));
-          dL += (kEpsPos + P.ddir * iv.s_in) / std::max(surface_cos(sh, q_in, dl), 1e-9);
-        }
-      }
+      double dL, dL_exit;  // [bookkeeping]
+      chord_uncertainty(sc.shape, P, start, iv.s_in, iv.s_out, &dL, &dL_exit);
       double att = std::exp(-mu.total * L);
       double a = -std::expm1(-mup.total * L);  // probability to interact
       tally->n_transcend += 2;
@@ -1442,7 +1494,7 @@ struct Sim {
         int kk = sc.nk - 1;
         for (int j = 0; j < sc.nk; ++j) {
           cum += mup.k[j];
-          if (j < sc.nk - 1)
+          if (j < sc.nk - 1)  // [bookkeeping]
             child_margin = std::min(child_margin, std::fabs(target - cum) / (kTauRel * mup.scat));
           if (target < cum) {
             kk = j;
@@ -1514,58 +1566,25 @@ struct Sim {
         }
         C.lineage = lin;
         C.order = P.order + 1;
-        C.margin_anc = std::min(P.margin_anc, child_margin);
         C.kinds = P.kinds | (1u << k.type);
-        // d log(1 - e^{-mu L}) / dL times the chord uncertainty
-        C.wsens = P.wsens + mup.total * std::exp(-mup.total * L) / a * dL;
-        {
-          double Ein = kEperV2 * P.speed * P.speed;
-          double Eout = kEperV2 * C.speed * C.speed;
-          C.cond = P.cond * (Eout > 0.0 ? std::max(1.0, Ein / Eout) : 1.0);
-          // the birth point sits x into the interval, with x ~ 1/mu(speed)
-          C.dpos = P.dpos + P.ddir * (iv.s_in + x) + kEpsPos + dL + x * P.dsp;
-          C.dtime = P.dtime + (dL + kEpsPos) / P.speed + (iv.s_in + x) / P.speed * P.dsp;
-          // the child's speed: unchanged by elastic kernels, amplified by
-          // E_i/E_f through an energy loss, plus a delta-function root
-          C.dsp = Eout == Ein ? P.dsp
-                              : P.dsp * (Eout > 0.0 ? std::max(1.0, Ein / Eout) : 1.0) + 2e-7;
-          C.dsp += r.dk_rel;
-          if (r.dq_sens > 0.0) {
-            double kin = k_from_speed(P.speed), kout = k_from_speed(C.speed);
-            double dq = kin * (P.ddir + 2e-7) + kout * 2e-7 + (kin + kout) * 2e-7 * P.cond;
-            C.wsens += r.dq_sens * dq;
-          }
-          C.wsens += r.wsens_add;
-          C.cond *= 1.0 + r.dk_rel / 1e-5;
-          if (k.type == K_POWDER) {
-            // the cone angle 2 asin(lambda/2d) from a binary32 wavelength:
-            // d(2 theta) = 2 tan(theta) d lambda / lambda
-            double c = dot(P.dir, C.dir);
-            double th = 0.5 * std::acos(std::max(-1.0, std::min(1.0, c)));
-            double tn = std::tan(std::min(th, 0.5 * kPi - 1e-6));
-            C.ddir = P.ddir + 2e-7 + 2.0 * tn * std::max(2e-7 * P.cond, P.dsp);
-          } else if (r.ddir_add >= 0.0) {
-            C.ddir = P.ddir + 2e-7 + r.ddir_add;  // a cone about the incident direction
-          } else {
-            C.ddir = 2e-7;  // a fresh isotropic direction
-          }
-        }
+        C.margin_anc = std::min(P.margin_anc, child_margin);  // [bookkeeping]
+        child_conditioning(P, r, k.type, iv.s_in, x, mup.total, L, a, dL, C);  // [bookkeeping]
         if (C.w > 0.0) children.push_back(C);
         else tally->n_zero_weight++;
       } else {
         tally->w_lost[P.order] += P.w * a;
       }
       P.w *= att;
-      P.wsens += mu.total * dL;
-      last_dL_exit = dL_exit;
+      P.wsens += mu.total * dL;  // [bookkeeping]
+      last_dL_exit = dL_exit;    // [bookkeeping]
       if (tangent) add_dmu(P.dlogw, iv.scat, P.speed, -L);
     }
     if (!segs.empty()) {
       double s_end = segs.back().s_out;
       P.pos = add(start, scale(P.dir, s_end));
       P.t = t0 + s_end / P.speed;
-      P.dpos += P.ddir * s_end + last_dL_exit;
-      P.dtime += last_dL_exit / P.speed + s_end / P.speed * P.dsp;
+      P.dpos += P.ddir * s_end + last_dL_exit;                        // [bookkeeping]
+      P.dtime += last_dL_exit / P.speed + s_end / P.speed * P.dsp;   // [bookkeeping]
     }
   }
 
