@@ -531,9 +531,10 @@ typedef struct {
 
 /* Builds the work queue (chunks of (item, id range), longest estimated
  * first), uploads it, and captures [histogram zeroing + queue reset +
- * persistent kernel] into a HIP graph.  The histograms and plans must stay
- * alive until mcv_batch_destroy.  Errors: MCV_EINVAL, MCV_EUNSUPPORTED,
- * MCV_EHIP. */
+ * persistent kernel] into a HIP graph.  Items may share one histogram (it is
+ * zeroed before the transport and receives the sum of their ranges).  The
+ * histograms and plans must stay alive until mcv_batch_destroy.  Errors:
+ * MCV_EINVAL, MCV_EUNSUPPORTED, MCV_EHIP. */
 mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t n,
                             const mcv_tuning* tuning, int32_t device);
 /* Replays the graph on `stream`.  Each item's histogram receives the same

@@ -610,17 +610,19 @@ def _batch_sigs():
 class Batch:
     """Many simulations in one persistent, graph-captured launch.
 
-    plans: list of Plan; hists: list of float64 device tensors (one per plan).
+    plans: list of Plan; hists: list of float64 device tensors (one per plan;
+    items may share one); ranges: optional list of (first, n) history ranges
+    per item (None: the plan's 0 .. N).
     """
 
-    def __init__(self, plans, hists, tuning=None, device=0):
+    def __init__(self, plans, hists, tuning=None, device=0, ranges=None):
         L = _batch_sigs()
         self.plans, self.hists = plans, hists
         self.items = (mcv_batch_item * len(plans))()
         for i, (p, h) in enumerate(zip(plans, hists)):
             p._check_hist(h)
-            self.items[i] = mcv_batch_item(p.h, p.beam, p.cfg["seed"], 0, p.cfg["N"],
-                                           h.data_ptr())
+            first, n = (0, p.cfg["N"]) if ranges is None or ranges[i] is None else ranges[i]
+            self.items[i] = mcv_batch_item(p.h, p.beam, p.cfg["seed"], first, n, h.data_ptr())
         t = tuning or mcv_tuning(0, 0, 0, 1)
         self.tuning = t
         self.h = C.c_void_p()

@@ -52,6 +52,30 @@ def test_batch_equals_plain_launches(torch_cuda):
         b.close()
 
 
+def test_batch_items_sharing_a_histogram(torch_cuda):
+    """Two items of one plan with disjoint id ranges and one histogram (and
+    a third with its own): the shared histogram is zeroed before each run's
+    transport and receives the sum of both ranges."""
+    from paper_1504_02776_amd import mcv
+    torch = torch_cuda
+    cfgs = _small_batch(2)
+    p0, p1 = mcv.Plan(cfgs[0]), mcv.Plan(cfgs[1])
+    n0 = cfgs[0]["N"]
+    shared, own = p0.zeros(), p1.zeros()
+    b = mcv.Batch([p0, p0, p1], [shared, shared, own], mcv.mcv_tuning(256, 1024, 0, 1),
+                  ranges=[(0, n0), (n0, n0), None])
+    ref0 = p0.zeros()
+    p0.run(ref0, first=0, n=2 * n0)
+    ref1 = p1.zeros()
+    p1.run(ref1)
+    for rep in range(3):
+        b.run()
+        torch.cuda.synchronize()
+        assert np.allclose(shared.cpu().numpy(), ref0.cpu().numpy(), rtol=1e-9, atol=1e-14), rep
+        assert np.allclose(own.cpu().numpy(), ref1.cpu().numpy(), rtol=1e-9, atol=1e-14), rep
+    b.close()
+
+
 def test_batch_accumulates_without_zeroing(torch_cuda):
     from paper_1504_02776_amd import mcv
     torch = torch_cuda
