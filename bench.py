@@ -171,6 +171,16 @@ def host_cpu():
                 info[keys[k.strip()]] = v.strip()
     except (OSError, subprocess.SubprocessError):
         pass
+    if "mhz" not in info and "max_mhz" not in info:
+        # virtual machines often leave the clock out of lscpu: the kernel's
+        # current clock of the first CPU
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("cpu MHz"):
+                    info["mhz"] = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
     return info
 
 
