@@ -184,16 +184,48 @@ def host_cpu():
     return info
 
 
-def cpu_baseline_entry(cfg, budget_s):
+def cpu_parallel(workload_name, n_each, procs):
+    """The oracle in `procs` child processes over disjoint id ranges of the
+    named workload, n_each histories each: aggregate histories/s (the
+    slowest process's time), or None if a child fails."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, {root!r}); import bench; "
+            "from oracle import oracle as O; cfg = bench.workload({w!r}); "
+            "t = time.perf_counter(); O.run(cfg, n={n}, first={f}, records=False); "
+            "print(time.perf_counter() - t)")
+    ps = [subprocess.Popen([sys.executable, "-c", code.format(root=ROOT, w=workload_name,
+                                                              n=n_each, f=k * n_each)],
+                           stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
+          for k in range(procs)]
+    times = []
+    for pr in ps:
+        out, _ = pr.communicate(timeout=600)
+        if pr.returncode != 0:
+            return None
+        times.append(float(out.strip().splitlines()[-1]))
+    return {"value": procs * n_each / max(times), "unit": "histories/s", "processes": procs,
+            "sample": f"{procs} processes x {n_each} histories over disjoint id ranges, "
+                      f"slowest {max(times):.1f} s"}
+
+
+def cpu_baseline_entry(cfg, budget_s, workload_name=None):
     """The cpu_baseline object: oracle rate on one core over a bounded
-    sample, with the time the oracle would take for the full workload."""
+    sample, with the time the oracle would take for the full workload; with
+    a workload name, also the oracle on every host core (one process per
+    core, at most 16) over disjoint id ranges."""
     n_s, el, tally = cpu_baseline(cfg, budget_s=budget_s)
     rate = n_s / el
-    return {"value": rate, "unit": "histories/s", "cores": 1, "kind": "oracle",
-            "cpu": host_cpu(),
-            "sample": f"first {n_s} histories of the same workload (seed {cfg['seed']}), "
-                      f"serial binary64 oracle, {el:.1f} s",
-            "full_workload_s": cfg["N"] / rate}, n_s, tally
+    out = {"value": rate, "unit": "histories/s", "cores": 1, "kind": "oracle",
+           "cpu": host_cpu(),
+           "sample": f"first {n_s} histories of the same workload (seed {cfg['seed']}), "
+                     f"serial binary64 oracle, {el:.1f} s",
+           "full_workload_s": cfg["N"] / rate}
+    if workload_name is not None:
+        procs = max(1, min(os.cpu_count() or 1, 16))
+        par = cpu_parallel(workload_name, n_s, procs)
+        if par is not None:
+            out["host_parallel"] = par
+    return out, n_s, tally
 
 
 def timed(torch, stream, fn, reps):
@@ -645,7 +677,7 @@ def main():
     base = args.workload.split("-")[0]
     hist_updates_per_s = None
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], n_s, tally = cpu_baseline_entry(cfg, 12.0)
+        out["cpu_baseline"], n_s, tally = cpu_baseline_entry(cfg, 12.0, args.workload)
         costs = load_costs({"powder-mp": "powder_mp"}.get(args.workload, base))
         if costs is not None:
             w_hist = work_per_history(costs, tally, n_s, cfg)
