@@ -133,8 +133,8 @@ probe_kernel(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, 
       acc += C.px + C.py + C.pz + C.t + C.w + x + (float)k;
     } else if (PR == PR_KERNEL) {
       const DevScat& S = PL.s[arg >> 2];
-      const Out o = kernel_eval<true>(S.k[arg & 3], S, dyn, P, u, (uint64_t)gid * iters + it, h,
-                                      seed);
+      const Out o = kernel_eval<true, true>(S.k[arg & 3], S, dyn, P, u,
+                                            (uint64_t)gid * iters + it, h, seed);
       acc += o.dx + o.dy + o.dz + o.sp + o.f + o.dwq2 + (float)o.bin;
     } else if (PR == PR_DETECT) {
       const Hit hh = PL.det.type == DET_SPHERE

@@ -439,6 +439,9 @@ __device__ __forceinline__ Out k_iso(const DevKernel& K, const DevScat& S, const
   return o;
 }
 
+// Per-kernel forms of the powder Bragg and one-phonon draws below: the
+// cost probe prices each kernel alone with them (the transport kernels
+// evaluate both through k_powder_phonon, which computes the same values).
 __device__ __forceinline__ Out k_powder(const DevKernel& K, const DevScat& S, const float* tab,
                                         const Pk& P, const float* u) {
   Out o;
@@ -503,6 +506,107 @@ __device__ __forceinline__ Out k_phonon(const DevKernel& K, const DevScat& S, co
   const float coth = (2.0f - m) / m;
   o.sp = kf * kVperK;
   o.f = (kf / ki) * K.h2m * q2 * dw * coth / e;
+  return o;
+}
+
+// Powder Bragg and incoherent one-phonon draws (Supplement S4).
+//   Powder Bragg: a reflection d > lambda/2 chosen in proportion to its
+//   cross section (inverse CDF of the cumulative d|F|^2 of the active
+//   reflections, u2); the outgoing direction on the Debye-Scherrer cone
+//   2 theta_B = 2 asin(lambda / 2d) about the incident one, uniform in
+//   azimuth (u3); weight the Debye-Waller factor at Q = 2 pi / d.
+//   One-phonon: energy e from the normalised DOS (bin by inverse CDF, u2;
+//   uniform in the bin, u3), phonon creation with probability (n+1)/(2n+1)
+//   (u4), isotropic direction (u5, u6); weight (k_f/k_i) (hbar^2 Q^2 / 2M)
+//   e^{-2W} coth(e / 2kT) / e, zero when E_f <= 0.
+// One function evaluates both, so that the steps they share -- the
+// inverse-CDF search of a table in LDS, the sincos of an azimuth and the
+// Debye-Waller exponential -- run once for the lanes of a wave that draw
+// either kernel instead of once per kernel type (powder 1e7: 1.45 -> 1.36
+// ms); every lane computes the same operations on the same values as a
+// separate function per kernel would.
+__device__ __forceinline__ Out k_powder_phonon(const DevKernel& K, const DevScat& S,
+                                               const float* tab, const Pk& P, const float* u) {
+  const bool pw = K.type == K_POWDER;
+  // table search
+  float lambda = 0.0f;
+  const float* tbl;
+  int n;
+  float target;
+  if (pw) {
+    lambda = kTwoPi / (P.sp * kKperV);
+    const int na = n_active(tab + K.t_d, K.nrefl, 0.5f * lambda);
+    tbl = tab + K.t_pref;
+    n = na;
+    target = u[2] * tbl[na - 1];
+  } else {
+    tbl = tab + K.t_cdf;
+    n = K.nbins;
+    target = u[2];
+  }
+  int i = first_above(tbl, n, target);
+  if (i > n - 1) i = n - 1;
+  // azimuth: the cone's (powder) or the isotropic direction's (phonon)
+  float sn, cs;
+  sincospif(2.0f * (pw ? u[3] : u[6]), &sn, &cs);
+  Out o;
+  float q2 = 0.0f;       // Q^2 of the Debye-Waller factor
+  float pre = 1.0f;      // weight before the Debye-Waller factor
+  float m = 0.0f, e = 0.0f;
+  bool ok = true;
+  if (pw) {
+    const float d = tab[K.t_d + i];
+    const float sb = lambda / (2.0f * d);              // sin(theta_B)
+    const float cb = sqrtf((1.0f - sb) * (1.0f + sb));  // cos(theta_B)
+    const float c2 = (cb - sb) * (cb + sb);             // cos(2 theta_B)
+    const float s2 = 2.0f * sb * cb;                    // sin(2 theta_B)
+    float e1x, e1y, e1z, e2x, e2y, e2z;
+    perp_basis(P.dx, P.dy, P.dz, e1x, e1y, e1z, e2x, e2y, e2z);
+    o.dx = c2 * P.dx + s2 * (cs * e1x + sn * e2x);
+    o.dy = c2 * P.dy + s2 * (cs * e1y + sn * e2y);
+    o.dz = c2 * P.dz + s2 * (cs * e1z + sn * e2z);
+    o.sp = P.sp;
+    o.bin = -1;
+    const float q = kTwoPi / d;
+    q2 = q * q;
+  } else {
+    e = ((float)i + u[3]) * K.de;
+    const float x = e / K.kT;
+    // m = 1 - e^{-x} without cancellation: (n+1)/(2n+1) = 1/(2 - m) and
+    // coth(x/2) = (2 - m)/m
+    m = -expm1f(-x);
+    const float p_create = 1.0f / (2.0f - m);
+    const bool create = u[4] < p_create;
+    const float Ei = kEperV2 * P.sp * P.sp;
+    const float Ef = create ? Ei - e : Ei + e;
+    const float c = 2.0f * u[5] - 1.0f;
+    const float s = 2.0f * sqrtf(u[5] * (1.0f - u[5]));
+    o.dx = s * cs;
+    o.dy = s * sn;
+    o.dz = c;
+    o.bin = i;
+    if (!(Ef > 0.0f)) {
+      ok = false;
+      o.sp = P.sp;
+    } else {
+      const float ki = P.sp * kKperV;
+      const float kf = sqrtf(Ef / kHb2m);
+      const float dk = (create ? e : -e) / (kHb2m * (ki + kf));
+      q2 = q2_of(ki, kf, dk, P, o.dx, o.dy, o.dz);
+      o.sp = kf * kVperK;
+      pre = (kf / ki) * K.h2m * q2;
+    }
+  }
+  const float dw = K.dw && ok ? expf(-S.dw_coef * q2) : 1.0f;
+  o.dwq2 = K.dw && ok ? q2 : 0.0f;
+  if (pw) {
+    o.f = K.dw ? dw : 1.0f;
+  } else if (ok) {
+    const float coth = (2.0f - m) / m;
+    o.f = pre * dw * coth / e;
+  } else {
+    o.f = 0.0f;
+  }
   return o;
 }
 
@@ -1139,7 +1243,8 @@ __device__ __forceinline__ void segment_terms(const DevScat& S, const float* tab
 // and the coherent one-phonon kernel, whose root scan and table gather
 // would otherwise raise the register count of every plan (plans without
 // them use the instantiations without those cases).
-template <bool HEAVY>
+// SEPARATE: the per-kernel powder and one-phonon forms (cost probe).
+template <bool HEAVY, bool SEPARATE = false>
 __device__ __forceinline__ Out kernel_eval(const DevKernel& K, const DevScat& S,
                                            const float* tab, const Pk& P, const float* u,
                                            uint64_t id, uint32_t lin, uint64_t seed) {
@@ -1147,10 +1252,14 @@ __device__ __forceinline__ Out kernel_eval(const DevKernel& K, const DevScat& S,
     if (K.type == K_DISPERSION) return k_dispersion(K, P, u);
     if (K.type == K_COH_PHONON) return k_cohphonon(K, S, P, u);
   }
+  if constexpr (SEPARATE) {
+    if (K.type == K_POWDER) return k_powder(K, S, tab, P, u);
+    if (K.type == K_PHONON) return k_phonon(K, S, tab, P, u);
+  }
   switch (K.type) {
     case K_ISO_EL: return k_iso(K, S, P, u);
-    case K_POWDER: return k_powder(K, S, tab, P, u);
-    case K_PHONON: return k_phonon(K, S, tab, P, u);
+    case K_POWDER:
+    case K_PHONON: return k_powder_phonon(K, S, tab, P, u);
     case K_SPINWAVE: return k_spinwave(K, P, u);
     case K_MULTIPHONON: return k_multiphonon(K, tab, P, u, id, lin, seed);
     default: return k_sqe(K, tab, P, u);

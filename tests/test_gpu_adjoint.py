@@ -355,3 +355,20 @@ def test_tape_overflow_marks_the_gradient(torch_cuda):
     g.zero_()
     plan.adjoint_tape_wl2(pm, tape, dLdI, dLdI, dLdI, part, g)
     assert torch.isnan(g).all() and torch.isnan(part).all()
+
+
+def test_tape_of_no_histories(torch_cuda):
+    """n = 0: nothing recorded, the tape pass adds nothing (the dense terms
+    are multiplied by sums that stay zero)."""
+    from paper_1504_02776_amd import mcv
+    torch = torch_cuda
+    plan = mcv.Plan(W.powder_config())
+    pm = mcv.param_map_of(PM)
+    tape = plan.tape(16)
+    h = plan.zeros()
+    plan.run_tape(pm, h, tape, n=0)
+    g = torch.zeros(plan.nparams(pm), dtype=torch.float64, device="cuda")
+    plan.adjoint_tape(pm, tape, torch.ones_like(h), g)
+    torch.cuda.synchronize()
+    assert int(tape[1].item()) == 0 and float(h.abs().sum()) == 0.0
+    assert float(g.abs().sum()) == 0.0
