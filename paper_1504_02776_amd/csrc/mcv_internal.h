@@ -17,7 +17,10 @@ constexpr int kMaxKern = 3;
 constexpr int kMaxRows = 8;
 constexpr int kMaxSlots = 2 * kMaxScat;  // material intervals per flight
 constexpr int kMaxOrders = 7;
-constexpr int kFields = 11;              // words per stacked packet
+// words per stacked packet: position, direction, speed, time, weight,
+// lineage, code, and for a child not built yet its interval's distance and
+// interaction probability
+constexpr int kFields = 13;
 
 enum { SHAPE_BOX = 1, SHAPE_CYLINDER = 2, SHAPE_ANNULUS = 3 };
 enum { K_ISO_EL = 1, K_POWDER = 2, K_PHONON = 3, K_SPINWAVE = 4, K_SQE = 5, K_MULTIPHONON = 6,

@@ -1158,12 +1158,23 @@ __device__ __forceinline__ void adj_push(Adj& a, uint32_t idx) {
   a.cnt += 1u << 16;
 }
 
+// The code a pending child carries: -1 none; 4 s + k: kernel k of
+// scatterer s still to be evaluated; kUnbuilt | s << 2 | e << 5: a
+// forced-collision child of scatterer s not built yet (free path, birth
+// point, time, weight and kernel are drawn when it is taken up; its packet
+// fields then hold the parent's ray: the flight's start point and time, the
+// parent's weight at the interval, and e is the surface the interval is
+// entered through).
+constexpr int kUnbuilt = 16;
+
 // A stacked packet: position, direction, speed, time, weight, lineage and
-// the code of a kernel still to be evaluated for it (scatterer 4 s + kernel
-// k, or -1), then the adjoint carry in adjoint mode.
-template <bool ADJ>
+// its code, then (LAZY: children not built yet) the distance to the
+// interval and the interaction probability in it, then the adjoint carry in
+// adjoint mode.
+template <bool ADJ, bool LAZY = false>
 __device__ __forceinline__ void push(float* st, int slot, int nthreads, int tid, const Pk& C,
-                                     const Adj& a, int code) {
+                                     const Adj& a, int code, float slo = 0.0f,
+                                     float pint = 0.0f) {
   constexpr int NF = kFields + (ADJ ? kAdjFields : 0);
   float* b = st + (size_t)slot * NF * nthreads + tid;
   b[0 * nthreads] = C.px;
@@ -1177,19 +1188,24 @@ __device__ __forceinline__ void push(float* st, int slot, int nthreads, int tid,
   b[8 * nthreads] = C.w;
   b[9 * nthreads] = __uint_as_float(C.lin);
   b[10 * nthreads] = __uint_as_float((uint32_t)code);
+  if (LAZY) {
+    b[11 * nthreads] = slo;
+    b[12 * nthreads] = pint;
+  }
   if (ADJ) {
-    b[11 * nthreads] = a.dabs;
-    b[12 * nthreads] = a.dsig;
-    b[13 * nthreads] = a.A;
-    b[14 * nthreads] = __uint_as_float(a.cnt);
+    b[(kFields + 0) * nthreads] = a.dabs;
+    b[(kFields + 1) * nthreads] = a.dsig;
+    b[(kFields + 2) * nthreads] = a.A;
+    b[(kFields + 3) * nthreads] = __uint_as_float(a.cnt);
 #pragma unroll
-    for (int w = 0; w < kAdjMaxSparse / 2; ++w) b[(15 + w) * nthreads] = __uint_as_float(a.s[w]);
+    for (int w = 0; w < kAdjMaxSparse / 2; ++w)
+      b[(kFields + 4 + w) * nthreads] = __uint_as_float(a.s[w]);
   }
 }
 
-template <bool ADJ>
+template <bool ADJ, bool LAZY = false>
 __device__ __forceinline__ void pop(const float* st, int slot, int nthreads, int tid, Pk& C,
-                                    Adj& a, int& code) {
+                                    Adj& a, int& code, float& slo, float& pint) {
   constexpr int NF = kFields + (ADJ ? kAdjFields : 0);
   const float* b = st + (size_t)slot * NF * nthreads + tid;
   C.px = b[0 * nthreads];
@@ -1203,13 +1219,18 @@ __device__ __forceinline__ void pop(const float* st, int slot, int nthreads, int
   C.w = b[8 * nthreads];
   C.lin = __float_as_uint(b[9 * nthreads]);
   code = (int)__float_as_uint(b[10 * nthreads]);
+  if (LAZY) {
+    slo = b[11 * nthreads];
+    pint = b[12 * nthreads];
+  }
   if (ADJ) {
-    a.dabs = b[11 * nthreads];
-    a.dsig = b[12 * nthreads];
-    a.A = b[13 * nthreads];
-    a.cnt = __float_as_uint(b[14 * nthreads]);
+    a.dabs = b[(kFields + 0) * nthreads];
+    a.dsig = b[(kFields + 1) * nthreads];
+    a.A = b[(kFields + 2) * nthreads];
+    a.cnt = __float_as_uint(b[(kFields + 3) * nthreads]);
 #pragma unroll
-    for (int w = 0; w < kAdjMaxSparse / 2; ++w) a.s[w] = __float_as_uint(b[(15 + w) * nthreads]);
+    for (int w = 0; w < kAdjMaxSparse / 2; ++w)
+      a.s[w] = __float_as_uint(b[(kFields + 4 + w) * nthreads]);
   }
 }
 
@@ -1409,17 +1430,36 @@ __device__ __forceinline__ void kernel_carries(const AdjArgs& AA, const DevScat&
 // Evaluates the kernel of a child born with DEFER (code = 4 s + k): the same
 // uniforms (blocks 0 and 1 of its scattering stream) and the same incoming
 // direction and speed as at its birth, so the result is the one an immediate
-// evaluation gives.
-template <bool ADJ, bool HEAVY>
+// evaluation gives.  LAZY: a child not built yet (code with kUnbuilt) is
+// first built by split_child from the parent's ray it carries, the
+// attenuation coefficients recomputed at its speed, and block 0's
+// uniforms, i.e. from the operands flight_step would have used at its birth.
+template <bool ADJ, bool HEAVY, bool LAZY = false>
 __device__ __forceinline__ void eval_deferred(const DevPlan& PL, const float* tab,
                                               const AdjArgs& AA, Pk& C, Adj& ca, int code,
-                                              uint64_t id, uint64_t seed) {
-  const int si = code >> 2, kk = code & 3;
+                                              uint64_t id, uint64_t seed, float slo = 0.0f,
+                                              float pint = 0.0f) {
+  const int si = (code >> 2) & 3;
+  int kk = code & 3;
   const DevScat& S = PL.s[si];
-  const DevKernel& K = S.k[kk];
   float u[8];
   draw4(id, STREAM_SCATTER, C.lin, 0u, seed, u);
   draw4(id, STREAM_SCATTER, C.lin, 1u, seed, u + 4);
+  if constexpr (LAZY) {
+    if (code & kUnbuilt) {
+      const Mu mu = attenuation(S, tab, C.sp);
+      Pk B;
+      float x;
+      kk = split_child(S, mu, pint, C, C.px, C.py, C.pz, C.t, slo, (code >> 5) & 15, u, C.lin,
+                       B, x);
+      C.px = B.px;
+      C.py = B.py;
+      C.pz = B.pz;
+      C.t = B.t;
+      C.w = B.w;
+    }
+  }
+  const DevKernel& K = S.k[kk];
   const Out o = kernel_eval<HEAVY>(K, S, tab, C, u, id, C.lin, seed);
   C.dx = o.dx;
   C.dy = o.dy;
@@ -1433,14 +1473,20 @@ __device__ __forceinline__ void eval_deferred(const DevPlan& PL, const float* ta
 // e^{-mu L}; with SPLIT (and order < K, w >= min_prob, mu_s > 0) a
 // forced-collision child is born in it and its kernel drawn.  The kernel is
 // evaluated at once, or, with DEFER, when the child is taken up (its code
-// travels with it; `nxt_code`).  The first child of a flight is kept in
+// travels with it; `nxt_code`).  With LAZY (which implies DEFER) the child
+// itself is built then too: it is kept as the parent's ray, the interval's
+// distance and interaction probability (`nxt_slo`, `nxt_pint` for the first
+// child), and only its weight is computed here, to drop a child of weight
+// zero as the immediate form does.  The first child of a flight is kept in
 // `nxt`, further ones go to the stack.
-template <bool ADJ, bool SPLIT, bool DEFER, int NSC, bool TWO, bool HEAVY>
+template <bool ADJ, bool SPLIT, bool DEFER, int NSC, bool TWO, bool HEAVY, bool LAZY = false>
 __device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
                                             const AdjArgs& AA, Pk& P, Adj& pa,
                                             Flight<NSC, TWO>& F, uint64_t id, uint64_t seed,
                                             Pk& nxt, Adj& na, int& nxt_code, bool& has_nxt,
-                                            float* st, int& nst, int nthreads, int tid) {
+                                            float* st, int& nst, int nthreads, int tid,
+                                            float& nxt_slo, float& nxt_pint) {
+  static_assert(!LAZY || (DEFER && !ADJ), "children are built lazily only with deferred kernels");
   using SL = Slots<NSC, TWO>;
   constexpr int NS = SL::N;
   // nearest remaining interval; ties to the lower scatterer index
@@ -1475,7 +1521,28 @@ __device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
     if (si == AA.abs_s) dmu_abs = S.n100 * 2200.0f / P.sp;
     if (si == AA.sig_s) dmu_sig = S.n100;
   }
-  if (SPLIT && order_of(P.lin) < PL.K && P.w >= PL.min_prob && mu.scat > 0.0f) {
+  const bool split = SPLIT && order_of(P.lin) < PL.K && P.w >= PL.min_prob && mu.scat > 0.0f;
+  if (LAZY && split) {
+    if (P.w * (mu.scat / mu.total) * pint > 0.0f) {  // split_child's weight
+      Pk C = P;
+      C.px = F.sx;
+      C.py = F.sy;
+      C.pz = F.sz;
+      C.t = F.t0;
+      C.lin = P.lin * 8u + F.g + 1u;
+      const int code = kUnbuilt | si << 2 | (int)((F.codes >> (4 * j)) & 0xFu) << 5;
+      if (!has_nxt) {
+        nxt = C;
+        nxt_code = code;
+        nxt_slo = slo;
+        nxt_pint = pint;
+        has_nxt = true;
+      } else if (nst < PL.stack_cap) {
+        push<false, true>(st, nst, nthreads, tid, C, pa, code, slo, pint);
+        ++nst;
+      }
+    }
+  } else if (!LAZY && split) {
     const uint32_t lin = P.lin * 8u + F.g + 1u;
     float u[8];
     draw4(id, STREAM_SCATTER, lin, 0u, seed, u);
@@ -2043,6 +2110,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
   Adj na = ca;
   bool has_nxt = false;
   int code = -1;  // kernels are evaluated at birth in this loop (no deferral)
+  float unused = 0.0f;
   Flight<NSC, TWO> F;
   F.valid = 0u;
   F.g = 0u;
@@ -2061,7 +2129,8 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
     if (__popcll(mI) >= __popcll(mD)) {
       if (state == LANE_FLY) {
         flight_step<ADJ, true, false, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na,
-                                                     code, has_nxt, st, nst, nthreads, tid);
+                                                     code, has_nxt, st, nst, nthreads, tid, unused,
+                                                     unused);
         if (F.valid == 0u) {
           flight_exit(cur, F);
           state = LANE_DET;
@@ -2102,7 +2171,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
     }
     if (state == LANE_NEED && nst > 0) {
       --nst;
-      pop<ADJ>(st, nst, nthreads, tid, cur, ca, code);
+      pop<ADJ>(st, nst, nthreads, tid, cur, ca, code, unused, unused);
       state = LANE_SETUP;
     }
     const bool need = state == LANE_NEED;
@@ -2124,7 +2193,8 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
       if (order_of(cur.lin) >= PL.K || cur.w < PL.min_prob) {
         while (F.valid != 0u)
           flight_step<ADJ, false, false, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt,
-                                                        na, code, has_nxt, st, nst, nthreads, tid);
+                                                        na, code, has_nxt, st, nst, nthreads, tid,
+                                                        unused, unused);
       }
       if (F.valid != 0u) {
         state = LANE_FLY;
@@ -2147,12 +2217,15 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
   constexpr bool ADJ = carries(MODE);
   static_assert(DQ == 0 || DQ == kDqWalk, "walk-loop queue size");
   constexpr bool DEFER = NSC > 1 || TWO || HEAVY;
+  // children built when taken up (run and trace modes with deferred kernels)
+  constexpr bool LAZY = DEFER && !ADJ;
   const uint64_t lt = lanemask_lt();
   Pk cur;
   cur.lin = 0u;
   Adj ca = adj_zero();
   bool has = false;
   int code = -1;
+  float cslo = 0.0f, cpint = 0.0f;  // an unbuilt current child's interval
   uint64_t hid = 0;
   int nst = 0;
   uint64_t next = begin;
@@ -2160,7 +2233,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
   while (true) {
     if (!has && nst > 0) {
       --nst;
-      pop<ADJ>(st, nst, nthreads, tid, cur, ca, code);
+      pop<ADJ, LAZY>(st, nst, nthreads, tid, cur, ca, code, cslo, cpint);
       has = true;
     }
     const bool need = !has;
@@ -2185,7 +2258,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
       break;
     }
     if (DEFER && has && code >= 0) {
-      eval_deferred<ADJ, HEAVY>(PL, tab, AA, cur, ca, code, hid, seed);
+      eval_deferred<ADJ, HEAVY, LAZY>(PL, tab, AA, cur, ca, code, hid, seed, cslo, cpint);
       code = -1;
       has = cur.w > 0.0f;  // a kernel of weight zero ends the child
     }
@@ -2195,13 +2268,15 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
     nxt.lin = 0u;
     Adj na = ca;
     int nxt_code = -1;
+    float nxt_slo = 0.0f, nxt_pint = 0.0f;
     bool has_nxt = false;
     if (has) {
       Flight<NSC, TWO> F;
       flight_setup(PL, cur, F);
       while (F.valid != 0u)
-        flight_step<ADJ, true, DEFER, NSC, TWO, HEAVY>(PL, tab, AA, cur, ca, F, hid, seed, nxt, na,
-                                                      nxt_code, has_nxt, st, nst, nthreads, tid);
+        flight_step<ADJ, true, DEFER, NSC, TWO, HEAVY, LAZY>(PL, tab, AA, cur, ca, F, hid, seed,
+                                                            nxt, na, nxt_code, has_nxt, st, nst,
+                                                            nthreads, tid, nxt_slo, nxt_pint);
       flight_exit(cur, F);
       if (!DQ) record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
     }
@@ -2225,6 +2300,8 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
       if (has_nxt) {
         cur = nxt;
         code = nxt_code;
+        cslo = nxt_slo;
+        cpint = nxt_pint;
         if (ADJ) ca = na;
       } else {
         has = false;
