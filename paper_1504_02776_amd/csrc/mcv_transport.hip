@@ -1332,7 +1332,27 @@ struct Flight {
   uint32_t valid, codes;
   float sx, sy, sz, t0, s_end;
   uint32_t g;  // intervals crossed so far (segment index of the next child)
+  // attenuation coefficients mu and mu_s of each scatterer at the packet's
+  // speed (filled by flight_coefs; used by flight_step with LAZY)
+  float mt[NSC], ms[NSC];
 };
+
+// The packet's speed is the same over its whole flight: the coefficients
+// of every scatterer are computed once, each for all lanes together (the
+// same function and operands as segment_terms, so the same values).
+template <int NSC, bool TWO>
+__device__ __forceinline__ void flight_coefs(const DevPlan& PL, const float* tab, float sp,
+                                             Flight<NSC, TWO>& F) {
+#pragma unroll
+  for (int s = 0; s < NSC; ++s) {
+    F.mt[s] = F.ms[s] = 0.0f;
+    if (s < PL.nscat) {
+      const Mu mu = attenuation(PL.s[s], tab, sp);
+      F.mt[s] = mu.total;
+      F.ms[s] = mu.scat;
+    }
+  }
+}
 
 template <int NSC, bool TWO>
 __device__ __forceinline__ void flight_setup(const DevPlan& PL, const Pk& P, Flight<NSC, TWO>& F) {
@@ -1515,7 +1535,22 @@ __device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
   const DevScat& S = PL.s[si];
   Mu mu;
   float att, pint;
-  segment_terms(S, tab, P.sp, sl, mu, att, pint);
+  if constexpr (LAZY) {
+    // segment_terms with the flight's coefficients (mu.k is not needed here)
+    mu.total = mu.scat = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NSC; ++q) {
+      if (q == si) {
+        mu.total = F.mt[q];
+        mu.scat = F.ms[q];
+      }
+    }
+    const float ml = mu.total * sl;
+    att = expf(-ml);
+    pint = -expm1f(-ml);
+  } else {
+    segment_terms(S, tab, P.sp, sl, mu, att, pint);
+  }
   float dmu_abs = 0.0f, dmu_sig = 0.0f;
   if (ADJ) {
     if (si == AA.abs_s) dmu_abs = S.n100 * 2200.0f / P.sp;
@@ -2273,6 +2308,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
     if (has) {
       Flight<NSC, TWO> F;
       flight_setup(PL, cur, F);
+      if (LAZY) flight_coefs(PL, tab, cur.sp, F);
       while (F.valid != 0u)
         flight_step<ADJ, true, DEFER, NSC, TWO, HEAVY, LAZY>(PL, tab, AA, cur, ca, F, hid, seed,
                                                             nxt, na, nxt_code, has_nxt, st, nst,
