@@ -884,7 +884,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
     // stacks of every wave of the largest grid (grid_shape: cus x 4 x
     // waves_per_simd x 2 waves), adjoint fields included
     const size_t waves = (size_t)p->cus * 4 * p->waves_per_simd * 2 + (size_t)block / 64;
-    p->stack_floats = waves * 64 * (size_t)P.stack_cap * (kFields + kAdjFields);
+    p->stack_floats = waves * 64 * (size_t)P.stack_cap * stack_words(true);
     if ((e = hipMalloc(&p->d_stack, p->stack_floats * sizeof(float))) != hipSuccess) {
       (void)hipSetDevice(cur);
       mcv_plan_destroy(p);
@@ -988,7 +988,7 @@ mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t firs
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
-  if (p->d_stack && grid * p->block * (size_t)p->host.stack_cap * kFields > p->stack_floats)
+  if (p->d_stack && grid * p->block * (size_t)p->host.stack_cap * stack_words(false) > p->stack_floats)
     return fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
   hipError_t e = launch_transport(p->d_plan, p->host, p->d_tables, B,
                                   seed, first, n, (int)grid, p->block, per_wave, hist, hist_w2,
@@ -1023,7 +1023,7 @@ static mcv_status run_deterministic(mcv_plan p, const mcv_beam* beam, uint64_t s
     const uint64_t m = std::min<uint64_t>(p->det_chunk, first + n - cf);
     uint64_t grid, per_wave;
     grid_shape(p, m, p->block, &grid, &per_wave);
-    if (p->d_stack && grid * p->block * (size_t)p->host.stack_cap * kFields > p->stack_floats) {
+    if (p->d_stack && grid * p->block * (size_t)p->host.stack_cap * stack_words(false) > p->stack_floats) {
       st = fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
       break;
     }
@@ -1319,7 +1319,7 @@ mcv_status adjoint_launch(mcv_plan p, const mcv_param_map* pm, const AdjSetup& A
     uint64_t grid, per_wave;
     grid_shape(p, n, A.block, &grid, &per_wave);
     if (p->d_stack &&
-        grid * A.block * (size_t)p->host.stack_cap * (kFields + kAdjFields) > p->stack_floats)
+        grid * A.block * (size_t)p->host.stack_cap * stack_words(true) > p->stack_floats)
       return fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
     e = launch_transport(p->d_plan, p->host, p->d_tables, B, seed, first, n, (int)grid, A.block,
                          per_wave, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, &AA,
@@ -1392,7 +1392,7 @@ mcv_status mcv_run_tape(mcv_plan p, const mcv_param_map* pm, const mcv_beam* bea
   uint64_t grid, per_wave;
   grid_shape(p, n, block, &grid, &per_wave);
   if (p->d_stack &&
-      grid * block * (size_t)p->host.stack_cap * (kFields + kAdjFields) > p->stack_floats)
+      grid * block * (size_t)p->host.stack_cap * stack_words(true) > p->stack_floats)
     return fail(MCV_EUNSUPPORTED, "packet stacks exceed their buffer");
   int cur = 0;
   (void)hipGetDevice(&cur);
@@ -1673,7 +1673,7 @@ mcv_status mcv_batch_create(mcv_batch* out, const mcv_batch_item* items, int32_t
   };
   b->stack_max = stack_max;
   if (stack_max > 0 && e == hipSuccess)
-    e = hipMalloc(&b->d_stack, (size_t)b->grid * block * stack_max * kFields * sizeof(float));
+    e = hipMalloc(&b->d_stack, (size_t)b->grid * block * stack_max * stack_words(false) * sizeof(float));
   up((void**)&b->d_items, hitems.data(), hitems.size() * sizeof(BatchItem));
   up((void**)&b->d_chunks, cl.data(), cl.size() * sizeof(BatchChunk));
   uint32_t zero = 0;

@@ -151,6 +151,9 @@ struct AdjArgs {
 };
 
 constexpr int kAdjFields = 10;     // extra words per stacked packet in adjoint mode
+// binary32 words of one stacked packet entry, without or with the adjoint
+// carry, padded to a multiple of 4 (moved with 16-byte accesses)
+constexpr int stack_words(bool carry) { return (kFields + (carry ? kAdjFields : 0) + 3) & ~3; }
 constexpr int kAdjMaxOrders = 4;
 constexpr int kAdjMaxSparse = 12;  // table indices a packet carries (16 bits each)
 constexpr int kAdjMaxTable = 65535;

@@ -1167,70 +1167,67 @@ __device__ __forceinline__ void adj_push(Adj& a, uint32_t idx) {
 // entered through).
 constexpr int kUnbuilt = 16;
 
-// A stacked packet: position, direction, speed, time, weight, lineage and
-// its code, then (LAZY: children not built yet) the distance to the
-// interval and the interaction probability in it, then the adjoint carry in
-// adjoint mode.
+// A stacked packet, one contiguous entry per lane and slot (stack_words
+// binary32 words, moved with 16-byte accesses): position, direction, speed,
+// time, weight, lineage, its code, then (LAZY: children not built yet) the
+// distance to the interval and the interaction probability in it, then the
+// adjoint carry in adjoint mode.  A lane's entries follow each other, `cap`
+// of them per lane.
+static_assert(kFields == 13 && kAdjFields == 10 && kAdjMaxSparse == 12, "stack entry layout");
 template <bool ADJ, bool LAZY = false>
-__device__ __forceinline__ void push(float* st, int slot, int nthreads, int tid, const Pk& C,
+__device__ __forceinline__ void push(float* st, int slot, int cap, int tid, const Pk& C,
                                      const Adj& a, int code, float slo = 0.0f,
                                      float pint = 0.0f) {
-  constexpr int NF = kFields + (ADJ ? kAdjFields : 0);
-  float* b = st + (size_t)slot * NF * nthreads + tid;
-  b[0 * nthreads] = C.px;
-  b[1 * nthreads] = C.py;
-  b[2 * nthreads] = C.pz;
-  b[3 * nthreads] = C.dx;
-  b[4 * nthreads] = C.dy;
-  b[5 * nthreads] = C.dz;
-  b[6 * nthreads] = C.sp;
-  b[7 * nthreads] = C.t;
-  b[8 * nthreads] = C.w;
-  b[9 * nthreads] = __uint_as_float(C.lin);
-  b[10 * nthreads] = __uint_as_float((uint32_t)code);
-  if (LAZY) {
-    b[11 * nthreads] = slo;
-    b[12 * nthreads] = pint;
-  }
+  constexpr int NW = stack_words(ADJ);
+  float4* b = reinterpret_cast<float4*>(st + ((size_t)tid * cap + slot) * NW);
+  b[0] = make_float4(C.px, C.py, C.pz, C.dx);
+  b[1] = make_float4(C.dy, C.dz, C.sp, C.t);
+  b[2] = make_float4(C.w, __uint_as_float(C.lin), __uint_as_float((uint32_t)code), slo);
   if (ADJ) {
-    b[(kFields + 0) * nthreads] = a.dabs;
-    b[(kFields + 1) * nthreads] = a.dsig;
-    b[(kFields + 2) * nthreads] = a.A;
-    b[(kFields + 3) * nthreads] = __uint_as_float(a.cnt);
-#pragma unroll
-    for (int w = 0; w < kAdjMaxSparse / 2; ++w)
-      b[(kFields + 4 + w) * nthreads] = __uint_as_float(a.s[w]);
+    b[3] = make_float4(pint, a.dabs, a.dsig, a.A);
+    b[4] = make_float4(__uint_as_float(a.cnt), __uint_as_float(a.s[0]), __uint_as_float(a.s[1]),
+                       __uint_as_float(a.s[2]));
+    b[5] = make_float4(__uint_as_float(a.s[3]), __uint_as_float(a.s[4]), __uint_as_float(a.s[5]),
+                       0.0f);
+  } else if (LAZY) {
+    b[3] = make_float4(pint, 0.0f, 0.0f, 0.0f);
   }
 }
 
 template <bool ADJ, bool LAZY = false>
-__device__ __forceinline__ void pop(const float* st, int slot, int nthreads, int tid, Pk& C,
-                                    Adj& a, int& code, float& slo, float& pint) {
-  constexpr int NF = kFields + (ADJ ? kAdjFields : 0);
-  const float* b = st + (size_t)slot * NF * nthreads + tid;
-  C.px = b[0 * nthreads];
-  C.py = b[1 * nthreads];
-  C.pz = b[2 * nthreads];
-  C.dx = b[3 * nthreads];
-  C.dy = b[4 * nthreads];
-  C.dz = b[5 * nthreads];
-  C.sp = b[6 * nthreads];
-  C.t = b[7 * nthreads];
-  C.w = b[8 * nthreads];
-  C.lin = __float_as_uint(b[9 * nthreads]);
-  code = (int)__float_as_uint(b[10 * nthreads]);
-  if (LAZY) {
-    slo = b[11 * nthreads];
-    pint = b[12 * nthreads];
-  }
-  if (ADJ) {
-    a.dabs = b[(kFields + 0) * nthreads];
-    a.dsig = b[(kFields + 1) * nthreads];
-    a.A = b[(kFields + 2) * nthreads];
-    a.cnt = __float_as_uint(b[(kFields + 3) * nthreads]);
-#pragma unroll
-    for (int w = 0; w < kAdjMaxSparse / 2; ++w)
-      a.s[w] = __float_as_uint(b[(kFields + 4 + w) * nthreads]);
+__device__ __forceinline__ void pop(const float* st, int slot, int cap, int tid, Pk& C, Adj& a,
+                                    int& code, float& slo, float& pint) {
+  constexpr int NW = stack_words(ADJ);
+  const float4* b = reinterpret_cast<const float4*>(st + ((size_t)tid * cap + slot) * NW);
+  const float4 v0 = b[0], v1 = b[1], v2 = b[2];
+  C.px = v0.x;
+  C.py = v0.y;
+  C.pz = v0.z;
+  C.dx = v0.w;
+  C.dy = v1.x;
+  C.dz = v1.y;
+  C.sp = v1.z;
+  C.t = v1.w;
+  C.w = v2.x;
+  C.lin = __float_as_uint(v2.y);
+  code = (int)__float_as_uint(v2.z);
+  slo = v2.w;
+  if (LAZY || ADJ) {
+    const float4 v3 = b[3];
+    pint = v3.x;
+    if (ADJ) {
+      const float4 v4 = b[4], v5 = b[5];
+      a.dabs = v3.y;
+      a.dsig = v3.z;
+      a.A = v3.w;
+      a.cnt = __float_as_uint(v4.x);
+      a.s[0] = __float_as_uint(v4.y);
+      a.s[1] = __float_as_uint(v4.z);
+      a.s[2] = __float_as_uint(v4.w);
+      a.s[3] = __float_as_uint(v5.x);
+      a.s[4] = __float_as_uint(v5.y);
+      a.s[5] = __float_as_uint(v5.z);
+    }
   }
 }
 
@@ -1573,7 +1570,7 @@ __device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
         nxt_pint = pint;
         has_nxt = true;
       } else if (nst < PL.stack_cap) {
-        push<false, true>(st, nst, nthreads, tid, C, pa, code, slo, pint);
+        push<false, true>(st, nst, PL.stack_cap, tid, C, pa, code, slo, pint);
         ++nst;
       }
     }
@@ -1616,7 +1613,7 @@ __device__ __forceinline__ void flight_step(const DevPlan& PL, const float* tab,
         if (ADJ) na = ca;
         has_nxt = true;
       } else if (nst < PL.stack_cap) {
-        push<ADJ>(st, nst, nthreads, tid, C, ca, code);
+        push<ADJ>(st, nst, PL.stack_cap, tid, C, ca, code);
         ++nst;
       }
     }
@@ -2206,7 +2203,7 @@ __device__ __forceinline__ void trace_phased(const DevPlan& PL, const float* tab
     }
     if (state == LANE_NEED && nst > 0) {
       --nst;
-      pop<ADJ>(st, nst, nthreads, tid, cur, ca, code, unused, unused);
+      pop<ADJ>(st, nst, PL.stack_cap, tid, cur, ca, code, unused, unused);
       state = LANE_SETUP;
     }
     const bool need = state == LANE_NEED;
@@ -2268,7 +2265,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
   while (true) {
     if (!has && nst > 0) {
       --nst;
-      pop<ADJ, LAZY>(st, nst, nthreads, tid, cur, ca, code, cslo, cpint);
+      pop<ADJ, LAZY>(st, nst, PL.stack_cap, tid, cur, ca, code, cslo, cpint);
       has = true;
     }
     const bool need = !has;
@@ -2414,8 +2411,7 @@ transport(const DevPlan* __restrict__ gplan, const float* __restrict__ gtab, Dev
   // the workgroup's packet stacks in device memory ([slot][field][lane],
   // consecutive lanes at consecutive addresses; a lane pushes only the
   // second and later children of a flight)
-  constexpr int NFS = kFields + (CARRY ? kAdjFields : 0);
-  float* st = out.gstack + (size_t)blockIdx.x * PL.stack_cap * NFS * nthreads;
+  float* st = out.gstack + (size_t)blockIdx.x * PL.stack_cap * stack_words(CARRY) * nthreads;
   // LDS after the bin cache: the waves' detection queues, then their event
   // stages
   float* dqs = dyn + tab_words + acc_words;
@@ -2502,7 +2498,7 @@ batch_persistent(const BatchItem* __restrict__ items, const BatchChunk* __restri
     float* tab = dyn + hot_words(hot_n);
     // the workgroup's packet stacks in device memory, sized for the largest
     // stack of the batch's plans
-    float* st = gstack + (size_t)blockIdx.x * stack_max * kFields * nthreads;
+    float* st = gstack + (size_t)blockIdx.x * stack_max * stack_words(false) * nthreads;
     const uint64_t per = (ch.count + nwaves - 1) / nwaves;
     const uint64_t b = ch.first + per * wid;
     const uint64_t e = ch.first + ch.count;
