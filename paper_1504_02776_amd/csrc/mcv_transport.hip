@@ -439,9 +439,11 @@ __device__ __forceinline__ Out k_iso(const DevKernel& K, const DevScat& S, const
   return o;
 }
 
-// Per-kernel forms of the powder Bragg and one-phonon draws below: the
-// cost probe prices each kernel alone with them (the transport kernels
-// evaluate both through k_powder_phonon, which computes the same values).
+// Per-kernel forms of the isotropic elastic (above), powder Bragg,
+// one-phonon and spin-wave draws: the cost probe prices each kernel alone
+// with them; the transport kernels evaluate them through k_shared, which
+// computes the same values (the instantiations with the heavy kernels call
+// k_iso and k_spinwave themselves).
 __device__ __forceinline__ Out k_powder(const DevKernel& K, const DevScat& S, const float* tab,
                                         const Pk& P, const float* u) {
   Out o;
@@ -509,106 +511,6 @@ __device__ __forceinline__ Out k_phonon(const DevKernel& K, const DevScat& S, co
   return o;
 }
 
-// Powder Bragg and incoherent one-phonon draws (Supplement S4).
-//   Powder Bragg: a reflection d > lambda/2 chosen in proportion to its
-//   cross section (inverse CDF of the cumulative d|F|^2 of the active
-//   reflections, u2); the outgoing direction on the Debye-Scherrer cone
-//   2 theta_B = 2 asin(lambda / 2d) about the incident one, uniform in
-//   azimuth (u3); weight the Debye-Waller factor at Q = 2 pi / d.
-//   One-phonon: energy e from the normalised DOS (bin by inverse CDF, u2;
-//   uniform in the bin, u3), phonon creation with probability (n+1)/(2n+1)
-//   (u4), isotropic direction (u5, u6); weight (k_f/k_i) (hbar^2 Q^2 / 2M)
-//   e^{-2W} coth(e / 2kT) / e, zero when E_f <= 0.
-// One function evaluates both, so that the steps they share -- the
-// inverse-CDF search of a table in LDS, the sincos of an azimuth and the
-// Debye-Waller exponential -- run once for the lanes of a wave that draw
-// either kernel instead of once per kernel type (powder 1e7: 1.45 -> 1.36
-// ms); every lane computes the same operations on the same values as a
-// separate function per kernel would.
-__device__ __forceinline__ Out k_powder_phonon(const DevKernel& K, const DevScat& S,
-                                               const float* tab, const Pk& P, const float* u) {
-  const bool pw = K.type == K_POWDER;
-  // table search
-  float lambda = 0.0f;
-  const float* tbl;
-  int n;
-  float target;
-  if (pw) {
-    lambda = kTwoPi / (P.sp * kKperV);
-    const int na = n_active(tab + K.t_d, K.nrefl, 0.5f * lambda);
-    tbl = tab + K.t_pref;
-    n = na;
-    target = u[2] * tbl[na - 1];
-  } else {
-    tbl = tab + K.t_cdf;
-    n = K.nbins;
-    target = u[2];
-  }
-  int i = first_above(tbl, n, target);
-  if (i > n - 1) i = n - 1;
-  // azimuth: the cone's (powder) or the isotropic direction's (phonon)
-  float sn, cs;
-  sincospif(2.0f * (pw ? u[3] : u[6]), &sn, &cs);
-  Out o;
-  float q2 = 0.0f;       // Q^2 of the Debye-Waller factor
-  float pre = 1.0f;      // weight before the Debye-Waller factor
-  float m = 0.0f, e = 0.0f;
-  bool ok = true;
-  if (pw) {
-    const float d = tab[K.t_d + i];
-    const float sb = lambda / (2.0f * d);              // sin(theta_B)
-    const float cb = sqrtf((1.0f - sb) * (1.0f + sb));  // cos(theta_B)
-    const float c2 = (cb - sb) * (cb + sb);             // cos(2 theta_B)
-    const float s2 = 2.0f * sb * cb;                    // sin(2 theta_B)
-    float e1x, e1y, e1z, e2x, e2y, e2z;
-    perp_basis(P.dx, P.dy, P.dz, e1x, e1y, e1z, e2x, e2y, e2z);
-    o.dx = c2 * P.dx + s2 * (cs * e1x + sn * e2x);
-    o.dy = c2 * P.dy + s2 * (cs * e1y + sn * e2y);
-    o.dz = c2 * P.dz + s2 * (cs * e1z + sn * e2z);
-    o.sp = P.sp;
-    o.bin = -1;
-    const float q = kTwoPi / d;
-    q2 = q * q;
-  } else {
-    e = ((float)i + u[3]) * K.de;
-    const float x = e / K.kT;
-    // m = 1 - e^{-x} without cancellation: (n+1)/(2n+1) = 1/(2 - m) and
-    // coth(x/2) = (2 - m)/m
-    m = -expm1f(-x);
-    const float p_create = 1.0f / (2.0f - m);
-    const bool create = u[4] < p_create;
-    const float Ei = kEperV2 * P.sp * P.sp;
-    const float Ef = create ? Ei - e : Ei + e;
-    const float c = 2.0f * u[5] - 1.0f;
-    const float s = 2.0f * sqrtf(u[5] * (1.0f - u[5]));
-    o.dx = s * cs;
-    o.dy = s * sn;
-    o.dz = c;
-    o.bin = i;
-    if (!(Ef > 0.0f)) {
-      ok = false;
-      o.sp = P.sp;
-    } else {
-      const float ki = P.sp * kKperV;
-      const float kf = sqrtf(Ef / kHb2m);
-      const float dk = (create ? e : -e) / (kHb2m * (ki + kf));
-      q2 = q2_of(ki, kf, dk, P, o.dx, o.dy, o.dz);
-      o.sp = kf * kVperK;
-      pre = (kf / ki) * K.h2m * q2;
-    }
-  }
-  const float dw = K.dw && ok ? expf(-S.dw_coef * q2) : 1.0f;
-  o.dwq2 = K.dw && ok ? q2 : 0.0f;
-  if (pw) {
-    o.f = K.dw ? dw : 1.0f;
-  } else if (ok) {
-    const float coth = (2.0f - m) / m;
-    o.f = pre * dw * coth / e;
-  } else {
-    o.f = 0.0f;
-  }
-  return o;
-}
 
 // Coherent one-phonon scattering from a powder (Supplement S4).  Averaging
 // over crystallite orientations turns every point K of reciprocal space
@@ -711,6 +613,160 @@ __device__ __forceinline__ Out k_spinwave(const DevKernel& K, const Pk& P, const
   const float lor = K.gamma * kInvPi / (xx * xx + K.gamma * K.gamma);
   o.sp = kf * kVperK;
   o.f = (kf / ki) * lor * (hi - lo);
+  return o;
+}
+
+// Isotropic elastic, powder Bragg, incoherent one-phonon and spin-wave
+// draws (Supplement S4), as the per-kernel functions above compute them:
+//   Isotropic elastic: isotropic direction (u2, u3), speed kept; weight the
+//   Debye-Waller factor when the scatterer has one.
+//   Powder Bragg: a reflection d > lambda/2 chosen in proportion to its
+//   cross section (inverse CDF of the cumulative d|F|^2 of the active
+//   reflections, u2); the outgoing direction on the Debye-Scherrer cone
+//   2 theta_B = 2 asin(lambda / 2d) about the incident one, uniform in
+//   azimuth (u3); weight the Debye-Waller factor at Q = 2 pi / d.
+//   One-phonon: energy e from the normalised DOS (bin by inverse CDF, u2;
+//   uniform in the bin, u3), phonon creation with probability (n+1)/(2n+1)
+//   (u4), isotropic direction (u5, u6); weight (k_f/k_i) (hbar^2 Q^2 / 2M)
+//   e^{-2W} coth(e / 2kT) / e, zero when E_f <= 0.
+//   Spin wave: energy transfer uniform on [-10 Gamma, min(omega_max +
+//   10 Gamma, 0.99 E_i)] (u2), isotropic direction (u3, u4); weight (k_f/k_i)
+//   times the Lorentzian of half width Gamma about omega(Q) times the range.
+// One function evaluates all four so that the steps they share run once for
+// the lanes of a wave that draw any of them, not once per kernel type: the
+// inverse-CDF search of a table in LDS (Bragg lines or DOS bins), the sincos
+// of the azimuth and the direction about its axis (the incident direction
+// for a cone, the lab z axis otherwise: c a + s (cos phi e1 + sin phi e2)
+// with a = z, e1 = x, e2 = y gives the isotropic direction's components
+// exactly), the Debye-Waller exponential.  Measured: powder 1e7 1.45 ->
+// 1.36 ms with the first two kernels shared, crystal in its can 1e8 80.3 ->
+// 79.1 ms with all four.  ALL = false: powder Bragg and one-phonon only (the
+// other two compiled out); the instantiations with the heavy kernels use
+// that form (the coherent one-phonon plate took 1.67 instead of 1.50 ms with
+// all four).
+template <bool ALL>
+__device__ __forceinline__ Out k_shared(const DevKernel& K, const DevScat& S, const float* tab,
+                                        const Pk& P, const float* u) {
+  const bool pw = K.type == K_POWDER;
+  const bool ph = K.type == K_PHONON;
+  const bool sw = ALL && K.type == K_SPINWAVE;
+  Out o;
+  o.bin = -1;
+  // table search
+  int i = 0;
+  float lambda = 0.0f;
+  if (pw || ph) {
+    const float* tbl;
+    int n;
+    float target;
+    if (pw) {
+      lambda = kTwoPi / (P.sp * kKperV);
+      const int na = n_active(tab + K.t_d, K.nrefl, 0.5f * lambda);
+      tbl = tab + K.t_pref;
+      n = na;
+      target = u[2] * tbl[na - 1];
+    } else {
+      tbl = tab + K.t_cdf;
+      n = K.nbins;
+      target = u[2];
+    }
+    i = first_above(tbl, n, target);
+    if (i > n - 1) i = n - 1;
+  }
+  // polar angle about the axis and azimuth
+  float c, s, up;
+  float q2 = 0.0f;  // Q^2 of the Debye-Waller factor
+  if (pw) {
+    const float d = tab[K.t_d + i];
+    const float sb = lambda / (2.0f * d);              // sin(theta_B)
+    const float cb = sqrtf((1.0f - sb) * (1.0f + sb));  // cos(theta_B)
+    c = (cb - sb) * (cb + sb);                          // cos(2 theta_B)
+    s = 2.0f * sb * cb;                                 // sin(2 theta_B)
+    up = u[3];
+    const float q = kTwoPi / d;
+    q2 = q * q;
+  } else {
+    // uniforms by value (a select of array elements would index the array)
+    const float u2 = u[2], u3 = u[3], u4 = u[4], u5 = u[5], u6 = u[6];
+    const float uc = ph ? u5 : sw ? u3 : u2;
+    c = 2.0f * uc - 1.0f;
+    s = 2.0f * sqrtf(uc * (1.0f - uc));
+    up = ph ? u6 : sw ? u4 : u3;
+  }
+  float sn, cs;
+  sincospif(2.0f * up, &sn, &cs);
+  float ax = 0.0f, ay = 0.0f, az = 1.0f;
+  float e1x = 1.0f, e1y = 0.0f, e1z = 0.0f, e2x = 0.0f, e2y = 1.0f, e2z = 0.0f;
+  if (pw) {
+    ax = P.dx;
+    ay = P.dy;
+    az = P.dz;
+    perp_basis(P.dx, P.dy, P.dz, e1x, e1y, e1z, e2x, e2y, e2z);
+  }
+  o.dx = c * ax + s * (cs * e1x + sn * e2x);
+  o.dy = c * ay + s * (cs * e1y + sn * e2y);
+  o.dz = c * az + s * (cs * e1z + sn * e2z);
+  o.sp = P.sp;
+  float pre = 1.0f;  // phonon weight before the Debye-Waller factor
+  float m = 0.0f, e = 0.0f;
+  float fsw = 0.0f;  // spin-wave weight
+  bool ok = true;    // false: no Debye-Waller factor (a phonon with E_f <= 0)
+  if (ph) {
+    e = ((float)i + u[3]) * K.de;
+    const float x = e / K.kT;
+    // m = 1 - e^{-x} without cancellation: (n+1)/(2n+1) = 1/(2 - m) and
+    // coth(x/2) = (2 - m)/m
+    m = -expm1f(-x);
+    const float p_create = 1.0f / (2.0f - m);
+    const bool create = u[4] < p_create;
+    const float Ei = kEperV2 * P.sp * P.sp;
+    const float Ef = create ? Ei - e : Ei + e;
+    o.bin = i;
+    if (!(Ef > 0.0f)) {
+      ok = false;
+    } else {
+      const float ki = P.sp * kKperV;
+      const float kf = sqrtf(Ef / kHb2m);
+      const float dk = (create ? e : -e) / (kHb2m * (ki + kf));
+      q2 = q2_of(ki, kf, dk, P, o.dx, o.dy, o.dz);
+      o.sp = kf * kVperK;
+      pre = (kf / ki) * K.h2m * q2;
+    }
+  } else if (sw) {
+    const float Ei = kEperV2 * P.sp * P.sp;
+    const float lo = -10.0f * K.gamma;
+    const float hi = fminf(K.wmax + 10.0f * K.gamma, 0.99f * Ei);
+    if (hi > lo) {
+      const float E = lo + u[2] * (hi - lo);
+      const float ki = P.sp * kKperV;
+      const float kf = sqrtf((Ei - E) / kHb2m);
+      const float qx = ki * P.dx - kf * o.dx, qy = ki * P.dy - kf * o.dy,
+                  qz = ki * P.dz - kf * o.dz;
+      const float* C = K.crot;
+      const float cx = C[0] * qx + C[1] * qy + C[2] * qz;
+      const float cy = C[3] * qx + C[4] * qy + C[5] * qz;
+      const float cz = C[6] * qx + C[7] * qy + C[8] * qz;
+      const float w = K.j4s * (3.0f - cosf(cx * K.a) - cosf(cy * K.a) - cosf(cz * K.a));
+      const float xx = E - w;
+      const float lor = K.gamma * kInvPi / (xx * xx + K.gamma * K.gamma);
+      o.sp = kf * kVperK;
+      fsw = (kf / ki) * lor * (hi - lo);
+    }
+  } else if (ALL && !pw && K.dw) {
+    const float k = P.sp * kKperV;
+    q2 = q2_of(k, k, 0.0f, P, o.dx, o.dy, o.dz);
+  }
+  const bool dwf = K.dw && ok && !sw;
+  const float dw = dwf ? expf(-S.dw_coef * q2) : 1.0f;
+  o.dwq2 = dwf ? q2 : 0.0f;
+  if (sw) {
+    o.f = fsw;
+  } else if (ph) {
+    const float coth = (2.0f - m) / m;
+    o.f = ok ? pre * dw * coth / e : 0.0f;
+  } else {
+    o.f = dw;
+  }
   return o;
 }
 
@@ -1269,16 +1325,18 @@ __device__ __forceinline__ Out kernel_eval(const DevKernel& K, const DevScat& S,
   if constexpr (HEAVY) {
     if (K.type == K_DISPERSION) return k_dispersion(K, P, u);
     if (K.type == K_COH_PHONON) return k_cohphonon(K, S, P, u);
+    if (K.type == K_ISO_EL) return k_iso(K, S, P, u);
+    if (K.type == K_SPINWAVE) return k_spinwave(K, P, u);
   }
   if constexpr (SEPARATE) {
     if (K.type == K_POWDER) return k_powder(K, S, tab, P, u);
     if (K.type == K_PHONON) return k_phonon(K, S, tab, P, u);
   }
   switch (K.type) {
-    case K_ISO_EL: return k_iso(K, S, P, u);
+    case K_ISO_EL:
     case K_POWDER:
-    case K_PHONON: return k_powder_phonon(K, S, tab, P, u);
-    case K_SPINWAVE: return k_spinwave(K, P, u);
+    case K_PHONON:
+    case K_SPINWAVE: return k_shared<!HEAVY>(K, S, tab, P, u);
     case K_MULTIPHONON: return k_multiphonon(K, tab, P, u, id, lin, seed);
     default: return k_sqe(K, tab, P, u);
   }
