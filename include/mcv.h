@@ -220,9 +220,13 @@ mcv_status mcv_detector_destroy(mcv_detector d);
 /* max_orders: maximum number of scattering events of a packet (Supplement
  * S3 max_ms); packets that reach it cross the remaining material with
  * attenuation only.  min_prob: packets below it are not split (0 = off).
- * block_size: threads per workgroup (0 = default 256; multiple of 64, <=
- * 1024).  waves_per_simd: target resident waves per SIMD used to size the
- * grid (0 = default).
+ * block_size: threads per workgroup (0 = default 256; 64, 128, 192 or 256).
+ * waves_per_simd: grid depth, the waves per SIMD the grid of a launch is
+ * sized for (0 = default 16, lowered for plans whose packet stacks would
+ * pass 2 GiB): a launch spreads its histories over up to 2 x 4 x CUs x
+ * waves_per_simd waves, each taking a contiguous id range of at least 512
+ * histories once it has more than two rounds of 4 waves per SIMD.  The
+ * plan's packet stacks are sized for that grid.
  * deterministic: 1 = mcv_run sums every histogram bin in a fixed order, so
  *   that two runs with the same arguments give bitwise equal histograms
  *   (Sec. 3: a bin's intensity is the sum of the probabilities of the

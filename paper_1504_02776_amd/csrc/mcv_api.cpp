@@ -109,6 +109,14 @@ bool finite_all(const double* x, int n) {
 
 // Slots of the LDS histogram bin cache: the most (kHotMin..kHotMax, a power
 // of two) that fit beside `base` bytes of LDS per workgroup when the
+// Default grid depth (waves_per_simd of mcv_opts: waves per SIMD the grid
+// is sized for, two rounds of them), the shallowest one used, and the
+// fewest histories per wave a launch spreads to beyond two rounds of the
+// shallowest.
+constexpr int kGridDepth = 16;
+constexpr int kGridDepthMin = 4;
+constexpr uint64_t kMinPerWave = 512;
+
 // workgroups of `waves_per_simd` resident waves share a CU's 160 KiB.
 int hot_slots(size_t base, int block, int waves_per_simd) {
   const int wgs = std::max(1, waves_per_simd * 4 * 64 / block);
@@ -349,7 +357,7 @@ struct mcv_plan_s {
   std::vector<float*> d_grids;   // mode tables of coherent phonon kernels
   int block = 256;
   int cus = 256;
-  int waves_per_simd = 4;
+  int waves_per_simd = kGridDepth;
   int64_t max_waves = 0;  // 0: fill the device
   int deterministic = 0;
   int64_t nbins = 0;
@@ -764,7 +772,7 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   p->block = block;
   p->device = device;
   p->scat = a->scat;
-  p->waves_per_simd = o.waves_per_simd > 0 ? o.waves_per_simd : 4;
+  p->waves_per_simd = o.waves_per_simd > 0 ? o.waves_per_simd : kGridDepth;
   p->max_waves = o.max_waves;
   p->deterministic = o.deterministic;
 
@@ -882,7 +890,15 @@ mcv_status mcv_plan_create(mcv_plan* out, mcv_assembly a, mcv_detector d, const 
   }
   if (P.stack_cap > 0) {
     // stacks of every wave of the largest grid (grid_shape: cus x 4 x
-    // waves_per_simd x 2 waves), adjoint fields included
+    // waves_per_simd x 2 waves), adjoint fields included; with the default
+    // depth, a shallower grid for plans whose stacks would pass 2 GiB
+    auto stack_bytes = [&](int depth) {
+      return ((size_t)p->cus * 4 * depth * 2 + (size_t)block / 64) * 64 * (size_t)P.stack_cap *
+             stack_words(true) * sizeof(float);
+    };
+    if (o.waves_per_simd <= 0)
+      while (p->waves_per_simd > kGridDepthMin && stack_bytes(p->waves_per_simd) > ((size_t)2 << 30))
+        p->waves_per_simd /= 2;
     const size_t waves = (size_t)p->cus * 4 * p->waves_per_simd * 2 + (size_t)block / 64;
     p->stack_floats = waves * 64 * (size_t)P.stack_cap * stack_words(true);
     if ((e = hipMalloc(&p->d_stack, p->stack_floats * sizeof(float))) != hipSuccess) {
@@ -963,9 +979,21 @@ mcv_status check_ids(const DevBeam& B, uint64_t first, uint64_t n) {
   return MCV_OK;
 }
 
+// Waves of a launch: each takes a contiguous id range.  At least two rounds
+// of the 4 resident waves per SIMD (when there are 64 histories per wave),
+// then up to cus x 4 x waves_per_simd x 2 waves while each keeps at least
+// kMinPerWave histories: shorter ranges shorten the tail where the last
+// waves run alone, and each workgroup pays to stage the plan and flush its
+// bin cache.  Measured (ms; depth 4 / 8 / 16 / 24, i.e. 2 to 12 rounds):
+// crystal in its can 1e8 79.1 / 75.7 / 73.5 / 73.0, powder 1e7 1.33 / 1.23
+// / 1.20 / 1.41, exact-delta crystal 1e7 24.6 / 23.6 / 24.0 / 24.6, plate
+// 1e9 31.8 / 30.1 / 28.9 / 28.5.
 void grid_shape(const mcv_plan_s* p, uint64_t n, int block, uint64_t* grid, uint64_t* per_wave) {
   const uint64_t waves_per_block = (uint64_t)block / 64;
+  const uint64_t two_rounds = (uint64_t)p->cus * 4 * kGridDepthMin * 2;
   uint64_t target = (uint64_t)p->cus * 4 * p->waves_per_simd * 2;
+  const uint64_t by_work = (n + kMinPerWave - 1) / kMinPerWave;
+  if (target > two_rounds) target = std::max(two_rounds, std::min(target, by_work));
   if (p->max_waves > 0 && (uint64_t)p->max_waves < target) target = (uint64_t)p->max_waves;
   uint64_t waves = (n + 63) / 64;
   if (waves > target) waves = target;
