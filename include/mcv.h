@@ -431,9 +431,11 @@ mcv_status mcv_adjoint(mcv_plan p, const mcv_param_map* pm, const mcv_beam* beam
  * Layout: MCV_TAPE_FIELDS x capacity uint32 words, field-major ([field]
  * [entry]): 0 bin, 1 value (binary32 bits), 2 d sigma_abs, 3 d sigma, 4 A
  * (binary32 bits), 5 counts (DOS draws low 16 bits, table indices high 16),
- * 6..11 table indices (16 bits each, two per word).  48 bytes per recorded
- * packet: 5.3e6 entries (254 MB) for 1e7 histories of the powder cylinder
- * seen by tubes. */
+ * 6..11 table indices (16 bits each, two per word; an entry with n indices
+ * writes only words 6 .. 6 + ceil(n/2) - 1, the others keep what the buffer
+ * held).  24 to 48 bytes per recorded packet: 5.3e6 entries for 1e7
+ * histories of the powder cylinder seen by tubes (capacity x 48 bytes
+ * allocated, 254 MB). */
 #define MCV_TAPE_FIELDS 12
 
 /* mcv_run (histogram hist, and Squared weights into hist_w2 when not NULL;

@@ -1972,8 +1972,12 @@ __device__ __forceinline__ void tape_append(const Sinks& out, int bin, float val
   __builtin_nontemporal_store(__float_as_uint(a.dsig), t + 3 * c);
   __builtin_nontemporal_store(__float_as_uint(a.A), t + 4 * c);
   __builtin_nontemporal_store(a.cnt, t + 5 * c);
+  // only the words that hold the entry's table indices (the backward pass
+  // reads no others): ceil(n / 2) for n indices
+  const uint32_t nw = ((a.cnt >> 16) + 1u) >> 1;
 #pragma unroll
-  for (int w = 0; w < kAdjMaxSparse / 2; ++w) __builtin_nontemporal_store(a.s[w], t + (6 + w) * c);
+  for (int w = 0; w < kAdjMaxSparse / 2; ++w)
+    if ((uint32_t)w < nw) __builtin_nontemporal_store(a.s[w], t + (6 + w) * c);
 }
 
 // Lane states of the transport loop
