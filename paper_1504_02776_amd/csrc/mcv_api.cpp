@@ -987,11 +987,16 @@ mcv_status check_ids(const DevBeam& B, uint64_t first, uint64_t n) {
 // bin cache.  Measured (ms; depth 4 / 8 / 16 / 24, i.e. 2 to 12 rounds):
 // crystal in its can 1e8 79.1 / 75.7 / 73.5 / 73.0, powder 1e7 1.33 / 1.23
 // / 1.20 / 1.41, exact-delta crystal 1e7 24.6 / 23.6 / 24.0 / 24.6, plate
-// 1e9 31.8 / 30.1 / 28.9 / 28.5.
-void grid_shape(const mcv_plan_s* p, uint64_t n, int block, uint64_t* grid, uint64_t* per_wave) {
+// 1e9 31.8 / 30.1 / 28.9 / 28.5.  shallow: at most two rounds (event
+// launches: every wave's last, partial stage of events is one more atomic
+// on the single event counter; powder 1e7 events 1.63 ms at the default
+// depth, 1.52 ms at 4).
+void grid_shape(const mcv_plan_s* p, uint64_t n, int block, uint64_t* grid, uint64_t* per_wave,
+                bool shallow = false) {
   const uint64_t waves_per_block = (uint64_t)block / 64;
   const uint64_t two_rounds = (uint64_t)p->cus * 4 * kGridDepthMin * 2;
-  uint64_t target = (uint64_t)p->cus * 4 * p->waves_per_simd * 2;
+  uint64_t target = (uint64_t)p->cus * 4 * (shallow ? std::min(p->waves_per_simd, kGridDepthMin)
+                                                    : p->waves_per_simd) * 2;
   const uint64_t by_work = (n + kMinPerWave - 1) / kMinPerWave;
   if (target > two_rounds) target = std::max(two_rounds, std::min(target, by_work));
   if (p->max_waves > 0 && (uint64_t)p->max_waves < target) target = (uint64_t)p->max_waves;
@@ -1012,7 +1017,7 @@ mcv_status launch(mcv_plan p, const mcv_beam* beam, uint64_t seed, uint64_t firs
   if ((st = check_ids(B, first, n)) != MCV_OK) return st;
   if (n == 0) return MCV_OK;
   uint64_t grid, per_wave;
-  grid_shape(p, n, p->block, &grid, &per_wave);
+  grid_shape(p, n, p->block, &grid, &per_wave, ev != nullptr);
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != p->device) (void)hipSetDevice(p->device);
