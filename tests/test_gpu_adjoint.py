@@ -223,8 +223,8 @@ def test_autograd_backward_is_the_adjoint(torch_cuda, tape_capacity):
 
 # Launch shapes with few waves: each wave takes hundreds of histories one
 # after another (the refill, the detection queue's flushes and the stacks
-# reused), as at the benchmark's 1e7 histories where a wave traces about
-# 1200.
+# reused), as at the benchmark's 1e7 histories where a wave traces 512
+# (here 1500 or 750).
 @pytest.mark.parametrize("via", ["retrace", "tape"])
 def test_adjoint_refill_launch_shape(torch_cuda, oracle_lib, via):
     _check_adjoint(torch_cuda, oracle_lib, W.powder_config, PM, 3000, via=via,

@@ -188,19 +188,21 @@ def _sampled_launch_shape(torch_cuda, oracle_lib, cfg, n, max_waves, cap_flag, c
 
 
 def test_crystal_sampled_at_full_launch_shape(torch_cuda, oracle_lib):
-    """The crystal's full 1e8-history launch gives each wave 12 208 histories;
-    1e6 histories on 82 waves (12 196 each) run the same walk-loop refill,
-    deferred kernels and detection queue over that many histories per wave."""
+    """The crystal's full 1e8-history launch gives each wave 3 052 histories
+    (32 768 waves); 1e6 histories on 328 waves (3 049 each) run the same
+    walk-loop refill, lazily built children, deferred kernels and detection
+    queue over that many histories per wave."""
     st = _sampled_launch_shape(torch_cuda, oracle_lib, W.crystal_config(N=1_000_000),
-                               1_000_000, 82, 3e-2, 3e-2)
+                               1_000_000, 328, 3e-2, 3e-2)
     print(f"[parity] crystal, full launch shape, sampled: {st}", flush=True)
 
 
 def test_plate_sampled_at_full_launch_shape(torch_cuda, oracle_lib):
-    """The plate's 1e9-history throughput launch gives each wave 122 071
-    histories; 2e6 histories on 16 waves (125 000 each) run that refill."""
+    """The plate's 1e9-history throughput launch gives each wave 30 518
+    histories (32 768 waves); 2e6 histories on 66 waves (30 304 each) run
+    that refill."""
     st = _sampled_launch_shape(torch_cuda, oracle_lib, W.plate_config(N=2_000_000),
-                               2_000_000, 16, 5e-3, 5e-3)
+                               2_000_000, 66, 5e-3, 5e-3)
     print(f"[parity] plate, full launch shape, sampled: {st}", flush=True)
 
 
