@@ -981,10 +981,10 @@ mcv_status check_ids(const DevBeam& B, uint64_t first, uint64_t n) {
 
 // Waves of a launch: each takes a contiguous id range.  At least two rounds
 // of the 4 resident waves per SIMD (when there are 64 histories per wave),
-// then up to cus x 4 x waves_per_simd x 2 waves while each keeps at least
-// kMinPerWave histories: shorter ranges shorten the tail where the last
-// waves run alone, and each workgroup pays to stage the plan and flush its
-// bin cache.  Measured (ms; depth 4 / 8 / 16 / 24, i.e. 2 to 12 rounds):
+// then up to cus x 4 x waves_per_simd x 2 waves, in whole rounds, while
+// each keeps at least kMinPerWave histories: shorter ranges shorten the tail
+// where the last waves run alone, and each workgroup pays to stage the plan
+// and flush its bin cache.  Measured (ms; depth 4 / 8 / 16 / 24, i.e. 2 to 12 rounds):
 // crystal in its can 1e8 79.1 / 75.7 / 73.5 / 73.0, powder 1e7 1.33 / 1.23
 // / 1.20 / 1.41, exact-delta crystal 1e7 24.6 / 23.6 / 24.0 / 24.6, plate
 // 1e9 31.8 / 30.1 / 28.9 / 28.5.  shallow: at most two rounds (event
@@ -994,11 +994,14 @@ mcv_status check_ids(const DevBeam& B, uint64_t first, uint64_t n) {
 void grid_shape(const mcv_plan_s* p, uint64_t n, int block, uint64_t* grid, uint64_t* per_wave,
                 bool shallow = false) {
   const uint64_t waves_per_block = (uint64_t)block / 64;
-  const uint64_t two_rounds = (uint64_t)p->cus * 4 * kGridDepthMin * 2;
+  // one round: the waves resident at once at 4 per SIMD
+  const uint64_t round = (uint64_t)p->cus * 4 * kGridDepthMin;
   uint64_t target = (uint64_t)p->cus * 4 * (shallow ? std::min(p->waves_per_simd, kGridDepthMin)
                                                     : p->waves_per_simd) * 2;
-  const uint64_t by_work = (n + kMinPerWave - 1) / kMinPerWave;
-  if (target > two_rounds) target = std::max(two_rounds, std::min(target, by_work));
+  // whole rounds only: a partial last round is a tail of its own (exact-delta
+  // crystal 1e7: 24.5 ms on 4.77 rounds, 23.6 ms on 4)
+  const uint64_t by_work = n / kMinPerWave / round * round;
+  if (target > 2 * round) target = std::max(2 * round, std::min(target, by_work));
   if (p->max_waves > 0 && (uint64_t)p->max_waves < target) target = (uint64_t)p->max_waves;
   uint64_t waves = (n + 63) / 64;
   if (waves > target) waves = target;
