@@ -1223,6 +1223,12 @@ __device__ __forceinline__ void adj_push(Adj& a, uint32_t idx) {
 // entered through).
 constexpr int kUnbuilt = 16;
 
+// Gathering of exact-delta dispersion draws in the walk loop: a wave
+// evaluates them once at least kDispMin lanes hold one, and no draw waits
+// more than kDispWaitMax iterations.
+constexpr int kDispMin = 32;
+constexpr int kDispWaitMax = 4;
+
 // A stacked packet, one contiguous entry per lane and slot (stack_words
 // binary32 words, moved with 16-byte accesses): position, direction, speed,
 // time, weight, lineage, its code, then (LAZY: children not built yet) the
@@ -1509,6 +1515,23 @@ __device__ __forceinline__ void kernel_carries(const AdjArgs& AA, const DevScat&
 // first built by split_child from the parent's ray it carries, the
 // attenuation coefficients recomputed at its speed, and block 0's
 // uniforms, i.e. from the operands flight_step would have used at its birth.
+// Builds an unbuilt child (code with kUnbuilt) from the parent's ray it
+// carries, with block 0's uniforms u[0], u[1]; returns its kernel index.
+__device__ __forceinline__ int build_child(const DevScat& S, const float* tab, Pk& C, int code,
+                                           float slo, float pint, const float* u) {
+  const Mu mu = attenuation(S, tab, C.sp);
+  Pk B;
+  float x;
+  const int kk = split_child(S, mu, pint, C, C.px, C.py, C.pz, C.t, slo, (code >> 5) & 15, u,
+                             C.lin, B, x);
+  C.px = B.px;
+  C.py = B.py;
+  C.pz = B.pz;
+  C.t = B.t;
+  C.w = B.w;
+  return kk;
+}
+
 template <bool ADJ, bool HEAVY, bool LAZY = false>
 __device__ __forceinline__ void eval_deferred(const DevPlan& PL, const float* tab,
                                               const AdjArgs& AA, Pk& C, Adj& ca, int code,
@@ -1521,18 +1544,7 @@ __device__ __forceinline__ void eval_deferred(const DevPlan& PL, const float* ta
   draw4(id, STREAM_SCATTER, C.lin, 0u, seed, u);
   draw4(id, STREAM_SCATTER, C.lin, 1u, seed, u + 4);
   if constexpr (LAZY) {
-    if (code & kUnbuilt) {
-      const Mu mu = attenuation(S, tab, C.sp);
-      Pk B;
-      float x;
-      kk = split_child(S, mu, pint, C, C.px, C.py, C.pz, C.t, slo, (code >> 5) & 15, u, C.lin,
-                       B, x);
-      C.px = B.px;
-      C.py = B.py;
-      C.pz = B.pz;
-      C.t = B.t;
-      C.w = B.w;
-    }
+    if (code & kUnbuilt) kk = build_child(S, tab, C, code, slo, pint, u);
   }
   const DevKernel& K = S.k[kk];
   const Out o = kernel_eval<HEAVY>(K, S, tab, C, u, id, C.lin, seed);
@@ -2313,6 +2325,9 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
   constexpr bool DEFER = NSC > 1 || TWO || HEAVY;
   // children built when taken up (run and trace modes with deferred kernels)
   constexpr bool LAZY = DEFER && !ADJ;
+  // exact-delta dispersion draws gathered across iterations (see below)
+  constexpr bool GATHER_DISP = HEAVY && LAZY;
+  int waited = 0;  // iterations this lane's dispersion draw has waited
   const uint64_t lt = lanemask_lt();
   Pk cur;
   cur.lin = 0u;
@@ -2351,11 +2366,33 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
       if (DQ && qn > 0) dq_run<MODE, DQ>(PL, tab, out, AA, acc, hot_n, dq, qn, seed);
       break;
     }
-    if (DEFER && has && code >= 0) {
+    // With the exact-delta kernel, a child that draws it waits (keeps its
+    // code and skips this iteration) unless at least kDispMin lanes draw it
+    // now, no lane has other work, or some lane has waited kDispWaitMax
+    // iterations: the kernel's root scan then runs for many lanes at once
+    // instead of for the few of each iteration.  Every wait ends (the last
+    // two conditions); the draws are those of an immediate evaluation.
+    bool wait = false;
+    if constexpr (GATHER_DISP) {
+      if (has && code >= 0 && (code & kUnbuilt)) {
+        float u[4];
+        draw4(hid, STREAM_SCATTER, cur.lin, 0u, seed, u);
+        const int si = (code >> 2) & 3;
+        code = 4 * si + build_child(PL.s[si], tab, cur, code, cslo, cpint, u);
+      }
+      const bool disp = has && code >= 0 && PL.s[(code >> 2) & 3].k[code & 3].type == K_DISPERSION;
+      const uint64_t md = __ballot(disp);
+      const bool others = __ballot(has && !disp) != 0ull;
+      const bool overdue = __ballot(disp && waited >= kDispWaitMax) != 0ull;
+      wait = disp && others && !overdue && __popcll(md) < kDispMin;
+      waited = wait ? waited + 1 : 0;
+    }
+    if (DEFER && has && code >= 0 && !wait) {
       eval_deferred<ADJ, HEAVY, LAZY>(PL, tab, AA, cur, ca, code, hid, seed, cslo, cpint);
       code = -1;
       has = cur.w > 0.0f;  // a kernel of weight zero ends the child
     }
+    const bool go = has && !wait;  // this lane's packet flies in this iteration
     int hbin = -1;
     float hval = 0.0f;
     Pk nxt;
@@ -2364,7 +2401,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
     int nxt_code = -1;
     float nxt_slo = 0.0f, nxt_pint = 0.0f;
     bool has_nxt = false;
-    if (has) {
+    if (go) {
       Flight<NSC, TWO> F;
       flight_setup(PL, cur, F);
       if (LAZY) flight_coefs(PL, tab, cur.sp, F);
@@ -2379,7 +2416,7 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
       float a;
       uint32_t rows;
       int col;
-      const bool q = has && tube_column(PL.det, cur, a, rows, col);
+      const bool q = go && tube_column(PL.det, cur, a, rows, col);
       const uint64_t mq = __ballot(q);
       const int k = __popcll(mq);
       if (qn + k > DQ) {
@@ -2388,10 +2425,10 @@ __device__ __forceinline__ void trace_walk(const DevPlan& PL, const float* tab, 
       }
       if (q) dq_put<DQ, ADJ>(dq, qn + __popcll(mq & lt), cur, hid, ca);
       qn += k;
-      if (MODE == MODE_TRACE && has && !q)
+      if (MODE == MODE_TRACE && go && !q)
         record_packet<MODE>(PL, tab, out, AA, acc, cur, ca, hid, seed, hbin, hval);
     }
-    if (has) {
+    if (go) {
       if (has_nxt) {
         cur = nxt;
         code = nxt_code;
