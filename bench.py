@@ -35,7 +35,7 @@ is the sum over primitives of (count per history in the algorithm, from the
 oracle's instrumentation on the CPU sample) x (measured cost of the
 primitive in lane-operation slots on gfx950, from probe_costs.py).
 
-Prints ONE JSON line.  Only one GPU is supported by this build.
+Prints ONE JSON line.  The benchmark runs on one GPU only.
 """
 
 from __future__ import annotations
@@ -614,7 +614,7 @@ def main():
                     help="also run one plain 256 MiB device copy (PMC byte calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
