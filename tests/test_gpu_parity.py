@@ -51,6 +51,14 @@ def _cases():
         # phased loop: ~750 per wave
         "powder-refill": (W.powder_config(), 3_000 + 11, {"max_waves": 4},
                           (8.5e-3, 1.5e-2, DIFFER)),
+        # exact-delta draws gathered across iterations: ~150 histories per
+        # wave (children wait for each other over many iterations), and 7
+        # histories (a few lanes: every wait is released because no lane has
+        # other work)
+        "crystal-delta-refill": (W.crystal_delta_config(psi_deg=23.0), 600 + 9,
+                                 {"max_waves": 4}, (3.2e-2, 3.2e-2, DIFFER)),
+        "crystal-delta-few": (W.crystal_delta_config(psi_deg=23.0), 7, {},
+                              (5e-2, 5e-2, DIFFER)),
         # saved beams with runs of 100 / 200 entries of weight zero (more than
         # a wave's 64 lanes draw at once) on walk-loop plans, 2 waves
         "crystal-saved-beam-gaps": (W.saved_beam_crystal_config(n=1_200), 1_200, {"max_waves": 2},
